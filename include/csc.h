@@ -1,0 +1,239 @@
+/*
+ * csc.h - C ABI of libcsc, the MI355X (gfx950) hot path of compressive
+ * spectral clustering (Tremblay, Puy, Gribonval, Vandergheynst, ICML 2016).
+ *
+ * The calls follow the statement of Alg. 2: the input is the normalized
+ * Laplacian L of an undirected graph and the number of clusters k, with
+ * parameters n (sampled nodes), d (random signals), p (polynomial order) and
+ * gamma (regularisation).  Steps 1, 3-5 and 7 run on the GPU; step 6 (k-means
+ * on an n x d matrix) runs on the host inside the library.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Return value: a csc_status.  CSC_OK and the CSC_W_* warnings leave every
+ *   output valid; CSC_E_* errors leave outputs unspecified.  The message of
+ *   the last error of the calling thread is returned by csc_last_error().
+ * Pointers: "device" pointers are HIP device allocations on the current
+ *   device; "host" pointers are ordinary host memory.  The caller owns every
+ *   buffer; the library never allocates device memory and never frees caller
+ *   memory.  Scratch memory is a caller-provided device workspace of at least
+ *   the size returned by the matching csc_*_workspace_bytes() call, aligned to
+ *   256 bytes.
+ * Streams: all device work is ordered on the hipStream_t passed as `stream`
+ *   (NULL = the null stream).  Calls that return host scalars synchronise that
+ *   stream before returning; the others return as soon as the work is queued.
+ * Dense blocks: node-major float32, row i of an N x w block starts at
+ *   ptr + i*ld, ld >= w.
+ * Determinism: the same inputs, seeds and parameters give bit-identical
+ *   outputs on the same device (no floating-point atomics; every reduction
+ *   runs in a fixed order).
+ * Random numbers: Philox4x64-10 (Salmon et al., SC'11) with key (seed, 0).
+ *   Gaussian entry (i, j) of an N x w block for sub-stream t of stream S uses
+ *   counter (i*w + j, t, S, 0) and the Box-Muller transform in float64 of the
+ *   first two output words x0, x1:
+ *   u1 = ((x0>>11)+1) 2^-53, u2 = (x1>>11) 2^-53,
+ *   z = sqrt(-2 ln u1) cos(2 pi u2) / sqrt(w), rounded to float32.
+ *   Streams: COUNT = 1 (eigencount signals, t = dichotomy step), FEAT = 2
+ *   (feature signals, t = 0), SAMPLE = 3 (sampling keys), KMEANS = 4.
+ * Thread safety: calls are reentrant when they use distinct workspaces.
+ */
+#ifndef CSC_H
+#define CSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t csc_status;
+
+enum {
+  CSC_OK = 0,
+  CSC_E_INVALID_ARG = 1,      /* bad size, pointer, parameter or workspace   */
+  CSC_E_GRAPH = 2,            /* malformed CSR (range, order, self-loop)      */
+  CSC_E_HIP = 3,              /* a HIP runtime call failed                    */
+  CSC_E_OOM = 4,              /* host memory exhausted                        */
+  CSC_W_NOT_CONVERGED = 5,    /* CG reached max_iter; outputs still valid     */
+  CSC_W_BISECT_EXHAUSTED = 6, /* dichotomy used max_steps; lambda = upper end */
+  CSC_W_BRACKET_MISS = 7      /* given bracket did not hold lambda_k; the
+                                 search fell back to [0, 2]                   */
+};
+
+enum { CSC_STREAM_COUNT = 1, CSC_STREAM_FEAT = 2, CSC_STREAM_SAMPLE = 3, CSC_STREAM_KMEANS = 4 };
+
+/* A = D^-1/2 W D^-1/2 of an undirected graph in CSR form (device pointers).
+ * L = I - A is never stored.  row_ptr[n+1] non-decreasing with row_ptr[0] = 0,
+ * col[nnz] in [0, n), val[nnz] = A_ij.  dinv_sqrt[n] = D_ii^-1/2 (0 for an
+ * isolated node) is kept for reference; the filters only read val. */
+typedef struct csc_graph {
+  int32_t n;
+  int32_t nnz;
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const float* val;
+  const float* dinv_sqrt;
+} csc_graph;
+
+/* Message of the last error returned on the calling thread ("" if none). */
+const char* csc_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t csc_version(void);
+
+/* Tuning.  Dense blocks inside the library are stored as panels of PW
+ * columns (PW in {4, 8, 16, 32, 64}); a Chebyshev step gathers neighbour rows
+ * of one panel at a time.  csc_set_panel_width(pw) forces PW for every later
+ * call of this process (0 restores the built-in choice); workspace sizes
+ * returned by the csc_*_workspace_bytes calls cover every PW.
+ * csc_get_panel_width(n, w) returns the PW the library will use for an
+ * n x w block. */
+csc_status csc_set_panel_width(int32_t pw);
+int32_t csc_get_panel_width(int32_t n, int32_t w);
+
+/* ------------------------------------------------------------------------
+ * Normalized adjacency (Sec. 2.1): D_ii = sum_{j != i} W_ij accumulated in
+ * float64, s_i = D_ii^-1/2 (0 when D_ii = 0, so that an isolated node has
+ * L_ii = 1), val_out[e] = s_i W_ij s_j for each stored entry e = (i, j), and 0
+ * for a stored diagonal entry.
+ * row_ptr, col, w, val_out, dinv_sqrt_out: device.  w = NULL means W_ij = 1.
+ * When `check` is non-zero the CSR is validated first (row_ptr monotone,
+ * row_ptr[0] = 0, row_ptr[n] = nnz, columns in range) and CSC_E_GRAPH is
+ * returned on failure; this synchronises the stream.
+ */
+csc_status csc_laplacian_from_adjacency(int32_t n, int32_t nnz, const int32_t* row_ptr,
+                                        const int32_t* col, const float* w, float* val_out,
+                                        float* dinv_sqrt_out, int32_t check, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Jackson-Chebyshev coefficients a_0..a_p (host, float64) of the order-p
+ * approximation of the ideal low-pass h_lc of Eq. (1) (Sec. 4.3) in the basis
+ * T_m(lambda - 1):  theta = arccos(lc - 1), c_0 = 1 - theta/pi,
+ * c_m = -2 sin(m theta)/(m pi), g_m = [(p+2-m) cos(m a) + sin(m a) cot a]/(p+2)
+ * with a = pi/(p+2), a_m = g_m c_m.  lc in [0, 2], p >= 0.  a_out: host[p+1].
+ */
+csc_status csc_jackson_coeffs(double lambda_c, int32_t p, double* a_out);
+
+/* ------------------------------------------------------------------------
+ * Gaussian signal block (Sec. 3.1, Alg. 2 step 3): R[i*ld + j] for i < n_rows,
+ * j < w, variance 1/w, drawn as in the header comment with sub-stream t of
+ * stream `stream_id`.  R: device.
+ */
+csc_status csc_gaussian_block(int32_t n_rows, int32_t w, uint64_t seed, uint32_t t,
+                              uint32_t stream_id, float* R, int32_t ld, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Polynomial filtering (Sec. 2.1, fast graph filtering) of a given block:
+ * Y = sum_{m=0}^{p} coeffs[m] T_m(L - I) X by the recurrence T_0 = X,
+ * T_1 = -A X, T_{m+1} = -2 A T_m - T_{m-1}, in float32.
+ * X, Y: device, N x w node-major with leading dimension ld (X and Y may not
+ * overlap).  coeffs: host[p+1].  ws: csc_filter_workspace_bytes(N, w).
+ */
+size_t csc_filter_workspace_bytes(int32_t n, int32_t w);
+csc_status csc_filter_block(const csc_graph* g, const double* coeffs, int32_t p, const float* X,
+                            int32_t w, int32_t ld, float* Y, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* ------------------------------------------------------------------------
+ * Feature pass, Alg. 2 steps 2-4: draws the N x d block R of stream FEAT
+ * (sub-stream 0), filters it by the order-p Jackson-Chebyshev low-pass at
+ * lambda_c, and writes rows of h~(L) R, scaled to unit length when
+ * `normalize` is non-zero (a zero row stays zero).
+ * rows = NULL: all N rows, Y is N x d.  Otherwise rows (device, n_rows
+ * distinct indices in [0, N)) selects the rows written, Y[s] = row rows[s]
+ * (Alg. 2 step 5 keeps only the sampled rows); the recurrence still runs
+ * over the whole graph.  Y: device, ld >= d.  ws: csc_filter_workspace_bytes.
+ */
+csc_status csc_filter(const csc_graph* g, double lambda_c, int32_t p, int32_t d, uint64_t seed,
+                      const int32_t* rows, int32_t n_rows, int32_t normalize, float* Y,
+                      int32_t ld, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Eigencount (Sec. 4.3): Hutchinson estimate of the number of eigenvalues of
+ * L in [0, lambda], count = sum_{i,l} R_il (h~_lambda(L) R)_il, with R the
+ * N x n_signals block of stream COUNT, sub-stream t.  It is evaluated as
+ * sum_m a_m mu_m with the moments mu_m = <R, T_m(L - I) R> accumulated in
+ * float64 on the GPU from float32 recurrences.
+ * count_out: host scalar.  moments_out: host[p+1] or NULL.
+ * ws: csc_estimate_workspace_bytes(N, n_signals, p).  Synchronises.
+ */
+size_t csc_estimate_workspace_bytes(int32_t n, int32_t n_signals, int32_t p);
+csc_status csc_eigencount(const csc_graph* g, double lambda, int32_t p, int32_t n_signals,
+                          uint64_t seed, uint32_t t, double* count_out, double* moments_out,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * lambda_k by eigencount dichotomy (Alg. 2 step 1, Sec. 4.3).  Starting from
+ * the bracket [lo, hi] (bracket = host[2], or NULL for [0, 2]), step
+ * t = 1, 2, ... tests mid = (lo + hi)/2 with fresh signals (sub-stream t):
+ * if floor(count + 1/2) = k it returns mid; if count < k then lo = mid, else
+ * hi = mid.  After max_steps tests it returns hi with CSC_W_BISECT_EXHAUSTED.
+ * With a caller bracket the search runs inside it; if it uses max_steps
+ * tests whose counts all fell on one side of k (lambda_k lies outside the
+ * bracket), it restarts from [0, 2] with the next sub-streams and returns
+ * CSC_W_BRACKET_MISS (steps_out counts the tests of both searches).
+ * lambda_out, steps_out: host scalars.  trace_out: host[2*max_steps] receiving
+ * (mid, count) of every tested point, or NULL.  moments_out: host[p+1]
+ * receiving the moments of the first tested point, or NULL.
+ * ws: csc_estimate_workspace_bytes(N, n_signals, p).  Synchronises.
+ */
+csc_status csc_estimate_lambda_k(const csc_graph* g, int32_t k, int32_t p, int32_t n_signals,
+                                 uint64_t seed, int32_t max_steps, const double* bracket,
+                                 double* lambda_out, int32_t* steps_out, double* trace_out,
+                                 double* moments_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Uniform sampling without replacement (Sec. 3.2.2, Eq. (4)): node i gets the
+ * 64-bit key x0 of counter (i, 0, SAMPLE, 0); idx[0..n) lists the n nodes
+ * with the smallest (key, i) pairs in increasing order.  Integer-only, hence
+ * bit-exact across implementations.  1 <= n <= N.  idx: device int32[n].
+ * ws: csc_sample_workspace_bytes(N, n).  Synchronises.
+ */
+size_t csc_sample_workspace_bytes(int32_t N, int32_t n);
+csc_status csc_sample(int32_t N, int32_t n, uint64_t seed, int32_t* idx, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * k-means on the n sampled features (Alg. 2 step 6), on the host in float64:
+ * `replicates` runs of k-means++ seeding (uniform draws at counter
+ * (c, r, KMEANS, 0), u = (x0>>11) 2^-53) followed by Lloyd iterations (at most
+ * max_iter; empty clusters re-seeded with the farthest point); the run with
+ * the smallest inertia is kept.  Squared distances sum coordinates in order,
+ * centroids sum points in index order, ties go to the lowest index.
+ * F: host n x d (float32 with leading dimension ld for the first call, float64
+ * for the _f64 call).  labels: host int32[n].  inertia_out: host or NULL.
+ */
+csc_status csc_kmeans_reduced(const float* F, int32_t n, int32_t d, int32_t ld, int32_t k,
+                              int32_t replicates, int32_t max_iter, uint64_t seed,
+                              int32_t* labels, double* inertia_out);
+csc_status csc_kmeans_reduced_f64(const double* F, int32_t n, int32_t d, int32_t ld, int32_t k,
+                                  int32_t replicates, int32_t max_iter, uint64_t seed,
+                                  int32_t* labels, double* inertia_out);
+
+/* ------------------------------------------------------------------------
+ * Interpolation, Eq. (5), and hard labels (Alg. 2 step 7, Sec. 4.1).
+ * Solves (diag(mask) + gamma (I - h~(L))) X = B for the k columns of
+ * B[idx[s], labels_r[s]] = 1 (mask_i = 1 iff i is in idx), h~ the order-p
+ * Jackson-Chebyshev low-pass at lambda_k, by conjugate gradient per column in
+ * lockstep: float32 vectors and recurrences, float64 inner products, step
+ * sizes and residual norms; column j stops when ||r_j|| / ||b_j|| <= tol.
+ * Then labels[i] = argmax_j X_ij / ||X_j|| (ties and zero columns -> lowest j).
+ * idx, labels_r: device int32[n] (idx distinct, labels_r in [0, k)).
+ * X: device N x k with leading dimension ldx >= k.  labels: device int32[N].
+ * iters_out: host int32[k] or NULL; relres_out: host double[k] or NULL.
+ * ws: csc_interpolate_workspace_bytes(N, k, n).  Synchronises.
+ * Returns CSC_W_NOT_CONVERGED if a column reached max_iter.
+ */
+size_t csc_interpolate_workspace_bytes(int32_t N, int32_t k, int32_t n);
+csc_status csc_interpolate(const csc_graph* g, double lambda_k, int32_t p, double gamma,
+                           const int32_t* idx, const int32_t* labels_r, int32_t n, int32_t k,
+                           double tol, int32_t max_iter, float* X, int32_t ldx, int32_t* labels,
+                           int32_t* iters_out, double* relres_out, void* ws, size_t ws_bytes,
+                           void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSC_H */

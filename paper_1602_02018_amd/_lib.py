@@ -1,0 +1,97 @@
+"""ctypes declarations of the libcsc C ABI (include/csc.h).
+
+Loading fails loudly when the shared library has not been built: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcsc.so")
+
+CSC_OK = 0
+CSC_E_INVALID_ARG = 1
+CSC_E_GRAPH = 2
+CSC_E_HIP = 3
+CSC_E_OOM = 4
+CSC_W_NOT_CONVERGED = 5
+CSC_W_BISECT_EXHAUSTED = 6
+CSC_W_BRACKET_MISS = 7
+WARNINGS = (CSC_W_NOT_CONVERGED, CSC_W_BISECT_EXHAUSTED, CSC_W_BRACKET_MISS)
+
+STREAM_COUNT, STREAM_FEAT, STREAM_SAMPLE, STREAM_KMEANS = 1, 2, 3, 4
+
+
+class CscGraph(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32),
+        ("nnz", C.c_int32),
+        ("row_ptr", C.c_void_p),
+        ("col", C.c_void_p),
+        ("val", C.c_void_p),
+        ("dinv_sqrt", C.c_void_p),
+    ]
+
+
+i32, u32, u64, f64, vp, sz = C.c_int32, C.c_uint32, C.c_uint64, C.c_double, C.c_void_p, C.c_size_t
+pg = C.POINTER(CscGraph)
+pd = C.POINTER(C.c_double)
+pi = C.POINTER(C.c_int32)
+
+# name: (restype, argtypes)
+PROTOTYPES = {
+    "csc_last_error": (C.c_char_p, []),
+    "csc_version": (i32, []),
+    "csc_set_panel_width": (i32, [i32]),
+    "csc_get_panel_width": (i32, [i32, i32]),
+    "csc_laplacian_from_adjacency": (i32, [i32, i32, vp, vp, vp, vp, vp, i32, vp]),
+    "csc_jackson_coeffs": (i32, [f64, i32, pd]),
+    "csc_gaussian_block": (i32, [i32, i32, u64, u32, u32, vp, i32, vp]),
+    "csc_filter_workspace_bytes": (sz, [i32, i32]),
+    "csc_filter_block": (i32, [pg, pd, i32, vp, i32, i32, vp, vp, sz, vp]),
+    "csc_filter": (i32, [pg, f64, i32, i32, u64, vp, i32, i32, vp, i32, vp, sz, vp]),
+    "csc_estimate_workspace_bytes": (sz, [i32, i32, i32]),
+    "csc_eigencount": (i32, [pg, f64, i32, i32, u64, u32, pd, pd, vp, sz, vp]),
+    "csc_estimate_lambda_k": (i32, [pg, i32, i32, i32, u64, i32, pd, pd, pi, pd, pd, vp, sz, vp]),
+    "csc_sample_workspace_bytes": (sz, [i32, i32]),
+    "csc_sample": (i32, [i32, i32, u64, vp, vp, sz, vp]),
+    "csc_kmeans_reduced": (i32, [vp, i32, i32, i32, i32, i32, i32, u64, pi, pd]),
+    "csc_kmeans_reduced_f64": (i32, [vp, i32, i32, i32, i32, i32, i32, u64, pi, pd]),
+    "csc_interpolate_workspace_bytes": (sz, [i32, i32, i32]),
+    "csc_interpolate": (i32, [pg, f64, i32, f64, vp, vp, i32, i32, f64, i32, vp, i32, vp, pi, pd,
+                              vp, sz, vp]),
+}
+
+
+class CscError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libcsc with prototypes set (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1602_02018_amd.build`")
+        handle = C.CDLL(LIB_PATH)
+        for name, (res, args) in PROTOTYPES.items():
+            f = getattr(handle, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def check(status: int, where: str, allow_warnings: bool = True) -> int:
+    if status == CSC_OK or (allow_warnings and status in WARNINGS):
+        return status
+    msg = lib().csc_last_error().decode(errors="replace")
+    raise CscError(status, where, msg)

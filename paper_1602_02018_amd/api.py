@@ -1,0 +1,256 @@
+"""Python binding of libcsc: argument marshalling only.
+
+PyTorch supplies device memory and the current HIP stream; every step on
+graph-sized data runs in the library's kernels (k-means on the n sampled
+features runs on the host inside the library).  The functions mirror the C
+calls of include/csc.h; ``run`` chains them into Alg. 2.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import CscGraph, check, lib
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _ws(nbytes: int, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _i32_device(x, device):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.int32).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.int32), device=device)
+
+
+class Graph:
+    """A = D^-1/2 W D^-1/2 on the GPU, built by csc_laplacian_from_adjacency."""
+
+    def __init__(self, row_ptr, col, device="cuda", weights=None, check_csr: bool = True):
+        self.device = torch.device(device)
+        self.row_ptr = _i32_device(row_ptr, self.device)
+        self.col = _i32_device(col, self.device)
+        self.n = int(self.row_ptr.numel() - 1)
+        self.nnz = int(self.col.numel())
+        w = None
+        if weights is not None:
+            w = torch.as_tensor(np.asarray(weights, dtype=np.float32), device=self.device)
+        self.val = torch.empty(max(self.nnz, 1), dtype=torch.float32, device=self.device)
+        self.dinv_sqrt = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        check(lib().csc_laplacian_from_adjacency(self.n, self.nnz, _ptr(self.row_ptr),
+                                                 _ptr(self.col), _ptr(w), _ptr(self.val),
+                                                 _ptr(self.dinv_sqrt), 1 if check_csr else 0,
+                                                 _stream()), "csc_laplacian_from_adjacency")
+        self.c = CscGraph(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
+                          self.val.data_ptr(), self.dinv_sqrt.data_ptr())
+
+    @property
+    def ref(self):
+        return C.byref(self.c)
+
+
+def version() -> int:
+    return int(lib().csc_version())
+
+
+def set_panel_width(pw: int) -> None:
+    check(lib().csc_set_panel_width(int(pw)), "csc_set_panel_width")
+
+
+def panel_width(n: int, w: int) -> int:
+    return int(lib().csc_get_panel_width(int(n), int(w)))
+
+
+def jackson_coeffs(lam: float, p: int) -> np.ndarray:
+    a = np.zeros(p + 1)
+    check(lib().csc_jackson_coeffs(float(lam), int(p), a.ctypes.data_as(_lib.pd)), "csc_jackson_coeffs")
+    return a
+
+
+def gaussian_block(n_rows: int, w: int, seed: int, t: int, stream_id: int, device="cuda"):
+    R = torch.empty((n_rows, w), dtype=torch.float32, device=device)
+    check(lib().csc_gaussian_block(n_rows, w, seed, t, stream_id, _ptr(R), w, _stream()),
+          "csc_gaussian_block")
+    return R
+
+
+def filter_block(g: Graph, coeffs, X: torch.Tensor) -> torch.Tensor:
+    coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+    X = X.contiguous()
+    n, w = X.shape
+    Y = torch.empty_like(X)
+    ws = _ws(lib().csc_filter_workspace_bytes(n, w), X.device)
+    check(lib().csc_filter_block(g.ref, coeffs.ctypes.data_as(_lib.pd), len(coeffs) - 1, _ptr(X),
+                                 w, w, _ptr(Y), _ptr(ws), ws.numel(), _stream()), "csc_filter_block")
+    return Y
+
+
+def filter(g: Graph, lam: float, p: int, d: int, seed: int, rows=None, normalize: bool = True):
+    """Alg. 2 steps 2-4 (and the row selection of step 5 when ``rows`` is given)."""
+    rows_t = None if rows is None else _i32_device(rows, g.device)
+    n_rows = g.n if rows_t is None else int(rows_t.numel())
+    Y = torch.empty((n_rows, d), dtype=torch.float32, device=g.device)
+    ws = _ws(lib().csc_filter_workspace_bytes(g.n, d), g.device)
+    check(lib().csc_filter(g.ref, float(lam), p, d, seed, _ptr(rows_t), n_rows if rows_t is not None else 0,
+                           1 if normalize else 0, _ptr(Y), d, _ptr(ws), ws.numel(), _stream()),
+          "csc_filter")
+    return Y
+
+
+def eigencount(g: Graph, lam: float, p: int, n_signals: int, seed: int, t: int = 1):
+    cnt = C.c_double(0.0)
+    mom = np.zeros(p + 1)
+    ws = _ws(lib().csc_estimate_workspace_bytes(g.n, n_signals, p), g.device)
+    check(lib().csc_eigencount(g.ref, float(lam), p, n_signals, seed, t, C.byref(cnt),
+                               mom.ctypes.data_as(_lib.pd), _ptr(ws), ws.numel(), _stream()),
+          "csc_eigencount")
+    return cnt.value, mom
+
+
+@dataclass
+class Bisection:
+    lam: float
+    steps: int
+    trace: list
+    moments: np.ndarray
+    status: int
+
+
+def estimate_lambda_k(g: Graph, k: int, p: int, n_signals: int, seed: int, max_steps: int = 30,
+                      bracket=None) -> Bisection:
+    lam = C.c_double(0.0)
+    steps = C.c_int32(0)
+    trace = np.zeros(2 * max_steps * 2)
+    mom = np.zeros(p + 1)
+    br = None
+    if bracket is not None:
+        br_arr = np.ascontiguousarray(bracket, dtype=np.float64)
+        br = br_arr.ctypes.data_as(_lib.pd)
+    ws = _ws(lib().csc_estimate_workspace_bytes(g.n, n_signals, p), g.device)
+    st = check(lib().csc_estimate_lambda_k(g.ref, k, p, n_signals, seed, max_steps, br,
+                                           C.byref(lam), C.byref(steps),
+                                           trace.ctypes.data_as(_lib.pd),
+                                           mom.ctypes.data_as(_lib.pd), _ptr(ws), ws.numel(),
+                                           _stream()), "csc_estimate_lambda_k")
+    tr = [(trace[2 * i], trace[2 * i + 1]) for i in range(steps.value)]
+    return Bisection(lam.value, steps.value, tr, mom, st)
+
+
+def sample(N: int, n: int, seed: int, device="cuda") -> torch.Tensor:
+    idx = torch.empty(n, dtype=torch.int32, device=device)
+    ws = _ws(lib().csc_sample_workspace_bytes(N, n), device)
+    check(lib().csc_sample(N, n, seed, _ptr(idx), _ptr(ws), ws.numel(), _stream()), "csc_sample")
+    return idx
+
+
+def kmeans_reduced(F, k: int, seed: int, replicates: int = 20, max_iter: int = 100):
+    """Host k-means of the library on an n x d float32 or float64 matrix."""
+    if isinstance(F, torch.Tensor):
+        F = F.detach().cpu().numpy()
+    F = np.ascontiguousarray(F)
+    n, d = F.shape
+    labels = np.zeros(n, dtype=np.int32)
+    inertia = C.c_double(0.0)
+    if F.dtype == np.float64:
+        fn, name = lib().csc_kmeans_reduced_f64, "csc_kmeans_reduced_f64"
+    else:
+        F = F.astype(np.float32, copy=False)
+        fn, name = lib().csc_kmeans_reduced, "csc_kmeans_reduced"
+    check(fn(C.c_void_p(F.ctypes.data), n, d, d, k, replicates, max_iter, seed,
+             labels.ctypes.data_as(_lib.pi), C.byref(inertia)), name)
+    return labels, inertia.value
+
+
+@dataclass
+class Interpolation:
+    X: torch.Tensor
+    labels: torch.Tensor
+    iters: np.ndarray
+    relres: np.ndarray
+    status: int
+
+
+def interpolate(g: Graph, lam: float, p: int, gamma: float, idx, labels_r, k: int,
+                tol: float = 1e-6, max_iter: int = 1000, want_X: bool = True) -> Interpolation:
+    idx_t = _i32_device(idx, g.device)
+    lab_t = _i32_device(labels_r, g.device)
+    n = int(idx_t.numel())
+    X = torch.empty((g.n, k), dtype=torch.float32, device=g.device) if want_X else None
+    labels = torch.empty(g.n, dtype=torch.int32, device=g.device)
+    iters = np.zeros(k, dtype=np.int32)
+    relres = np.zeros(k)
+    ws = _ws(lib().csc_interpolate_workspace_bytes(g.n, k, n), g.device)
+    st = check(lib().csc_interpolate(g.ref, float(lam), p, float(gamma), _ptr(idx_t), _ptr(lab_t),
+                                     n, k, float(tol), max_iter, _ptr(X), k, _ptr(labels),
+                                     iters.ctypes.data_as(_lib.pi), relres.ctypes.data_as(_lib.pd),
+                                     _ptr(ws), ws.numel(), _stream()), "csc_interpolate")
+    return Interpolation(X, labels, iters, relres, st)
+
+
+# ------------------------------------------------------------ Alg. 2 ---------
+
+def default_n(k: int) -> int:
+    return int(math.ceil(2.0 * k * math.log(k)))
+
+
+def count_signals(N: int) -> int:
+    return int(math.ceil(2.0 * math.log(N)))
+
+
+@dataclass
+class Result:
+    lam: float
+    bisection: Bisection
+    omega: torch.Tensor
+    features: torch.Tensor
+    labels_r: np.ndarray
+    inertia: float
+    interp: Interpolation
+    timings: dict = field(default_factory=dict)
+
+    @property
+    def labels(self) -> torch.Tensor:
+        return self.interp.labels
+
+
+def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
+        gamma: float = 1e-3, n_c: int | None = None, tol: float = 1e-6, max_iter: int = 1000,
+        max_steps: int = 30, replicates: int = 20, kmeans_iter: int = 100, lam: float | None = None,
+        bracket=None, want_X: bool = False) -> Result:
+    """Compressive spectral clustering (Alg. 2) with every graph-sized step on the GPU."""
+    n = default_n(k) if n is None else n
+    n_c = count_signals(g.n) if n_c is None else n_c
+    tm = {}
+    t0 = time.perf_counter()
+    if lam is None:
+        bis = estimate_lambda_k(g, k, p, n_c, seed, max_steps, bracket)
+        lam = bis.lam
+    else:
+        bis = Bisection(lam, 0, [], np.zeros(p + 1), 0)
+    t1 = time.perf_counter()
+    omega = sample(g.n, n, seed, g.device)
+    F = filter(g, lam, p, d, seed, rows=omega, normalize=True)
+    Fh = F.cpu().numpy()
+    t2 = time.perf_counter()
+    labels_r, inertia = kmeans_reduced(Fh, k, seed, replicates, kmeans_iter)
+    t3 = time.perf_counter()
+    it = interpolate(g, lam, p, gamma, omega, labels_r, k, tol, max_iter, want_X=want_X)
+    torch.cuda.current_stream().synchronize()
+    t4 = time.perf_counter()
+    tm.update(bisection_s=t1 - t0, features_s=t2 - t1, kmeans_s=t3 - t2, interpolate_s=t4 - t3,
+              total_s=t4 - t0)
+    return Result(lam, bis, omega, F, labels_r, inertia, it, tm)

@@ -1,0 +1,635 @@
+// C ABI of libcsc: argument checks, workspace carving and the host side of
+// Alg. 2 (dichotomy loop, CG loop).  Every arithmetic step on graph-sized data
+// runs in the kernels of kernels.hip.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace csc {
+
+namespace {
+thread_local std::string g_error;
+std::atomic<int> g_panel_override{0};
+constexpr int kPanelWidths[] = {4, 8, 16, 32, 64};
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+void clear_error() { g_error.clear(); }
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int choose_panel_width(int n, int w) {
+  (void)n;
+  const int o = g_panel_override.load();
+  if (o) return o;
+  if (w <= 4) return 4;
+  if (w <= 8) return 8;
+  return 16;
+}
+
+Layout make_layout(int n, int w, int pw) {
+  Layout L;
+  L.n = n;
+  L.w = w;
+  L.pw = pw;
+  L.np = (w + pw - 1) / pw;
+  return L;
+}
+
+namespace {
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+csc_status check_graph(const csc_graph* g) {
+  CSC_REQUIRE(g != nullptr, "graph is NULL");
+  CSC_REQUIRE(g->n >= 1, "graph must have at least one node");
+  CSC_REQUIRE(g->nnz >= 0, "nnz must be non-negative");
+  CSC_REQUIRE(g->row_ptr != nullptr, "graph row_ptr is NULL");
+  CSC_REQUIRE(g->nnz == 0 || (g->col != nullptr && g->val != nullptr),
+              "graph col/val are NULL");
+  return CSC_OK;
+}
+
+csc_status check_ws(void* ws, size_t ws_bytes, size_t need) {
+  if (need == 0) return CSC_OK;
+  CSC_REQUIRE(ws != nullptr, "workspace is NULL");
+  CSC_REQUIRE(((uintptr_t)ws % 256) == 0, "workspace must be 256-byte aligned");
+  if (ws_bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes, got " +
+              std::to_string(ws_bytes));
+    return CSC_E_INVALID_ARG;
+  }
+  return CSC_OK;
+}
+
+// Jackson-Chebyshev coefficients of the ideal low-pass at lc (Sec. 4.3).
+void jackson_lowpass(double lc, int p, double* a) {
+  const double pi = 3.14159265358979323846;
+  double xc = lc - 1.0;
+  xc = xc < -1.0 ? -1.0 : (xc > 1.0 ? 1.0 : xc);
+  const double th = std::acos(xc);
+  const double al = pi / (p + 2);
+  for (int m = 0; m <= p; ++m) {
+    const double c = m == 0 ? 1.0 - th / pi : -2.0 * std::sin(m * th) / (m * pi);
+    const double g = ((p + 2 - m) * std::cos(m * al) + std::sin(m * al) / std::tan(al)) / (p + 2);
+    a[m] = g * c;
+  }
+}
+
+// Buffers of one p-step pass.
+struct Pass {
+  const float* T0 = nullptr;
+  float* Ta = nullptr;
+  float* Tb = nullptr;
+  float* Y = nullptr;
+  double* part = nullptr;  // EPI_MOM: (p+1) x nblocks; EPI_CG: columns x tiles
+  const int* slot = nullptr;
+  float* Ys = nullptr;
+  int lds = 0;
+  const float* mask = nullptr;
+  float gamma = 0.f;
+};
+
+// h~(L) applied to T0 by the Chebyshev recurrence; `epi` selects the
+// consumer of each T_{m+1}.  For epi == EPI_CG the steps before the last
+// accumulate into Y and the last one forms the CG operator.
+csc_status chebyshev_pass(const csc_graph& g, const Layout& L, const double* a, int p, int epi,
+                          const Pass& b, hipStream_t s) {
+  StepArgs sa;
+  sa.L = L;
+  sa.tiles = tiles_for(L);
+  sa.row_ptr = g.row_ptr;
+  sa.col = g.col;
+  sa.val = g.val;
+  sa.T0 = b.T0;
+  sa.Y = b.Y;
+  sa.slot = b.slot;
+  sa.Ys = b.Ys;
+  sa.lds = b.lds;
+  sa.mask = b.mask;
+  sa.gamma = b.gamma;
+  const size_t nblocks = (size_t)L.np * sa.tiles;
+  for (int m = 0; m < p; ++m) {  // step m produces T_{m+1}
+    const bool first = m == 0, last = m + 1 == p;
+    sa.Tm = first ? b.T0 : ((m & 1) ? b.Ta : b.Tb);
+    sa.Tprev = first ? b.T0 : ((m - 1) == 0 ? b.T0 : (((m - 1) & 1) ? b.Ta : b.Tb));
+    sa.Tnext = ((m + 1) & 1) ? b.Ta : b.Tb;
+    sa.c0 = (float)a[0];
+    sa.c1 = (float)a[m + 1];
+    int e = epi;
+    if (epi == EPI_MOM) {
+      sa.part = b.part + (size_t)(m + 1) * nblocks;
+      sa.part2 = b.part;
+    } else if (epi == EPI_CG) {
+      e = last ? EPI_CG : EPI_Y;
+      sa.part = b.part;
+    }
+    CSC_HIP(launch_cheb_step(sa, e, first, last, s));
+  }
+  return CSC_OK;
+}
+
+// ------------------------------------------------------ workspace plans ---
+struct FilterPlan {
+  Layout L;
+  size_t bytes = 0;
+};
+
+size_t filter_bytes(const Layout& L) {
+  size_t b = 0;
+  b += 4 * align_up(L.bytes());                // T0, Ta, Tb, Y
+  b += align_up((size_t)L.n * sizeof(int));    // slot map
+  b += align_up(4 * sizeof(int));              // bad-index flag
+  return b + 256;
+}
+
+size_t count_bytes(const Layout& L, int p) {
+  const size_t nblocks = (size_t)L.np * tiles_for(L);
+  size_t b = 3 * align_up(L.bytes());
+  b += align_up((size_t)(p + 1) * nblocks * sizeof(double));
+  b += align_up((size_t)(p + 1) * sizeof(double));
+  return b + 256;
+}
+
+size_t interp_bytes(const Layout& L) {
+  const size_t tiles = tiles_for(L), wp = (size_t)L.np * L.pw;
+  size_t b = 6 * align_up(L.bytes());
+  b += align_up((size_t)L.n * sizeof(float));          // mask
+  b += align_up(wp * tiles * sizeof(double));          // column partials
+  b += 7 * align_up(wp * sizeof(double));              // rr rrn pAp alpha beta bnorm2 colnorm2
+  b += 2 * align_up(wp * sizeof(int));                 // active iters
+  b += align_up(wp * sizeof(double));                  // relres
+  b += align_up(4 * sizeof(int));                      // nactive, breakdown
+  return b + 256;
+}
+
+template <class F>
+size_t max_over_widths(int n, int w, F f) {
+  size_t m = 0;
+  for (int pw : kPanelWidths) m = std::max(m, f(make_layout(n, w, pw)));
+  return m;
+}
+
+// ------------------------------------------------------------ eigencount ---
+struct CountBuffers {
+  float* T0;
+  float* Ta;
+  float* Tb;
+  double* part;
+  double* mom;
+};
+
+CountBuffers carve_count(Arena& ar, const Layout& L, int p) {
+  const size_t nblocks = (size_t)L.np * tiles_for(L);
+  CountBuffers c;
+  c.T0 = ar.take<float>(L.elems());
+  c.Ta = ar.take<float>(L.elems());
+  c.Tb = ar.take<float>(L.elems());
+  c.part = ar.take<double>((size_t)(p + 1) * nblocks);
+  c.mom = ar.take<double>(p + 1);
+  return c;
+}
+
+csc_status moments_pass(const csc_graph& g, const Layout& L, int p, uint64_t seed, uint32_t t,
+                        const CountBuffers& c, double* mom_host, hipStream_t s) {
+  const size_t nblocks = (size_t)L.np * tiles_for(L);
+  CSC_HIP(launch_gaussian_panels(L, seed, t, CSC_STREAM_COUNT, c.T0, s));
+  Pass b;
+  b.T0 = c.T0;
+  b.Ta = c.Ta;
+  b.Tb = c.Tb;
+  b.part = c.part;
+  std::vector<double> zero(p + 1, 0.0);
+  CSC_TRY(chebyshev_pass(g, L, zero.data(), p, EPI_MOM, b, s));
+  CSC_HIP(launch_reduce(c.part, (int)nblocks, p + 1, c.mom, s));
+  CSC_HIP(hipMemcpyAsync(mom_host, c.mom, (p + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  return CSC_OK;
+}
+
+double count_from_moments(double lambda, int p, const double* mom) {
+  std::vector<double> a(p + 1);
+  jackson_lowpass(lambda, p, a.data());
+  double c = 0.0;
+  for (int m = 0; m <= p; ++m) c += a[m] * mom[m];
+  return c;
+}
+
+}  // namespace
+}  // namespace csc
+
+using namespace csc;
+
+// ===================================================================== ABI ==
+extern "C" const char* csc_last_error(void) { return g_error.c_str(); }
+
+extern "C" int32_t csc_version(void) { return 100; }
+
+extern "C" csc_status csc_set_panel_width(int32_t pw) {
+  clear_error();
+  CSC_REQUIRE(pw == 0 || pw == 4 || pw == 8 || pw == 16 || pw == 32 || pw == 64,
+              "panel width must be 0, 4, 8, 16, 32 or 64");
+  g_panel_override.store(pw);
+  return CSC_OK;
+}
+
+extern "C" int32_t csc_get_panel_width(int32_t n, int32_t w) { return choose_panel_width(n, w); }
+
+extern "C" csc_status csc_laplacian_from_adjacency(int32_t n, int32_t nnz, const int32_t* row_ptr,
+                                                   const int32_t* col, const float* w,
+                                                   float* val_out, float* dinv_sqrt_out,
+                                                   int32_t check, void* stream) {
+  clear_error();
+  CSC_REQUIRE(n >= 1 && nnz >= 0, "n must be >= 1 and nnz >= 0");
+  CSC_REQUIRE(row_ptr && dinv_sqrt_out, "row_ptr and dinv_sqrt_out must be non-NULL");
+  CSC_REQUIRE(nnz == 0 || (col && val_out), "col and val_out must be non-NULL");
+  hipStream_t s = as_stream(stream);
+  if (check) {
+    int* flag = nullptr;
+    // the flag lives in the output array of scales until the check is done
+    flag = reinterpret_cast<int*>(dinv_sqrt_out);
+    CSC_HIP(launch_fill_i32(flag, 1, 0, s));
+    CSC_HIP(launch_check_csr(n, nnz, row_ptr, col, flag, s));
+    int h = 0;
+    CSC_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    if (h) {
+      set_error("malformed CSR (flags " + std::to_string(h) +
+                "): row_ptr must start at 0, end at nnz and be non-decreasing; columns in [0, n)");
+      return CSC_E_GRAPH;
+    }
+  }
+  CSC_HIP(launch_degree_scale(n, row_ptr, col, w, dinv_sqrt_out, s));
+  if (nnz > 0) CSC_HIP(launch_adjacency_values(n, row_ptr, col, w, dinv_sqrt_out, val_out, s));
+  return CSC_OK;
+}
+
+extern "C" csc_status csc_jackson_coeffs(double lambda_c, int32_t p, double* a_out) {
+  clear_error();
+  CSC_REQUIRE(a_out != nullptr, "a_out is NULL");
+  CSC_REQUIRE(p >= 0, "p must be >= 0");
+  CSC_REQUIRE(lambda_c >= 0.0 && lambda_c <= 2.0, "lambda_c must lie in [0, 2]");
+  jackson_lowpass(lambda_c, p, a_out);
+  return CSC_OK;
+}
+
+extern "C" csc_status csc_gaussian_block(int32_t n_rows, int32_t w, uint64_t seed, uint32_t t,
+                                         uint32_t stream_id, float* R, int32_t ld, void* stream) {
+  clear_error();
+  CSC_REQUIRE(n_rows >= 0 && w >= 1 && ld >= w, "need n_rows >= 0, w >= 1, ld >= w");
+  CSC_REQUIRE(R != nullptr || n_rows == 0, "R is NULL");
+  if (n_rows == 0) return CSC_OK;
+  CSC_HIP(launch_gaussian_rows(n_rows, w, seed, t, stream_id, R, ld, as_stream(stream)));
+  return CSC_OK;
+}
+
+extern "C" size_t csc_filter_workspace_bytes(int32_t n, int32_t w) {
+  if (n < 1 || w < 1) return 0;
+  return max_over_widths(n, w, [](const Layout& L) { return filter_bytes(L); });
+}
+
+namespace {
+csc_status filter_common(const csc_graph* g, const double* a, int p, int w, const float* Xin,
+                         int ldx, bool draw, uint64_t seed, const int32_t* rows, int n_rows,
+                         int normalize, float* Y, int ld, void* ws, size_t ws_bytes,
+                         hipStream_t s) {
+  const int n = g->n;
+  const Layout L = make_layout(n, w, choose_panel_width(n, w));
+  CSC_TRY(check_ws(ws, ws_bytes, filter_bytes(L)));
+  Arena ar(ws, ws_bytes);
+  float* T0 = ar.take<float>(L.elems());
+  float* Ta = ar.take<float>(L.elems());
+  float* Tb = ar.take<float>(L.elems());
+  float* Yi = ar.take<float>(L.elems());
+  int* slot = ar.take<int>(n);
+  int* bad = ar.take<int>(4);
+  if (draw)
+    CSC_HIP(launch_gaussian_panels(L, seed, 0, CSC_STREAM_FEAT, T0, s));
+  else
+    CSC_HIP(launch_pack(L, Xin, ldx, T0, s));
+  Pass b;
+  b.T0 = T0;
+  b.Ta = Ta;
+  b.Tb = Tb;
+  if (rows) {
+    CSC_HIP(launch_fill_i32(slot, n, -1, s));
+    CSC_HIP(launch_fill_i32(bad, 1, 0, s));
+    CSC_HIP(launch_slot_map(n_rows, rows, n, slot, bad, s));
+    int hbad = 0;
+    CSC_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    if (hbad) {
+      set_error("rows holds an index outside [0, N)");
+      return CSC_E_INVALID_ARG;
+    }
+    b.slot = slot;
+    b.Ys = Y;
+    b.lds = ld;
+    CSC_TRY(chebyshev_pass(*g, L, a, p, EPI_YS, b, s));
+    if (normalize) CSC_HIP(launch_normalize_rows(n_rows, w, Y, ld, s));
+  } else {
+    b.Y = Yi;
+    CSC_TRY(chebyshev_pass(*g, L, a, p, EPI_Y, b, s));
+    CSC_HIP(launch_unpack(L, Yi, Y, ld, normalize, s));
+  }
+  return CSC_OK;
+}
+}  // namespace
+
+extern "C" csc_status csc_filter_block(const csc_graph* g, const double* coeffs, int32_t p,
+                                       const float* X, int32_t w, int32_t ld, float* Y, void* ws,
+                                       size_t ws_bytes, void* stream) {
+  clear_error();
+  CSC_TRY(check_graph(g));
+  CSC_REQUIRE(coeffs && X && Y, "coeffs, X and Y must be non-NULL");
+  CSC_REQUIRE(p >= 1, "p must be >= 1");
+  CSC_REQUIRE(w >= 1 && ld >= w, "need w >= 1 and ld >= w");
+  return filter_common(g, coeffs, p, w, X, ld, false, 0, nullptr, 0, 0, Y, ld, ws, ws_bytes,
+                       as_stream(stream));
+}
+
+extern "C" csc_status csc_filter(const csc_graph* g, double lambda_c, int32_t p, int32_t d,
+                                 uint64_t seed, const int32_t* rows, int32_t n_rows,
+                                 int32_t normalize, float* Y, int32_t ld, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  clear_error();
+  CSC_TRY(check_graph(g));
+  CSC_REQUIRE(Y != nullptr, "Y is NULL");
+  CSC_REQUIRE(p >= 1, "p must be >= 1");
+  CSC_REQUIRE(d >= 1 && ld >= d, "need d >= 1 and ld >= d");
+  CSC_REQUIRE(lambda_c >= 0.0 && lambda_c <= 2.0, "lambda_c must lie in [0, 2]");
+  CSC_REQUIRE(rows == nullptr || (n_rows >= 1 && n_rows <= g->n),
+              "n_rows must lie in [1, N] when rows is given");
+  std::vector<double> a(p + 1);
+  jackson_lowpass(lambda_c, p, a.data());
+  return filter_common(g, a.data(), p, d, nullptr, 0, true, seed, rows, n_rows, normalize, Y, ld,
+                       ws, ws_bytes, as_stream(stream));
+}
+
+extern "C" size_t csc_estimate_workspace_bytes(int32_t n, int32_t n_signals, int32_t p) {
+  if (n < 1 || n_signals < 1 || p < 1) return 0;
+  return max_over_widths(n, n_signals, [p](const Layout& L) { return count_bytes(L, p); });
+}
+
+extern "C" csc_status csc_eigencount(const csc_graph* g, double lambda, int32_t p,
+                                     int32_t n_signals, uint64_t seed, uint32_t t,
+                                     double* count_out, double* moments_out, void* ws,
+                                     size_t ws_bytes, void* stream) {
+  clear_error();
+  CSC_TRY(check_graph(g));
+  CSC_REQUIRE(count_out != nullptr, "count_out is NULL");
+  CSC_REQUIRE(p >= 1 && n_signals >= 1, "need p >= 1 and n_signals >= 1");
+  CSC_REQUIRE(lambda >= 0.0 && lambda <= 2.0, "lambda must lie in [0, 2]");
+  const Layout L = make_layout(g->n, n_signals, choose_panel_width(g->n, n_signals));
+  CSC_TRY(check_ws(ws, ws_bytes, count_bytes(L, p)));
+  Arena ar(ws, ws_bytes);
+  const CountBuffers c = carve_count(ar, L, p);
+  std::vector<double> mom(p + 1);
+  CSC_TRY(moments_pass(*g, L, p, seed, t, c, mom.data(), as_stream(stream)));
+  *count_out = count_from_moments(lambda, p, mom.data());
+  if (moments_out) std::memcpy(moments_out, mom.data(), (p + 1) * sizeof(double));
+  return CSC_OK;
+}
+
+extern "C" csc_status csc_estimate_lambda_k(const csc_graph* g, int32_t k, int32_t p,
+                                            int32_t n_signals, uint64_t seed, int32_t max_steps,
+                                            const double* bracket, double* lambda_out,
+                                            int32_t* steps_out, double* trace_out,
+                                            double* moments_out, void* ws, size_t ws_bytes,
+                                            void* stream) {
+  clear_error();
+  CSC_TRY(check_graph(g));
+  CSC_REQUIRE(lambda_out && steps_out, "lambda_out and steps_out must be non-NULL");
+  CSC_REQUIRE(k >= 1 && k <= g->n, "k must lie in [1, N]");
+  CSC_REQUIRE(p >= 1 && n_signals >= 1 && max_steps >= 1,
+              "need p >= 1, n_signals >= 1, max_steps >= 1");
+  double lo = 0.0, hi = 2.0;
+  if (bracket) {
+    CSC_REQUIRE(bracket[0] >= 0.0 && bracket[1] <= 2.0 && bracket[0] < bracket[1],
+                "bracket must satisfy 0 <= lo < hi <= 2");
+    lo = bracket[0];
+    hi = bracket[1];
+  }
+  const Layout L = make_layout(g->n, n_signals, choose_panel_width(g->n, n_signals));
+  CSC_TRY(check_ws(ws, ws_bytes, count_bytes(L, p)));
+  Arena ar(ws, ws_bytes);
+  const CountBuffers c = carve_count(ar, L, p);
+  hipStream_t s = as_stream(stream);
+  std::vector<double> mom(p + 1);
+  int used = 0;
+  bool below = false, above = false, missed = false;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    for (int t = 1; t <= max_steps; ++t) {
+      const double mid = 0.5 * (lo + hi);
+      CSC_TRY(moments_pass(*g, L, p, seed, (uint32_t)(used + 1), c, mom.data(), s));
+      if (used == 0 && moments_out) std::memcpy(moments_out, mom.data(), (p + 1) * sizeof(double));
+      const double cnt = count_from_moments(mid, p, mom.data());
+      if (trace_out) {
+        trace_out[2 * used] = mid;
+        trace_out[2 * used + 1] = cnt;
+      }
+      ++used;
+      if (std::floor(cnt + 0.5) == (double)k) {
+        *lambda_out = mid;
+        *steps_out = used;
+        return missed ? CSC_W_BRACKET_MISS : CSC_OK;
+      }
+      if (cnt < k) {
+        lo = mid;
+        below = true;
+      } else {
+        hi = mid;
+        above = true;
+      }
+    }
+    // exhausted: with a caller bracket, a one-sided history means lambda_k lies outside
+    if (bracket && attempt == 0 && !(below && above)) {
+      missed = true;
+      lo = 0.0;
+      hi = 2.0;
+      continue;
+    }
+    break;
+  }
+  *lambda_out = hi;
+  *steps_out = used;
+  return missed ? CSC_W_BRACKET_MISS : CSC_W_BISECT_EXHAUSTED;
+}
+
+extern "C" size_t csc_sample_workspace_bytes(int32_t N, int32_t n) {
+  if (N < 1 || n < 1) return 0;
+  const int nch = sample_chunks(N);
+  size_t b = 2 * align_up((size_t)nch * sizeof(int)) + align_up(4 * sizeof(int));
+  b += 2 * align_up((size_t)N * sizeof(uint64_t)) + 2 * align_up((size_t)N * sizeof(int));
+  b += align_up(sort_pairs_temp_bytes(N));
+  return b + 256;
+}
+
+extern "C" csc_status csc_sample(int32_t N, int32_t n, uint64_t seed, int32_t* idx, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  clear_error();
+  CSC_REQUIRE(N >= 1 && n >= 1 && n <= N, "need 1 <= n <= N");
+  CSC_REQUIRE(idx != nullptr, "idx is NULL");
+  CSC_TRY(check_ws(ws, ws_bytes, csc_sample_workspace_bytes(N, n)));
+  hipStream_t s = as_stream(stream);
+  const int nch = sample_chunks(N);
+  Arena ar(ws, ws_bytes);
+  int* counts = ar.take<int>(nch);
+  int* offsets = ar.take<int>(nch);
+  int* total = ar.take<int>(4);
+  uint64_t* kin = ar.take<uint64_t>(N);
+  uint64_t* kout = ar.take<uint64_t>(N);
+  int* vin = ar.take<int>(N);
+  int* vout = ar.take<int>(N);
+  const size_t temp_bytes = sort_pairs_temp_bytes(N);
+  void* temp = ar.take<char>(temp_bytes);
+  // Keys are uniform on [0, 2^64); keep those below a threshold expected to
+  // admit n + 8 sqrt(n) + 64 nodes and widen it if fewer than n made it.
+  double frac = ((double)n + 8.0 * std::sqrt((double)n) + 64.0) / (double)N;
+  for (int attempt = 0; attempt < 64; ++attempt) {
+    const uint64_t thresh =
+        frac >= 1.0 ? ~0ull : (uint64_t)std::ldexp(frac, 64);
+    CSC_HIP(launch_sample_count(N, seed, thresh, counts, s));
+    CSC_HIP(launch_scan_counts(counts, nch, offsets, total, s));
+    int h_total = 0;
+    CSC_HIP(hipMemcpyAsync(&h_total, total, sizeof(int), hipMemcpyDeviceToHost, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    if (h_total < n) {
+      frac *= 2.0;
+      continue;
+    }
+    if (sort_pairs_temp_bytes(h_total) > temp_bytes) {
+      set_error("internal: sort scratch too small");
+      return CSC_E_INVALID_ARG;
+    }
+    CSC_HIP(launch_sample_write(N, seed, thresh, offsets, kin, vin, s));
+    CSC_HIP(sort_pairs(temp, temp_bytes, kin, kout, vin, vout, h_total, s));
+    CSC_HIP(hipMemcpyAsync(idx, vout, (size_t)n * sizeof(int), hipMemcpyDeviceToDevice, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    return CSC_OK;
+  }
+  set_error("sampling threshold did not admit n keys");
+  return CSC_E_INVALID_ARG;
+}
+
+extern "C" size_t csc_interpolate_workspace_bytes(int32_t N, int32_t k, int32_t n) {
+  if (N < 1 || k < 1 || n < 1) return 0;
+  return max_over_widths(N, k, [](const Layout& L) { return interp_bytes(L); });
+}
+
+extern "C" csc_status csc_interpolate(const csc_graph* g, double lambda_k, int32_t p,
+                                      double gamma, const int32_t* idx, const int32_t* labels_r,
+                                      int32_t n, int32_t k, double tol, int32_t max_iter,
+                                      float* X, int32_t ldx, int32_t* labels, int32_t* iters_out,
+                                      double* relres_out, void* ws, size_t ws_bytes,
+                                      void* stream) {
+  clear_error();
+  CSC_TRY(check_graph(g));
+  const int N = g->n;
+  CSC_REQUIRE(idx && labels_r && labels, "idx, labels_r and labels must be non-NULL");
+  CSC_REQUIRE(k >= 1 && k <= N && n >= 1 && n <= N, "need 1 <= k <= N and 1 <= n <= N");
+  CSC_REQUIRE(p >= 1 && gamma > 0.0 && tol > 0.0 && max_iter >= 1,
+              "need p >= 1, gamma > 0, tol > 0, max_iter >= 1");
+  CSC_REQUIRE(lambda_k >= 0.0 && lambda_k <= 2.0, "lambda_k must lie in [0, 2]");
+  CSC_REQUIRE(X == nullptr || ldx >= k, "ldx must be >= k");
+  const Layout L = make_layout(N, k, choose_panel_width(N, k));
+  CSC_TRY(check_ws(ws, ws_bytes, interp_bytes(L)));
+  hipStream_t s = as_stream(stream);
+  const int tiles = tiles_for(L);
+  const size_t wp = (size_t)L.np * L.pw;
+  Arena ar(ws, ws_bytes);
+  float* P = ar.take<float>(L.elems());
+  float* Ta = ar.take<float>(L.elems());
+  float* Tb = ar.take<float>(L.elems());
+  float* AP = ar.take<float>(L.elems());
+  float* Xi = ar.take<float>(L.elems());
+  float* Rr = ar.take<float>(L.elems());
+  float* mask = ar.take<float>(N);
+  double* part = ar.take<double>(wp * tiles);
+  double* rr = ar.take<double>(wp);
+  double* rrn = ar.take<double>(wp);
+  double* pAp = ar.take<double>(wp);
+  double* alpha = ar.take<double>(wp);
+  double* beta = ar.take<double>(wp);
+  double* bnorm2 = ar.take<double>(wp);
+  double* colnorm2 = ar.take<double>(wp);
+  int* active = ar.take<int>(wp);
+  int* iters = ar.take<int>(wp);
+  double* relres = ar.take<double>(wp);
+  int* flags = ar.take<int>(4);  // nactive, breakdown
+
+  CSC_HIP(launch_fill_f32(P, L.elems(), 0.f, s));
+  CSC_HIP(launch_fill_f32(Xi, L.elems(), 0.f, s));
+  CSC_HIP(launch_fill_f32(Rr, L.elems(), 0.f, s));
+  CSC_HIP(launch_fill_f32(mask, N, 0.f, s));
+  CSC_HIP(launch_fill_i32(iters, wp, 0, s));
+  CSC_HIP(launch_fill_f64(relres, wp, 0.0, s));
+  CSC_HIP(launch_fill_i32(flags, 4, 0, s));
+  CSC_HIP(launch_cg_scatter(L, n, idx, labels_r, Rr, P, mask, flags + 2, s));
+  CSC_HIP(launch_col_dot(L, Rr, Rr, part, s));
+  CSC_HIP(launch_reduce(part, tiles, k, bnorm2, s));
+  // rr = bnorm2; active = bnorm2 > 0 (beta doubles as the activity probe)
+  CSC_HIP(hipMemcpyAsync(rr, bnorm2, k * sizeof(double), hipMemcpyDeviceToDevice, s));
+  {
+    std::vector<double> hb(k);
+    CSC_HIP(hipMemcpyAsync(hb.data(), bnorm2, k * sizeof(double), hipMemcpyDeviceToHost, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    int hbad = 0;
+    CSC_HIP(hipMemcpyAsync(&hbad, flags + 2, sizeof(int), hipMemcpyDeviceToHost, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    if (hbad) {
+      set_error("idx or labels_r holds a value out of range");
+      return CSC_E_INVALID_ARG;
+    }
+    std::vector<int> ha(k);
+    for (int j = 0; j < k; ++j) ha[j] = hb[j] > 0.0 ? 1 : 0;
+    CSC_HIP(hipMemcpyAsync(active, ha.data(), k * sizeof(int), hipMemcpyHostToDevice, s));
+    CSC_HIP(hipStreamSynchronize(s));
+  }
+
+  std::vector<double> a(p + 1);
+  jackson_lowpass(lambda_k, p, a.data());
+  Pass b;
+  b.T0 = P;
+  b.Ta = Ta;
+  b.Tb = Tb;
+  b.Y = AP;
+  b.part = part;
+  b.mask = mask;
+  b.gamma = (float)gamma;
+  int it = 0, nactive = 1;
+  for (it = 1; it <= max_iter; ++it) {
+    CSC_TRY(chebyshev_pass(*g, L, a.data(), p, EPI_CG, b, s));
+    CSC_HIP(launch_reduce(part, tiles, k, pAp, s));
+    CSC_HIP(launch_cg_alpha(k, rr, pAp, active, alpha, flags + 1, s));
+    CSC_HIP(launch_cg_update1(L, AP, P, Xi, Rr, alpha, part, s));
+    CSC_HIP(launch_reduce(part, tiles, k, rrn, s));
+    CSC_HIP(launch_cg_scalar(k, rrn, rr, bnorm2, beta, active, iters, relres, it, tol, flags, s));
+    CSC_HIP(launch_cg_update2(L, Rr, P, beta, active, s));
+    CSC_HIP(hipMemcpyAsync(&nactive, flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    if (nactive == 0) break;
+  }
+  CSC_HIP(launch_col_dot(L, Xi, Xi, part, s));
+  CSC_HIP(launch_reduce(part, tiles, k, colnorm2, s));
+  CSC_HIP(launch_labels(L, Xi, colnorm2, labels, X, ldx, s));
+  std::vector<int> hit(k);
+  std::vector<double> hrel(k);
+  int breakdown = 0;
+  CSC_HIP(hipMemcpyAsync(hit.data(), iters, k * sizeof(int), hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipMemcpyAsync(hrel.data(), relres, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipMemcpyAsync(&breakdown, flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  if (iters_out) std::memcpy(iters_out, hit.data(), k * sizeof(int));
+  if (relres_out) std::memcpy(relres_out, hrel.data(), k * sizeof(double));
+  if (breakdown) {
+    set_error("CG breakdown: p^T A p <= 0 in some column");
+    return CSC_W_NOT_CONVERGED;
+  }
+  return nactive > 0 ? CSC_W_NOT_CONVERGED : CSC_OK;
+}

@@ -1,0 +1,98 @@
+// Launch wrappers of the libcsc device kernels (kernels.hip).
+#pragma once
+
+#include "common.hpp"
+
+namespace csc {
+
+enum Epi : int {
+  EPI_Y = 0,    // Y (panel-major) accumulates coefficient * T_{m+1}
+  EPI_MOM = 1,  // float64 partial of <T_0, T_{m+1}> per workgroup
+  EPI_YS = 2,   // only sampled rows accumulate, straight into a node-major output
+  EPI_CG = 3,   // last step of the CG operator: AP = mask*P + gamma*(P - h~(L)P)
+};
+
+struct StepArgs {
+  Layout L;
+  int tiles = 0;  // row tiles per panel
+  const int* row_ptr = nullptr;
+  const int* col = nullptr;
+  const float* val = nullptr;
+  const float* Tm = nullptr;     // T_m, gathered through A
+  const float* Tprev = nullptr;  // T_{m-1}; on the first step T_0
+  float* Tnext = nullptr;        // T_{m+1} (may alias Tprev)
+  const float* T0 = nullptr;     // T_0 (moments, CG)
+  float* Y = nullptr;            // accumulator (EPI_Y, EPI_CG)
+  float c0 = 0.f, c1 = 0.f;      // first step: Y = c0 T_0 + c1 T_1; later: Y += c1 T_{m+1}
+  double* part = nullptr;        // partial sums
+  double* part2 = nullptr;       // second partial on the first moment step (mu_0)
+  const int* slot = nullptr;     // EPI_YS: output row of node i or -1
+  float* Ys = nullptr;
+  int lds = 0;
+  const float* mask = nullptr;   // EPI_CG
+  float gamma = 0.f;
+};
+
+int rows_per_tile(int pw);
+int tiles_for(const Layout& L);
+
+hipError_t launch_cheb_step(const StepArgs& a, int epi, bool first, bool last, hipStream_t s);
+
+// Laplacian scaling.
+hipError_t launch_degree_scale(int n, const int* row_ptr, const int* col, const float* w,
+                               float* dinv_sqrt, hipStream_t s);
+hipError_t launch_adjacency_values(int n, const int* row_ptr, const int* col, const float* w,
+                                   const float* dinv_sqrt, float* val, hipStream_t s);
+hipError_t launch_check_csr(int n, int nnz, const int* row_ptr, const int* col, int* flag,
+                            hipStream_t s);
+
+// Random blocks.
+hipError_t launch_gaussian_panels(const Layout& L, uint64_t seed, uint32_t t, uint32_t stream_id,
+                                  float* out, hipStream_t s);
+hipError_t launch_gaussian_rows(int n_rows, int w, uint64_t seed, uint32_t t, uint32_t stream_id,
+                                float* R, int ld, hipStream_t s);
+
+// Layout conversion and row scaling.
+hipError_t launch_pack(const Layout& L, const float* X, int ld, float* out, hipStream_t s);
+hipError_t launch_unpack(const Layout& L, const float* in, float* Y, int ld, int normalize,
+                         hipStream_t s);
+hipError_t launch_normalize_rows(int n_rows, int w, float* Y, int ld, hipStream_t s);
+hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s);
+hipError_t launch_fill_i32(int* p, size_t n, int v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s);
+hipError_t launch_slot_map(int n_rows, const int* rows, int n, int* slot, int* bad,
+                           hipStream_t s);
+
+// Deterministic reductions: out[v] = sum_t part[v * len + t], fixed order.
+hipError_t launch_reduce(const double* part, int len, int nvec, double* out, hipStream_t s);
+// part[c * tiles + tile] = sum over the tile's rows of A(i, c) * B(i, c).
+hipError_t launch_col_dot(const Layout& L, const float* A, const float* B, double* part,
+                          hipStream_t s);
+
+// Sampling by smallest keys.
+int sample_chunks(int N);
+hipError_t launch_sample_count(int N, uint64_t seed, uint64_t thresh, int* counts, hipStream_t s);
+hipError_t launch_scan_counts(const int* counts, int nchunks, int* offsets, int* total,
+                              hipStream_t s);
+hipError_t launch_sample_write(int N, uint64_t seed, uint64_t thresh, const int* offsets,
+                               uint64_t* keys, int* idx, hipStream_t s);
+size_t sort_pairs_temp_bytes(int count);
+hipError_t sort_pairs(void* temp, size_t temp_bytes, const uint64_t* kin, uint64_t* kout,
+                      const int* vin, int* vout, int count, hipStream_t s);
+
+// Conjugate gradient.
+hipError_t launch_cg_scatter(const Layout& L, int n, const int* idx, const int* lab, float* R,
+                             float* P, float* mask, int* bad, hipStream_t s);
+hipError_t launch_cg_alpha(int k, const double* rr, const double* pAp, int* active,
+                           double* alpha, int* breakdown, hipStream_t s);
+hipError_t launch_cg_update1(const Layout& L, const float* AP, const float* P, float* X, float* R,
+                             const double* alpha, double* part, hipStream_t s);
+hipError_t launch_cg_scalar(int k, const double* rrn, double* rr, const double* bnorm2,
+                            double* beta, int* active, int* iters, double* relres, int it,
+                            double tol, int* nactive, hipStream_t s);
+hipError_t launch_cg_update2(const Layout& L, const float* R, float* P, const double* beta,
+                             const int* active, hipStream_t s);
+hipError_t launch_labels(const Layout& L, const float* X, const double* colnorm2, int* labels,
+                         float* Xout, int ldx, hipStream_t s);
+
+}  // namespace csc

@@ -1,0 +1,117 @@
+"""CPU checks of the C ABI: the library loads, exports what include/csc.h
+declares, rejects bad arguments before touching the GPU, and its host-side
+k-means matches the oracle exactly on identical float64 inputs."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1602_02018_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(csc_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_header_declares_the_five_calls():
+    names = declared_functions()
+    for n in ("csc_estimate_lambda_k", "csc_filter", "csc_sample", "csc_kmeans_reduced",
+              "csc_interpolate"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(_lib.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(_lib.PROTOTYPES) == set(declared_functions())
+
+
+def test_version_and_panel_width_validation():
+    lib = _lib.lib()
+    assert lib.csc_version() >= 100
+    assert lib.csc_set_panel_width(3) == _lib.CSC_E_INVALID_ARG
+    assert b"panel width" in lib.csc_last_error()
+    assert lib.csc_set_panel_width(8) == _lib.CSC_OK
+    assert lib.csc_get_panel_width(1000, 47) == 8
+    assert lib.csc_set_panel_width(0) == _lib.CSC_OK
+
+
+def test_argument_errors_are_reported_without_gpu_work():
+    lib = _lib.lib()
+    assert lib.csc_sample(10, 0, 0, None, None, 0, None) == _lib.CSC_E_INVALID_ARG
+    assert lib.csc_sample(10, 11, 0, None, None, 0, None) == _lib.CSC_E_INVALID_ARG
+    assert lib.csc_filter(None, 0.5, 50, 4, 0, None, 0, 1, None, 4, None, 0, None) == _lib.CSC_E_INVALID_ARG
+    assert lib.csc_laplacian_from_adjacency(0, 0, None, None, None, None, None, 0, None) == _lib.CSC_E_INVALID_ARG
+    g = _lib.CscGraph(10, 0, 0, 0, 0, 0)
+    assert lib.csc_filter(C.byref(g), 0.5, 50, 4, 0, None, 0, 1, None, 4, None, 0, None) == _lib.CSC_E_INVALID_ARG
+    assert b"row_ptr" in lib.csc_last_error()
+    g = _lib.CscGraph(10, 0, 16, 0, 0, 0)
+    assert lib.csc_filter(C.byref(g), 2.5, 50, 4, 0, None, 0, 1, C.c_void_p(16), 4, None, 0, None) == _lib.CSC_E_INVALID_ARG
+    assert b"lambda_c" in lib.csc_last_error()
+    # workspace too small is caught before any launch
+    assert lib.csc_filter(C.byref(g), 0.5, 50, 4, 0, None, 0, 1, C.c_void_p(16), 4,
+                          C.c_void_p(256), 8, None) == _lib.CSC_E_INVALID_ARG
+    assert b"workspace too small" in lib.csc_last_error()
+    lam = C.c_double()
+    st = C.c_int32()
+    assert lib.csc_estimate_lambda_k(C.byref(g), 11, 50, 4, 0, 30, None, C.byref(lam), C.byref(st),
+                                     None, None, None, 0, None) == _lib.CSC_E_INVALID_ARG
+    assert lib.csc_interpolate(C.byref(g), 0.5, 50, 0.0, C.c_void_p(16), C.c_void_p(16), 2, 2, 1e-6,
+                               10, None, 2, C.c_void_p(16), None, None, None, 0, None) == _lib.CSC_E_INVALID_ARG
+
+
+def test_workspace_sizes_grow_with_problem():
+    lib = _lib.lib()
+    a = lib.csc_filter_workspace_bytes(1000, 28)
+    b = lib.csc_filter_workspace_bytes(100000, 47)
+    assert 0 < a < b
+    assert lib.csc_filter_workspace_bytes(0, 4) == 0
+    assert lib.csc_estimate_workspace_bytes(1000, 14, 50) > 3 * 1000 * 14 * 4
+    assert lib.csc_interpolate_workspace_bytes(1000, 10, 47) > 6 * 1000 * 10 * 4
+    assert lib.csc_sample_workspace_bytes(1000, 47) > 1000 * 24
+
+
+def test_jackson_coefficients_host_call_matches_oracle():
+    from oracle import jackson
+    from paper_1602_02018_amd import api
+
+    for lc, p in ((0.3, 50), (1.7, 60), (0.0, 10), (2.0, 10), (1.0, 0)):
+        np.testing.assert_allclose(api.jackson_coeffs(lc, p), jackson.lowpass_coeffs(lc, p),
+                                   rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed,n,d,k", [(0, 47, 28, 10), (3, 300, 12, 25), (5, 922, 47, 100)])
+def test_host_kmeans_matches_oracle_exactly(seed, n, d, k):
+    from oracle import kmeans
+    from paper_1602_02018_amd import api
+
+    rng = np.random.default_rng(seed)
+    centers = rng.normal(size=(k, d))
+    X = centers[rng.integers(0, k, n)] + 0.3 * rng.normal(size=(n, d))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    reps = 20 if n < 500 else 4
+    lab, _, inertia = kmeans.kmeans(X, k, seed, replicates=reps)
+    lab2, inertia2 = api.kmeans_reduced(X, k, seed, replicates=reps)
+    assert np.array_equal(lab, lab2)
+    assert inertia == inertia2
+
+
+def test_host_kmeans_float32_input_and_errors():
+    from paper_1602_02018_amd import api
+
+    X = np.random.default_rng(0).normal(size=(50, 4)).astype(np.float32)
+    lab, inertia = api.kmeans_reduced(X, 3, 0)
+    assert lab.min() >= 0 and lab.max() < 3 and inertia > 0
+    with pytest.raises(_lib.CscError):
+        api.kmeans_reduced(X, 51, 0)
