@@ -1,0 +1,252 @@
+"""Benchmark of the compressive spectral clustering hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sbm-1e5]
+
+A step is one pass of the whole path over one synthetic graph already
+resident in HBM: lambda_k dichotomy (eigencount passes), feature pass,
+sampling, k-means on the sampled features, interpolation by CG and the hard
+labels.  Prints one JSON line:
+
+* value: whole-job throughput in GB/s, the algorithmic bytes of every
+  Chebyshev step, random block and CG update in the step divided by the wall
+  time of the step;
+* roofline: the dominant kernel, the Chebyshev step of the CG operator at width
+  k, timed per launch with HIP events on the stream it runs on, against the
+  MI355X HBM peak (8 TB/s); its HBM traffic comes from rocprofv3 FETCH_SIZE /
+  WRITE_SIZE counters recorded in profiles/ and is null when the kernel source
+  changed since they were taken;
+* cpu_baseline: the float64 CPU oracle's filter pass (p products of the CSR
+  matrix with an N x k block) on the same graph, in the same unit.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1602_02018_amd", "csrc", "kernels.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "cheb_step_cg_sbm_N1e5_k100_counters.txt")
+
+WORKLOADS = {
+    # SBM N = 1e5, k = 100, mean degree 16, eps = eps_c / 4; d = ceil(4 ln N), p = 50
+    "sbm-1e5": dict(N=100000, k=100, s=16.0, p=50, model="sbm"),
+    # Chung-Lu N = 1e6, power-law degrees (exponent 2.5, mean 20, max 2000), k = 250 blocks
+    "chunglu-1e6": dict(N=1000000, k=250, p=60, model="chunglu"),
+    # SBM N = 1000, k = 10 (oracle-sized)
+    "sbm-1e3": dict(N=1000, k=10, s=16.0, p=50, model="sbm"),
+}
+
+
+def step_bytes(N, nnz, w, kind):
+    """Algorithmic bytes of one Chebyshev step (float32 blocks, int32 indices).
+
+    CSR read once (4(N+1) + 8 nnz) plus, per node and column, 4 bytes for each
+    block touched: gathered T_m, T_{m-1}, T_{m+1} and the accumulator
+    read + write (kind "y": 20), or T_0 instead of the accumulator ("mom": 16).
+    """
+    csr = 4 * (N + 1) + 8 * nnz
+    per = {"y": 20, "mom": 16, "ys": 12}[kind]
+    return csr + per * N * w
+
+
+def job_bytes(N, nnz, k, d, n_c, p, bis_steps, cg_iters):
+    gauss = 4 * N
+    count = bis_steps * (gauss * n_c + p * step_bytes(N, nnz, n_c, "mom"))
+    feat = gauss * d + p * step_bytes(N, nnz, d, "ys")
+    cg = cg_iters * (p * step_bytes(N, nnz, k, "y") + 36 * N * k)
+    return count + feat + cg
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic(per_launch_alg_bytes):
+    """HBM bytes per launch from the committed counter summary, or None."""
+    if not os.path.exists(COUNTERS):
+        return None
+    rec = {}
+    for line in open(COUNTERS):
+        if line.startswith("#") or "=" not in line:
+            continue
+        key, val = line.split("=", 1)
+        rec[key.strip()] = val.strip()
+    if rec.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_graph(wl, seed):
+    import synth
+
+    if wl["model"] == "sbm":
+        return synth.sbm_config(wl["N"], wl["k"], s=wl["s"], seed=seed)
+    return synth.chung_lu_blocks(wl["N"], wl["k"], seed=seed)
+
+
+def cpu_baseline(gr, k, p, budget_s=30.0):
+    """Oracle filter pass on an N x k block; fewer columns if it would run long."""
+    import numpy as np
+
+    from oracle import cheb, jackson, laplacian, philox
+
+    A, _ = laplacian.normalized_adjacency(gr.row_ptr, gr.col)
+    a = jackson.lowpass_coeffs(0.4, p)
+    # time one product to bound the sample at ~budget_s of CPU work
+    X1 = philox.gaussian_block(0, gr.n, k, 0, philox.FEAT)
+    t0 = time.perf_counter()
+    _ = A @ X1
+    one = time.perf_counter() - t0
+    w = k
+    if one * p > budget_s:
+        w = max(1, int(k * budget_s / (one * p)))
+    X = X1[:, :w].copy()
+    t0 = time.perf_counter()
+    cheb.filter_block(A, X, a)
+    t = time.perf_counter() - t0
+    by = p * step_bytes(gr.n, gr.nnz, w, "y")
+    return {
+        "value": round(by / t / 1e9, 3),
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"float64 oracle filter pass, p={p} products of the {gr.n}-node CSR matrix "
+                  f"with an N x {w} block (the CG operator's filter), {t:.1f} s; scipy's CSR "
+                  f"product runs on one thread; host reports {os.cpu_count()} CPUs",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sbm-1e5", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 256 MiB device copy (for scaling memory counters)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        x = torch.ones(64 * 2**20, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4,
+                          "dispatches": 3}), flush=True)
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the path shards by columns across GPUs, which this build does not run)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from oracle.metrics import adjusted_rand_index  # ARI of the labels only
+    from paper_1602_02018_amd import api
+
+    wl = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    gr = make_graph(wl, args.seed)
+    N, nnz, k, p = gr.n, gr.nnz, wl["k"], wl["p"]
+    d = int(math.ceil(4 * math.log(N)))
+    n_c = api.count_signals(N)
+    g = api.Graph(gr.row_ptr, gr.col, dev)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        api.run(g, k, d, args.seed, p=p)
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        results.append(api.run(g, k, d, args.seed, p=p))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+
+    total = 0.0
+    for r in results:
+        total += job_bytes(N, nnz, k, d, n_c, p, r.bisection.steps, int(r.interp.iters.max()))
+    value = total / elapsed / 1e9
+    last = results[-1]
+    ari = adjusted_rand_index(last.labels.cpu().numpy(), gr.truth)
+
+    # dominant kernel: Chebyshev step of the CG operator (width k), per-launch time
+    st = api.StepTimer(g, k, 0)
+    st.launch(10)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    launches = args.kernel_reps * p
+    e0.record()
+    for _ in range(args.kernel_reps):
+        st.launch(p)
+    e1.record()
+    torch.cuda.synchronize()
+    avg_s = e0.elapsed_time(e1) / 1e3 / launches
+    per_launch = step_bytes(N, nnz, k, "y")
+    achieved = per_launch / avg_s / 1e9
+    traffic = read_traffic(per_launch)
+
+    out = {
+        "metric": "filter SpMM HBM GB/s (% peak) + end-to-end CSC s/graph vs plain at ARI>=0.99",
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {wl['model']} N={N} nnz={nnz} k={k} d={d} p={p} "
+                        f"n={api.default_n(k)} n_c={n_c} gamma=1e-3 tol=1e-6",
+            "plain": True,
+        },
+        "s_per_graph": round(ms_per_step / 1e3, 4),
+        "phases_s": {kk: round(v, 4) for kk, v in last.timings.items()},
+        "bisection_steps": last.bisection.steps,
+        "lambda_k": last.lam,
+        "cg_iters_max": int(last.interp.iters.max()),
+        "ari_vs_truth": round(float(ari), 4),
+        "roofline": {
+            "kernel": f"k_cheb_step<EPI_Y> (CG operator pass, w={k}, "
+                      f"panel width {api.panel_width(N, k, nnz)})",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "alg_bytes_per_launch": per_launch,
+            "avg_launch_us": round(avg_s * 1e6, 2),
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(gr, k, p)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

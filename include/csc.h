@@ -83,14 +83,30 @@ const char* csc_last_error(void);
 int32_t csc_version(void);
 
 /* Tuning.  Dense blocks inside the library are stored as panels of PW
- * columns (PW in {4, 8, 16, 32, 64}); a Chebyshev step gathers neighbour rows
- * of one panel at a time.  csc_set_panel_width(pw) forces PW for every later
+ * columns (PW a multiple of 4 in [4, 256]); a Chebyshev step gathers
+ * neighbour rows of one panel at a time.  csc_set_panel_width(pw) forces PW for every later
  * call of this process (0 restores the built-in choice); workspace sizes
  * returned by the csc_*_workspace_bytes calls cover every PW.
- * csc_get_panel_width(n, w) returns the PW the library will use for an
- * n x w block. */
+ * csc_get_panel_width(n, nnz, w) returns the PW the library will use for an
+ * n x w block of a graph with nnz stored entries. */
 csc_status csc_set_panel_width(int32_t pw);
-int32_t csc_get_panel_width(int32_t n, int32_t w);
+int32_t csc_get_panel_width(int32_t n, int64_t nnz, int32_t w);
+
+/* Kernel tuning knobs, process-wide; results do not depend on them.
+ * CSC_TUNE_PANEL_WIDTH: as csc_set_panel_width.
+ * CSC_TUNE_XCD_ORDER (0/1, default 1): order work so that each XCD of the
+ *   GPU (workgroup b runs on XCD b mod 8) walks a contiguous range of
+ *   panel-major row tiles.
+ * CSC_TUNE_NONTEMPORAL (0/1, default 0): non-temporal loads and stores for
+ *   the streamed blocks (T_{m-1}, T_{m+1}, accumulators).
+ * csc_get_tuning returns the current value (-1 for an unknown key). */
+enum {
+  CSC_TUNE_PANEL_WIDTH = 0,
+  CSC_TUNE_XCD_ORDER = 1,
+  CSC_TUNE_NONTEMPORAL = 2
+};
+csc_status csc_set_tuning(int32_t key, int32_t value);
+int32_t csc_get_tuning(int32_t key);
 
 /* ------------------------------------------------------------------------
  * Normalized adjacency (Sec. 2.1): D_ii = sum_{j != i} W_ij accumulated in
@@ -231,6 +247,23 @@ csc_status csc_interpolate(const csc_graph* g, double lambda_k, int32_t p, doubl
                            double tol, int32_t max_iter, float* X, int32_t ldx, int32_t* labels,
                            int32_t* iters_out, double* relres_out, void* ws, size_t ws_bytes,
                            void* stream);
+
+/* ------------------------------------------------------------------------
+ * Measurement hook (not a step of Alg. 2).  Launches exactly `steps`
+ * Chebyshev-step kernels of one kind on an N x w block held in the workspace,
+ * so that a caller can time one kernel with events on `stream`:
+ * kind 0: T_{m+1} = -2 A T_m - T_{m-1} with Y += c T_{m+1} (feature and CG
+ *         passes), kind 1: the same recurrence with the float64 moment
+ *         epilogue (eigencount passes), kind 2: the last CG step (operator
+ *         and per-column p^T A p partials).
+ * prepare != 0 first fills the block with a Gaussian block and zeroes the
+ * other buffers (these launches precede the timed ones; call once with
+ * steps = 0 and prepare = 1, then time calls with prepare = 0).
+ * ws: csc_cheb_steps_workspace_bytes(N, w).
+ */
+size_t csc_cheb_steps_workspace_bytes(int32_t n, int32_t w);
+csc_status csc_cheb_steps(const csc_graph* g, int32_t w, int32_t kind, int32_t prepare,
+                          int32_t steps, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -22,6 +22,7 @@ CSC_W_BRACKET_MISS = 7
 WARNINGS = (CSC_W_NOT_CONVERGED, CSC_W_BISECT_EXHAUSTED, CSC_W_BRACKET_MISS)
 
 STREAM_COUNT, STREAM_FEAT, STREAM_SAMPLE, STREAM_KMEANS = 1, 2, 3, 4
+TUNE_PANEL_WIDTH, TUNE_XCD_ORDER, TUNE_NONTEMPORAL = 0, 1, 2
 
 
 class CscGraph(C.Structure):
@@ -45,7 +46,9 @@ PROTOTYPES = {
     "csc_last_error": (C.c_char_p, []),
     "csc_version": (i32, []),
     "csc_set_panel_width": (i32, [i32]),
-    "csc_get_panel_width": (i32, [i32, i32]),
+    "csc_get_panel_width": (i32, [i32, C.c_int64, i32]),
+    "csc_set_tuning": (i32, [i32, i32]),
+    "csc_get_tuning": (i32, [i32]),
     "csc_laplacian_from_adjacency": (i32, [i32, i32, vp, vp, vp, vp, vp, i32, vp]),
     "csc_jackson_coeffs": (i32, [f64, i32, pd]),
     "csc_gaussian_block": (i32, [i32, i32, u64, u32, u32, vp, i32, vp]),
@@ -62,6 +65,8 @@ PROTOTYPES = {
     "csc_interpolate_workspace_bytes": (sz, [i32, i32, i32]),
     "csc_interpolate": (i32, [pg, f64, i32, f64, vp, vp, i32, i32, f64, i32, vp, i32, vp, pi, pd,
                               vp, sz, vp]),
+    "csc_cheb_steps_workspace_bytes": (sz, [i32, i32]),
+    "csc_cheb_steps": (i32, [pg, i32, i32, i32, i32, vp, sz, vp]),
 }
 
 

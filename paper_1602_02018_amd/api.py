@@ -71,8 +71,16 @@ def set_panel_width(pw: int) -> None:
     check(lib().csc_set_panel_width(int(pw)), "csc_set_panel_width")
 
 
-def panel_width(n: int, w: int) -> int:
-    return int(lib().csc_get_panel_width(int(n), int(w)))
+def set_tuning(key: int, value: int) -> None:
+    check(lib().csc_set_tuning(int(key), int(value)), "csc_set_tuning")
+
+
+def get_tuning(key: int) -> int:
+    return int(lib().csc_get_tuning(int(key)))
+
+
+def panel_width(n: int, w: int, nnz: int = 0) -> int:
+    return int(lib().csc_get_panel_width(int(n), int(nnz) if nnz else 16 * int(n), int(w)))
 
 
 def jackson_coeffs(lam: float, p: int) -> np.ndarray:
@@ -199,6 +207,19 @@ def interpolate(g: Graph, lam: float, p: int, gamma: float, idx, labels_r, k: in
                                      iters.ctypes.data_as(_lib.pi), relres.ctypes.data_as(_lib.pd),
                                      _ptr(ws), ws.numel(), _stream()), "csc_interpolate")
     return Interpolation(X, labels, iters, relres, st)
+
+
+class StepTimer:
+    """Launches Chebyshev-step kernels through csc_cheb_steps (measurement hook)."""
+
+    def __init__(self, g: Graph, w: int, kind: int = 0):
+        self.g, self.w, self.kind = g, w, kind
+        self.ws = _ws(lib().csc_cheb_steps_workspace_bytes(g.n, w), g.device)
+        self.launch(0, prepare=True)
+
+    def launch(self, steps: int, prepare: bool = False):
+        check(lib().csc_cheb_steps(self.g.ref, self.w, self.kind, 1 if prepare else 0, steps,
+                                   _ptr(self.ws), self.ws.numel(), _stream()), "csc_cheb_steps")
 
 
 # ------------------------------------------------------------ Alg. 2 ---------

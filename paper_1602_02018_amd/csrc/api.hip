@@ -15,7 +15,8 @@ namespace csc {
 namespace {
 thread_local std::string g_error;
 std::atomic<int> g_panel_override{0};
-constexpr int kPanelWidths[] = {4, 8, 16, 32, 64};
+std::atomic<int> g_tune_xcd{1};
+std::atomic<int> g_tune_nt{0};
 }  // namespace
 
 void set_error(const std::string& msg) { g_error = msg; }
@@ -23,13 +24,44 @@ void clear_error() { g_error.clear(); }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-int choose_panel_width(int n, int w) {
-  (void)n;
+Tuning tuning() {
+  Tuning t;
+  t.xcd = g_tune_xcd.load();
+  t.nt = g_tune_nt.load();
+  return t;
+}
+
+void apply_tuning(StepArgs& sa) {
+  const Tuning t = tuning();
+  sa.xcd = t.xcd;
+  sa.nt = t.nt;
+}
+
+// Panel width PW = 4 * lanes-per-row.  A Chebyshev step is bound by the
+// 128-byte cache lines it gathers: a neighbour row of PW floats starting at
+// byte offset 4*PW*j touches (4PW + 128 - gcd(4PW, 128)) / 128 lines on
+// average.  The choice minimises, per row and step, gathered line bytes
+// (deg * 128 * lines per panel) + streamed bytes (16 per padded column)
+// + CSR bytes re-read for every panel (8 deg + 4).
+int choose_panel_width(int n, int w, long long nnz) {
   const int o = g_panel_override.load();
   if (o) return o;
-  if (w <= 4) return 4;
-  if (w <= 8) return 8;
-  return 16;
+  const double deg = n > 0 ? (double)nnz / n : 16.0;
+  double best = 0.0;
+  int arg = 4;
+  for (int pw = 4; pw <= 256; pw += 4) {
+    const int np = (w + pw - 1) / pw;
+    const int b = 4 * pw;
+    int g = 128;
+    while (b % g) g >>= 1;
+    const double lines = (double)(b + 128 - g) / 128.0;
+    const double cost = np * (deg * 128.0 * lines + 16.0 * pw + 8.0 * deg + 4.0);
+    if (pw == 4 || cost < best) {
+      best = cost;
+      arg = pw;
+    }
+  }
+  return arg;
 }
 
 Layout make_layout(int n, int w, int pw) {
@@ -113,6 +145,7 @@ csc_status chebyshev_pass(const csc_graph& g, const Layout& L, const double* a, 
   sa.lds = b.lds;
   sa.mask = b.mask;
   sa.gamma = b.gamma;
+  apply_tuning(sa);
   const size_t nblocks = (size_t)L.np * sa.tiles;
   for (int m = 0; m < p; ++m) {  // step m produces T_{m+1}
     const bool first = m == 0, last = m + 1 == p;
@@ -171,7 +204,7 @@ size_t interp_bytes(const Layout& L) {
 template <class F>
 size_t max_over_widths(int n, int w, F f) {
   size_t m = 0;
-  for (int pw : kPanelWidths) m = std::max(m, f(make_layout(n, w, pw)));
+  for (int pw = 4; pw <= 256; pw += 4) m = std::max(m, f(make_layout(n, w, pw)));
   return m;
 }
 
@@ -232,13 +265,42 @@ extern "C" int32_t csc_version(void) { return 100; }
 
 extern "C" csc_status csc_set_panel_width(int32_t pw) {
   clear_error();
-  CSC_REQUIRE(pw == 0 || pw == 4 || pw == 8 || pw == 16 || pw == 32 || pw == 64,
-              "panel width must be 0, 4, 8, 16, 32 or 64");
+  CSC_REQUIRE(pw == 0 || (pw >= 4 && pw <= 256 && pw % 4 == 0),
+              "panel width must be 0 or a multiple of 4 in [4, 256]");
   g_panel_override.store(pw);
   return CSC_OK;
 }
 
-extern "C" int32_t csc_get_panel_width(int32_t n, int32_t w) { return choose_panel_width(n, w); }
+extern "C" int32_t csc_get_panel_width(int32_t n, int64_t nnz, int32_t w) {
+  return choose_panel_width(n, w, nnz);
+}
+
+extern "C" csc_status csc_set_tuning(int32_t key, int32_t value) {
+  clear_error();
+  switch (key) {
+    case CSC_TUNE_PANEL_WIDTH:
+      return csc_set_panel_width(value);
+    case CSC_TUNE_XCD_ORDER:
+      CSC_REQUIRE(value == 0 || value == 1, "value must be 0 or 1");
+      g_tune_xcd.store(value);
+      return CSC_OK;
+    case CSC_TUNE_NONTEMPORAL:
+      CSC_REQUIRE(value == 0 || value == 1, "value must be 0 or 1");
+      g_tune_nt.store(value);
+      return CSC_OK;
+    default:
+      CSC_REQUIRE(false, "unknown tuning key");
+  }
+}
+
+extern "C" int32_t csc_get_tuning(int32_t key) {
+  switch (key) {
+    case CSC_TUNE_PANEL_WIDTH: return g_panel_override.load();
+    case CSC_TUNE_XCD_ORDER: return g_tune_xcd.load();
+    case CSC_TUNE_NONTEMPORAL: return g_tune_nt.load();
+    default: return -1;
+  }
+}
 
 extern "C" csc_status csc_laplacian_from_adjacency(int32_t n, int32_t nnz, const int32_t* row_ptr,
                                                    const int32_t* col, const float* w,
@@ -299,7 +361,7 @@ csc_status filter_common(const csc_graph* g, const double* a, int p, int w, cons
                          int normalize, float* Y, int ld, void* ws, size_t ws_bytes,
                          hipStream_t s) {
   const int n = g->n;
-  const Layout L = make_layout(n, w, choose_panel_width(n, w));
+  const Layout L = make_layout(n, w, choose_panel_width(n, w, g->nnz));
   CSC_TRY(check_ws(ws, ws_bytes, filter_bytes(L)));
   Arena ar(ws, ws_bytes);
   float* T0 = ar.take<float>(L.elems());
@@ -385,7 +447,7 @@ extern "C" csc_status csc_eigencount(const csc_graph* g, double lambda, int32_t 
   CSC_REQUIRE(count_out != nullptr, "count_out is NULL");
   CSC_REQUIRE(p >= 1 && n_signals >= 1, "need p >= 1 and n_signals >= 1");
   CSC_REQUIRE(lambda >= 0.0 && lambda <= 2.0, "lambda must lie in [0, 2]");
-  const Layout L = make_layout(g->n, n_signals, choose_panel_width(g->n, n_signals));
+  const Layout L = make_layout(g->n, n_signals, choose_panel_width(g->n, n_signals, g->nnz));
   CSC_TRY(check_ws(ws, ws_bytes, count_bytes(L, p)));
   Arena ar(ws, ws_bytes);
   const CountBuffers c = carve_count(ar, L, p);
@@ -415,7 +477,7 @@ extern "C" csc_status csc_estimate_lambda_k(const csc_graph* g, int32_t k, int32
     lo = bracket[0];
     hi = bracket[1];
   }
-  const Layout L = make_layout(g->n, n_signals, choose_panel_width(g->n, n_signals));
+  const Layout L = make_layout(g->n, n_signals, choose_panel_width(g->n, n_signals, g->nnz));
   CSC_TRY(check_ws(ws, ws_bytes, count_bytes(L, p)));
   Arena ar(ws, ws_bytes);
   const CountBuffers c = carve_count(ar, L, p);
@@ -537,7 +599,7 @@ extern "C" csc_status csc_interpolate(const csc_graph* g, double lambda_k, int32
               "need p >= 1, gamma > 0, tol > 0, max_iter >= 1");
   CSC_REQUIRE(lambda_k >= 0.0 && lambda_k <= 2.0, "lambda_k must lie in [0, 2]");
   CSC_REQUIRE(X == nullptr || ldx >= k, "ldx must be >= k");
-  const Layout L = make_layout(N, k, choose_panel_width(N, k));
+  const Layout L = make_layout(N, k, choose_panel_width(N, k, g->nnz));
   CSC_TRY(check_ws(ws, ws_bytes, interp_bytes(L)));
   hipStream_t s = as_stream(stream);
   const int tiles = tiles_for(L);
@@ -632,4 +694,70 @@ extern "C" csc_status csc_interpolate(const csc_graph* g, double lambda_k, int32
     return CSC_W_NOT_CONVERGED;
   }
   return nactive > 0 ? CSC_W_NOT_CONVERGED : CSC_OK;
+}
+
+namespace {
+size_t steps_bytes(const Layout& L) {
+  const size_t tiles = tiles_for(L), wp = (size_t)L.np * L.pw;
+  size_t b = 4 * align_up(L.bytes());                       // T0, Ta, Tb, Y
+  b += align_up((size_t)L.n * sizeof(float));               // mask
+  b += align_up(std::max(wp * tiles, (size_t)L.np * tiles) * sizeof(double));
+  return b + 256;
+}
+}  // namespace
+
+extern "C" size_t csc_cheb_steps_workspace_bytes(int32_t n, int32_t w) {
+  if (n < 1 || w < 1) return 0;
+  return max_over_widths(n, w, [](const Layout& L) { return steps_bytes(L); });
+}
+
+extern "C" csc_status csc_cheb_steps(const csc_graph* g, int32_t w, int32_t kind, int32_t prepare,
+                                     int32_t steps, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  CSC_TRY(check_graph(g));
+  CSC_REQUIRE(w >= 1 && steps >= 0, "need w >= 1 and steps >= 0");
+  CSC_REQUIRE(kind >= 0 && kind <= 2, "kind must be 0, 1 or 2");
+  const Layout L = make_layout(g->n, w, choose_panel_width(g->n, w, g->nnz));
+  CSC_TRY(check_ws(ws, ws_bytes, steps_bytes(L)));
+  hipStream_t s = as_stream(stream);
+  const int tiles = tiles_for(L);
+  Arena ar(ws, ws_bytes);
+  float* T0 = ar.take<float>(L.elems());
+  float* Ta = ar.take<float>(L.elems());
+  float* Tb = ar.take<float>(L.elems());
+  float* Y = ar.take<float>(L.elems());
+  float* mask = ar.take<float>(g->n);
+  double* part = ar.take<double>(std::max((size_t)L.np * L.pw * tiles, (size_t)L.np * tiles));
+  if (prepare) {
+    CSC_HIP(launch_gaussian_panels(L, 1, 0, CSC_STREAM_FEAT, T0, s));
+    CSC_HIP(launch_fill_f32(Ta, L.elems(), 0.f, s));
+    CSC_HIP(launch_fill_f32(Tb, L.elems(), 0.f, s));
+    CSC_HIP(launch_fill_f32(Y, L.elems(), 0.f, s));
+    CSC_HIP(launch_fill_f32(mask, g->n, 0.f, s));
+  }
+  StepArgs sa;
+  sa.L = L;
+  sa.tiles = tiles;
+  sa.row_ptr = g->row_ptr;
+  sa.col = g->col;
+  sa.val = g->val;
+  sa.T0 = T0;
+  sa.Y = Y;
+  sa.mask = mask;
+  sa.gamma = 1e-3f;
+  sa.c0 = 0.5f;
+  sa.c1 = 0.25f;
+  sa.part = part;
+  sa.part2 = part;
+  apply_tuning(sa);
+  const int epi = kind == 0 ? EPI_Y : (kind == 1 ? EPI_MOM : EPI_CG);
+  for (int m = 1; m <= steps; ++m) {
+    // T_{m+1} from T_m (gathered) and T_{m-1}; buffers alternate as in a pass
+    sa.Tm = (m & 1) ? Ta : Tb;
+    sa.Tprev = (m & 1) ? Tb : Ta;
+    sa.Tnext = (m & 1) ? Tb : Ta;
+    if (m == 1) sa.Tm = T0;
+    CSC_HIP(launch_cheb_step(sa, epi, false, epi == EPI_CG, s));
+  }
+  return CSC_OK;
 }

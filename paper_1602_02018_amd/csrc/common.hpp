@@ -94,7 +94,7 @@ struct Layout {
 };
 
 Layout make_layout(int n, int w, int pw);
-int choose_panel_width(int n, int w);
+int choose_panel_width(int n, int w, long long nnz);
 size_t align_up(size_t x, size_t a = 256);
 
 // Bump allocator over a caller workspace.

@@ -5,8 +5,8 @@
 // float32 block, fused with the consumer of T_{m+1} (feature accumulation,
 // sampled-row accumulation, float64 moments for the eigencount, or the CG
 // operator).  It is a CSR SpMM: each row of A is walked by PW/4 lanes, each
-// lane owning one float4 of the panel, so one gathered neighbour row is a
-// contiguous PW*4-byte segment read by consecutive lanes.  No MFMA: the step
+// lane owning four consecutive columns of the panel, so one gathered
+// neighbour row is a contiguous PW*4-byte segment read by consecutive lanes.  No MFMA: the step
 // moves ~16-20 bytes per 2 flops and is bound by memory bandwidth.
 #include <hipcub/hipcub.hpp>
 
@@ -35,19 +35,6 @@ __device__ inline double block_sum(double v, double* sh) {
   return r;
 }
 
-__device__ inline float4 f4_fma(float a, float4 x, float4 acc) {
-  acc.x = fmaf(a, x.x, acc.x);
-  acc.y = fmaf(a, x.y, acc.y);
-  acc.z = fmaf(a, x.z, acc.z);
-  acc.w = fmaf(a, x.w, acc.w);
-  return acc;
-}
-
-__device__ inline double dot4(float4 a, float4 b) {
-  return (double)a.x * (double)b.x + (double)a.y * (double)b.y + (double)a.z * (double)b.z +
-         (double)a.w * (double)b.w;
-}
-
 __device__ inline float gauss_entry(uint64_t e, uint32_t t, uint32_t sid, uint64_t seed, int w) {
   const Words4 x = philox4x64_10(e, (uint64_t)t, (uint64_t)sid, 0ull, seed, 0ull);
   const double u1 = (double)((x.x0 >> 11) + 1ull) * 0x1p-53;
@@ -57,69 +44,137 @@ __device__ inline float gauss_entry(uint64_t e, uint32_t t, uint32_t sid, uint64
 }
 
 // ------------------------------------------------------- Chebyshev step ---
-template <int PW, int EPI, bool FIRST, bool LAST>
-__global__ __launch_bounds__(kBlock) void k_cheb_step(StepArgs a) {
-  constexpr int LPR = PW / 4;       // lanes per row
-  constexpr int RPB = kBlock / LPR; // rows per tile
-  __shared__ double sh[4 * LPR * 4 + 8];
+typedef float v4f __attribute__((ext_vector_type(4)));
 
-  const int tid = threadIdx.x;
-  const int panel = blockIdx.x / a.tiles;
-  const int tile = blockIdx.x - panel * a.tiles;
-  const int r = tid / LPR, q = tid - (tid / LPR) * LPR;
-  const int n = a.L.n;
-  const int i = tile * RPB + r;
-  const bool valid = i < n;
-  const size_t pbase4 = (size_t)panel * a.L.panel_elems() / 4;
-  const size_t o4 = pbase4 + (size_t)i * LPR + q;
-  const float4* __restrict__ Tm4 = reinterpret_cast<const float4*>(a.Tm) + pbase4;
+__device__ inline v4f fma4(float a, v4f x, v4f acc) {
+  return __builtin_elementwise_fma((v4f)a, x, acc);
+}
 
-  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+__device__ inline v4f ld4(const float* base, size_t o4, int nt) {
+  const v4f* p = reinterpret_cast<const v4f*>(base) + o4;
+  return nt ? __builtin_nontemporal_load(p) : *p;
+}
+
+__device__ inline void st4(float* base, size_t o4, v4f v, int nt) {
+  v4f* p = reinterpret_cast<v4f*>(base) + o4;
+  if (nt)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+__device__ inline double dot4v(v4f a, v4f b) {
+  return (double)a.x * (double)b.x + (double)a.y * (double)b.y + (double)a.z * (double)b.z +
+         (double)a.w * (double)b.w;
+}
+
+// Workgroups are handed to the 8 XCDs round-robin (workgroup b runs on XCD
+// b mod 8).  With xcd mapping on, XCD x processes a contiguous range of the
+// panel-major work units, so each XCD's L2 sees the gathered rows of one
+// panel at a time instead of all panels at once.
+__device__ inline int work_unit(int b, int U, int xcd) {
+  if (!xcd) return b;
+  const int x = b & 7, j = b >> 3, q = U >> 3, r = U & 7;
+  return x * q + (x < r ? x : r) + j;
+}
+
+// Lanes of a wave walk rows of a panel: a row takes lpr = PW/4 lanes (one
+// float4 each), a wave holds rpw = floor(64 / lpr) rows, spare lanes idle.
+struct RowMap {
+  int lpr, rpw, rpb, r, q;
+  bool lane_ok;
+};
+
+__device__ inline RowMap row_map(int pw) {
+  RowMap m;
+  m.lpr = pw >> 2;
+  m.rpw = 64 / m.lpr;
+  m.rpb = 4 * m.rpw;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane / m.lpr;
+  m.q = lane - lr * m.lpr;
+  m.lane_ok = lr < m.rpw;
+  m.r = wave * m.rpw + lr;
+  return m;
+}
+
+// Row i of A times the gathered panel: sum_k val[k] T_m[col[k]], k in CSR order.
+__device__ inline v4f spmm_row(const StepArgs& a, const v4f* __restrict__ Tm4, int i, int q,
+                               int lpr, bool valid) {
+  v4f acc = (v4f)0.f;
   if (valid) {
     int k = a.row_ptr[i];
     const int end = a.row_ptr[i + 1];
     for (; k + 4 <= end; k += 4) {
       const int j0 = a.col[k], j1 = a.col[k + 1], j2 = a.col[k + 2], j3 = a.col[k + 3];
       const float v0 = a.val[k], v1 = a.val[k + 1], v2 = a.val[k + 2], v3 = a.val[k + 3];
-      const float4 t0 = Tm4[(size_t)j0 * LPR + q];
-      const float4 t1 = Tm4[(size_t)j1 * LPR + q];
-      const float4 t2 = Tm4[(size_t)j2 * LPR + q];
-      const float4 t3 = Tm4[(size_t)j3 * LPR + q];
-      acc = f4_fma(v0, t0, acc);
-      acc = f4_fma(v1, t1, acc);
-      acc = f4_fma(v2, t2, acc);
-      acc = f4_fma(v3, t3, acc);
+      const v4f t0 = Tm4[(unsigned)j0 * lpr + q];
+      const v4f t1 = Tm4[(unsigned)j1 * lpr + q];
+      const v4f t2 = Tm4[(unsigned)j2 * lpr + q];
+      const v4f t3 = Tm4[(unsigned)j3 * lpr + q];
+      acc = fma4(v0, t0, acc);
+      acc = fma4(v1, t1, acc);
+      acc = fma4(v2, t2, acc);
+      acc = fma4(v3, t3, acc);
     }
-    for (; k < end; ++k) acc = f4_fma(a.val[k], Tm4[(size_t)a.col[k] * LPR + q], acc);
+    for (; k < end; ++k) acc = fma4(a.val[k], Tm4[(unsigned)a.col[k] * lpr + q], acc);
   }
+  return acc;
+}
 
-  const float4* Tprev4 = reinterpret_cast<const float4*>(a.Tprev);
-  float4 tn = make_float4(0.f, 0.f, 0.f, 0.f);
-  float4 x0 = make_float4(0.f, 0.f, 0.f, 0.f);  // T_0 row (first step, moments, CG)
+// Per-column sums over the rows of a workgroup in a fixed order, written to
+// out[c * stride] for the pw columns c of the panel.  sh holds 4*64*4 doubles.
+__device__ inline void column_partials(const double cs[4], const RowMap& m, int pw, double* sh,
+                                       double* out, size_t stride) {
+  if (m.lane_ok) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sh[m.r * pw + m.q * 4 + e] = cs[e];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < pw) {
+    double t = 0.0;
+    for (int rr = 0; rr < m.rpb; ++rr) t += sh[rr * pw + threadIdx.x];
+    out[(size_t)threadIdx.x * stride] = t;
+  }
+}
+
+template <int EPI, bool FIRST, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_cheb_step(StepArgs a) {
+  const RowMap m = row_map(a.L.pw);
+  const int u = work_unit(blockIdx.x, a.L.np * a.tiles, a.xcd);
+  const int panel = u / a.tiles;
+  const int tile = u - panel * a.tiles;
+  const int n = a.L.n;
+  const int i = tile * m.rpb + m.r;
+  const bool valid = m.lane_ok && i < n;
+  const int nt = a.nt;
+  const size_t pbase4 = (size_t)panel * a.L.panel_elems() / 4;
+  const size_t o4 = pbase4 + (size_t)i * m.lpr + m.q;
+  const v4f* __restrict__ Tm4 = reinterpret_cast<const v4f*>(a.Tm) + pbase4;
+
+  const v4f acc = spmm_row(a, Tm4, i, m.q, m.lpr, valid);
+
+  v4f tn = (v4f)0.f;
+  v4f x0 = (v4f)0.f;  // T_0 row (first step, moments, CG)
   if (valid) {
     if (FIRST) {
-      x0 = Tprev4[o4];
-      tn = make_float4(-acc.x, -acc.y, -acc.z, -acc.w);
+      x0 = ld4(a.Tprev, o4, nt);
+      tn = -acc;
     } else {
-      const float4 tp = Tprev4[o4];
-      tn = make_float4(fmaf(-2.f, acc.x, -tp.x), fmaf(-2.f, acc.y, -tp.y),
-                       fmaf(-2.f, acc.z, -tp.z), fmaf(-2.f, acc.w, -tp.w));
+      const v4f tp = ld4(a.Tprev, o4, nt);
+      tn = __builtin_elementwise_fma((v4f)-2.f, acc, -tp);
     }
-    if (!LAST && EPI != EPI_CG) reinterpret_cast<float4*>(a.Tnext)[o4] = tn;
+    if (!LAST && EPI != EPI_CG) st4(a.Tnext, o4, tn, nt);
   }
 
   if constexpr (EPI == EPI_Y) {
     if (valid) {
-      float4* Y4 = reinterpret_cast<float4*>(a.Y);
-      float4 y;
-      if (FIRST) {
-        y = make_float4(fmaf(a.c1, tn.x, a.c0 * x0.x), fmaf(a.c1, tn.y, a.c0 * x0.y),
-                        fmaf(a.c1, tn.z, a.c0 * x0.z), fmaf(a.c1, tn.w, a.c0 * x0.w));
-      } else {
-        y = Y4[o4];
-        y = f4_fma(a.c1, tn, y);
-      }
-      Y4[o4] = y;
+      v4f y;
+      if (FIRST)
+        y = __builtin_elementwise_fma((v4f)a.c1, tn, (v4f)a.c0 * x0);
+      else
+        y = fma4(a.c1, tn, ld4(a.Y, o4, nt));
+      st4(a.Y, o4, y, nt);
     }
   } else if constexpr (EPI == EPI_YS) {
     if (valid) {
@@ -127,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(StepArgs a) {
       if (s >= 0) {
         const float t[4] = {tn.x, tn.y, tn.z, tn.w};
         const float z[4] = {x0.x, x0.y, x0.z, x0.w};
-        const int c0 = panel * PW + q * 4;
+        const int c0 = panel * a.L.pw + m.q * 4;
         float* out = a.Ys + (size_t)s * a.lds;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -141,65 +196,46 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(StepArgs a) {
       }
     }
   } else if constexpr (EPI == EPI_MOM) {
+    __shared__ double sh[8];
     double s1 = 0.0, s0 = 0.0;
     if (valid) {
-      const float4 r0 = FIRST ? x0 : reinterpret_cast<const float4*>(a.T0)[o4];
-      s1 = dot4(r0, tn);
-      if (FIRST) s0 = dot4(r0, r0);
+      const v4f r0 = FIRST ? x0 : ld4(a.T0, o4, nt);
+      s1 = dot4v(r0, tn);
+      if (FIRST) s0 = dot4v(r0, r0);
     }
     const double b1 = block_sum(s1, sh);
-    if (tid == 0) a.part[blockIdx.x] = b1;
+    if (threadIdx.x == 0) a.part[blockIdx.x] = b1;
     if (FIRST) {
       __syncthreads();
       const double b0 = block_sum(s0, sh);
-      if (tid == 0) a.part2[blockIdx.x] = b0;
+      if (threadIdx.x == 0) a.part2[blockIdx.x] = b0;
     }
   } else if constexpr (EPI == EPI_CG) {
+    __shared__ double sh[4 * 64 * 4];
     double cs[4] = {0.0, 0.0, 0.0, 0.0};
     if (valid) {
-      float4* Y4 = reinterpret_cast<float4*>(a.Y);
-      const float4 p0 = FIRST ? x0 : reinterpret_cast<const float4*>(a.T0)[o4];
-      float4 yf;
+      const v4f p0 = FIRST ? x0 : ld4(a.T0, o4, nt);
+      v4f yf;
       if (FIRST)
-        yf = make_float4(fmaf(a.c1, tn.x, a.c0 * p0.x), fmaf(a.c1, tn.y, a.c0 * p0.y),
-                         fmaf(a.c1, tn.z, a.c0 * p0.z), fmaf(a.c1, tn.w, a.c0 * p0.w));
+        yf = __builtin_elementwise_fma((v4f)a.c1, tn, (v4f)a.c0 * p0);
       else
-        yf = f4_fma(a.c1, tn, Y4[o4]);
-      const float m = a.mask[i];
-      const float4 ap = make_float4(fmaf(m, p0.x, a.gamma * (p0.x - yf.x)),
-                                    fmaf(m, p0.y, a.gamma * (p0.y - yf.y)),
-                                    fmaf(m, p0.z, a.gamma * (p0.z - yf.z)),
-                                    fmaf(m, p0.w, a.gamma * (p0.w - yf.w)));
-      Y4[o4] = ap;
+        yf = fma4(a.c1, tn, ld4(a.Y, o4, nt));
+      const float mk = a.mask[i];
+      const v4f ap = __builtin_elementwise_fma((v4f)mk, p0, (v4f)a.gamma * (p0 - yf));
+      st4(a.Y, o4, ap, nt);
       cs[0] = (double)p0.x * (double)ap.x;
       cs[1] = (double)p0.y * (double)ap.y;
       cs[2] = (double)p0.z * (double)ap.z;
       cs[3] = (double)p0.w * (double)ap.w;
     }
-    const int wave = tid >> 6, lane = tid & 63;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      double v = cs[e];
-#pragma unroll
-      for (int off = 32; off >= LPR; off >>= 1) v += __shfl_xor(v, off);
-      if (lane < LPR) sh[(wave * LPR + lane) * 4 + e] = v;
-    }
-    __syncthreads();
-    if (tid < LPR) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const double t = (sh[(0 * LPR + tid) * 4 + e] + sh[(1 * LPR + tid) * 4 + e]) +
-                         (sh[(2 * LPR + tid) * 4 + e] + sh[(3 * LPR + tid) * 4 + e]);
-        a.part[(size_t)(panel * PW + tid * 4 + e) * a.tiles + tile] = t;
-      }
-    }
+    column_partials(cs, m, a.L.pw, sh, a.part + (size_t)panel * a.L.pw * a.tiles + tile,
+                    (size_t)a.tiles);
   }
 }
 
-template <int PW>
-hipError_t launch_step_pw(const StepArgs& a, int epi, bool first, bool last, hipStream_t s) {
+hipError_t launch_step(const StepArgs& a, int epi, bool first, bool last, hipStream_t s) {
   const dim3 grid((unsigned)(a.L.np * a.tiles)), block(kBlock);
-#define CSC_STEP(E, F, L) hipLaunchKernelGGL((k_cheb_step<PW, E, F, L>), grid, block, 0, s, a)
+#define CSC_STEP(E, F, L) hipLaunchKernelGGL((k_cheb_step<E, F, L>), grid, block, 0, s, a)
   switch (epi) {
     case EPI_Y:
       if (first) { if (last) CSC_STEP(EPI_Y, true, true); else CSC_STEP(EPI_Y, true, false); }
@@ -357,40 +393,23 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* part, int len, 
   if (threadIdx.x == 0) out[blockIdx.x] = b;
 }
 
-template <int PW>
 __global__ __launch_bounds__(kBlock) void k_col_dot(Layout L, int tiles, const float* A,
                                                     const float* B, double* part) {
-  constexpr int LPR = PW / 4, RPB = kBlock / LPR;
-  __shared__ double sh[4 * LPR * 4];
-  const int tid = threadIdx.x, panel = blockIdx.x / tiles, tile = blockIdx.x - panel * tiles;
-  const int r = tid / LPR, q = tid - r * LPR, i = tile * RPB + r;
+  __shared__ double sh[4 * 64 * 4];
+  const RowMap m = row_map(L.pw);
+  const int panel = blockIdx.x / tiles, tile = blockIdx.x - panel * tiles;
+  const int i = tile * m.rpb + m.r;
   double cs[4] = {0.0, 0.0, 0.0, 0.0};
-  if (i < L.n) {
-    const size_t o4 = (size_t)panel * L.panel_elems() / 4 + (size_t)i * LPR + q;
-    const float4 x = reinterpret_cast<const float4*>(A)[o4];
-    const float4 y = reinterpret_cast<const float4*>(B)[o4];
+  if (m.lane_ok && i < L.n) {
+    const size_t o4 = (size_t)panel * L.panel_elems() / 4 + (size_t)i * m.lpr + m.q;
+    const v4f x = reinterpret_cast<const v4f*>(A)[o4];
+    const v4f y = reinterpret_cast<const v4f*>(B)[o4];
     cs[0] = (double)x.x * y.x;
     cs[1] = (double)x.y * y.y;
     cs[2] = (double)x.z * y.z;
     cs[3] = (double)x.w * y.w;
   }
-  const int wave = tid >> 6, lane = tid & 63;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    double v = cs[e];
-#pragma unroll
-    for (int off = 32; off >= LPR; off >>= 1) v += __shfl_xor(v, off);
-    if (lane < LPR) sh[(wave * LPR + lane) * 4 + e] = v;
-  }
-  __syncthreads();
-  if (tid < LPR) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const double t = (sh[(0 * LPR + tid) * 4 + e] + sh[(1 * LPR + tid) * 4 + e]) +
-                       (sh[(2 * LPR + tid) * 4 + e] + sh[(3 * LPR + tid) * 4 + e]);
-      part[(size_t)(panel * PW + tid * 4 + e) * tiles + tile] = t;
-    }
-  }
+  column_partials(cs, m, L.pw, sh, part + (size_t)panel * L.pw * tiles + tile, (size_t)tiles);
 }
 
 // ------------------------------------------------------------ sampling ---
@@ -492,52 +511,35 @@ __global__ void k_cg_alpha(int k, const double* rr, const double* pAp, int* acti
   }
 }
 
-template <int PW>
+// x += alpha p and r -= alpha A p per column (float64 scalars), then the
+// per-column partial sums of r^T r.
 __global__ __launch_bounds__(kBlock) void k_cg_update1(Layout L, int tiles, const float* AP,
                                                        const float* P, float* X, float* R,
                                                        const double* alpha, double* part) {
-  constexpr int LPR = PW / 4, RPB = kBlock / LPR;
-  __shared__ double sh[4 * LPR * 4];
-  const int tid = threadIdx.x, panel = blockIdx.x / tiles, tile = blockIdx.x - panel * tiles;
-  const int r = tid / LPR, q = tid - r * LPR, i = tile * RPB + r;
-  const int c0 = panel * PW + q * 4;
+  __shared__ double sh[4 * 64 * 4];
+  const RowMap m = row_map(L.pw);
+  const int panel = blockIdx.x / tiles, tile = blockIdx.x - panel * tiles;
+  const int i = tile * m.rpb + m.r;
+  const int c0 = panel * L.pw + m.q * 4;
   double cs[4] = {0.0, 0.0, 0.0, 0.0};
-  if (i < L.n) {
-    const size_t o4 = (size_t)panel * L.panel_elems() / 4 + (size_t)i * LPR + q;
-    const float4 ap = reinterpret_cast<const float4*>(AP)[o4];
-    const float4 p = reinterpret_cast<const float4*>(P)[o4];
-    float4 x = reinterpret_cast<float4*>(X)[o4];
-    float4 rr = reinterpret_cast<float4*>(R)[o4];
-    const float pa[4] = {p.x, p.y, p.z, p.w}, aa[4] = {ap.x, ap.y, ap.z, ap.w};
-    float xa[4] = {x.x, x.y, x.z, x.w}, ra[4] = {rr.x, rr.y, rr.z, rr.w};
+  if (m.lane_ok && i < L.n) {
+    const size_t o4 = (size_t)panel * L.panel_elems() / 4 + (size_t)i * m.lpr + m.q;
+    const v4f ap = reinterpret_cast<const v4f*>(AP)[o4];
+    const v4f p = reinterpret_cast<const v4f*>(P)[o4];
+    v4f x = reinterpret_cast<v4f*>(X)[o4];
+    v4f rr = reinterpret_cast<v4f*>(R)[o4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int c = c0 + e;
       const double al = c < L.w ? alpha[c] : 0.0;
-      xa[e] = (float)((double)xa[e] + al * (double)pa[e]);
-      ra[e] = (float)((double)ra[e] - al * (double)aa[e]);
-      cs[e] = (double)ra[e] * (double)ra[e];
+      x[e] = (float)((double)x[e] + al * (double)p[e]);
+      rr[e] = (float)((double)rr[e] - al * (double)ap[e]);
+      cs[e] = (double)rr[e] * (double)rr[e];
     }
-    reinterpret_cast<float4*>(X)[o4] = make_float4(xa[0], xa[1], xa[2], xa[3]);
-    reinterpret_cast<float4*>(R)[o4] = make_float4(ra[0], ra[1], ra[2], ra[3]);
+    reinterpret_cast<v4f*>(X)[o4] = x;
+    reinterpret_cast<v4f*>(R)[o4] = rr;
   }
-  const int wave = tid >> 6, lane = tid & 63;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    double v = cs[e];
-#pragma unroll
-    for (int off = 32; off >= LPR; off >>= 1) v += __shfl_xor(v, off);
-    if (lane < LPR) sh[(wave * LPR + lane) * 4 + e] = v;
-  }
-  __syncthreads();
-  if (tid < LPR) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const double t = (sh[(0 * LPR + tid) * 4 + e] + sh[(1 * LPR + tid) * 4 + e]) +
-                       (sh[(2 * LPR + tid) * 4 + e] + sh[(3 * LPR + tid) * 4 + e]);
-      part[(size_t)(panel * PW + tid * 4 + e) * tiles + tile] = t;
-    }
-  }
+  column_partials(cs, m, L.pw, sh, part + (size_t)panel * L.pw * tiles + tile, (size_t)tiles);
 }
 
 __global__ void k_cg_scalar(int k, const double* rrn, double* rr, const double* bnorm2,
@@ -567,27 +569,24 @@ __global__ void k_cg_scalar(int k, const double* rrn, double* rr, const double* 
   if (threadIdx.x == 0) *nactive = cnt;
 }
 
-template <int PW>
+// p = r + beta p for the columns still iterating.
 __global__ __launch_bounds__(kBlock) void k_cg_update2(Layout L, const float* R, float* P,
                                                        const double* beta, const int* active) {
-  constexpr int LPR = PW / 4;
-  const size_t total4 = L.elems() / 4;
+  const int lpr = L.pw >> 2;
+  const size_t total4 = L.elems() / 4, pe4 = L.panel_elems() / 4;
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total4;
        t += (size_t)gridDim.x * blockDim.x) {
-    const size_t e0 = t * 4;
-    const int panel = (int)(e0 / L.panel_elems());
-    const int q = (int)(t % LPR);
-    const int c0 = panel * PW + q * 4;
-    const float4 rv = reinterpret_cast<const float4*>(R)[t];
-    float4 pv = reinterpret_cast<float4*>(P)[t];
-    const float ra[4] = {rv.x, rv.y, rv.z, rv.w};
-    float pa[4] = {pv.x, pv.y, pv.z, pv.w};
+    const int panel = (int)(t / pe4);
+    const int q = (int)((t - (size_t)panel * pe4) % lpr);
+    const int c0 = panel * L.pw + q * 4;
+    const v4f rv = reinterpret_cast<const v4f*>(R)[t];
+    v4f pv = reinterpret_cast<v4f*>(P)[t];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int c = c0 + e;
-      if (c < L.w && active[c]) pa[e] = (float)((double)ra[e] + beta[c] * (double)pa[e]);
+      if (c < L.w && active[c]) pv[e] = (float)((double)rv[e] + beta[c] * (double)pv[e]);
     }
-    reinterpret_cast<float4*>(P)[t] = make_float4(pa[0], pa[1], pa[2], pa[3]);
+    reinterpret_cast<v4f*>(P)[t] = pv;
   }
 }
 
@@ -625,18 +624,12 @@ inline unsigned grid_for(size_t n, size_t per = kBlock, size_t cap = 65536) {
 }  // namespace
 
 // ============================================================ launchers ===
-int rows_per_tile(int pw) { return kBlock / (pw / 4); }
+int rows_per_tile(int pw) { return 4 * (64 / (pw / 4)); }
 int tiles_for(const Layout& L) { return (L.n + rows_per_tile(L.pw) - 1) / rows_per_tile(L.pw); }
 
 hipError_t launch_cheb_step(const StepArgs& a, int epi, bool first, bool last, hipStream_t s) {
-  switch (a.L.pw) {
-    case 4: return launch_step_pw<4>(a, epi, first, last, s);
-    case 8: return launch_step_pw<8>(a, epi, first, last, s);
-    case 16: return launch_step_pw<16>(a, epi, first, last, s);
-    case 32: return launch_step_pw<32>(a, epi, first, last, s);
-    case 64: return launch_step_pw<64>(a, epi, first, last, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (a.L.pw < 4 || a.L.pw > 256 || (a.L.pw & 3)) return hipErrorInvalidValue;
+  return launch_step(a, epi, first, last, s);
 }
 
 hipError_t launch_degree_scale(int n, const int* row_ptr, const int* col, const float* w,
@@ -720,15 +713,8 @@ hipError_t launch_reduce(const double* part, int len, int nvec, double* out, hip
 hipError_t launch_col_dot(const Layout& L, const float* A, const float* B, double* part,
                           hipStream_t s) {
   const int tiles = tiles_for(L);
-  const dim3 grid((unsigned)(L.np * tiles)), block(kBlock);
-  switch (L.pw) {
-    case 4: hipLaunchKernelGGL(k_col_dot<4>, grid, block, 0, s, L, tiles, A, B, part); break;
-    case 8: hipLaunchKernelGGL(k_col_dot<8>, grid, block, 0, s, L, tiles, A, B, part); break;
-    case 16: hipLaunchKernelGGL(k_col_dot<16>, grid, block, 0, s, L, tiles, A, B, part); break;
-    case 32: hipLaunchKernelGGL(k_col_dot<32>, grid, block, 0, s, L, tiles, A, B, part); break;
-    case 64: hipLaunchKernelGGL(k_col_dot<64>, grid, block, 0, s, L, tiles, A, B, part); break;
-    default: return hipErrorInvalidValue;
-  }
+  hipLaunchKernelGGL(k_col_dot, dim3((unsigned)(L.np * tiles)), dim3(kBlock), 0, s, L, tiles, A,
+                     B, part);
   return hipGetLastError();
 }
 
@@ -783,15 +769,8 @@ hipError_t launch_cg_alpha(int k, const double* rr, const double* pAp, int* acti
 hipError_t launch_cg_update1(const Layout& L, const float* AP, const float* P, float* X, float* R,
                              const double* alpha, double* part, hipStream_t s) {
   const int tiles = tiles_for(L);
-  const dim3 grid((unsigned)(L.np * tiles)), block(kBlock);
-  switch (L.pw) {
-    case 4: hipLaunchKernelGGL(k_cg_update1<4>, grid, block, 0, s, L, tiles, AP, P, X, R, alpha, part); break;
-    case 8: hipLaunchKernelGGL(k_cg_update1<8>, grid, block, 0, s, L, tiles, AP, P, X, R, alpha, part); break;
-    case 16: hipLaunchKernelGGL(k_cg_update1<16>, grid, block, 0, s, L, tiles, AP, P, X, R, alpha, part); break;
-    case 32: hipLaunchKernelGGL(k_cg_update1<32>, grid, block, 0, s, L, tiles, AP, P, X, R, alpha, part); break;
-    case 64: hipLaunchKernelGGL(k_cg_update1<64>, grid, block, 0, s, L, tiles, AP, P, X, R, alpha, part); break;
-    default: return hipErrorInvalidValue;
-  }
+  hipLaunchKernelGGL(k_cg_update1, dim3((unsigned)(L.np * tiles)), dim3(kBlock), 0, s, L, tiles,
+                     AP, P, X, R, alpha, part);
   return hipGetLastError();
 }
 
@@ -805,15 +784,8 @@ hipError_t launch_cg_scalar(int k, const double* rrn, double* rr, const double* 
 
 hipError_t launch_cg_update2(const Layout& L, const float* R, float* P, const double* beta,
                              const int* active, hipStream_t s) {
-  const dim3 grid(grid_for(L.elems() / 4)), block(kBlock);
-  switch (L.pw) {
-    case 4: hipLaunchKernelGGL(k_cg_update2<4>, grid, block, 0, s, L, R, P, beta, active); break;
-    case 8: hipLaunchKernelGGL(k_cg_update2<8>, grid, block, 0, s, L, R, P, beta, active); break;
-    case 16: hipLaunchKernelGGL(k_cg_update2<16>, grid, block, 0, s, L, R, P, beta, active); break;
-    case 32: hipLaunchKernelGGL(k_cg_update2<32>, grid, block, 0, s, L, R, P, beta, active); break;
-    case 64: hipLaunchKernelGGL(k_cg_update2<64>, grid, block, 0, s, L, R, P, beta, active); break;
-    default: return hipErrorInvalidValue;
-  }
+  hipLaunchKernelGGL(k_cg_update2, dim3(grid_for(L.elems() / 4)), dim3(kBlock), 0, s, L, R, P,
+                     beta, active);
   return hipGetLastError();
 }
 

@@ -31,7 +31,16 @@ struct StepArgs {
   int lds = 0;
   const float* mask = nullptr;   // EPI_CG
   float gamma = 0.f;
+  int xcd = 0;                   // XCD-aware work-unit order
+  int nt = 0;                    // non-temporal loads/stores for streamed blocks
 };
+
+// Process-wide kernel tuning (csc_set_tuning).
+struct Tuning {
+  int xcd = 1;
+  int nt = 0;
+};
+Tuning tuning();
 
 int rows_per_tile(int pw);
 int tiles_for(const Layout& L);

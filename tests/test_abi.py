@@ -43,8 +43,11 @@ def test_version_and_panel_width_validation():
     assert lib.csc_set_panel_width(3) == _lib.CSC_E_INVALID_ARG
     assert b"panel width" in lib.csc_last_error()
     assert lib.csc_set_panel_width(8) == _lib.CSC_OK
-    assert lib.csc_get_panel_width(1000, 47) == 8
+    assert lib.csc_get_panel_width(1000, 16000, 47) == 8
     assert lib.csc_set_panel_width(0) == _lib.CSC_OK
+    # built-in choice follows gathered cache lines: 128-byte aligned rows when padding is cheap
+    widths = [lib.csc_get_panel_width(100000, 1600000, w) for w in (1, 24, 28, 47, 56, 100, 250)]
+    assert widths == [4, 32, 32, 48, 64, 100, 256], widths
 
 
 def test_argument_errors_are_reported_without_gpu_work():

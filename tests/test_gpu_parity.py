@@ -24,7 +24,7 @@ from oracle import csc as ocsc
 
 pytestmark = pytest.mark.gpu
 
-PANEL_WIDTHS = (4, 8, 16, 32, 64)
+PANEL_WIDTHS = (4, 8, 12, 16, 28, 32, 48, 64, 100, 256)
 
 
 @pytest.fixture(scope="module")
@@ -344,3 +344,29 @@ def test_determinism(api, ragged):
     c1, m1 = api.eigencount(g, 0.5, 50, 14, 2, 1)
     c2, m2 = api.eigencount(g, 0.5, 50, 14, 2, 1)
     assert c1 == c2 and np.array_equal(m1, m2)
+
+
+@pytest.mark.parametrize("xcd", [0, 1])
+@pytest.mark.parametrize("nt", [0, 1])
+@pytest.mark.parametrize("pw", [8, 28, 52, 100, 256])
+def test_tuning_knobs_do_not_change_results(api, ragged, xcd, nt, pw):
+    from paper_1602_02018_amd import _lib
+
+    keys = (_lib.TUNE_XCD_ORDER, _lib.TUNE_NONTEMPORAL, _lib.TUNE_PANEL_WIDTH)
+    old = [api.get_tuning(k) for k in keys]
+    try:
+        for k, v in zip(keys, (xcd, nt, pw)):
+            api.set_tuning(k, v)
+        g = api.Graph(ragged.row_ptr, ragged.col)
+        X = api.gaussian_block(ragged.n, 37, 2, 0, 2)
+        a = jackson.lowpass_coeffs(0.7, 20)
+        Y = api.filter_block(g, a, X).cpu().numpy()
+        ref = cheb.filter_block(_A(ragged), X.cpu().numpy().astype(np.float64), a)
+        assert _relfro(Y, ref) <= 1e-4
+        cnt, mom = api.eigencount(g, 0.5, 30, 11, 5, 1)
+        R = philox.gaussian_block(5, ragged.n, 11, 1, philox.COUNT)
+        mref = cheb.moments(_A(ragged), R, 30)
+        assert np.max(np.abs(mom - mref)) <= 1e-5 * mref[0]
+    finally:
+        for k, v in zip(keys, old):
+            api.set_tuning(k, v)
