@@ -99,11 +99,15 @@ int32_t csc_get_panel_width(int32_t n, int64_t nnz, int32_t w);
  *   panel-major row tiles.
  * CSC_TUNE_NONTEMPORAL (0/1, default 0): non-temporal loads and stores for
  *   the streamed blocks (T_{m-1}, T_{m+1}, accumulators).
+ * CSC_TUNE_HIP_GRAPHS (0/1, default 1): the batched calls record their
+ *   repeated passes (eigencount passes, CG iterations) once as a HIP graph
+ *   and replay it; 0 launches every kernel directly.
  * csc_get_tuning returns the current value (-1 for an unknown key). */
 enum {
   CSC_TUNE_PANEL_WIDTH = 0,
   CSC_TUNE_XCD_ORDER = 1,
-  CSC_TUNE_NONTEMPORAL = 2
+  CSC_TUNE_NONTEMPORAL = 2,
+  CSC_TUNE_HIP_GRAPHS = 3
 };
 csc_status csc_set_tuning(int32_t key, int32_t value);
 int32_t csc_get_tuning(int32_t key);
@@ -247,6 +251,74 @@ csc_status csc_interpolate(const csc_graph* g, double lambda_k, int32_t p, doubl
                            double tol, int32_t max_iter, float* X, int32_t ldx, int32_t* labels,
                            int32_t* iters_out, double* relres_out, void* ws, size_t ws_bytes,
                            void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched form: the same steps for G graphs of uneven size at once.  Every
+ * Chebyshev step, reduction and CG update is one kernel launch covering all
+ * graphs (workgroups stride over a table of per-graph work units); the
+ * repeated passes (one eigencount pass per dichotomy step, one CG iteration)
+ * are recorded once as a HIP graph and replayed (CSC_TUNE_HIP_GRAPHS).
+ * Graph g follows exactly the arithmetic of the single-graph call with the
+ * same arguments, so its outputs are bit-identical to that call's.
+ * `graphs` is a host array of G csc_graph (device pointers inside); every
+ * other per-graph array below is a host array indexed by g, and "device
+ * per-graph" means a host array of G device pointers.  Workspaces: device, at
+ * least the size returned by the matching *_workspace_bytes_batched call.
+ * Per-graph statuses are written to status_out[g].
+ *
+ * csc_estimate_lambda_k_batched: csc_estimate_lambda_k for every graph
+ * (k[g], n_signals[g], seeds[g], brackets[2g..2g+1] or NULL for [0, 2]);
+ * each dichotomy round runs one batched eigencount pass for the graphs still
+ * searching.  lambda_out, steps_out, status_out: host[G]; trace_out:
+ * host[G][2*max_steps][2] or NULL; moments_out: host[G][p+1] or NULL.
+ * Synchronises.
+ */
+size_t csc_estimate_workspace_bytes_batched(const csc_graph* graphs, int32_t G,
+                                            const int32_t* n_signals, int32_t p);
+csc_status csc_estimate_lambda_k_batched(const csc_graph* graphs, int32_t G, const int32_t* k,
+                                         int32_t p, const int32_t* n_signals,
+                                         const uint64_t* seeds, int32_t max_steps,
+                                         const double* brackets, double* lambda_out,
+                                         int32_t* steps_out, double* trace_out,
+                                         double* moments_out, int32_t* status_out, void* ws,
+                                         size_t ws_bytes, void* stream);
+
+/* csc_filter_batched: csc_filter in its sampled-rows form for every graph
+ * (lambda[g], d[g], seeds[g], rows[g] device per-graph with n_rows[g]
+ * entries, output Y[g] device per-graph n_rows[g] x d[g] with ld[g]). */
+size_t csc_filter_workspace_bytes_batched(const csc_graph* graphs, int32_t G, const int32_t* d,
+                                          int32_t p);
+csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, const double* lambda,
+                              int32_t p, const int32_t* d, const uint64_t* seeds,
+                              const int32_t* const* rows, const int32_t* n_rows,
+                              int32_t normalize, float* const* Y, const int32_t* ld, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* csc_interpolate_batched: csc_interpolate for every graph (lambda[g],
+ * idx[g] / labels_r[g] device per-graph of n[g] entries, k[g]); all graphs'
+ * CG iterations advance together, a graph leaving the batch once its columns
+ * converge (or after max_iter iterations).  X: device per-graph N_g x k[g]
+ * with ldx[g] (X or X[g] may be NULL), labels: device per-graph int32[N_g].
+ * iters_out / relres_out: host arrays of sum_g k[g] entries (graph-major) or
+ * NULL.  Returns CSC_W_NOT_CONVERGED if any graph did not converge. */
+size_t csc_interpolate_workspace_bytes_batched(const csc_graph* graphs, int32_t G,
+                                               const int32_t* k, int32_t p);
+csc_status csc_interpolate_batched(const csc_graph* graphs, int32_t G, const double* lambda,
+                                   int32_t p, double gamma, const int32_t* const* idx,
+                                   const int32_t* const* labels_r, const int32_t* n,
+                                   const int32_t* k, double tol, int32_t max_iter,
+                                   float* const* X, const int32_t* ldx, int32_t* const* labels,
+                                   int32_t* iters_out, double* relres_out, int32_t* status_out,
+                                   void* ws, size_t ws_bytes, void* stream);
+
+/* csc_kmeans_reduced_batched: csc_kmeans_reduced for G independent float32
+ * inputs F[g] (host n[g] x d[g], leading dimension d[g]) with k[g] and
+ * seeds[g]; the (graph, replicate) runs share one pool of host threads.
+ * labels[g]: host int32[n[g]]; inertia_out: host[G] or NULL. */
+csc_status csc_kmeans_reduced_batched(int32_t G, const float* const* F, const int32_t* n,
+                                      const int32_t* d, const int32_t* k, int32_t replicates,
+                                      int32_t max_iter, const uint64_t* seeds,
+                                      int32_t* const* labels, double* inertia_out);
 
 /* ------------------------------------------------------------------------
  * Measurement hook (not a step of Alg. 2).  Launches exactly `steps`

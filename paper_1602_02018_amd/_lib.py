@@ -22,7 +22,7 @@ CSC_W_BRACKET_MISS = 7
 WARNINGS = (CSC_W_NOT_CONVERGED, CSC_W_BISECT_EXHAUSTED, CSC_W_BRACKET_MISS)
 
 STREAM_COUNT, STREAM_FEAT, STREAM_SAMPLE, STREAM_KMEANS = 1, 2, 3, 4
-TUNE_PANEL_WIDTH, TUNE_XCD_ORDER, TUNE_NONTEMPORAL = 0, 1, 2
+TUNE_PANEL_WIDTH, TUNE_XCD_ORDER, TUNE_NONTEMPORAL, TUNE_HIP_GRAPHS = 0, 1, 2, 3
 
 
 class CscGraph(C.Structure):
@@ -40,6 +40,7 @@ i32, u32, u64, f64, vp, sz = C.c_int32, C.c_uint32, C.c_uint64, C.c_double, C.c_
 pg = C.POINTER(CscGraph)
 pd = C.POINTER(C.c_double)
 pi = C.POINTER(C.c_int32)
+pu = C.POINTER(C.c_uint64)
 
 # name: (restype, argtypes)
 PROTOTYPES = {
@@ -65,6 +66,15 @@ PROTOTYPES = {
     "csc_interpolate_workspace_bytes": (sz, [i32, i32, i32]),
     "csc_interpolate": (i32, [pg, f64, i32, f64, vp, vp, i32, i32, f64, i32, vp, i32, vp, pi, pd,
                               vp, sz, vp]),
+    "csc_estimate_workspace_bytes_batched": (sz, [pg, i32, pi, i32]),
+    "csc_estimate_lambda_k_batched": (i32, [pg, i32, pi, i32, pi, pu, i32, pd, pd, pi, pd, pd, pi,
+                                            vp, sz, vp]),
+    "csc_filter_workspace_bytes_batched": (sz, [pg, i32, pi, i32]),
+    "csc_filter_batched": (i32, [pg, i32, pd, i32, pi, pu, vp, pi, i32, vp, pi, vp, sz, vp]),
+    "csc_interpolate_workspace_bytes_batched": (sz, [pg, i32, pi, i32]),
+    "csc_interpolate_batched": (i32, [pg, i32, pd, i32, f64, vp, vp, pi, pi, f64, i32, vp, pi, vp,
+                                      pi, pd, pi, vp, sz, vp]),
+    "csc_kmeans_reduced_batched": (i32, [i32, vp, pi, pi, pi, i32, i32, pu, vp, pd]),
     "csc_cheb_steps_workspace_bytes": (sz, [i32, i32]),
     "csc_cheb_steps": (i32, [pg, i32, i32, i32, i32, vp, sz, vp]),
 }

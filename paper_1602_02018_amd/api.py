@@ -275,3 +275,145 @@ def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
     tm.update(bisection_s=t1 - t0, features_s=t2 - t1, kmeans_s=t3 - t2, interpolate_s=t4 - t3,
               total_s=t4 - t0)
     return Result(lam, bis, omega, F, labels_r, inertia, it, tm)
+
+
+# ------------------------------------------------------------ batched --------
+
+def _i32(xs):
+    return np.ascontiguousarray(xs, dtype=np.int32)
+
+
+def _pa(ptrs):
+    """ctypes array of void pointers (device or host addresses)."""
+    arr = (C.c_void_p * len(ptrs))(*[C.c_void_p(int(p) if p else 0) for p in ptrs])
+    return arr
+
+
+def _graphs(graphs):
+    return (CscGraph * len(graphs))(*[g.c for g in graphs])
+
+
+def estimate_lambda_k_batched(graphs, ks, p, n_signals, seeds, max_steps=30, brackets=None):
+    G = len(graphs)
+    ga = _graphs(graphs)
+    ks, ns = _i32(ks), _i32(n_signals)
+    sd = np.ascontiguousarray(seeds, dtype=np.uint64)
+    lam = np.zeros(G)
+    steps = np.zeros(G, dtype=np.int32)
+    status = np.zeros(G, dtype=np.int32)
+    trace = np.zeros((G, 2 * max_steps, 2))
+    mom = np.zeros((G, p + 1))
+    br = None
+    if brackets is not None:
+        br_arr = np.ascontiguousarray(brackets, dtype=np.float64).reshape(G, 2)
+        br = br_arr.ctypes.data_as(_lib.pd)
+    dev = graphs[0].device
+    ws = _ws(lib().csc_estimate_workspace_bytes_batched(ga, G, ns.ctypes.data_as(_lib.pi), p), dev)
+    check(lib().csc_estimate_lambda_k_batched(
+        ga, G, ks.ctypes.data_as(_lib.pi), p, ns.ctypes.data_as(_lib.pi), sd.ctypes.data_as(_lib.pu),
+        max_steps, br, lam.ctypes.data_as(_lib.pd), steps.ctypes.data_as(_lib.pi),
+        trace.ctypes.data_as(_lib.pd), mom.ctypes.data_as(_lib.pd), status.ctypes.data_as(_lib.pi),
+        _ptr(ws), ws.numel(), _stream()), "csc_estimate_lambda_k_batched")
+    return [Bisection(float(lam[g]), int(steps[g]),
+                      [(trace[g, i, 0], trace[g, i, 1]) for i in range(steps[g])], mom[g].copy(),
+                      int(status[g])) for g in range(G)]
+
+
+def filter_batched(graphs, lams, p, ds, seeds, rows, normalize=True):
+    G = len(graphs)
+    ga = _graphs(graphs)
+    dev = graphs[0].device
+    rows_t = [_i32_device(r, dev) for r in rows]
+    n_rows = _i32([r.numel() for r in rows_t])
+    ds = _i32(ds)
+    Ys = [torch.empty((int(n_rows[g]), int(ds[g])), dtype=torch.float32, device=dev) for g in range(G)]
+    lam = np.ascontiguousarray(lams, dtype=np.float64)
+    sd = np.ascontiguousarray(seeds, dtype=np.uint64)
+    ws = _ws(lib().csc_filter_workspace_bytes_batched(ga, G, ds.ctypes.data_as(_lib.pi), p), dev)
+    check(lib().csc_filter_batched(ga, G, lam.ctypes.data_as(_lib.pd), p, ds.ctypes.data_as(_lib.pi),
+                                   sd.ctypes.data_as(_lib.pu), _pa([r.data_ptr() for r in rows_t]),
+                                   n_rows.ctypes.data_as(_lib.pi), 1 if normalize else 0,
+                                   _pa([y.data_ptr() for y in Ys]), ds.ctypes.data_as(_lib.pi),
+                                   _ptr(ws), ws.numel(), _stream()), "csc_filter_batched")
+    return Ys
+
+
+def interpolate_batched(graphs, lams, p, gamma, idx, labels_r, ks, tol=1e-6, max_iter=1000,
+                        want_X=True):
+    G = len(graphs)
+    ga = _graphs(graphs)
+    dev = graphs[0].device
+    idx_t = [_i32_device(x, dev) for x in idx]
+    lab_t = [_i32_device(x, dev) for x in labels_r]
+    ns = _i32([x.numel() for x in idx_t])
+    ks = _i32(ks)
+    Xs = [torch.empty((g.n, int(ks[i])), dtype=torch.float32, device=dev) if want_X else None
+          for i, g in enumerate(graphs)]
+    labels = [torch.empty(g.n, dtype=torch.int32, device=dev) for g in graphs]
+    iters = np.zeros(int(ks.sum()), dtype=np.int32)
+    relres = np.zeros(int(ks.sum()))
+    status = np.zeros(G, dtype=np.int32)
+    lam = np.ascontiguousarray(lams, dtype=np.float64)
+    ws = _ws(lib().csc_interpolate_workspace_bytes_batched(ga, G, ks.ctypes.data_as(_lib.pi), p), dev)
+    st = check(lib().csc_interpolate_batched(
+        ga, G, lam.ctypes.data_as(_lib.pd), p, float(gamma), _pa([x.data_ptr() for x in idx_t]),
+        _pa([x.data_ptr() for x in lab_t]), ns.ctypes.data_as(_lib.pi), ks.ctypes.data_as(_lib.pi),
+        float(tol), max_iter, _pa([x.data_ptr() if x is not None else 0 for x in Xs]) if want_X else None,
+        ks.ctypes.data_as(_lib.pi), _pa([x.data_ptr() for x in labels]),
+        iters.ctypes.data_as(_lib.pi), relres.ctypes.data_as(_lib.pd), status.ctypes.data_as(_lib.pi),
+        _ptr(ws), ws.numel(), _stream()), "csc_interpolate_batched")
+    out, off = [], 0
+    for g in range(G):
+        kg = int(ks[g])
+        out.append(Interpolation(Xs[g], labels[g], iters[off:off + kg].copy(),
+                                 relres[off:off + kg].copy(), int(status[g])))
+        off += kg
+    return out
+
+
+def kmeans_reduced_batched(Fs, ks, seeds, replicates=20, max_iter=100):
+    G = len(Fs)
+    Fs = [np.ascontiguousarray(f.detach().cpu().numpy() if isinstance(f, torch.Tensor) else f,
+                               dtype=np.float32) for f in Fs]
+    ns = _i32([f.shape[0] for f in Fs])
+    ds = _i32([f.shape[1] for f in Fs])
+    ks = _i32(ks)
+    sd = np.ascontiguousarray(seeds, dtype=np.uint64)
+    labels = [np.zeros(f.shape[0], dtype=np.int32) for f in Fs]
+    inertia = np.zeros(G)
+    check(lib().csc_kmeans_reduced_batched(G, _pa([f.ctypes.data for f in Fs]), ns.ctypes.data_as(_lib.pi),
+                                           ds.ctypes.data_as(_lib.pi), ks.ctypes.data_as(_lib.pi),
+                                           replicates, max_iter, sd.ctypes.data_as(_lib.pu),
+                                           _pa([l.ctypes.data for l in labels]),
+                                           inertia.ctypes.data_as(_lib.pd)), "csc_kmeans_reduced_batched")
+    return labels, inertia
+
+
+def run_batched(graphs, ks, ds, seeds, p=50, ns=None, gamma=1e-3, n_cs=None, tol=1e-6,
+                max_iter=1000, max_steps=30, replicates=20, kmeans_iter=100, brackets=None,
+                lams=None, want_X=False):
+    """Alg. 2 for G graphs at once with the batched calls; graph g matches run(graphs[g], ...)."""
+    G = len(graphs)
+    ns = [default_n(k) for k in ks] if ns is None else list(ns)
+    n_cs = [count_signals(g.n) for g in graphs] if n_cs is None else list(n_cs)
+    tm = {}
+    t0 = time.perf_counter()
+    if lams is None:
+        bis = estimate_lambda_k_batched(graphs, ks, p, n_cs, seeds, max_steps, brackets)
+        lams = [b.lam for b in bis]
+    else:
+        bis = [Bisection(l, 0, [], np.zeros(p + 1), 0) for l in lams]
+    t1 = time.perf_counter()
+    omegas = [sample(g.n, n, sd, g.device) for g, n, sd in zip(graphs, ns, seeds)]
+    Fs = filter_batched(graphs, lams, p, ds, seeds, omegas, normalize=True)
+    Fh = [f.cpu().numpy() for f in Fs]
+    t2 = time.perf_counter()
+    labels_r, inertia = kmeans_reduced_batched(Fh, ks, seeds, replicates, kmeans_iter)
+    t3 = time.perf_counter()
+    its = interpolate_batched(graphs, lams, p, gamma, omegas, labels_r, ks, tol, max_iter, want_X)
+    torch.cuda.current_stream().synchronize()
+    t4 = time.perf_counter()
+    tm.update(bisection_s=t1 - t0, features_s=t2 - t1, kmeans_s=t3 - t2, interpolate_s=t4 - t3,
+              total_s=t4 - t0)
+    return [Result(lams[g], bis[g], omegas[g], Fs[g], labels_r[g], float(inertia[g]), its[g], dict(tm))
+            for g in range(G)]

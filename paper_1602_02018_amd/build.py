@@ -19,6 +19,8 @@ ARCH = "gfx950"
 SOURCES = {
     "kernels.hip": [],
     "api.hip": [],
+    "batched.hip": [],
+    "api_batched.hip": [],
     "kmeans.hip": ["-ffp-contract=off"],
 }
 

@@ -3,12 +3,13 @@
 // runs in the kernels of kernels.hip.
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
 
-#include "kernels.hpp"
+#include "host.hpp"
 
 namespace csc {
 
@@ -17,6 +18,7 @@ thread_local std::string g_error;
 std::atomic<int> g_panel_override{0};
 std::atomic<int> g_tune_xcd{1};
 std::atomic<int> g_tune_nt{0};
+std::atomic<int> g_tune_graphs{1};
 }  // namespace
 
 void set_error(const std::string& msg) { g_error = msg; }
@@ -29,6 +31,21 @@ Tuning tuning() {
   t.xcd = g_tune_xcd.load();
   t.nt = g_tune_nt.load();
   return t;
+}
+
+int use_hip_graphs() { return g_tune_graphs.load(); }
+
+// Stream used only to record HIP graphs (kernels are captured, never run on
+// it); one per device, default priority, kept for the life of the process.
+hipStream_t capture_stream() {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+    streams[dev] = nullptr;
+  return streams[dev];
 }
 
 void apply_tuning(StepArgs& sa) {
@@ -73,9 +90,7 @@ Layout make_layout(int n, int w, int pw) {
   return L;
 }
 
-namespace {
-
-inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 csc_status check_graph(const csc_graph* g) {
   CSC_REQUIRE(g != nullptr, "graph is NULL");
@@ -112,6 +127,8 @@ void jackson_lowpass(double lc, int p, double* a) {
     a[m] = g * c;
   }
 }
+
+namespace {
 
 // Buffers of one p-step pass.
 struct Pass {
@@ -167,12 +184,9 @@ csc_status chebyshev_pass(const csc_graph& g, const Layout& L, const double* a, 
   return CSC_OK;
 }
 
-// ------------------------------------------------------ workspace plans ---
-struct FilterPlan {
-  Layout L;
-  size_t bytes = 0;
-};
+}  // namespace
 
+// ------------------------------------------------------ workspace plans ---
 size_t filter_bytes(const Layout& L) {
   size_t b = 0;
   b += 4 * align_up(L.bytes());                // T0, Ta, Tb, Y
@@ -201,6 +215,7 @@ size_t interp_bytes(const Layout& L) {
   return b + 256;
 }
 
+namespace {
 template <class F>
 size_t max_over_widths(int n, int w, F f) {
   size_t m = 0;
@@ -245,6 +260,8 @@ csc_status moments_pass(const csc_graph& g, const Layout& L, int p, uint64_t see
   return CSC_OK;
 }
 
+}  // namespace
+
 double count_from_moments(double lambda, int p, const double* mom) {
   std::vector<double> a(p + 1);
   jackson_lowpass(lambda, p, a.data());
@@ -253,7 +270,6 @@ double count_from_moments(double lambda, int p, const double* mom) {
   return c;
 }
 
-}  // namespace
 }  // namespace csc
 
 using namespace csc;
@@ -288,6 +304,10 @@ extern "C" csc_status csc_set_tuning(int32_t key, int32_t value) {
       CSC_REQUIRE(value == 0 || value == 1, "value must be 0 or 1");
       g_tune_nt.store(value);
       return CSC_OK;
+    case CSC_TUNE_HIP_GRAPHS:
+      CSC_REQUIRE(value == 0 || value == 1, "value must be 0 or 1");
+      g_tune_graphs.store(value);
+      return CSC_OK;
     default:
       CSC_REQUIRE(false, "unknown tuning key");
   }
@@ -298,6 +318,7 @@ extern "C" int32_t csc_get_tuning(int32_t key) {
     case CSC_TUNE_PANEL_WIDTH: return g_panel_override.load();
     case CSC_TUNE_XCD_ORDER: return g_tune_xcd.load();
     case CSC_TUNE_NONTEMPORAL: return g_tune_nt.load();
+    case CSC_TUNE_HIP_GRAPHS: return g_tune_graphs.load();
     default: return -1;
   }
 }

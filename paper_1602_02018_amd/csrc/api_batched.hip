@@ -1,0 +1,723 @@
+// Batched C calls: Alg. 2 steps 1, 3-4 and 7 for G graphs of uneven size and
+// width at once.  Every Chebyshev step, reduction and CG update is one launch
+// for all graphs (batched.hip); the repeated passes (one eigencount pass per
+// dichotomy step, one CG iteration) are recorded once as a HIP graph and
+// replayed.  Each graph follows exactly the arithmetic of the single-graph
+// calls, so outputs are bit-identical to calling those graph by graph.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host.hpp"
+
+namespace csc {
+namespace {
+
+struct Captured {
+  hipGraphExec_t exec = nullptr;
+  Captured() = default;
+  Captured(const Captured&) = delete;
+  Captured& operator=(const Captured&) = delete;
+  ~Captured() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+};
+
+// Records launch(stream) as a HIP graph on the capture stream.
+template <class F>
+csc_status capture(F&& launch, Captured& out) {
+  hipStream_t cs = capture_stream();
+  if (!cs) {
+    set_error("could not create the graph-capture stream");
+    return CSC_E_HIP;
+  }
+  CSC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  const csc_status st = launch(cs);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(cs, &graph);
+  if (st != CSC_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) {
+    set_error(std::string("hipStreamEndCapture failed: ") + hipGetErrorString(e));
+    return CSC_E_HIP;
+  }
+  const hipError_t e2 = hipGraphInstantiate(&out.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) {
+    out.exec = nullptr;
+    set_error(std::string("hipGraphInstantiate failed: ") + hipGetErrorString(e2));
+    return CSC_E_HIP;
+  }
+  return CSC_OK;
+}
+
+// Replays the recorded pass (recording it on first use), or launches directly.
+template <class F>
+csc_status run_pass(F&& launch, Captured& cap, hipStream_t s) {
+  if (!use_hip_graphs()) return launch(s);
+  if (!cap.exec) CSC_TRY(capture(launch, cap));
+  CSC_HIP(hipGraphLaunch(cap.exec, s));
+  return CSC_OK;
+}
+
+template <class T>
+csc_status upload(T* dst, const std::vector<T>& src, hipStream_t s) {
+  CSC_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return CSC_OK;
+}
+
+// Chunk size: up to 8 units per workgroup while keeping >= 16384 workgroups.
+int chunk_for(const std::vector<int>& units) {
+  long long tot = 0;
+  for (int u : units) tot += u;
+  return (int)std::max(1LL, std::min(8LL, tot / 16384));
+}
+
+// Work list of a per-graph unit count in the workspace; returns its table.
+struct WorkList {
+  std::vector<Work> h;
+  Work* d = nullptr;
+  BTable table() const { return BTable{d, (int)h.size()}; }
+};
+
+void plan_work(Arena& ar, const std::vector<int>& units, int chunk, WorkList& wl) {
+  build_work(units.data(), (int)units.size(), chunk, wl.h);
+  wl.d = ar.take<Work>(std::max<size_t>(wl.h.size(), 1));
+}
+
+size_t work_bytes(const std::vector<int>& units) {
+  size_t n = 0;
+  for (int u : units) n += (size_t)u;  // chunk >= 1 => at most one entry per unit
+  return align_up(std::max<size_t>(n, 1) * sizeof(Work));
+}
+
+template <class F>
+size_t max_widths(int n, int w, F f) {
+  size_t m = 0;
+  for (int pw = 4; pw <= 256; pw += 4) m = std::max(m, f(make_layout(n, w, pw)));
+  return m;
+}
+
+// Largest number of (panel, tile) units and of block elements over all panel widths.
+size_t max_units(int n, int w) {
+  size_t m = 0;
+  for (int pw = 4; pw <= 256; pw += 4) {
+    const Layout L = make_layout(n, w, pw);
+    m = std::max(m, (size_t)L.np * tiles_for(L));
+  }
+  return m;
+}
+
+size_t max_elems(int n, int w) {
+  size_t m = 0;
+  for (int pw = 4; pw <= 256; pw += 4) m = std::max(m, make_layout(n, w, pw).elems());
+  return m;
+}
+
+int elem_units(size_t elems) { return (int)((elems + kElemsPerUnit - 1) / kElemsPerUnit); }
+
+csc_status check_graphs(const csc_graph* graphs, int G) {
+  CSC_REQUIRE(graphs != nullptr && G >= 1, "need at least one graph");
+  for (int g = 0; g < G; ++g) CSC_TRY(check_graph(&graphs[g]));
+  return CSC_OK;
+}
+
+size_t desc_bytes(int G, int p) {
+  size_t b = align_up((size_t)p * G * sizeof(StepArgs)) + align_up(G * sizeof(GaussItem)) +
+             2 * align_up(G * sizeof(ReduceItem)) + align_up(G * sizeof(ColDotItem)) +
+             align_up(G * sizeof(CgItem)) + align_up(G * sizeof(LabelItem));
+  b += 2 * align_up((size_t)G * sizeof(int));  // live flags, scratch flags
+  return b + 4096;
+}
+
+}  // namespace
+}  // namespace csc
+
+using namespace csc;
+
+// ------------------------------------------------------------ dichotomy ---
+extern "C" size_t csc_estimate_workspace_bytes_batched(const csc_graph* graphs, int32_t G,
+                                                       const int32_t* n_signals, int32_t p) {
+  if (!graphs || G < 1 || !n_signals || p < 1) return 0;
+  size_t b = desc_bytes(G, p) + align_up((size_t)G * (p + 1) * sizeof(double));
+  std::vector<int> u(G), gu(G), rv(G, p + 1);
+  for (int g = 0; g < G; ++g) {
+    b += max_widths(graphs[g].n, n_signals[g], [p](const Layout& L) { return count_bytes(L, p); });
+    u[g] = (int)std::min<size_t>(max_units(graphs[g].n, n_signals[g]), 1u << 30);
+    gu[g] = (int)((max_elems(graphs[g].n, n_signals[g]) + kElemsPerUnit - 1) / kElemsPerUnit);
+  }
+  return b + work_bytes(u) + work_bytes(gu) + work_bytes(rv);
+}
+
+extern "C" csc_status csc_estimate_lambda_k_batched(
+    const csc_graph* graphs, int32_t G, const int32_t* k, int32_t p, const int32_t* n_signals,
+    const uint64_t* seeds, int32_t max_steps, const double* brackets, double* lambda_out,
+    int32_t* steps_out, double* trace_out, double* moments_out, int32_t* status_out, void* ws,
+    size_t ws_bytes, void* stream) {
+  clear_error();
+  CSC_TRY(check_graphs(graphs, G));
+  CSC_REQUIRE(k && n_signals && seeds && lambda_out && steps_out && status_out,
+              "k, n_signals, seeds, lambda_out, steps_out and status_out must be non-NULL");
+  CSC_REQUIRE(p >= 1 && max_steps >= 1, "need p >= 1 and max_steps >= 1");
+  for (int g = 0; g < G; ++g) {
+    CSC_REQUIRE(k[g] >= 1 && k[g] <= graphs[g].n, "k[g] must lie in [1, N_g]");
+    CSC_REQUIRE(n_signals[g] >= 1, "n_signals[g] must be >= 1");
+    if (brackets)
+      CSC_REQUIRE(brackets[2 * g] >= 0.0 && brackets[2 * g + 1] <= 2.0 &&
+                      brackets[2 * g] < brackets[2 * g + 1],
+                  "brackets must satisfy 0 <= lo < hi <= 2");
+  }
+  CSC_TRY(check_ws(ws, ws_bytes,
+                   csc_estimate_workspace_bytes_batched(graphs, G, n_signals, p)));
+  hipStream_t s = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+
+  std::vector<Layout> L(G);
+  std::vector<int> tiles(G), units(G), gunits(G), rvec(G, p + 1);
+  std::vector<float*> T0(G), Ta(G), Tb(G);
+  std::vector<double*> part(G);
+  for (int g = 0; g < G; ++g) {
+    L[g] = make_layout(graphs[g].n, n_signals[g],
+                       choose_panel_width(graphs[g].n, n_signals[g], graphs[g].nnz));
+    tiles[g] = tiles_for(L[g]);
+    units[g] = L[g].np * tiles[g];
+    gunits[g] = elem_units(L[g].elems());
+    T0[g] = ar.take<float>(L[g].elems());
+    Ta[g] = ar.take<float>(L[g].elems());
+    Tb[g] = ar.take<float>(L[g].elems());
+    part[g] = ar.take<double>((size_t)(p + 1) * units[g]);
+  }
+  double* mom = ar.take<double>((size_t)G * (p + 1));
+  StepArgs* d_steps = ar.take<StepArgs>((size_t)p * G);
+  GaussItem* d_gauss = ar.take<GaussItem>(G);
+  ReduceItem* d_red = ar.take<ReduceItem>(G);
+  int* d_live = ar.take<int>(G);
+  WorkList w_step, w_gauss, w_red;
+  plan_work(ar, units, chunk_for(units), w_step);
+  plan_work(ar, gunits, chunk_for(gunits), w_gauss);
+  plan_work(ar, rvec, 1, w_red);
+  if (!ar.ok()) {
+    set_error("internal: batched workspace plan overflow");
+    return CSC_E_INVALID_ARG;
+  }
+
+  // per-step descriptors never change between passes
+  std::vector<StepArgs> h_steps((size_t)p * G);
+  std::vector<ReduceItem> h_red(G);
+  std::vector<GaussItem> h_gauss(G);
+  for (int g = 0; g < G; ++g) {
+    for (int m = 0; m < p; ++m) {
+      StepArgs& a = h_steps[(size_t)m * G + g];
+      a.L = L[g];
+      a.tiles = tiles[g];
+      a.row_ptr = graphs[g].row_ptr;
+      a.col = graphs[g].col;
+      a.val = graphs[g].val;
+      a.T0 = T0[g];
+      apply_tuning(a);
+      a.xcd = 0;
+      a.live = d_live + g;
+      const bool first = m == 0;
+      a.Tm = first ? T0[g] : ((m & 1) ? Ta[g] : Tb[g]);
+      a.Tprev = first ? T0[g] : ((m - 1) == 0 ? T0[g] : (((m - 1) & 1) ? Ta[g] : Tb[g]));
+      a.Tnext = ((m + 1) & 1) ? Ta[g] : Tb[g];
+      a.part = part[g] + (size_t)(m + 1) * units[g];
+      a.part2 = part[g];
+    }
+    h_red[g].part = part[g];
+    h_red[g].len = units[g];
+    h_red[g].out = mom + (size_t)g * (p + 1);
+    h_red[g].live = d_live + g;
+    h_gauss[g].L = L[g];
+    h_gauss[g].seed = seeds[g];
+    h_gauss[g].sid = CSC_STREAM_COUNT;
+    h_gauss[g].out = T0[g];
+    h_gauss[g].live = d_live + g;
+  }
+  CSC_TRY(upload(d_steps, h_steps, s));
+  CSC_TRY(upload(d_red, h_red, s));
+  CSC_TRY(upload(w_step.d, w_step.h, s));
+  CSC_TRY(upload(w_gauss.d, w_gauss.h, s));
+  CSC_TRY(upload(w_red.d, w_red.h, s));
+
+  auto pass = [&](hipStream_t st) -> csc_status {
+    CSC_HIP(launch_gaussian_batched(d_gauss, w_gauss.table(), st));
+    for (int m = 0; m < p; ++m)
+      CSC_HIP(launch_cheb_step_batched(d_steps + (size_t)m * G, w_step.table(), EPI_MOM, m == 0,
+                                       m + 1 == p, st));
+    CSC_HIP(launch_reduce_batched(d_red, w_red.table(), st));
+    return CSC_OK;
+  };
+
+  struct State {
+    double lo = 0.0, hi = 2.0;
+    int used = 0, t_in = 0, attempt = 0;
+    bool below = false, above = false, missed = false, done = false;
+  };
+  std::vector<State> st(G);
+  for (int g = 0; g < G; ++g)
+    if (brackets) {
+      st[g].lo = brackets[2 * g];
+      st[g].hi = brackets[2 * g + 1];
+    }
+  std::vector<int> live(G);
+  std::vector<double> hmom((size_t)G * (p + 1)), a(p + 1);
+  Captured cap;
+  for (int round = 0; round < 2 * max_steps; ++round) {
+    int nlive = 0;
+    for (int g = 0; g < G; ++g) {
+      live[g] = st[g].done ? 0 : 1;
+      nlive += live[g];
+      h_gauss[g].t = (uint32_t)(st[g].used + 1);
+    }
+    if (nlive == 0) break;
+    CSC_TRY(upload(d_live, live, s));
+    CSC_TRY(upload(d_gauss, h_gauss, s));
+    CSC_TRY(run_pass(pass, cap, s));
+    CSC_HIP(hipMemcpyAsync(hmom.data(), mom, hmom.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           s));
+    CSC_HIP(hipStreamSynchronize(s));
+    for (int g = 0; g < G; ++g) {
+      if (!live[g]) continue;
+      State& S = st[g];
+      const double* mg = hmom.data() + (size_t)g * (p + 1);
+      const double mid = 0.5 * (S.lo + S.hi);
+      const double cnt = count_from_moments(mid, p, mg);
+      if (S.used == 0 && moments_out)
+        std::memcpy(moments_out + (size_t)g * (p + 1), mg, (p + 1) * sizeof(double));
+      if (trace_out) {
+        trace_out[((size_t)g * 2 * max_steps + S.used) * 2] = mid;
+        trace_out[((size_t)g * 2 * max_steps + S.used) * 2 + 1] = cnt;
+      }
+      ++S.used;
+      ++S.t_in;
+      if (std::floor(cnt + 0.5) == (double)k[g]) {
+        lambda_out[g] = mid;
+        status_out[g] = S.missed ? CSC_W_BRACKET_MISS : CSC_OK;
+        S.done = true;
+        continue;
+      }
+      if (cnt < k[g]) {
+        S.lo = mid;
+        S.below = true;
+      } else {
+        S.hi = mid;
+        S.above = true;
+      }
+      if (S.t_in == max_steps) {
+        if (brackets && S.attempt == 0 && !(S.below && S.above)) {
+          S.missed = true;
+          S.attempt = 1;
+          S.t_in = 0;
+          S.lo = 0.0;
+          S.hi = 2.0;
+        } else {
+          lambda_out[g] = S.hi;
+          status_out[g] = S.missed ? CSC_W_BRACKET_MISS : CSC_W_BISECT_EXHAUSTED;
+          S.done = true;
+        }
+      }
+    }
+  }
+  for (int g = 0; g < G; ++g) steps_out[g] = st[g].used;
+  return CSC_OK;
+}
+
+// ---------------------------------------------------------- feature pass ---
+extern "C" size_t csc_filter_workspace_bytes_batched(const csc_graph* graphs, int32_t G,
+                                                     const int32_t* d, int32_t p) {
+  if (!graphs || G < 1 || !d || p < 1) return 0;
+  size_t b = desc_bytes(G, p);
+  std::vector<int> u(G), gu(G);
+  for (int g = 0; g < G; ++g) {
+    b += max_widths(graphs[g].n, d[g], [](const Layout& L) { return filter_bytes(L); });
+    u[g] = (int)max_units(graphs[g].n, d[g]);
+    gu[g] = (int)((max_elems(graphs[g].n, d[g]) + kElemsPerUnit - 1) / kElemsPerUnit);
+  }
+  return b + work_bytes(u) + work_bytes(gu);
+}
+
+extern "C" csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, const double* lambda,
+                                         int32_t p, const int32_t* d, const uint64_t* seeds,
+                                         const int32_t* const* rows, const int32_t* n_rows,
+                                         int32_t normalize, float* const* Y, const int32_t* ld,
+                                         void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  CSC_TRY(check_graphs(graphs, G));
+  CSC_REQUIRE(lambda && d && seeds && rows && n_rows && Y && ld,
+              "lambda, d, seeds, rows, n_rows, Y and ld must be non-NULL");
+  CSC_REQUIRE(p >= 1, "p must be >= 1");
+  for (int g = 0; g < G; ++g) {
+    CSC_REQUIRE(lambda[g] >= 0.0 && lambda[g] <= 2.0, "lambda[g] must lie in [0, 2]");
+    CSC_REQUIRE(d[g] >= 1 && ld[g] >= d[g], "need d[g] >= 1 and ld[g] >= d[g]");
+    CSC_REQUIRE(rows[g] && Y[g] && n_rows[g] >= 1 && n_rows[g] <= graphs[g].n,
+                "rows[g] and Y[g] must be non-NULL with 1 <= n_rows[g] <= N_g");
+  }
+  CSC_TRY(check_ws(ws, ws_bytes, csc_filter_workspace_bytes_batched(graphs, G, d, p)));
+  hipStream_t s = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  std::vector<Layout> L(G);
+  std::vector<int> tiles(G), units(G), gunits(G);
+  std::vector<float*> T0(G), Ta(G), Tb(G);
+  std::vector<int*> slot(G);
+  for (int g = 0; g < G; ++g) {
+    L[g] = make_layout(graphs[g].n, d[g], choose_panel_width(graphs[g].n, d[g], graphs[g].nnz));
+    tiles[g] = tiles_for(L[g]);
+    units[g] = L[g].np * tiles[g];
+    gunits[g] = elem_units(L[g].elems());
+    T0[g] = ar.take<float>(L[g].elems());
+    Ta[g] = ar.take<float>(L[g].elems());
+    Tb[g] = ar.take<float>(L[g].elems());
+    slot[g] = ar.take<int>(graphs[g].n);
+  }
+  StepArgs* d_steps = ar.take<StepArgs>((size_t)p * G);
+  GaussItem* d_gauss = ar.take<GaussItem>(G);
+  int* bad = ar.take<int>(G);
+  WorkList w_step, w_gauss;
+  plan_work(ar, units, chunk_for(units), w_step);
+  plan_work(ar, gunits, chunk_for(gunits), w_gauss);
+  if (!ar.ok()) {
+    set_error("internal: batched workspace plan overflow");
+    return CSC_E_INVALID_ARG;
+  }
+  std::vector<StepArgs> h_steps((size_t)p * G);
+  std::vector<GaussItem> h_gauss(G);
+  std::vector<double> a(p + 1);
+  for (int g = 0; g < G; ++g) {
+    jackson_lowpass(lambda[g], p, a.data());
+    for (int m = 0; m < p; ++m) {
+      StepArgs& x = h_steps[(size_t)m * G + g];
+      x.L = L[g];
+      x.tiles = tiles[g];
+      x.row_ptr = graphs[g].row_ptr;
+      x.col = graphs[g].col;
+      x.val = graphs[g].val;
+      x.T0 = T0[g];
+      apply_tuning(x);
+      x.xcd = 0;
+      const bool first = m == 0;
+      x.Tm = first ? T0[g] : ((m & 1) ? Ta[g] : Tb[g]);
+      x.Tprev = first ? T0[g] : ((m - 1) == 0 ? T0[g] : (((m - 1) & 1) ? Ta[g] : Tb[g]));
+      x.Tnext = ((m + 1) & 1) ? Ta[g] : Tb[g];
+      x.c0 = (float)a[0];
+      x.c1 = (float)a[m + 1];
+      x.slot = slot[g];
+      x.Ys = Y[g];
+      x.lds = ld[g];
+    }
+    h_gauss[g].L = L[g];
+    h_gauss[g].seed = seeds[g];
+    h_gauss[g].t = 0;
+    h_gauss[g].sid = CSC_STREAM_FEAT;
+    h_gauss[g].out = T0[g];
+  }
+  CSC_TRY(upload(d_steps, h_steps, s));
+  CSC_TRY(upload(d_gauss, h_gauss, s));
+  CSC_TRY(upload(w_step.d, w_step.h, s));
+  CSC_TRY(upload(w_gauss.d, w_gauss.h, s));
+  CSC_HIP(launch_fill_i32(bad, G, 0, s));
+  for (int g = 0; g < G; ++g) {
+    CSC_HIP(launch_fill_i32(slot[g], graphs[g].n, -1, s));
+    CSC_HIP(launch_slot_map(n_rows[g], rows[g], graphs[g].n, slot[g], bad + g, s));
+  }
+  std::vector<int> hbad(G);
+  CSC_HIP(hipMemcpyAsync(hbad.data(), bad, G * sizeof(int), hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  for (int g = 0; g < G; ++g)
+    if (hbad[g]) {
+      set_error("rows[" + std::to_string(g) + "] holds an index outside [0, N)");
+      return CSC_E_INVALID_ARG;
+    }
+  CSC_HIP(launch_gaussian_batched(d_gauss, w_gauss.table(), s));
+  for (int m = 0; m < p; ++m)
+    CSC_HIP(launch_cheb_step_batched(d_steps + (size_t)m * G, w_step.table(), EPI_YS, m == 0,
+                                     m + 1 == p, s));
+  if (normalize)
+    for (int g = 0; g < G; ++g) CSC_HIP(launch_normalize_rows(n_rows[g], d[g], Y[g], ld[g], s));
+  return CSC_OK;
+}
+
+// --------------------------------------------------------- interpolation ---
+extern "C" size_t csc_interpolate_workspace_bytes_batched(const csc_graph* graphs, int32_t G,
+                                                          const int32_t* k, int32_t p) {
+  if (!graphs || G < 1 || !k || p < 1) return 0;
+  size_t b = desc_bytes(G, p) + align_up((size_t)G * 4 * sizeof(int));
+  std::vector<int> u(G), kv(G), u2(G), lu(G);
+  for (int g = 0; g < G; ++g) {
+    b += max_widths(graphs[g].n, k[g], [](const Layout& L) { return interp_bytes(L); });
+    u[g] = (int)max_units(graphs[g].n, k[g]);
+    kv[g] = k[g];
+    u2[g] = (int)((max_elems(graphs[g].n, k[g]) / 4 + kElemsPerUnit - 1) / kElemsPerUnit);
+    lu[g] = (graphs[g].n + 255) / 256;
+  }
+  return b + work_bytes(u) + work_bytes(kv) + work_bytes(u2) + work_bytes(lu);
+}
+
+extern "C" csc_status csc_interpolate_batched(
+    const csc_graph* graphs, int32_t G, const double* lambda, int32_t p, double gamma,
+    const int32_t* const* idx, const int32_t* const* labels_r, const int32_t* n, const int32_t* k,
+    double tol, int32_t max_iter, float* const* X, const int32_t* ldx, int32_t* const* labels,
+    int32_t* iters_out, double* relres_out, int32_t* status_out, void* ws, size_t ws_bytes,
+    void* stream) {
+  clear_error();
+  CSC_TRY(check_graphs(graphs, G));
+  CSC_REQUIRE(lambda && idx && labels_r && n && k && labels && status_out,
+              "lambda, idx, labels_r, n, k, labels and status_out must be non-NULL");
+  CSC_REQUIRE(p >= 1 && gamma > 0.0 && tol > 0.0 && max_iter >= 1,
+              "need p >= 1, gamma > 0, tol > 0, max_iter >= 1");
+  for (int g = 0; g < G; ++g) {
+    const int N = graphs[g].n;
+    CSC_REQUIRE(idx[g] && labels_r[g] && labels[g], "idx[g], labels_r[g], labels[g] must be non-NULL");
+    CSC_REQUIRE(k[g] >= 1 && k[g] <= N && n[g] >= 1 && n[g] <= N,
+                "need 1 <= k[g] <= N_g and 1 <= n[g] <= N_g");
+    CSC_REQUIRE(lambda[g] >= 0.0 && lambda[g] <= 2.0, "lambda[g] must lie in [0, 2]");
+    CSC_REQUIRE(!X || !X[g] || (ldx && ldx[g] >= k[g]), "ldx[g] must be >= k[g]");
+  }
+  CSC_TRY(check_ws(ws, ws_bytes, csc_interpolate_workspace_bytes_batched(graphs, G, k, p)));
+  hipStream_t s = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+
+  struct Buf {
+    Layout L;
+    int tiles, units, u2;
+    size_t wp;
+    float *P, *Ta, *Tb, *AP, *Xi, *Rr, *mask;
+    double *part, *rr, *rrn, *pAp, *alpha, *beta, *bnorm2, *colnorm2, *relres;
+    int *active, *iters;
+  };
+  std::vector<Buf> B(G);
+  for (int g = 0; g < G; ++g) {
+    Buf& b = B[g];
+    const int N = graphs[g].n;
+    b.L = make_layout(N, k[g], choose_panel_width(N, k[g], graphs[g].nnz));
+    b.tiles = tiles_for(b.L);
+    b.units = b.L.np * b.tiles;
+    b.u2 = elem_units(b.L.elems() / 4);
+    b.wp = (size_t)b.L.np * b.L.pw;
+    b.P = ar.take<float>(b.L.elems());
+    b.Ta = ar.take<float>(b.L.elems());
+    b.Tb = ar.take<float>(b.L.elems());
+    b.AP = ar.take<float>(b.L.elems());
+    b.Xi = ar.take<float>(b.L.elems());
+    b.Rr = ar.take<float>(b.L.elems());
+    b.mask = ar.take<float>(N);
+    b.part = ar.take<double>(b.wp * b.tiles);
+    b.rr = ar.take<double>(b.wp);
+    b.rrn = ar.take<double>(b.wp);
+    b.pAp = ar.take<double>(b.wp);
+    b.alpha = ar.take<double>(b.wp);
+    b.beta = ar.take<double>(b.wp);
+    b.bnorm2 = ar.take<double>(b.wp);
+    b.colnorm2 = ar.take<double>(b.wp);
+    b.active = ar.take<int>(b.wp);
+    b.iters = ar.take<int>(b.wp);
+    b.relres = ar.take<double>(b.wp);
+  }
+  int* flags = ar.take<int>((size_t)G * 4);  // per graph: nactive, breakdown, bad, it
+  int* d_live = ar.take<int>(G);
+  StepArgs* d_steps = ar.take<StepArgs>((size_t)p * G);
+  ReduceItem* d_red_pap = ar.take<ReduceItem>(G);
+  ReduceItem* d_red_rrn = ar.take<ReduceItem>(G);
+  CgItem* d_cg = ar.take<CgItem>(G);
+  ColDotItem* d_cd = ar.take<ColDotItem>(G);
+  LabelItem* d_lab = ar.take<LabelItem>(G);
+  std::vector<int> units(G), kvec(G), u2(G), lunits(G);
+  for (int g = 0; g < G; ++g) {
+    units[g] = B[g].units;
+    kvec[g] = k[g];
+    u2[g] = B[g].u2;
+    lunits[g] = (graphs[g].n + 255) / 256;  // kb_labels: one row per thread, 256 per unit
+  }
+  WorkList w_step, w_k, w_u2, w_lab;
+  plan_work(ar, units, chunk_for(units), w_step);
+  plan_work(ar, kvec, 1, w_k);
+  plan_work(ar, u2, chunk_for(u2), w_u2);
+  plan_work(ar, lunits, chunk_for(lunits), w_lab);
+  if (!ar.ok()) {
+    set_error("internal: batched workspace plan overflow");
+    return CSC_E_INVALID_ARG;
+  }
+
+  // set-up, graph by graph: zero blocks, scatter the right-hand sides, ||b_j||^2
+  CSC_HIP(launch_fill_i32(flags, (size_t)G * 4, 0, s));
+  std::vector<int> live(G, 1);
+  CSC_TRY(upload(d_live, live, s));
+  for (int g = 0; g < G; ++g) {
+    Buf& b = B[g];
+    CSC_HIP(launch_fill_f32(b.P, b.L.elems(), 0.f, s));
+    CSC_HIP(launch_fill_f32(b.Xi, b.L.elems(), 0.f, s));
+    CSC_HIP(launch_fill_f32(b.Rr, b.L.elems(), 0.f, s));
+    CSC_HIP(launch_fill_f32(b.mask, graphs[g].n, 0.f, s));
+    CSC_HIP(launch_fill_i32(b.iters, b.wp, 0, s));
+    CSC_HIP(launch_fill_f64(b.relres, b.wp, 0.0, s));
+    CSC_HIP(launch_cg_scatter(b.L, n[g], idx[g], labels_r[g], b.Rr, b.P, b.mask,
+                              flags + 4 * g + 2, s));
+    CSC_HIP(launch_col_dot(b.L, b.Rr, b.Rr, b.part, s));
+    CSC_HIP(launch_reduce(b.part, b.tiles, k[g], b.bnorm2, s));
+    CSC_HIP(hipMemcpyAsync(b.rr, b.bnorm2, k[g] * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  std::vector<int> hflags((size_t)G * 4);
+  CSC_HIP(hipMemcpyAsync(hflags.data(), flags, hflags.size() * sizeof(int),
+                         hipMemcpyDeviceToHost, s));
+  std::vector<std::vector<double>> hb(G);
+  for (int g = 0; g < G; ++g) {
+    hb[g].resize(k[g]);
+    CSC_HIP(hipMemcpyAsync(hb[g].data(), B[g].bnorm2, k[g] * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+  }
+  CSC_HIP(hipStreamSynchronize(s));
+  for (int g = 0; g < G; ++g) {
+    if (hflags[4 * g + 2]) {
+      set_error("idx[" + std::to_string(g) + "] or labels_r[" + std::to_string(g) +
+                "] holds a value out of range");
+      return CSC_E_INVALID_ARG;
+    }
+  }
+  {
+    std::vector<std::vector<int>> ha(G);
+    for (int g = 0; g < G; ++g) {
+      ha[g].resize(k[g]);
+      for (int j = 0; j < k[g]; ++j) ha[g][j] = hb[g][j] > 0.0 ? 1 : 0;
+      CSC_HIP(hipMemcpyAsync(B[g].active, ha[g].data(), k[g] * sizeof(int),
+                             hipMemcpyHostToDevice, s));
+    }
+    CSC_HIP(hipStreamSynchronize(s));
+  }
+
+  // descriptors of one CG iteration
+  std::vector<StepArgs> h_steps((size_t)p * G);
+  std::vector<ReduceItem> h_pap(G), h_rrn(G);
+  std::vector<CgItem> h_cg(G);
+  std::vector<double> a(p + 1);
+  for (int g = 0; g < G; ++g) {
+    const Buf& b = B[g];
+    jackson_lowpass(lambda[g], p, a.data());
+    for (int m = 0; m < p; ++m) {
+      StepArgs& x = h_steps[(size_t)m * G + g];
+      x.L = b.L;
+      x.tiles = b.tiles;
+      x.row_ptr = graphs[g].row_ptr;
+      x.col = graphs[g].col;
+      x.val = graphs[g].val;
+      x.T0 = b.P;
+      x.Y = b.AP;
+      x.mask = b.mask;
+      x.gamma = (float)gamma;
+      x.part = b.part;
+      apply_tuning(x);
+      x.xcd = 0;
+      x.live = d_live + g;
+      const bool first = m == 0;
+      x.Tm = first ? b.P : ((m & 1) ? b.Ta : b.Tb);
+      x.Tprev = first ? b.P : ((m - 1) == 0 ? b.P : (((m - 1) & 1) ? b.Ta : b.Tb));
+      x.Tnext = ((m + 1) & 1) ? b.Ta : b.Tb;
+      x.c0 = (float)a[0];
+      x.c1 = (float)a[m + 1];
+    }
+    h_pap[g] = ReduceItem{b.part, b.tiles, b.pAp, d_live + g};
+    h_rrn[g] = ReduceItem{b.part, b.tiles, b.rrn, d_live + g};
+    CgItem& c = h_cg[g];
+    c.L = b.L;
+    c.tiles = b.tiles;
+    c.k = k[g];
+    c.AP = b.AP;
+    c.P = b.P;
+    c.X = b.Xi;
+    c.R = b.Rr;
+    c.rr = b.rr;
+    c.rrn = b.rrn;
+    c.pAp = b.pAp;
+    c.alpha = b.alpha;
+    c.beta = b.beta;
+    c.bnorm2 = b.bnorm2;
+    c.active = b.active;
+    c.iters = b.iters;
+    c.relres = b.relres;
+    c.part = b.part;
+    c.nactive = flags + 4 * g;
+    c.breakdown = flags + 4 * g + 1;
+    c.it = flags + 4 * g + 3;
+    c.tol = tol;
+    c.max_iter = max_iter;
+    c.live = d_live + g;
+  }
+  CSC_TRY(upload(d_steps, h_steps, s));
+  CSC_TRY(upload(d_red_pap, h_pap, s));
+  CSC_TRY(upload(d_red_rrn, h_rrn, s));
+  CSC_TRY(upload(d_cg, h_cg, s));
+  CSC_TRY(upload(w_step.d, w_step.h, s));
+  CSC_TRY(upload(w_k.d, w_k.h, s));
+  CSC_TRY(upload(w_u2.d, w_u2.h, s));
+  CSC_TRY(upload(w_lab.d, w_lab.h, s));
+
+  auto iteration = [&](hipStream_t st) -> csc_status {
+    for (int m = 0; m < p; ++m) {
+      const bool last = m + 1 == p;
+      CSC_HIP(launch_cheb_step_batched(d_steps + (size_t)m * G, w_step.table(),
+                                       last ? EPI_CG : EPI_Y, m == 0, last, st));
+    }
+    CSC_HIP(launch_reduce_batched(d_red_pap, w_k.table(), st));
+    CSC_HIP(launch_cg_alpha_batched(d_cg, G, st));
+    CSC_HIP(launch_cg_update1_batched(d_cg, w_step.table(), st));
+    CSC_HIP(launch_reduce_batched(d_red_rrn, w_k.table(), st));
+    CSC_HIP(launch_cg_scalar_batched(d_cg, G, st));
+    CSC_HIP(launch_cg_update2_batched(d_cg, w_u2.table(), st));
+    return CSC_OK;
+  };
+  Captured cap;
+  for (int it = 1; it <= max_iter; ++it) {
+    CSC_TRY(run_pass(iteration, cap, s));
+    CSC_HIP(hipMemcpyAsync(live.data(), d_live, G * sizeof(int), hipMemcpyDeviceToHost, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    bool any = false;
+    for (int g = 0; g < G; ++g) any = any || live[g];
+    if (!any) break;
+  }
+
+  // column norms of X and hard labels
+  std::vector<ColDotItem> h_cd(G);
+  std::vector<ReduceItem> h_cn(G);
+  std::vector<LabelItem> h_lab(G);
+  for (int g = 0; g < G; ++g) {
+    const Buf& b = B[g];
+    h_cd[g] = ColDotItem{b.L, b.tiles, b.Xi, b.Xi, b.part, nullptr};
+    h_cn[g] = ReduceItem{b.part, b.tiles, b.colnorm2, nullptr};
+    h_lab[g] = LabelItem{b.L, b.Xi, b.colnorm2, labels[g], X ? X[g] : nullptr,
+                         (X && X[g]) ? ldx[g] : 0};
+  }
+  CSC_TRY(upload(d_cd, h_cd, s));
+  CSC_TRY(upload(d_red_pap, h_cn, s));
+  CSC_TRY(upload(d_lab, h_lab, s));
+  CSC_HIP(launch_col_dot_batched(d_cd, w_step.table(), s));
+  CSC_HIP(launch_reduce_batched(d_red_pap, w_k.table(), s));
+  CSC_HIP(launch_labels_batched(d_lab, w_lab.table(), s));
+
+  CSC_HIP(hipMemcpyAsync(hflags.data(), flags, hflags.size() * sizeof(int),
+                         hipMemcpyDeviceToHost, s));
+  size_t off = 0;
+  std::vector<std::vector<int>> hit(G);
+  std::vector<std::vector<double>> hrel(G);
+  for (int g = 0; g < G; ++g) {
+    hit[g].resize(k[g]);
+    hrel[g].resize(k[g]);
+    CSC_HIP(hipMemcpyAsync(hit[g].data(), B[g].iters, k[g] * sizeof(int), hipMemcpyDeviceToHost,
+                           s));
+    CSC_HIP(hipMemcpyAsync(hrel[g].data(), B[g].relres, k[g] * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+  }
+  CSC_HIP(hipStreamSynchronize(s));
+  csc_status worst = CSC_OK;
+  for (int g = 0; g < G; ++g) {
+    if (iters_out) std::memcpy(iters_out + off, hit[g].data(), k[g] * sizeof(int));
+    if (relres_out) std::memcpy(relres_out + off, hrel[g].data(), k[g] * sizeof(double));
+    off += k[g];
+    const bool unfinished = hflags[4 * g] > 0 || hflags[4 * g + 1] != 0;
+    status_out[g] = unfinished ? CSC_W_NOT_CONVERGED : CSC_OK;
+    if (unfinished) worst = CSC_W_NOT_CONVERGED;
+  }
+  return worst;
+}

@@ -1,0 +1,392 @@
+// Device-side building blocks shared by the single-graph and the batched
+// kernels: each body processes one work unit, so both launch styles run the
+// same arithmetic.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace csc {
+namespace dev {
+
+constexpr int kBlock = 256;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Sum over the 256 threads of a block in a fixed order; result on thread 0.
+__device__ inline double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  return r;
+}
+
+__device__ inline float gauss_entry(uint64_t e, uint32_t t, uint32_t sid, uint64_t seed, int w) {
+  const Words4 x = philox4x64_10(e, (uint64_t)t, (uint64_t)sid, 0ull, seed, 0ull);
+  const double u1 = (double)((x.x0 >> 11) + 1ull) * 0x1p-53;
+  const double u2 = (double)(x.x1 >> 11) * 0x1p-53;
+  const double z = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+  return (float)(z / sqrt((double)w));
+}
+
+// ------------------------------------------------------- Chebyshev step ---
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ inline v4f fma4(float a, v4f x, v4f acc) {
+  return __builtin_elementwise_fma((v4f)a, x, acc);
+}
+
+__device__ inline v4f ld4(const float* base, size_t o4, int nt) {
+  const v4f* p = reinterpret_cast<const v4f*>(base) + o4;
+  return nt ? __builtin_nontemporal_load(p) : *p;
+}
+
+__device__ inline void st4(float* base, size_t o4, v4f v, int nt) {
+  v4f* p = reinterpret_cast<v4f*>(base) + o4;
+  if (nt)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+__device__ inline double dot4v(v4f a, v4f b) {
+  return (double)a.x * (double)b.x + (double)a.y * (double)b.y + (double)a.z * (double)b.z +
+         (double)a.w * (double)b.w;
+}
+
+// Workgroups are handed to the 8 XCDs round-robin (workgroup b runs on XCD
+// b mod 8).  With xcd mapping on, XCD x processes a contiguous range of the
+// panel-major work units, so each XCD's L2 sees the gathered rows of one
+// panel at a time instead of all panels at once.
+__device__ inline int work_unit(int b, int U, int xcd) {
+  if (!xcd) return b;
+  const int x = b & 7, j = b >> 3, q = U >> 3, r = U & 7;
+  return x * q + (x < r ? x : r) + j;
+}
+
+// Lanes of a wave walk rows of a panel: a row takes lpr = PW/4 lanes (one
+// float4 each), a wave holds rpw = floor(64 / lpr) rows, spare lanes idle.
+struct RowMap {
+  int lpr, rpw, rpb, r, q;
+  bool lane_ok;
+};
+
+__device__ inline RowMap row_map(int pw) {
+  RowMap m;
+  m.lpr = pw >> 2;
+  m.rpw = 64 / m.lpr;
+  m.rpb = 4 * m.rpw;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane / m.lpr;
+  m.q = lane - lr * m.lpr;
+  m.lane_ok = lr < m.rpw;
+  m.r = wave * m.rpw + lr;
+  return m;
+}
+
+// Row i of A times the gathered panel: sum_k val[k] T_m[col[k]], k in CSR order.
+__device__ inline v4f spmm_row(const StepArgs& a, const v4f* __restrict__ Tm4, int i, int q,
+                               int lpr, bool valid) {
+  v4f acc = (v4f)0.f;
+  if (valid) {
+    int k = a.row_ptr[i];
+    const int end = a.row_ptr[i + 1];
+    for (; k + 4 <= end; k += 4) {
+      const int j0 = a.col[k], j1 = a.col[k + 1], j2 = a.col[k + 2], j3 = a.col[k + 3];
+      const float v0 = a.val[k], v1 = a.val[k + 1], v2 = a.val[k + 2], v3 = a.val[k + 3];
+      const v4f t0 = Tm4[(unsigned)j0 * lpr + q];
+      const v4f t1 = Tm4[(unsigned)j1 * lpr + q];
+      const v4f t2 = Tm4[(unsigned)j2 * lpr + q];
+      const v4f t3 = Tm4[(unsigned)j3 * lpr + q];
+      acc = fma4(v0, t0, acc);
+      acc = fma4(v1, t1, acc);
+      acc = fma4(v2, t2, acc);
+      acc = fma4(v3, t3, acc);
+    }
+    for (; k < end; ++k) acc = fma4(a.val[k], Tm4[(unsigned)a.col[k] * lpr + q], acc);
+  }
+  return acc;
+}
+
+// Per-column sums over the rows of a workgroup in a fixed order, written to
+// out[c * stride] for the pw columns c of the panel.  sh holds 4*64*4 doubles.
+__device__ inline void column_partials(const double cs[4], const RowMap& m, int pw, double* sh,
+                                       double* out, size_t stride) {
+  if (m.lane_ok) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sh[m.r * pw + m.q * 4 + e] = cs[e];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < pw) {
+    double t = 0.0;
+    for (int rr = 0; rr < m.rpb; ++rr) t += sh[rr * pw + threadIdx.x];
+    out[(size_t)threadIdx.x * stride] = t;
+  }
+}
+
+// One work unit (panel, row tile) of one Chebyshev step.
+template <int EPI, bool FIRST, bool LAST>
+__device__ inline void cheb_unit(const StepArgs& a, int u) {
+  const RowMap m = row_map(a.L.pw);
+  const int panel = u / a.tiles;
+  const int tile = u - panel * a.tiles;
+  const int n = a.L.n;
+  const int i = tile * m.rpb + m.r;
+  const bool valid = m.lane_ok && i < n;
+  const int nt = a.nt;
+  const size_t pbase4 = (size_t)panel * a.L.panel_elems() / 4;
+  const size_t o4 = pbase4 + (size_t)i * m.lpr + m.q;
+  const v4f* __restrict__ Tm4 = reinterpret_cast<const v4f*>(a.Tm) + pbase4;
+
+  const v4f acc = spmm_row(a, Tm4, i, m.q, m.lpr, valid);
+
+  v4f tn = (v4f)0.f;
+  v4f x0 = (v4f)0.f;  // T_0 row (first step, moments, CG)
+  if (valid) {
+    if (FIRST) {
+      x0 = ld4(a.Tprev, o4, nt);
+      tn = -acc;
+    } else {
+      const v4f tp = ld4(a.Tprev, o4, nt);
+      tn = __builtin_elementwise_fma((v4f)-2.f, acc, -tp);
+    }
+    if (!LAST && EPI != EPI_CG) st4(a.Tnext, o4, tn, nt);
+  }
+
+  if constexpr (EPI == EPI_Y) {
+    if (valid) {
+      v4f y;
+      if (FIRST)
+        y = __builtin_elementwise_fma((v4f)a.c1, tn, (v4f)a.c0 * x0);
+      else
+        y = fma4(a.c1, tn, ld4(a.Y, o4, nt));
+      st4(a.Y, o4, y, nt);
+    }
+  } else if constexpr (EPI == EPI_YS) {
+    if (valid) {
+      const int s = a.slot[i];
+      if (s >= 0) {
+        const float t[4] = {tn.x, tn.y, tn.z, tn.w};
+        const float z[4] = {x0.x, x0.y, x0.z, x0.w};
+        const int c0 = panel * a.L.pw + m.q * 4;
+        float* out = a.Ys + (size_t)s * a.lds;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (c0 + e < a.L.w) {
+            if (FIRST)
+              out[c0 + e] = fmaf(a.c1, t[e], a.c0 * z[e]);
+            else
+              out[c0 + e] = fmaf(a.c1, t[e], out[c0 + e]);
+          }
+        }
+      }
+    }
+  } else if constexpr (EPI == EPI_MOM) {
+    __shared__ double sh[8];
+    double s1 = 0.0, s0 = 0.0;
+    if (valid) {
+      const v4f r0 = FIRST ? x0 : ld4(a.T0, o4, nt);
+      s1 = dot4v(r0, tn);
+      if (FIRST) s0 = dot4v(r0, r0);
+    }
+    const double b1 = block_sum(s1, sh);
+    if (threadIdx.x == 0) a.part[u] = b1;
+    if (FIRST) {
+      __syncthreads();
+      const double b0 = block_sum(s0, sh);
+      if (threadIdx.x == 0) a.part2[u] = b0;
+    }
+    __syncthreads();  // shared memory is reused by the next unit of a grid-stride loop
+  } else if constexpr (EPI == EPI_CG) {
+    __shared__ double sh[4 * 64 * 4];
+    double cs[4] = {0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+      const v4f p0 = FIRST ? x0 : ld4(a.T0, o4, nt);
+      v4f yf;
+      if (FIRST)
+        yf = __builtin_elementwise_fma((v4f)a.c1, tn, (v4f)a.c0 * p0);
+      else
+        yf = fma4(a.c1, tn, ld4(a.Y, o4, nt));
+      const float mk = a.mask[i];
+      const v4f ap = __builtin_elementwise_fma((v4f)mk, p0, (v4f)a.gamma * (p0 - yf));
+      st4(a.Y, o4, ap, nt);
+      cs[0] = (double)p0.x * (double)ap.x;
+      cs[1] = (double)p0.y * (double)ap.y;
+      cs[2] = (double)p0.z * (double)ap.z;
+      cs[3] = (double)p0.w * (double)ap.w;
+    }
+    column_partials(cs, m, a.L.pw, sh, a.part + (size_t)panel * a.L.pw * a.tiles + tile,
+                    (size_t)a.tiles);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ random -----
+__device__ inline void gaussian_elem(const Layout& L, uint64_t seed, uint32_t t, uint32_t sid,
+                                     float* out, size_t idx) {
+  const size_t pe = L.panel_elems();
+  const size_t q = idx / pe, rem = idx - q * pe;
+  const int i = (int)(rem / L.pw), c = (int)(rem - (size_t)i * L.pw);
+  const int cg = (int)q * L.pw + c;
+  out[idx] = cg < L.w ? gauss_entry((uint64_t)i * L.w + cg, t, sid, seed, L.w) : 0.f;
+}
+
+// ---------------------------------------------------------- reductions ---
+// out[0] = sum_t part[t], t < len, by one workgroup in a fixed order.
+__device__ inline void reduce_vec(const double* part, int len, double* out) {
+  __shared__ double sh[8];
+  double s = 0.0;
+  for (int t = threadIdx.x; t < len; t += kBlock) s += part[t];
+  const double b = block_sum(s, sh);
+  if (threadIdx.x == 0) *out = b;
+  __syncthreads();
+}
+
+// Work unit u = (panel, tile): per-column sums of A(i, c) B(i, c) over the tile.
+__device__ inline void col_dot_unit(const Layout& L, int tiles, const float* A, const float* B,
+                                    double* part, int u) {
+  __shared__ double sh[4 * 64 * 4];
+  const RowMap m = row_map(L.pw);
+  const int panel = u / tiles, tile = u - panel * tiles;
+  const int i = tile * m.rpb + m.r;
+  double cs[4] = {0.0, 0.0, 0.0, 0.0};
+  if (m.lane_ok && i < L.n) {
+    const size_t o4 = (size_t)panel * L.panel_elems() / 4 + (size_t)i * m.lpr + m.q;
+    const v4f x = reinterpret_cast<const v4f*>(A)[o4];
+    const v4f y = reinterpret_cast<const v4f*>(B)[o4];
+    cs[0] = (double)x.x * y.x;
+    cs[1] = (double)x.y * y.y;
+    cs[2] = (double)x.z * y.z;
+    cs[3] = (double)x.w * y.w;
+  }
+  column_partials(cs, m, L.pw, sh, part + (size_t)panel * L.pw * tiles + tile, (size_t)tiles);
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ CG ---
+__device__ inline void cg_alpha_block(int k, const double* rr, const double* pAp, int* active,
+                                      double* alpha, int* breakdown) {
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    double al = 0.0;
+    if (active[j]) {
+      if (pAp[j] > 0.0) {
+        al = rr[j] / pAp[j];
+      } else {
+        active[j] = 0;
+        atomicOr(breakdown, 1);
+      }
+    }
+    alpha[j] = al;
+  }
+}
+
+// x += alpha p and r -= alpha A p per column (float64 scalars), then the
+// per-column partial sums of r^T r for work unit u = (panel, tile).
+__device__ inline void cg_update1_unit(const Layout& L, int tiles, const float* AP,
+                                       const float* P, float* X, float* R, const double* alpha,
+                                       double* part, int u) {
+  __shared__ double sh[4 * 64 * 4];
+  const RowMap m = row_map(L.pw);
+  const int panel = u / tiles, tile = u - panel * tiles;
+  const int i = tile * m.rpb + m.r;
+  const int c0 = panel * L.pw + m.q * 4;
+  double cs[4] = {0.0, 0.0, 0.0, 0.0};
+  if (m.lane_ok && i < L.n) {
+    const size_t o4 = (size_t)panel * L.panel_elems() / 4 + (size_t)i * m.lpr + m.q;
+    const v4f ap = reinterpret_cast<const v4f*>(AP)[o4];
+    const v4f p = reinterpret_cast<const v4f*>(P)[o4];
+    v4f x = reinterpret_cast<v4f*>(X)[o4];
+    v4f rr = reinterpret_cast<v4f*>(R)[o4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = c0 + e;
+      const double al = c < L.w ? alpha[c] : 0.0;
+      x[e] = (float)((double)x[e] + al * (double)p[e]);
+      rr[e] = (float)((double)rr[e] - al * (double)ap[e]);
+      cs[e] = (double)rr[e] * (double)rr[e];
+    }
+    reinterpret_cast<v4f*>(X)[o4] = x;
+    reinterpret_cast<v4f*>(R)[o4] = rr;
+  }
+  column_partials(cs, m, L.pw, sh, part + (size_t)panel * L.pw * tiles + tile, (size_t)tiles);
+  __syncthreads();
+}
+
+__device__ inline void cg_scalar_block(int k, const double* rrn, double* rr, const double* bnorm2,
+                                       double* beta, int* active, int* iters, double* relres,
+                                       int it, double tol, int* nactive) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    double b = 0.0;
+    if (active[j]) {
+      const double rel = sqrt(rrn[j]) / sqrt(bnorm2[j]);
+      relres[j] = rel;
+      iters[j] = it;
+      b = rrn[j] / rr[j];
+      rr[j] = rrn[j];
+      if (rel <= tol)
+        active[j] = 0;
+      else
+        ++mine;
+    }
+    beta[j] = b;
+  }
+  atomicAdd(&cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) *nactive = cnt;
+  __syncthreads();
+}
+
+// p = r + beta p for the columns still iterating; t indexes float4 elements.
+__device__ inline void cg_update2_elem(const Layout& L, const float* R, float* P,
+                                       const double* beta, const int* active, size_t t) {
+  const int lpr = L.pw >> 2;
+  const size_t pe4 = L.panel_elems() / 4;
+  const int panel = (int)(t / pe4);
+  const int q = (int)((t - (size_t)panel * pe4) % lpr);
+  const int c0 = panel * L.pw + q * 4;
+  const v4f rv = reinterpret_cast<const v4f*>(R)[t];
+  v4f pv = reinterpret_cast<v4f*>(P)[t];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int c = c0 + e;
+    if (c < L.w && active[c]) pv[e] = (float)((double)rv[e] + beta[c] * (double)pv[e]);
+  }
+  reinterpret_cast<v4f*>(P)[t] = pv;
+}
+
+// labels[i] = argmax_c X(i, c) / ||X_c|| (ties and zero columns -> lowest c);
+// also copies row i to the node-major output when Xout is given.
+__device__ inline void labels_row(const Layout& L, const float* X, const double* colnorm2,
+                                  int* labels, float* Xout, int ldx, int i) {
+  const size_t pe = L.panel_elems();
+  double best = 0.0;
+  int arg = 0;
+  bool found = false;
+  for (int c = 0; c < L.w; ++c) {
+    const float x = X[(size_t)(c / L.pw) * pe + (size_t)i * L.pw + c % L.pw];
+    if (Xout) Xout[(size_t)i * ldx + c] = x;
+    const double n2 = colnorm2[c];
+    if (n2 > 0.0) {
+      const double v = (double)x / sqrt(n2);
+      if (!found || v > best) {
+        best = v;
+        arg = c;
+        found = true;
+      }
+    }
+  }
+  labels[i] = arg;
+}
+
+}  // namespace dev
+}  // namespace csc

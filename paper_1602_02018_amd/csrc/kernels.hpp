@@ -1,6 +1,8 @@
 // Launch wrappers of the libcsc device kernels (kernels.hip).
 #pragma once
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace csc {
@@ -33,7 +35,97 @@ struct StepArgs {
   float gamma = 0.f;
   int xcd = 0;                   // XCD-aware work-unit order
   int nt = 0;                    // non-temporal loads/stores for streamed blocks
+  const int* live = nullptr;     // batched launches: skip the graph when *live == 0
 };
+
+// ------------------------------------------------------- batched launches --
+// A batched launch covers G items (graphs).  Its work list has one entry per
+// workgroup: (item, first local work unit, number of units), so a workgroup
+// reads one entry and one descriptor and then runs up to kChunk consecutive
+// units of that item with the same bodies as the single-graph kernels.
+struct Work {
+  int item, u0, cnt, pad;
+};
+
+struct BTable {
+  const Work* work = nullptr;
+  int n = 0;  // entries (= workgroups)
+};
+
+struct GaussItem {
+  Layout L;
+  uint64_t seed = 0;
+  uint32_t t = 0, sid = 0;
+  float* out = nullptr;
+  const int* live = nullptr;
+};
+
+// one item per graph; its units are its nvec vectors
+struct ReduceItem {
+  const double* part = nullptr;
+  int len = 0;
+  double* out = nullptr;
+  const int* live = nullptr;
+};
+
+struct ColDotItem {
+  Layout L;
+  int tiles = 0;
+  const float* A = nullptr;
+  const float* B = nullptr;
+  double* part = nullptr;
+  const int* live = nullptr;
+};
+
+struct CgItem {
+  Layout L;
+  int tiles = 0;
+  int k = 0;
+  const float* AP = nullptr;
+  float* P = nullptr;
+  float* X = nullptr;
+  float* R = nullptr;
+  double* rr = nullptr;
+  double* rrn = nullptr;
+  double* pAp = nullptr;
+  double* alpha = nullptr;
+  double* beta = nullptr;
+  const double* bnorm2 = nullptr;
+  int* active = nullptr;
+  int* iters = nullptr;
+  double* relres = nullptr;
+  double* part = nullptr;        // per-column partials (columns x tiles)
+  int* nactive = nullptr;
+  int* breakdown = nullptr;
+  int* it = nullptr;             // iterations done by this graph
+  double tol = 0.0;
+  int max_iter = 0;
+  int* live = nullptr;           // cleared once no column iterates
+};
+
+struct LabelItem {
+  Layout L;
+  const float* X = nullptr;
+  const double* colnorm2 = nullptr;
+  int* labels = nullptr;
+  float* Xout = nullptr;
+  int ldx = 0;
+};
+
+hipError_t launch_cheb_step_batched(const StepArgs* items, BTable t, int epi, bool first,
+                                    bool last, hipStream_t s);
+hipError_t launch_gaussian_batched(const GaussItem* items, BTable t, hipStream_t s);
+hipError_t launch_reduce_batched(const ReduceItem* items, BTable t, hipStream_t s);
+hipError_t launch_col_dot_batched(const ColDotItem* items, BTable t, hipStream_t s);
+hipError_t launch_cg_alpha_batched(const CgItem* items, int G, hipStream_t s);
+hipError_t launch_cg_update1_batched(const CgItem* items, BTable t, hipStream_t s);
+hipError_t launch_cg_scalar_batched(const CgItem* items, int G, hipStream_t s);
+hipError_t launch_cg_update2_batched(const CgItem* items, BTable t, hipStream_t s);
+hipError_t launch_labels_batched(const LabelItem* items, BTable t, hipStream_t s);
+constexpr int kElemsPerUnit = 1024;  // gaussian / update2 / labels: elements per work unit
+
+// Work list for per-item unit counts, chunks of up to `chunk` units.
+void build_work(const int* units, int G, int chunk, std::vector<Work>& out);
 
 // Process-wide kernel tuning (csc_set_tuning).
 struct Tuning {

@@ -169,6 +169,35 @@ csc_status kmeans_f64(const double* X, int n, int d, int k, int replicates, int 
   return CSC_OK;
 }
 
+csc_status kmeans_batched(int G, const std::vector<std::vector<double>>& X, const int32_t* n,
+                          const int32_t* d, const int32_t* k, int replicates, int max_iter,
+                          const uint64_t* seeds, int32_t* const* labels, double* inertia_out) {
+  std::vector<std::vector<Run>> runs(G, std::vector<Run>(replicates));
+  const int total = G * replicates;
+  auto work = [&](int job) {
+    const int g = job / replicates, r = job - g * replicates;
+    std::vector<double> C((size_t)k[g] * d[g]);
+    seed_plusplus(X[g].data(), n[g], d[g], k[g], seeds[g], r, C.data());
+    runs[g][r] = lloyd(X[g].data(), n[g], d[g], k[g], C, max_iter);
+  };
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int nt = std::min<int>((int)hw, total);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&, t] {
+      for (int job = t; job < total; job += nt) work(job);
+    });
+  for (auto& th : pool) th.join();
+  for (int g = 0; g < G; ++g) {
+    int best = 0;
+    for (int r = 1; r < replicates; ++r)
+      if (runs[g][r].inertia < runs[g][best].inertia) best = r;
+    std::memcpy(labels[g], runs[g][best].labels.data(), (size_t)n[g] * sizeof(int32_t));
+    if (inertia_out) inertia_out[g] = runs[g][best].inertia;
+  }
+  return CSC_OK;
+}
+
 csc_status check_kmeans_args(const void* F, int n, int d, int ld, int k, int replicates,
                              int max_iter, const int32_t* labels) {
   CSC_REQUIRE(F && labels, "F and labels must be non-NULL");
@@ -204,4 +233,20 @@ extern "C" csc_status csc_kmeans_reduced_f64(const double* F, int32_t n, int32_t
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < d; ++j) X[(size_t)i * d + j] = F[(size_t)i * ld + j];
   return kmeans_f64(X.data(), n, d, k, replicates, max_iter, seed, labels, inertia_out);
+}
+
+extern "C" csc_status csc_kmeans_reduced_batched(int32_t G, const float* const* F, const int32_t* n,
+                                                 const int32_t* d, const int32_t* k,
+                                                 int32_t replicates, int32_t max_iter,
+                                                 const uint64_t* seeds, int32_t* const* labels,
+                                                 double* inertia_out) {
+  clear_error();
+  CSC_REQUIRE(G >= 1 && F && n && d && k && seeds && labels, "bad batched k-means arguments");
+  std::vector<std::vector<double>> X(G);
+  for (int g = 0; g < G; ++g) {
+    CSC_TRY(check_kmeans_args(F[g], n[g], d[g], d[g], k[g], replicates, max_iter, labels[g]));
+    X[g].resize((size_t)n[g] * d[g]);
+    for (size_t e = 0; e < X[g].size(); ++e) X[g][e] = (double)F[g][e];
+  }
+  return kmeans_batched(G, X, n, d, k, replicates, max_iter, seeds, labels, inertia_out);
 }
