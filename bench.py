@@ -42,6 +42,8 @@ WORKLOADS = {
     "chunglu-1e6": dict(N=1000000, k=250, p=60, model="chunglu"),
     # SBM N = 1000, k = 10 (oracle-sized)
     "sbm-1e3": dict(N=1000, k=10, s=16.0, p=50, model="sbm"),
+    # 64 SBMs, N ~ U[2e3, 2e5], k ~ U[10, 100], s ~ U[8, 32], eps = eps_c / 4
+    "batch64": dict(G=64, p=50, model="sbm_batch"),
 }
 
 
@@ -164,6 +166,8 @@ def main():
 
     wl = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
+    if args.workload == "batch64":
+        return bench_batch(args, wl, dev)
     gr = make_graph(wl, args.seed)
     N, nnz, k, p = gr.n, gr.nnz, wl["k"], wl["p"]
     d = int(math.ceil(4 * math.log(N)))
@@ -188,6 +192,18 @@ def main():
     value = total / elapsed / 1e9
     last = results[-1]
     ari = adjusted_rand_index(last.labels.cpu().numpy(), gr.truth)
+
+    # the same graph with the learned lambda_k bracket
+    from paper_1602_02018_amd import learned
+
+    mlp = learned.load_params(dev)
+    api.run(g, k, d, args.seed, p=p, mlp_params=mlp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lres = [api.run(g, k, d, args.seed, p=p, mlp_params=mlp) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    ms_learned = (time.perf_counter() - t0) / args.steps * 1e3
+    ari_lp = adjusted_rand_index(lres[-1].labels.cpu().numpy(), last.labels.cpu().numpy())
 
     # dominant kernel: Chebyshev step of the CG operator (width k), per-launch time
     st = api.StepTimer(g, k, 0)
@@ -230,6 +246,14 @@ def main():
         "lambda_k": last.lam,
         "cg_iters_max": int(last.interp.iters.max()),
         "ari_vs_truth": round(float(ari), 4),
+        "learned": {
+            "s_per_graph": round(ms_learned / 1e3, 4),
+            "bisection_steps": lres[-1].bisection.steps,
+            "lambda_k": lres[-1].lam,
+            "ari_vs_plain": round(float(ari_lp), 4),
+            "ari_vs_truth": round(float(adjusted_rand_index(lres[-1].labels.cpu().numpy(),
+                                                            gr.truth)), 4),
+        },
         "roofline": {
             "kernel": f"k_cheb_step<EPI_Y> (CG operator pass, w={k}, "
                       f"panel width {api.panel_width(N, k, nnz)})",
@@ -245,6 +269,76 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(gr, k, p)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, wl, dev):
+    """64 SBMs: plain form graph by graph vs batched vs batched + learned bracket."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle.metrics import adjusted_rand_index
+    from paper_1602_02018_amd import api, learned
+
+    gs = synth.sbm_batch(wl["G"], seed=args.seed)
+    p = wl["p"]
+    G = [api.Graph(g.row_ptr, g.col, dev) for g in gs]
+    ks = [g.k for g in gs]
+    ds = [int(math.ceil(4 * math.log(g.n))) for g in gs]
+    seeds = [args.seed + i for i in range(len(gs))]
+    mlp = learned.load_params(dev)
+    api.run_batched(G[:4], ks[:4], ds[:4], seeds[:4], p=p, mlp_params=mlp)  # warm-up
+    api.run(G[0], ks[0], ds[0], seeds[0], p=p)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    plain, t_plain = timed(lambda: [api.run(g, k, d, s, p=p) for g, k, d, s in zip(G, ks, ds, seeds)])
+    batched, t_batched = timed(lambda: api.run_batched(G, ks, ds, seeds, p=p))
+    both, t_both = timed(lambda: api.run_batched(G, ks, ds, seeds, p=p, mlp_params=mlp))
+
+    def ari_truth(res):
+        return [adjusted_rand_index(r.labels.cpu().numpy(), g.truth) for r, g in zip(res, gs)]
+
+    a_plain, a_both = ari_truth(plain), ari_truth(both)
+    a_pair = [adjusted_rand_index(x.labels.cpu().numpy(), y.labels.cpu().numpy())
+              for x, y in zip(both, plain)]
+    total = sum(job_bytes(g.n, g.nnz, k, d, api.count_signals(g.n), p, r.bisection.steps,
+                          int(r.interp.iters.max())) for g, k, d, r in zip(gs, ks, ds, both))
+    out = {
+        "metric": "filter SpMM HBM GB/s (% peak) + end-to-end CSC s/graph vs plain at ARI>=0.99",
+        "value": round(total / t_both / 1e9, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": round(t_both * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch64: {len(gs)} SBMs, sum N={sum(g.n for g in gs)}, "
+                               f"sum nnz={sum(g.nnz for g in gs)}, k in [10,100], p={p}",
+                   "form": "batched + learned"},
+        "s_per_graph": {"plain": round(t_plain / len(gs), 4), "batched": round(t_batched / len(gs), 4),
+                        "batched_learned": round(t_both / len(gs), 4)},
+        "speedup_vs_plain": round(t_plain / t_both, 3),
+        "bisection_passes": {"plain": int(sum(r.bisection.steps for r in plain)),
+                             "batched_learned": int(sum(r.bisection.steps for r in both))},
+        "ari_vs_truth_mean": {"plain": round(float(np.mean(a_plain)), 4),
+                              "batched_learned": round(float(np.mean(a_both)), 4)},
+        "ari_batched_learned_vs_plain": {"median": round(float(np.median(a_pair)), 4),
+                                         "frac_ge_0.99": round(float(np.mean(np.array(a_pair) >= 0.99)), 4)},
+        "batched_identical_to_plain": int(sum(torch.equal(x.labels, y.labels)
+                                              for x, y in zip(batched, plain))),
+    }
     print(json.dumps(out), flush=True)
 
 

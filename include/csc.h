@@ -267,9 +267,11 @@ csc_status csc_interpolate(const csc_graph* g, double lambda_k, int32_t p, doubl
  * Per-graph statuses are written to status_out[g].
  *
  * csc_estimate_lambda_k_batched: csc_estimate_lambda_k for every graph
- * (k[g], n_signals[g], seeds[g], brackets[2g..2g+1] or NULL for [0, 2]);
- * each dichotomy round runs one batched eigencount pass for the graphs still
- * searching.  lambda_out, steps_out, status_out: host[G]; trace_out:
+ * (k[g], n_signals[g], seeds[g], brackets[2g..2g+1] or NULL for [0, 2]), or
+ * csc_estimate_lambda_k_learned when mlp_params (device) is given instead of
+ * brackets; each dichotomy round runs one batched eigencount pass for the
+ * graphs still searching (and one batched network evaluation after the
+ * first).  lambda_out, steps_out, status_out: host[G]; trace_out:
  * host[G][2*max_steps][2] or NULL; moments_out: host[G][p+1] or NULL.
  * Synchronises.
  */
@@ -278,7 +280,8 @@ size_t csc_estimate_workspace_bytes_batched(const csc_graph* graphs, int32_t G,
 csc_status csc_estimate_lambda_k_batched(const csc_graph* graphs, int32_t G, const int32_t* k,
                                          int32_t p, const int32_t* n_signals,
                                          const uint64_t* seeds, int32_t max_steps,
-                                         const double* brackets, double* lambda_out,
+                                         const double* brackets, const float* mlp_params,
+                                         double* lambda_out,
                                          int32_t* steps_out, double* trace_out,
                                          double* moments_out, int32_t* status_out, void* ws,
                                          size_t ws_bytes, void* stream);
@@ -319,6 +322,68 @@ csc_status csc_kmeans_reduced_batched(int32_t G, const float* const* F, const in
                                       const int32_t* d, const int32_t* k, int32_t replicates,
                                       int32_t max_iter, const uint64_t* seeds,
                                       int32_t* const* labels, double* inertia_out);
+
+/* ------------------------------------------------------------------------
+ * Learned lambda_k bracket.  The paper notes that a better estimate of
+ * lambda_k would help the method (Sec. 5.2); this network proposes a bracket
+ * for the dichotomy of Sec. 4.3 from the first eigencount pass.
+ * A 52 -> 128 -> 128 -> 2 perceptron with GELU activations, float32, trained
+ * and run on the GPU.  Parameters: one flat device array of
+ * csc_mlp_param_count() = 23554 floats, W1 (52 x 128, row = input), b1 (128),
+ * W2 (128 x 128), b2 (128), W3 (128 x 2), b3 (2).
+ *
+ * csc_mlp_features: the 52 inputs (host float[52]) from the moments
+ *   mu_0..mu_p (host, p >= 50) of one eigencount pass: g_m mu_m / mu_0 for
+ *   m = 1..50 (g_m the Jackson factors of order 50), ln N / 10 and k / N.
+ * csc_mlp_forward: Y (device B x 2) for inputs X (device B x 52).
+ * csc_count_root: lambda_0, the root of the count curve
+ *   c(lambda) = sum_m a_m(lambda) mu_m of one eigencount pass (host moments
+ *   mu_0..mu_p; 50 halvings of [0, 2]), and s = sqrt(2k / n_signals) /
+ *   c'(lambda_0) clipped to [1e-4, 0.5]: the spread of lambda implied by the
+ *   count's standard deviation.  The network's two outputs y are offsets in
+ *   units of s: the bracket is [lambda_0 + s min(y), lambda_0 + s max(y)].
+ * csc_mlp_loss_grad: mean pinball loss of output 0 at tau = 0.02 and output 1
+ *   at tau = 0.98 against target (device float[B]) and its gradient with
+ *   respect to the parameters (device float[23554]); loss_out: host or NULL
+ *   (synchronises when given).  Every sum runs in a fixed order.
+ * csc_mlp_adam_step: Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected,
+ *   step counted from 1) on params with moment buffers m, v (device, zeroed
+ *   before the first step).
+ * Workspace for forward / loss_grad: csc_mlp_workspace_bytes(B).
+ */
+int32_t csc_mlp_param_count(void);
+size_t csc_mlp_workspace_bytes(int32_t B);
+csc_status csc_mlp_features(const double* moments, int32_t p, int32_t N, int32_t k, float* x_out);
+csc_status csc_count_root(const double* moments, int32_t p, int32_t k, int32_t n_signals,
+                          double* lambda0_out, double* scale_out);
+csc_status csc_mlp_forward(const float* params, const float* X, int32_t B, float* Y, void* ws,
+                           size_t ws_bytes, void* stream);
+csc_status csc_mlp_loss_grad(const float* params, const float* X, const float* target, int32_t B,
+                             float* grad, double* loss_out, void* ws, size_t ws_bytes,
+                             void* stream);
+csc_status csc_mlp_adam_step(float* params, const float* grad, float* m, float* v, int32_t step,
+                             float lr, void* stream);
+
+/* csc_estimate_lambda_k_learned: the dichotomy of csc_estimate_lambda_k
+ * started from a learned bracket.  Its first pass is the plain dichotomy's
+ * first test (lambda = 1, sub-stream 1); if that does not stop the search,
+ * the network maps that pass's moments to offsets around the pass's own count
+ * root (csc_count_root), giving [lo, hi], intersected with the half of [0, 2]
+ * the first count selects.  The dichotomy then runs inside with fresh
+ * signals (sub-streams 2, 3, ...), stopping as the plain one does; if every
+ * count falls on one side of k until the interval is an eighth of the
+ * bracket, the interval reopens once towards the rest of the half
+ * (CSC_W_BRACKET_MISS).  steps_out counts every pass (max_steps in total).
+ * params: device.  trace_out: host[2*max_steps] or NULL; bracket_out: host[2]
+ * or NULL.  p >= 50.  ws: csc_estimate_workspace_bytes_learned.  Synchronises.
+ */
+size_t csc_estimate_workspace_bytes_learned(int32_t n, int32_t n_signals, int32_t p);
+csc_status csc_estimate_lambda_k_learned(const csc_graph* g, int32_t k, int32_t p,
+                                         int32_t n_signals, uint64_t seed, int32_t max_steps,
+                                         const float* params, double* lambda_out,
+                                         int32_t* steps_out, double* trace_out,
+                                         double* bracket_out, void* ws, size_t ws_bytes,
+                                         void* stream);
 
 /* ------------------------------------------------------------------------
  * Measurement hook (not a step of Alg. 2).  Launches exactly `steps`

@@ -12,9 +12,16 @@ Inputs (``features``): the Jackson-damped Chebyshev moments
 g_m mu_m / mu_0, m = 1..50, of the first eigencount pass (mu_m = <R, T_m R>,
 the kernel polynomial estimate of the spectral density), ln N / 10 and k / N.
 
-Loss: quantile (pinball) loss of output 0 at tau = 0.05 and of output 1 at
-tau = 0.95 against the lambda_k found by the plain dichotomy, averaged over
-the batch: rho_tau(u) = u (tau - 1[u < 0]), u = target - output.
+Outputs are offsets in a scale-free unit around the root of the first pass's
+own count curve: with c(lambda) = sum_m a_m(lambda) mu_m (the count those
+signals give at any lambda), lambda_0 solves c(lambda_0) = k and
+s = sqrt(2k / n_c) / c'(lambda_0) is the spread of lambda implied by the
+count's standard deviation; the bracket is [lambda_0 + s y_lo, lambda_0 + s y_hi].
+
+Loss: quantile (pinball) loss of output 0 at tau = 0.02 and of output 1 at
+tau = 0.98 against (lambda_k - lambda_0) / s, lambda_k from the plain
+dichotomy, averaged over the batch: rho_tau(u) = u (tau - 1[u < 0]),
+u = target - output.
 
 Optimiser: Adam (Kingma & Ba) with bias correction.
 """
@@ -26,7 +33,7 @@ import numpy as np
 from scipy.special import erf
 
 D_IN, H, D_OUT = 52, 128, 2
-TAUS = (0.05, 0.95)
+TAUS = (0.02, 0.98)
 SHAPES = [(D_IN, H), (H,), (H, H), (H,), (H, D_OUT), (D_OUT,)]
 N_PARAMS = sum(int(np.prod(s)) for s in SHAPES)  # 23554
 
@@ -113,8 +120,31 @@ def features(moments, N, k, p=50):
     return x
 
 
-def bracket(theta, x):
-    """[lo, hi] from the two outputs, ordered and clipped to [0, 2]."""
+def count_root(moments, p, k, n_c):
+    """(lambda_0, s): root of the first pass's count curve and the lambda spread."""
+    from .jackson import lowpass_coeffs
+
+    mu = np.asarray(moments, dtype=np.float64)
+
+    def c(lam):
+        return float(np.dot(lowpass_coeffs(lam, p), mu))
+
+    lo, hi = 0.0, 2.0
+    for _ in range(50):
+        mid = 0.5 * (lo + hi)
+        if c(mid) < k:
+            lo = mid
+        else:
+            hi = mid
+    lam0 = 0.5 * (lo + hi)
+    h = 1e-3
+    slope = (c(min(2.0, lam0 + h)) - c(max(0.0, lam0 - h))) / (min(2.0, lam0 + h) - max(0.0, lam0 - h))
+    s = math.sqrt(2.0 * k / n_c) / max(slope, 1e-9)
+    return lam0, min(max(s, 1e-4), 0.5)
+
+
+def bracket(theta, x, lam0, s):
+    """[lo, hi] = lambda_0 + s * sorted outputs, clipped to [0, 2]."""
     y, _ = forward(theta, np.asarray(x, dtype=np.float64).reshape(1, -1))
-    lo, hi = sorted((float(y[0, 0]), float(y[0, 1])))
-    return max(0.0, min(2.0, lo)), max(0.0, min(2.0, hi))
+    a, b = sorted((float(y[0, 0]), float(y[0, 1])))
+    return max(0.0, min(2.0, lam0 + s * a)), max(0.0, min(2.0, lam0 + s * b))

@@ -67,14 +67,24 @@ PROTOTYPES = {
     "csc_interpolate": (i32, [pg, f64, i32, f64, vp, vp, i32, i32, f64, i32, vp, i32, vp, pi, pd,
                               vp, sz, vp]),
     "csc_estimate_workspace_bytes_batched": (sz, [pg, i32, pi, i32]),
-    "csc_estimate_lambda_k_batched": (i32, [pg, i32, pi, i32, pi, pu, i32, pd, pd, pi, pd, pd, pi,
-                                            vp, sz, vp]),
+    "csc_estimate_lambda_k_batched": (i32, [pg, i32, pi, i32, pi, pu, i32, pd, vp, pd, pi, pd, pd,
+                                            pi, vp, sz, vp]),
     "csc_filter_workspace_bytes_batched": (sz, [pg, i32, pi, i32]),
     "csc_filter_batched": (i32, [pg, i32, pd, i32, pi, pu, vp, pi, i32, vp, pi, vp, sz, vp]),
     "csc_interpolate_workspace_bytes_batched": (sz, [pg, i32, pi, i32]),
     "csc_interpolate_batched": (i32, [pg, i32, pd, i32, f64, vp, vp, pi, pi, f64, i32, vp, pi, vp,
                                       pi, pd, pi, vp, sz, vp]),
     "csc_kmeans_reduced_batched": (i32, [i32, vp, pi, pi, pi, i32, i32, pu, vp, pd]),
+    "csc_mlp_param_count": (i32, []),
+    "csc_mlp_workspace_bytes": (sz, [i32]),
+    "csc_mlp_features": (i32, [pd, i32, i32, i32, C.POINTER(C.c_float)]),
+    "csc_count_root": (i32, [pd, i32, i32, i32, pd, pd]),
+    "csc_mlp_forward": (i32, [vp, vp, i32, vp, vp, sz, vp]),
+    "csc_mlp_loss_grad": (i32, [vp, vp, vp, i32, vp, pd, vp, sz, vp]),
+    "csc_mlp_adam_step": (i32, [vp, vp, vp, vp, i32, C.c_float, vp]),
+    "csc_estimate_workspace_bytes_learned": (sz, [i32, i32, i32]),
+    "csc_estimate_lambda_k_learned": (i32, [pg, i32, i32, i32, u64, i32, vp, pd, pi, pd, pd, vp,
+                                            sz, vp]),
     "csc_cheb_steps_workspace_bytes": (sz, [i32, i32]),
     "csc_cheb_steps": (i32, [pg, i32, i32, i32, i32, vp, sz, vp]),
 }

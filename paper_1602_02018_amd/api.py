@@ -251,13 +251,20 @@ class Result:
 def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
         gamma: float = 1e-3, n_c: int | None = None, tol: float = 1e-6, max_iter: int = 1000,
         max_steps: int = 30, replicates: int = 20, kmeans_iter: int = 100, lam: float | None = None,
-        bracket=None, want_X: bool = False) -> Result:
-    """Compressive spectral clustering (Alg. 2) with every graph-sized step on the GPU."""
+        bracket=None, want_X: bool = False, mlp_params: torch.Tensor | None = None) -> Result:
+    """Compressive spectral clustering (Alg. 2) with every graph-sized step on the GPU.
+
+    With ``mlp_params`` the dichotomy starts from the learned bracket.
+    """
     n = default_n(k) if n is None else n
     n_c = count_signals(g.n) if n_c is None else n_c
     tm = {}
     t0 = time.perf_counter()
-    if lam is None:
+    if lam is None and mlp_params is not None:
+        lb = estimate_lambda_k_learned(g, k, p, n_c, seed, mlp_params, max_steps)
+        bis = Bisection(lb.lam, lb.steps, lb.trace, np.zeros(p + 1), lb.status)
+        lam = lb.lam
+    elif lam is None:
         bis = estimate_lambda_k(g, k, p, n_c, seed, max_steps, bracket)
         lam = bis.lam
     else:
@@ -293,7 +300,8 @@ def _graphs(graphs):
     return (CscGraph * len(graphs))(*[g.c for g in graphs])
 
 
-def estimate_lambda_k_batched(graphs, ks, p, n_signals, seeds, max_steps=30, brackets=None):
+def estimate_lambda_k_batched(graphs, ks, p, n_signals, seeds, max_steps=30, brackets=None,
+                              mlp_params=None):
     G = len(graphs)
     ga = _graphs(graphs)
     ks, ns = _i32(ks), _i32(n_signals)
@@ -311,7 +319,7 @@ def estimate_lambda_k_batched(graphs, ks, p, n_signals, seeds, max_steps=30, bra
     ws = _ws(lib().csc_estimate_workspace_bytes_batched(ga, G, ns.ctypes.data_as(_lib.pi), p), dev)
     check(lib().csc_estimate_lambda_k_batched(
         ga, G, ks.ctypes.data_as(_lib.pi), p, ns.ctypes.data_as(_lib.pi), sd.ctypes.data_as(_lib.pu),
-        max_steps, br, lam.ctypes.data_as(_lib.pd), steps.ctypes.data_as(_lib.pi),
+        max_steps, br, _ptr(mlp_params), lam.ctypes.data_as(_lib.pd), steps.ctypes.data_as(_lib.pi),
         trace.ctypes.data_as(_lib.pd), mom.ctypes.data_as(_lib.pd), status.ctypes.data_as(_lib.pi),
         _ptr(ws), ws.numel(), _stream()), "csc_estimate_lambda_k_batched")
     return [Bisection(float(lam[g]), int(steps[g]),
@@ -391,7 +399,7 @@ def kmeans_reduced_batched(Fs, ks, seeds, replicates=20, max_iter=100):
 
 def run_batched(graphs, ks, ds, seeds, p=50, ns=None, gamma=1e-3, n_cs=None, tol=1e-6,
                 max_iter=1000, max_steps=30, replicates=20, kmeans_iter=100, brackets=None,
-                lams=None, want_X=False):
+                lams=None, want_X=False, mlp_params=None):
     """Alg. 2 for G graphs at once with the batched calls; graph g matches run(graphs[g], ...)."""
     G = len(graphs)
     ns = [default_n(k) for k in ks] if ns is None else list(ns)
@@ -399,7 +407,7 @@ def run_batched(graphs, ks, ds, seeds, p=50, ns=None, gamma=1e-3, n_cs=None, tol
     tm = {}
     t0 = time.perf_counter()
     if lams is None:
-        bis = estimate_lambda_k_batched(graphs, ks, p, n_cs, seeds, max_steps, brackets)
+        bis = estimate_lambda_k_batched(graphs, ks, p, n_cs, seeds, max_steps, brackets, mlp_params)
         lams = [b.lam for b in bis]
     else:
         bis = [Bisection(l, 0, [], np.zeros(p + 1), 0) for l in lams]
@@ -417,3 +425,77 @@ def run_batched(graphs, ks, ds, seeds, p=50, ns=None, gamma=1e-3, n_cs=None, tol
               total_s=t4 - t0)
     return [Result(lams[g], bis[g], omegas[g], Fs[g], labels_r[g], float(inertia[g]), its[g], dict(tm))
             for g in range(G)]
+
+
+# ------------------------------------------------ learned lambda_k bracket ---
+
+def mlp_param_count() -> int:
+    return int(lib().csc_mlp_param_count())
+
+
+def mlp_features(moments, N: int, k: int) -> np.ndarray:
+    mom = np.ascontiguousarray(moments, dtype=np.float64)
+    x = np.zeros(52, dtype=np.float32)
+    check(lib().csc_mlp_features(mom.ctypes.data_as(_lib.pd), len(mom) - 1, int(N), int(k),
+                                 x.ctypes.data_as(C.POINTER(C.c_float))), "csc_mlp_features")
+    return x
+
+
+def count_root(moments, k: int, n_signals: int):
+    mom = np.ascontiguousarray(moments, dtype=np.float64)
+    l0, sc = C.c_double(0.0), C.c_double(0.0)
+    check(lib().csc_count_root(mom.ctypes.data_as(_lib.pd), len(mom) - 1, int(k), int(n_signals),
+                               C.byref(l0), C.byref(sc)), "csc_count_root")
+    return l0.value, sc.value
+
+
+def mlp_forward(params: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+    X = X.contiguous()
+    B = X.shape[0]
+    Y = torch.empty((B, 2), dtype=torch.float32, device=X.device)
+    ws = _ws(lib().csc_mlp_workspace_bytes(B), X.device)
+    check(lib().csc_mlp_forward(_ptr(params), _ptr(X), B, _ptr(Y), _ptr(ws), ws.numel(), _stream()),
+          "csc_mlp_forward")
+    return Y
+
+
+def mlp_loss_grad(params: torch.Tensor, X: torch.Tensor, target: torch.Tensor, ws=None):
+    X = X.contiguous()
+    B = X.shape[0]
+    grad = torch.empty_like(params)
+    loss = C.c_double(0.0)
+    if ws is None:
+        ws = _ws(lib().csc_mlp_workspace_bytes(B), X.device)
+    check(lib().csc_mlp_loss_grad(_ptr(params), _ptr(X), _ptr(target.contiguous()), B, _ptr(grad),
+                                  C.byref(loss), _ptr(ws), ws.numel(), _stream()), "csc_mlp_loss_grad")
+    return loss.value, grad
+
+
+def mlp_adam_step(params, grad, m, v, step: int, lr: float) -> None:
+    check(lib().csc_mlp_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr),
+                                  _stream()), "csc_mlp_adam_step")
+
+
+@dataclass
+class LearnedBisection:
+    lam: float
+    steps: int
+    trace: list
+    bracket: tuple
+    status: int
+
+
+def estimate_lambda_k_learned(g: Graph, k: int, p: int, n_signals: int, seed: int,
+                              params: torch.Tensor, max_steps: int = 30) -> LearnedBisection:
+    lam = C.c_double(0.0)
+    steps = C.c_int32(0)
+    trace = np.zeros(2 * max_steps)
+    br = np.zeros(2)
+    ws = _ws(lib().csc_estimate_workspace_bytes_learned(g.n, n_signals, p), g.device)
+    st = check(lib().csc_estimate_lambda_k_learned(g.ref, k, p, n_signals, seed, max_steps, _ptr(params),
+                                                   C.byref(lam), C.byref(steps),
+                                                   trace.ctypes.data_as(_lib.pd),
+                                                   br.ctypes.data_as(_lib.pd), _ptr(ws), ws.numel(),
+                                                   _stream()), "csc_estimate_lambda_k_learned")
+    tr = [(trace[2 * i], trace[2 * i + 1]) for i in range(steps.value)]
+    return LearnedBisection(lam.value, steps.value, tr, (br[0], br[1]), st)

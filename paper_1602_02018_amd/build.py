@@ -21,6 +21,7 @@ SOURCES = {
     "api.hip": [],
     "batched.hip": [],
     "api_batched.hip": [],
+    "mlp.hip": [],
     "kmeans.hip": ["-ffp-contract=off"],
 }
 

@@ -144,6 +144,7 @@ extern "C" size_t csc_estimate_workspace_bytes_batched(const csc_graph* graphs, 
                                                        const int32_t* n_signals, int32_t p) {
   if (!graphs || G < 1 || !n_signals || p < 1) return 0;
   size_t b = desc_bytes(G, p) + align_up((size_t)G * (p + 1) * sizeof(double));
+  b += mlp_workspace(G) + align_up((size_t)G * 54 * sizeof(float)) + 1024;  // learned mode
   std::vector<int> u(G), gu(G), rv(G, p + 1);
   for (int g = 0; g < G; ++g) {
     b += max_widths(graphs[g].n, n_signals[g], [p](const Layout& L) { return count_bytes(L, p); });
@@ -155,11 +156,14 @@ extern "C" size_t csc_estimate_workspace_bytes_batched(const csc_graph* graphs, 
 
 extern "C" csc_status csc_estimate_lambda_k_batched(
     const csc_graph* graphs, int32_t G, const int32_t* k, int32_t p, const int32_t* n_signals,
-    const uint64_t* seeds, int32_t max_steps, const double* brackets, double* lambda_out,
-    int32_t* steps_out, double* trace_out, double* moments_out, int32_t* status_out, void* ws,
-    size_t ws_bytes, void* stream) {
+    const uint64_t* seeds, int32_t max_steps, const double* brackets, const float* mlp_params,
+    double* lambda_out, int32_t* steps_out, double* trace_out, double* moments_out,
+    int32_t* status_out, void* ws, size_t ws_bytes, void* stream) {
   clear_error();
   CSC_TRY(check_graphs(graphs, G));
+  CSC_REQUIRE(!(brackets && mlp_params), "give either brackets or mlp_params, not both");
+  CSC_REQUIRE(!mlp_params || (p >= 50 && max_steps >= 2),
+              "the learned bracket needs p >= 50 and max_steps >= 2");
   CSC_REQUIRE(k && n_signals && seeds && lambda_out && steps_out && status_out,
               "k, n_signals, seeds, lambda_out, steps_out and status_out must be non-NULL");
   CSC_REQUIRE(p >= 1 && max_steps >= 1, "need p >= 1 and max_steps >= 1");
@@ -200,6 +204,9 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
   plan_work(ar, units, chunk_for(units), w_step);
   plan_work(ar, gunits, chunk_for(gunits), w_gauss);
   plan_work(ar, rvec, 1, w_red);
+  float* d_x = ar.take<float>((size_t)G * 52);
+  float* d_y = ar.take<float>((size_t)G * 2);
+  char* d_mws = ar.take<char>(mlp_workspace(G));
   if (!ar.ok()) {
     set_error("internal: batched workspace plan overflow");
     return CSC_E_INVALID_ARG;
@@ -257,6 +264,7 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
     double lo = 0.0, hi = 2.0;
     int used = 0, t_in = 0, attempt = 0;
     bool below = false, above = false, missed = false, done = false;
+    LearnedState ls;  // learned mode, after the first pass
   };
   std::vector<State> st(G);
   for (int g = 0; g < G; ++g)
@@ -265,9 +273,11 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
       st[g].hi = brackets[2 * g + 1];
     }
   std::vector<int> live(G);
-  std::vector<double> hmom((size_t)G * (p + 1)), a(p + 1);
+  std::vector<double> hmom((size_t)G * (p + 1));
+  std::vector<float> hx((size_t)G * 52, 0.f), hy((size_t)G * 2, 0.f);
   Captured cap;
-  for (int round = 0; round < 2 * max_steps; ++round) {
+  const int rounds = mlp_params ? max_steps : 2 * max_steps;
+  for (int round = 0; round < rounds; ++round) {
     int nlive = 0;
     for (int g = 0; g < G; ++g) {
       live[g] = st[g].done ? 0 : 1;
@@ -281,11 +291,12 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
     CSC_HIP(hipMemcpyAsync(hmom.data(), mom, hmom.size() * sizeof(double), hipMemcpyDeviceToHost,
                            s));
     CSC_HIP(hipStreamSynchronize(s));
+    bool need_mlp = false;
     for (int g = 0; g < G; ++g) {
       if (!live[g]) continue;
       State& S = st[g];
       const double* mg = hmom.data() + (size_t)g * (p + 1);
-      const double mid = 0.5 * (S.lo + S.hi);
+      const double mid = (mlp_params && S.used > 0) ? 0.5 * (S.ls.lo + S.ls.hi) : 0.5 * (S.lo + S.hi);
       const double cnt = count_from_moments(mid, p, mg);
       if (S.used == 0 && moments_out)
         std::memcpy(moments_out + (size_t)g * (p + 1), mg, (p + 1) * sizeof(double));
@@ -295,6 +306,31 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
       }
       ++S.used;
       ++S.t_in;
+      if (mlp_params) {
+        // learned mode: the first pass picks the half and feeds the network
+        if (S.used == 1) {
+          if (std::floor(cnt + 0.5) == (double)k[g]) {
+            lambda_out[g] = mid;
+            status_out[g] = CSC_OK;
+            S.done = true;
+          } else {
+            learned_features(mg, graphs[g].n, k[g], hx.data() + (size_t)g * 52);
+            S.ls.half_lo = cnt;  // first count, consumed by learned_begin below
+            need_mlp = true;
+          }
+          continue;
+        }
+        if (learned_update(S.ls, mid, cnt, k[g])) {
+          lambda_out[g] = mid;
+          status_out[g] = S.ls.status;
+          S.done = true;
+        } else if (S.used == max_steps) {
+          lambda_out[g] = S.ls.hi;
+          status_out[g] = S.ls.status == CSC_OK ? CSC_W_BISECT_EXHAUSTED : S.ls.status;
+          S.done = true;
+        }
+        continue;
+      }
       if (std::floor(cnt + 0.5) == (double)k[g]) {
         lambda_out[g] = mid;
         status_out[g] = S.missed ? CSC_W_BRACKET_MISS : CSC_OK;
@@ -320,6 +356,19 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
           status_out[g] = S.missed ? CSC_W_BRACKET_MISS : CSC_W_BISECT_EXHAUSTED;
           S.done = true;
         }
+      }
+    }
+    if (need_mlp) {
+      CSC_TRY(upload(d_x, hx, s));
+      CSC_TRY(csc_mlp_forward(mlp_params, d_x, G, d_y, d_mws, mlp_workspace(G), stream));
+      CSC_HIP(hipMemcpyAsync(hy.data(), d_y, hy.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+      CSC_HIP(hipStreamSynchronize(s));
+      for (int g = 0; g < G; ++g) {
+        State& S = st[g];
+        if (!live[g] || S.done || S.used != 1) continue;
+        const double c1 = S.ls.half_lo;
+        learned_begin(S.ls, hmom.data() + (size_t)g * (p + 1), p, k[g], n_signals[g], c1,
+                      hy.data() + (size_t)g * 2);
       }
     }
   }

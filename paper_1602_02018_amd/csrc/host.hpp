@@ -15,6 +15,20 @@ size_t filter_bytes(const Layout& L);
 size_t count_bytes(const Layout& L, int p);
 size_t interp_bytes(const Layout& L);
 int use_hip_graphs();
+
+// Learned dichotomy (mlp.hip): the bracket from the network outputs y for a
+// graph whose first pass at lambda = 1 gave count c1 and moments mom, and the
+// update after each later count (true once the count rounds to k).
+struct LearnedState {
+  double lo = 0, hi = 2, lo0 = 0, hi0 = 2, half_lo = 0, half_hi = 2;
+  bool below = false, above = false, widened = false;
+  int status = CSC_OK;
+};
+void learned_features(const double* mom, int N, int k, float* x);
+void learned_begin(LearnedState& S, const double* mom, int p, int k, int n_signals, double c1,
+                   const float y[2]);
+bool learned_update(LearnedState& S, double mid, double cnt, int k);
+size_t mlp_workspace(int B);
 hipStream_t capture_stream();
 
 }  // namespace csc

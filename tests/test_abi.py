@@ -118,3 +118,18 @@ def test_host_kmeans_float32_input_and_errors():
     assert lab.min() >= 0 and lab.max() < 3 and inertia > 0
     with pytest.raises(_lib.CscError):
         api.kmeans_reduced(X, 51, 0)
+
+
+def test_count_root_host_call_matches_oracle():
+    from oracle import mlp
+    from paper_1602_02018_amd import api
+
+    rng = np.random.default_rng(0)
+    for k, nc in ((10, 14), (100, 24), (250, 28)):
+        # a monotone synthetic count curve: moments of a spectrum with 3k eigenvalues in [0, 2]
+        lam = np.sort(rng.uniform(0, 2, 3 * k))
+        t = np.arccos(lam - 1.0)
+        mu = np.array([np.sum(np.cos(m * t)) for m in range(51)])
+        l0, s = api.count_root(mu, k, nc)
+        r0, rs = mlp.count_root(mu, 50, k, nc)
+        assert abs(l0 - r0) < 1e-12 and abs(s - rs) <= 1e-9 * rs

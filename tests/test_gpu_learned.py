@@ -1,0 +1,49 @@
+"""The trained bracket network against the plain dichotomy on held-out graphs
+larger than any training graph (training used N <= 1e5)."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+def test_learned_bracket_saves_passes_at_equal_accuracy():
+    from paper_1602_02018_amd import api, learned
+
+    params = learned.load_params()
+    specs = [learned.graph_spec(i, 7, (1.2e5, 2.5e5)) for i in range(8)]
+    plain_steps, learned_steps, err_plain, err_learned = [], [], [], []
+    for spec, rp, col in learned.generate(specs):
+        g = api.Graph(rp, col)
+        nc = api.count_signals(g.n)
+        a = api.estimate_lambda_k(g, spec["k"], 50, nc, spec["seed"])
+        b = api.estimate_lambda_k_learned(g, spec["k"], 50, nc, spec["seed"], params)
+        plain_steps.append(a.steps)
+        learned_steps.append(b.steps)
+        for lam, errs in ((a.lam, err_plain), (b.lam, err_learned)):
+            cnt, _ = api.eigencount(g, lam, 50, nc, spec["seed"], 1000)  # independent judge
+            errs.append(abs(cnt - spec["k"]))
+    print(f"passes plain {np.mean(plain_steps):.2f} learned {np.mean(learned_steps):.2f}; "
+          f"|count - k| plain {np.mean(err_plain):.2f} learned {np.mean(err_learned):.2f}")
+    assert np.mean(learned_steps) <= 0.6 * np.mean(plain_steps)
+    assert np.mean(err_learned) <= np.mean(err_plain) + 1.0
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_end_to_end_with_learned_bracket_recovers_as_well_as_plain(seed):
+    # the learned search stops at another point of the interval where the count
+    # rounds to k, so labels are compared through their agreement with the truth
+    import synth
+    from oracle import metrics
+    from paper_1602_02018_amd import api, learned
+
+    params = learned.load_params()
+    gr = synth.sbm_config(20000, 40, seed=seed)
+    g = api.Graph(gr.row_ptr, gr.col)
+    plain = api.run(g, 40, 40, seed)
+    lrn = api.run(g, 40, 40, seed, mlp_params=params)
+    assert lrn.bisection.steps < plain.bisection.steps
+    a_plain = metrics.adjusted_rand_index(plain.labels.cpu().numpy(), gr.truth)
+    a_lrn = metrics.adjusted_rand_index(lrn.labels.cpu().numpy(), gr.truth)
+    print(f"ARI vs truth plain {a_plain:.4f} learned {a_lrn:.4f}")
+    assert a_lrn >= a_plain - 0.05 and a_lrn > 0.5

@@ -113,6 +113,22 @@ def test_features_estimate_the_damped_spectral_moments():
 def test_bracket_is_ordered_and_clipped():
     theta = np.zeros(mlp.N_PARAMS)
     W1, b1, W2, b2, W3, b3 = mlp.unpack(theta)
-    b3[:] = [2.7, -0.4]
-    lo, hi = mlp.bracket(mlp.pack([W1, b1, W2, b2, W3, b3]), np.zeros(mlp.D_IN))
-    assert (lo, hi) == (0.0, 2.0)
+    b3[:] = [2.0, -1.0]
+    th = mlp.pack([W1, b1, W2, b2, W3, b3])
+    assert mlp.bracket(th, np.zeros(mlp.D_IN), 0.5, 0.1) == (0.4, 0.7)
+    assert mlp.bracket(th, np.zeros(mlp.D_IN), 1.9, 0.5) == (1.4, 2.0)
+
+
+def test_count_root_recovers_the_eigenvalue_crossing():
+    # with many signals the count curve is close to tr h~, whose k crossing lies
+    # between lambda_k and lambda_{k+1} of a graph with a clear gap
+    g = synth.disconnected_regular(5, 60, 6, seed=2)
+    A, _ = laplacian.normalized_adjacency(g.row_ptr, g.col)
+    ev = np.linalg.eigvalsh(laplacian.laplacian_dense(g.row_ptr, g.col))
+    R = philox.gaussian_block(0, g.n, 400, 1, philox.COUNT)
+    mu = cheb.moments(A, R, 50)
+    lam0, s = mlp.count_root(mu, 50, 5, 400)
+    assert ev[4] - 0.05 <= lam0 <= ev[5] + 0.05
+    c = float(np.dot(jackson.lowpass_coeffs(lam0, 50), mu))
+    assert abs(c - 5) < 1e-6
+    assert 1e-4 <= s <= 0.5
