@@ -112,6 +112,23 @@ enum {
 csc_status csc_set_tuning(int32_t key, int32_t value);
 int32_t csc_get_tuning(int32_t key);
 
+/* Autotuner.  csc_autotune times one kind of Chebyshev step (as in
+ * csc_cheb_steps: 0 accumulate, 1 moments, 2 CG operator) on graph g at block
+ * width w for candidate panel widths (the six best of the built-in cost
+ * model and every multiple of 32 columns that pads w less than twofold) and
+ * both XCD orders, `reps` launches each, timed with HIP events on `stream`.
+ * The fastest panel width is recorded for the shape bucket (floor(log2 N),
+ * rounded mean degree, w) and used by every later call of the process on a
+ * graph of that bucket; pw_out / xcd_out / us_out (host, or NULL) receive the
+ * winner and its microseconds per launch.  The XCD-order knob is left as it
+ * was (pass xcd_out to csc_set_tuning to apply it).  ws:
+ * csc_cheb_steps_workspace_bytes(N, w).  Synchronises.  csc_autotune_clear
+ * forgets every recorded bucket. */
+csc_status csc_autotune(const csc_graph* g, int32_t w, int32_t kind, int32_t reps,
+                        int32_t* pw_out, int32_t* xcd_out, double* us_out, void* ws,
+                        size_t ws_bytes, void* stream);
+void csc_autotune_clear(void);
+
 /* ------------------------------------------------------------------------
  * Normalized adjacency (Sec. 2.1): D_ii = sum_{j != i} W_ij accumulated in
  * float64, s_i = D_ii^-1/2 (0 when D_ii = 0, so that an isolated node has

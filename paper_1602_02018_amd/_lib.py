@@ -49,6 +49,8 @@ PROTOTYPES = {
     "csc_set_panel_width": (i32, [i32]),
     "csc_get_panel_width": (i32, [i32, C.c_int64, i32]),
     "csc_set_tuning": (i32, [i32, i32]),
+    "csc_autotune": (i32, [pg, i32, i32, i32, pi, pi, pd, vp, sz, vp]),
+    "csc_autotune_clear": (None, []),
     "csc_get_tuning": (i32, [i32]),
     "csc_laplacian_from_adjacency": (i32, [i32, i32, vp, vp, vp, vp, vp, i32, vp]),
     "csc_jackson_coeffs": (i32, [f64, i32, pd]),

@@ -79,6 +79,19 @@ def get_tuning(key: int) -> int:
     return int(lib().csc_get_tuning(int(key)))
 
 
+def autotune(g: Graph, w: int, kind: int = 0, reps: int = 20):
+    """Times candidate panel widths for (g, w); the winner is used for this shape from now on."""
+    pw, xcd, us = C.c_int32(0), C.c_int32(0), C.c_double(0.0)
+    ws = _ws(lib().csc_cheb_steps_workspace_bytes(g.n, w), g.device)
+    check(lib().csc_autotune(g.ref, int(w), int(kind), int(reps), C.byref(pw), C.byref(xcd),
+                             C.byref(us), _ptr(ws), ws.numel(), _stream()), "csc_autotune")
+    return pw.value, xcd.value, us.value
+
+
+def autotune_clear() -> None:
+    lib().csc_autotune_clear()
+
+
 def panel_width(n: int, w: int, nnz: int = 0) -> int:
     return int(lib().csc_get_panel_width(int(n), int(nnz) if nnz else 16 * int(n), int(w)))
 

@@ -3,7 +3,9 @@
 // runs in the kernels of kernels.hip.
 #include <algorithm>
 #include <atomic>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -60,25 +62,50 @@ void apply_tuning(StepArgs& sa) {
 // average.  The choice minimises, per row and step, gathered line bytes
 // (deg * 128 * lines per panel) + streamed bytes (16 per padded column)
 // + CSR bytes re-read for every panel (8 deg + 4).
+double panel_cost(int n, int w, long long nnz, int pw);
+
+namespace {
+// Autotuner results: panel width per shape bucket (log2 N, rounded mean
+// degree, width).  Written by csc_autotune, read by every later call.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tuned;
+
+std::tuple<int, int, int> shape_key(int n, int w, long long nnz) {
+  int lg = 0;
+  while ((1LL << (lg + 1)) <= (long long)n) ++lg;
+  const int deg = n > 0 ? (int)std::lround((double)nnz / n) : 0;
+  return std::make_tuple(lg, deg, w);
+}
+}  // namespace
+
 int choose_panel_width(int n, int w, long long nnz) {
   const int o = g_panel_override.load();
   if (o) return o;
-  const double deg = n > 0 ? (double)nnz / n : 16.0;
-  double best = 0.0;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tuned.find(shape_key(n, w, nnz));
+    if (it != g_tuned.end()) return it->second;
+  }
   int arg = 4;
+  double best = 0.0;
   for (int pw = 4; pw <= 256; pw += 4) {
-    const int np = (w + pw - 1) / pw;
-    const int b = 4 * pw;
-    int g = 128;
-    while (b % g) g >>= 1;
-    const double lines = (double)(b + 128 - g) / 128.0;
-    const double cost = np * (deg * 128.0 * lines + 16.0 * pw + 8.0 * deg + 4.0);
-    if (pw == 4 || cost < best) {
-      best = cost;
+    const double c = panel_cost(n, w, nnz, pw);
+    if (pw == 4 || c < best) {
+      best = c;
       arg = pw;
     }
   }
   return arg;
+}
+
+double panel_cost(int n, int w, long long nnz, int pw) {
+  const double deg = n > 0 ? (double)nnz / n : 16.0;
+  const int np = (w + pw - 1) / pw;
+  const int b = 4 * pw;
+  int g = 128;
+  while (b % g) g >>= 1;
+  const double lines = (double)(b + 128 - g) / 128.0;
+  return np * (deg * 128.0 * lines + 16.0 * pw + 8.0 * deg + 4.0);
 }
 
 Layout make_layout(int n, int w, int pw) {
@@ -781,4 +808,75 @@ extern "C" csc_status csc_cheb_steps(const csc_graph* g, int32_t w, int32_t kind
     CSC_HIP(launch_cheb_step(sa, epi, false, epi == EPI_CG, s));
   }
   return CSC_OK;
+}
+
+extern "C" csc_status csc_autotune(const csc_graph* g, int32_t w, int32_t kind, int32_t reps,
+                                   int32_t* pw_out, int32_t* xcd_out, double* us_out, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  clear_error();
+  CSC_TRY(check_graph(g));
+  CSC_REQUIRE(w >= 1 && kind >= 0 && kind <= 2 && reps >= 1, "need w >= 1, kind 0..2, reps >= 1");
+  CSC_REQUIRE(g_panel_override.load() == 0, "a forced panel width is in effect");
+  CSC_TRY(check_ws(ws, ws_bytes, csc_cheb_steps_workspace_bytes(g->n, w)));
+  hipStream_t s = as_stream(stream);
+  // candidates: the six cheapest widths of the cost model and every 128-byte multiple
+  std::vector<std::pair<double, int>> ranked;
+  for (int pw = 4; pw <= 256; pw += 4) ranked.push_back({panel_cost(g->n, w, g->nnz, pw), pw});
+  std::sort(ranked.begin(), ranked.end());
+  std::vector<int> cand;
+  for (size_t i = 0; i < ranked.size() && cand.size() < 6; ++i) cand.push_back(ranked[i].second);
+  for (int pw = 32; pw <= 256; pw += 32)
+    if (std::find(cand.begin(), cand.end(), pw) == cand.end() && (w + pw - 1) / pw * pw < 2 * w + 32)
+      cand.push_back(pw);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  CSC_HIP(hipEventCreate(&e0));
+  CSC_HIP(hipEventCreate(&e1));
+  const int xcd_saved = g_tune_xcd.load();
+  double best = -1.0;
+  int best_pw = cand[0], best_xcd = xcd_saved;
+  csc_status st = CSC_OK;
+  for (int pw : cand) {
+    for (int xcd = 0; xcd <= 1 && st == CSC_OK; ++xcd) {
+      g_panel_override.store(pw);
+      g_tune_xcd.store(xcd);
+      st = csc_cheb_steps(g, w, kind, 1, 2, ws, ws_bytes, stream);  // prepare + warm
+      if (st != CSC_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(e0, s) != hipSuccess ||
+          (st = csc_cheb_steps(g, w, kind, 0, reps, ws, ws_bytes, stream)) != CSC_OK ||
+          hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        if (st == CSC_OK) {
+          set_error("event timing failed during autotuning");
+          st = CSC_E_HIP;
+        }
+        break;
+      }
+      const double us = 1000.0 * ms / reps;
+      if (best < 0.0 || us < best) {
+        best = us;
+        best_pw = pw;
+        best_xcd = xcd;
+      }
+    }
+    if (st != CSC_OK) break;
+  }
+  g_panel_override.store(0);
+  g_tune_xcd.store(xcd_saved);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != CSC_OK) return st;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tuned[shape_key(g->n, w, g->nnz)] = best_pw;
+  }
+  if (pw_out) *pw_out = best_pw;
+  if (xcd_out) *xcd_out = best_xcd;
+  if (us_out) *us_out = best;
+  return CSC_OK;
+}
+
+extern "C" void csc_autotune_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tuned.clear();
 }

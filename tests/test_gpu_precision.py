@@ -1,0 +1,68 @@
+"""Precision form: float32 recurrences and SpMM, float64 only for the
+eigencount moments and the CG inner products and norms.  Reports the error of
+every result of Alg. 2 against the float64 oracle on the same seeded inputs
+(printed with -s) and bounds it."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import cheb, eigencount, interp, jackson, kmeans, laplacian, metrics, philox, sampling
+from oracle import csc as ocsc
+
+pytestmark = pytest.mark.gpu
+
+
+def test_per_result_error_against_float64():
+    from paper_1602_02018_amd import api
+
+    gr = synth.sbm_config(1000, 10, seed=0)
+    A, _ = laplacian.normalized_adjacency(gr.row_ptr, gr.col)
+    g = api.Graph(gr.row_ptr, gr.col)
+    k, p, seed = 10, 50, 0
+    d = int(math.ceil(4 * math.log(gr.n)))
+    n_c = eigencount.count_signals(gr.n)
+    rep = {}
+
+    # eigencount moments and counts
+    _, mom = api.eigencount(g, 0.5, p, n_c, seed, 1)
+    mref = cheb.moments(A, philox.gaussian_block(seed, gr.n, n_c, 1, philox.COUNT), p)
+    rep["moments max |err| / mu_0"] = float(np.max(np.abs(mom - mref)) / mref[0])
+    counts = [(lam, float(np.dot(jackson.lowpass_coeffs(lam, p), mom)),
+               float(np.dot(jackson.lowpass_coeffs(lam, p), mref))) for lam in (0.25, 0.4, 0.5, 1.0)]
+    rep["count max |err|"] = max(abs(a - b) for _, a, b in counts)
+
+    # dichotomy
+    bis = api.estimate_lambda_k(g, k, p, n_c, seed)
+    lam_ref, steps_ref, _, _ = eigencount.estimate_lambda_k(A, k, p, n_c, seed)
+    rep["lambda_k |err|"] = abs(bis.lam - lam_ref)
+
+    # features (unit rows, all nodes)
+    F = api.filter(g, lam_ref, p, d, seed).cpu().numpy()
+    Fref = ocsc.features(A, lam_ref, p, d, seed)
+    rep["features rel Frobenius err"] = float(np.linalg.norm(F - Fref) / np.linalg.norm(Fref))
+
+    # k-means labels from the float32 features vs from the float64 features
+    omega = sampling.sample(gr.n, ocsc.default_n(k), seed)
+    lab32, _ = api.kmeans_reduced(F[omega].astype(np.float64), k, seed)
+    lab64, _, _ = kmeans.kmeans(Fref[omega], k, seed)
+    rep["sampled labels ARI (f32 vs f64 features)"] = metrics.adjusted_rand_index(lab32, lab64)
+
+    # interpolation
+    res = api.interpolate(g, lam_ref, p, 1e-3, omega, lab64, k)
+    X, lab, _, _ = interp.interpolate(A, lam_ref, p, 1e-3, omega, lab64, k)
+    Xg = res.X.cpu().numpy()
+    rep["X rel Frobenius err"] = float(np.linalg.norm(Xg - X) / np.linalg.norm(X))
+    rep["labels ARI vs float64"] = metrics.adjusted_rand_index(res.labels.cpu().numpy(), lab)
+
+    for key, val in rep.items():
+        print(f"{key:45s} {val:.3e}")
+    assert rep["moments max |err| / mu_0"] <= 1e-5
+    assert rep["count max |err|"] <= 1e-2
+    assert rep["lambda_k |err|"] <= 2.0 / 2 ** min(bis.steps, steps_ref)
+    assert rep["features rel Frobenius err"] <= 1e-4
+    assert rep["sampled labels ARI (f32 vs f64 features)"] >= 0.99
+    assert rep["X rel Frobenius err"] <= 1e-3
+    assert rep["labels ARI vs float64"] >= 0.99
