@@ -94,9 +94,10 @@ int32_t csc_get_panel_width(int32_t n, int64_t nnz, int32_t w);
 
 /* Kernel tuning knobs, process-wide; results do not depend on them.
  * CSC_TUNE_PANEL_WIDTH: as csc_set_panel_width.
- * CSC_TUNE_XCD_ORDER (0/1, default 1): order work so that each XCD of the
- *   GPU (workgroup b runs on XCD b mod 8) walks a contiguous range of
- *   panel-major row tiles.
+ * CSC_TUNE_XCD_ORDER (0/1/2, default 1): how row tiles are spread over the
+ *   8 XCDs of the GPU (workgroup b runs on XCD b mod 8): 0 round-robin; 1
+ *   each XCD walks a contiguous range of panel-major row tiles; 2 each XCD
+ *   keeps one eighth of the rows and all XCDs walk the panels in step.
  * CSC_TUNE_NONTEMPORAL (0/1, default 0): non-temporal loads and stores for
  *   the streamed blocks (T_{m-1}, T_{m+1}, accumulators).
  * CSC_TUNE_HIP_GRAPHS (0/1, default 1): the batched calls record their
@@ -259,14 +260,53 @@ csc_status csc_kmeans_reduced_f64(const double* F, int32_t n, int32_t d, int32_t
  * idx, labels_r: device int32[n] (idx distinct, labels_r in [0, k)).
  * X: device N x k with leading dimension ldx >= k.  labels: device int32[N].
  * iters_out: host int32[k] or NULL; relres_out: host double[k] or NULL.
- * ws: csc_interpolate_workspace_bytes(N, k, n).  Synchronises.
- * Returns CSC_W_NOT_CONVERGED if a column reached max_iter.
+ * order: device int32[N] permutation of [0, N), or NULL.  With an order the
+ *   solve runs on a copy of the graph permuted so that row r is node order[r]
+ *   (neighbours kept in CSR order), which only changes where rows sit in
+ *   memory (see csc_community_order); X and labels are written in the
+ *   caller's node numbering either way.  Per-element products are unchanged;
+ *   the float64 column sums run in the new row order.  An order that is not a
+ *   permutation returns CSC_E_INVALID_ARG.
+ * ws: csc_interpolate_workspace_bytes(N, nnz, k, n) (covers both forms).
+ * Synchronises.  Returns CSC_W_NOT_CONVERGED if a column reached max_iter.
  */
-size_t csc_interpolate_workspace_bytes(int32_t N, int32_t k, int32_t n);
-csc_status csc_interpolate(const csc_graph* g, double lambda_k, int32_t p, double gamma,
-                           const int32_t* idx, const int32_t* labels_r, int32_t n, int32_t k,
-                           double tol, int32_t max_iter, float* X, int32_t ldx, int32_t* labels,
-                           int32_t* iters_out, double* relres_out, void* ws, size_t ws_bytes,
+size_t csc_interpolate_workspace_bytes(int32_t N, int64_t nnz, int32_t k, int32_t n);
+csc_status csc_interpolate(const csc_graph* g, const int32_t* order, double lambda_k, int32_t p,
+                           double gamma, const int32_t* idx, const int32_t* labels_r, int32_t n,
+                           int32_t k, double tol, int32_t max_iter, float* X, int32_t ldx,
+                           int32_t* labels, int32_t* iters_out, double* relres_out, void* ws,
+                           size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Community order of the nodes, a memory layout for the interpolation (the
+ * paper fixes no node order).  Each node gets the label of the nearest
+ * centroid (squared Euclidean distance in float32, coordinates summed in
+ * order, ties to the lowest label) among the centroids of the k-means of
+ * Alg. 2 step 6: centroid c is the float64 mean, rounded to float32, of the
+ * rows F[idx[s]] with labels_r[s] = c (empty clusters are skipped).  order
+ * lists the nodes by that label, ties in index order.  Listing communities
+ * contiguously lets the gathers of a Chebyshev step hit the L2 of the XCD
+ * that walks a community's rows.
+ * F: device N x d, leading dimension ldf (the normalized features of every
+ *   node, csc_filter with rows = NULL), d <= 128.  idx: device int32[n].
+ *   labels_r: HOST int32[n] in [0, k) (csc_kmeans_reduced's output).
+ * order: device int32[N].  node_labels: device int32[N] (the nearest-centroid
+ *   label of every node) or NULL.
+ * ws: csc_community_order_workspace_bytes(N, d, k, n).  Synchronises.
+ */
+size_t csc_community_order_workspace_bytes(int32_t N, int32_t d, int32_t k, int32_t n);
+csc_status csc_community_order(int32_t N, const float* F, int64_t ldf, int32_t d,
+                               const int32_t* idx, const int32_t* labels_r, int32_t n, int32_t k,
+                               int32_t* order, int32_t* node_labels, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/* Rows of a device block: out[s, :] = F[rows[s], :] for s < n (Alg. 2 step 5,
+ * the sampled features F_Omega from the features of every node).  F: device
+ * N x d with leading dimension ldf; rows: device int32[n]; out: device n x d
+ * with leading dimension ldo.  Returns CSC_E_INVALID_ARG if a row index lies
+ * outside [0, N).  ws: 256 bytes of device memory.  Synchronises. */
+csc_status csc_gather_rows(const float* F, int64_t ldf, int32_t N, int32_t d, const int32_t* rows,
+                           int32_t n, float* out, int32_t ldo, void* ws, size_t ws_bytes,
                            void* stream);
 
 /* ------------------------------------------------------------------------
@@ -303,9 +343,10 @@ csc_status csc_estimate_lambda_k_batched(const csc_graph* graphs, int32_t G, con
                                          double* moments_out, int32_t* status_out, void* ws,
                                          size_t ws_bytes, void* stream);
 
-/* csc_filter_batched: csc_filter in its sampled-rows form for every graph
- * (lambda[g], d[g], seeds[g], rows[g] device per-graph with n_rows[g]
- * entries, output Y[g] device per-graph n_rows[g] x d[g] with ld[g]). */
+/* csc_filter_batched: csc_filter for every graph (lambda[g], d[g], seeds[g],
+ * rows[g] device per-graph with n_rows[g] entries, or NULL for all N_g rows;
+ * output Y[g] device per-graph n_rows[g] (or N_g) x d[g] with ld[g]).
+ * Results are bit-identical to csc_filter's. */
 size_t csc_filter_workspace_bytes_batched(const csc_graph* graphs, int32_t G, const int32_t* d,
                                           int32_t p);
 csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, const double* lambda,
@@ -320,11 +361,14 @@ csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, const double* 
  * converge (or after max_iter iterations).  X: device per-graph N_g x k[g]
  * with ldx[g] (X or X[g] may be NULL), labels: device per-graph int32[N_g].
  * iters_out / relres_out: host arrays of sum_g k[g] entries (graph-major) or
- * NULL.  Returns CSC_W_NOT_CONVERGED if any graph did not converge. */
+ * NULL.  order: NULL, or per-graph device int32[N_g] node orders (entries
+ * may be NULL), as in csc_interpolate.  Returns CSC_W_NOT_CONVERGED if any
+ * graph did not converge. */
 size_t csc_interpolate_workspace_bytes_batched(const csc_graph* graphs, int32_t G,
                                                const int32_t* k, int32_t p);
-csc_status csc_interpolate_batched(const csc_graph* graphs, int32_t G, const double* lambda,
-                                   int32_t p, double gamma, const int32_t* const* idx,
+csc_status csc_interpolate_batched(const csc_graph* graphs, int32_t G, const int32_t* const* order,
+                                   const double* lambda, int32_t p, double gamma,
+                                   const int32_t* const* idx,
                                    const int32_t* const* labels_r, const int32_t* n,
                                    const int32_t* k, double tol, int32_t max_iter,
                                    float* const* X, const int32_t* ldx, int32_t* const* labels,

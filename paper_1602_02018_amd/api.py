@@ -206,20 +206,58 @@ class Interpolation:
 
 
 def interpolate(g: Graph, lam: float, p: int, gamma: float, idx, labels_r, k: int,
-                tol: float = 1e-6, max_iter: int = 1000, want_X: bool = True) -> Interpolation:
+                tol: float = 1e-6, max_iter: int = 1000, want_X: bool = True,
+                order: torch.Tensor | None = None) -> Interpolation:
+    """Eq. (5) by CG; with ``order`` (a permutation, see community_order) the
+    solve runs on the graph listed in that order, outputs in node order."""
     idx_t = _i32_device(idx, g.device)
     lab_t = _i32_device(labels_r, g.device)
+    ord_t = None if order is None else _i32_device(order, g.device)
     n = int(idx_t.numel())
     X = torch.empty((g.n, k), dtype=torch.float32, device=g.device) if want_X else None
     labels = torch.empty(g.n, dtype=torch.int32, device=g.device)
     iters = np.zeros(k, dtype=np.int32)
     relres = np.zeros(k)
-    ws = _ws(lib().csc_interpolate_workspace_bytes(g.n, k, n), g.device)
-    st = check(lib().csc_interpolate(g.ref, float(lam), p, float(gamma), _ptr(idx_t), _ptr(lab_t),
-                                     n, k, float(tol), max_iter, _ptr(X), k, _ptr(labels),
-                                     iters.ctypes.data_as(_lib.pi), relres.ctypes.data_as(_lib.pd),
-                                     _ptr(ws), ws.numel(), _stream()), "csc_interpolate")
+    ws = _ws(lib().csc_interpolate_workspace_bytes(g.n, g.nnz, k, n), g.device)
+    st = check(lib().csc_interpolate(g.ref, _ptr(ord_t), float(lam), p, float(gamma), _ptr(idx_t),
+                                     _ptr(lab_t), n, k, float(tol), max_iter, _ptr(X), k,
+                                     _ptr(labels), iters.ctypes.data_as(_lib.pi),
+                                     relres.ctypes.data_as(_lib.pd), _ptr(ws), ws.numel(),
+                                     _stream()), "csc_interpolate")
     return Interpolation(X, labels, iters, relres, st)
+
+
+def community_order(F: torch.Tensor, idx, labels_r, k: int, want_labels: bool = False):
+    """Node order by nearest k-means centroid (csc_community_order).
+
+    F: device N x d features of every node; idx: sampled nodes; labels_r: their
+    k-means labels.  Returns the order (device int32[N]) and, with
+    ``want_labels``, every node's nearest-centroid label."""
+    assert F.is_cuda and F.dtype == torch.float32 and F.dim() == 2 and F.stride(1) == 1
+    N, d = F.shape
+    idx_t = _i32_device(idx, F.device)
+    lab = np.ascontiguousarray(labels_r, dtype=np.int32)
+    n = int(idx_t.numel())
+    order = torch.empty(N, dtype=torch.int32, device=F.device)
+    nl = torch.empty(N, dtype=torch.int32, device=F.device) if want_labels else None
+    ws = _ws(lib().csc_community_order_workspace_bytes(N, d, k, n), F.device)
+    check(lib().csc_community_order(N, _ptr(F), F.stride(0), d, _ptr(idx_t),
+                                    lab.ctypes.data_as(_lib.pi), n, k, _ptr(order), _ptr(nl),
+                                    _ptr(ws), ws.numel(), _stream()), "csc_community_order")
+    return (order, nl) if want_labels else order
+
+
+def gather_rows(F: torch.Tensor, rows) -> torch.Tensor:
+    """F[rows] through csc_gather_rows."""
+    assert F.is_cuda and F.dtype == torch.float32 and F.dim() == 2 and F.stride(1) == 1
+    N, d = F.shape
+    rows_t = _i32_device(rows, F.device)
+    n = int(rows_t.numel())
+    out = torch.empty((n, d), dtype=torch.float32, device=F.device)
+    ws = _ws(256, F.device)
+    check(lib().csc_gather_rows(_ptr(F), F.stride(0), N, d, _ptr(rows_t), n, _ptr(out), d,
+                                _ptr(ws), ws.numel(), _stream()), "csc_gather_rows")
+    return out
 
 
 class StepTimer:
@@ -255,6 +293,7 @@ class Result:
     inertia: float
     interp: Interpolation
     timings: dict = field(default_factory=dict)
+    order: torch.Tensor | None = None  # node order of the interpolation, if any
 
     @property
     def labels(self) -> torch.Tensor:
@@ -264,10 +303,15 @@ class Result:
 def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
         gamma: float = 1e-3, n_c: int | None = None, tol: float = 1e-6, max_iter: int = 1000,
         max_steps: int = 30, replicates: int = 20, kmeans_iter: int = 100, lam: float | None = None,
-        bracket=None, want_X: bool = False, mlp_params: torch.Tensor | None = None) -> Result:
+        bracket=None, want_X: bool = False, mlp_params: torch.Tensor | None = None,
+        reorder: bool = True) -> Result:
     """Compressive spectral clustering (Alg. 2) with every graph-sized step on the GPU.
 
-    With ``mlp_params`` the dichotomy starts from the learned bracket.
+    With ``mlp_params`` the dichotomy starts from the learned bracket.  With
+    ``reorder`` the feature pass keeps every node's features, and the
+    interpolation runs on the graph listed community by community
+    (community_order); the sampled features, and so the k-means, are the same
+    either way.
     """
     n = default_n(k) if n is None else n
     n_c = count_signals(g.n) if n_c is None else n_c
@@ -283,18 +327,25 @@ def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
     else:
         bis = Bisection(lam, 0, [], np.zeros(p + 1), 0)
     t1 = time.perf_counter()
+    reorder = reorder and d <= 128
     omega = sample(g.n, n, seed, g.device)
-    F = filter(g, lam, p, d, seed, rows=omega, normalize=True)
+    if reorder:
+        F_all = filter(g, lam, p, d, seed, rows=None, normalize=True)
+        F = gather_rows(F_all, omega)
+    else:
+        F = filter(g, lam, p, d, seed, rows=omega, normalize=True)
     Fh = F.cpu().numpy()
     t2 = time.perf_counter()
     labels_r, inertia = kmeans_reduced(Fh, k, seed, replicates, kmeans_iter)
     t3 = time.perf_counter()
-    it = interpolate(g, lam, p, gamma, omega, labels_r, k, tol, max_iter, want_X=want_X)
+    order = community_order(F_all, omega, labels_r, k) if reorder else None
+    it = interpolate(g, lam, p, gamma, omega, labels_r, k, tol, max_iter, want_X=want_X,
+                     order=order)
     torch.cuda.current_stream().synchronize()
     t4 = time.perf_counter()
     tm.update(bisection_s=t1 - t0, features_s=t2 - t1, kmeans_s=t3 - t2, interpolate_s=t4 - t3,
               total_s=t4 - t0)
-    return Result(lam, bis, omega, F, labels_r, inertia, it, tm)
+    return Result(lam, bis, omega, F, labels_r, inertia, it, tm, order)
 
 
 # ------------------------------------------------------------ batched --------
@@ -341,18 +392,20 @@ def estimate_lambda_k_batched(graphs, ks, p, n_signals, seeds, max_steps=30, bra
 
 
 def filter_batched(graphs, lams, p, ds, seeds, rows, normalize=True):
+    """csc_filter_batched; rows[g] None keeps all N_g rows."""
     G = len(graphs)
     ga = _graphs(graphs)
     dev = graphs[0].device
-    rows_t = [_i32_device(r, dev) for r in rows]
-    n_rows = _i32([r.numel() for r in rows_t])
+    rows_t = [None if r is None else _i32_device(r, dev) for r in rows]
+    n_rows = _i32([g.n if r is None else r.numel() for g, r in zip(graphs, rows_t)])
     ds = _i32(ds)
     Ys = [torch.empty((int(n_rows[g]), int(ds[g])), dtype=torch.float32, device=dev) for g in range(G)]
     lam = np.ascontiguousarray(lams, dtype=np.float64)
     sd = np.ascontiguousarray(seeds, dtype=np.uint64)
     ws = _ws(lib().csc_filter_workspace_bytes_batched(ga, G, ds.ctypes.data_as(_lib.pi), p), dev)
     check(lib().csc_filter_batched(ga, G, lam.ctypes.data_as(_lib.pd), p, ds.ctypes.data_as(_lib.pi),
-                                   sd.ctypes.data_as(_lib.pu), _pa([r.data_ptr() for r in rows_t]),
+                                   sd.ctypes.data_as(_lib.pu),
+                                   _pa([0 if r is None else r.data_ptr() for r in rows_t]),
                                    n_rows.ctypes.data_as(_lib.pi), 1 if normalize else 0,
                                    _pa([y.data_ptr() for y in Ys]), ds.ctypes.data_as(_lib.pi),
                                    _ptr(ws), ws.numel(), _stream()), "csc_filter_batched")
@@ -360,7 +413,7 @@ def filter_batched(graphs, lams, p, ds, seeds, rows, normalize=True):
 
 
 def interpolate_batched(graphs, lams, p, gamma, idx, labels_r, ks, tol=1e-6, max_iter=1000,
-                        want_X=True):
+                        want_X=True, orders=None):
     G = len(graphs)
     ga = _graphs(graphs)
     dev = graphs[0].device
@@ -376,8 +429,10 @@ def interpolate_batched(graphs, lams, p, gamma, idx, labels_r, ks, tol=1e-6, max
     status = np.zeros(G, dtype=np.int32)
     lam = np.ascontiguousarray(lams, dtype=np.float64)
     ws = _ws(lib().csc_interpolate_workspace_bytes_batched(ga, G, ks.ctypes.data_as(_lib.pi), p), dev)
+    ord_t = None if orders is None else [None if o is None else _i32_device(o, dev) for o in orders]
     st = check(lib().csc_interpolate_batched(
-        ga, G, lam.ctypes.data_as(_lib.pd), p, float(gamma), _pa([x.data_ptr() for x in idx_t]),
+        ga, G, None if ord_t is None else _pa([0 if o is None else o.data_ptr() for o in ord_t]),
+        lam.ctypes.data_as(_lib.pd), p, float(gamma), _pa([x.data_ptr() for x in idx_t]),
         _pa([x.data_ptr() for x in lab_t]), ns.ctypes.data_as(_lib.pi), ks.ctypes.data_as(_lib.pi),
         float(tol), max_iter, _pa([x.data_ptr() if x is not None else 0 for x in Xs]) if want_X else None,
         ks.ctypes.data_as(_lib.pi), _pa([x.data_ptr() for x in labels]),
@@ -412,7 +467,7 @@ def kmeans_reduced_batched(Fs, ks, seeds, replicates=20, max_iter=100):
 
 def run_batched(graphs, ks, ds, seeds, p=50, ns=None, gamma=1e-3, n_cs=None, tol=1e-6,
                 max_iter=1000, max_steps=30, replicates=20, kmeans_iter=100, brackets=None,
-                lams=None, want_X=False, mlp_params=None):
+                lams=None, want_X=False, mlp_params=None, reorder=True):
     """Alg. 2 for G graphs at once with the batched calls; graph g matches run(graphs[g], ...)."""
     G = len(graphs)
     ns = [default_n(k) for k in ks] if ns is None else list(ns)
@@ -426,18 +481,29 @@ def run_batched(graphs, ks, ds, seeds, p=50, ns=None, gamma=1e-3, n_cs=None, tol
         bis = [Bisection(l, 0, [], np.zeros(p + 1), 0) for l in lams]
     t1 = time.perf_counter()
     omegas = [sample(g.n, n, sd, g.device) for g, n, sd in zip(graphs, ns, seeds)]
-    Fs = filter_batched(graphs, lams, p, ds, seeds, omegas, normalize=True)
+    re = [reorder and d <= 128 for d in ds]
+    if any(re):
+        F_all = filter_batched(graphs, lams, p, ds, seeds,
+                               [None if r else o for r, o in zip(re, omegas)], normalize=True)
+        Fs = [gather_rows(f, o) if r else f for f, o, r in zip(F_all, omegas, re)]
+    else:
+        Fs = filter_batched(graphs, lams, p, ds, seeds, omegas, normalize=True)
     Fh = [f.cpu().numpy() for f in Fs]
     t2 = time.perf_counter()
     labels_r, inertia = kmeans_reduced_batched(Fh, ks, seeds, replicates, kmeans_iter)
     t3 = time.perf_counter()
-    its = interpolate_batched(graphs, lams, p, gamma, omegas, labels_r, ks, tol, max_iter, want_X)
+    orders = None
+    if any(re):
+        orders = [community_order(f, o, l, k) if r else None
+                  for f, o, l, k, r in zip(F_all, omegas, labels_r, ks, re)]
+    its = interpolate_batched(graphs, lams, p, gamma, omegas, labels_r, ks, tol, max_iter, want_X,
+                              orders)
     torch.cuda.current_stream().synchronize()
     t4 = time.perf_counter()
     tm.update(bisection_s=t1 - t0, features_s=t2 - t1, kmeans_s=t3 - t2, interpolate_s=t4 - t3,
               total_s=t4 - t0)
-    return [Result(lams[g], bis[g], omegas[g], Fs[g], labels_r[g], float(inertia[g]), its[g], dict(tm))
-            for g in range(G)]
+    return [Result(lams[g], bis[g], omegas[g], Fs[g], labels_r[g], float(inertia[g]), its[g], dict(tm),
+                   orders[g] if orders is not None else None) for g in range(G)]
 
 
 # ------------------------------------------------ learned lambda_k bracket ---

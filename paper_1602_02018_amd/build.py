@@ -22,6 +22,7 @@ SOURCES = {
     "batched.hip": [],
     "api_batched.hip": [],
     "mlp.hip": [],
+    "order.hip": [],
     "kmeans.hip": ["-ffp-contract=off"],
 }
 

@@ -324,7 +324,7 @@ extern "C" csc_status csc_set_tuning(int32_t key, int32_t value) {
     case CSC_TUNE_PANEL_WIDTH:
       return csc_set_panel_width(value);
     case CSC_TUNE_XCD_ORDER:
-      CSC_REQUIRE(value == 0 || value == 1, "value must be 0 or 1");
+      CSC_REQUIRE(value >= 0 && value <= 2, "value must be 0, 1 or 2");
       g_tune_xcd.store(value);
       return CSC_OK;
     case CSC_TUNE_NONTEMPORAL:
@@ -627,32 +627,90 @@ extern "C" csc_status csc_sample(int32_t N, int32_t n, uint64_t seed, int32_t* i
   return CSC_E_INVALID_ARG;
 }
 
-extern "C" size_t csc_interpolate_workspace_bytes(int32_t N, int32_t k, int32_t n) {
-  if (N < 1 || k < 1 || n < 1) return 0;
-  return max_over_widths(N, k, [](const Layout& L) { return interp_bytes(L); });
+namespace csc {
+size_t perm_bytes(int N, int64_t nnz, int n) {
+  size_t b = align_up(((size_t)N + 1) * sizeof(int)) + align_up((size_t)nnz * sizeof(int));
+  b += align_up((size_t)nnz * sizeof(float)) + 2 * align_up((size_t)N * sizeof(int));
+  b += align_up((size_t)n * sizeof(int)) + align_up(perm_graph_temp_bytes(N));
+  return b + align_up(4 * sizeof(int));
 }
 
-extern "C" csc_status csc_interpolate(const csc_graph* g, double lambda_k, int32_t p,
-                                      double gamma, const int32_t* idx, const int32_t* labels_r,
-                                      int32_t n, int32_t k, double tol, int32_t max_iter,
-                                      float* X, int32_t ldx, int32_t* labels, int32_t* iters_out,
+// The graph permuted to `order` (row r = node order[r], neighbours relabelled
+// and kept in CSR order) and the sampled indices in the new numbering, in
+// workspace carved from ar.
+csc_status permuted_graph(const csc_graph& g, const int* order, const int* idx, int n, Arena& ar,
+                          csc_graph& gp, const int*& idxp, hipStream_t s) {
+  const int N = g.n;
+  int* rp = ar.take<int>((size_t)N + 1);
+  int* col = ar.take<int>((size_t)g.nnz);
+  float* val = ar.take<float>((size_t)g.nnz);
+  int* inv = ar.take<int>(N);
+  int* deg = ar.take<int>(N);
+  int* idx2 = ar.take<int>(n);
+  const size_t temp_bytes = perm_graph_temp_bytes(N);
+  void* temp = ar.take<char>(temp_bytes);
+  int* bad = ar.take<int>(4);
+  if (!ar.ok()) {
+    set_error("internal: permutation workspace overflow");
+    return CSC_E_INVALID_ARG;
+  }
+  CSC_HIP(launch_fill_i32(bad, 1, 0, s));
+  CSC_HIP(launch_fill_i32(inv, N, -1, s));
+  CSC_HIP(launch_perm_inverse(N, order, inv, bad, s));
+  CSC_HIP(launch_perm_check(N, inv, bad, s));
+  int hbad = 0;
+  CSC_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  CSC_REQUIRE(!hbad, "order is not a permutation of [0, N)");
+  CSC_HIP(perm_graph(N, order, inv, g.row_ptr, g.col, g.val, rp, col, val, deg, temp, temp_bytes,
+                     s));
+  CSC_HIP(launch_map_indices(n, N, inv, idx, idx2, s));
+  gp = g;
+  gp.row_ptr = rp;
+  gp.col = col;
+  gp.val = val;
+  gp.dinv_sqrt = nullptr;
+  idxp = idx2;
+  return CSC_OK;
+}
+}  // namespace csc
+
+extern "C" size_t csc_interpolate_workspace_bytes(int32_t N, int64_t nnz, int32_t k, int32_t n) {
+  if (N < 1 || nnz < 0 || k < 1 || n < 1) return 0;
+  return max_over_widths(N, k, [](const Layout& L) { return interp_bytes(L); }) +
+         perm_bytes(N, nnz, n);
+}
+
+extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* order,
+                                      double lambda_k, int32_t p, double gamma,
+                                      const int32_t* idx_in, const int32_t* labels_r, int32_t n,
+                                      int32_t k, double tol, int32_t max_iter, float* X,
+                                      int32_t ldx, int32_t* labels, int32_t* iters_out,
                                       double* relres_out, void* ws, size_t ws_bytes,
                                       void* stream) {
   clear_error();
-  CSC_TRY(check_graph(g));
-  const int N = g->n;
-  CSC_REQUIRE(idx && labels_r && labels, "idx, labels_r and labels must be non-NULL");
+  CSC_TRY(check_graph(g_in));
+  const int N = g_in->n;
+  const csc_graph* g = g_in;
+  const int32_t* idx = idx_in;
+  CSC_REQUIRE(idx_in && labels_r && labels, "idx, labels_r and labels must be non-NULL");
   CSC_REQUIRE(k >= 1 && k <= N && n >= 1 && n <= N, "need 1 <= k <= N and 1 <= n <= N");
   CSC_REQUIRE(p >= 1 && gamma > 0.0 && tol > 0.0 && max_iter >= 1,
               "need p >= 1, gamma > 0, tol > 0, max_iter >= 1");
   CSC_REQUIRE(lambda_k >= 0.0 && lambda_k <= 2.0, "lambda_k must lie in [0, 2]");
   CSC_REQUIRE(X == nullptr || ldx >= k, "ldx must be >= k");
   const Layout L = make_layout(N, k, choose_panel_width(N, k, g->nnz));
-  CSC_TRY(check_ws(ws, ws_bytes, interp_bytes(L)));
+  CSC_TRY(check_ws(ws, ws_bytes, interp_bytes(L) + (order ? perm_bytes(N, g->nnz, n) : 0)));
   hipStream_t s = as_stream(stream);
   const int tiles = tiles_for(L);
   const size_t wp = (size_t)L.np * L.pw;
   Arena ar(ws, ws_bytes);
+  csc_graph gperm;
+  if (order) {
+    Arena tail(static_cast<char*>(ws) + interp_bytes(L), ws_bytes - interp_bytes(L));
+    CSC_TRY(permuted_graph(*g_in, order, idx_in, n, tail, gperm, idx, s));
+    g = &gperm;
+  }
   float* P = ar.take<float>(L.elems());
   float* Ta = ar.take<float>(L.elems());
   float* Tb = ar.take<float>(L.elems());
@@ -727,7 +785,7 @@ extern "C" csc_status csc_interpolate(const csc_graph* g, double lambda_k, int32
   }
   CSC_HIP(launch_col_dot(L, Xi, Xi, part, s));
   CSC_HIP(launch_reduce(part, tiles, k, colnorm2, s));
-  CSC_HIP(launch_labels(L, Xi, colnorm2, labels, X, ldx, s));
+  CSC_HIP(launch_labels(L, Xi, colnorm2, labels, X, ldx, order, s));
   std::vector<int> hit(k);
   std::vector<double> hrel(k);
   int breakdown = 0;

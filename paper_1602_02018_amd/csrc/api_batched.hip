@@ -403,8 +403,8 @@ extern "C" csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, con
   for (int g = 0; g < G; ++g) {
     CSC_REQUIRE(lambda[g] >= 0.0 && lambda[g] <= 2.0, "lambda[g] must lie in [0, 2]");
     CSC_REQUIRE(d[g] >= 1 && ld[g] >= d[g], "need d[g] >= 1 and ld[g] >= d[g]");
-    CSC_REQUIRE(rows[g] && Y[g] && n_rows[g] >= 1 && n_rows[g] <= graphs[g].n,
-                "rows[g] and Y[g] must be non-NULL with 1 <= n_rows[g] <= N_g");
+    CSC_REQUIRE(Y[g] && (rows[g] == nullptr || (n_rows[g] >= 1 && n_rows[g] <= graphs[g].n)),
+                "Y[g] must be non-NULL, and 1 <= n_rows[g] <= N_g when rows[g] is given");
   }
   CSC_TRY(check_ws(ws, ws_bytes, csc_filter_workspace_bytes_batched(graphs, G, d, p)));
   hipStream_t s = as_stream(stream);
@@ -470,8 +470,12 @@ extern "C" csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, con
   CSC_TRY(upload(w_gauss.d, w_gauss.h, s));
   CSC_HIP(launch_fill_i32(bad, G, 0, s));
   for (int g = 0; g < G; ++g) {
-    CSC_HIP(launch_fill_i32(slot[g], graphs[g].n, -1, s));
-    CSC_HIP(launch_slot_map(n_rows[g], rows[g], graphs[g].n, slot[g], bad + g, s));
+    if (rows[g]) {
+      CSC_HIP(launch_fill_i32(slot[g], graphs[g].n, -1, s));
+      CSC_HIP(launch_slot_map(n_rows[g], rows[g], graphs[g].n, slot[g], bad + g, s));
+    } else {
+      CSC_HIP(launch_iota(graphs[g].n, slot[g], s));  // every row, in node order
+    }
   }
   std::vector<int> hbad(G);
   CSC_HIP(hipMemcpyAsync(hbad.data(), bad, G * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -486,7 +490,8 @@ extern "C" csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, con
     CSC_HIP(launch_cheb_step_batched(d_steps + (size_t)m * G, w_step.table(), EPI_YS, m == 0,
                                      m + 1 == p, s));
   if (normalize)
-    for (int g = 0; g < G; ++g) CSC_HIP(launch_normalize_rows(n_rows[g], d[g], Y[g], ld[g], s));
+    for (int g = 0; g < G; ++g)
+      CSC_HIP(launch_normalize_rows(rows[g] ? n_rows[g] : graphs[g].n, d[g], Y[g], ld[g], s));
   return CSC_OK;
 }
 
@@ -498,6 +503,7 @@ extern "C" size_t csc_interpolate_workspace_bytes_batched(const csc_graph* graph
   std::vector<int> u(G), kv(G), u2(G), lu(G);
   for (int g = 0; g < G; ++g) {
     b += max_widths(graphs[g].n, k[g], [](const Layout& L) { return interp_bytes(L); });
+    b += perm_bytes(graphs[g].n, graphs[g].nnz, graphs[g].n);
     u[g] = (int)max_units(graphs[g].n, k[g]);
     kv[g] = k[g];
     u2[g] = (int)((max_elems(graphs[g].n, k[g]) / 4 + kElemsPerUnit - 1) / kElemsPerUnit);
@@ -507,20 +513,22 @@ extern "C" size_t csc_interpolate_workspace_bytes_batched(const csc_graph* graph
 }
 
 extern "C" csc_status csc_interpolate_batched(
-    const csc_graph* graphs, int32_t G, const double* lambda, int32_t p, double gamma,
-    const int32_t* const* idx, const int32_t* const* labels_r, const int32_t* n, const int32_t* k,
+    const csc_graph* graphs, int32_t G, const int32_t* const* order, const double* lambda,
+    int32_t p, double gamma, const int32_t* const* idx_in, const int32_t* const* labels_r,
+    const int32_t* n, const int32_t* k,
     double tol, int32_t max_iter, float* const* X, const int32_t* ldx, int32_t* const* labels,
     int32_t* iters_out, double* relres_out, int32_t* status_out, void* ws, size_t ws_bytes,
     void* stream) {
   clear_error();
   CSC_TRY(check_graphs(graphs, G));
-  CSC_REQUIRE(lambda && idx && labels_r && n && k && labels && status_out,
+  CSC_REQUIRE(lambda && idx_in && labels_r && n && k && labels && status_out,
               "lambda, idx, labels_r, n, k, labels and status_out must be non-NULL");
   CSC_REQUIRE(p >= 1 && gamma > 0.0 && tol > 0.0 && max_iter >= 1,
               "need p >= 1, gamma > 0, tol > 0, max_iter >= 1");
   for (int g = 0; g < G; ++g) {
     const int N = graphs[g].n;
-    CSC_REQUIRE(idx[g] && labels_r[g] && labels[g], "idx[g], labels_r[g], labels[g] must be non-NULL");
+    CSC_REQUIRE(idx_in[g] && labels_r[g] && labels[g],
+                "idx[g], labels_r[g], labels[g] must be non-NULL");
     CSC_REQUIRE(k[g] >= 1 && k[g] <= N && n[g] >= 1 && n[g] <= N,
                 "need 1 <= k[g] <= N_g and 1 <= n[g] <= N_g");
     CSC_REQUIRE(lambda[g] >= 0.0 && lambda[g] <= 2.0, "lambda[g] must lie in [0, 2]");
@@ -590,6 +598,12 @@ extern "C" csc_status csc_interpolate_batched(
     set_error("internal: batched workspace plan overflow");
     return CSC_E_INVALID_ARG;
   }
+  // graphs with a node order run on their permuted copy
+  std::vector<csc_graph> gv(graphs, graphs + G);
+  std::vector<const int32_t*> idx(idx_in, idx_in + G);
+  for (int g = 0; g < G; ++g)
+    if (order && order[g])
+      CSC_TRY(permuted_graph(graphs[g], order[g], idx_in[g], n[g], ar, gv[g], idx[g], s));
 
   // set-up, graph by graph: zero blocks, scatter the right-hand sides, ||b_j||^2
   CSC_HIP(launch_fill_i32(flags, (size_t)G * 4, 0, s));
@@ -649,9 +663,9 @@ extern "C" csc_status csc_interpolate_batched(
       StepArgs& x = h_steps[(size_t)m * G + g];
       x.L = b.L;
       x.tiles = b.tiles;
-      x.row_ptr = graphs[g].row_ptr;
-      x.col = graphs[g].col;
-      x.val = graphs[g].val;
+      x.row_ptr = gv[g].row_ptr;
+      x.col = gv[g].col;
+      x.val = gv[g].val;
       x.T0 = b.P;
       x.Y = b.AP;
       x.mask = b.mask;
@@ -736,7 +750,7 @@ extern "C" csc_status csc_interpolate_batched(
     h_cd[g] = ColDotItem{b.L, b.tiles, b.Xi, b.Xi, b.part, nullptr};
     h_cn[g] = ReduceItem{b.part, b.tiles, b.colnorm2, nullptr};
     h_lab[g] = LabelItem{b.L, b.Xi, b.colnorm2, labels[g], X ? X[g] : nullptr,
-                         (X && X[g]) ? ldx[g] : 0};
+                         (X && X[g]) ? ldx[g] : 0, order ? order[g] : nullptr};
   }
   CSC_TRY(upload(d_cd, h_cd, s));
   CSC_TRY(upload(d_red_pap, h_cn, s));

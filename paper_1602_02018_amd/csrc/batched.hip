@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void kb_labels(const LabelItem* items, cons
   const LabelItem it = items[w.item];
   for (int u = w.u0; u < w.u0 + w.cnt; ++u) {
     const int i = u * kBlock + threadIdx.x;
-    if (i < it.L.n) labels_row(it.L, it.X, it.colnorm2, it.labels, it.Xout, it.ldx, i);
+    if (i < it.L.n) labels_row(it.L, it.X, it.colnorm2, it.labels, it.Xout, it.ldx, it.out_map, i);
   }
 }
 

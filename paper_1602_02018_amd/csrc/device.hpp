@@ -61,13 +61,35 @@ __device__ inline double dot4v(v4f a, v4f b) {
 }
 
 // Workgroups are handed to the 8 XCDs round-robin (workgroup b runs on XCD
-// b mod 8).  With xcd mapping on, XCD x processes a contiguous range of the
-// panel-major work units, so each XCD's L2 sees the gathered rows of one
-// panel at a time instead of all panels at once.
-__device__ inline int work_unit(int b, int U, int xcd) {
+// b mod 8).  Orders of the U = P * T panel-major work units (P panels of T
+// row tiles):
+//   0  unit b: consecutive workgroups on different XCDs;
+//   1  XCD x takes the x-th contiguous eighth of the units, so with several
+//      panels each XCD's L2 sees the gathered rows of one panel;
+//   2  the units are re-listed slab-major (row slab s = the s-th eighth of
+//      the tiles, then panel, then tile) before the split of order 1: every
+//      XCD keeps one row slab and all XCDs walk the panels in step, so only
+//      one panel's gathered rows are live at a time.
+// Each order is a bijection of [0, U).
+__device__ inline int work_unit(int b, int U, int T, int xcd) {
   if (!xcd) return b;
   const int x = b & 7, j = b >> 3, q = U >> 3, r = U & 7;
-  return x * q + (x < r ? x : r) + j;
+  const int v = x * q + (x < r ? x : r) + j;
+  if (xcd == 1) return v;
+  const int P = U / T, tq = T >> 3, tr = T & 7;
+  const int big = P * (tq + 1);  // units of a slab with tq + 1 tiles
+  int s, start, ts;
+  if (v < big * tr) {
+    s = v / big;
+    start = s * big;
+    ts = tq + 1;
+  } else {  // tq >= 1 here: slabs with tq + 1 tiles hold every unit when tq == 0
+    s = tr + (v - big * tr) / (P * tq);
+    start = big * tr + (s - tr) * P * tq;
+    ts = tq;
+  }
+  const int off = v - start, panel = off / ts;
+  return panel * T + s * tq + (s < tr ? s : tr) + (off - panel * ts);
 }
 
 // Lanes of a wave walk rows of a panel: a row takes lpr = PW/4 lanes (one
@@ -366,15 +388,17 @@ __device__ inline void cg_update2_elem(const Layout& L, const float* R, float* P
 
 // labels[i] = argmax_c X(i, c) / ||X_c|| (ties and zero columns -> lowest c);
 // also copies row i to the node-major output when Xout is given.
+// Row i of the layout is node out_map[i] of the caller (out_map NULL: node i).
 __device__ inline void labels_row(const Layout& L, const float* X, const double* colnorm2,
-                                  int* labels, float* Xout, int ldx, int i) {
+                                  int* labels, float* Xout, int ldx, const int* out_map, int i) {
   const size_t pe = L.panel_elems();
+  const int o = out_map ? out_map[i] : i;
   double best = 0.0;
   int arg = 0;
   bool found = false;
   for (int c = 0; c < L.w; ++c) {
     const float x = X[(size_t)(c / L.pw) * pe + (size_t)i * L.pw + c % L.pw];
-    if (Xout) Xout[(size_t)i * ldx + c] = x;
+    if (Xout) Xout[(size_t)o * ldx + c] = x;
     const double n2 = colnorm2[c];
     if (n2 > 0.0) {
       const double v = (double)x / sqrt(n2);
@@ -385,7 +409,7 @@ __device__ inline void labels_row(const Layout& L, const float* X, const double*
       }
     }
   }
-  labels[i] = arg;
+  labels[o] = arg;
 }
 
 }  // namespace dev

@@ -16,6 +16,13 @@ size_t count_bytes(const Layout& L, int p);
 size_t interp_bytes(const Layout& L);
 int use_hip_graphs();
 
+// Workspace of permuted_graph, and the graph g permuted to `order` (row r =
+// node order[r], neighbours relabelled and kept in CSR order) with the sampled
+// indices renumbered, carved from ar; synchronises s to check `order`.
+size_t perm_bytes(int N, int64_t nnz, int n);
+csc_status permuted_graph(const csc_graph& g, const int* order, const int* idx, int n, Arena& ar,
+                          csc_graph& gp, const int*& idxp, hipStream_t s);
+
 // Learned dichotomy (mlp.hip): the bracket from the network outputs y for a
 // graph whose first pass at lambda = 1 gave count c1 and moments mom, and the
 // update after each later count (true once the count rounds to k).

@@ -20,7 +20,7 @@ using namespace dev;
 
 template <int EPI, bool FIRST, bool LAST>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(StepArgs a) {
-  cheb_unit<EPI, FIRST, LAST>(a, work_unit(blockIdx.x, a.L.np * a.tiles, a.xcd));
+  cheb_unit<EPI, FIRST, LAST>(a, work_unit(blockIdx.x, a.L.np * a.tiles, a.tiles, a.xcd));
 }
 
 hipError_t launch_step(const StepArgs& a, int epi, bool first, bool last, hipStream_t s) {
@@ -288,9 +288,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_update2(Layout L, const float* R,
 }
 
 __global__ void k_labels(Layout L, const float* X, const double* colnorm2, int* labels,
-                         float* Xout, int ldx) {
+                         float* Xout, int ldx, const int* out_map) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < L.n) labels_row(L, X, colnorm2, labels, Xout, ldx, i);
+  if (i < L.n) labels_row(L, X, colnorm2, labels, Xout, ldx, out_map, i);
 }
 
 inline unsigned grid_for(size_t n, size_t per = kBlock, size_t cap = 65536) {
@@ -469,9 +469,9 @@ hipError_t launch_cg_update2(const Layout& L, const float* R, float* P, const do
 }
 
 hipError_t launch_labels(const Layout& L, const float* X, const double* colnorm2, int* labels,
-                         float* Xout, int ldx, hipStream_t s) {
+                         float* Xout, int ldx, const int* out_map, hipStream_t s) {
   hipLaunchKernelGGL(k_labels, dim3(grid_for(L.n, kBlock, 1u << 30)), dim3(kBlock), 0, s, L, X,
-                     colnorm2, labels, Xout, ldx);
+                     colnorm2, labels, Xout, ldx, out_map);
   return hipGetLastError();
 }
 

@@ -110,6 +110,7 @@ struct LabelItem {
   int* labels = nullptr;
   float* Xout = nullptr;
   int ldx = 0;
+  const int* out_map = nullptr;  // layout row i is node out_map[i] (NULL: i)
 };
 
 hipError_t launch_cheb_step_batched(const StepArgs* items, BTable t, int epi, bool first,
@@ -194,6 +195,24 @@ hipError_t launch_cg_scalar(int k, const double* rrn, double* rr, const double* 
 hipError_t launch_cg_update2(const Layout& L, const float* R, float* P, const double* beta,
                              const int* active, hipStream_t s);
 hipError_t launch_labels(const Layout& L, const float* X, const double* colnorm2, int* labels,
-                         float* Xout, int ldx, hipStream_t s);
+                         float* Xout, int ldx, const int* out_map, hipStream_t s);
+
+// Node orders (order.hip).  order[r] = node placed at position r.
+hipError_t launch_perm_inverse(int N, const int* order, int* inv, int* bad, hipStream_t s);
+hipError_t launch_perm_check(int N, const int* inv, int* bad, hipStream_t s);
+size_t perm_graph_temp_bytes(int N);
+hipError_t perm_graph(int N, const int* order, const int* inv, const int* row_ptr, const int* col,
+                      const float* val, int* row_ptr_out, int* col_out, float* val_out, int* deg,
+                      void* temp, size_t temp_bytes, hipStream_t s);
+hipError_t launch_map_indices(int n, int N, const int* inv, const int* idx, int* out,
+                              hipStream_t s);
+hipError_t launch_gather_rows(int n, int d, const float* F, size_t ldf, const int* rows, int N,
+                              float* out, int ldo, int* bad, hipStream_t s);
+hipError_t launch_nearest_centroid(int N, int d, const float* F, size_t ldf, const float* C,
+                                   const int* usable, int k, int* labels, hipStream_t s);
+size_t sort_labels_temp_bytes(int N);
+hipError_t sort_labels(void* temp, size_t temp_bytes, const int* kin, int* kout, const int* vin,
+                       int* vout, int N, int key_bits, hipStream_t s);
+hipError_t launch_iota(int N, int* out, hipStream_t s);
 
 }  // namespace csc

@@ -1,0 +1,340 @@
+// Node orders for locality of the gathered rows.
+//
+// A Chebyshev step gathers, for every node, the rows of its neighbours.  On a
+// graph with communities listed in random order those rows are scattered over
+// the whole block, and most gathers miss the L2 of the XCD that runs them.
+// Listing the nodes community by community puts most neighbours of a node
+// (all of them on a disconnected graph, Sec. 3.2.1) within the row range the
+// same XCD is walking, so the gathers hit its L2.  The paper fixes no node
+// order; this is a memory-layout choice and changes no result beyond the
+// rounding order of float64 sums over rows.
+//
+// csc_community_order labels every node with the nearest centroid of the
+// sampled, clustered features (the centroids of Alg. 2 step 6) and lists the
+// nodes by that label, ties in index order.  csc_interpolate can run its CG on
+// the graph permuted to such an order and writes its outputs back in the
+// caller's order.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "host.hpp"
+
+namespace csc {
+namespace {
+
+constexpr int kBlk = 256;
+constexpr int kLdsFloats = 12288;  // 48 KB of centroids per chunk
+
+inline unsigned blocks_for(size_t n, size_t per) {
+  size_t g = (n + per - 1) / per;
+  return (unsigned)std::min<size_t>(std::max<size_t>(g, 1), 1u << 20);
+}
+
+__global__ void k_perm_inverse(int N, const int* order, int* inv, int* bad) {
+  for (size_t r = blockIdx.x * (size_t)blockDim.x + threadIdx.x; r < (size_t)N;
+       r += (size_t)gridDim.x * blockDim.x) {
+    const int o = order[r];
+    if (o < 0 || o >= N)
+      atomicOr(bad, 1);
+    else
+      inv[o] = (int)r;
+  }
+}
+
+__global__ void k_perm_check(int N, const int* inv, int* bad) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)N;
+       i += (size_t)gridDim.x * blockDim.x)
+    if (inv[i] < 0) atomicOr(bad, 1);
+}
+
+__global__ void k_perm_degrees(int N, const int* order, const int* row_ptr, int* deg,
+                               int* row_ptr_out) {
+  for (size_t r = blockIdx.x * (size_t)blockDim.x + threadIdx.x; r < (size_t)N;
+       r += (size_t)gridDim.x * blockDim.x) {
+    const int o = order[r];
+    deg[r] = row_ptr[o + 1] - row_ptr[o];
+    if (r == 0) row_ptr_out[0] = 0;
+  }
+}
+
+// One wave per permuted row: the neighbours keep their CSR order, relabelled.
+__global__ __launch_bounds__(kBlk) void k_perm_rows(int N, const int* order, const int* inv,
+                                                    const int* row_ptr, const int* col,
+                                                    const float* val, const int* row_ptr_out,
+                                                    int* col_out, float* val_out) {
+  const int lane = threadIdx.x & 63;
+  const size_t waves = (size_t)gridDim.x * (kBlk / 64);
+  for (size_t r = blockIdx.x * (size_t)(kBlk / 64) + (threadIdx.x >> 6); r < (size_t)N;
+       r += waves) {
+    const int o = order[r];
+    const int src = row_ptr[o], len = row_ptr[o + 1] - src, dst = row_ptr_out[r];
+    for (int e = lane; e < len; e += 64) {
+      col_out[dst + e] = inv[col[src + e]];
+      val_out[dst + e] = val[src + e];
+    }
+  }
+}
+
+// An index outside [0, N) maps to -1, which the consumer's own range check
+// reports.
+__global__ void k_map_indices(int n, int N, const int* inv, const int* idx, int* out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) {
+    const int i = idx[s];
+    out[s] = (i >= 0 && i < N) ? inv[i] : -1;
+  }
+}
+
+__global__ void k_gather_rows(int n, int d, const float* F, size_t ldf, const int* rows, int N,
+                              float* out, int ldo, int* bad) {
+  const size_t total = (size_t)n * d;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int s = (int)(e / d), j = (int)(e - (size_t)s * d);
+    const int i = rows[s];
+    if (i < 0 || i >= N) {
+      if (j == 0) atomicOr(bad, 1);
+      continue;
+    }
+    out[(size_t)s * ldo + j] = F[(size_t)i * ldf + j];
+  }
+}
+
+__global__ void k_iota(int N, int* out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)N;
+       i += (size_t)gridDim.x * blockDim.x)
+    out[i] = (int)i;
+}
+
+// Nearest usable centroid of every row of F (squared Euclidean distance,
+// coordinates summed in order, ties to the lowest index).  A thread keeps its
+// row in registers; centroids are staged through LDS in chunks.
+template <int DMAX>
+__global__ __launch_bounds__(kBlk) void k_nearest_centroid(int N, int d, const float* F,
+                                                           size_t ldf, const float* C,
+                                                           const int* usable, int k,
+                                                           int* labels) {
+  __shared__ float cs[kLdsFloats];
+  const int i = blockIdx.x * kBlk + threadIdx.x;
+  const bool row = i < N;
+  float f[DMAX];
+#pragma unroll
+  for (int j = 0; j < DMAX; ++j) f[j] = (row && j < d) ? F[(size_t)i * ldf + j] : 0.f;
+  const int kc = kLdsFloats / d;
+  float best = 0.f;
+  int arg = 0;
+  bool found = false;
+  for (int c0 = 0; c0 < k; c0 += kc) {
+    const int nc = min(kc, k - c0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nc * d; e += kBlk) cs[e] = C[(size_t)c0 * d + e];
+    __syncthreads();
+    if (row) {
+      for (int c = 0; c < nc; ++c) {
+        if (!usable[c0 + c]) continue;
+        const float* cc = cs + c * d;
+        float dist = 0.f;
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j)
+          if (j < d) {
+            const float t = f[j] - cc[j];
+            dist = fmaf(t, t, dist);
+          }
+        if (!found || dist < best) {
+          best = dist;
+          arg = c0 + c;
+          found = true;
+        }
+      }
+    }
+  }
+  if (row) labels[i] = arg;
+}
+
+}  // namespace
+
+hipError_t launch_perm_inverse(int N, const int* order, int* inv, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_perm_inverse, dim3(blocks_for(N, kBlk)), dim3(kBlk), 0, s, N, order, inv,
+                     bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_perm_check(int N, const int* inv, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_perm_check, dim3(blocks_for(N, kBlk)), dim3(kBlk), 0, s, N, inv, bad);
+  return hipGetLastError();
+}
+
+size_t perm_graph_temp_bytes(int N) {
+  size_t bytes = 0;
+  hipcub::DeviceScan::InclusiveSum(nullptr, bytes, (const int*)nullptr, (int*)nullptr, N);
+  return bytes;
+}
+
+hipError_t perm_graph(int N, const int* order, const int* inv, const int* row_ptr, const int* col,
+                      const float* val, int* row_ptr_out, int* col_out, float* val_out, int* deg,
+                      void* temp, size_t temp_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_perm_degrees, dim3(blocks_for(N, kBlk)), dim3(kBlk), 0, s, N, order,
+                     row_ptr, deg, row_ptr_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipcub::DeviceScan::InclusiveSum(temp, temp_bytes, deg, row_ptr_out + 1, N, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_perm_rows, dim3(blocks_for(N, kBlk / 64)), dim3(kBlk), 0, s, N, order, inv,
+                     row_ptr, col, val, row_ptr_out, col_out, val_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_indices(int n, int N, const int* inv, const int* idx, int* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_map_indices, dim3((n + kBlk - 1) / kBlk), dim3(kBlk), 0, s, n, N, inv, idx,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(int n, int d, const float* F, size_t ldf, const int* rows, int N,
+                              float* out, int ldo, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_rows, dim3(blocks_for((size_t)n * d, kBlk)), dim3(kBlk), 0, s, n, d,
+                     F, ldf, rows, N, out, ldo, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_nearest_centroid(int N, int d, const float* F, size_t ldf, const float* C,
+                                   const int* usable, int k, int* labels, hipStream_t s) {
+  const dim3 grid((unsigned)((N + kBlk - 1) / kBlk)), block(kBlk);
+  if (d <= 32)
+    hipLaunchKernelGGL(k_nearest_centroid<32>, grid, block, 0, s, N, d, F, ldf, C, usable, k,
+                       labels);
+  else if (d <= 64)
+    hipLaunchKernelGGL(k_nearest_centroid<64>, grid, block, 0, s, N, d, F, ldf, C, usable, k,
+                       labels);
+  else
+    hipLaunchKernelGGL(k_nearest_centroid<128>, grid, block, 0, s, N, d, F, ldf, C, usable, k,
+                       labels);
+  return hipGetLastError();
+}
+
+size_t sort_labels_temp_bytes(int N) {
+  size_t bytes = 0;
+  hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const unsigned*)nullptr, (unsigned*)nullptr,
+                                     (const int*)nullptr, (int*)nullptr, N);
+  return bytes;
+}
+
+hipError_t sort_labels(void* temp, size_t temp_bytes, const int* kin, int* kout, const int* vin,
+                       int* vout, int N, int key_bits, hipStream_t s) {
+  // LSD radix sort: stable, so equal labels keep their index order
+  return hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, (const unsigned*)kin,
+                                            (unsigned*)kout, vin, vout, N, 0, key_bits, s);
+}
+
+hipError_t launch_iota(int N, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota, dim3(blocks_for(N, kBlk)), dim3(kBlk), 0, s, N, out);
+  return hipGetLastError();
+}
+
+}  // namespace csc
+
+using namespace csc;
+
+extern "C" csc_status csc_gather_rows(const float* F, int64_t ldf, int32_t N, int32_t d,
+                                      const int32_t* rows, int32_t n, float* out, int32_t ldo,
+                                      void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  CSC_REQUIRE(N >= 1 && d >= 1 && ldf >= d && n >= 0 && ldo >= d,
+              "need N >= 1, d >= 1, ldf >= d, n >= 0 and ldo >= d");
+  CSC_REQUIRE(F && (rows || n == 0) && (out || n == 0), "F, rows and out must be non-NULL");
+  CSC_TRY(check_ws(ws, ws_bytes, 256));
+  if (n == 0) return CSC_OK;
+  hipStream_t s = as_stream(stream);
+  int* bad = static_cast<int*>(ws);
+  CSC_HIP(launch_fill_i32(bad, 1, 0, s));
+  CSC_HIP(launch_gather_rows(n, d, F, (size_t)ldf, rows, N, out, ldo, bad, s));
+  int hbad = 0;
+  CSC_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  CSC_REQUIRE(!hbad, "rows holds an index outside [0, N)");
+  return CSC_OK;
+}
+
+namespace {
+size_t order_bytes(int N, int d, int k, int n) {
+  size_t b = align_up((size_t)n * d * sizeof(float));         // sampled rows
+  b += align_up((size_t)k * d * sizeof(float));               // centroids
+  b += align_up((size_t)k * sizeof(int));                     // usable
+  b += 4 * align_up((size_t)N * sizeof(int));                 // labels, sorted labels, iota, out
+  b += align_up(sort_labels_temp_bytes(N)) + align_up(4 * sizeof(int));
+  return b + 256;
+}
+}  // namespace
+
+extern "C" size_t csc_community_order_workspace_bytes(int32_t N, int32_t d, int32_t k,
+                                                      int32_t n) {
+  if (N < 1 || d < 1 || k < 1 || n < 1) return 0;
+  return order_bytes(N, d, k, n);
+}
+
+extern "C" csc_status csc_community_order(int32_t N, const float* F, int64_t ldf, int32_t d,
+                                          const int32_t* idx, const int32_t* labels_r,
+                                          int32_t n, int32_t k, int32_t* order,
+                                          int32_t* node_labels, void* ws, size_t ws_bytes,
+                                          void* stream) {
+  clear_error();
+  CSC_REQUIRE(N >= 1 && d >= 1 && d <= 128 && ldf >= d, "need N >= 1, 1 <= d <= 128, ldf >= d");
+  CSC_REQUIRE(k >= 1 && n >= 1 && n <= N, "need k >= 1 and 1 <= n <= N");
+  CSC_REQUIRE(F && idx && labels_r && order, "F, idx, labels_r and order must be non-NULL");
+  for (int s = 0; s < n; ++s)
+    CSC_REQUIRE(labels_r[s] >= 0 && labels_r[s] < k, "labels_r holds a value outside [0, k)");
+  CSC_TRY(check_ws(ws, ws_bytes, order_bytes(N, d, k, n)));
+  hipStream_t s = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  float* Fs = ar.take<float>((size_t)n * d);
+  float* C = ar.take<float>((size_t)k * d);
+  int* usable = ar.take<int>(k);
+  int* lab = ar.take<int>(N);
+  int* lab_sorted = ar.take<int>(N);
+  int* iota = ar.take<int>(N);
+  int* out = ar.take<int>(N);
+  const size_t temp_bytes = sort_labels_temp_bytes(N);
+  void* temp = ar.take<char>(temp_bytes);
+  int* bad = ar.take<int>(4);
+
+  // centroids of the clustered sampled rows, summed in sample order in float64
+  CSC_HIP(launch_fill_i32(bad, 1, 0, s));
+  CSC_HIP(launch_gather_rows(n, d, F, (size_t)ldf, idx, N, Fs, d, bad, s));
+  std::vector<float> hF((size_t)n * d);
+  int hbad = 0;
+  CSC_HIP(hipMemcpyAsync(hF.data(), Fs, hF.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  CSC_REQUIRE(!hbad, "idx holds an index outside [0, N)");
+  std::vector<double> sum((size_t)k * d, 0.0);
+  std::vector<int> cnt(k, 0);
+  for (int r = 0; r < n; ++r) {
+    const int c = labels_r[r];
+    ++cnt[c];
+    for (int j = 0; j < d; ++j) sum[(size_t)c * d + j] += (double)hF[(size_t)r * d + j];
+  }
+  std::vector<float> hC((size_t)k * d, 0.f);
+  for (int c = 0; c < k; ++c)
+    if (cnt[c] > 0)
+      for (int j = 0; j < d; ++j) hC[(size_t)c * d + j] = (float)(sum[(size_t)c * d + j] / cnt[c]);
+  std::vector<int> hu(k);
+  for (int c = 0; c < k; ++c) hu[c] = cnt[c] > 0 ? 1 : 0;
+  CSC_HIP(hipMemcpyAsync(C, hC.data(), hC.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  CSC_HIP(hipMemcpyAsync(usable, hu.data(), k * sizeof(int), hipMemcpyHostToDevice, s));
+
+  CSC_HIP(launch_nearest_centroid(N, d, F, (size_t)ldf, C, usable, k, lab, s));
+  CSC_HIP(launch_iota(N, iota, s));
+  int bits = 1;
+  while (bits < 31 && (1 << bits) < k) ++bits;
+  CSC_HIP(sort_labels(temp, temp_bytes, lab, lab_sorted, iota, out, N, bits, s));
+  CSC_HIP(hipMemcpyAsync(order, out, (size_t)N * sizeof(int), hipMemcpyDeviceToDevice, s));
+  if (node_labels)
+    CSC_HIP(hipMemcpyAsync(node_labels, lab, (size_t)N * sizeof(int), hipMemcpyDeviceToDevice, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  return CSC_OK;
+}

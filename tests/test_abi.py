@@ -70,8 +70,20 @@ def test_argument_errors_are_reported_without_gpu_work():
     st = C.c_int32()
     assert lib.csc_estimate_lambda_k(C.byref(g), 11, 50, 4, 0, 30, None, C.byref(lam), C.byref(st),
                                      None, None, None, 0, None) == _lib.CSC_E_INVALID_ARG
-    assert lib.csc_interpolate(C.byref(g), 0.5, 50, 0.0, C.c_void_p(16), C.c_void_p(16), 2, 2, 1e-6,
-                               10, None, 2, C.c_void_p(16), None, None, None, 0, None) == _lib.CSC_E_INVALID_ARG
+    assert lib.csc_interpolate(C.byref(g), None, 0.5, 50, 0.0, C.c_void_p(16), C.c_void_p(16), 2, 2,
+                               1e-6, 10, None, 2, C.c_void_p(16), None, None, None, 0,
+                               None) == _lib.CSC_E_INVALID_ARG
+    # community order: d above the register-resident limit, labels outside [0, k)
+    lab = (C.c_int32 * 3)(0, 1, 2)
+    assert lib.csc_community_order(10, C.c_void_p(16), 200, 200, C.c_void_p(16), lab, 3, 3,
+                                   C.c_void_p(16), None, None, 0, None) == _lib.CSC_E_INVALID_ARG
+    assert b"d <= 128" in lib.csc_last_error()
+    assert lib.csc_community_order(10, C.c_void_p(16), 8, 8, C.c_void_p(16), lab, 3, 2,
+                                   C.c_void_p(16), None, None, 0, None) == _lib.CSC_E_INVALID_ARG
+    assert b"labels_r" in lib.csc_last_error()
+    assert lib.csc_gather_rows(C.c_void_p(16), 4, 10, 8, C.c_void_p(16), 2, C.c_void_p(16), 8,
+                               None, 0, None) == _lib.CSC_E_INVALID_ARG
+    assert b"ldf" in lib.csc_last_error()
 
 
 def test_workspace_sizes_grow_with_problem():
@@ -81,7 +93,8 @@ def test_workspace_sizes_grow_with_problem():
     assert 0 < a < b
     assert lib.csc_filter_workspace_bytes(0, 4) == 0
     assert lib.csc_estimate_workspace_bytes(1000, 14, 50) > 3 * 1000 * 14 * 4
-    assert lib.csc_interpolate_workspace_bytes(1000, 10, 47) > 6 * 1000 * 10 * 4
+    assert lib.csc_interpolate_workspace_bytes(1000, 16000, 10, 47) > 6 * 1000 * 10 * 4 + 8 * 16000
+    assert lib.csc_community_order_workspace_bytes(1000, 28, 10, 47) > 4 * 1000 * 4
     assert lib.csc_sample_workspace_bytes(1000, 47) > 1000 * 24
 
 

@@ -88,6 +88,16 @@ def test_sbm_1e5_sampling_and_interpolation(api, sbm1e5):
         assert np.linalg.norm(r) / np.linalg.norm(B[:, c]) <= 1e-4
     res2 = api.interpolate(g, lam, 50, 1e-3, omega, lab_r, k)
     assert torch.equal(res.labels, res2.labels) and torch.equal(res.X, res2.X)
+    # the same solve on the graph in community order (the benchmarked launch)
+    F_all = api.filter(g, lam, 50, d, 0, rows=None)
+    assert torch.equal(api.gather_rows(F_all, omega), F)
+    order = api.community_order(F_all, omega, lab_r, k)
+    res3 = api.interpolate(g, lam, 50, 1e-3, omega, lab_r, k, order=order)
+    assert res3.status == 0 and np.all(res3.relres <= 1e-6)
+    X3 = res3.X.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(X3 - X) <= 1e-5 * np.linalg.norm(X)
+    agree = float((res3.labels == res.labels).float().mean())
+    assert agree >= 0.999, agree
 
 
 @pytest.mark.slow

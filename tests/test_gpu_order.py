@@ -1,0 +1,187 @@
+"""Community node order, a memory layout for the interpolation.
+
+* the all-rows feature pass gives the sampled features bit for bit (so the
+  k-means sees the same input with and without the order);
+* the order is the stable sort of every node's nearest-centroid label, the
+  labels agree with a float64 host computation wherever the two nearest
+  centroids are not tied within float32 rounding;
+* the CG on the permuted graph gives the natural-order result: per-element
+  products are identical, only the float64 column sums run in another row
+  order, so X agrees to float32 rounding and the labels are the same;
+* the batched forms match the single ones bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import interp, metrics, sampling
+from oracle import laplacian
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1602_02018_amd import api as a
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    yield a
+    a.set_panel_width(0)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return synth.sbm_config(1000, 10, seed=0)
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    g = synth.chung_lu_blocks(1037, 7, mean_deg=6.0, max_deg=80.0, seed=2)
+    assert (g.degrees() == 0).any()
+    return g
+
+
+def _features(api, gr, g, lam, k, n, seed):
+    d = int(math.ceil(4 * math.log(gr.n)))
+    omega = api.sample(gr.n, n, seed)
+    F_all = api.filter(g, lam, 50, d, seed, rows=None)
+    F = api.gather_rows(F_all, omega)
+    lab_r, _ = api.kmeans_reduced(F.cpu().numpy(), k, seed, replicates=5)
+    return omega, F_all, F, lab_r
+
+
+def test_all_rows_then_gather_equals_sampled_rows(api, ragged):
+    g = api.Graph(ragged.row_ptr, ragged.col)
+    omega = sampling.sample(ragged.n, 97, 4)
+    F_all = api.filter(g, 0.5, 50, 13, 9, rows=None)
+    F_s = api.filter(g, 0.5, 50, 13, 9, rows=omega)
+    assert torch.equal(api.gather_rows(F_all, omega), F_s)
+
+
+def test_gather_rejects_out_of_range_rows(api):
+    F = torch.zeros((10, 4), device="cuda")
+    with pytest.raises(RuntimeError, match="outside"):
+        api.gather_rows(F, np.array([0, 10], np.int32))
+
+
+@pytest.mark.parametrize("which", ["cfg1", "ragged"])
+def test_order_is_stable_sort_of_nearest_centroid(api, cfg1, ragged, which):
+    gr = cfg1 if which == "cfg1" else ragged
+    k = 10 if which == "cfg1" else 7
+    g = api.Graph(gr.row_ptr, gr.col)
+    omega, F_all, F, lab_r = _features(api, gr, g, 0.45, k, api.default_n(k), 0)
+    order, nl = api.community_order(F_all, omega, lab_r, k, want_labels=True)
+    order, nl = order.cpu().numpy(), nl.cpu().numpy()
+    assert np.array_equal(np.sort(order), np.arange(gr.n))
+    assert np.array_equal(order, np.argsort(nl, kind="stable"))
+    # nearest centroid in float64 on the host
+    Fh = F.cpu().numpy().astype(np.float64)
+    C = np.zeros((k, Fh.shape[1]))
+    cnt = np.bincount(lab_r, minlength=k)
+    for c in range(k):
+        if cnt[c]:
+            C[c] = Fh[lab_r == c].mean(axis=0)
+    C = C.astype(np.float32).astype(np.float64)
+    Fa = F_all.cpu().numpy().astype(np.float64)
+    D = ((Fa[:, None, :] - C[None, :, :]) ** 2).sum(axis=2)
+    D[:, cnt == 0] = np.inf
+    srt = np.sort(D, axis=1)
+    clear = srt[:, 1] - srt[:, 0] > 1e-5 * (1 + srt[:, 0])
+    assert clear.mean() > 0.95
+    assert np.array_equal(nl[clear], np.argmin(D, axis=1)[clear])
+    if which == "cfg1":
+        assert metrics.adjusted_rand_index(nl, gr.truth) > 0.7  # community structure, not accuracy
+
+
+def test_empty_cluster_gets_no_node(api, cfg1):
+    g = api.Graph(cfg1.row_ptr, cfg1.col)
+    omega, F_all, F, _ = _features(api, cfg1, g, 0.45, 10, 47, 1)
+    lab_r = np.where(np.arange(47) % 2 == 0, 0, 2).astype(np.int32)
+    _, nl = api.community_order(F_all, omega, lab_r, 3, want_labels=True)
+    assert set(np.unique(nl.cpu().numpy())) <= {0, 2}
+
+
+@pytest.mark.parametrize("pw", [0, 8, 100])
+@pytest.mark.parametrize("kind", ["community", "random"])
+def test_interpolation_with_order_matches_natural_order(api, cfg1, pw, kind):
+    api.set_panel_width(pw)
+    try:
+        g = api.Graph(cfg1.row_ptr, cfg1.col)
+        k, lam = 10, 0.46875
+        omega, F_all, F, lab_r = _features(api, cfg1, g, lam, k, 47, 0)
+        if kind == "community":
+            order = api.community_order(F_all, omega, lab_r, k)
+        else:
+            order = torch.as_tensor(np.random.default_rng(3).permutation(cfg1.n).astype(np.int32),
+                                    device="cuda")
+        a = api.interpolate(g, lam, 50, 1e-3, omega, lab_r, k)
+        b = api.interpolate(g, lam, 50, 1e-3, omega, lab_r, k, order=order)
+        assert a.status == 0 and b.status == 0
+        assert np.all(np.abs(a.iters - b.iters) <= 1)
+        assert np.all(b.relres <= 1e-6)
+        Xa, Xb = a.X.cpu().numpy(), b.X.cpu().numpy()
+        assert np.linalg.norm(Xa - Xb) <= 1e-5 * np.linalg.norm(Xa)
+        assert metrics.adjusted_rand_index(a.labels.cpu().numpy(), b.labels.cpu().numpy()) >= 0.999
+        # the permuted solve against the float64 oracle (true residual)
+        A = laplacian.normalized_adjacency(cfg1.row_ptr, cfg1.col)[0]
+        omega_h = omega.cpu().numpy()
+        X, lab, _, _ = interp.interpolate(A, lam, 50, 1e-3, omega_h, lab_r, k, tol=1e-6)
+        assert np.linalg.norm(Xb - X) <= 1e-3 * np.linalg.norm(X)
+        assert metrics.adjusted_rand_index(b.labels.cpu().numpy(), lab) >= 0.99
+    finally:
+        api.set_panel_width(0)
+
+
+def test_order_that_is_not_a_permutation_is_rejected(api, cfg1):
+    g = api.Graph(cfg1.row_ptr, cfg1.col)
+    omega = api.sample(cfg1.n, 47, 0)
+    bad = np.arange(cfg1.n, dtype=np.int32)
+    bad[5] = 6
+    with pytest.raises(RuntimeError, match="permutation"):
+        api.interpolate(g, 0.45, 50, 1e-3, omega, np.arange(47) % 10, 10, order=bad)
+    bad[5] = cfg1.n
+    with pytest.raises(RuntimeError, match="permutation"):
+        api.interpolate(g, 0.45, 50, 1e-3, omega, np.arange(47) % 10, 10, order=bad)
+
+
+def test_batched_all_rows_filter_and_ordered_interpolation_match_single(api, cfg1, ragged):
+    batch = [cfg1, ragged, synth.sbm_config(3000, 12, seed=4)]
+    G = [api.Graph(b.row_ptr, b.col) for b in batch]
+    ks = [10, 7, 12]
+    ds = [int(math.ceil(4 * math.log(b.n))) for b in batch]
+    lams = [0.45, 0.5, 0.4]
+    seeds = [0, 1, 2]
+    F_all = api.filter_batched(G, lams, 50, ds, seeds, [None, None, None])
+    omegas, labs, orders = [], [], []
+    for i, g in enumerate(G):
+        ref = api.filter(g, lams[i], 50, ds[i], seeds[i], rows=None)
+        assert torch.equal(F_all[i], ref)
+        n = api.default_n(ks[i])
+        omegas.append(api.sample(g.n, n, seeds[i]))
+        lab, _ = api.kmeans_reduced(api.gather_rows(ref, omegas[i]).cpu().numpy(), ks[i], seeds[i],
+                                    replicates=3)
+        labs.append(lab)
+        orders.append(api.community_order(ref, omegas[i], lab, ks[i]) if i != 1 else None)
+    res = api.interpolate_batched(G, lams, 50, 1e-3, omegas, labs, ks, orders=orders)
+    for i, g in enumerate(G):
+        one = api.interpolate(g, lams[i], 50, 1e-3, omegas[i], labs[i], ks[i], order=orders[i])
+        assert torch.equal(res[i].labels, one.labels)
+        assert torch.equal(res[i].X, one.X)
+        assert np.array_equal(res[i].iters, one.iters)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_run_with_and_without_order(api, cfg1, seed):
+    d = int(math.ceil(4 * math.log(cfg1.n)))
+    g = api.Graph(cfg1.row_ptr, cfg1.col)
+    a = api.run(g, 10, d, seed, reorder=False)
+    b = api.run(g, 10, d, seed, reorder=True)
+    assert a.lam == b.lam
+    assert torch.equal(a.omega, b.omega)
+    assert torch.equal(a.features, b.features)
+    assert np.array_equal(a.labels_r, b.labels_r)
+    assert metrics.adjusted_rand_index(a.labels.cpu().numpy(), b.labels.cpu().numpy()) >= 0.99
+    assert metrics.adjusted_rand_index(b.labels.cpu().numpy(), cfg1.truth) > 0.9

@@ -346,7 +346,7 @@ def test_determinism(api, ragged):
     assert c1 == c2 and np.array_equal(m1, m2)
 
 
-@pytest.mark.parametrize("xcd", [0, 1])
+@pytest.mark.parametrize("xcd", [0, 1, 2])
 @pytest.mark.parametrize("nt", [0, 1])
 @pytest.mark.parametrize("pw", [8, 28, 52, 100, 256])
 def test_tuning_knobs_do_not_change_results(api, ragged, xcd, nt, pw):
