@@ -267,15 +267,29 @@ csc_status csc_kmeans_reduced_f64(const double* F, int32_t n, int32_t d, int32_t
  *   caller's node numbering either way.  Per-element products are unchanged;
  *   the float64 column sums run in the new row order.  An order that is not a
  *   permutation returns CSC_E_INVALID_ARG.
- * ws: csc_interpolate_workspace_bytes(N, nnz, k, n) (covers both forms).
- * Synchronises.  Returns CSC_W_NOT_CONVERGED if a column reached max_iter.
+ * method: CSC_CG_COLUMNS runs the k conjugate gradients above side by side
+ *   (columns never mix).  CSC_CG_BLOCK solves the k columns as one block CG
+ *   (O'Leary 1980) in its breakdown-free form (Ji and Li 2017): the search
+ *   block is the rank-revealing orthonormalisation of R + P beta (columns
+ *   scaled to unit norm, pivoted Cholesky of their float64 Gram matrix, pivots
+ *   below 1e-10 dropped), step matrices from float64 Gram matrices solved on
+ *   the host; one Chebyshev pass per iteration serves every column, and the
+ *   block Krylov space usually needs far fewer iterations.  Both stop when
+ *   every column has ||r_j|| / ||b_j|| <= tol (recursive residuals); iters_out
+ *   gives the iteration at which each column first met it.  Both solve the
+ *   same system; X agrees to the accuracy the tolerance implies.
+ * ws: csc_interpolate_workspace_bytes(N, nnz, k, n) (covers every form).
+ * Synchronises.  Returns CSC_W_NOT_CONVERGED if a column reached max_iter or
+ * the block iteration broke down (outputs still hold the last iterate).
  */
+enum { CSC_CG_COLUMNS = 0, CSC_CG_BLOCK = 1 };
 size_t csc_interpolate_workspace_bytes(int32_t N, int64_t nnz, int32_t k, int32_t n);
-csc_status csc_interpolate(const csc_graph* g, const int32_t* order, double lambda_k, int32_t p,
-                           double gamma, const int32_t* idx, const int32_t* labels_r, int32_t n,
-                           int32_t k, double tol, int32_t max_iter, float* X, int32_t ldx,
-                           int32_t* labels, int32_t* iters_out, double* relres_out, void* ws,
-                           size_t ws_bytes, void* stream);
+csc_status csc_interpolate(const csc_graph* g, const int32_t* order, int32_t method,
+                           double lambda_k, int32_t p, double gamma, const int32_t* idx,
+                           const int32_t* labels_r, int32_t n, int32_t k, double tol,
+                           int32_t max_iter, float* X, int32_t ldx, int32_t* labels,
+                           int32_t* iters_out, double* relres_out, void* ws, size_t ws_bytes,
+                           void* stream);
 
 /* ------------------------------------------------------------------------
  * Community order of the nodes, a memory layout for the interpolation (the
@@ -362,12 +376,12 @@ csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, const double* 
  * with ldx[g] (X or X[g] may be NULL), labels: device per-graph int32[N_g].
  * iters_out / relres_out: host arrays of sum_g k[g] entries (graph-major) or
  * NULL.  order: NULL, or per-graph device int32[N_g] node orders (entries
- * may be NULL), as in csc_interpolate.  Returns CSC_W_NOT_CONVERGED if any
+ * may be NULL), and method, as in csc_interpolate.  Returns CSC_W_NOT_CONVERGED if any
  * graph did not converge. */
 size_t csc_interpolate_workspace_bytes_batched(const csc_graph* graphs, int32_t G,
                                                const int32_t* k, int32_t p);
 csc_status csc_interpolate_batched(const csc_graph* graphs, int32_t G, const int32_t* const* order,
-                                   const double* lambda, int32_t p, double gamma,
+                                   int32_t method, const double* lambda, int32_t p, double gamma,
                                    const int32_t* const* idx,
                                    const int32_t* const* labels_r, const int32_t* n,
                                    const int32_t* k, double tol, int32_t max_iter,

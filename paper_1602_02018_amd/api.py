@@ -205,11 +205,16 @@ class Interpolation:
     status: int
 
 
+CG_COLUMNS, CG_BLOCK = 0, 1
+
+
 def interpolate(g: Graph, lam: float, p: int, gamma: float, idx, labels_r, k: int,
                 tol: float = 1e-6, max_iter: int = 1000, want_X: bool = True,
-                order: torch.Tensor | None = None) -> Interpolation:
-    """Eq. (5) by CG; with ``order`` (a permutation, see community_order) the
-    solve runs on the graph listed in that order, outputs in node order."""
+                order: torch.Tensor | None = None, method: int = CG_BLOCK) -> Interpolation:
+    """Eq. (5) by CG (``method``: CG_BLOCK, one block CG over the k columns, or
+    CG_COLUMNS, k side-by-side CGs); with ``order`` (a permutation, see
+    community_order) the solve runs on the graph listed in that order,
+    outputs in node order."""
     idx_t = _i32_device(idx, g.device)
     lab_t = _i32_device(labels_r, g.device)
     ord_t = None if order is None else _i32_device(order, g.device)
@@ -219,7 +224,8 @@ def interpolate(g: Graph, lam: float, p: int, gamma: float, idx, labels_r, k: in
     iters = np.zeros(k, dtype=np.int32)
     relres = np.zeros(k)
     ws = _ws(lib().csc_interpolate_workspace_bytes(g.n, g.nnz, k, n), g.device)
-    st = check(lib().csc_interpolate(g.ref, _ptr(ord_t), float(lam), p, float(gamma), _ptr(idx_t),
+    st = check(lib().csc_interpolate(g.ref, _ptr(ord_t), int(method), float(lam), p, float(gamma),
+                                     _ptr(idx_t),
                                      _ptr(lab_t), n, k, float(tol), max_iter, _ptr(X), k,
                                      _ptr(labels), iters.ctypes.data_as(_lib.pi),
                                      relres.ctypes.data_as(_lib.pd), _ptr(ws), ws.numel(),
@@ -304,7 +310,7 @@ def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
         gamma: float = 1e-3, n_c: int | None = None, tol: float = 1e-6, max_iter: int = 1000,
         max_steps: int = 30, replicates: int = 20, kmeans_iter: int = 100, lam: float | None = None,
         bracket=None, want_X: bool = False, mlp_params: torch.Tensor | None = None,
-        reorder: bool = True) -> Result:
+        reorder: bool = True, cg: int = CG_BLOCK) -> Result:
     """Compressive spectral clustering (Alg. 2) with every graph-sized step on the GPU.
 
     With ``mlp_params`` the dichotomy starts from the learned bracket.  With
@@ -340,7 +346,7 @@ def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
     t3 = time.perf_counter()
     order = community_order(F_all, omega, labels_r, k) if reorder else None
     it = interpolate(g, lam, p, gamma, omega, labels_r, k, tol, max_iter, want_X=want_X,
-                     order=order)
+                     order=order, method=cg)
     torch.cuda.current_stream().synchronize()
     t4 = time.perf_counter()
     tm.update(bisection_s=t1 - t0, features_s=t2 - t1, kmeans_s=t3 - t2, interpolate_s=t4 - t3,
@@ -413,7 +419,7 @@ def filter_batched(graphs, lams, p, ds, seeds, rows, normalize=True):
 
 
 def interpolate_batched(graphs, lams, p, gamma, idx, labels_r, ks, tol=1e-6, max_iter=1000,
-                        want_X=True, orders=None):
+                        want_X=True, orders=None, method=CG_BLOCK):
     G = len(graphs)
     ga = _graphs(graphs)
     dev = graphs[0].device
@@ -432,7 +438,7 @@ def interpolate_batched(graphs, lams, p, gamma, idx, labels_r, ks, tol=1e-6, max
     ord_t = None if orders is None else [None if o is None else _i32_device(o, dev) for o in orders]
     st = check(lib().csc_interpolate_batched(
         ga, G, None if ord_t is None else _pa([0 if o is None else o.data_ptr() for o in ord_t]),
-        lam.ctypes.data_as(_lib.pd), p, float(gamma), _pa([x.data_ptr() for x in idx_t]),
+        int(method), lam.ctypes.data_as(_lib.pd), p, float(gamma), _pa([x.data_ptr() for x in idx_t]),
         _pa([x.data_ptr() for x in lab_t]), ns.ctypes.data_as(_lib.pi), ks.ctypes.data_as(_lib.pi),
         float(tol), max_iter, _pa([x.data_ptr() if x is not None else 0 for x in Xs]) if want_X else None,
         ks.ctypes.data_as(_lib.pi), _pa([x.data_ptr() for x in labels]),
@@ -467,7 +473,7 @@ def kmeans_reduced_batched(Fs, ks, seeds, replicates=20, max_iter=100):
 
 def run_batched(graphs, ks, ds, seeds, p=50, ns=None, gamma=1e-3, n_cs=None, tol=1e-6,
                 max_iter=1000, max_steps=30, replicates=20, kmeans_iter=100, brackets=None,
-                lams=None, want_X=False, mlp_params=None, reorder=True):
+                lams=None, want_X=False, mlp_params=None, reorder=True, cg=CG_BLOCK):
     """Alg. 2 for G graphs at once with the batched calls; graph g matches run(graphs[g], ...)."""
     G = len(graphs)
     ns = [default_n(k) for k in ks] if ns is None else list(ns)
@@ -497,7 +503,7 @@ def run_batched(graphs, ks, ds, seeds, p=50, ns=None, gamma=1e-3, n_cs=None, tol
         orders = [community_order(f, o, l, k) if r else None
                   for f, o, l, k, r in zip(F_all, omegas, labels_r, ks, re)]
     its = interpolate_batched(graphs, lams, p, gamma, omegas, labels_r, ks, tol, max_iter, want_X,
-                              orders)
+                              orders, cg)
     torch.cuda.current_stream().synchronize()
     t4 = time.perf_counter()
     tm.update(bisection_s=t1 - t0, features_s=t2 - t1, kmeans_s=t3 - t2, interpolate_s=t4 - t3,

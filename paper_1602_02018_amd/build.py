@@ -23,6 +23,7 @@ SOURCES = {
     "api_batched.hip": [],
     "mlp.hip": [],
     "order.hip": [],
+    "block.hip": [],
     "kmeans.hip": ["-ffp-contract=off"],
 }
 

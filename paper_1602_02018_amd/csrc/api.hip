@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "dense.hpp"
 #include "host.hpp"
 
 namespace csc {
@@ -231,7 +232,7 @@ size_t count_bytes(const Layout& L, int p) {
 }
 
 size_t interp_bytes(const Layout& L) {
-  const size_t tiles = tiles_for(L), wp = (size_t)L.np * L.pw;
+  const size_t tiles = tiles_for(L), wp = (size_t)L.np * L.pw, kk = (size_t)L.w * L.w;
   size_t b = 6 * align_up(L.bytes());
   b += align_up((size_t)L.n * sizeof(float));          // mask
   b += align_up(wp * tiles * sizeof(double));          // column partials
@@ -239,6 +240,9 @@ size_t interp_bytes(const Layout& L) {
   b += 2 * align_up(wp * sizeof(int));                 // active iters
   b += align_up(wp * sizeof(double));                  // relres
   b += align_up(4 * sizeof(int));                      // nactive, breakdown
+  // block CG: Z, Gram partials, Gram results, four small coefficient matrices
+  b += align_up(L.bytes()) + align_up(gram_part_elems(L, L.w) * sizeof(double));
+  b += 5 * align_up(kk * sizeof(double));
   return b + 256;
 }
 
@@ -673,6 +677,125 @@ csc_status permuted_graph(const csc_graph& g, const int* order, const int* idx, 
   idxp = idx2;
   return CSC_OK;
 }
+
+namespace {
+
+csc_status download(std::vector<double>& h, const double* d, size_t n, hipStream_t s) {
+  h.resize(n);
+  CSC_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  return CSC_OK;
+}
+
+csc_status upload_d(double* d, const std::vector<double>& h, hipStream_t s) {
+  CSC_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  return CSC_OK;
+}
+
+}  // namespace
+
+// Block conjugate gradient on the k columns of R = B at once, in the
+// breakdown-free form (Ji and Li, 2017): the search block P is the
+// orthonormalised (rank-revealing) Z = R + P beta, so columns that converge
+// or become dependent leave the search space instead of breaking it.  Every
+// iteration costs one Chebyshev pass (Q = M P) plus a few Gram matrices and
+// block products; the small k x k algebra runs on the host in float64.
+// block_pre forms P before the pass, block_post the rest after it.
+csc_status block_init(BlockState& st, const Layout& L, int k, double tol,
+                      const BlockBufs& b, const double* bnorm2_dev, hipStream_t s) {
+  st.L = L;
+  st.k = k;
+  st.tol = tol;
+  st.b = b;
+  CSC_TRY(download(st.bn2, bnorm2_dev, (size_t)k, s));
+  st.done.assign(k, 0);
+  st.iters.assign(k, 0);
+  st.relres.assign(k, 0.0);
+  st.ndone = st.nlive = 0;
+  for (int j = 0; j < k; ++j) {
+    if (st.bn2[j] > 0.0)
+      ++st.nlive;
+    else
+      st.done[j] = 1;
+  }
+  st.finished = st.converged = st.nlive == 0;
+  st.broke = false;
+  CSC_HIP(hipMemcpyAsync(b.Z, b.R, L.bytes(), hipMemcpyDeviceToDevice, s));
+  return CSC_OK;
+}
+
+csc_status block_pre(BlockState& st, hipStream_t s) {
+  const BlockBufs& b = st.b;
+  const int k = st.k;
+  CSC_HIP(launch_gram(st.L, b.Z, b.Z, k, k, b.gpart, b.G, k, s));
+  CSC_TRY(download(st.G, b.G, (size_t)k * k, s));
+  st.sr = dense::orth_transform(st.G, k, 1e-10, st.T);
+  if (st.sr == 0) {  // Z = 0: every residual column vanished
+    st.finished = true;
+    st.converged = true;
+    return CSC_OK;
+  }
+  CSC_TRY(upload_d(b.S_t, st.T, s));
+  CSC_HIP(launch_block_mul(st.L, 0.f, nullptr, b.Z, b.S_t, k, st.sr, k, b.P, s));
+  return CSC_OK;
+}
+
+csc_status block_post(BlockState& st, int it, int max_iter, hipStream_t s) {
+  const BlockBufs& b = st.b;
+  const Layout& L = st.L;
+  const int k = st.k, sr = st.sr;
+  // W = P^T Q (s x s), alpha = W^{-1} P^T R (s x k)
+  CSC_HIP(launch_gram(L, b.P, b.Q, sr, sr, b.gpart, b.G, sr, s));
+  CSC_TRY(download(st.W, b.G, (size_t)sr * sr, s));
+  CSC_HIP(launch_gram(L, b.P, b.R, sr, k, b.gpart, b.G, k, s));
+  CSC_TRY(download(st.C, b.G, (size_t)sr * k, s));
+  if (!dense::cholesky(st.W, sr, sr)) {
+    st.finished = true;
+    st.broke = true;
+    return CSC_OK;
+  }
+  dense::chol_solve(st.W, sr, sr, st.C, k, 1.0);
+  st.N = st.C;
+  for (auto& v : st.N) v = -v;
+  CSC_TRY(upload_d(b.S_a, st.C, s));
+  CSC_TRY(upload_d(b.S_na, st.N, s));
+  CSC_HIP(launch_block_mul(L, 1.f, b.X, b.P, b.S_a, sr, k, k, b.X, s));
+  CSC_HIP(launch_block_mul(L, 1.f, b.R, b.Q, b.S_na, sr, k, k, b.R, s));
+  // every column: ||r_j|| <= tol ||b_j||
+  CSC_HIP(launch_col_dot(L, b.R, b.R, b.part, s));
+  CSC_HIP(launch_reduce(b.part, tiles_for(L), k, b.rn2, s));
+  CSC_TRY(download(st.rn2, b.rn2, (size_t)k, s));
+  for (int j = 0; j < k; ++j) {
+    if (st.bn2[j] <= 0.0) continue;
+    st.relres[j] = std::sqrt(st.rn2[j] / st.bn2[j]);
+    if (!st.done[j] && st.relres[j] <= st.tol) {
+      st.done[j] = 1;
+      st.iters[j] = it;
+      ++st.ndone;
+    }
+  }
+  if (st.ndone == st.nlive) {
+    st.finished = st.converged = true;
+    return CSC_OK;
+  }
+  if (it == max_iter) {
+    st.finished = true;
+    return CSC_OK;
+  }
+  // beta = -W^{-1} Q^T R;  Z = R + P beta
+  CSC_HIP(launch_gram(L, b.Q, b.R, sr, k, b.gpart, b.G, k, s));
+  CSC_TRY(download(st.C, b.G, (size_t)sr * k, s));
+  dense::chol_solve(st.W, sr, sr, st.C, k, -1.0);
+  CSC_TRY(upload_d(b.S_b, st.C, s));
+  CSC_HIP(launch_block_mul(L, 1.f, b.R, b.P, b.S_b, sr, k, k, b.Z, s));
+  return CSC_OK;
+}
+
+void block_finish(BlockState& st, int max_iter) {
+  for (int j = 0; j < st.k; ++j)
+    if (!st.done[j]) st.iters[j] = max_iter;
+}
+
 }  // namespace csc
 
 extern "C" size_t csc_interpolate_workspace_bytes(int32_t N, int64_t nnz, int32_t k, int32_t n) {
@@ -682,7 +805,7 @@ extern "C" size_t csc_interpolate_workspace_bytes(int32_t N, int64_t nnz, int32_
 }
 
 extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* order,
-                                      double lambda_k, int32_t p, double gamma,
+                                      int32_t method, double lambda_k, int32_t p, double gamma,
                                       const int32_t* idx_in, const int32_t* labels_r, int32_t n,
                                       int32_t k, double tol, int32_t max_iter, float* X,
                                       int32_t ldx, int32_t* labels, int32_t* iters_out,
@@ -699,6 +822,8 @@ extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* orde
               "need p >= 1, gamma > 0, tol > 0, max_iter >= 1");
   CSC_REQUIRE(lambda_k >= 0.0 && lambda_k <= 2.0, "lambda_k must lie in [0, 2]");
   CSC_REQUIRE(X == nullptr || ldx >= k, "ldx must be >= k");
+  CSC_REQUIRE(method == CSC_CG_COLUMNS || method == CSC_CG_BLOCK,
+              "method must be CSC_CG_COLUMNS or CSC_CG_BLOCK");
   const Layout L = make_layout(N, k, choose_panel_width(N, k, g->nnz));
   CSC_TRY(check_ws(ws, ws_bytes, interp_bytes(L) + (order ? perm_bytes(N, g->nnz, n) : 0)));
   hipStream_t s = as_stream(stream);
@@ -730,6 +855,13 @@ extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* orde
   int* iters = ar.take<int>(wp);
   double* relres = ar.take<double>(wp);
   int* flags = ar.take<int>(4);  // nactive, breakdown
+  float* Zb = ar.take<float>(L.elems());
+  double* gpart = ar.take<double>(gram_part_elems(L, L.w));
+  double* Gd = ar.take<double>((size_t)k * k);
+  double* S_t = ar.take<double>((size_t)k * k);
+  double* S_a = ar.take<double>((size_t)k * k);
+  double* S_na = ar.take<double>((size_t)k * k);
+  double* S_b = ar.take<double>((size_t)k * k);
 
   CSC_HIP(launch_fill_f32(P, L.elems(), 0.f, s));
   CSC_HIP(launch_fill_f32(Xi, L.elems(), 0.f, s));
@@ -762,6 +894,39 @@ extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* orde
 
   std::vector<double> a(p + 1);
   jackson_lowpass(lambda_k, p, a.data());
+  if (method == CSC_CG_BLOCK) {
+    BlockState bs;
+    CSC_TRY(block_init(bs, L, k, tol,
+                       BlockBufs{P, AP, Ta, Tb, Xi, Rr, Zb, mask, part, gpart, Gd, S_t, S_a, S_na,
+                                 S_b, rrn},
+                       bnorm2, s));
+    Pass pb;
+    pb.T0 = P;
+    pb.Ta = Ta;
+    pb.Tb = Tb;
+    pb.Y = AP;
+    pb.part = part;
+    pb.mask = mask;
+    pb.gamma = (float)gamma;
+    for (int it = 1; it <= max_iter && !bs.finished; ++it) {
+      CSC_TRY(block_pre(bs, s));
+      if (bs.finished) break;
+      CSC_TRY(chebyshev_pass(*g, L, a.data(), p, EPI_CG, pb, s));  // Q = M P
+      CSC_TRY(block_post(bs, it, max_iter, s));
+    }
+    block_finish(bs, max_iter);
+    CSC_HIP(launch_col_dot(L, Xi, Xi, part, s));
+    CSC_HIP(launch_reduce(part, tiles, k, colnorm2, s));
+    CSC_HIP(launch_labels(L, Xi, colnorm2, labels, X, ldx, order, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    if (iters_out) std::memcpy(iters_out, bs.iters.data(), k * sizeof(int));
+    if (relres_out) std::memcpy(relres_out, bs.relres.data(), k * sizeof(double));
+    if (bs.broke) {
+      set_error("block CG breakdown: P^T M P is not positive definite");
+      return CSC_W_NOT_CONVERGED;
+    }
+    return bs.converged ? CSC_OK : CSC_W_NOT_CONVERGED;
+  }
   Pass b;
   b.T0 = P;
   b.Ta = Ta;

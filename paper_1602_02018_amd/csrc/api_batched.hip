@@ -513,7 +513,8 @@ extern "C" size_t csc_interpolate_workspace_bytes_batched(const csc_graph* graph
 }
 
 extern "C" csc_status csc_interpolate_batched(
-    const csc_graph* graphs, int32_t G, const int32_t* const* order, const double* lambda,
+    const csc_graph* graphs, int32_t G, const int32_t* const* order, int32_t method,
+    const double* lambda,
     int32_t p, double gamma, const int32_t* const* idx_in, const int32_t* const* labels_r,
     const int32_t* n, const int32_t* k,
     double tol, int32_t max_iter, float* const* X, const int32_t* ldx, int32_t* const* labels,
@@ -525,6 +526,8 @@ extern "C" csc_status csc_interpolate_batched(
               "lambda, idx, labels_r, n, k, labels and status_out must be non-NULL");
   CSC_REQUIRE(p >= 1 && gamma > 0.0 && tol > 0.0 && max_iter >= 1,
               "need p >= 1, gamma > 0, tol > 0, max_iter >= 1");
+  CSC_REQUIRE(method == CSC_CG_COLUMNS || method == CSC_CG_BLOCK,
+              "method must be CSC_CG_COLUMNS or CSC_CG_BLOCK");
   for (int g = 0; g < G; ++g) {
     const int N = graphs[g].n;
     CSC_REQUIRE(idx_in[g] && labels_r[g] && labels[g],
@@ -545,6 +548,8 @@ extern "C" csc_status csc_interpolate_batched(
     float *P, *Ta, *Tb, *AP, *Xi, *Rr, *mask;
     double *part, *rr, *rrn, *pAp, *alpha, *beta, *bnorm2, *colnorm2, *relres;
     int *active, *iters;
+    float* Z;  // block CG
+    double *gpart, *G, *S_t, *S_a, *S_na, *S_b;
   };
   std::vector<Buf> B(G);
   for (int g = 0; g < G; ++g) {
@@ -573,6 +578,14 @@ extern "C" csc_status csc_interpolate_batched(
     b.active = ar.take<int>(b.wp);
     b.iters = ar.take<int>(b.wp);
     b.relres = ar.take<double>(b.wp);
+    const size_t kk = (size_t)k[g] * k[g];
+    b.Z = ar.take<float>(b.L.elems());
+    b.gpart = ar.take<double>(gram_part_elems(b.L, b.L.w));
+    b.G = ar.take<double>(kk);
+    b.S_t = ar.take<double>(kk);
+    b.S_a = ar.take<double>(kk);
+    b.S_na = ar.take<double>(kk);
+    b.S_b = ar.take<double>(kk);
   }
   int* flags = ar.take<int>((size_t)G * 4);  // per graph: nactive, breakdown, bad, it
   int* d_live = ar.take<int>(G);
@@ -716,6 +729,70 @@ extern "C" csc_status csc_interpolate_batched(
   CSC_TRY(upload(w_k.d, w_k.h, s));
   CSC_TRY(upload(w_u2.d, w_u2.h, s));
   CSC_TRY(upload(w_lab.d, w_lab.h, s));
+
+  if (method == CSC_CG_BLOCK) {
+    // every graph's block CG; the Chebyshev pass Q = M P of all graphs still
+    // iterating is one batched launch per step
+    std::vector<BlockState> bs(G);
+    for (int g = 0; g < G; ++g) {
+      const Buf& b = B[g];
+      CSC_TRY(block_init(bs[g], b.L, k[g], tol,
+                         BlockBufs{b.P, b.AP, b.Ta, b.Tb, b.Xi, b.Rr, b.Z, b.mask, b.part,
+                                   b.gpart, b.G, b.S_t, b.S_a, b.S_na, b.S_b, b.rrn},
+                         b.bnorm2, s));
+    }
+    auto filter_pass = [&](hipStream_t st) -> csc_status {
+      for (int m = 0; m < p; ++m) {
+        const bool last = m + 1 == p;
+        CSC_HIP(launch_cheb_step_batched(d_steps + (size_t)m * G, w_step.table(),
+                                         last ? EPI_CG : EPI_Y, m == 0, last, st));
+      }
+      return CSC_OK;
+    };
+    Captured cap_pass;
+    for (int it = 1; it <= max_iter; ++it) {
+      bool any = false;
+      for (int g = 0; g < G; ++g) {
+        if (!bs[g].finished) CSC_TRY(block_pre(bs[g], s));
+        live[g] = bs[g].finished ? 0 : 1;
+        any = any || live[g];
+      }
+      if (!any) break;
+      CSC_TRY(upload(d_live, live, s));
+      CSC_TRY(run_pass(filter_pass, cap_pass, s));
+      for (int g = 0; g < G; ++g)
+        if (live[g]) CSC_TRY(block_post(bs[g], it, max_iter, s));
+    }
+    std::vector<ColDotItem> h_cd(G);
+    std::vector<ReduceItem> h_cn(G);
+    std::vector<LabelItem> h_lab(G);
+    for (int g = 0; g < G; ++g) {
+      block_finish(bs[g], max_iter);
+      const Buf& b = B[g];
+      h_cd[g] = ColDotItem{b.L, b.tiles, b.Xi, b.Xi, b.part, nullptr};
+      h_cn[g] = ReduceItem{b.part, b.tiles, b.colnorm2, nullptr};
+      h_lab[g] = LabelItem{b.L, b.Xi, b.colnorm2, labels[g], X ? X[g] : nullptr,
+                           (X && X[g]) ? ldx[g] : 0, order ? order[g] : nullptr};
+    }
+    CSC_TRY(upload(d_cd, h_cd, s));
+    CSC_TRY(upload(d_red_pap, h_cn, s));
+    CSC_TRY(upload(d_lab, h_lab, s));
+    CSC_HIP(launch_col_dot_batched(d_cd, w_step.table(), s));
+    CSC_HIP(launch_reduce_batched(d_red_pap, w_k.table(), s));
+    CSC_HIP(launch_labels_batched(d_lab, w_lab.table(), s));
+    CSC_HIP(hipStreamSynchronize(s));
+    csc_status worst = CSC_OK;
+    size_t off = 0;
+    for (int g = 0; g < G; ++g) {
+      if (iters_out) std::memcpy(iters_out + off, bs[g].iters.data(), k[g] * sizeof(int));
+      if (relres_out) std::memcpy(relres_out + off, bs[g].relres.data(), k[g] * sizeof(double));
+      off += k[g];
+      const bool ok = bs[g].converged && !bs[g].broke;
+      status_out[g] = ok ? CSC_OK : CSC_W_NOT_CONVERGED;
+      if (!ok) worst = CSC_W_NOT_CONVERGED;
+    }
+    return worst;
+  }
 
   auto iteration = [&](hipStream_t st) -> csc_status {
     for (int m = 0; m < p; ++m) {

@@ -1,0 +1,187 @@
+// Dense products of tall panel-major blocks, for the block conjugate gradient
+// of the interpolation: Gram matrices A^T B (float32 entries, float64 sums)
+// and right products by a small float64 matrix.
+//
+// Both are memory-light next to a Chebyshev pass (k x k work per node for an
+// N x k block, against p gathered steps), so they use plain float64 FMAs on
+// LDS tiles rather than matrix cores: float64 accumulation keeps the
+// orthonormalisation and the step sizes of the block CG accurate.
+#include <algorithm>
+
+#include "device.hpp"
+
+namespace csc {
+namespace {
+
+constexpr int kT = 64;   // output tile (64 x 64 per workgroup)
+constexpr int kR = 32;   // rows (Gram) or inner columns (product) staged per round
+
+__device__ inline float panel_at(const Layout& L, const float* A, int i, int c) {
+  return A[(size_t)(c / L.pw) * L.panel_elems() + (size_t)i * L.pw + c % L.pw];
+}
+
+// part[chunk][ti*64 + r][tj*64 + c] = sum over the chunk's rows i of
+// A[i, ti*64 + r] * B[i, tj*64 + c], rows in increasing order.
+__global__ __launch_bounds__(256) void k_gram(Layout L, const float* A, const float* B, int ka,
+                                              int kb, int rows_per_chunk, int tiles_b,
+                                              double* part) {
+  __shared__ float As[kR][kT + 1];
+  __shared__ float Bs[kR][kT + 1];
+  const int ti = blockIdx.x / tiles_b, tj = blockIdx.x - ti * tiles_b;
+  const int chunk = blockIdx.y;
+  const int r0 = chunk * rows_per_chunk;
+  const int r1 = min(L.n, r0 + rows_per_chunk);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int rb = r0; rb < r1; rb += kR) {
+    for (int e = threadIdx.x; e < kR * kT; e += 256) {
+      const int r = e / kT, c = e - r * kT, gi = rb + r;
+      const int ca = ti * kT + c, cb = tj * kT + c;
+      As[r][c] = (gi < r1 && ca < ka) ? panel_at(L, A, gi, ca) : 0.f;
+      Bs[r][c] = (gi < r1 && cb < kb) ? panel_at(L, B, gi, cb) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int r = 0; r < kR; ++r) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = (double)As[r][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = (double)Bs[r][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  const int ldp = tiles_b * kT;
+  double* out = part + (size_t)chunk * (gridDim.x / tiles_b) * kT * ldp;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      out[(size_t)(ti * kT + ty * 4 + i) * ldp + tj * kT + tx * 4 + j] = acc[i][j];
+}
+
+// G[i * ldg + j] = sum over chunks (in order) of the partial tiles.
+__global__ void k_gram_reduce(const double* part, int chunks, int rows_pad, int cols_pad, int ka,
+                              int kb, double* G, int ldg) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ka * kb) return;
+  const int i = e / kb, j = e - i * kb;
+  double s = 0.0;
+  for (int c = 0; c < chunks; ++c) s += part[((size_t)c * rows_pad + i) * cols_pad + j];
+  G[(size_t)i * ldg + j] = s;
+}
+
+// Out[i, j] = c0 * In0[i, j] + sum_{l < kin} In1[i, l] * S[l * lds + j] for
+// every stored column j of the layout (S is zero beyond its live columns, so
+// padding columns stay zero); float64 sums, rounded once to float32.  Out may
+// be In0, never In1.
+__global__ __launch_bounds__(256) void k_block_mul(Layout L, float c0, const float* In0,
+                                                   const float* In1, const double* S, int kin,
+                                                   int kout, int lds, float* Out) {
+  __shared__ float Xs[kT][kR + 1];
+  __shared__ double Ss[kR][kT + 1];
+  const int W = L.np * L.pw;
+  const int i0 = blockIdx.x * kT, j0 = blockIdx.y * kT;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int lb = 0; lb < kin; lb += kR) {
+    for (int e = threadIdx.x; e < kT * kR; e += 256) {
+      const int r = e / kR, l = e - r * kR, gi = i0 + r, gl = lb + l;
+      Xs[r][l] = (gi < L.n && gl < kin) ? panel_at(L, In1, gi, gl) : 0.f;
+    }
+    for (int e = threadIdx.x; e < kR * kT; e += 256) {
+      const int l = e / kT, c = e - l * kT, gl = lb + l, gj = j0 + c;
+      Ss[l][c] = (gl < kin && gj < kout) ? S[(size_t)gl * lds + gj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int l = 0; l < kR; ++l) {
+      double x[4], sv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[i] = (double)Xs[ty * 4 + i][l];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sv[j] = Ss[l][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(x[i], sv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gi = i0 + ty * 4 + i;
+    if (gi >= L.n) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gj = j0 + tx * 4 + j;
+      if (gj >= W) continue;
+      const size_t o = (size_t)(gj / L.pw) * L.panel_elems() + (size_t)gi * L.pw + gj % L.pw;
+      const double base = c0 != 0.f ? (double)c0 * (double)In0[o] : 0.0;
+      Out[o] = (float)(base + acc[i][j]);
+    }
+  }
+}
+
+}  // namespace
+
+GramPlan gram_plan(const Layout& L, int ka, int kb) {
+  GramPlan g;
+  g.tiles_a = (ka + kT - 1) / kT;
+  g.tiles_b = (kb + kT - 1) / kT;
+  const int tiles = g.tiles_a * g.tiles_b;
+  int chunks = std::max(1, 1024 / tiles);
+  const int max_chunks = (L.n + kR - 1) / kR;
+  chunks = std::min(chunks, max_chunks);
+  int rows = (L.n + chunks - 1) / chunks;
+  rows = (rows + kR - 1) / kR * kR;
+  g.rows_per_chunk = rows;
+  g.chunks = (L.n + rows - 1) / rows;
+  return g;
+}
+
+size_t gram_part_elems(const Layout& L, int kmax) {
+  size_t m = 0;
+  for (int ka = kT; ka < kmax + kT; ka += kT)
+    for (int kb = kT; kb < kmax + kT; kb += kT) {
+      const GramPlan g = gram_plan(L, std::min(ka, kmax), std::min(kb, kmax));
+      m = std::max(m, (size_t)g.chunks * g.tiles_a * kT * g.tiles_b * kT);
+    }
+  return m;
+}
+
+hipError_t launch_gram(const Layout& L, const float* A, const float* B, int ka, int kb,
+                       double* part, double* G, int ldg, hipStream_t s) {
+  const GramPlan g = gram_plan(L, ka, kb);
+  hipLaunchKernelGGL(k_gram, dim3((unsigned)(g.tiles_a * g.tiles_b), (unsigned)g.chunks), dim3(256),
+                     0, s, L, A, B, ka, kb, g.rows_per_chunk, g.tiles_b, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int n = ka * kb;
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
+                     g.chunks, g.tiles_a * kT, g.tiles_b * kT, ka, kb, G, ldg);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_mul(const Layout& L, float c0, const float* In0, const float* In1,
+                            const double* S, int kin, int kout, int lds, float* Out,
+                            hipStream_t s) {
+  const int W = L.np * L.pw;
+  const dim3 grid((unsigned)((L.n + kT - 1) / kT), (unsigned)((W + kT - 1) / kT));
+  hipLaunchKernelGGL(k_block_mul, grid, dim3(256), 0, s, L, c0, In0, In1, S, kin, kout, lds, Out);
+  return hipGetLastError();
+}
+
+}  // namespace csc

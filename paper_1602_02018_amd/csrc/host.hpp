@@ -1,6 +1,8 @@
 // Host-side helpers shared by the single-graph and the batched C calls.
 #pragma once
 
+#include <vector>
+
 #include "kernels.hpp"
 
 namespace csc {
@@ -15,6 +17,28 @@ size_t filter_bytes(const Layout& L);
 size_t count_bytes(const Layout& L, int p);
 size_t interp_bytes(const Layout& L);
 int use_hip_graphs();
+
+// Block conjugate gradient of the interpolation (api.hip), one graph's state;
+// the Chebyshev pass Q = M P runs between block_pre and block_post.
+struct BlockBufs {
+  float *P, *Q, *Ta, *Tb, *X, *R, *Z, *mask;
+  double *part, *gpart, *G, *S_t, *S_a, *S_na, *S_b, *rn2;
+};
+struct BlockState {
+  Layout L;
+  int k = 0, sr = 0, ndone = 0, nlive = 0;
+  double tol = 0.0;
+  BlockBufs b{};
+  bool finished = false, converged = false, broke = false;
+  std::vector<char> done;
+  std::vector<int> iters;
+  std::vector<double> bn2, relres, G, T, W, C, N, rn2;
+};
+csc_status block_init(BlockState& st, const Layout& L, int k, double tol, const BlockBufs& b,
+                      const double* bnorm2_dev, hipStream_t s);
+csc_status block_pre(BlockState& st, hipStream_t s);
+csc_status block_post(BlockState& st, int it, int max_iter, hipStream_t s);
+void block_finish(BlockState& st, int max_iter);
 
 // Workspace of permuted_graph, and the graph g permuted to `order` (row r =
 // node order[r], neighbours relabelled and kept in CSR order) with the sampled

@@ -197,6 +197,22 @@ hipError_t launch_cg_update2(const Layout& L, const float* R, float* P, const do
 hipError_t launch_labels(const Layout& L, const float* X, const double* colnorm2, int* labels,
                          float* Xout, int ldx, const int* out_map, hipStream_t s);
 
+// Block products (block.hip).  Gram G = A^T B of the first ka and kb columns
+// of two N-row panel-major blocks (float64 sums in a fixed order, row-major
+// with leading dimension ldg); part holds gram_part_elems(L, max(ka, kb))
+// doubles.  Block product Out = c0 In0 + In1[:, :kin] S with S float64
+// kin x kout (leading dimension lds), every stored column written.
+struct GramPlan {
+  int tiles_a = 0, tiles_b = 0, chunks = 0, rows_per_chunk = 0;
+};
+GramPlan gram_plan(const Layout& L, int ka, int kb);
+size_t gram_part_elems(const Layout& L, int kmax);
+hipError_t launch_gram(const Layout& L, const float* A, const float* B, int ka, int kb,
+                       double* part, double* G, int ldg, hipStream_t s);
+hipError_t launch_block_mul(const Layout& L, float c0, const float* In0, const float* In1,
+                            const double* S, int kin, int kout, int lds, float* Out,
+                            hipStream_t s);
+
 // Node orders (order.hip).  order[r] = node placed at position r.
 hipError_t launch_perm_inverse(int N, const int* order, int* inv, int* bad, hipStream_t s);
 hipError_t launch_perm_check(int N, const int* inv, int* bad, hipStream_t s);

@@ -70,9 +70,13 @@ def test_argument_errors_are_reported_without_gpu_work():
     st = C.c_int32()
     assert lib.csc_estimate_lambda_k(C.byref(g), 11, 50, 4, 0, 30, None, C.byref(lam), C.byref(st),
                                      None, None, None, 0, None) == _lib.CSC_E_INVALID_ARG
-    assert lib.csc_interpolate(C.byref(g), None, 0.5, 50, 0.0, C.c_void_p(16), C.c_void_p(16), 2, 2,
-                               1e-6, 10, None, 2, C.c_void_p(16), None, None, None, 0,
+    assert lib.csc_interpolate(C.byref(g), None, 1, 0.5, 50, 0.0, C.c_void_p(16), C.c_void_p(16), 2,
+                               2, 1e-6, 10, None, 2, C.c_void_p(16), None, None, None, 0,
                                None) == _lib.CSC_E_INVALID_ARG
+    assert lib.csc_interpolate(C.byref(g), None, 2, 0.5, 50, 1e-3, C.c_void_p(16), C.c_void_p(16), 2,
+                               2, 1e-6, 10, None, 2, C.c_void_p(16), None, None, None, 0,
+                               None) == _lib.CSC_E_INVALID_ARG
+    assert b"method" in lib.csc_last_error()
     # community order: d above the register-resident limit, labels outside [0, k)
     lab = (C.c_int32 * 3)(0, 1, 2)
     assert lib.csc_community_order(10, C.c_void_p(16), 200, 200, C.c_void_p(16), lab, 3, 3,

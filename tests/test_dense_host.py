@@ -1,0 +1,89 @@
+"""Host float64 algebra of the block CG (rank-revealing orthonormalisation,
+Cholesky solves), checked against numpy on random and rank-deficient blocks."""
+import ctypes as C
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def dense(tmp_path_factory):
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("no C++ compiler")
+    out = tmp_path_factory.mktemp("dense") / "libdense.so"
+    subprocess.run([cxx, "-O2", "-shared", "-fPIC", "-o", str(out),
+                    os.path.join(HERE, "dense_host.cpp")], check=True)
+    lib = C.CDLL(str(out))
+    pd = C.POINTER(C.c_double)
+    lib.dense_orth.argtypes = [pd, C.c_int, C.c_double, pd]
+    lib.dense_orth.restype = C.c_int
+    lib.dense_solve.argtypes = [pd, C.c_int, pd, C.c_int, C.c_double]
+    lib.dense_solve.restype = C.c_int
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _orth(lib, Z, rtol=1e-10):
+    k = Z.shape[1]
+    G = np.ascontiguousarray(Z.T @ Z)
+    T = np.zeros((k, k))
+    s = lib.dense_orth(_p(G), k, rtol, _p(T))
+    return s, T[:, :s]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_orth_of_full_rank_block(dense, seed):
+    rng = np.random.default_rng(seed)
+    Z = rng.normal(size=(300, 12)) * rng.uniform(1e-4, 10, size=12)  # widely scaled columns
+    s, T = _orth(dense, Z)
+    assert s == 12
+    P = Z @ T
+    np.testing.assert_allclose(P.T @ P, np.eye(s), atol=1e-10)
+    # P spans Z: Z = P (P^T Z)
+    np.testing.assert_allclose(P @ (P.T @ Z), Z, atol=1e-9 * np.abs(Z).max())
+
+
+def test_orth_drops_dependent_and_zero_columns(dense):
+    rng = np.random.default_rng(7)
+    B = rng.normal(size=(200, 5))
+    Z = np.concatenate([B, B[:, :2] @ rng.normal(size=(2, 3)), np.zeros((200, 2))], axis=1)
+    s, T = _orth(dense, Z)
+    assert s == 5
+    P = Z @ T
+    np.testing.assert_allclose(P.T @ P, np.eye(5), atol=1e-10)
+    np.testing.assert_allclose(P @ (P.T @ Z), Z, atol=1e-9 * np.abs(Z).max())
+    assert np.all(T[-2:] == 0.0)  # zero columns take no part
+
+
+def test_orth_keeps_a_small_but_independent_column(dense):
+    rng = np.random.default_rng(3)
+    Z = rng.normal(size=(100, 4))
+    Z[:, 2] *= 1e-9  # a nearly converged residual column is still a direction
+    s, T = _orth(dense, Z)
+    assert s == 4
+
+
+@pytest.mark.parametrize("s,k", [(1, 3), (7, 7), (20, 5)])
+def test_cholesky_solve(dense, s, k):
+    rng = np.random.default_rng(s * 31 + k)
+    M = rng.normal(size=(s, s))
+    W = M @ M.T + s * np.eye(s)
+    Cm = rng.normal(size=(s, k))
+    out = Cm.copy()
+    assert dense.dense_solve(_p(np.ascontiguousarray(W)), s, _p(out), k, -1.0) == 1
+    np.testing.assert_allclose(out, -np.linalg.solve(W, Cm), rtol=1e-10, atol=1e-12)
+
+
+def test_cholesky_rejects_indefinite(dense):
+    W = np.array([[1.0, 2.0], [2.0, 1.0]])
+    Cm = np.ones((2, 1))
+    assert dense.dense_solve(_p(W), 2, _p(Cm), 1, 1.0) == 0

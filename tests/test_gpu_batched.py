@@ -87,7 +87,8 @@ def test_batched_features_match_single(api, batch):
 
 
 @pytest.mark.parametrize("use_graphs", [1, 0])
-def test_batched_interpolation_matches_single(api, batch, use_graphs):
+@pytest.mark.parametrize("method", [1, 0])
+def test_batched_interpolation_matches_single(api, batch, use_graphs, method):
     _set_graphs(api, use_graphs)
     try:
         G = _graphs(api, batch)
@@ -99,9 +100,9 @@ def test_batched_interpolation_matches_single(api, batch, use_graphs):
             omegas.append(api.sample(g.n, n, i))
             labs.append(np.arange(n) % ks[i])
         for _ in range(2):
-            res = api.interpolate_batched(G, lams, 50, 1e-3, omegas, labs, ks)
+            res = api.interpolate_batched(G, lams, 50, 1e-3, omegas, labs, ks, method=method)
             for i, g in enumerate(G):
-                ref = api.interpolate(g, lams[i], 50, 1e-3, omegas[i], labs[i], ks[i])
+                ref = api.interpolate(g, lams[i], 50, 1e-3, omegas[i], labs[i], ks[i], method=method)
                 assert torch.equal(res[i].X, ref.X)
                 assert torch.equal(res[i].labels, ref.labels)
                 assert np.array_equal(res[i].iters, ref.iters)
@@ -111,15 +112,17 @@ def test_batched_interpolation_matches_single(api, batch, use_graphs):
         _set_graphs(api, 1)
 
 
-def test_batched_interpolation_max_iter(api, batch):
+@pytest.mark.parametrize("method", [1, 0])
+def test_batched_interpolation_max_iter(api, batch, method):
     G = _graphs(api, batch)
     ks = [g.k for g in batch]
     omegas = [api.sample(g.n, min(g.n, 30), i) for i, g in enumerate(batch)]
     labs = [np.arange(30) % k for k in ks]
     res = api.interpolate_batched(G, [0.4] * len(batch), 50, 1e-3, omegas, labs, ks, tol=1e-12,
-                                  max_iter=3)
+                                  max_iter=3, method=method)
     for i, g in enumerate(G):
-        ref = api.interpolate(g, 0.4, 50, 1e-3, omegas[i], labs[i], ks[i], tol=1e-12, max_iter=3)
+        ref = api.interpolate(g, 0.4, 50, 1e-3, omegas[i], labs[i], ks[i], tol=1e-12, max_iter=3,
+                              method=method)
         assert res[i].status == ref.status
         assert torch.equal(res[i].X, ref.X)
 

@@ -117,8 +117,9 @@ def test_interpolation_with_order_matches_natural_order(api, cfg1, pw, kind):
         else:
             order = torch.as_tensor(np.random.default_rng(3).permutation(cfg1.n).astype(np.int32),
                                     device="cuda")
-        a = api.interpolate(g, lam, 50, 1e-3, omega, lab_r, k)
-        b = api.interpolate(g, lam, 50, 1e-3, omega, lab_r, k, order=order)
+        # side-by-side CGs: identical products, only row order of the float64 sums differs
+        a = api.interpolate(g, lam, 50, 1e-3, omega, lab_r, k, method=0)
+        b = api.interpolate(g, lam, 50, 1e-3, omega, lab_r, k, order=order, method=0)
         assert a.status == 0 and b.status == 0
         assert np.all(np.abs(a.iters - b.iters) <= 1)
         assert np.all(b.relres <= 1e-6)
@@ -131,6 +132,13 @@ def test_interpolation_with_order_matches_natural_order(api, cfg1, pw, kind):
         X, lab, _, _ = interp.interpolate(A, lam, 50, 1e-3, omega_h, lab_r, k, tol=1e-6)
         assert np.linalg.norm(Xb - X) <= 1e-3 * np.linalg.norm(X)
         assert metrics.adjusted_rand_index(b.labels.cpu().numpy(), lab) >= 0.99
+        # block CG with and without the order: same system, same tolerance
+        c = api.interpolate(g, lam, 50, 1e-3, omega, lab_r, k, order=order, method=1)
+        d = api.interpolate(g, lam, 50, 1e-3, omega, lab_r, k, method=1)
+        assert c.status == 0 and d.status == 0 and np.all(c.relres <= 1e-6)
+        Xc, Xd = c.X.cpu().numpy(), d.X.cpu().numpy()
+        assert np.linalg.norm(Xc - Xd) <= 1e-3 * np.linalg.norm(Xd)
+        assert metrics.adjusted_rand_index(c.labels.cpu().numpy(), d.labels.cpu().numpy()) >= 0.99
     finally:
         api.set_panel_width(0)
 

@@ -260,8 +260,9 @@ def test_kmeans_on_gpu_features_matches_oracle_given_same_input(api, cfg1):
 
 # ------------------------------------------------------- interpolation -----
 
-@pytest.mark.parametrize("pw", [4, 8, 16])
-def test_interpolation_matches_oracle(api, cfg1, pw):
+@pytest.mark.parametrize("pw", [4, 8, 16, 0])
+@pytest.mark.parametrize("method", [0, 1])
+def test_interpolation_matches_oracle(api, cfg1, pw, method):
     api.set_panel_width(pw)
     try:
         g = api.Graph(cfg1.row_ptr, cfg1.col)
@@ -269,12 +270,20 @@ def test_interpolation_matches_oracle(api, cfg1, pw):
         omega = sampling.sample(cfg1.n, 47, 0)
         A = _A(cfg1)
         lab_r, _, _ = kmeans.kmeans(ocsc.features(A, lam, p, 28, 0)[omega], k, 0)
-        res = api.interpolate(g, lam, p, gamma, omega, lab_r, k, tol=1e-6)
+        res = api.interpolate(g, lam, p, gamma, omega, lab_r, k, tol=1e-6, method=method)
         X, lab, iters, relres = interp.interpolate(A, lam, p, gamma, omega, lab_r, k, tol=1e-6)
         assert res.status == 0
         assert np.all(res.relres <= 1e-6) and np.all(res.iters >= 1)
-        assert np.all(np.abs(res.iters - iters) <= 2)
-        assert _relfro(res.X.cpu().numpy(), X) <= 1e-3
+        if method == 0:
+            # the same iteration as the oracle's: same iteration counts, iterates close
+            assert np.all(np.abs(res.iters - iters) <= 2)
+            assert _relfro(res.X.cpu().numpy(), X) <= 1e-3
+        else:
+            # another Krylov method for the same system: fewer iterations; compare
+            # with the solution the oracle reaches at a tolerance far below 1e-6
+            assert res.iters.max() < iters.max()
+            Xt, _, _, _ = interp.interpolate(A, lam, p, gamma, omega, lab_r, k, tol=1e-12)
+            assert _relfro(res.X.cpu().numpy(), Xt) <= 1e-3
         assert metrics.adjusted_rand_index(res.labels.cpu().numpy(), lab) >= 0.99
         # true residual with the float64 operator
         mask = np.zeros(cfg1.n)
@@ -295,19 +304,24 @@ def test_interpolation_single_cluster_and_max_iter(api, cfg1):
     omega = sampling.sample(cfg1.n, 20, 1)
     res = api.interpolate(g, 0.4, 50, 1e-3, omega, np.zeros(20, np.int32), 1, tol=1e-6)
     assert res.status == 0 and np.all(res.labels.cpu().numpy() == 0)
-    res = api.interpolate(g, 0.4, 50, 1e-3, omega, np.arange(20) % 3, 3, tol=1e-12, max_iter=2)
+    res = api.interpolate(g, 0.4, 50, 1e-3, omega, np.arange(20) % 3, 3, tol=1e-12, max_iter=2,
+                          method=0)
     assert res.status == _lib.CSC_W_NOT_CONVERGED and np.all(res.iters == 2)
     X, lab, iters, relres = interp.interpolate(_A(cfg1), 0.4, 50, 1e-3, omega, np.arange(20) % 3, 3,
                                                tol=1e-12, max_iter=2)
     assert _relfro(res.X.cpu().numpy(), X) <= 1e-4
+    res = api.interpolate(g, 0.4, 50, 1e-3, omega, np.arange(20) % 3, 3, tol=1e-12, max_iter=2,
+                          method=1)
+    assert res.status == _lib.CSC_W_NOT_CONVERGED and np.all(res.iters == 2)
 
 
-def test_interpolation_cluster_without_samples(api, cfg1):
+@pytest.mark.parametrize("method", [0, 1])
+def test_interpolation_cluster_without_samples(api, cfg1, method):
     # cluster 2 has no sampled node: b_2 = 0, its column stays 0 and never wins
     g = api.Graph(cfg1.row_ptr, cfg1.col)
     omega = sampling.sample(cfg1.n, 30, 2)
     lab_r = np.arange(30) % 2
-    res = api.interpolate(g, 0.46875, 50, 1e-3, omega, lab_r, 3)
+    res = api.interpolate(g, 0.46875, 50, 1e-3, omega, lab_r, 3, method=method)
     X = res.X.cpu().numpy()
     assert np.all(X[:, 2] == 0.0) and res.iters[2] == 0
     assert set(np.unique(res.labels.cpu().numpy())) <= {0, 1}

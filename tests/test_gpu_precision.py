@@ -50,12 +50,19 @@ def test_per_result_error_against_float64():
     lab64, _, _ = kmeans.kmeans(Fref[omega], k, seed)
     rep["sampled labels ARI (f32 vs f64 features)"] = metrics.adjusted_rand_index(lab32, lab64)
 
-    # interpolation
-    res = api.interpolate(g, lam_ref, p, 1e-3, omega, lab64, k)
+    # interpolation: the side-by-side CGs against the oracle's (same iteration),
+    # the block CG against the solution the oracle reaches at tolerance 1e-12
+    res = api.interpolate(g, lam_ref, p, 1e-3, omega, lab64, k, method=0)
     X, lab, _, _ = interp.interpolate(A, lam_ref, p, 1e-3, omega, lab64, k)
     Xg = res.X.cpu().numpy()
     rep["X rel Frobenius err"] = float(np.linalg.norm(Xg - X) / np.linalg.norm(X))
     rep["labels ARI vs float64"] = metrics.adjusted_rand_index(res.labels.cpu().numpy(), lab)
+    rb = api.interpolate(g, lam_ref, p, 1e-3, omega, lab64, k, method=1)
+    Xt, _, _, _ = interp.interpolate(A, lam_ref, p, 1e-3, omega, lab64, k, tol=1e-12)
+    rep["block CG X rel err vs tight solve"] = float(np.linalg.norm(rb.X.cpu().numpy() - Xt)
+                                                     / np.linalg.norm(Xt))
+    rep["side-by-side CG X rel err vs tight solve"] = float(np.linalg.norm(Xg - Xt) / np.linalg.norm(Xt))
+    rep["block CG labels ARI vs float64"] = metrics.adjusted_rand_index(rb.labels.cpu().numpy(), lab)
 
     for key, val in rep.items():
         print(f"{key:45s} {val:.3e}")
@@ -66,3 +73,5 @@ def test_per_result_error_against_float64():
     assert rep["sampled labels ARI (f32 vs f64 features)"] >= 0.99
     assert rep["X rel Frobenius err"] <= 1e-3
     assert rep["labels ARI vs float64"] >= 0.99
+    assert rep["block CG X rel err vs tight solve"] <= 1e-3
+    assert rep["block CG labels ARI vs float64"] >= 0.99
