@@ -32,17 +32,78 @@ inline double sqd(const double* x, const double* c, int d) {
   return acc;
 }
 
+// Eight squared distances at once, each summed over coordinates in order
+// exactly as sqd does (independent chains, so the loop pipelines and
+// vectorises without changing any rounding).
+constexpr int kB = 8;
+
+// x (d coordinates) against the centroids c0 .. c0+7 stored transposed:
+// coordinate j of centroid c at Ct[j * kp + c].
+inline void sqd_centroids8(const double* x, const double* Ct, int kp, int c0, int d, double* out) {
+  double acc[kB] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int j = 0; j < d; ++j) {
+    const double xj = x[j];
+    const double* cr = Ct + (size_t)j * kp + c0;
+    for (int u = 0; u < kB; ++u) {
+      const double diff = xj - cr[u];
+      acc[u] = acc[u] + diff * diff;
+    }
+  }
+  for (int u = 0; u < kB; ++u) out[u] = acc[u];
+}
+
+// points i0 .. i0+7 stored transposed (coordinate j of point i at Xt[j * np + i])
+// against one centroid c.
+inline void sqd_points8(const double* Xt, int np, int i0, const double* c, int d, double* out) {
+  double acc[kB] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int j = 0; j < d; ++j) {
+    const double cj = c[j];
+    const double* xr = Xt + (size_t)j * np + i0;
+    for (int u = 0; u < kB; ++u) {
+      const double diff = xr[u] - cj;
+      acc[u] = acc[u] + diff * diff;
+    }
+  }
+  for (int u = 0; u < kB; ++u) out[u] = acc[u];
+}
+
+inline int round8(int v) { return (v + kB - 1) / kB * kB; }
+
+// A point set in both layouts: X (n x d) and Xt (d x np, np = n rounded up to 8,
+// padding points at the origin).
+struct Points {
+  const double* X;
+  std::vector<double> Xt;
+  int n, d, np;
+  Points(const double* X_, int n_, int d_) : X(X_), n(n_), d(d_), np(round8(n_)) {
+    Xt.assign((size_t)d * np, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < d; ++j) Xt[(size_t)j * np + i] = X[(size_t)i * d + j];
+  }
+};
+
+// squared distances of every point to centroid c (n entries of out)
+void dist_to(const Points& P, const double* c, double* out) {
+  double v[kB];
+  for (int i0 = 0; i0 < P.n; i0 += kB) {
+    sqd_points8(P.Xt.data(), P.np, i0, c, P.d, v);
+    for (int u = 0; u < kB && i0 + u < P.n; ++u) out[i0 + u] = v[u];
+  }
+}
+
 struct Run {
   std::vector<int> labels;
   double inertia = 0.0;
 };
 
-void seed_plusplus(const double* X, int n, int d, int k, uint64_t seed, int r, double* C) {
-  std::vector<double> mind(n), cum(n);
+void seed_plusplus(const Points& P, int k, uint64_t seed, int r, double* C) {
+  const int n = P.n, d = P.d;
+  const double* X = P.X;
+  std::vector<double> mind(n), cum(n), dist(n);
   double u = draw_uniform(seed, 0, (uint64_t)r);
   int first = std::min((int)std::floor(u * n), n - 1);
   std::memcpy(C, X + (size_t)first * d, d * sizeof(double));
-  for (int i = 0; i < n; ++i) mind[i] = sqd(X + (size_t)i * d, C, d);
+  dist_to(P, C, mind.data());
   for (int c = 1; c < k; ++c) {
     u = draw_uniform(seed, (uint64_t)c, (uint64_t)r);
     double run = 0.0;
@@ -71,36 +132,47 @@ void seed_plusplus(const double* X, int n, int d, int k, uint64_t seed, int r, d
     }
     double* cc = C + (size_t)c * d;
     std::memcpy(cc, X + (size_t)pick * d, d * sizeof(double));
-    for (int i = 0; i < n; ++i) {
-      const double v = sqd(X + (size_t)i * d, cc, d);
-      mind[i] = v < mind[i] ? v : mind[i];
-    }
+    dist_to(P, cc, dist.data());
+    for (int i = 0; i < n; ++i) mind[i] = dist[i] < mind[i] ? dist[i] : mind[i];
   }
 }
 
-void assign(const double* X, int n, int d, int k, const double* C, int* lab) {
-  for (int i = 0; i < n; ++i) {
-    const double* x = X + (size_t)i * d;
-    double best = sqd(x, C, d);
+// nearest centroid of every point (ties to the lowest index); Ct is C transposed
+void assign(const Points& P, int k, const double* Ct, int kp, int* lab) {
+  double v[kB];
+  for (int i = 0; i < P.n; ++i) {
+    const double* x = P.X + (size_t)i * P.d;
+    double best = 0.0;
     int arg = 0;
-    for (int c = 1; c < k; ++c) {
-      const double v = sqd(x, C + (size_t)c * d, d);
-      if (v < best) {
-        best = v;
-        arg = c;
+    for (int c0 = 0; c0 < k; c0 += kB) {
+      sqd_centroids8(x, Ct, kp, c0, P.d, v);
+      for (int u = 0; u < kB && c0 + u < k; ++u) {
+        if (c0 + u == 0 || v[u] < best) {
+          best = v[u];
+          arg = c0 + u;
+        }
       }
     }
     lab[i] = arg;
   }
 }
 
-Run lloyd(const double* X, int n, int d, int k, std::vector<double>& C, int max_iter) {
+void transpose_centroids(const std::vector<double>& C, int k, int d, int kp, std::vector<double>& Ct) {
+  Ct.assign((size_t)d * kp, 0.0);
+  for (int c = 0; c < k; ++c)
+    for (int j = 0; j < d; ++j) Ct[(size_t)j * kp + c] = C[(size_t)c * d + j];
+}
+
+Run lloyd(const Points& P, int k, std::vector<double>& C, int max_iter) {
+  const int n = P.n, d = P.d, kp = round8(k);
+  const double* X = P.X;
   Run out;
   std::vector<int> labels, fresh(n), counts(k);
-  std::vector<double> sum(d);
+  std::vector<double> sum(d), Ct;
   bool have = false, reseeded = false;
   for (int it = 0; it < max_iter; ++it) {
-    assign(X, n, d, k, C.data(), fresh.data());
+    transpose_centroids(C, k, d, kp, Ct);
+    assign(P, k, Ct.data(), kp, fresh.data());
     if (have && !reseeded && fresh == labels) break;
     labels = fresh;
     have = true;
@@ -144,10 +216,11 @@ Run lloyd(const double* X, int n, int d, int k, std::vector<double>& C, int max_
 csc_status kmeans_f64(const double* X, int n, int d, int k, int replicates, int max_iter,
                       uint64_t seed, int32_t* labels, double* inertia_out) {
   std::vector<Run> runs(replicates);
+  const Points P(X, n, d);
   auto work = [&](int r) {
     std::vector<double> C((size_t)k * d);
-    seed_plusplus(X, n, d, k, seed, r, C.data());
-    runs[r] = lloyd(X, n, d, k, C, max_iter);
+    seed_plusplus(P, k, seed, r, C.data());
+    runs[r] = lloyd(P, k, C, max_iter);
   };
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   const int nt = std::min<int>((int)hw, replicates);
@@ -174,11 +247,14 @@ csc_status kmeans_batched(int G, const std::vector<std::vector<double>>& X, cons
                           const uint64_t* seeds, int32_t* const* labels, double* inertia_out) {
   std::vector<std::vector<Run>> runs(G, std::vector<Run>(replicates));
   const int total = G * replicates;
+  std::vector<Points> P;
+  P.reserve(G);
+  for (int g = 0; g < G; ++g) P.emplace_back(X[g].data(), n[g], d[g]);
   auto work = [&](int job) {
     const int g = job / replicates, r = job - g * replicates;
     std::vector<double> C((size_t)k[g] * d[g]);
-    seed_plusplus(X[g].data(), n[g], d[g], k[g], seeds[g], r, C.data());
-    runs[g][r] = lloyd(X[g].data(), n[g], d[g], k[g], C, max_iter);
+    seed_plusplus(P[g], k[g], seeds[g], r, C.data());
+    runs[g][r] = lloyd(P[g], k[g], C, max_iter);
   };
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   const int nt = std::min<int>((int)hw, total);
