@@ -249,6 +249,18 @@ csc_status csc_kmeans_reduced_f64(const double* F, int32_t n, int32_t d, int32_t
                                   int32_t replicates, int32_t max_iter, uint64_t seed,
                                   int32_t* labels, double* inertia_out);
 
+/* The same k-means on the GPU, for float32 features already in device
+ * memory: one workgroup per replicate, the same sums in the same order, so
+ * labels and inertia are bit-identical to csc_kmeans_reduced's.
+ * F: device n x d with leading dimension ld.  labels: HOST int32[n].
+ * inertia_out: host or NULL.  ws: csc_kmeans_device_workspace_bytes(n, d, k,
+ * replicates).  Synchronises. */
+size_t csc_kmeans_device_workspace_bytes(int32_t n, int32_t d, int32_t k, int32_t replicates);
+csc_status csc_kmeans_reduced_device(const float* F, int32_t n, int32_t d, int32_t ld, int32_t k,
+                                     int32_t replicates, int32_t max_iter, uint64_t seed,
+                                     int32_t* labels, double* inertia_out, void* ws,
+                                     size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * Interpolation, Eq. (5), and hard labels (Alg. 2 step 7, Sec. 4.1).
  * Solves (diag(mask) + gamma (I - h~(L))) X = B for the k columns of
@@ -397,6 +409,19 @@ csc_status csc_kmeans_reduced_batched(int32_t G, const float* const* F, const in
                                       const int32_t* d, const int32_t* k, int32_t replicates,
                                       int32_t max_iter, const uint64_t* seeds,
                                       int32_t* const* labels, double* inertia_out);
+
+/* csc_kmeans_reduced_device_batched: csc_kmeans_reduced_device for G inputs
+ * (F[g] device n[g] x d[g], leading dimension d[g]) in one launch of
+ * G * replicates workgroups.  labels[g]: HOST int32[n[g]]; inertia_out: host[G]
+ * or NULL.  ws: csc_kmeans_device_workspace_bytes_batched(...). */
+size_t csc_kmeans_device_workspace_bytes_batched(int32_t G, const int32_t* n, const int32_t* d,
+                                                 const int32_t* k, int32_t replicates);
+csc_status csc_kmeans_reduced_device_batched(int32_t G, const float* const* F, const int32_t* n,
+                                             const int32_t* d, const int32_t* k,
+                                             int32_t replicates, int32_t max_iter,
+                                             const uint64_t* seeds, int32_t* const* labels,
+                                             double* inertia_out, void* ws, size_t ws_bytes,
+                                             void* stream);
 
 /* ------------------------------------------------------------------------
  * Learned lambda_k bracket.  The paper notes that a better estimate of

@@ -81,6 +81,11 @@ PROTOTYPES = {
     "csc_interpolate_batched": (i32, [pg, i32, vp, i32, pd, i32, f64, vp, vp, pi, pi, f64, i32, vp,
                                       pi, vp, pi, pd, pi, vp, sz, vp]),
     "csc_kmeans_reduced_batched": (i32, [i32, vp, pi, pi, pi, i32, i32, pu, vp, pd]),
+    "csc_kmeans_device_workspace_bytes": (sz, [i32, i32, i32, i32]),
+    "csc_kmeans_reduced_device": (i32, [vp, i32, i32, i32, i32, i32, i32, u64, pi, pd, vp, sz, vp]),
+    "csc_kmeans_device_workspace_bytes_batched": (sz, [i32, pi, pi, pi, i32]),
+    "csc_kmeans_reduced_device_batched": (i32, [i32, vp, pi, pi, pi, i32, i32, pu, vp, pd, vp, sz,
+                                                vp]),
     "csc_mlp_param_count": (i32, []),
     "csc_mlp_workspace_bytes": (sz, [i32]),
     "csc_mlp_features": (i32, [pd, i32, i32, i32, C.POINTER(C.c_float)]),

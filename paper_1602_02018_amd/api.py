@@ -196,6 +196,21 @@ def kmeans_reduced(F, k: int, seed: int, replicates: int = 20, max_iter: int = 1
     return labels, inertia.value
 
 
+def kmeans_reduced_device(F: torch.Tensor, k: int, seed: int, replicates: int = 20,
+                          max_iter: int = 100):
+    """csc_kmeans_reduced_device: the host k-means, bit for bit, on the GPU."""
+    assert F.is_cuda and F.dtype == torch.float32 and F.dim() == 2 and F.stride(1) == 1
+    n, d = F.shape
+    labels = np.zeros(n, dtype=np.int32)
+    inertia = C.c_double()
+    ws = _ws(lib().csc_kmeans_device_workspace_bytes(n, d, k, replicates), F.device)
+    check(lib().csc_kmeans_reduced_device(_ptr(F), n, d, F.stride(0), k, replicates, max_iter,
+                                          seed, labels.ctypes.data_as(_lib.pi), C.byref(inertia),
+                                          _ptr(ws), ws.numel(), _stream()),
+          "csc_kmeans_reduced_device")
+    return labels, inertia.value
+
+
 @dataclass
 class Interpolation:
     X: torch.Tensor
@@ -310,7 +325,7 @@ def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
         gamma: float = 1e-3, n_c: int | None = None, tol: float = 1e-6, max_iter: int = 1000,
         max_steps: int = 30, replicates: int = 20, kmeans_iter: int = 100, lam: float | None = None,
         bracket=None, want_X: bool = False, mlp_params: torch.Tensor | None = None,
-        reorder: bool = True, cg: int = CG_BLOCK) -> Result:
+        reorder: bool = True, cg: int = CG_BLOCK, kmeans_on_gpu: bool = True) -> Result:
     """Compressive spectral clustering (Alg. 2) with every graph-sized step on the GPU.
 
     With ``mlp_params`` the dichotomy starts from the learned bracket.  With
@@ -340,9 +355,11 @@ def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
         F = gather_rows(F_all, omega)
     else:
         F = filter(g, lam, p, d, seed, rows=omega, normalize=True)
-    Fh = F.cpu().numpy()
     t2 = time.perf_counter()
-    labels_r, inertia = kmeans_reduced(Fh, k, seed, replicates, kmeans_iter)
+    if kmeans_on_gpu:
+        labels_r, inertia = kmeans_reduced_device(F, k, seed, replicates, kmeans_iter)
+    else:
+        labels_r, inertia = kmeans_reduced(F.cpu().numpy(), k, seed, replicates, kmeans_iter)
     t3 = time.perf_counter()
     order = community_order(F_all, omega, labels_r, k) if reorder else None
     it = interpolate(g, lam, p, gamma, omega, labels_r, k, tol, max_iter, want_X=want_X,
@@ -471,9 +488,33 @@ def kmeans_reduced_batched(Fs, ks, seeds, replicates=20, max_iter=100):
     return labels, inertia
 
 
+def kmeans_reduced_device_batched(Fs, ks, seeds, replicates=20, max_iter=100):
+    G = len(Fs)
+    for f in Fs:
+        assert f.is_cuda and f.dtype == torch.float32 and f.dim() == 2 and f.is_contiguous()
+    ns = _i32([f.shape[0] for f in Fs])
+    ds = _i32([f.shape[1] for f in Fs])
+    ks = _i32(ks)
+    sd = np.ascontiguousarray(seeds, dtype=np.uint64)
+    labels = [np.zeros(f.shape[0], dtype=np.int32) for f in Fs]
+    inertia = np.zeros(G)
+    pi_ = _lib.pi
+    ws = _ws(lib().csc_kmeans_device_workspace_bytes_batched(G, ns.ctypes.data_as(pi_),
+                                                            ds.ctypes.data_as(pi_),
+                                                            ks.ctypes.data_as(pi_), replicates),
+             Fs[0].device)
+    check(lib().csc_kmeans_reduced_device_batched(
+        G, _pa([f.data_ptr() for f in Fs]), ns.ctypes.data_as(pi_), ds.ctypes.data_as(pi_),
+        ks.ctypes.data_as(pi_), replicates, max_iter, sd.ctypes.data_as(_lib.pu),
+        _pa([l.ctypes.data for l in labels]), inertia.ctypes.data_as(_lib.pd), _ptr(ws), ws.numel(),
+        _stream()), "csc_kmeans_reduced_device_batched")
+    return labels, inertia
+
+
 def run_batched(graphs, ks, ds, seeds, p=50, ns=None, gamma=1e-3, n_cs=None, tol=1e-6,
                 max_iter=1000, max_steps=30, replicates=20, kmeans_iter=100, brackets=None,
-                lams=None, want_X=False, mlp_params=None, reorder=True, cg=CG_BLOCK):
+                lams=None, want_X=False, mlp_params=None, reorder=True, cg=CG_BLOCK,
+                kmeans_on_gpu=True):
     """Alg. 2 for G graphs at once with the batched calls; graph g matches run(graphs[g], ...)."""
     G = len(graphs)
     ns = [default_n(k) for k in ks] if ns is None else list(ns)
@@ -494,9 +535,13 @@ def run_batched(graphs, ks, ds, seeds, p=50, ns=None, gamma=1e-3, n_cs=None, tol
         Fs = [gather_rows(f, o) if r else f for f, o, r in zip(F_all, omegas, re)]
     else:
         Fs = filter_batched(graphs, lams, p, ds, seeds, omegas, normalize=True)
-    Fh = [f.cpu().numpy() for f in Fs]
     t2 = time.perf_counter()
-    labels_r, inertia = kmeans_reduced_batched(Fh, ks, seeds, replicates, kmeans_iter)
+    if kmeans_on_gpu:
+        labels_r, inertia = kmeans_reduced_device_batched([f.contiguous() for f in Fs], ks, seeds,
+                                                          replicates, kmeans_iter)
+    else:
+        labels_r, inertia = kmeans_reduced_batched([f.cpu().numpy() for f in Fs], ks, seeds,
+                                                   replicates, kmeans_iter)
     t3 = time.perf_counter()
     orders = None
     if any(re):

@@ -25,6 +25,7 @@ SOURCES = {
     "order.hip": [],
     "block.hip": [],
     "kmeans.hip": ["-ffp-contract=off"],
+    "kmeans_gpu.hip": ["-ffp-contract=off"],
 }
 
 COMMON = [

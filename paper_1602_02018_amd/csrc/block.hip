@@ -16,8 +16,11 @@ namespace {
 constexpr int kT = 64;   // output tile (64 x 64 per workgroup)
 constexpr int kR = 32;   // rows (Gram) or inner columns (product) staged per round
 
-__device__ inline float panel_at(const Layout& L, const float* A, int i, int c) {
-  return A[(size_t)(c / L.pw) * L.panel_elems() + (size_t)i * L.pw + c % L.pw];
+// Offset of column c within row 0 of a panel-major block: element (i, c) is at
+// col_base(L, c) + i * pw.
+__device__ inline size_t col_base(const Layout& L, int c) {
+  const int pan = c / L.pw;
+  return (size_t)pan * L.panel_elems() + (size_t)(c - pan * L.pw);
 }
 
 // part[chunk][ti*64 + r][tj*64 + c] = sum over the chunk's rows i of
@@ -37,12 +40,19 @@ __global__ __launch_bounds__(256) void k_gram(Layout L, const float* A, const fl
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  // a thread always stages the same column (256 is a multiple of 64)
+  const int c = threadIdx.x & (kT - 1), r_0 = threadIdx.x >> 6;
+  const int ca = ti * kT + c, cb = tj * kT + c;
+  const bool va = ca < ka, vb = cb < kb;
+  const float* Ac = A + (va ? col_base(L, ca) : 0);
+  const float* Bc = B + (vb ? col_base(L, cb) : 0);
   for (int rb = r0; rb < r1; rb += kR) {
-    for (int e = threadIdx.x; e < kR * kT; e += 256) {
-      const int r = e / kT, c = e - r * kT, gi = rb + r;
-      const int ca = ti * kT + c, cb = tj * kT + c;
-      As[r][c] = (gi < r1 && ca < ka) ? panel_at(L, A, gi, ca) : 0.f;
-      Bs[r][c] = (gi < r1 && cb < kb) ? panel_at(L, B, gi, cb) : 0.f;
+#pragma unroll
+    for (int r = r_0; r < kR; r += 256 / kT) {
+      const int gi = rb + r;
+      const bool in = gi < r1;
+      As[r][c] = (in && va) ? Ac[(size_t)gi * L.pw] : 0.f;
+      Bs[r][c] = (in && vb) ? Bc[(size_t)gi * L.pw] : 0.f;
     }
     __syncthreads();
 #pragma unroll 4
@@ -96,14 +106,23 @@ __global__ __launch_bounds__(256) void k_block_mul(Layout L, float c0, const flo
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  // a thread always stages the same inner column of In1 and output column of S
+  const int xl = threadIdx.x & (kR - 1), xr0 = threadIdx.x >> 5;
+  const int sc = threadIdx.x & (kT - 1), sl0 = threadIdx.x >> 6;
+  const int gj_s = j0 + sc;
   for (int lb = 0; lb < kin; lb += kR) {
-    for (int e = threadIdx.x; e < kT * kR; e += 256) {
-      const int r = e / kR, l = e - r * kR, gi = i0 + r, gl = lb + l;
-      Xs[r][l] = (gi < L.n && gl < kin) ? panel_at(L, In1, gi, gl) : 0.f;
+    const int gl = lb + xl;
+    const bool vl = gl < kin;
+    const float* Xc = In1 + (vl ? col_base(L, gl) : 0);
+#pragma unroll
+    for (int r = xr0; r < kT; r += 256 / kR) {
+      const int gi = i0 + r;
+      Xs[r][xl] = (vl && gi < L.n) ? Xc[(size_t)gi * L.pw] : 0.f;
     }
-    for (int e = threadIdx.x; e < kR * kT; e += 256) {
-      const int l = e / kT, c = e - l * kT, gl = lb + l, gj = j0 + c;
-      Ss[l][c] = (gl < kin && gj < kout) ? S[(size_t)gl * lds + gj] : 0.0;
+#pragma unroll
+    for (int l = sl0; l < kR; l += 256 / kT) {
+      const int g2 = lb + l;
+      Ss[l][sc] = (g2 < kin && gj_s < kout) ? S[(size_t)g2 * lds + gj_s] : 0.0;
     }
     __syncthreads();
 #pragma unroll 4
@@ -120,18 +139,23 @@ __global__ __launch_bounds__(256) void k_block_mul(Layout L, float c0, const flo
     }
     __syncthreads();
   }
+  // four consecutive columns of one panel (pw is a multiple of 4): float4 access
+  const int gj = j0 + tx * 4;
+  if (gj >= W) return;
+  const size_t cb = col_base(L, gj);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int gi = i0 + ty * 4 + i;
     if (gi >= L.n) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gj = j0 + tx * 4 + j;
-      if (gj >= W) continue;
-      const size_t o = (size_t)(gj / L.pw) * L.panel_elems() + (size_t)gi * L.pw + gj % L.pw;
-      const double base = c0 != 0.f ? (double)c0 * (double)In0[o] : 0.0;
-      Out[o] = (float)(base + acc[i][j]);
-    }
+    const size_t o = cb + (size_t)gi * L.pw;
+    float4 base = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (c0 != 0.f) base = *reinterpret_cast<const float4*>(In0 + o);
+    float4 out;
+    out.x = (float)((double)c0 * (double)base.x + acc[i][0]);
+    out.y = (float)((double)c0 * (double)base.y + acc[i][1]);
+    out.z = (float)((double)c0 * (double)base.z + acc[i][2]);
+    out.w = (float)((double)c0 * (double)base.w + acc[i][3]);
+    *reinterpret_cast<float4*>(Out + o) = out;
   }
 }
 
@@ -142,7 +166,7 @@ GramPlan gram_plan(const Layout& L, int ka, int kb) {
   g.tiles_a = (ka + kT - 1) / kT;
   g.tiles_b = (kb + kT - 1) / kT;
   const int tiles = g.tiles_a * g.tiles_b;
-  int chunks = std::max(1, 1024 / tiles);
+  int chunks = std::max(1, 512 / tiles);
   const int max_chunks = (L.n + kR - 1) / kR;
   chunks = std::min(chunks, max_chunks);
   int rows = (L.n + chunks - 1) / chunks;

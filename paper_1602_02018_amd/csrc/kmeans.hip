@@ -130,6 +130,7 @@ void seed_plusplus(const Points& P, int k, uint64_t seed, int r, double* C) {
             break;
           }
     }
+    if (pick >= n) pick = n - 1;  // only with non-finite weights
     double* cc = C + (size_t)c * d;
     std::memcpy(cc, X + (size_t)pick * d, d * sizeof(double));
     dist_to(P, cc, dist.data());

@@ -1,0 +1,522 @@
+// k-means on the sampled features (Alg. 2 step 6) on the GPU, float64, with
+// the same arithmetic as the host form in kmeans.hip: k-means++ seeding from
+// Philox draws, Lloyd iterations, empty clusters re-seeded with the farthest
+// point, the lowest inertia over replicates kept.  Every sum keeps the host's
+// order (squared distances over coordinates in order, the k-means++ running
+// sum over points in order, centroids over members in index order, inertia
+// over points in order), every tie goes to the lowest index, and this file is
+// compiled without floating-point contraction, so labels and inertia are
+// bit-identical to the host's.
+//
+// One workgroup runs one replicate of one input; the parallel parts are the
+// distance evaluations (independent per point and centroid), the centroid
+// sums (independent per centroid and coordinate) and order-free reductions
+// (argmin / argmax with index ties, integer counts).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host.hpp"
+
+namespace csc {
+namespace {
+
+constexpr int kKmBlock = 1024;
+constexpr int kLdsDoubles = 6144;  // 48 KB of LDS per workgroup, reused by the phases
+
+struct KmItem {
+  const double* X;   // n x d, row-major
+  const double* Xt;  // d x n (coordinate j of point i at Xt[j * n + i])
+  int n, d, k, r, max_iter;
+  uint64_t seed;
+  double* C;        // k x d
+  double* mind;     // n (used when the weights do not fit in LDS)
+  double* cum;      // n (likewise)
+  int* lab;         // n
+  int* fresh;       // n
+  int* counts;      // k
+  int* mstart;      // k + 1
+  int* members;     // n
+  int* out_labels;  // n
+  double* out_inertia;
+};
+
+__device__ inline double sqd(const double* x, const double* c, int d) {
+  double acc = 0.0;
+  for (int j = 0; j < d; ++j) {
+    const double diff = x[j] - c[j];
+    acc = acc + diff * diff;
+  }
+  return acc;
+}
+
+// the same sum with the point read from the transposed block (coalesced
+// across the threads of a wave, one point per thread)
+__device__ inline double sqd_t(const double* Xt, int n, int i, const double* c, int d) {
+  double acc = 0.0;
+  for (int j = 0; j < d; ++j) {
+    const double diff = Xt[(size_t)j * n + i] - c[j];
+    acc = acc + diff * diff;
+  }
+  return acc;
+}
+
+__device__ inline double draw_uniform(uint64_t seed, uint64_t j, uint64_t r) {
+  const Words4 x = philox4x64_10(j, r, (uint64_t)CSC_STREAM_KMEANS, 0ull, seed, 0ull);
+  return (double)(x.x0 >> 11) * 0x1p-53;
+}
+
+// Block-wide reductions over (value, index) with index ties to the lowest.
+struct VI {
+  double v;
+  int i;
+};
+
+__device__ inline VI better_min(VI a, VI b) { return (b.v < a.v || (b.v == a.v && b.i < a.i)) ? b : a; }
+__device__ inline VI better_max(VI a, VI b) { return (b.v > a.v || (b.v == a.v && b.i < a.i)) ? b : a; }
+
+template <bool MAX>
+__device__ VI block_reduce(VI x, VI* sh) {
+  for (int o = 32; o > 0; o >>= 1) {
+    VI y;
+    y.v = __shfl_down(x.v, o, 64);
+    y.i = __shfl_down(x.i, o, 64);
+    x = MAX ? better_max(x, y) : better_min(x, y);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    VI b = sh[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = MAX ? better_max(b, sh[w]) : better_min(b, sh[w]);
+    sh[0] = b;
+  }
+  __syncthreads();
+  const VI out = sh[0];
+  __syncthreads();
+  return out;
+}
+
+__device__ inline int block_or(int v, int* sh) {
+  __syncthreads();
+  if (threadIdx.x == 0) *sh = 0;
+  __syncthreads();
+  if (v) atomicOr(sh, 1);
+  __syncthreads();
+  const int out = *sh;
+  __syncthreads();
+  return out;
+}
+
+// nearest centroid of every point, ties to the lowest index; four centroids
+// at a time (independent sums, each in coordinate order)
+__device__ void assign(const KmItem& t, const double* C, int* out) {
+  const int n = t.n, d = t.d, k = t.k;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double* x = t.Xt + i;
+    double best = 0.0;
+    int arg = 0;
+    int c = 0;
+    for (; c + 4 <= k; c += 4) {
+      const double *c0 = C + (size_t)c * d, *c1 = c0 + d, *c2 = c1 + d, *c3 = c2 + d;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      for (int j = 0; j < d; ++j) {
+        const double xj = x[(size_t)j * n];
+        const double e0 = xj - c0[j], e1 = xj - c1[j], e2 = xj - c2[j], e3 = xj - c3[j];
+        a0 = a0 + e0 * e0;
+        a1 = a1 + e1 * e1;
+        a2 = a2 + e2 * e2;
+        a3 = a3 + e3 * e3;
+      }
+      const double v[4] = {a0, a1, a2, a3};
+      for (int u = 0; u < 4; ++u)
+        if (c + u == 0 || v[u] < best) {
+          best = v[u];
+          arg = c + u;
+        }
+    }
+    for (; c < k; ++c) {
+      const double v = sqd_t(t.Xt, n, i, C + (size_t)c * d, d);
+      if (c == 0 || v < best) {
+        best = v;
+        arg = c;
+      }
+    }
+    out[i] = arg;
+  }
+}
+
+// SEED_LDS: D^2 weights and running sums in LDS; C_LDS: centroids in LDS
+// during Lloyd; LAB_LDS: labels in LDS during Lloyd (after the centroids
+// when both are).
+template <bool SEED_LDS, bool C_LDS, bool LAB_LDS>
+__global__ __launch_bounds__(kKmBlock) void k_kmeans(const KmItem* items) {
+  const KmItem t = items[blockIdx.x];
+  const int n = t.n, d = t.d, k = t.k;
+  __shared__ VI sh_vi[kKmBlock / 64];
+  __shared__ int sh_i;
+
+  // ---- k-means++ seeding.  The D^2 weights and their running sums live in
+  // LDS when they fit; one thread forms the running sum in point order,
+  // exactly as the host loop, and the first point whose running sum passes
+  // u * total is found by an index reduction.
+  __shared__ double smem[kLdsDoubles];
+  double* mind = SEED_LDS ? smem : t.mind;
+  double* cum = SEED_LDS ? smem + n : t.cum;
+  {
+    const double u = draw_uniform(t.seed, 0, (uint64_t)t.r);
+    const int first = min((int)floor(u * n), n - 1);
+    for (int j = threadIdx.x; j < d; j += blockDim.x) t.C[j] = t.X[(size_t)first * d + j];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) mind[i] = sqd_t(t.Xt, n, i, t.C, d);
+    __syncthreads();
+  }
+  for (int c = 1; c < k; ++c) {
+    const double u = draw_uniform(t.seed, (uint64_t)c, (uint64_t)t.r);
+    if (threadIdx.x == 0) {
+      double run = 0.0;
+      int i = 0;
+      for (; i + 8 <= n; i += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = mind[i + q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          run = run + v[q];
+          cum[i + q] = run;
+        }
+      }
+      for (; i < n; ++i) {
+        run = run + mind[i];
+        cum[i] = run;
+      }
+    }
+    __syncthreads();
+    const double total = cum[n - 1];
+    int pick;
+    if (total == 0.0) {
+      pick = min((int)floor(u * n), n - 1);
+    } else {
+      const double target = u * total;
+      VI x{0.0, n};
+      for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if (cum[i] > target && i < x.i) x.i = i;
+      pick = block_reduce<false>(x, sh_vi).i;
+      if (pick >= n) {  // rounding left the target at the total: last point with mass
+        VI z{0.0, n};   // n - 1 - i of the largest such i, under the lowest-index rule
+        for (int i = threadIdx.x; i < n; i += blockDim.x)
+          if (mind[i] > 0.0 && n - 1 - i < z.i) z.i = n - 1 - i;
+        const int m = block_reduce<false>(z, sh_vi).i;
+        pick = m < n ? n - 1 - m : n - 1;  // none only with non-finite weights
+      }
+    }
+    double* cc = t.C + (size_t)c * d;
+    for (int j = threadIdx.x; j < d; j += blockDim.x) cc[j] = t.X[(size_t)pick * d + j];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double v = sqd_t(t.Xt, n, i, cc, d);
+      mind[i] = v < mind[i] ? v : mind[i];
+    }
+    __syncthreads();
+  }
+
+  // ---- Lloyd iterations.  Centroids and labels move to LDS when they fit.
+  const size_t kd = (size_t)k * d;
+  double* C = C_LDS ? smem : t.C;
+  int* lab = LAB_LDS ? reinterpret_cast<int*>(smem + (C_LDS ? kd : 0)) : t.lab;
+  if (C_LDS)
+    for (size_t e = threadIdx.x; e < kd; e += blockDim.x) C[e] = t.C[e];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lab[i] = -1;
+  __syncthreads();
+  bool have = false, reseeded = false;
+  for (int it = 0; it < t.max_iter; ++it) {
+    assign(t, C, t.fresh);
+    __syncthreads();
+    int diff = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) diff |= t.fresh[i] != lab[i];
+    const int changed = block_or(diff, &sh_i);
+    if (have && !reseeded && !changed) break;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) lab[i] = t.fresh[i];
+    have = true;
+    __syncthreads();
+    // members of every cluster in index order
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+      int m = 0;
+      for (int i = 0; i < n; ++i) m += lab[i] == c;
+      t.counts[c] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int sum = 0;
+      for (int c = 0; c < k; ++c) {
+        t.mstart[c] = sum;
+        sum += t.counts[c];
+      }
+      t.mstart[k] = sum;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+      int w = t.mstart[c];
+      for (int i = 0; i < n; ++i)
+        if (lab[i] == c) t.members[w++] = i;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < k * d; e += blockDim.x) {
+      const int c = e / d, j = e - c * d;
+      const int cnt = t.counts[c];
+      if (cnt == 0) continue;
+      double acc = 0.0;
+      const double* xj = t.Xt + (size_t)j * n;
+      for (int m = t.mstart[c]; m < t.mstart[c + 1]; ++m) acc = acc + xj[t.members[m]];
+      C[(size_t)c * d + j] = acc / (double)cnt;
+    }
+    __syncthreads();
+    int empty = 0;
+    for (int c = threadIdx.x; c < k; c += blockDim.x) empty |= t.counts[c] == 0;
+    reseeded = block_or(empty, &sh_i) != 0;
+    if (reseeded) {
+      for (int c = 0; c < k; ++c) {
+        if (t.counts[c] != 0) continue;  // uniform: every thread reads the same value
+        VI x{-1.0, n};
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+          const double v = sqd_t(t.Xt, n, i, C + (size_t)lab[i] * d, d);
+          x = better_max(x, VI{v, i});
+        }
+        const int far = block_reduce<true>(x, sh_vi).i;
+        for (int j = threadIdx.x; j < d; j += blockDim.x) C[(size_t)c * d + j] = t.X[(size_t)far * d + j];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          --t.counts[lab[far]];
+          lab[far] = c;
+          t.counts[c] = 1;
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  // ---- inertia (points in order) and labels
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    t.mind[i] = sqd_t(t.Xt, n, i, C + (size_t)lab[i] * d, d);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc = acc + t.mind[i];
+    *t.out_inertia = acc;
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) t.out_labels[i] = lab[i];
+}
+
+__global__ void k_to_f64(int n, int d, const float* F, int ld, double* X, double* Xt) {
+  const size_t total = (size_t)n * d;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / d), j = (int)(e - (size_t)i * d);
+    const double v = (double)F[(size_t)i * ld + j];
+    X[e] = v;
+    Xt[(size_t)j * n + i] = v;
+  }
+}
+
+// which k_kmeans variant a (n, d, k) input takes
+int km_variant(int n, int d, int k) {
+  const size_t kd = (size_t)k * d, lab = ((size_t)n + 1) / 2;
+  const bool seed = 2 * (size_t)n <= (size_t)kLdsDoubles;
+  const bool c = kd + lab <= (size_t)kLdsDoubles;
+  const bool l = c || lab <= (size_t)kLdsDoubles;
+  return (seed ? 4 : 0) | (c ? 2 : 0) | (l ? 1 : 0);
+}
+
+hipError_t launch_km(int variant, const KmItem* items, int count, hipStream_t s) {
+  const dim3 grid((unsigned)count), block(kKmBlock);
+#define CSC_KM(A, B, C)                                                                 \
+  case (A ? 4 : 0) | (B ? 2 : 0) | (C ? 1 : 0):                                         \
+    hipLaunchKernelGGL((k_kmeans<A, B, C>), grid, block, 0, s, items);                  \
+    break;
+  switch (variant) {
+    CSC_KM(true, true, true)
+    CSC_KM(true, false, true)
+    CSC_KM(true, false, false)
+    CSC_KM(false, true, true)
+    CSC_KM(false, false, true)
+    CSC_KM(false, false, false)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef CSC_KM
+  return hipGetLastError();
+}
+
+// workspace of one input: X (n x d doubles) + per replicate C, mind, cum,
+// lab, fresh, counts, mstart, members, labels; plus inertias
+size_t km_bytes(int n, int d, int k, int reps) {
+  size_t b = 2 * align_up((size_t)n * d * sizeof(double));
+  const size_t per = align_up((size_t)k * d * sizeof(double)) + 2 * align_up((size_t)n * sizeof(double)) +
+                     4 * align_up((size_t)n * sizeof(int)) + 2 * align_up(((size_t)k + 1) * sizeof(int));
+  b += per * reps + align_up((size_t)reps * sizeof(double));
+  return b;
+}
+
+struct KmPlan {
+  double* X;
+  double* Xt;
+  std::vector<KmItem> items;
+  double* inertia;
+  int* labels0;  // replicate r's labels at labels0 + r * n
+};
+
+csc_status plan_km(Arena& ar, const float* F, int n, int d, int ld, int k, int reps, int max_iter,
+                   uint64_t seed, KmPlan& P, hipStream_t s) {
+  P.X = ar.take<double>((size_t)n * d);
+  P.Xt = ar.take<double>((size_t)n * d);
+  P.inertia = ar.take<double>(reps);
+  P.items.resize(reps);
+  P.labels0 = nullptr;
+  for (int r = 0; r < reps; ++r) {
+    KmItem& t = P.items[r];
+    t.X = P.X;
+    t.Xt = P.Xt;
+    t.n = n;
+    t.d = d;
+    t.k = k;
+    t.r = r;
+    t.max_iter = max_iter;
+    t.seed = seed;
+    t.C = ar.take<double>((size_t)k * d);
+    t.mind = ar.take<double>(n);
+    t.cum = ar.take<double>(n);
+    t.lab = ar.take<int>(n);
+    t.fresh = ar.take<int>(n);
+    t.members = ar.take<int>(n);
+    t.counts = ar.take<int>((size_t)k + 1);
+    t.mstart = ar.take<int>((size_t)k + 1);
+    t.out_labels = ar.take<int>(n);
+    t.out_inertia = P.inertia + r;
+  }
+  if (!ar.ok()) {
+    set_error("internal: k-means workspace overflow");
+    return CSC_E_INVALID_ARG;
+  }
+  hipLaunchKernelGGL(k_to_f64, dim3((unsigned)std::min<size_t>(((size_t)n * d + 255) / 256, 4096)),
+                     dim3(256), 0, s, n, d, F, ld, P.X, P.Xt);
+  CSC_HIP(hipGetLastError());
+  return CSC_OK;
+}
+
+// best replicate in replicate order (first minimum), as the host form
+csc_status finish_km(const KmPlan& P, int n, int reps, int32_t* labels, double* inertia_out,
+                     hipStream_t s) {
+  std::vector<double> in(reps);
+  CSC_HIP(hipMemcpyAsync(in.data(), P.inertia, reps * sizeof(double), hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  int best = 0;
+  for (int r = 1; r < reps; ++r)
+    if (in[r] < in[best]) best = r;
+  CSC_HIP(hipMemcpyAsync(labels, P.items[best].out_labels, (size_t)n * sizeof(int),
+                         hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  if (inertia_out) *inertia_out = in[best];
+  return CSC_OK;
+}
+
+csc_status check_args(const float* F, int n, int d, int ld, int k, int reps, int max_iter,
+                      const int32_t* labels) {
+  CSC_REQUIRE(F && labels, "F and labels must be non-NULL");
+  CSC_REQUIRE(n >= 1 && d >= 1 && ld >= d, "need n >= 1, d >= 1, ld >= d");
+  CSC_REQUIRE(k >= 1 && k <= n, "k must lie in [1, n]");
+  CSC_REQUIRE(reps >= 1 && max_iter >= 1, "need replicates >= 1 and max_iter >= 1");
+  return CSC_OK;
+}
+
+}  // namespace
+}  // namespace csc
+
+using namespace csc;
+
+extern "C" size_t csc_kmeans_device_workspace_bytes(int32_t n, int32_t d, int32_t k,
+                                                    int32_t replicates) {
+  if (n < 1 || d < 1 || k < 1 || replicates < 1) return 0;
+  return km_bytes(n, d, k, replicates) + 256 * (14 * (size_t)replicates + 6);
+}
+
+extern "C" csc_status csc_kmeans_reduced_device(const float* F, int32_t n, int32_t d, int32_t ld,
+                                                int32_t k, int32_t replicates, int32_t max_iter,
+                                                uint64_t seed, int32_t* labels,
+                                                double* inertia_out, void* ws, size_t ws_bytes,
+                                                void* stream) {
+  clear_error();
+  CSC_TRY(check_args(F, n, d, ld, k, replicates, max_iter, labels));
+  CSC_TRY(check_ws(ws, ws_bytes, csc_kmeans_device_workspace_bytes(n, d, k, replicates)));
+  hipStream_t s = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  KmPlan P;
+  CSC_TRY(plan_km(ar, F, n, d, ld, k, replicates, max_iter, seed, P, s));
+  KmItem* d_items = ar.take<KmItem>(replicates);
+  if (!ar.ok()) {
+    set_error("internal: k-means workspace overflow");
+    return CSC_E_INVALID_ARG;
+  }
+  CSC_HIP(hipMemcpyAsync(d_items, P.items.data(), replicates * sizeof(KmItem),
+                         hipMemcpyHostToDevice, s));
+  CSC_HIP(launch_km(km_variant(n, d, k), d_items, replicates, s));
+  return finish_km(P, n, replicates, labels, inertia_out, s);
+}
+
+extern "C" size_t csc_kmeans_device_workspace_bytes_batched(int32_t G, const int32_t* n,
+                                                            const int32_t* d, const int32_t* k,
+                                                            int32_t replicates) {
+  if (G < 1 || !n || !d || !k || replicates < 1) return 0;
+  size_t b = 256 * 4 + align_up((size_t)G * replicates * sizeof(KmItem));
+  for (int g = 0; g < G; ++g) b += csc_kmeans_device_workspace_bytes(n[g], d[g], k[g], replicates);
+  return b;
+}
+
+extern "C" csc_status csc_kmeans_reduced_device_batched(int32_t G, const float* const* F,
+                                                        const int32_t* n, const int32_t* d,
+                                                        const int32_t* k, int32_t replicates,
+                                                        int32_t max_iter, const uint64_t* seeds,
+                                                        int32_t* const* labels,
+                                                        double* inertia_out, void* ws,
+                                                        size_t ws_bytes, void* stream) {
+  clear_error();
+  CSC_REQUIRE(G >= 1 && F && n && d && k && seeds && labels, "bad batched k-means arguments");
+  for (int g = 0; g < G; ++g)
+    CSC_TRY(check_args(F[g], n[g], d[g], d[g], k[g], replicates, max_iter, labels[g]));
+  CSC_TRY(check_ws(ws, ws_bytes, csc_kmeans_device_workspace_bytes_batched(G, n, d, k, replicates)));
+  hipStream_t s = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  std::vector<KmPlan> P(G);
+  std::vector<KmItem> all;
+  std::vector<int> var;  // inputs grouped by kernel variant, one launch per group
+  for (int v = 7; v >= 0; --v)
+    for (int g = 0; g < G; ++g)
+      if (km_variant(n[g], d[g], k[g]) == v) var.push_back(g);
+  std::vector<std::pair<int, int>> launches;  // (variant, item count)
+  for (int g : var) {
+    CSC_TRY(plan_km(ar, F[g], n[g], d[g], d[g], k[g], replicates, max_iter, seeds[g], P[g], s));
+    all.insert(all.end(), P[g].items.begin(), P[g].items.end());
+    const int v = km_variant(n[g], d[g], k[g]);
+    if (launches.empty() || launches.back().first != v)
+      launches.push_back({v, 0});
+    launches.back().second += replicates;
+  }
+  KmItem* d_items = ar.take<KmItem>(all.size());
+  if (!ar.ok()) {
+    set_error("internal: k-means workspace overflow");
+    return CSC_E_INVALID_ARG;
+  }
+  CSC_HIP(hipMemcpyAsync(d_items, all.data(), all.size() * sizeof(KmItem), hipMemcpyHostToDevice,
+                         s));
+  size_t off = 0;
+  for (const auto& l : launches) {
+    CSC_HIP(launch_km(l.first, d_items + off, l.second, s));
+    off += l.second;
+  }
+  for (int g = 0; g < G; ++g)
+    CSC_TRY(finish_km(P[g], n[g], replicates, labels[g], inertia_out ? inertia_out + g : nullptr,
+                      s));
+  return CSC_OK;
+}
