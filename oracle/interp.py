@@ -8,7 +8,9 @@ gives the linear system
     (M^T M + gamma g~(L)) x_j = M^T c_j^r,
 
 where M^T M = diag(mask) (mask_i = 1 iff node i is sampled) and M^T c_j^r puts
-a 1 at every sampled node that k-means placed in cluster j.
+a 1 at every sampled node that k-means placed in cluster j.  With the
+weighted fidelity term of variable-density sampling, the 1s become the
+decoder weights of the sampled nodes.
 
 Readings taken:
 * g~ = 1 - h~ with the same order and Jackson damping as the low-pass, so the
@@ -28,10 +30,18 @@ from .cheb import filter_block
 from .jackson import lowpass_coeffs
 
 
-def rhs(N: int, omega: np.ndarray, labels_r: np.ndarray, k: int) -> np.ndarray:
+def rhs(N: int, omega: np.ndarray, labels_r: np.ndarray, k: int, weights=None) -> np.ndarray:
+    """M^T W c_j^r for every j: weight w_s at (omega_s, labels_r[s]) (W = I by default)."""
     B = np.zeros((N, k))
-    B[np.asarray(omega), np.asarray(labels_r)] = 1.0
+    B[np.asarray(omega), np.asarray(labels_r)] = 1.0 if weights is None else np.asarray(weights)
     return B
+
+
+def sample_mask(N: int, omega: np.ndarray, weights=None) -> np.ndarray:
+    """Diagonal of M^T W M."""
+    mask = np.zeros(N)
+    mask[np.asarray(omega)] = 1.0 if weights is None else np.asarray(weights)
+    return mask
 
 
 def apply_operator(A, mask: np.ndarray, gamma: float, a: np.ndarray, X: np.ndarray) -> np.ndarray:
@@ -87,11 +97,13 @@ def hard_labels(X: np.ndarray) -> np.ndarray:
     return lab
 
 
-def interpolate(A, lam_k, p, gamma, omega, labels_r, k, tol=1e-6, max_iter=1000):
+def interpolate(A, lam_k, p, gamma, omega, labels_r, k, tol=1e-6, max_iter=1000, weights=None):
+    """Eq. (5) for every cluster; with ``weights`` (w_s > 0 per sampled node)
+    the fidelity term is Puy et al.'s weighted ||W^(1/2) (M x - c_j^r)||^2
+    used with variable-density sampling: (M^T W M + gamma g~(L)) x = M^T W c_j^r."""
     N = A.shape[0]
-    mask = np.zeros(N)
-    mask[np.asarray(omega)] = 1.0
+    mask = sample_mask(N, omega, weights)
     a = lowpass_coeffs(lam_k, p)
-    B = rhs(N, omega, labels_r, k)
+    B = rhs(N, omega, labels_r, k, weights)
     X, iters, relres = cg(A, mask, gamma, a, B, tol, max_iter)
     return X, hard_labels(X), iters, relres
