@@ -270,6 +270,10 @@ csc_status csc_kmeans_reduced_device(const float* F, int32_t n, int32_t d, int32
  * sizes and residual norms; column j stops when ||r_j|| / ||b_j|| <= tol.
  * Then labels[i] = argmax_j X_ij / ||X_j|| (ties and zero columns -> lowest j).
  * idx, labels_r: device int32[n] (idx distinct, labels_r in [0, k)).
+ * weights: device float[n] or NULL (all 1).  Fidelity weight w_s of sampled
+ *   node idx[s]: the system becomes (M^T W M + gamma g~(L)) X = M^T W B, the
+ *   weighted fidelity term that goes with variable-density sampling
+ *   (csc_sample_density's decoder weights).
  * X: device N x k with leading dimension ldx >= k.  labels: device int32[N].
  * iters_out: host int32[k] or NULL; relres_out: host double[k] or NULL.
  * order: device int32[N] permutation of [0, N), or NULL.  With an order the
@@ -298,7 +302,8 @@ enum { CSC_CG_COLUMNS = 0, CSC_CG_BLOCK = 1 };
 size_t csc_interpolate_workspace_bytes(int32_t N, int64_t nnz, int32_t k, int32_t n);
 csc_status csc_interpolate(const csc_graph* g, const int32_t* order, int32_t method,
                            double lambda_k, int32_t p, double gamma, const int32_t* idx,
-                           const int32_t* labels_r, int32_t n, int32_t k, double tol,
+                           const int32_t* labels_r, const float* weights, int32_t n, int32_t k,
+                           double tol,
                            int32_t max_iter, float* X, int32_t ldx, int32_t* labels,
                            int32_t* iters_out, double* relres_out, void* ws, size_t ws_bytes,
                            void* stream);
@@ -325,6 +330,30 @@ csc_status csc_community_order(int32_t N, const float* F, int64_t ldf, int32_t d
                                const int32_t* idx, const int32_t* labels_r, int32_t n, int32_t k,
                                int32_t* order, int32_t* node_labels, void* ws, size_t ws_bytes,
                                void* stream);
+
+/* Variable-density sampling (Alg. 2 step 5 with the sampling distribution
+ * that Sec. 3.2.3 points to: p_i proportional to the local cumulative
+ * coherence v_k(i)^2, estimated by the squared row norms of the filtered
+ * signals, Sec. 4.1).  n distinct nodes by successive sampling, as an
+ * exponential race: node i gets the float64 key E_i / w_i with
+ * E_i = -ln(u_i), u_i = ((x0 >> 11) + 1) 2^-53 from Philox at counter
+ * (i, 1, SAMPLE, 0) (+inf when w_i <= 0); idx lists the n smallest
+ * (key, index) pairs in increasing order.
+ * w: device double[N] (csc_normalize_rows' squared norms).  idx: device
+ * int32[n].  dec_weights: device float[n] or NULL: the decoder weights
+ * 1 / (N p_i) = (sum(w) / N) / w_i of the sampled nodes (0 where w_i = 0),
+ * for csc_interpolate.  ws: csc_sample_density_workspace_bytes(N).
+ * Synchronises. */
+size_t csc_sample_density_workspace_bytes(int32_t N);
+csc_status csc_sample_density(int32_t N, int32_t n, uint64_t seed, const double* w, int32_t* idx,
+                              float* dec_weights, void* ws, size_t ws_bytes, void* stream);
+
+/* Unit-length rows in place (Alg. 2 step 4), with the same arithmetic as
+ * csc_filter's normalisation: s_i = sum_j Y_ij^2 in float64, Y_ij <- Y_ij / sqrt(s_i)
+ * (a zero row stays zero).  sqnorm: device double[n_rows] receiving s_i, or
+ * NULL.  Y: device n_rows x d with leading dimension ld. */
+csc_status csc_normalize_rows(float* Y, int64_t ld, int32_t n_rows, int32_t d, double* sqnorm,
+                              void* stream);
 
 /* Rows of a device block: out[s, :] = F[rows[s], :] for s < n (Alg. 2 step 5,
  * the sampled features F_Omega from the features of every node).  F: device
@@ -388,14 +417,16 @@ csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, const double* 
  * with ldx[g] (X or X[g] may be NULL), labels: device per-graph int32[N_g].
  * iters_out / relres_out: host arrays of sum_g k[g] entries (graph-major) or
  * NULL.  order: NULL, or per-graph device int32[N_g] node orders (entries
- * may be NULL), and method, as in csc_interpolate.  Returns CSC_W_NOT_CONVERGED if any
+ * may be NULL); weights: NULL, or per-graph device float[n[g]] (entries may
+ * be NULL); method: as in csc_interpolate.  Returns CSC_W_NOT_CONVERGED if any
  * graph did not converge. */
 size_t csc_interpolate_workspace_bytes_batched(const csc_graph* graphs, int32_t G,
                                                const int32_t* k, int32_t p);
 csc_status csc_interpolate_batched(const csc_graph* graphs, int32_t G, const int32_t* const* order,
                                    int32_t method, const double* lambda, int32_t p, double gamma,
                                    const int32_t* const* idx,
-                                   const int32_t* const* labels_r, const int32_t* n,
+                                   const int32_t* const* labels_r, const float* const* weights,
+                                   const int32_t* n,
                                    const int32_t* k, double tol, int32_t max_iter,
                                    float* const* X, const int32_t* ldx, int32_t* const* labels,
                                    int32_t* iters_out, double* relres_out, int32_t* status_out,

@@ -67,8 +67,11 @@ PROTOTYPES = {
     "csc_kmeans_reduced": (i32, [vp, i32, i32, i32, i32, i32, i32, u64, pi, pd]),
     "csc_kmeans_reduced_f64": (i32, [vp, i32, i32, i32, i32, i32, i32, u64, pi, pd]),
     "csc_interpolate_workspace_bytes": (sz, [i32, i64, i32, i32]),
-    "csc_interpolate": (i32, [pg, vp, i32, f64, i32, f64, vp, vp, i32, i32, f64, i32, vp, i32, vp,
-                              pi, pd, vp, sz, vp]),
+    "csc_interpolate": (i32, [pg, vp, i32, f64, i32, f64, vp, vp, vp, i32, i32, f64, i32, vp, i32,
+                              vp, pi, pd, vp, sz, vp]),
+    "csc_sample_density_workspace_bytes": (sz, [i32]),
+    "csc_sample_density": (i32, [i32, i32, u64, vp, vp, vp, vp, sz, vp]),
+    "csc_normalize_rows": (i32, [vp, i64, i32, i32, vp, vp]),
     "csc_community_order_workspace_bytes": (sz, [i32, i32, i32, i32]),
     "csc_community_order": (i32, [i32, vp, i64, i32, vp, pi, i32, i32, vp, vp, vp, sz, vp]),
     "csc_gather_rows": (i32, [vp, i64, i32, i32, vp, i32, vp, i32, vp, sz, vp]),
@@ -78,8 +81,8 @@ PROTOTYPES = {
     "csc_filter_workspace_bytes_batched": (sz, [pg, i32, pi, i32]),
     "csc_filter_batched": (i32, [pg, i32, pd, i32, pi, pu, vp, pi, i32, vp, pi, vp, sz, vp]),
     "csc_interpolate_workspace_bytes_batched": (sz, [pg, i32, pi, i32]),
-    "csc_interpolate_batched": (i32, [pg, i32, vp, i32, pd, i32, f64, vp, vp, pi, pi, f64, i32, vp,
-                                      pi, vp, pi, pd, pi, vp, sz, vp]),
+    "csc_interpolate_batched": (i32, [pg, i32, vp, i32, pd, i32, f64, vp, vp, vp, pi, pi, f64, i32,
+                                      vp, pi, vp, pi, pd, pi, vp, sz, vp]),
     "csc_kmeans_reduced_batched": (i32, [i32, vp, pi, pi, pi, i32, i32, pu, vp, pd]),
     "csc_kmeans_device_workspace_bytes": (sz, [i32, i32, i32, i32]),
     "csc_kmeans_reduced_device": (i32, [vp, i32, i32, i32, i32, i32, i32, u64, pi, pd, vp, sz, vp]),

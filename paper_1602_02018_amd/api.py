@@ -225,7 +225,8 @@ CG_COLUMNS, CG_BLOCK = 0, 1
 
 def interpolate(g: Graph, lam: float, p: int, gamma: float, idx, labels_r, k: int,
                 tol: float = 1e-6, max_iter: int = 1000, want_X: bool = True,
-                order: torch.Tensor | None = None, method: int = CG_BLOCK) -> Interpolation:
+                order: torch.Tensor | None = None, method: int = CG_BLOCK,
+                weights: torch.Tensor | None = None) -> Interpolation:
     """Eq. (5) by CG (``method``: CG_BLOCK, one block CG over the k columns, or
     CG_COLUMNS, k side-by-side CGs); with ``order`` (a permutation, see
     community_order) the solve runs on the graph listed in that order,
@@ -233,6 +234,7 @@ def interpolate(g: Graph, lam: float, p: int, gamma: float, idx, labels_r, k: in
     idx_t = _i32_device(idx, g.device)
     lab_t = _i32_device(labels_r, g.device)
     ord_t = None if order is None else _i32_device(order, g.device)
+    w_t = None if weights is None else torch.as_tensor(weights, dtype=torch.float32, device=g.device).contiguous()
     n = int(idx_t.numel())
     X = torch.empty((g.n, k), dtype=torch.float32, device=g.device) if want_X else None
     labels = torch.empty(g.n, dtype=torch.int32, device=g.device)
@@ -241,7 +243,7 @@ def interpolate(g: Graph, lam: float, p: int, gamma: float, idx, labels_r, k: in
     ws = _ws(lib().csc_interpolate_workspace_bytes(g.n, g.nnz, k, n), g.device)
     st = check(lib().csc_interpolate(g.ref, _ptr(ord_t), int(method), float(lam), p, float(gamma),
                                      _ptr(idx_t),
-                                     _ptr(lab_t), n, k, float(tol), max_iter, _ptr(X), k,
+                                     _ptr(lab_t), _ptr(w_t), n, k, float(tol), max_iter, _ptr(X), k,
                                      _ptr(labels), iters.ctypes.data_as(_lib.pi),
                                      relres.ctypes.data_as(_lib.pd), _ptr(ws), ws.numel(),
                                      _stream()), "csc_interpolate")
@@ -266,6 +268,28 @@ def community_order(F: torch.Tensor, idx, labels_r, k: int, want_labels: bool = 
                                     lab.ctypes.data_as(_lib.pi), n, k, _ptr(order), _ptr(nl),
                                     _ptr(ws), ws.numel(), _stream()), "csc_community_order")
     return (order, nl) if want_labels else order
+
+
+def normalize_rows(Y: torch.Tensor) -> torch.Tensor:
+    """Unit rows in place (csc_normalize_rows); returns the float64 squared norms."""
+    assert Y.is_cuda and Y.dtype == torch.float32 and Y.dim() == 2 and Y.stride(1) == 1
+    sq = torch.empty(Y.shape[0], dtype=torch.float64, device=Y.device)
+    check(lib().csc_normalize_rows(_ptr(Y), Y.stride(0), Y.shape[0], Y.shape[1], _ptr(sq),
+                                   _stream()), "csc_normalize_rows")
+    return sq
+
+
+def sample_density(w: torch.Tensor, n: int, seed: int, decoder_weights: bool = True):
+    """Variable-density sampling on weights w (device float64[N]); returns
+    (omega, decoder weights or None)."""
+    assert w.is_cuda and w.dtype == torch.float64 and w.dim() == 1
+    N = w.numel()
+    idx = torch.empty(n, dtype=torch.int32, device=w.device)
+    dw = torch.empty(n, dtype=torch.float32, device=w.device) if decoder_weights else None
+    ws = _ws(lib().csc_sample_density_workspace_bytes(N), w.device)
+    check(lib().csc_sample_density(N, n, seed, _ptr(w), _ptr(idx), _ptr(dw), _ptr(ws), ws.numel(),
+                                   _stream()), "csc_sample_density")
+    return idx, dw
 
 
 def gather_rows(F: torch.Tensor, rows) -> torch.Tensor:
@@ -325,7 +349,8 @@ def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
         gamma: float = 1e-3, n_c: int | None = None, tol: float = 1e-6, max_iter: int = 1000,
         max_steps: int = 30, replicates: int = 20, kmeans_iter: int = 100, lam: float | None = None,
         bracket=None, want_X: bool = False, mlp_params: torch.Tensor | None = None,
-        reorder: bool = True, cg: int = CG_BLOCK, kmeans_on_gpu: bool = True) -> Result:
+        reorder: bool = True, cg: int = CG_BLOCK, kmeans_on_gpu: bool = True,
+        sampling: str = "uniform") -> Result:
     """Compressive spectral clustering (Alg. 2) with every graph-sized step on the GPU.
 
     With ``mlp_params`` the dichotomy starts from the learned bracket.  With
@@ -349,11 +374,18 @@ def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
         bis = Bisection(lam, 0, [], np.zeros(p + 1), 0)
     t1 = time.perf_counter()
     reorder = reorder and d <= 128
-    omega = sample(g.n, n, seed, g.device)
-    if reorder:
-        F_all = filter(g, lam, p, d, seed, rows=None, normalize=True)
+    density = sampling == "density"
+    dec_w = None
+    if reorder or density:
+        F_all = filter(g, lam, p, d, seed, rows=None, normalize=False)
+        sq = normalize_rows(F_all)
+        if density:
+            omega, dec_w = sample_density(sq, n, seed)
+        else:
+            omega = sample(g.n, n, seed, g.device)
         F = gather_rows(F_all, omega)
     else:
+        omega = sample(g.n, n, seed, g.device)
         F = filter(g, lam, p, d, seed, rows=omega, normalize=True)
     t2 = time.perf_counter()
     if kmeans_on_gpu:
@@ -363,7 +395,7 @@ def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
     t3 = time.perf_counter()
     order = community_order(F_all, omega, labels_r, k) if reorder else None
     it = interpolate(g, lam, p, gamma, omega, labels_r, k, tol, max_iter, want_X=want_X,
-                     order=order, method=cg)
+                     order=order, method=cg, weights=dec_w)
     torch.cuda.current_stream().synchronize()
     t4 = time.perf_counter()
     tm.update(bisection_s=t1 - t0, features_s=t2 - t1, kmeans_s=t3 - t2, interpolate_s=t4 - t3,
@@ -436,7 +468,7 @@ def filter_batched(graphs, lams, p, ds, seeds, rows, normalize=True):
 
 
 def interpolate_batched(graphs, lams, p, gamma, idx, labels_r, ks, tol=1e-6, max_iter=1000,
-                        want_X=True, orders=None, method=CG_BLOCK):
+                        want_X=True, orders=None, method=CG_BLOCK, weights=None):
     G = len(graphs)
     ga = _graphs(graphs)
     dev = graphs[0].device
@@ -456,7 +488,8 @@ def interpolate_batched(graphs, lams, p, gamma, idx, labels_r, ks, tol=1e-6, max
     st = check(lib().csc_interpolate_batched(
         ga, G, None if ord_t is None else _pa([0 if o is None else o.data_ptr() for o in ord_t]),
         int(method), lam.ctypes.data_as(_lib.pd), p, float(gamma), _pa([x.data_ptr() for x in idx_t]),
-        _pa([x.data_ptr() for x in lab_t]), ns.ctypes.data_as(_lib.pi), ks.ctypes.data_as(_lib.pi),
+        _pa([x.data_ptr() for x in lab_t]),
+        None if weights is None else _pa([0 if w is None else w.data_ptr() for w in weights]), ns.ctypes.data_as(_lib.pi), ks.ctypes.data_as(_lib.pi),
         float(tol), max_iter, _pa([x.data_ptr() if x is not None else 0 for x in Xs]) if want_X else None,
         ks.ctypes.data_as(_lib.pi), _pa([x.data_ptr() for x in labels]),
         iters.ctypes.data_as(_lib.pi), relres.ctypes.data_as(_lib.pd), status.ctypes.data_as(_lib.pi),
@@ -514,7 +547,7 @@ def kmeans_reduced_device_batched(Fs, ks, seeds, replicates=20, max_iter=100):
 def run_batched(graphs, ks, ds, seeds, p=50, ns=None, gamma=1e-3, n_cs=None, tol=1e-6,
                 max_iter=1000, max_steps=30, replicates=20, kmeans_iter=100, brackets=None,
                 lams=None, want_X=False, mlp_params=None, reorder=True, cg=CG_BLOCK,
-                kmeans_on_gpu=True):
+                kmeans_on_gpu=True, sampling="uniform"):
     """Alg. 2 for G graphs at once with the batched calls; graph g matches run(graphs[g], ...)."""
     G = len(graphs)
     ns = [default_n(k) for k in ks] if ns is None else list(ns)
@@ -527,13 +560,27 @@ def run_batched(graphs, ks, ds, seeds, p=50, ns=None, gamma=1e-3, n_cs=None, tol
     else:
         bis = [Bisection(l, 0, [], np.zeros(p + 1), 0) for l in lams]
     t1 = time.perf_counter()
-    omegas = [sample(g.n, n, sd, g.device) for g, n, sd in zip(graphs, ns, seeds)]
+    density = sampling == "density"
     re = [reorder and d <= 128 for d in ds]
-    if any(re):
-        F_all = filter_batched(graphs, lams, p, ds, seeds,
-                               [None if r else o for r, o in zip(re, omegas)], normalize=True)
-        Fs = [gather_rows(f, o) if r else f for f, o, r in zip(F_all, omegas, re)]
+    full = [r or density for r in re]
+    dec_ws = None
+    if any(full):
+        omegas = [None if f else sample(g.n, n, sd, g.device)
+                  for g, n, sd, f in zip(graphs, ns, seeds, full)]
+        F_all = filter_batched(graphs, lams, p, ds, seeds, omegas, normalize=False)
+        dec_ws = [None] * G
+        for i in range(G):
+            if not full[i]:
+                normalize_rows(F_all[i])
+                continue
+            sq = normalize_rows(F_all[i])
+            if density:
+                omegas[i], dec_ws[i] = sample_density(sq, ns[i], seeds[i])
+            else:
+                omegas[i] = sample(graphs[i].n, ns[i], seeds[i], graphs[i].device)
+        Fs = [gather_rows(f, o) if fl else f for f, o, fl in zip(F_all, omegas, full)]
     else:
+        omegas = [sample(g.n, n, sd, g.device) for g, n, sd in zip(graphs, ns, seeds)]
         Fs = filter_batched(graphs, lams, p, ds, seeds, omegas, normalize=True)
     t2 = time.perf_counter()
     if kmeans_on_gpu:
@@ -548,7 +595,7 @@ def run_batched(graphs, ks, ds, seeds, p=50, ns=None, gamma=1e-3, n_cs=None, tol
         orders = [community_order(f, o, l, k) if r else None
                   for f, o, l, k, r in zip(F_all, omegas, labels_r, ks, re)]
     its = interpolate_batched(graphs, lams, p, gamma, omegas, labels_r, ks, tol, max_iter, want_X,
-                              orders, cg)
+                              orders, cg, dec_ws)
     torch.cuda.current_stream().synchronize()
     t4 = time.perf_counter()
     tm.update(bisection_s=t1 - t0, features_s=t2 - t1, kmeans_s=t3 - t2, interpolate_s=t4 - t3,

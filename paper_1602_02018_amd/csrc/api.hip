@@ -806,7 +806,8 @@ extern "C" size_t csc_interpolate_workspace_bytes(int32_t N, int64_t nnz, int32_
 
 extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* order,
                                       int32_t method, double lambda_k, int32_t p, double gamma,
-                                      const int32_t* idx_in, const int32_t* labels_r, int32_t n,
+                                      const int32_t* idx_in, const int32_t* labels_r,
+                                      const float* weights, int32_t n,
                                       int32_t k, double tol, int32_t max_iter, float* X,
                                       int32_t ldx, int32_t* labels, int32_t* iters_out,
                                       double* relres_out, void* ws, size_t ws_bytes,
@@ -870,7 +871,7 @@ extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* orde
   CSC_HIP(launch_fill_i32(iters, wp, 0, s));
   CSC_HIP(launch_fill_f64(relres, wp, 0.0, s));
   CSC_HIP(launch_fill_i32(flags, 4, 0, s));
-  CSC_HIP(launch_cg_scatter(L, n, idx, labels_r, Rr, P, mask, flags + 2, s));
+  CSC_HIP(launch_cg_scatter(L, n, idx, labels_r, weights, Rr, P, mask, flags + 2, s));
   CSC_HIP(launch_col_dot(L, Rr, Rr, part, s));
   CSC_HIP(launch_reduce(part, tiles, k, bnorm2, s));
   // rr = bnorm2; active = bnorm2 > 0 (beta doubles as the activity probe)

@@ -516,7 +516,7 @@ extern "C" csc_status csc_interpolate_batched(
     const csc_graph* graphs, int32_t G, const int32_t* const* order, int32_t method,
     const double* lambda,
     int32_t p, double gamma, const int32_t* const* idx_in, const int32_t* const* labels_r,
-    const int32_t* n, const int32_t* k,
+    const float* const* weights, const int32_t* n, const int32_t* k,
     double tol, int32_t max_iter, float* const* X, const int32_t* ldx, int32_t* const* labels,
     int32_t* iters_out, double* relres_out, int32_t* status_out, void* ws, size_t ws_bytes,
     void* stream) {
@@ -630,7 +630,8 @@ extern "C" csc_status csc_interpolate_batched(
     CSC_HIP(launch_fill_f32(b.mask, graphs[g].n, 0.f, s));
     CSC_HIP(launch_fill_i32(b.iters, b.wp, 0, s));
     CSC_HIP(launch_fill_f64(b.relres, b.wp, 0.0, s));
-    CSC_HIP(launch_cg_scatter(b.L, n[g], idx[g], labels_r[g], b.Rr, b.P, b.mask,
+    CSC_HIP(launch_cg_scatter(b.L, n[g], idx[g], labels_r[g], weights ? weights[g] : nullptr, b.Rr,
+                              b.P, b.mask,
                               flags + 4 * g + 2, s));
     CSC_HIP(launch_col_dot(b.L, b.Rr, b.Rr, b.part, s));
     CSC_HIP(launch_reduce(b.part, b.tiles, k[g], b.bnorm2, s));

@@ -141,12 +141,13 @@ __global__ void k_unpack(Layout L, const float* in, float* Y, int ld, int normal
   }
 }
 
-__global__ void k_normalize_rows(int n_rows, int w, float* Y, int ld) {
+__global__ void k_normalize_rows(int n_rows, int w, float* Y, int ld, double* sq) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_rows) return;
   float* y = Y + (size_t)i * ld;
   double s = 0.0;
   for (int c = 0; c < w; ++c) s += (double)y[c] * (double)y[c];
+  if (sq) sq[i] = s;
   const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
   for (int c = 0; c < w; ++c) y[c] = (float)((double)y[c] * inv);
 }
@@ -247,8 +248,8 @@ __global__ __launch_bounds__(kBlock) void k_sample_write(int N, uint64_t seed, u
 }
 
 // ------------------------------------------------------------------ CG ---
-__global__ void k_cg_scatter(Layout L, int n, const int* idx, const int* lab, float* R, float* P,
-                             float* mask, int* bad) {
+__global__ void k_cg_scatter(Layout L, int n, const int* idx, const int* lab, const float* wts,
+                             float* R, float* P, float* mask, int* bad) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int i = idx[s], j = lab[s];
@@ -256,10 +257,11 @@ __global__ void k_cg_scatter(Layout L, int n, const int* idx, const int* lab, fl
     atomicOr(bad, 1);
     return;
   }
+  const float w = wts ? wts[s] : 1.f;  // fidelity weight of sampled node s
   const size_t o = (size_t)(j / L.pw) * L.panel_elems() + (size_t)i * L.pw + j % L.pw;
-  R[o] = 1.f;
-  P[o] = 1.f;
-  mask[i] = 1.f;
+  R[o] = w;
+  P[o] = w;
+  mask[i] = w;
 }
 
 __global__ void k_cg_alpha(int k, const double* rr, const double* pAp, int* active, double* alpha,
@@ -358,9 +360,10 @@ hipError_t launch_unpack(const Layout& L, const float* in, float* Y, int ld, int
   return hipGetLastError();
 }
 
-hipError_t launch_normalize_rows(int n_rows, int w, float* Y, int ld, hipStream_t s) {
-  hipLaunchKernelGGL(k_normalize_rows, dim3(grid_for(n_rows, kBlock, 1u << 30)), dim3(kBlock), 0,
-                     s, n_rows, w, Y, ld);
+hipError_t launch_normalize_rows(int n_rows, int w, float* Y, int ld, hipStream_t s,
+                                double* sq) {
+  hipLaunchKernelGGL(k_normalize_rows, dim3(grid_for(n_rows, kBlock, 1u << 30)), dim3(kBlock), 0, s,
+                     n_rows, w, Y, ld, sq);
   return hipGetLastError();
 }
 
@@ -431,10 +434,11 @@ hipError_t sort_pairs(void* temp, size_t temp_bytes, const uint64_t* kin, uint64
                                             s);
 }
 
-hipError_t launch_cg_scatter(const Layout& L, int n, const int* idx, const int* lab, float* R,
-                             float* P, float* mask, int* bad, hipStream_t s) {
+hipError_t launch_cg_scatter(const Layout& L, int n, const int* idx, const int* lab,
+                             const float* wts, float* R, float* P, float* mask, int* bad,
+                             hipStream_t s) {
   hipLaunchKernelGGL(k_cg_scatter, dim3(grid_for(n, kBlock, 1u << 30)), dim3(kBlock), 0, s, L, n,
-                     idx, lab, R, P, mask, bad);
+                     idx, lab, wts, R, P, mask, bad);
   return hipGetLastError();
 }
 

@@ -158,7 +158,8 @@ hipError_t launch_gaussian_rows(int n_rows, int w, uint64_t seed, uint32_t t, ui
 hipError_t launch_pack(const Layout& L, const float* X, int ld, float* out, hipStream_t s);
 hipError_t launch_unpack(const Layout& L, const float* in, float* Y, int ld, int normalize,
                          hipStream_t s);
-hipError_t launch_normalize_rows(int n_rows, int w, float* Y, int ld, hipStream_t s);
+hipError_t launch_normalize_rows(int n_rows, int w, float* Y, int ld, hipStream_t s,
+                                double* sq = nullptr);
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int* p, size_t n, int v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s);
@@ -183,8 +184,9 @@ hipError_t sort_pairs(void* temp, size_t temp_bytes, const uint64_t* kin, uint64
                       const int* vin, int* vout, int count, hipStream_t s);
 
 // Conjugate gradient.
-hipError_t launch_cg_scatter(const Layout& L, int n, const int* idx, const int* lab, float* R,
-                             float* P, float* mask, int* bad, hipStream_t s);
+hipError_t launch_cg_scatter(const Layout& L, int n, const int* idx, const int* lab,
+                             const float* wts, float* R, float* P, float* mask, int* bad,
+                             hipStream_t s);
 hipError_t launch_cg_alpha(int k, const double* rr, const double* pAp, int* active,
                            double* alpha, int* breakdown, hipStream_t s);
 hipError_t launch_cg_update1(const Layout& L, const float* AP, const float* P, float* X, float* R,
@@ -230,5 +232,11 @@ size_t sort_labels_temp_bytes(int N);
 hipError_t sort_labels(void* temp, size_t temp_bytes, const int* kin, int* kout, const int* vin,
                        int* vout, int N, int key_bits, hipStream_t s);
 hipError_t launch_iota(int N, int* out, hipStream_t s);
+hipError_t launch_density_keys(int N, const double* w, uint64_t seed, uint64_t* keys, int* vals,
+                               hipStream_t s);
+hipError_t launch_sum_f64(const double* x, int N, double* part, int nparts, double* out,
+                          hipStream_t s);
+hipError_t launch_decoder_weights(int n, const int* idx, const double* w, const double* sum, int N,
+                                  float* out, hipStream_t s);
 
 }  // namespace csc

@@ -155,7 +155,81 @@ __global__ __launch_bounds__(kBlk) void k_nearest_centroid(int N, int d, const f
   if (row) labels[i] = arg;
 }
 
+// Exponential-race keys of variable-density sampling: E_i / w_i with
+// E_i = -ln(u_i), u_i = ((x0 >> 11) + 1) 2^-53 from Philox at counter
+// (i, 1, SAMPLE, 0); +inf when w_i is not positive.  A positive double's bits
+// order like the double, so the keys sort as unsigned integers.
+__global__ void k_density_keys(int N, const double* w, uint64_t seed, uint64_t* keys, int* vals) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)N;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const Words4 x = philox4x64_10((uint64_t)i, 1ull, (uint64_t)CSC_STREAM_SAMPLE, 0ull, seed, 0ull);
+    const double u = (double)((x.x0 >> 11) + 1ull) * 0x1p-53;
+    const double wi = w[i];
+    const double key = (wi > 0.0 && wi <= 1.7976931348623157e308) ? -log(u) / wi : __builtin_inf();
+    keys[i] = (uint64_t)__double_as_longlong(key);
+    vals[i] = (int)i;
+  }
+}
+
+// Per-block float64 partial sums over contiguous ranges (fixed order).
+__global__ __launch_bounds__(kBlk) void k_sum_parts(const double* x, int N, int per, double* part) {
+  __shared__ double sh[kBlk / 64];
+  const int b = blockIdx.x;
+  const size_t lo = (size_t)b * per, hi = min((size_t)N, lo + per);
+  double acc = 0.0;
+  for (size_t i = lo + threadIdx.x; i < hi; i += kBlk) acc += x[i];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBlk / 64; ++w) t += sh[w];
+    part[b] = t;
+  }
+}
+
+__global__ void k_sum_final(const double* part, int nparts, double* out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double t = 0.0;
+    for (int b = 0; b < nparts; ++b) t += part[b];
+    *out = t;
+  }
+}
+
+// decoder weight 1 / (N p_i) = (sum(w) / N) / w_i of every sampled node
+__global__ void k_decoder_weights(int n, const int* idx, const double* w, const double* sum, int N,
+                                  float* out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const double wi = w[idx[s]];
+  out[s] = wi > 0.0 ? (float)((*sum / (double)N) / wi) : 0.f;
+}
+
 }  // namespace
+
+hipError_t launch_density_keys(int N, const double* w, uint64_t seed, uint64_t* keys, int* vals,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_density_keys, dim3(blocks_for(N, kBlk)), dim3(kBlk), 0, s, N, w, seed, keys,
+                     vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_f64(const double* x, int N, double* part, int nparts, double* out,
+                          hipStream_t s) {
+  const int per = (N + nparts - 1) / nparts;
+  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)nparts), dim3(kBlk), 0, s, x, N, per, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, s, part, nparts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_decoder_weights(int n, const int* idx, const double* w, const double* sum, int N,
+                                  float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_decoder_weights, dim3((n + kBlk - 1) / kBlk), dim3(kBlk), 0, s, n, idx, w,
+                     sum, N, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_perm_inverse(int N, const int* order, int* inv, int* bad, hipStream_t s) {
   hipLaunchKernelGGL(k_perm_inverse, dim3(blocks_for(N, kBlk)), dim3(kBlk), 0, s, N, order, inv,
@@ -336,5 +410,57 @@ extern "C" csc_status csc_community_order(int32_t N, const float* F, int64_t ldf
   if (node_labels)
     CSC_HIP(hipMemcpyAsync(node_labels, lab, (size_t)N * sizeof(int), hipMemcpyDeviceToDevice, s));
   CSC_HIP(hipStreamSynchronize(s));
+  return CSC_OK;
+}
+
+namespace {
+constexpr int kSumParts = 256;
+size_t density_bytes(int N) {
+  size_t b = 2 * align_up((size_t)N * sizeof(uint64_t)) + 2 * align_up((size_t)N * sizeof(int));
+  b += align_up(sort_pairs_temp_bytes(N)) + align_up(kSumParts * sizeof(double));
+  return b + align_up(4 * sizeof(double)) + 256;
+}
+}  // namespace
+
+extern "C" size_t csc_sample_density_workspace_bytes(int32_t N) {
+  if (N < 1) return 0;
+  return density_bytes(N);
+}
+
+extern "C" csc_status csc_sample_density(int32_t N, int32_t n, uint64_t seed, const double* w,
+                                         int32_t* idx, float* dec_weights, void* ws,
+                                         size_t ws_bytes, void* stream) {
+  clear_error();
+  CSC_REQUIRE(N >= 1 && n >= 1 && n <= N, "need 1 <= n <= N");
+  CSC_REQUIRE(w && idx, "w and idx must be non-NULL");
+  CSC_TRY(check_ws(ws, ws_bytes, density_bytes(N)));
+  hipStream_t s = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  uint64_t* kin = ar.take<uint64_t>(N);
+  uint64_t* kout = ar.take<uint64_t>(N);
+  int* vin = ar.take<int>(N);
+  int* vout = ar.take<int>(N);
+  const size_t temp_bytes = sort_pairs_temp_bytes(N);
+  void* temp = ar.take<char>(temp_bytes);
+  double* part = ar.take<double>(kSumParts);
+  double* sum = ar.take<double>(4);
+  CSC_HIP(launch_density_keys(N, w, seed, kin, vin, s));
+  CSC_HIP(sort_pairs(temp, temp_bytes, kin, kout, vin, vout, N, s));
+  CSC_HIP(hipMemcpyAsync(idx, vout, (size_t)n * sizeof(int), hipMemcpyDeviceToDevice, s));
+  if (dec_weights) {
+    CSC_HIP(launch_sum_f64(w, N, part, std::min(kSumParts, N), sum, s));
+    CSC_HIP(launch_decoder_weights(n, vout, w, sum, N, dec_weights, s));
+  }
+  CSC_HIP(hipStreamSynchronize(s));
+  return CSC_OK;
+}
+
+extern "C" csc_status csc_normalize_rows(float* Y, int64_t ld, int32_t n_rows, int32_t d,
+                                         double* sqnorm, void* stream) {
+  clear_error();
+  CSC_REQUIRE(n_rows >= 0 && d >= 1 && ld >= d, "need n_rows >= 0, d >= 1, ld >= d");
+  CSC_REQUIRE(Y || n_rows == 0, "Y is NULL");
+  if (n_rows == 0) return CSC_OK;
+  CSC_HIP(launch_normalize_rows(n_rows, d, Y, (int)ld, as_stream(stream), sqnorm));
   return CSC_OK;
 }

@@ -70,11 +70,11 @@ def test_argument_errors_are_reported_without_gpu_work():
     st = C.c_int32()
     assert lib.csc_estimate_lambda_k(C.byref(g), 11, 50, 4, 0, 30, None, C.byref(lam), C.byref(st),
                                      None, None, None, 0, None) == _lib.CSC_E_INVALID_ARG
-    assert lib.csc_interpolate(C.byref(g), None, 1, 0.5, 50, 0.0, C.c_void_p(16), C.c_void_p(16), 2,
-                               2, 1e-6, 10, None, 2, C.c_void_p(16), None, None, None, 0,
+    assert lib.csc_interpolate(C.byref(g), None, 1, 0.5, 50, 0.0, C.c_void_p(16), C.c_void_p(16),
+                               None, 2, 2, 1e-6, 10, None, 2, C.c_void_p(16), None, None, None, 0,
                                None) == _lib.CSC_E_INVALID_ARG
-    assert lib.csc_interpolate(C.byref(g), None, 2, 0.5, 50, 1e-3, C.c_void_p(16), C.c_void_p(16), 2,
-                               2, 1e-6, 10, None, 2, C.c_void_p(16), None, None, None, 0,
+    assert lib.csc_interpolate(C.byref(g), None, 2, 0.5, 50, 1e-3, C.c_void_p(16), C.c_void_p(16),
+                               None, 2, 2, 1e-6, 10, None, 2, C.c_void_p(16), None, None, None, 0,
                                None) == _lib.CSC_E_INVALID_ARG
     assert b"method" in lib.csc_last_error()
     # community order: d above the register-resident limit, labels outside [0, k)
@@ -88,6 +88,9 @@ def test_argument_errors_are_reported_without_gpu_work():
     assert lib.csc_gather_rows(C.c_void_p(16), 4, 10, 8, C.c_void_p(16), 2, C.c_void_p(16), 8,
                                None, 0, None) == _lib.CSC_E_INVALID_ARG
     assert b"ldf" in lib.csc_last_error()
+    assert lib.csc_sample_density(10, 11, 0, C.c_void_p(16), C.c_void_p(16), None, None, 0,
+                                  None) == _lib.CSC_E_INVALID_ARG
+    assert lib.csc_normalize_rows(C.c_void_p(16), 2, 4, 3, None, None) == _lib.CSC_E_INVALID_ARG
 
 
 def test_workspace_sizes_grow_with_problem():
