@@ -10,8 +10,9 @@ labels.  Prints one JSON line:
 * value: whole-job throughput in GB/s, the algorithmic bytes of every
   Chebyshev step, random block and CG update in the step divided by the wall
   time of the step;
-* roofline: the dominant kernel, the Chebyshev step of the CG operator at width
-  k, timed per launch with HIP events on the stream it runs on, against the
+* roofline: the dominant kernel, the Chebyshev (Clenshaw) step of the CG
+  operator at width k on the graph in community order, timed per launch with
+  HIP events on the stream it runs on, against the
   MI355X HBM peak (8 TB/s); its HBM traffic comes from rocprofv3 FETCH_SIZE /
   WRITE_SIZE counters recorded in profiles/ and is null when the kernel source
   changed since they were taken;
@@ -52,19 +53,27 @@ def step_bytes(N, nnz, w, kind):
     """Algorithmic bytes of one Chebyshev step (float32 blocks, int32 indices).
 
     CSR read once (4(N+1) + 8 nnz) plus, per node and column, 4 bytes for each
-    block touched: gathered T_m, T_{m-1}, T_{m+1} and the accumulator
-    read + write (kind "y": 20), or T_0 instead of the accumulator ("mom": 16).
+    block touched: forward recurrence with a running sum, gathered T_m,
+    T_{m-1}, T_{m+1} and the sum read + write (kind "y": 20); the moment form
+    reads T_0 instead of the sum ("mom": 16); Clenshaw's step reads the
+    gathered b_{m+1}, b_{m+2} and R and writes b_m ("clen": 16).
     """
     csr = 4 * (N + 1) + 8 * nnz
-    per = {"y": 20, "mom": 16, "ys": 12}[kind]
+    per = {"y": 20, "mom": 16, "ys": 12, "clen": 16}[kind]
     return csr + per * N * w
+
+
+# block CG per iteration besides the pass, in N x k blocks touched: Gram Z^T Z
+# (1), P = Z T (2), Grams P^T Q and P^T R (4), X and R updates (6), column
+# norms of R (1), Gram Q^T R (2), Z = R + P beta (3)
+BLOCK_CG_BLOCKS = 19
 
 
 def job_bytes(N, nnz, k, d, n_c, p, bis_steps, cg_iters):
     gauss = 4 * N
     count = bis_steps * (gauss * n_c + p * step_bytes(N, nnz, n_c, "mom"))
-    feat = gauss * d + p * step_bytes(N, nnz, d, "ys")
-    cg = cg_iters * (p * step_bytes(N, nnz, k, "y") + 36 * N * k)
+    feat = gauss * d + p * step_bytes(N, nnz, d, "clen") + 8 * N * d
+    cg = cg_iters * (p * step_bytes(N, nnz, k, "clen") + BLOCK_CG_BLOCKS * 4 * N * k)
     return count + feat + cg
 
 
@@ -225,6 +234,14 @@ def main():
     ms_learned = (time.perf_counter() - t0) / args.steps * 1e3
     ari_lp = adjusted_rand_index(lres[-1].labels.cpu().numpy(), last.labels.cpu().numpy())
 
+    # the same graph with the one-pass KPM dichotomy
+    api.run(g, k, d, args.seed, p=p, lambda_method="kpm")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kres = [api.run(g, k, d, args.seed, p=p, lambda_method="kpm") for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    ms_kpm = (time.perf_counter() - t0) / args.steps * 1e3
+
     # dominant kernel: Chebyshev step of the CG operator (width k) on the graph
     # in the community order the interpolation runs on, per-launch time
     if last.order is not None:
@@ -232,7 +249,7 @@ def main():
         g_run = api.Graph(rp, cl, dev)
     else:
         g_run = g
-    st = api.StepTimer(g_run, k, 0)
+    st = api.StepTimer(g_run, k, 3)  # Clenshaw step, as the CG passes run it
     st.launch(10)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -244,7 +261,7 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     avg_s = e0.elapsed_time(e1) / 1e3 / launches
-    per_launch = step_bytes(N, nnz, k, "y")
+    per_launch = step_bytes(N, nnz, k, "clen")
     achieved = per_launch / avg_s / 1e9
     traffic = read_traffic(per_launch)
 
@@ -280,8 +297,18 @@ def main():
             "ari_vs_truth": round(float(adjusted_rand_index(lres[-1].labels.cpu().numpy(),
                                                             gr.truth)), 4),
         },
+        "kpm": {
+            "s_per_graph": round(ms_kpm / 1e3, 4),
+            "moment_passes": 1,
+            "tested_points": kres[-1].bisection.steps,
+            "lambda_k": kres[-1].lam,
+            "ari_vs_plain": round(float(adjusted_rand_index(kres[-1].labels.cpu().numpy(),
+                                                            last.labels.cpu().numpy())), 4),
+            "ari_vs_truth": round(float(adjusted_rand_index(kres[-1].labels.cpu().numpy(),
+                                                            gr.truth)), 4),
+        },
         "roofline": {
-            "kernel": f"k_cheb_step<EPI_Y> (CG operator pass, w={k}, "
+            "kernel": f"k_cheb_step<EPI_CLEN> (Clenshaw step of the CG operator pass, w={k}, "
                       f"panel width {api.panel_width(N, k, nnz)}"
                       f"{', community order' if last.order is not None else ''})",
             "bound": "hbm",

@@ -92,6 +92,21 @@ int32_t csc_version(void);
 csc_status csc_set_panel_width(int32_t pw);
 int32_t csc_get_panel_width(int32_t n, int64_t nnz, int32_t w);
 
+/* Evaluation form of the accumulated filters (Sec. 2.1, fast graph filtering):
+ * the features h~(L) R of every node and the CG operator's h~(L) P.
+ * CSC_FORM_FORWARD: the three-term recurrence T_{m+1} = 2 (L - I) T_m - T_{m-1}
+ *   with a running sum Y += a_m T_m (per step: the gathered T_m, T_{m-1}, the
+ *   written T_{m+1}, Y read and written: five block accesses);
+ * CSC_FORM_CLENSHAW (default): Clenshaw's backward recurrence
+ *   b_m = a_m R + 2 (L - I) b_{m+1} - b_{m+2}, h~(L) R = a_0 R + (L - I) b_1 - b_2
+ *   (gathered b_{m+1}, b_{m+2}, R, written b_m: four accesses).
+ * Both take p products by A; results agree to float32 rounding (not bit for
+ * bit).  Moment passes (eigencount) and sampled-row feature passes always use
+ * the forward recurrence.  Process-wide. */
+enum { CSC_FORM_FORWARD = 0, CSC_FORM_CLENSHAW = 1 };
+csc_status csc_set_filter_form(int32_t form);
+int32_t csc_get_filter_form(void);
+
 /* Kernel tuning knobs, process-wide; results do not depend on them.
  * CSC_TUNE_PANEL_WIDTH: as csc_set_panel_width.
  * CSC_TUNE_XCD_ORDER (0/1/2, default 1): how row tiles are spread over the
@@ -216,6 +231,21 @@ csc_status csc_eigencount(const csc_graph* g, double lambda, int32_t p, int32_t 
  * receiving the moments of the first tested point, or NULL.
  * ws: csc_estimate_workspace_bytes(N, n_signals, p).  Synchronises.
  */
+/* One-pass form of the dichotomy (kernel polynomial method).  The count of
+ * Sec. 4.3 written in the Chebyshev basis, count(lambda) = sum_m a_m(lambda)
+ * mu_m with mu_m = <R, T_m(L - I) R>, holds for every lambda with the same
+ * signals, so one moment pass (the signals of the plain search's first test,
+ * sub-stream 1) serves every tested point and the dichotomy, with the same
+ * rules as csc_estimate_lambda_k, runs on the host from the moments.
+ * Arguments and outputs as csc_estimate_lambda_k (steps_out counts tested
+ * points; one pass is run whatever their number; moments_out receives the
+ * pass's moments).  Returns CSC_W_BISECT_EXHAUSTED after max_steps tests.
+ * ws: csc_estimate_workspace_bytes(N, n_signals, p).  Synchronises. */
+csc_status csc_estimate_lambda_k_kpm(const csc_graph* g, int32_t k, int32_t p, int32_t n_signals,
+                                     uint64_t seed, int32_t max_steps, double* lambda_out,
+                                     int32_t* steps_out, double* trace_out, double* moments_out,
+                                     void* ws, size_t ws_bytes, void* stream);
+
 csc_status csc_estimate_lambda_k(const csc_graph* g, int32_t k, int32_t p, int32_t n_signals,
                                  uint64_t seed, int32_t max_steps, const double* bracket,
                                  double* lambda_out, int32_t* steps_out, double* trace_out,

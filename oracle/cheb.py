@@ -41,3 +41,23 @@ def filter_block(A, X: np.ndarray, a: np.ndarray) -> np.ndarray:
 def moments(A, R: np.ndarray, p: int) -> np.ndarray:
     """mu_m = <R, T_m(L - I) R> (Frobenius), m = 0..p."""
     return np.array([float(np.sum(R * T)) for T in chebyshev_terms(A, R, p)])
+
+
+def filter_block_clenshaw(A, X: np.ndarray, a: np.ndarray) -> np.ndarray:
+    """h~(L) X by Clenshaw's backward recurrence for Chebyshev sums.
+
+    With x = L - I (so x B = -A B):  b_{p+1} = b_{p+2} = 0,
+    b_m = a_m X + 2 x b_{m+1} - b_{m+2} for m = p, ..., 1, and
+    h~(L) X = a_0 X + x b_1 - b_2.  The same p products by A as the forward
+    recurrence; each step reads one block fewer (no running sum).
+    """
+    X = np.asarray(X, dtype=np.float64)
+    p = len(a) - 1
+    if p == 0:
+        return a[0] * X
+    b2 = np.zeros_like(X)       # b_{m+2}
+    b1 = a[p] * X               # b_p
+    for m in range(p - 1, 0, -1):
+        b0 = a[m] * X - 2.0 * (A @ b1) - b2
+        b2, b1 = b1, b0
+    return a[0] * X - (A @ b1) - b2

@@ -54,3 +54,37 @@ def estimate_lambda_k(A, k: int, p: int, n_c: int, seed: int, max_steps: int = 3
         else:
             hi = mid
     return hi, max_steps, trace, False
+
+
+def estimate_lambda_k_kpm(A, k: int, p: int, n_c: int, seed: int, max_steps: int = 30,
+                          n_signals_pass: int | None = None):
+    """One-pass form of the dichotomy (kernel polynomial method).
+
+    count(lambda) = sum_m a_m(lambda) mu_m with mu_m = <R, T_m(L - I) R> holds
+    for every lambda with the same signals R (Sec. 4.3's count written in the
+    Chebyshev basis), so one moment pass serves every tested lambda and the
+    dichotomy, with the rules of ``estimate_lambda_k``, becomes scalar work.
+    Reading taken: the pass uses the first dichotomy pass's signals (sub-stream
+    1 of stream COUNT), with ``n_signals_pass`` columns (default n_c).
+
+    Returns (lambda_hat, tested points, [(lambda_t, count_t)], converged, mu).
+    """
+    from .cheb import moments
+
+    N = A.shape[0]
+    nc = n_c if n_signals_pass is None else n_signals_pass
+    R = gaussian_block(seed, N, nc, 1, COUNT)
+    mu = moments(A, R, p)
+    lo, hi = 0.0, 2.0
+    trace = []
+    for t in range(1, max_steps + 1):
+        mid = 0.5 * (lo + hi)
+        c = float(np.dot(lowpass_coeffs(mid, p), mu))
+        trace.append((mid, c))
+        if math.floor(c + 0.5) == k:
+            return mid, t, trace, True, mu
+        if c < k:
+            lo = mid
+        else:
+            hi = mid
+    return hi, max_steps, trace, False, mu

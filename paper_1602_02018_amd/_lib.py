@@ -23,6 +23,7 @@ WARNINGS = (CSC_W_NOT_CONVERGED, CSC_W_BISECT_EXHAUSTED, CSC_W_BRACKET_MISS)
 
 STREAM_COUNT, STREAM_FEAT, STREAM_SAMPLE, STREAM_KMEANS = 1, 2, 3, 4
 TUNE_PANEL_WIDTH, TUNE_XCD_ORDER, TUNE_NONTEMPORAL, TUNE_HIP_GRAPHS = 0, 1, 2, 3
+FORM_FORWARD, FORM_CLENSHAW = 0, 1
 
 
 class CscGraph(C.Structure):
@@ -62,6 +63,7 @@ PROTOTYPES = {
     "csc_estimate_workspace_bytes": (sz, [i32, i32, i32]),
     "csc_eigencount": (i32, [pg, f64, i32, i32, u64, u32, pd, pd, vp, sz, vp]),
     "csc_estimate_lambda_k": (i32, [pg, i32, i32, i32, u64, i32, pd, pd, pi, pd, pd, vp, sz, vp]),
+    "csc_estimate_lambda_k_kpm": (i32, [pg, i32, i32, i32, u64, i32, pd, pi, pd, pd, vp, sz, vp]),
     "csc_sample_workspace_bytes": (sz, [i32, i32]),
     "csc_sample": (i32, [i32, i32, u64, vp, vp, sz, vp]),
     "csc_kmeans_reduced": (i32, [vp, i32, i32, i32, i32, i32, i32, u64, pi, pd]),
@@ -101,6 +103,8 @@ PROTOTYPES = {
                                             sz, vp]),
     "csc_cheb_steps_workspace_bytes": (sz, [i32, i32]),
     "csc_cheb_steps": (i32, [pg, i32, i32, i32, i32, vp, sz, vp]),
+    "csc_set_filter_form": (i32, [i32]),
+    "csc_get_filter_form": (i32, []),
 }
 
 

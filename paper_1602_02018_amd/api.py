@@ -75,6 +75,15 @@ def set_tuning(key: int, value: int) -> None:
     check(lib().csc_set_tuning(int(key), int(value)), "csc_set_tuning")
 
 
+def set_filter_form(form: int) -> None:
+    """Forward recurrence (0) or Clenshaw (1, default) for accumulated filters."""
+    check(lib().csc_set_filter_form(int(form)), "csc_set_filter_form")
+
+
+def get_filter_form() -> int:
+    return int(lib().csc_get_filter_form())
+
+
 def get_tuning(key: int) -> int:
     return int(lib().csc_get_tuning(int(key)))
 
@@ -167,6 +176,24 @@ def estimate_lambda_k(g: Graph, k: int, p: int, n_signals: int, seed: int, max_s
                                            trace.ctypes.data_as(_lib.pd),
                                            mom.ctypes.data_as(_lib.pd), _ptr(ws), ws.numel(),
                                            _stream()), "csc_estimate_lambda_k")
+    tr = [(trace[2 * i], trace[2 * i + 1]) for i in range(steps.value)]
+    return Bisection(lam.value, steps.value, tr, mom, st)
+
+
+def estimate_lambda_k_kpm(g: Graph, k: int, p: int, n_signals: int, seed: int,
+                          max_steps: int = 30) -> Bisection:
+    """One moment pass, then the dichotomy on its count curve (csc_estimate_lambda_k_kpm).
+    ``steps`` counts tested points; the GPU ran one pass."""
+    lam = C.c_double(0.0)
+    steps = C.c_int32(0)
+    trace = np.zeros(2 * max_steps)
+    mom = np.zeros(p + 1)
+    ws = _ws(lib().csc_estimate_workspace_bytes(g.n, n_signals, p), g.device)
+    st = check(lib().csc_estimate_lambda_k_kpm(g.ref, k, p, n_signals, seed, max_steps,
+                                               C.byref(lam), C.byref(steps),
+                                               trace.ctypes.data_as(_lib.pd),
+                                               mom.ctypes.data_as(_lib.pd), _ptr(ws), ws.numel(),
+                                               _stream()), "csc_estimate_lambda_k_kpm")
     tr = [(trace[2 * i], trace[2 * i + 1]) for i in range(steps.value)]
     return Bisection(lam.value, steps.value, tr, mom, st)
 
@@ -350,7 +377,7 @@ def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
         max_steps: int = 30, replicates: int = 20, kmeans_iter: int = 100, lam: float | None = None,
         bracket=None, want_X: bool = False, mlp_params: torch.Tensor | None = None,
         reorder: bool = True, cg: int = CG_BLOCK, kmeans_on_gpu: bool = True,
-        sampling: str = "uniform") -> Result:
+        sampling: str = "uniform", lambda_method: str = "dichotomy") -> Result:
     """Compressive spectral clustering (Alg. 2) with every graph-sized step on the GPU.
 
     With ``mlp_params`` the dichotomy starts from the learned bracket.  With
@@ -363,7 +390,10 @@ def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
     n_c = count_signals(g.n) if n_c is None else n_c
     tm = {}
     t0 = time.perf_counter()
-    if lam is None and mlp_params is not None:
+    if lam is None and lambda_method == "kpm":
+        bis = estimate_lambda_k_kpm(g, k, p, n_c, seed, max_steps)
+        lam = bis.lam
+    elif lam is None and mlp_params is not None:
         lb = estimate_lambda_k_learned(g, k, p, n_c, seed, mlp_params, max_steps)
         bis = Bisection(lb.lam, lb.steps, lb.trace, np.zeros(p + 1), lb.status)
         lam = lb.lam

@@ -20,6 +20,7 @@ namespace {
 thread_local std::string g_error;
 std::atomic<int> g_panel_override{0};
 std::atomic<int> g_tune_xcd{1};
+std::atomic<int> g_filter_form{FORM_CLENSHAW};
 std::atomic<int> g_tune_nt{0};
 std::atomic<int> g_tune_graphs{1};
 }  // namespace
@@ -172,6 +173,50 @@ struct Pass {
   float gamma = 0.f;
 };
 
+}  // namespace
+
+int filter_form() { return g_filter_form.load(); }
+
+std::vector<PassStep> pass_plan(int epi, const double* a, int p, const float* T0, float* Ta,
+                                float* Tb, int form) {
+  std::vector<PassStep> out;
+  if (form == FORM_CLENSHAW) {
+    // b_m = a_m T0 + 2 (L - I) b_{m+1} - b_{m+2} for m = p-1 .. 1 (b_p = a_p T0
+    // is folded into the coefficients, never stored), then
+    // h~(L) T0 = a_0 T0 + (L - I) b_1 - b_2; b_m lives in Ta (m odd) or Tb.
+    auto buf = [&](int m) { return (m & 1) ? Ta : Tb; };
+    for (int m = p - 1; m >= 0; --m) {
+      PassStep st;
+      const bool top = m + 1 == p;
+      st.Tm = top ? T0 : buf(m + 1);
+      st.c1 = (float)((m >= 1 ? -2.0 : -1.0) * (top ? a[p] : 1.0));
+      st.c0 = (float)(a[m] - (m + 2 == p ? a[p] : 0.0));
+      st.first = !(m + 2 <= p - 1);  // no stored b_{m+2}
+      st.Tprev = st.first ? nullptr : buf(m + 2);
+      st.Tnext = m >= 1 ? buf(m) : nullptr;
+      st.last = m == 0;
+      st.epi = m >= 1 ? EPI_CLEN : (epi == EPI_CG ? EPI_CLEN_CG : EPI_CLEN_Y);
+      out.push_back(st);
+    }
+    return out;
+  }
+  for (int m = 0; m < p; ++m) {  // step m produces T_{m+1}
+    PassStep st;
+    st.first = m == 0;
+    st.last = m + 1 == p;
+    st.Tm = st.first ? T0 : ((m & 1) ? Ta : Tb);
+    st.Tprev = st.first ? T0 : ((m - 1) == 0 ? T0 : (((m - 1) & 1) ? Ta : Tb));
+    st.Tnext = ((m + 1) & 1) ? Ta : Tb;
+    st.c0 = (float)a[0];
+    st.c1 = (float)a[m + 1];
+    st.epi = (epi == EPI_CG && st.last) ? EPI_CG : EPI_Y;
+    out.push_back(st);
+  }
+  return out;
+}
+
+namespace {
+
 // h~(L) applied to T0 by the Chebyshev recurrence; `epi` selects the
 // consumer of each T_{m+1}.  For epi == EPI_CG the steps before the last
 // accumulate into Y and the last one forms the CG operator.
@@ -192,6 +237,18 @@ csc_status chebyshev_pass(const csc_graph& g, const Layout& L, const double* a, 
   sa.gamma = b.gamma;
   apply_tuning(sa);
   const size_t nblocks = (size_t)L.np * sa.tiles;
+  if (epi == EPI_Y || epi == EPI_CG) {
+    for (const PassStep& st : pass_plan(epi, a, p, b.T0, b.Ta, b.Tb, filter_form())) {
+      sa.Tm = st.Tm;
+      sa.Tprev = st.Tprev;
+      sa.Tnext = st.Tnext;
+      sa.c0 = st.c0;
+      sa.c1 = st.c1;
+      sa.part = b.part;
+      CSC_HIP(launch_cheb_step(sa, st.epi, st.first, st.last, s));
+    }
+    return CSC_OK;
+  }
   for (int m = 0; m < p; ++m) {  // step m produces T_{m+1}
     const bool first = m == 0, last = m + 1 == p;
     sa.Tm = first ? b.T0 : ((m & 1) ? b.Ta : b.Tb);
@@ -321,6 +378,16 @@ extern "C" csc_status csc_set_panel_width(int32_t pw) {
 extern "C" int32_t csc_get_panel_width(int32_t n, int64_t nnz, int32_t w) {
   return choose_panel_width(n, w, nnz);
 }
+
+extern "C" csc_status csc_set_filter_form(int32_t form) {
+  clear_error();
+  CSC_REQUIRE(form == CSC_FORM_FORWARD || form == CSC_FORM_CLENSHAW,
+              "form must be CSC_FORM_FORWARD or CSC_FORM_CLENSHAW");
+  g_filter_form.store(form);
+  return CSC_OK;
+}
+
+extern "C" int32_t csc_get_filter_form(void) { return g_filter_form.load(); }
 
 extern "C" csc_status csc_set_tuning(int32_t key, int32_t value) {
   clear_error();
@@ -508,6 +575,48 @@ extern "C" csc_status csc_eigencount(const csc_graph* g, double lambda, int32_t 
   *count_out = count_from_moments(lambda, p, mom.data());
   if (moments_out) std::memcpy(moments_out, mom.data(), (p + 1) * sizeof(double));
   return CSC_OK;
+}
+
+extern "C" csc_status csc_estimate_lambda_k_kpm(const csc_graph* g, int32_t k, int32_t p,
+                                                int32_t n_signals, uint64_t seed,
+                                                int32_t max_steps, double* lambda_out,
+                                                int32_t* steps_out, double* trace_out,
+                                                double* moments_out, void* ws, size_t ws_bytes,
+                                                void* stream) {
+  clear_error();
+  CSC_TRY(check_graph(g));
+  CSC_REQUIRE(lambda_out && steps_out, "lambda_out and steps_out must be non-NULL");
+  CSC_REQUIRE(k >= 1 && k <= g->n, "k must lie in [1, N]");
+  CSC_REQUIRE(p >= 1 && n_signals >= 1 && max_steps >= 1,
+              "need p >= 1, n_signals >= 1 and max_steps >= 1");
+  const Layout L = make_layout(g->n, n_signals, choose_panel_width(g->n, n_signals, g->nnz));
+  CSC_TRY(check_ws(ws, ws_bytes, count_bytes(L, p)));
+  Arena ar(ws, ws_bytes);
+  const CountBuffers c = carve_count(ar, L, p);
+  std::vector<double> mom(p + 1);
+  CSC_TRY(moments_pass(*g, L, p, seed, 1, c, mom.data(), as_stream(stream)));
+  if (moments_out) std::memcpy(moments_out, mom.data(), (p + 1) * sizeof(double));
+  double lo = 0.0, hi = 2.0;
+  for (int t = 1; t <= max_steps; ++t) {
+    const double mid = 0.5 * (lo + hi);
+    const double cnt = count_from_moments(mid, p, mom.data());
+    if (trace_out) {
+      trace_out[2 * (t - 1)] = mid;
+      trace_out[2 * (t - 1) + 1] = cnt;
+    }
+    if (std::floor(cnt + 0.5) == (double)k) {
+      *lambda_out = mid;
+      *steps_out = t;
+      return CSC_OK;
+    }
+    if (cnt < k)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  *lambda_out = hi;
+  *steps_out = max_steps;
+  return CSC_W_BISECT_EXHAUSTED;
 }
 
 extern "C" csc_status csc_estimate_lambda_k(const csc_graph* g, int32_t k, int32_t p,
@@ -988,7 +1097,7 @@ extern "C" csc_status csc_cheb_steps(const csc_graph* g, int32_t w, int32_t kind
   clear_error();
   CSC_TRY(check_graph(g));
   CSC_REQUIRE(w >= 1 && steps >= 0, "need w >= 1 and steps >= 0");
-  CSC_REQUIRE(kind >= 0 && kind <= 2, "kind must be 0, 1 or 2");
+  CSC_REQUIRE(kind >= 0 && kind <= 3, "kind must be 0, 1, 2 or 3");
   const Layout L = make_layout(g->n, w, choose_panel_width(g->n, w, g->nnz));
   CSC_TRY(check_ws(ws, ws_bytes, steps_bytes(L)));
   hipStream_t s = as_stream(stream);
@@ -1022,7 +1131,7 @@ extern "C" csc_status csc_cheb_steps(const csc_graph* g, int32_t w, int32_t kind
   sa.part = part;
   sa.part2 = part;
   apply_tuning(sa);
-  const int epi = kind == 0 ? EPI_Y : (kind == 1 ? EPI_MOM : EPI_CG);
+  const int epi = kind == 0 ? EPI_Y : (kind == 1 ? EPI_MOM : (kind == 2 ? EPI_CG : EPI_CLEN));
   for (int m = 1; m <= steps; ++m) {
     // T_{m+1} from T_m (gathered) and T_{m-1}; buffers alternate as in a pass
     sa.Tm = (m & 1) ? Ta : Tb;

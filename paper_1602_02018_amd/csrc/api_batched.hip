@@ -66,6 +66,7 @@ csc_status run_pass(F&& launch, Captured& cap, hipStream_t s) {
 
 template <class T>
 csc_status upload(T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (src.empty()) return CSC_OK;
   CSC_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
   return CSC_OK;
 }
@@ -387,7 +388,8 @@ extern "C" size_t csc_filter_workspace_bytes_batched(const csc_graph* graphs, in
     u[g] = (int)max_units(graphs[g].n, d[g]);
     gu[g] = (int)((max_elems(graphs[g].n, d[g]) + kElemsPerUnit - 1) / kElemsPerUnit);
   }
-  return b + work_bytes(u) + work_bytes(gu);
+  // second descriptor set and work list: all-row graphs run the accumulated pass
+  return b + align_up((size_t)p * G * sizeof(StepArgs)) + 2 * work_bytes(u) + work_bytes(gu);
 }
 
 extern "C" csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, const double* lambda,
@@ -411,33 +413,62 @@ extern "C" csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, con
   Arena ar(ws, ws_bytes);
   std::vector<Layout> L(G);
   std::vector<int> tiles(G), units(G), gunits(G);
-  std::vector<float*> T0(G), Ta(G), Tb(G);
+  // graphs with sampled rows run the forward recurrence with the sampled-row
+  // epilogue; graphs with all rows run the accumulated pass in the process-wide
+  // form, exactly as csc_filter does, so every output matches csc_filter's
+  std::vector<float*> T0(G), Ta(G), Tb(G), Yi(G);
   std::vector<int*> slot(G);
+  std::vector<int> units_s(G, 0), units_a(G, 0);
   for (int g = 0; g < G; ++g) {
     L[g] = make_layout(graphs[g].n, d[g], choose_panel_width(graphs[g].n, d[g], graphs[g].nnz));
     tiles[g] = tiles_for(L[g]);
     units[g] = L[g].np * tiles[g];
+    (rows[g] ? units_s : units_a)[g] = units[g];
     gunits[g] = elem_units(L[g].elems());
     T0[g] = ar.take<float>(L[g].elems());
     Ta[g] = ar.take<float>(L[g].elems());
     Tb[g] = ar.take<float>(L[g].elems());
+    Yi[g] = ar.take<float>(L[g].elems());
     slot[g] = ar.take<int>(graphs[g].n);
   }
   StepArgs* d_steps = ar.take<StepArgs>((size_t)p * G);
+  StepArgs* d_steps_a = ar.take<StepArgs>((size_t)p * G);
   GaussItem* d_gauss = ar.take<GaussItem>(G);
   int* bad = ar.take<int>(G);
-  WorkList w_step, w_gauss;
-  plan_work(ar, units, chunk_for(units), w_step);
+  WorkList w_step, w_step_a, w_gauss;
+  plan_work(ar, units_s, chunk_for(units_s), w_step);
+  plan_work(ar, units_a, chunk_for(units_a), w_step_a);
   plan_work(ar, gunits, chunk_for(gunits), w_gauss);
   if (!ar.ok()) {
     set_error("internal: batched workspace plan overflow");
     return CSC_E_INVALID_ARG;
   }
-  std::vector<StepArgs> h_steps((size_t)p * G);
+  std::vector<StepArgs> h_steps((size_t)p * G), h_steps_a((size_t)p * G);
   std::vector<GaussItem> h_gauss(G);
   std::vector<double> a(p + 1);
+  const int form = filter_form();
+  std::vector<PassStep> plan0;
   for (int g = 0; g < G; ++g) {
     jackson_lowpass(lambda[g], p, a.data());
+    const std::vector<PassStep> plan = pass_plan(EPI_Y, a.data(), p, T0[g], Ta[g], Tb[g], form);
+    if (plan0.empty()) plan0 = plan;
+    for (int m = 0; m < p; ++m) {
+      StepArgs& x = h_steps_a[(size_t)m * G + g];
+      x.L = L[g];
+      x.tiles = tiles[g];
+      x.row_ptr = graphs[g].row_ptr;
+      x.col = graphs[g].col;
+      x.val = graphs[g].val;
+      x.T0 = T0[g];
+      x.Y = Yi[g];
+      apply_tuning(x);
+      x.xcd = 0;
+      x.Tm = plan[m].Tm;
+      x.Tprev = plan[m].Tprev;
+      x.Tnext = plan[m].Tnext;
+      x.c0 = plan[m].c0;
+      x.c1 = plan[m].c1;
+    }
     for (int m = 0; m < p; ++m) {
       StepArgs& x = h_steps[(size_t)m * G + g];
       x.L = L[g];
@@ -465,16 +496,16 @@ extern "C" csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, con
     h_gauss[g].out = T0[g];
   }
   CSC_TRY(upload(d_steps, h_steps, s));
+  CSC_TRY(upload(d_steps_a, h_steps_a, s));
   CSC_TRY(upload(d_gauss, h_gauss, s));
   CSC_TRY(upload(w_step.d, w_step.h, s));
+  CSC_TRY(upload(w_step_a.d, w_step_a.h, s));
   CSC_TRY(upload(w_gauss.d, w_gauss.h, s));
   CSC_HIP(launch_fill_i32(bad, G, 0, s));
   for (int g = 0; g < G; ++g) {
     if (rows[g]) {
       CSC_HIP(launch_fill_i32(slot[g], graphs[g].n, -1, s));
       CSC_HIP(launch_slot_map(n_rows[g], rows[g], graphs[g].n, slot[g], bad + g, s));
-    } else {
-      CSC_HIP(launch_iota(graphs[g].n, slot[g], s));  // every row, in node order
     }
   }
   std::vector<int> hbad(G);
@@ -486,12 +517,19 @@ extern "C" csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, con
       return CSC_E_INVALID_ARG;
     }
   CSC_HIP(launch_gaussian_batched(d_gauss, w_gauss.table(), s));
-  for (int m = 0; m < p; ++m)
+  for (int m = 0; m < p; ++m) {
     CSC_HIP(launch_cheb_step_batched(d_steps + (size_t)m * G, w_step.table(), EPI_YS, m == 0,
                                      m + 1 == p, s));
-  if (normalize)
-    for (int g = 0; g < G; ++g)
-      CSC_HIP(launch_normalize_rows(rows[g] ? n_rows[g] : graphs[g].n, d[g], Y[g], ld[g], s));
+    CSC_HIP(launch_cheb_step_batched(d_steps_a + (size_t)m * G, w_step_a.table(), plan0[m].epi,
+                                     plan0[m].first, plan0[m].last, s));
+  }
+  for (int g = 0; g < G; ++g) {
+    if (rows[g]) {
+      if (normalize) CSC_HIP(launch_normalize_rows(n_rows[g], d[g], Y[g], ld[g], s));
+    } else {
+      CSC_HIP(launch_unpack(L[g], Yi[g], Y[g], ld[g], normalize, s));
+    }
+  }
   return CSC_OK;
 }
 
@@ -666,6 +704,8 @@ extern "C" csc_status csc_interpolate_batched(
   }
 
   // descriptors of one CG iteration
+  const int form = filter_form();
+  std::vector<PassStep> plan0;
   std::vector<StepArgs> h_steps((size_t)p * G);
   std::vector<ReduceItem> h_pap(G), h_rrn(G);
   std::vector<CgItem> h_cg(G);
@@ -673,6 +713,10 @@ extern "C" csc_status csc_interpolate_batched(
   for (int g = 0; g < G; ++g) {
     const Buf& b = B[g];
     jackson_lowpass(lambda[g], p, a.data());
+    // the same launch sequence as the single-graph pass (epilogue and flags
+    // per step depend on p only, so one batched launch per step serves all)
+    const std::vector<PassStep> plan_g = pass_plan(EPI_CG, a.data(), p, b.P, b.Ta, b.Tb, form);
+    if (g == 0) plan0 = plan_g;
     for (int m = 0; m < p; ++m) {
       StepArgs& x = h_steps[(size_t)m * G + g];
       x.L = b.L;
@@ -688,12 +732,12 @@ extern "C" csc_status csc_interpolate_batched(
       apply_tuning(x);
       x.xcd = 0;
       x.live = d_live + g;
-      const bool first = m == 0;
-      x.Tm = first ? b.P : ((m & 1) ? b.Ta : b.Tb);
-      x.Tprev = first ? b.P : ((m - 1) == 0 ? b.P : (((m - 1) & 1) ? b.Ta : b.Tb));
-      x.Tnext = ((m + 1) & 1) ? b.Ta : b.Tb;
-      x.c0 = (float)a[0];
-      x.c1 = (float)a[m + 1];
+      const PassStep& ps = plan_g[m];
+      x.Tm = ps.Tm;
+      x.Tprev = ps.Tprev;
+      x.Tnext = ps.Tnext;
+      x.c0 = ps.c0;
+      x.c1 = ps.c1;
     }
     h_pap[g] = ReduceItem{b.part, b.tiles, b.pAp, d_live + g};
     h_rrn[g] = ReduceItem{b.part, b.tiles, b.rrn, d_live + g};
@@ -744,9 +788,9 @@ extern "C" csc_status csc_interpolate_batched(
     }
     auto filter_pass = [&](hipStream_t st) -> csc_status {
       for (int m = 0; m < p; ++m) {
-        const bool last = m + 1 == p;
+        const PassStep& ps = plan0[m];
         CSC_HIP(launch_cheb_step_batched(d_steps + (size_t)m * G, w_step.table(),
-                                         last ? EPI_CG : EPI_Y, m == 0, last, st));
+                                         ps.epi, ps.first, ps.last, st));
       }
       return CSC_OK;
     };
@@ -797,9 +841,9 @@ extern "C" csc_status csc_interpolate_batched(
 
   auto iteration = [&](hipStream_t st) -> csc_status {
     for (int m = 0; m < p; ++m) {
-      const bool last = m + 1 == p;
+      const PassStep& ps = plan0[m];
       CSC_HIP(launch_cheb_step_batched(d_steps + (size_t)m * G, w_step.table(),
-                                       last ? EPI_CG : EPI_Y, m == 0, last, st));
+                                       ps.epi, ps.first, ps.last, st));
     }
     CSC_HIP(launch_reduce_batched(d_red_pap, w_k.table(), st));
     CSC_HIP(launch_cg_alpha_batched(d_cg, G, st));

@@ -129,6 +129,15 @@ hipError_t launch_cheb_step_batched(const StepArgs* items, BTable t, int epi, bo
     case EPI_CG:
       if (first) CSC_BSTEP(EPI_CG, true, true); else CSC_BSTEP(EPI_CG, false, true);
       break;
+    case EPI_CLEN:
+      if (first) CSC_BSTEP(EPI_CLEN, true, false); else CSC_BSTEP(EPI_CLEN, false, false);
+      break;
+    case EPI_CLEN_Y:
+      if (first) CSC_BSTEP(EPI_CLEN_Y, true, false); else CSC_BSTEP(EPI_CLEN_Y, false, false);
+      break;
+    case EPI_CLEN_CG:
+      if (first) CSC_BSTEP(EPI_CLEN_CG, true, false); else CSC_BSTEP(EPI_CLEN_CG, false, false);
+      break;
     default:
       return hipErrorInvalidValue;
   }

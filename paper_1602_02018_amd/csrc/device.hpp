@@ -153,8 +153,55 @@ __device__ inline void column_partials(const double cs[4], const RowMap& m, int 
 }
 
 // One work unit (panel, row tile) of one Chebyshev step.
+// One step of Clenshaw's recurrence for sum_m a_m T_m(L - I) R:
+// out = c0 R + c1 (A Tm) - Tprev (Tprev only when PREV).  Each element reads
+// R, Tprev and the gathered rows of Tm and writes one block: four block
+// accesses where the forward recurrence with a running sum needs five.
+template <int EPI, bool PREV>
+__device__ inline void clen_unit(const StepArgs& a, int u) {
+  const RowMap m = row_map(a.L.pw);
+  const int panel = u / a.tiles;
+  const int tile = u - panel * a.tiles;
+  const int i = tile * m.rpb + m.r;
+  const bool valid = m.lane_ok && i < a.L.n;
+  const int nt = a.nt;
+  const size_t pbase4 = (size_t)panel * a.L.panel_elems() / 4;
+  const size_t o4 = pbase4 + (size_t)i * m.lpr + m.q;
+  const v4f* __restrict__ Tm4 = reinterpret_cast<const v4f*>(a.Tm) + pbase4;
+
+  const v4f acc = spmm_row(a, Tm4, i, m.q, m.lpr, valid);
+  v4f r = (v4f)0.f, out = (v4f)0.f;
+  if (valid) {
+    r = ld4(a.T0, o4, nt);
+    out = __builtin_elementwise_fma((v4f)a.c1, acc, (v4f)a.c0 * r);
+    if (PREV) out = out - ld4(a.Tprev, o4, nt);
+    if constexpr (EPI == EPI_CLEN) st4(a.Tnext, o4, out, nt);
+    if constexpr (EPI == EPI_CLEN_Y) st4(a.Y, o4, out, nt);
+  }
+  if constexpr (EPI == EPI_CLEN_CG) {
+    __shared__ double sh[4 * 64 * 4];
+    double cs[4] = {0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+      const float mk = a.mask[i];
+      const v4f ap = __builtin_elementwise_fma((v4f)mk, r, (v4f)a.gamma * (r - out));
+      st4(a.Y, o4, ap, nt);
+      cs[0] = (double)r.x * (double)ap.x;
+      cs[1] = (double)r.y * (double)ap.y;
+      cs[2] = (double)r.z * (double)ap.z;
+      cs[3] = (double)r.w * (double)ap.w;
+    }
+    column_partials(cs, m, a.L.pw, sh, a.part + (size_t)panel * a.L.pw * a.tiles + tile,
+                    (size_t)a.tiles);
+    __syncthreads();
+  }
+}
+
 template <int EPI, bool FIRST, bool LAST>
 __device__ inline void cheb_unit(const StepArgs& a, int u) {
+  if constexpr (EPI >= EPI_CLEN) {
+    clen_unit<EPI, !FIRST>(a, u);
+    return;
+  }
   const RowMap m = row_map(a.L.pw);
   const int panel = u / a.tiles;
   const int tile = u - panel * a.tiles;

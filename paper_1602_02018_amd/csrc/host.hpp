@@ -18,6 +18,22 @@ size_t count_bytes(const Layout& L, int p);
 size_t interp_bytes(const Layout& L);
 int use_hip_graphs();
 
+// Launch sequence of one pass h~(L) T0 for the accumulating epilogues
+// (EPI_Y: Y = h~(L) T0; EPI_CG: the CG operator), in the process-wide form:
+// forward recurrence with a running sum, or Clenshaw's backward recurrence.
+struct PassStep {
+  const float* Tm;
+  const float* Tprev;
+  float* Tnext;
+  float c0, c1;
+  int epi;
+  bool first, last;
+};
+enum { FORM_FORWARD = 0, FORM_CLENSHAW = 1 };
+int filter_form();
+std::vector<PassStep> pass_plan(int epi, const double* a, int p, const float* T0, float* Ta,
+                                float* Tb, int form);
+
 // Block conjugate gradient of the interpolation (api.hip), one graph's state;
 // the Chebyshev pass Q = M P runs between block_pre and block_post.
 struct BlockBufs {

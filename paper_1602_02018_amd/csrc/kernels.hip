@@ -42,6 +42,15 @@ hipError_t launch_step(const StepArgs& a, int epi, bool first, bool last, hipStr
     case EPI_CG:
       if (first) CSC_STEP(EPI_CG, true, true); else CSC_STEP(EPI_CG, false, true);
       break;
+    case EPI_CLEN:
+      if (first) CSC_STEP(EPI_CLEN, true, false); else CSC_STEP(EPI_CLEN, false, false);
+      break;
+    case EPI_CLEN_Y:
+      if (first) CSC_STEP(EPI_CLEN_Y, true, false); else CSC_STEP(EPI_CLEN_Y, false, false);
+      break;
+    case EPI_CLEN_CG:
+      if (first) CSC_STEP(EPI_CLEN_CG, true, false); else CSC_STEP(EPI_CLEN_CG, false, false);
+      break;
     default:
       return hipErrorInvalidValue;
   }

@@ -12,6 +12,11 @@ enum Epi : int {
   EPI_MOM = 1,  // float64 partial of <T_0, T_{m+1}> per workgroup
   EPI_YS = 2,   // only sampled rows accumulate, straight into a node-major output
   EPI_CG = 3,   // last step of the CG operator: AP = mask*P + gamma*(P - h~(L)P)
+  // Clenshaw's backward recurrence (b_m = c0 R + c1 A b_{m+1} - b_{m+2}, with
+  // T0 = R, Tm = b_{m+1}, Tprev = b_{m+2}, Tnext = b_m); FIRST = no b_{m+2}
+  EPI_CLEN = 4,     // intermediate b_m
+  EPI_CLEN_Y = 5,   // final step: Y = h~(L) R
+  EPI_CLEN_CG = 6,  // final step of the CG operator, as EPI_CG
 };
 
 struct StepArgs {

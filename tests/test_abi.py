@@ -70,6 +70,8 @@ def test_argument_errors_are_reported_without_gpu_work():
     st = C.c_int32()
     assert lib.csc_estimate_lambda_k(C.byref(g), 11, 50, 4, 0, 30, None, C.byref(lam), C.byref(st),
                                      None, None, None, 0, None) == _lib.CSC_E_INVALID_ARG
+    assert lib.csc_estimate_lambda_k_kpm(C.byref(g), 11, 50, 4, 0, 30, C.byref(lam), C.byref(st),
+                                         None, None, None, 0, None) == _lib.CSC_E_INVALID_ARG
     assert lib.csc_interpolate(C.byref(g), None, 1, 0.5, 50, 0.0, C.c_void_p(16), C.c_void_p(16),
                                None, 2, 2, 1e-6, 10, None, 2, C.c_void_p(16), None, None, None, 0,
                                None) == _lib.CSC_E_INVALID_ARG
@@ -91,6 +93,15 @@ def test_argument_errors_are_reported_without_gpu_work():
     assert lib.csc_sample_density(10, 11, 0, C.c_void_p(16), C.c_void_p(16), None, None, 0,
                                   None) == _lib.CSC_E_INVALID_ARG
     assert lib.csc_normalize_rows(C.c_void_p(16), 2, 4, 3, None, None) == _lib.CSC_E_INVALID_ARG
+
+
+def test_filter_form_setting():
+    lib = _lib.lib()
+    assert lib.csc_get_filter_form() == _lib.FORM_CLENSHAW
+    assert lib.csc_set_filter_form(5) == _lib.CSC_E_INVALID_ARG
+    assert lib.csc_set_filter_form(_lib.FORM_FORWARD) == _lib.CSC_OK
+    assert lib.csc_get_filter_form() == _lib.FORM_FORWARD
+    assert lib.csc_set_filter_form(_lib.FORM_CLENSHAW) == _lib.CSC_OK
 
 
 def test_workspace_sizes_grow_with_problem():

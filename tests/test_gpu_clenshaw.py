@@ -1,0 +1,100 @@
+"""Clenshaw evaluation of the accumulated filters against the float64 oracle
+(its Clenshaw and its forward recurrence agree to 1e-12), for every order
+edge case (p = 1, 2, 3) and panel widths; the CG operator in both forms; the
+batched interpolation bit for bit equal to the single one in each form."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import cheb, interp, jackson, laplacian, metrics, sampling
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1602_02018_amd import api as a
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    yield a
+    a.set_filter_form(1)
+    a.set_panel_width(0)
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    return synth.chung_lu_blocks(1037, 7, mean_deg=6.0, max_deg=80.0, seed=2)
+
+
+def _A(g):
+    return laplacian.normalized_adjacency(g.row_ptr, g.col)[0]
+
+
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("p", [1, 2, 3, 50])
+@pytest.mark.parametrize("pw", [4, 28, 0])
+def test_filter_block_in_both_forms(api, ragged, form, p, pw):
+    api.set_filter_form(form)
+    api.set_panel_width(pw)
+    try:
+        g = api.Graph(ragged.row_ptr, ragged.col)
+        X = api.gaussian_block(ragged.n, 19, 5, 0, 2)
+        a = jackson.lowpass_coeffs(0.35, p)
+        Y = api.filter_block(g, a, X).cpu().numpy()
+        ref = cheb.filter_block_clenshaw(_A(ragged), X.cpu().numpy().astype(np.float64), a)
+        assert np.linalg.norm(Y - ref) <= 1e-4 * np.linalg.norm(ref)
+    finally:
+        api.set_filter_form(1)
+        api.set_panel_width(0)
+
+
+def test_forms_agree_on_features(api, ragged):
+    g = api.Graph(ragged.row_ptr, ragged.col)
+    api.set_filter_form(0)
+    F0 = api.filter(g, 0.5, 50, 13, 9).cpu().numpy()
+    api.set_filter_form(1)
+    F1 = api.filter(g, 0.5, 50, 13, 9).cpu().numpy()
+    assert np.linalg.norm(F0 - F1) <= 1e-4 * np.linalg.norm(F0)  # each is within 1e-4 of float64
+
+
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("method", [0, 1])
+def test_interpolation_in_both_forms(api, form, method):
+    gr = synth.sbm_config(1000, 10, seed=0)
+    api.set_filter_form(form)
+    try:
+        g = api.Graph(gr.row_ptr, gr.col)
+        omega = sampling.sample(gr.n, 47, 0)
+        lab_r = gr.truth[omega]
+        res = api.interpolate(g, 0.46875, 50, 1e-3, omega, lab_r, 10, method=method)
+        assert res.status == 0 and np.all(res.relres <= 1e-6)
+        Xt, lab, _, _ = interp.interpolate(_A(gr), 0.46875, 50, 1e-3, omega, lab_r, 10, tol=1e-12)
+        tol = 1e-3 if method == 1 else 5e-3  # side-by-side CGs stop at the 1e-6 residual
+        assert np.linalg.norm(res.X.cpu().numpy() - Xt) <= tol * np.linalg.norm(Xt)
+        assert metrics.adjusted_rand_index(res.labels.cpu().numpy(), lab) >= 0.99
+    finally:
+        api.set_filter_form(1)
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_batched_interpolation_matches_single_in_each_form(api, ragged, form):
+    batch = [synth.sbm_config(1000, 10, seed=0), ragged]
+    api.set_filter_form(form)
+    try:
+        G = [api.Graph(b.row_ptr, b.col) for b in batch]
+        ks = [10, 7]
+        omegas = [api.sample(b.n, api.default_n(k), i) for i, (b, k) in enumerate(zip(batch, ks))]
+        labs = [np.arange(o.numel()) % k for o, k in zip(omegas, ks)]
+        res = api.interpolate_batched(G, [0.45, 0.5], 50, 1e-3, omegas, labs, ks)
+        for i, g in enumerate(G):
+            one = api.interpolate(g, [0.45, 0.5][i], 50, 1e-3, omegas[i], labs[i], ks[i])
+            assert torch.equal(res[i].X, one.X) and torch.equal(res[i].labels, one.labels)
+    finally:
+        api.set_filter_form(1)
+
+
+def test_form_setting_is_validated(api):
+    with pytest.raises(RuntimeError, match="form"):
+        api.set_filter_form(2)
+    assert api.get_filter_form() == 1

@@ -90,7 +90,9 @@ def test_sbm_1e5_sampling_and_interpolation(api, sbm1e5):
     assert torch.equal(res.labels, res2.labels) and torch.equal(res.X, res2.X)
     # the same solve on the graph in community order (the benchmarked launch)
     F_all = api.filter(g, lam, 50, d, 0, rows=None)
-    assert torch.equal(api.gather_rows(F_all, omega), F)
+    # all rows by Clenshaw, sampled rows by the forward recurrence: float32 rounding apart
+    Fg = api.gather_rows(F_all, omega)
+    assert torch.linalg.norm(Fg - F) <= 1e-4 * torch.linalg.norm(F)
     order = api.community_order(F_all, omega, lab_r, k)
     res3 = api.interpolate(g, lam, 50, 1e-3, omega, lab_r, k, order=order)
     assert res3.status == 0 and np.all(res3.relres <= 1e-6)

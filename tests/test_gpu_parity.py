@@ -160,8 +160,9 @@ def test_feature_pass_sampled_rows(api, ragged):
     Fall = api.filter(g, lam, p, d, seed, normalize=True).cpu().numpy()
     ref = ocsc.features(_A(ragged), lam, p, d, seed)[rows]
     assert _relfro(Fs, ref) <= 1e-4
-    # the sampled-row epilogue and the full pass agree to float32 rounding
-    np.testing.assert_allclose(Fs, Fall[rows], rtol=1e-5, atol=1e-6)
+    # the sampled-row epilogue (forward recurrence) and the full pass (Clenshaw
+    # by default) agree to float32 rounding
+    assert _relfro(Fs, Fall[rows].astype(np.float64)) <= 1e-4
 
 
 # ---------------------------------------------------------- eigencount -----

@@ -453,3 +453,39 @@ def test_golden_fixtures_parse():
     assert np.bincount(g.truth).tolist() == sizes
     d = json.load(open(os.path.join(GOLDEN, "alg2_defaults.json")))
     assert d["p"] == 50 and d["gamma"] == 1e-3
+
+
+def test_clenshaw_filter_equals_forward_recurrence_and_spectral_definition():
+    from oracle import cheb, jackson, laplacian
+
+    g = synth.sbm_config(400, 5, seed=7)
+    A, _ = laplacian.normalized_adjacency(g.row_ptr, g.col)
+    X = np.random.default_rng(1).normal(size=(g.n, 3))
+    for lam, p in ((0.3, 50), (1.2, 7), (0.05, 1), (0.7, 2)):
+        a = jackson.lowpass_coeffs(lam, p)
+        Yc = cheb.filter_block_clenshaw(A, X, a)
+        Yf = cheb.filter_block(A, X, a)
+        assert np.linalg.norm(Yc - Yf) <= 1e-12 * np.linalg.norm(Yf)
+        ev, U = np.linalg.eigh(laplacian.laplacian_dense(g.row_ptr, g.col))
+        h = np.polynomial.chebyshev.chebval(ev - 1.0, a)
+        Yd = U @ (h[:, None] * (U.T @ X))
+        assert np.linalg.norm(Yc - Yd) <= 1e-10 * np.linalg.norm(Yd)
+    a0 = np.array([0.25])
+    assert np.array_equal(cheb.filter_block_clenshaw(A, X, a0), 0.25 * X)
+
+
+def test_one_pass_kpm_dichotomy():
+    from oracle import eigencount, laplacian
+
+    g = synth.disconnected_regular(5, 60, 6, seed=2)
+    A, _ = laplacian.normalized_adjacency(g.row_ptr, g.col)
+    ev = np.linalg.eigvalsh(laplacian.laplacian_dense(g.row_ptr, g.col))
+    lam, steps, trace, conv, mu = eigencount.estimate_lambda_k_kpm(A, 5, 50, 400, 0)
+    assert conv and ev[4] - 1e-9 <= lam < ev[5]
+    # the first tested point is the plain dichotomy's first pass, count for count
+    plam, psteps, ptrace, pconv = eigencount.estimate_lambda_k(A, 5, 50, 400, 0)
+    assert abs(trace[0][1] - ptrace[0][1]) <= 1e-9 * max(1.0, abs(ptrace[0][1]))
+    # every count is the Hutchinson count of the pass's signals at that lambda
+    R = philox.gaussian_block(0, g.n, 400, 1, philox.COUNT)
+    for lt, ct in trace[:4]:
+        assert abs(eigencount.eigencount(A, lt, 50, R) - ct) <= 1e-9 * max(1.0, abs(ct))
