@@ -92,6 +92,17 @@ int32_t csc_version(void);
 csc_status csc_set_panel_width(int32_t pw);
 int32_t csc_get_panel_width(int32_t n, int64_t nnz, int32_t w);
 
+/* Damping of the Chebyshev coefficients used by every call that builds a
+ * low-pass from lambda (eigencount, dichotomy, features, interpolation,
+ * csc_jackson_coeffs): CSC_DAMP_JACKSON (default) multiplies c_m by the
+ * Jackson factors g_m (Sec. 4.3); CSC_DAMP_NONE keeps the plain truncated
+ * Chebyshev series c_m, which overshoots near lambda_c (Gibbs) and can make
+ * 1 - h~ indefinite, so the interpolation may stop with
+ * CSC_W_NOT_CONVERGED.  Process-wide; for comparisons of the two filters. */
+enum { CSC_DAMP_JACKSON = 0, CSC_DAMP_NONE = 1 };
+csc_status csc_set_damping(int32_t damping);
+int32_t csc_get_damping(void);
+
 /* Evaluation form of the accumulated filters (Sec. 2.1, fast graph filtering):
  * the features h~(L) R of every node and the CG operator's h~(L) P.
  * CSC_FORM_FORWARD: the three-term recurrence T_{m+1} = 2 (L - I) T_m - T_{m-1}

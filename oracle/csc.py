@@ -35,12 +35,13 @@ def default_n(k: int) -> int:
     return int(math.ceil(2.0 * k * math.log(k)))
 
 
-def features(A, lam: float, p: int, d: int, seed: int, with_norms: bool = False):
+def features(A, lam: float, p: int, d: int, seed: int, with_norms: bool = False,
+             damping: bool = True):
     """Rows of h~_lam(L) R scaled to unit length (Alg. 2 steps 3-4); with
     ``with_norms`` also the squared row norms before scaling (the estimates of
     v_k(i)^2, Sec. 4.1)."""
     R = gaussian_block(seed, A.shape[0], d, 0, FEAT)
-    Y = filter_block(A, R, lowpass_coeffs(lam, p))
+    Y = filter_block(A, R, lowpass_coeffs(lam, p, damping))
     sq = np.sum(Y * Y, axis=1)
     nrm = np.sqrt(sq)
     F = np.zeros_like(Y)
@@ -68,7 +69,7 @@ class Result:
 def run(row_ptr, col, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
         gamma: float = 1e-3, n_c: int | None = None, tol: float = 1e-6, max_iter: int = 1000,
         max_steps: int = 30, replicates: int = 20, kmeans_iter: int = 100, lam: float | None = None,
-        sampling: str = "uniform"):
+        sampling: str = "uniform", damping: bool = True):
     """Alg. 2.  ``sampling="density"`` draws the n nodes by variable-density
     sampling on the squared feature norms and uses the weighted fidelity term
     in Eq. (5) (``sampling.sample_density``)."""
@@ -77,10 +78,11 @@ def run(row_ptr, col, k: int, d: int, seed: int, p: int = 50, n: int | None = No
     n = default_n(k) if n is None else n
     n_c = count_signals(N) if n_c is None else n_c
     if lam is None:
-        lam, steps, trace, conv = estimate_lambda_k(A, k, p, n_c, seed, max_steps)
+        lam, steps, trace, conv = estimate_lambda_k(A, k, p, n_c, seed, max_steps,
+                                                    damping=damping)
     else:
         steps, trace, conv = 0, [], True
-    F, sq = features(A, lam, p, d, seed, with_norms=True)
+    F, sq = features(A, lam, p, d, seed, with_norms=True, damping=damping)
     weights = None
     if sampling == "density":
         omega, weights = sample_density(sq, n, seed)
@@ -89,5 +91,5 @@ def run(row_ptr, col, k: int, d: int, seed: int, p: int = 50, n: int | None = No
     Fr = F[omega]
     labels_r, _, inertia = kmeans(Fr, k, seed, replicates, kmeans_iter)
     X, labels, iters, relres = interpolate(A, lam, p, gamma, omega, labels_r, k, tol, max_iter,
-                                           weights)
+                                           weights, damping)
     return Result(lam, steps, trace, conv, omega, Fr, labels_r, inertia, X, labels, iters, relres)

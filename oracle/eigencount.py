@@ -31,13 +31,13 @@ def count_signals(N: int) -> int:
     return int(math.ceil(2.0 * math.log(N)))
 
 
-def eigencount(A, lam: float, p: int, R: np.ndarray) -> float:
-    a = lowpass_coeffs(lam, p)
+def eigencount(A, lam: float, p: int, R: np.ndarray, damping: bool = True) -> float:
+    a = lowpass_coeffs(lam, p, damping)
     return float(np.sum(R * filter_block(A, R, a)))
 
 
 def estimate_lambda_k(A, k: int, p: int, n_c: int, seed: int, max_steps: int = 30,
-                      bracket=(0.0, 2.0)):
+                      bracket=(0.0, 2.0), damping: bool = True):
     """Returns (lambda_hat, steps_used, [(lambda_t, count_t)], converged)."""
     N = A.shape[0]
     lo, hi = float(bracket[0]), float(bracket[1])
@@ -45,7 +45,7 @@ def estimate_lambda_k(A, k: int, p: int, n_c: int, seed: int, max_steps: int = 3
     for t in range(1, max_steps + 1):
         mid = 0.5 * (lo + hi)
         R = gaussian_block(seed, N, n_c, t, COUNT)
-        c = eigencount(A, mid, p, R)
+        c = eigencount(A, mid, p, R, damping)
         trace.append((mid, c))
         if math.floor(c + 0.5) == k:
             return mid, t, trace, True

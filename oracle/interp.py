@@ -97,13 +97,14 @@ def hard_labels(X: np.ndarray) -> np.ndarray:
     return lab
 
 
-def interpolate(A, lam_k, p, gamma, omega, labels_r, k, tol=1e-6, max_iter=1000, weights=None):
+def interpolate(A, lam_k, p, gamma, omega, labels_r, k, tol=1e-6, max_iter=1000, weights=None,
+                damping: bool = True):
     """Eq. (5) for every cluster; with ``weights`` (w_s > 0 per sampled node)
     the fidelity term is Puy et al.'s weighted ||W^(1/2) (M x - c_j^r)||^2
     used with variable-density sampling: (M^T W M + gamma g~(L)) x = M^T W c_j^r."""
     N = A.shape[0]
     mask = sample_mask(N, omega, weights)
-    a = lowpass_coeffs(lam_k, p)
+    a = lowpass_coeffs(lam_k, p, damping)
     B = rhs(N, omega, labels_r, k, weights)
     X, iters, relres = cg(A, mask, gamma, a, B, tol, max_iter)
     return X, hard_labels(X), iters, relres

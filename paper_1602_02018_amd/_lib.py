@@ -24,6 +24,7 @@ WARNINGS = (CSC_W_NOT_CONVERGED, CSC_W_BISECT_EXHAUSTED, CSC_W_BRACKET_MISS)
 STREAM_COUNT, STREAM_FEAT, STREAM_SAMPLE, STREAM_KMEANS = 1, 2, 3, 4
 TUNE_PANEL_WIDTH, TUNE_XCD_ORDER, TUNE_NONTEMPORAL, TUNE_HIP_GRAPHS = 0, 1, 2, 3
 FORM_FORWARD, FORM_CLENSHAW = 0, 1
+DAMP_JACKSON, DAMP_NONE = 0, 1
 
 
 class CscGraph(C.Structure):
@@ -104,6 +105,8 @@ PROTOTYPES = {
     "csc_cheb_steps_workspace_bytes": (sz, [i32, i32]),
     "csc_cheb_steps": (i32, [pg, i32, i32, i32, i32, vp, sz, vp]),
     "csc_set_filter_form": (i32, [i32]),
+    "csc_set_damping": (i32, [i32]),
+    "csc_get_damping": (i32, []),
     "csc_get_filter_form": (i32, []),
 }
 

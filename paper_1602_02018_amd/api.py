@@ -75,6 +75,15 @@ def set_tuning(key: int, value: int) -> None:
     check(lib().csc_set_tuning(int(key), int(value)), "csc_set_tuning")
 
 
+def set_damping(damping: int) -> None:
+    """Jackson-damped (0, default) or plain truncated (1) Chebyshev low-pass."""
+    check(lib().csc_set_damping(int(damping)), "csc_set_damping")
+
+
+def get_damping() -> int:
+    return int(lib().csc_get_damping())
+
+
 def set_filter_form(form: int) -> None:
     """Forward recurrence (0) or Clenshaw (1, default) for accumulated filters."""
     check(lib().csc_set_filter_form(int(form)), "csc_set_filter_form")

@@ -21,6 +21,7 @@ thread_local std::string g_error;
 std::atomic<int> g_panel_override{0};
 std::atomic<int> g_tune_xcd{1};
 std::atomic<int> g_filter_form{FORM_CLENSHAW};
+std::atomic<int> g_damping{CSC_DAMP_JACKSON};
 std::atomic<int> g_tune_nt{0};
 std::atomic<int> g_tune_graphs{1};
 }  // namespace
@@ -145,6 +146,7 @@ csc_status check_ws(void* ws, size_t ws_bytes, size_t need) {
 
 // Jackson-Chebyshev coefficients of the ideal low-pass at lc (Sec. 4.3).
 void jackson_lowpass(double lc, int p, double* a) {
+  const bool damp = g_damping.load() == CSC_DAMP_JACKSON;
   const double pi = 3.14159265358979323846;
   double xc = lc - 1.0;
   xc = xc < -1.0 ? -1.0 : (xc > 1.0 ? 1.0 : xc);
@@ -153,7 +155,7 @@ void jackson_lowpass(double lc, int p, double* a) {
   for (int m = 0; m <= p; ++m) {
     const double c = m == 0 ? 1.0 - th / pi : -2.0 * std::sin(m * th) / (m * pi);
     const double g = ((p + 2 - m) * std::cos(m * al) + std::sin(m * al) / std::tan(al)) / (p + 2);
-    a[m] = g * c;
+    a[m] = damp ? g * c : c;
   }
 }
 
@@ -378,6 +380,16 @@ extern "C" csc_status csc_set_panel_width(int32_t pw) {
 extern "C" int32_t csc_get_panel_width(int32_t n, int64_t nnz, int32_t w) {
   return choose_panel_width(n, w, nnz);
 }
+
+extern "C" csc_status csc_set_damping(int32_t damping) {
+  clear_error();
+  CSC_REQUIRE(damping == CSC_DAMP_JACKSON || damping == CSC_DAMP_NONE,
+              "damping must be CSC_DAMP_JACKSON or CSC_DAMP_NONE");
+  g_damping.store(damping);
+  return CSC_OK;
+}
+
+extern "C" int32_t csc_get_damping(void) { return g_damping.load(); }
 
 extern "C" csc_status csc_set_filter_form(int32_t form) {
   clear_error();
