@@ -290,6 +290,17 @@ csc_status csc_kmeans_reduced_f64(const double* F, int32_t n, int32_t d, int32_t
                                   int32_t replicates, int32_t max_iter, uint64_t seed,
                                   int32_t* labels, double* inertia_out);
 
+/* Community cores (the paper's conclusion: repeat the filtering with new
+ * signals and the clustering of the sampled nodes, keep the nodes always
+ * clustered together, interpolate from these stable cores only).  labels:
+ * host T x n (run t's k-means labels of the n sampled nodes, row t).  Two
+ * nodes share a class iff their labels agree in every run; the cores are the
+ * k largest classes (ties: the class whose first member comes first), and
+ * core_labels (host int32[n]) gets c for members of core c (0 = largest),
+ * -1 for nodes outside the cores.  Host only. */
+csc_status csc_community_cores(int32_t n, int32_t T, int32_t k, const int32_t* labels,
+                               int32_t* core_labels);
+
 /* The same k-means on the GPU, for float32 features already in device
  * memory: one workgroup per replicate, the same sums in the same order, so
  * labels and inertia are bit-identical to csc_kmeans_reduced's.

@@ -88,6 +88,7 @@ PROTOTYPES = {
                                       vp, pi, vp, pi, pd, pi, vp, sz, vp]),
     "csc_kmeans_reduced_batched": (i32, [i32, vp, pi, pi, pi, i32, i32, pu, vp, pd]),
     "csc_kmeans_device_workspace_bytes": (sz, [i32, i32, i32, i32]),
+    "csc_community_cores": (i32, [i32, i32, i32, pi, pi]),
     "csc_kmeans_reduced_device": (i32, [vp, i32, i32, i32, i32, i32, i32, u64, pi, pd, vp, sz, vp]),
     "csc_kmeans_device_workspace_bytes_batched": (sz, [i32, pi, pi, pi, i32]),
     "csc_kmeans_reduced_device_batched": (i32, [i32, vp, pi, pi, pi, i32, i32, pu, vp, pd, vp, sz,

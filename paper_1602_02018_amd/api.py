@@ -247,6 +247,24 @@ def kmeans_reduced_device(F: torch.Tensor, k: int, seed: int, replicates: int = 
     return labels, inertia.value
 
 
+GOLDEN = 0x9E3779B97F4A7C15
+
+
+def run_seed(seed: int, t: int) -> int:
+    """Seed of run t of the community-core repetitions (run 0 is the plain run)."""
+    return (int(seed) + t * GOLDEN) % (1 << 64)
+
+
+def community_cores(labels_runs, k: int) -> np.ndarray:
+    """csc_community_cores: labels_runs is T x n; returns int32[n] (-1 outside the cores)."""
+    L = np.ascontiguousarray(labels_runs, dtype=np.int32)
+    T, n = L.shape
+    out = np.zeros(n, dtype=np.int32)
+    check(lib().csc_community_cores(n, T, k, L.ctypes.data_as(_lib.pi), out.ctypes.data_as(_lib.pi)),
+          "csc_community_cores")
+    return out
+
+
 @dataclass
 class Interpolation:
     X: torch.Tensor
@@ -386,7 +404,7 @@ def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
         max_steps: int = 30, replicates: int = 20, kmeans_iter: int = 100, lam: float | None = None,
         bracket=None, want_X: bool = False, mlp_params: torch.Tensor | None = None,
         reorder: bool = True, cg: int = CG_BLOCK, kmeans_on_gpu: bool = True,
-        sampling: str = "uniform", lambda_method: str = "dichotomy") -> Result:
+        sampling: str = "uniform", lambda_method: str = "dichotomy", cores: int = 1) -> Result:
     """Compressive spectral clustering (Alg. 2) with every graph-sized step on the GPU.
 
     With ``mlp_params`` the dichotomy starts from the learned bracket.  With
@@ -433,8 +451,22 @@ def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
         labels_r, inertia = kmeans_reduced(F.cpu().numpy(), k, seed, replicates, kmeans_iter)
     t3 = time.perf_counter()
     order = community_order(F_all, omega, labels_r, k) if reorder else None
-    it = interpolate(g, lam, p, gamma, omega, labels_r, k, tol, max_iter, want_X=want_X,
-                     order=order, method=cg, weights=dec_w)
+    omega_i, labels_i, w_i = omega, labels_r, dec_w
+    if cores > 1:  # community cores: T - 1 more filterings and clusterings
+        runs = [labels_r]
+        for t in range(1, cores):
+            Ft = filter(g, lam, p, d, run_seed(seed, t), rows=omega, normalize=True)
+            lt, _ = (kmeans_reduced_device(Ft, k, seed, replicates, kmeans_iter) if kmeans_on_gpu
+                     else kmeans_reduced(Ft.cpu().numpy(), k, seed, replicates, kmeans_iter))
+            runs.append(lt)
+        cl = community_cores(np.stack(runs), k)
+        keep = np.nonzero(cl >= 0)[0]
+        keep_t = torch.as_tensor(keep, device=g.device)
+        omega_i = omega[keep_t]
+        labels_i = cl[keep]
+        w_i = None if dec_w is None else dec_w[keep_t]
+    it = interpolate(g, lam, p, gamma, omega_i, labels_i, k, tol, max_iter, want_X=want_X,
+                     order=order, method=cg, weights=w_i)
     torch.cuda.current_stream().synchronize()
     t4 = time.perf_counter()
     tm.update(bisection_s=t1 - t0, features_s=t2 - t1, kmeans_s=t3 - t2, interpolate_s=t4 - t3,

@@ -327,3 +327,40 @@ extern "C" csc_status csc_kmeans_reduced_batched(int32_t G, const float* const* 
   }
   return kmeans_batched(G, X, n, d, k, replicates, max_iter, seeds, labels, inertia_out);
 }
+
+// Community cores: the k largest classes of sampled nodes that share their
+// label in every run (tuple of T labels), ranked by size and then by their
+// first member's position; members of core c get label c, others -1.
+extern "C" csc_status csc_community_cores(int32_t n, int32_t T, int32_t k, const int32_t* labels,
+                                          int32_t* core_labels) {
+  clear_error();
+  CSC_REQUIRE(n >= 1 && T >= 1 && k >= 1, "need n >= 1, T >= 1 and k >= 1");
+  CSC_REQUIRE(labels && core_labels, "labels and core_labels must be non-NULL");
+  std::vector<int> idx(n);
+  for (int s = 0; s < n; ++s) idx[s] = s;
+  auto less = [&](int a, int b) {
+    for (int t = 0; t < T; ++t) {
+      const int la = labels[(size_t)t * n + a], lb = labels[(size_t)t * n + b];
+      if (la != lb) return la < lb;
+    }
+    return false;
+  };
+  std::stable_sort(idx.begin(), idx.end(), less);  // equal tuples keep sample order
+  struct Cls {
+    int size, first, begin;
+  };
+  std::vector<Cls> cls;
+  for (int i = 0; i < n;) {
+    int j = i + 1;
+    while (j < n && !less(idx[i], idx[j]) && !less(idx[j], idx[i])) ++j;
+    cls.push_back(Cls{j - i, idx[i], i});
+    i = j;
+  }
+  std::sort(cls.begin(), cls.end(), [](const Cls& a, const Cls& b) {
+    return a.size != b.size ? a.size > b.size : a.first < b.first;
+  });
+  for (int s = 0; s < n; ++s) core_labels[s] = -1;
+  for (int c = 0; c < (int)cls.size() && c < k; ++c)
+    for (int q = cls[c].begin; q < cls[c].begin + cls[c].size; ++q) core_labels[idx[q]] = c;
+  return CSC_OK;
+}
