@@ -166,6 +166,8 @@ def main():
     ap.add_argument("--workload", default="sbm-1e5", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 1e6-node Chung-Lu run and its step timings")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB device copy (for scaling memory counters)")
@@ -244,26 +246,11 @@ def main():
 
     # dominant kernel: Chebyshev step of the CG operator (width k) on the graph
     # in the community order the interpolation runs on, per-launch time
-    if last.order is not None:
-        rp, cl = permuted_csr(gr, last.order.cpu().numpy())
-        g_run = api.Graph(rp, cl, dev)
-    else:
-        g_run = g
-    st = api.StepTimer(g_run, k, 3)  # Clenshaw step, as the CG passes run it
-    st.launch(10)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    launches = args.kernel_reps * p
-    e0.record()
-    for _ in range(args.kernel_reps):
-        st.launch(p)
-    e1.record()
-    torch.cuda.synchronize()
-    avg_s = e0.elapsed_time(e1) / 1e3 / launches
+    avg_s = step_time(api, gr, last.order, k, p, args.kernel_reps, dev)
     per_launch = step_bytes(N, nnz, k, "clen")
     achieved = per_launch / avg_s / 1e9
     traffic = read_traffic(per_launch)
+    large = None if args.no_large else large_shapes(api, args, dev)
 
     out = {
         "metric": "filter SpMM HBM GB/s (% peak) + end-to-end CSC s/graph vs plain at ARI>=0.99",
@@ -321,9 +308,69 @@ def main():
             "avg_launch_us": round(avg_s * 1e6, 2),
         },
     }
+    if large is not None:
+        out["chunglu_1e6"] = large
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(gr, k, p)
     print(json.dumps(out), flush=True)
+
+
+def step_time(api, gr, order, w, p, reps, dev, kind=3):
+    """Average seconds per launch of the Chebyshev step (kind 3: Clenshaw) at
+    width w, on the graph in `order` (None: as given), timed with HIP events on
+    the current stream, which the library launches on."""
+    import torch
+
+    if order is not None:
+        rp, cl = permuted_csr(gr, order.cpu().numpy())
+        g_run = api.Graph(rp, cl, dev)
+    else:
+        g_run = api.Graph(gr.row_ptr, gr.col, dev)
+    st = api.StepTimer(g_run, w, kind)
+    st.launch(10)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        st.launch(p)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / (reps * p)
+
+
+def large_shapes(api, args, dev):
+    """The 1e6-node Chung-Lu configuration (k = 250, d = 56, p = 60): one
+    end-to-end run and the per-launch Clenshaw step at the filter width d
+    (natural order) and the CG width k (the community order of that run)."""
+    import torch
+
+    from oracle.metrics import adjusted_rand_index  # ARI of the labels only
+
+    wl = WORKLOADS["chunglu-1e6"]
+    gr = make_graph(wl, args.seed)
+    N, nnz, k, p = gr.n, gr.nnz, wl["k"], wl["p"]
+    d = int(math.ceil(4 * math.log(N)))
+    g = api.Graph(gr.row_ptr, gr.col, dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = api.run(g, k, d, args.seed, p=p)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    out = {"workload": f"chunglu N={N} nnz={nnz} k={k} d={d} p={p} n={api.default_n(k)}",
+           "s_per_graph": round(secs, 3),
+           "phases_s": {kk: round(v, 4) for kk, v in r.timings.items()},
+           "cg_iters_max": int(r.interp.iters.max()),
+           "ari_vs_truth": round(float(adjusted_rand_index(r.labels.cpu().numpy(), gr.truth)), 4)}
+    for name, w, order in (("filter_step", d, None), ("cg_step", k, r.order)):
+        avg = step_time(api, gr, order, w, p, max(2, args.kernel_reps // 5), dev)
+        by = step_bytes(N, nnz, w, "clen")
+        out[name] = {"w": w, "panel_width": api.panel_width(N, w, nnz),
+                     "order": "community" if order is not None else "natural",
+                     "avg_launch_us": round(avg * 1e6, 1), "alg_bytes_per_launch": by,
+                     "achieved_GBs": round(by / avg / 1e9, 1),
+                     "frac": round(by / avg / 1e9 / PEAK_HBM_GBS, 4)}
+    return out
 
 
 def bench_batch(args, wl, dev):

@@ -373,15 +373,19 @@ csc_status csc_interpolate(const csc_graph* g, const int32_t* order, int32_t met
  * F: device N x d, leading dimension ldf (the normalized features of every
  *   node, csc_filter with rows = NULL), d <= 128.  idx: device int32[n].
  *   labels_r: HOST int32[n] in [0, k) (csc_kmeans_reduced's output).
- * order: device int32[N].  node_labels: device int32[N] (the nearest-centroid
- *   label of every node) or NULL.
+ * g: the graph (N = g->n nodes).  order: device int32[N].  node_labels: device
+ *   int32[N] (the nearest-centroid label of every node) or NULL.
+ * same_label_frac: host double or NULL: the fraction of stored edges whose
+ *   ends share a label, i.e. of the gathers an XCD can serve from the rows it
+ *   walks itself; on graphs without such structure the order only moves
+ *   hubs around and callers should keep the natural order.
  * ws: csc_community_order_workspace_bytes(N, d, k, n).  Synchronises.
  */
 size_t csc_community_order_workspace_bytes(int32_t N, int32_t d, int32_t k, int32_t n);
-csc_status csc_community_order(int32_t N, const float* F, int64_t ldf, int32_t d,
+csc_status csc_community_order(const csc_graph* g, const float* F, int64_t ldf, int32_t d,
                                const int32_t* idx, const int32_t* labels_r, int32_t n, int32_t k,
-                               int32_t* order, int32_t* node_labels, void* ws, size_t ws_bytes,
-                               void* stream);
+                               int32_t* order, int32_t* node_labels, double* same_label_frac,
+                               void* ws, size_t ws_bytes, void* stream);
 
 /* Variable-density sampling (Alg. 2 step 5 with the sampling distribution
  * that Sec. 3.2.3 points to: p_i proportional to the local cumulative

@@ -76,7 +76,7 @@ PROTOTYPES = {
     "csc_sample_density": (i32, [i32, i32, u64, vp, vp, vp, vp, sz, vp]),
     "csc_normalize_rows": (i32, [vp, i64, i32, i32, vp, vp]),
     "csc_community_order_workspace_bytes": (sz, [i32, i32, i32, i32]),
-    "csc_community_order": (i32, [i32, vp, i64, i32, vp, pi, i32, i32, vp, vp, vp, sz, vp]),
+    "csc_community_order": (i32, [pg, vp, i64, i32, vp, pi, i32, i32, vp, vp, pd, vp, sz, vp]),
     "csc_gather_rows": (i32, [vp, i64, i32, i32, vp, i32, vp, i32, vp, sz, vp]),
     "csc_estimate_workspace_bytes_batched": (sz, [pg, i32, pi, i32]),
     "csc_estimate_lambda_k_batched": (i32, [pg, i32, pi, i32, pi, pu, i32, pd, vp, pd, pi, pd, pd,

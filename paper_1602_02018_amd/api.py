@@ -304,24 +304,38 @@ def interpolate(g: Graph, lam: float, p: int, gamma: float, idx, labels_r, k: in
     return Interpolation(X, labels, iters, relres, st)
 
 
-def community_order(F: torch.Tensor, idx, labels_r, k: int, want_labels: bool = False):
+# the community order pays off when most gathers stay inside a community
+ORDER_MIN_SAME_LABEL = 0.25
+
+
+def community_order(g: Graph, F: torch.Tensor, idx, labels_r, k: int, want_labels: bool = False,
+                    want_frac: bool = False):
     """Node order by nearest k-means centroid (csc_community_order).
 
     F: device N x d features of every node; idx: sampled nodes; labels_r: their
-    k-means labels.  Returns the order (device int32[N]) and, with
-    ``want_labels``, every node's nearest-centroid label."""
+    k-means labels.  Returns the order (device int32[N]), then, with
+    ``want_labels``, every node's nearest-centroid label and, with
+    ``want_frac``, the fraction of edges whose ends share a label."""
     assert F.is_cuda and F.dtype == torch.float32 and F.dim() == 2 and F.stride(1) == 1
     N, d = F.shape
+    assert N == g.n
     idx_t = _i32_device(idx, F.device)
     lab = np.ascontiguousarray(labels_r, dtype=np.int32)
     n = int(idx_t.numel())
     order = torch.empty(N, dtype=torch.int32, device=F.device)
     nl = torch.empty(N, dtype=torch.int32, device=F.device) if want_labels else None
+    frac = C.c_double(0.0)
     ws = _ws(lib().csc_community_order_workspace_bytes(N, d, k, n), F.device)
-    check(lib().csc_community_order(N, _ptr(F), F.stride(0), d, _ptr(idx_t),
+    check(lib().csc_community_order(g.ref, _ptr(F), F.stride(0), d, _ptr(idx_t),
                                     lab.ctypes.data_as(_lib.pi), n, k, _ptr(order), _ptr(nl),
-                                    _ptr(ws), ws.numel(), _stream()), "csc_community_order")
-    return (order, nl) if want_labels else order
+                                    C.byref(frac), _ptr(ws), ws.numel(), _stream()),
+          "csc_community_order")
+    out = (order,)
+    if want_labels:
+        out += (nl,)
+    if want_frac:
+        out += (frac.value,)
+    return out if len(out) > 1 else order
 
 
 def normalize_rows(Y: torch.Tensor) -> torch.Tensor:
@@ -450,7 +464,11 @@ def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
     else:
         labels_r, inertia = kmeans_reduced(F.cpu().numpy(), k, seed, replicates, kmeans_iter)
     t3 = time.perf_counter()
-    order = community_order(F_all, omega, labels_r, k) if reorder else None
+    order = None
+    if reorder:
+        order, frac = community_order(g, F_all, omega, labels_r, k, want_frac=True)
+        if frac < ORDER_MIN_SAME_LABEL:
+            order = None
     omega_i, labels_i, w_i = omega, labels_r, dec_w
     if cores > 1:  # community cores: T - 1 more filterings and clusterings
         runs = [labels_r]
@@ -663,8 +681,12 @@ def run_batched(graphs, ks, ds, seeds, p=50, ns=None, gamma=1e-3, n_cs=None, tol
     t3 = time.perf_counter()
     orders = None
     if any(re):
-        orders = [community_order(f, o, l, k) if r else None
-                  for f, o, l, k, r in zip(F_all, omegas, labels_r, ks, re)]
+        orders = [None] * G
+        for i in range(G):
+            if re[i]:
+                o, frac = community_order(graphs[i], F_all[i], omegas[i], labels_r[i], ks[i],
+                                          want_frac=True)
+                orders[i] = o if frac >= ORDER_MIN_SAME_LABEL else None
     its = interpolate_batched(graphs, lams, p, gamma, omegas, labels_r, ks, tol, max_iter, want_X,
                               orders, cg, dec_ws)
     torch.cuda.current_stream().synchronize()

@@ -155,6 +155,19 @@ __global__ __launch_bounds__(kBlk) void k_nearest_centroid(int N, int d, const f
   if (row) labels[i] = arg;
 }
 
+// Number of stored edges whose two ends carry the same label (integer atomics:
+// the count does not depend on the order of the additions).
+__global__ void k_same_label_edges(int N, const int* row_ptr, const int* col, const int* lab,
+                                   unsigned long long* count) {
+  unsigned long long c = 0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)N;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int li = lab[i];
+    for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) c += lab[col[e]] == li;
+  }
+  if (c) atomicAdd(count, c);
+}
+
 // Exponential-race keys of variable-density sampling: E_i / w_i with
 // E_i = -ln(u_i), u_i = ((x0 >> 11) + 1) 2^-53 from Philox at counter
 // (i, 1, SAMPLE, 0); +inf when w_i is not positive.  A positive double's bits
@@ -351,13 +364,16 @@ extern "C" size_t csc_community_order_workspace_bytes(int32_t N, int32_t d, int3
   return order_bytes(N, d, k, n);
 }
 
-extern "C" csc_status csc_community_order(int32_t N, const float* F, int64_t ldf, int32_t d,
-                                          const int32_t* idx, const int32_t* labels_r,
-                                          int32_t n, int32_t k, int32_t* order,
-                                          int32_t* node_labels, void* ws, size_t ws_bytes,
+extern "C" csc_status csc_community_order(const csc_graph* g, const float* F, int64_t ldf,
+                                          int32_t d, const int32_t* idx,
+                                          const int32_t* labels_r, int32_t n, int32_t k,
+                                          int32_t* order, int32_t* node_labels,
+                                          double* same_label_frac, void* ws, size_t ws_bytes,
                                           void* stream) {
   clear_error();
-  CSC_REQUIRE(N >= 1 && d >= 1 && d <= 128 && ldf >= d, "need N >= 1, 1 <= d <= 128, ldf >= d");
+  CSC_TRY(check_graph(g));
+  const int32_t N = g->n;
+  CSC_REQUIRE(d >= 1 && d <= 128 && ldf >= d, "need 1 <= d <= 128 and ldf >= d");
   CSC_REQUIRE(k >= 1 && n >= 1 && n <= N, "need k >= 1 and 1 <= n <= N");
   CSC_REQUIRE(F && idx && labels_r && order, "F, idx, labels_r and order must be non-NULL");
   for (int s = 0; s < n; ++s)
@@ -409,6 +425,19 @@ extern "C" csc_status csc_community_order(int32_t N, const float* F, int64_t ldf
   CSC_HIP(hipMemcpyAsync(order, out, (size_t)N * sizeof(int), hipMemcpyDeviceToDevice, s));
   if (node_labels)
     CSC_HIP(hipMemcpyAsync(node_labels, lab, (size_t)N * sizeof(int), hipMemcpyDeviceToDevice, s));
+  if (same_label_frac) {
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(bad);
+    CSC_HIP(launch_fill_i32(bad, 2, 0, s));  // the 64-bit counter
+    if (g->nnz > 0) {
+      hipLaunchKernelGGL(k_same_label_edges, dim3(blocks_for(N, kBlk)), dim3(kBlk), 0, s, N,
+                         g->row_ptr, g->col, lab, cnt);
+      CSC_HIP(hipGetLastError());
+    }
+    unsigned long long h = 0;
+    CSC_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    *same_label_frac = g->nnz > 0 ? (double)h / (double)g->nnz : 0.0;
+  }
   CSC_HIP(hipStreamSynchronize(s));
   return CSC_OK;
 }

@@ -81,11 +81,13 @@ def test_argument_errors_are_reported_without_gpu_work():
     assert b"method" in lib.csc_last_error()
     # community order: d above the register-resident limit, labels outside [0, k)
     lab = (C.c_int32 * 3)(0, 1, 2)
-    assert lib.csc_community_order(10, C.c_void_p(16), 200, 200, C.c_void_p(16), lab, 3, 3,
-                                   C.c_void_p(16), None, None, 0, None) == _lib.CSC_E_INVALID_ARG
+    assert lib.csc_community_order(C.byref(g), C.c_void_p(16), 200, 200, C.c_void_p(16), lab, 3, 3,
+                                   C.c_void_p(16), None, None, None, 0,
+                                   None) == _lib.CSC_E_INVALID_ARG
     assert b"d <= 128" in lib.csc_last_error()
-    assert lib.csc_community_order(10, C.c_void_p(16), 8, 8, C.c_void_p(16), lab, 3, 2,
-                                   C.c_void_p(16), None, None, 0, None) == _lib.CSC_E_INVALID_ARG
+    assert lib.csc_community_order(C.byref(g), C.c_void_p(16), 8, 8, C.c_void_p(16), lab, 3, 2,
+                                   C.c_void_p(16), None, None, None, 0,
+                                   None) == _lib.CSC_E_INVALID_ARG
     assert b"labels_r" in lib.csc_last_error()
     assert lib.csc_gather_rows(C.c_void_p(16), 4, 10, 8, C.c_void_p(16), 2, C.c_void_p(16), 8,
                                None, 0, None) == _lib.CSC_E_INVALID_ARG

@@ -93,7 +93,8 @@ def test_sbm_1e5_sampling_and_interpolation(api, sbm1e5):
     # all rows by Clenshaw, sampled rows by the forward recurrence: float32 rounding apart
     Fg = api.gather_rows(F_all, omega)
     assert torch.linalg.norm(Fg - F) <= 1e-4 * torch.linalg.norm(F)
-    order = api.community_order(F_all, omega, lab_r, k)
+    order, frac = api.community_order(g, F_all, omega, lab_r, k, want_frac=True)
+    assert frac > 0.4  # most edges of this SBM stay inside a community
     res3 = api.interpolate(g, lam, 50, 1e-3, omega, lab_r, k, order=order)
     assert res3.status == 0 and np.all(res3.relres <= 1e-6)
     X3 = res3.X.cpu().numpy().astype(np.float64)

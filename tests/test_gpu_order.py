@@ -82,7 +82,7 @@ def test_order_is_stable_sort_of_nearest_centroid(api, cfg1, ragged, which):
     k = 10 if which == "cfg1" else 7
     g = api.Graph(gr.row_ptr, gr.col)
     omega, F_all, F, lab_r = _features(api, gr, g, 0.45, k, api.default_n(k), 0)
-    order, nl = api.community_order(F_all, omega, lab_r, k, want_labels=True)
+    order, nl, frac = api.community_order(g, F_all, omega, lab_r, k, want_labels=True, want_frac=True)
     order, nl = order.cpu().numpy(), nl.cpu().numpy()
     assert np.array_equal(np.sort(order), np.arange(gr.n))
     assert np.array_equal(order, np.argsort(nl, kind="stable"))
@@ -101,6 +101,8 @@ def test_order_is_stable_sort_of_nearest_centroid(api, cfg1, ragged, which):
     clear = srt[:, 1] - srt[:, 0] > 1e-5 * (1 + srt[:, 0])
     assert clear.mean() > 0.95
     assert np.array_equal(nl[clear], np.argmin(D, axis=1)[clear])
+    rows = np.repeat(np.arange(gr.n), np.diff(gr.row_ptr))
+    assert frac == np.mean(nl[rows] == nl[gr.col])  # exact: an integer count over nnz
     if which == "cfg1":
         assert metrics.adjusted_rand_index(nl, gr.truth) > 0.7  # community structure, not accuracy
 
@@ -109,7 +111,7 @@ def test_empty_cluster_gets_no_node(api, cfg1):
     g = api.Graph(cfg1.row_ptr, cfg1.col)
     omega, F_all, F, _ = _features(api, cfg1, g, 0.45, 10, 47, 1)
     lab_r = np.where(np.arange(47) % 2 == 0, 0, 2).astype(np.int32)
-    _, nl = api.community_order(F_all, omega, lab_r, 3, want_labels=True)
+    _, nl = api.community_order(g, F_all, omega, lab_r, 3, want_labels=True)
     assert set(np.unique(nl.cpu().numpy())) <= {0, 2}
 
 
@@ -122,7 +124,7 @@ def test_interpolation_with_order_matches_natural_order(api, cfg1, pw, kind):
         k, lam = 10, 0.46875
         omega, F_all, F, lab_r = _features(api, cfg1, g, lam, k, 47, 0)
         if kind == "community":
-            order = api.community_order(F_all, omega, lab_r, k)
+            order = api.community_order(g, F_all, omega, lab_r, k)
         else:
             order = torch.as_tensor(np.random.default_rng(3).permutation(cfg1.n).astype(np.int32),
                                     device="cuda")
@@ -181,7 +183,7 @@ def test_batched_all_rows_filter_and_ordered_interpolation_match_single(api, cfg
         lab, _ = api.kmeans_reduced(api.gather_rows(ref, omegas[i]).cpu().numpy(), ks[i], seeds[i],
                                     replicates=3)
         labs.append(lab)
-        orders.append(api.community_order(ref, omegas[i], lab, ks[i]) if i != 1 else None)
+        orders.append(api.community_order(g, ref, omegas[i], lab, ks[i]) if i != 1 else None)
     res = api.interpolate_batched(G, lams, 50, 1e-3, omegas, labs, ks, orders=orders)
     for i, g in enumerate(G):
         one = api.interpolate(g, lams[i], 50, 1e-3, omegas[i], labs[i], ks[i], order=orders[i])
