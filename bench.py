@@ -65,8 +65,8 @@ def step_bytes(N, nnz, w, kind):
 
 # block CG per iteration besides the pass, in N x k blocks touched: Gram Z^T Z
 # (1), P = Z T (2), Grams P^T Q and P^T R (4), X and R updates (6), column
-# norms of R (1), Gram Q^T R (2), Z = R + P beta (3)
-BLOCK_CG_BLOCKS = 19
+# norms of R (1), Jacobi scaling Z = D^-1 R (2), Gram Q^T Z (2), Z = Z + P beta (3)
+BLOCK_CG_BLOCKS = 21
 
 
 def job_bytes(N, nnz, k, d, n_c, p, bis_steps, cg_iters):

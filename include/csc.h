@@ -342,15 +342,21 @@ csc_status csc_kmeans_reduced_device(const float* F, int32_t n, int32_t d, int32
  *   scaled to unit norm, pivoted Cholesky of their float64 Gram matrix, pivots
  *   below 1e-10 dropped), step matrices from float64 Gram matrices solved on
  *   the host; one Chebyshev pass per iteration serves every column, and the
- *   block Krylov space usually needs far fewer iterations.  Both stop when
+ *   block Krylov space usually needs far fewer iterations.
+ *   CSC_CG_BLOCK_JACOBI is the same block CG preconditioned by the diagonal
+ *   D = diag(mask) + gamma I (the operator's diagonal without the small
+ *   h~(L)_ii terms): the next search block comes from D^-1 R instead of R.
+ *   The sampled rows (~1 + gamma) and the unsampled ones (~gamma) then share
+ *   one scale, which leaves only about k small eigenvalues for the block
+ *   Krylov space to resolve.  All three stop when
  *   every column has ||r_j|| / ||b_j|| <= tol (recursive residuals); iters_out
- *   gives the iteration at which each column first met it.  Both solve the
+ *   gives the iteration at which each column first met it.  All solve the
  *   same system; X agrees to the accuracy the tolerance implies.
  * ws: csc_interpolate_workspace_bytes(N, nnz, k, n) (covers every form).
  * Synchronises.  Returns CSC_W_NOT_CONVERGED if a column reached max_iter or
  * the block iteration broke down (outputs still hold the last iterate).
  */
-enum { CSC_CG_COLUMNS = 0, CSC_CG_BLOCK = 1 };
+enum { CSC_CG_COLUMNS = 0, CSC_CG_BLOCK = 1, CSC_CG_BLOCK_JACOBI = 2 };
 size_t csc_interpolate_workspace_bytes(int32_t N, int64_t nnz, int32_t k, int32_t n);
 csc_status csc_interpolate(const csc_graph* g, const int32_t* order, int32_t method,
                            double lambda_k, int32_t p, double gamma, const int32_t* idx,

@@ -274,14 +274,15 @@ class Interpolation:
     status: int
 
 
-CG_COLUMNS, CG_BLOCK = 0, 1
+CG_COLUMNS, CG_BLOCK, CG_BLOCK_JACOBI = 0, 1, 2
 
 
 def interpolate(g: Graph, lam: float, p: int, gamma: float, idx, labels_r, k: int,
                 tol: float = 1e-6, max_iter: int = 1000, want_X: bool = True,
-                order: torch.Tensor | None = None, method: int = CG_BLOCK,
+                order: torch.Tensor | None = None, method: int = CG_BLOCK_JACOBI,
                 weights: torch.Tensor | None = None) -> Interpolation:
-    """Eq. (5) by CG (``method``: CG_BLOCK, one block CG over the k columns, or
+    """Eq. (5) by CG (``method``: CG_BLOCK, one block CG over the k columns,
+    CG_BLOCK_JACOBI, the same preconditioned by diag(mask) + gamma I, or
     CG_COLUMNS, k side-by-side CGs); with ``order`` (a permutation, see
     community_order) the solve runs on the graph listed in that order,
     outputs in node order."""
@@ -417,7 +418,7 @@ def run(g: Graph, k: int, d: int, seed: int, p: int = 50, n: int | None = None,
         gamma: float = 1e-3, n_c: int | None = None, tol: float = 1e-6, max_iter: int = 1000,
         max_steps: int = 30, replicates: int = 20, kmeans_iter: int = 100, lam: float | None = None,
         bracket=None, want_X: bool = False, mlp_params: torch.Tensor | None = None,
-        reorder: bool = True, cg: int = CG_BLOCK, kmeans_on_gpu: bool = True,
+        reorder: bool = True, cg: int = CG_BLOCK_JACOBI, kmeans_on_gpu: bool = True,
         sampling: str = "uniform", lambda_method: str = "dichotomy", cores: int = 1) -> Result:
     """Compressive spectral clustering (Alg. 2) with every graph-sized step on the GPU.
 
@@ -557,7 +558,7 @@ def filter_batched(graphs, lams, p, ds, seeds, rows, normalize=True):
 
 
 def interpolate_batched(graphs, lams, p, gamma, idx, labels_r, ks, tol=1e-6, max_iter=1000,
-                        want_X=True, orders=None, method=CG_BLOCK, weights=None):
+                        want_X=True, orders=None, method=CG_BLOCK_JACOBI, weights=None):
     G = len(graphs)
     ga = _graphs(graphs)
     dev = graphs[0].device
@@ -635,7 +636,7 @@ def kmeans_reduced_device_batched(Fs, ks, seeds, replicates=20, max_iter=100):
 
 def run_batched(graphs, ks, ds, seeds, p=50, ns=None, gamma=1e-3, n_cs=None, tol=1e-6,
                 max_iter=1000, max_steps=30, replicates=20, kmeans_iter=100, brackets=None,
-                lams=None, want_X=False, mlp_params=None, reorder=True, cg=CG_BLOCK,
+                lams=None, want_X=False, mlp_params=None, reorder=True, cg=CG_BLOCK_JACOBI,
                 kmeans_on_gpu=True, sampling="uniform"):
     """Alg. 2 for G graphs at once with the batched calls; graph g matches run(graphs[g], ...)."""
     G = len(graphs)

@@ -39,6 +39,7 @@ Tuning tuning() {
 }
 
 int use_hip_graphs() { return g_tune_graphs.load(); }
+bool xcd_batched() { return g_tune_xcd.load() != 0; }
 
 // Stream used only to record HIP graphs (kernels are captured, never run on
 // it); one per device, default priority, kept for the life of the process.
@@ -817,16 +818,22 @@ csc_status upload_d(double* d, const std::vector<double>& h, hipStream_t s) {
 
 // Block conjugate gradient on the k columns of R = B at once, in the
 // breakdown-free form (Ji and Li, 2017): the search block P is the
-// orthonormalised (rank-revealing) Z = R + P beta, so columns that converge
-// or become dependent leave the search space instead of breaking it.  Every
-// iteration costs one Chebyshev pass (Q = M P) plus a few Gram matrices and
-// block products; the small k x k algebra runs on the host in float64.
-// block_pre forms P before the pass, block_post the rest after it.
-csc_status block_init(BlockState& st, const Layout& L, int k, double tol,
+// orthonormalised (rank-revealing) Z + P beta, so columns that converge or
+// become dependent leave the search space instead of breaking it.  Z is the
+// residual block R, or in the preconditioned form D^-1 R with the Jacobi
+// diagonal D = diag(mask) + gamma I of the operator (its diagonal up to the
+// small h~(L)_ii terms): that maps the sampled rows (~1 + gamma) and the
+// unsampled rows (~gamma) to a common scale.  Every iteration costs one
+// Chebyshev pass (Q = M P) plus a few Gram matrices and block products; the
+// small k x k algebra runs on the host in float64.  block_pre forms P before
+// the pass, block_post the rest after it.
+csc_status block_init(BlockState& st, const Layout& L, int k, double tol, bool jacobi, float gamma,
                       const BlockBufs& b, const double* bnorm2_dev, hipStream_t s) {
   st.L = L;
   st.k = k;
   st.tol = tol;
+  st.jacobi = jacobi;
+  st.gamma = gamma;
   st.b = b;
   CSC_TRY(download(st.bn2, bnorm2_dev, (size_t)k, s));
   st.done.assign(k, 0);
@@ -841,7 +848,10 @@ csc_status block_init(BlockState& st, const Layout& L, int k, double tol,
   }
   st.finished = st.converged = st.nlive == 0;
   st.broke = false;
-  CSC_HIP(hipMemcpyAsync(b.Z, b.R, L.bytes(), hipMemcpyDeviceToDevice, s));
+  if (jacobi)
+    CSC_HIP(launch_jacobi(L, b.R, b.mask, gamma, b.Z, s));
+  else
+    CSC_HIP(hipMemcpyAsync(b.Z, b.R, L.bytes(), hipMemcpyDeviceToDevice, s));
   return CSC_OK;
 }
 
@@ -903,12 +913,17 @@ csc_status block_post(BlockState& st, int it, int max_iter, hipStream_t s) {
     st.finished = true;
     return CSC_OK;
   }
-  // beta = -W^{-1} Q^T R;  Z = R + P beta
-  CSC_HIP(launch_gram(L, b.Q, b.R, sr, k, b.gpart, b.G, k, s));
+  // Z = R (or D^-1 R);  beta = -W^{-1} Q^T Z;  Z = Z + P beta
+  const float* Zr = b.R;
+  if (st.jacobi) {
+    CSC_HIP(launch_jacobi(L, b.R, b.mask, st.gamma, b.Z, s));
+    Zr = b.Z;
+  }
+  CSC_HIP(launch_gram(L, b.Q, Zr, sr, k, b.gpart, b.G, k, s));
   CSC_TRY(download(st.C, b.G, (size_t)sr * k, s));
   dense::chol_solve(st.W, sr, sr, st.C, k, -1.0);
   CSC_TRY(upload_d(b.S_b, st.C, s));
-  CSC_HIP(launch_block_mul(L, 1.f, b.R, b.P, b.S_b, sr, k, k, b.Z, s));
+  CSC_HIP(launch_block_mul(L, 1.f, Zr, b.P, b.S_b, sr, k, k, b.Z, s));
   return CSC_OK;
 }
 
@@ -944,8 +959,8 @@ extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* orde
               "need p >= 1, gamma > 0, tol > 0, max_iter >= 1");
   CSC_REQUIRE(lambda_k >= 0.0 && lambda_k <= 2.0, "lambda_k must lie in [0, 2]");
   CSC_REQUIRE(X == nullptr || ldx >= k, "ldx must be >= k");
-  CSC_REQUIRE(method == CSC_CG_COLUMNS || method == CSC_CG_BLOCK,
-              "method must be CSC_CG_COLUMNS or CSC_CG_BLOCK");
+  CSC_REQUIRE(method == CSC_CG_COLUMNS || method == CSC_CG_BLOCK || method == CSC_CG_BLOCK_JACOBI,
+              "method must be CSC_CG_COLUMNS, CSC_CG_BLOCK or CSC_CG_BLOCK_JACOBI");
   const Layout L = make_layout(N, k, choose_panel_width(N, k, g->nnz));
   CSC_TRY(check_ws(ws, ws_bytes, interp_bytes(L) + (order ? perm_bytes(N, g->nnz, n) : 0)));
   hipStream_t s = as_stream(stream);
@@ -1016,9 +1031,9 @@ extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* orde
 
   std::vector<double> a(p + 1);
   jackson_lowpass(lambda_k, p, a.data());
-  if (method == CSC_CG_BLOCK) {
+  if (method != CSC_CG_COLUMNS) {
     BlockState bs;
-    CSC_TRY(block_init(bs, L, k, tol,
+    CSC_TRY(block_init(bs, L, k, tol, method == CSC_CG_BLOCK_JACOBI, (float)gamma,
                        BlockBufs{P, AP, Ta, Tb, Xi, Rr, Zb, mask, part, gpart, Gd, S_t, S_a, S_na,
                                  S_b, rrn},
                        bnorm2, s));

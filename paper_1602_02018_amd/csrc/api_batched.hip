@@ -85,14 +85,19 @@ struct WorkList {
   BTable table() const { return BTable{d, (int)h.size()}; }
 };
 
-void plan_work(Arena& ar, const std::vector<int>& units, int chunk, WorkList& wl) {
-  build_work(units.data(), (int)units.size(), chunk, wl.h);
+// xcd: lay the entries out in the XCD-aware order of the single-graph step
+// kernels (for tables of panel x tile units).
+void plan_work(Arena& ar, const std::vector<int>& units, int chunk, WorkList& wl,
+               bool xcd = false) {
+  build_work(units.data(), (int)units.size(), chunk, xcd, wl.h);
   wl.d = ar.take<Work>(std::max<size_t>(wl.h.size(), 1));
 }
 
 size_t work_bytes(const std::vector<int>& units) {
   size_t n = 0;
-  for (int u : units) n += (size_t)u;  // chunk >= 1 => at most one entry per unit
+  // chunk >= 1 => at most one entry per unit, plus the XCD-aware layout's
+  // alignment and padding (at most 15 entries per graph)
+  for (int u : units) n += (size_t)u + 16;
   return align_up(std::max<size_t>(n, 1) * sizeof(Work));
 }
 
@@ -202,7 +207,7 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
   ReduceItem* d_red = ar.take<ReduceItem>(G);
   int* d_live = ar.take<int>(G);
   WorkList w_step, w_gauss, w_red;
-  plan_work(ar, units, chunk_for(units), w_step);
+  plan_work(ar, units, chunk_for(units), w_step, xcd_batched());
   plan_work(ar, gunits, chunk_for(gunits), w_gauss);
   plan_work(ar, rvec, 1, w_red);
   float* d_x = ar.take<float>((size_t)G * 52);
@@ -436,7 +441,7 @@ extern "C" csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, con
   GaussItem* d_gauss = ar.take<GaussItem>(G);
   int* bad = ar.take<int>(G);
   WorkList w_step, w_step_a, w_gauss;
-  plan_work(ar, units_s, chunk_for(units_s), w_step);
+  plan_work(ar, units_s, chunk_for(units_s), w_step, xcd_batched());
   plan_work(ar, units_a, chunk_for(units_a), w_step_a);
   plan_work(ar, gunits, chunk_for(gunits), w_gauss);
   if (!ar.ok()) {
@@ -564,8 +569,8 @@ extern "C" csc_status csc_interpolate_batched(
               "lambda, idx, labels_r, n, k, labels and status_out must be non-NULL");
   CSC_REQUIRE(p >= 1 && gamma > 0.0 && tol > 0.0 && max_iter >= 1,
               "need p >= 1, gamma > 0, tol > 0, max_iter >= 1");
-  CSC_REQUIRE(method == CSC_CG_COLUMNS || method == CSC_CG_BLOCK,
-              "method must be CSC_CG_COLUMNS or CSC_CG_BLOCK");
+  CSC_REQUIRE(method == CSC_CG_COLUMNS || method == CSC_CG_BLOCK || method == CSC_CG_BLOCK_JACOBI,
+              "method must be CSC_CG_COLUMNS, CSC_CG_BLOCK or CSC_CG_BLOCK_JACOBI");
   for (int g = 0; g < G; ++g) {
     const int N = graphs[g].n;
     CSC_REQUIRE(idx_in[g] && labels_r[g] && labels[g],
@@ -641,7 +646,7 @@ extern "C" csc_status csc_interpolate_batched(
     lunits[g] = (graphs[g].n + 255) / 256;  // kb_labels: one row per thread, 256 per unit
   }
   WorkList w_step, w_k, w_u2, w_lab;
-  plan_work(ar, units, chunk_for(units), w_step);
+  plan_work(ar, units, chunk_for(units), w_step, xcd_batched());
   plan_work(ar, kvec, 1, w_k);
   plan_work(ar, u2, chunk_for(u2), w_u2);
   plan_work(ar, lunits, chunk_for(lunits), w_lab);
@@ -775,13 +780,13 @@ extern "C" csc_status csc_interpolate_batched(
   CSC_TRY(upload(w_u2.d, w_u2.h, s));
   CSC_TRY(upload(w_lab.d, w_lab.h, s));
 
-  if (method == CSC_CG_BLOCK) {
+  if (method != CSC_CG_COLUMNS) {
     // every graph's block CG; the Chebyshev pass Q = M P of all graphs still
     // iterating is one batched launch per step
     std::vector<BlockState> bs(G);
     for (int g = 0; g < G; ++g) {
       const Buf& b = B[g];
-      CSC_TRY(block_init(bs[g], b.L, k[g], tol,
+      CSC_TRY(block_init(bs[g], b.L, k[g], tol, method == CSC_CG_BLOCK_JACOBI, (float)gamma,
                          BlockBufs{b.P, b.AP, b.Ta, b.Tb, b.Xi, b.Rr, b.Z, b.mask, b.part,
                                    b.gpart, b.G, b.S_t, b.S_a, b.S_na, b.S_b, b.rrn},
                          b.bnorm2, s));

@@ -101,10 +101,30 @@ __global__ __launch_bounds__(kBlock) void kb_labels(const LabelItem* items, cons
 
 }  // namespace
 
-void build_work(const int* units, int G, int chunk, std::vector<Work>& out) {
+void build_work(const int* units, int G, int chunk, bool xcd, std::vector<Work>& out) {
   out.clear();
-  for (int g = 0; g < G; ++g)
-    for (int u = 0; u < units[g]; u += chunk) out.push_back(Work{g, u, std::min(chunk, units[g] - u), 0});
+  for (int g = 0; g < G; ++g) {
+    const int U = units[g];
+    if (!xcd) {
+      for (int u = 0; u < U; u += chunk) out.push_back(Work{g, u, std::min(chunk, U - u), 0});
+      continue;
+    }
+    // The single-graph kernels' contiguous-eighths order: XCD x walks the
+    // x-th eighth of the graph's units.  Entry j of the graph's block goes to
+    // XCD (j mod 8), so the block starts on a multiple of 8 and slab x's
+    // chunks sit at positions x, x + 8, ...; slabs shorter than the longest
+    // are padded with empty entries.
+    while (out.size() % 8) out.push_back(Work{g, 0, 0, 0});
+    const int q = U >> 3, r = U & 7;
+    const int rounds = (q + (r ? 1 : 0) + chunk - 1) / chunk;
+    for (int j = 0; j < rounds; ++j)
+      for (int x = 0; x < 8; ++x) {
+        const int start = x * q + (x < r ? x : r), len = q + (x < r ? 1 : 0);
+        const int u0 = j * chunk;
+        const int cnt = std::max(0, std::min(chunk, len - u0));
+        out.push_back(Work{g, cnt ? start + u0 : 0, cnt, 0});
+      }
+  }
 }
 
 hipError_t launch_cheb_step_batched(const StepArgs* items, BTable t, int epi, bool first,

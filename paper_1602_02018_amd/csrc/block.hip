@@ -159,7 +159,29 @@ __global__ __launch_bounds__(256) void k_block_mul(Layout L, float c0, const flo
   }
 }
 
+// Z = D^-1 R for the diagonal D_ii = mask_i + gamma (the Jacobi
+// preconditioner of the interpolation system): every stored element, four
+// columns of one row per thread (pw is a multiple of 4).
+__global__ void k_jacobi(Layout L, const float* R, const float* mask, float gamma, float* Z) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t e = q * 4;
+  if (e >= L.elems()) return;
+  const int row = (int)((e % L.panel_elems()) / (size_t)L.pw);
+  const float d = mask[row] + gamma;
+  const float4 r = *reinterpret_cast<const float4*>(R + e);
+  *reinterpret_cast<float4*>(Z + e) = make_float4(r.x / d, r.y / d, r.z / d, r.w / d);
+}
+
 }  // namespace
+
+hipError_t launch_jacobi(const Layout& L, const float* R, const float* mask, float gamma, float* Z,
+                         hipStream_t s) {
+  const size_t q = L.elems() / 4;
+  if (q == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_jacobi, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, L, R, mask,
+                     gamma, Z);
+  return hipGetLastError();
+}
 
 GramPlan gram_plan(const Layout& L, int ka, int kb) {
   GramPlan g;

@@ -17,6 +17,8 @@ size_t filter_bytes(const Layout& L);
 size_t count_bytes(const Layout& L, int p);
 size_t interp_bytes(const Layout& L);
 int use_hip_graphs();
+// Batched step work lists follow the single kernels' XCD-aware order (order != 0).
+bool xcd_batched();
 
 // Launch sequence of one pass h~(L) T0 for the accumulating epilogues
 // (EPI_Y: Y = h~(L) T0; EPI_CG: the CG operator), in the process-wide form:
@@ -44,14 +46,16 @@ struct BlockState {
   Layout L;
   int k = 0, sr = 0, ndone = 0, nlive = 0;
   double tol = 0.0;
+  bool jacobi = false;  // preconditioned form: Z = D^-1 R, D = diag(mask) + gamma I
+  float gamma = 0.f;
   BlockBufs b{};
   bool finished = false, converged = false, broke = false;
   std::vector<char> done;
   std::vector<int> iters;
   std::vector<double> bn2, relres, G, T, W, C, N, rn2;
 };
-csc_status block_init(BlockState& st, const Layout& L, int k, double tol, const BlockBufs& b,
-                      const double* bnorm2_dev, hipStream_t s);
+csc_status block_init(BlockState& st, const Layout& L, int k, double tol, bool jacobi, float gamma,
+                      const BlockBufs& b, const double* bnorm2_dev, hipStream_t s);
 csc_status block_pre(BlockState& st, hipStream_t s);
 csc_status block_post(BlockState& st, int it, int max_iter, hipStream_t s);
 void block_finish(BlockState& st, int max_iter);

@@ -131,7 +131,7 @@ hipError_t launch_labels_batched(const LabelItem* items, BTable t, hipStream_t s
 constexpr int kElemsPerUnit = 1024;  // gaussian / update2 / labels: elements per work unit
 
 // Work list for per-item unit counts, chunks of up to `chunk` units.
-void build_work(const int* units, int G, int chunk, std::vector<Work>& out);
+void build_work(const int* units, int G, int chunk, bool xcd, std::vector<Work>& out);
 
 // Process-wide kernel tuning (csc_set_tuning).
 struct Tuning {
@@ -216,6 +216,9 @@ GramPlan gram_plan(const Layout& L, int ka, int kb);
 size_t gram_part_elems(const Layout& L, int kmax);
 hipError_t launch_gram(const Layout& L, const float* A, const float* B, int ka, int kb,
                        double* part, double* G, int ldg, hipStream_t s);
+// Z = R / (mask_i + gamma) row by row (Jacobi preconditioner of the interpolation).
+hipError_t launch_jacobi(const Layout& L, const float* R, const float* mask, float gamma, float* Z,
+                         hipStream_t s);
 hipError_t launch_block_mul(const Layout& L, float c0, const float* In0, const float* In1,
                             const double* S, int kin, int kout, int lds, float* Out,
                             hipStream_t s);

@@ -75,7 +75,7 @@ def test_argument_errors_are_reported_without_gpu_work():
     assert lib.csc_interpolate(C.byref(g), None, 1, 0.5, 50, 0.0, C.c_void_p(16), C.c_void_p(16),
                                None, 2, 2, 1e-6, 10, None, 2, C.c_void_p(16), None, None, None, 0,
                                None) == _lib.CSC_E_INVALID_ARG
-    assert lib.csc_interpolate(C.byref(g), None, 2, 0.5, 50, 1e-3, C.c_void_p(16), C.c_void_p(16),
+    assert lib.csc_interpolate(C.byref(g), None, 3, 0.5, 50, 1e-3, C.c_void_p(16), C.c_void_p(16),
                                None, 2, 2, 1e-6, 10, None, 2, C.c_void_p(16), None, None, None, 0,
                                None) == _lib.CSC_E_INVALID_ARG
     assert b"method" in lib.csc_last_error()

@@ -87,7 +87,7 @@ def test_batched_features_match_single(api, batch):
 
 
 @pytest.mark.parametrize("use_graphs", [1, 0])
-@pytest.mark.parametrize("method", [1, 0])
+@pytest.mark.parametrize("method", [2, 1, 0])
 def test_batched_interpolation_matches_single(api, batch, use_graphs, method):
     _set_graphs(api, use_graphs)
     try:
@@ -112,7 +112,7 @@ def test_batched_interpolation_matches_single(api, batch, use_graphs, method):
         _set_graphs(api, 1)
 
 
-@pytest.mark.parametrize("method", [1, 0])
+@pytest.mark.parametrize("method", [2, 1, 0])
 def test_batched_interpolation_max_iter(api, batch, method):
     G = _graphs(api, batch)
     ks = [g.k for g in batch]

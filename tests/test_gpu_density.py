@@ -65,7 +65,7 @@ def test_sampler_matches_oracle_on_the_same_weights(api, N, n, seed):
     np.testing.assert_allclose(dw.cpu().numpy(), dw_ref, rtol=1e-6)
 
 
-@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("method", [0, 1, 2])
 def test_weighted_interpolation_matches_oracle(api, hetero, method):
     g = api.Graph(hetero.row_ptr, hetero.col)
     A, _ = laplacian.normalized_adjacency(hetero.row_ptr, hetero.col)

@@ -262,7 +262,7 @@ def test_kmeans_on_gpu_features_matches_oracle_given_same_input(api, cfg1):
 # ------------------------------------------------------- interpolation -----
 
 @pytest.mark.parametrize("pw", [4, 8, 16, 0])
-@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("method", [0, 1, 2])
 def test_interpolation_matches_oracle(api, cfg1, pw, method):
     api.set_panel_width(pw)
     try:
@@ -311,12 +311,13 @@ def test_interpolation_single_cluster_and_max_iter(api, cfg1):
     X, lab, iters, relres = interp.interpolate(_A(cfg1), 0.4, 50, 1e-3, omega, np.arange(20) % 3, 3,
                                                tol=1e-12, max_iter=2)
     assert _relfro(res.X.cpu().numpy(), X) <= 1e-4
-    res = api.interpolate(g, 0.4, 50, 1e-3, omega, np.arange(20) % 3, 3, tol=1e-12, max_iter=2,
-                          method=1)
-    assert res.status == _lib.CSC_W_NOT_CONVERGED and np.all(res.iters == 2)
+    for method in (1, 2):
+        res = api.interpolate(g, 0.4, 50, 1e-3, omega, np.arange(20) % 3, 3, tol=1e-12, max_iter=2,
+                              method=method)
+        assert res.status == _lib.CSC_W_NOT_CONVERGED and np.all(res.iters == 2)
 
 
-@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("method", [0, 1, 2])
 def test_interpolation_cluster_without_samples(api, cfg1, method):
     # cluster 2 has no sampled node: b_2 = 0, its column stays 0 and never wins
     g = api.Graph(cfg1.row_ptr, cfg1.col)
@@ -385,3 +386,18 @@ def test_tuning_knobs_do_not_change_results(api, ragged, xcd, nt, pw):
     finally:
         for k, v in zip(keys, old):
             api.set_tuning(k, v)
+
+
+def test_jacobi_block_cg_needs_no_more_iterations(api, cfg1):
+    """The preconditioned block CG solves the same system in at most as many
+    iterations as the plain one (the diagonal maps sampled and unsampled rows
+    to one scale)."""
+    g = api.Graph(cfg1.row_ptr, cfg1.col)
+    omega = sampling.sample(cfg1.n, 47, 0)
+    lab_r = cfg1.truth[omega]
+    a = api.interpolate(g, 0.46875, 50, 1e-3, omega, lab_r, 10, method=1)
+    b = api.interpolate(g, 0.46875, 50, 1e-3, omega, lab_r, 10, method=2)
+    print("block CG iterations, plain / Jacobi:", a.iters.max(), b.iters.max())
+    assert a.status == 0 and b.status == 0
+    assert b.iters.max() <= a.iters.max()
+    assert _relfro(b.X.cpu().numpy(), a.X.cpu().numpy()) <= 1e-3
