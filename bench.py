@@ -10,12 +10,14 @@ labels.  Prints one JSON line:
 * value: whole-job throughput in GB/s, the algorithmic bytes of every
   Chebyshev step, random block and CG update in the step divided by the wall
   time of the step;
-* roofline: the dominant kernel, the Chebyshev (Clenshaw) step of the CG
-  operator at width k on the graph in community order, timed per launch with
-  HIP events on the stream it runs on, against the
-  MI355X HBM peak (8 TB/s); its HBM traffic comes from rocprofv3 FETCH_SIZE /
-  WRITE_SIZE counters recorded in profiles/ and is null when the kernel source
-  changed since they were taken;
+* roofline: the dominant kernel of the step, the Chebyshev-step kernel with
+  the largest launches x time: the moment step of the eigencount passes at
+  width n_c (natural node order) or the Clenshaw step of the CG operator at
+  width k (graph in community order), each timed per launch with HIP events on
+  the stream it runs on, against the MI355X HBM peak (8 TB/s); its HBM traffic
+  comes from rocprofv3 FETCH_SIZE / WRITE_SIZE counters recorded in profiles/
+  and is null when the kernel source changed since they were taken (the other
+  kernel is reported beside it);
 * cpu_baseline: the float64 CPU oracle's filter pass (p products of the CSR
   matrix with an N x k block) on the same graph, in the same unit.
 """
@@ -35,7 +37,11 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 KERNEL_SRC = [os.path.join(ROOT, "paper_1602_02018_amd", "csrc", f)
               for f in ("kernels.hip", "device.hpp", "kernels.hpp", "common.hpp")]
-COUNTERS = os.path.join(ROOT, "profiles", "cheb_step_cg_sbm_N1e5_k100_counters.txt")
+# rocprofv3 counter summaries of the two candidate dominant kernels
+COUNTERS = {
+    "count": os.path.join(ROOT, "profiles", "cheb_step_count_sbm_N1e5_w24_counters.txt"),
+    "cg": os.path.join(ROOT, "profiles", "cheb_step_cg_sbm_N1e5_k100_counters.txt"),
+}
 
 WORKLOADS = {
     # SBM N = 1e5, k = 100, mean degree 16, eps = eps_c / 4; d = ceil(4 ln N), p = 50
@@ -100,12 +106,13 @@ def permuted_csr(gr, order):
     return rp.astype(np.int32), inv[gr.col[src]].astype(np.int32)
 
 
-def read_traffic(per_launch_alg_bytes):
+def read_traffic(which):
     """HBM bytes per launch from the committed counter summary, or None."""
-    if not os.path.exists(COUNTERS):
+    path = COUNTERS[which]
+    if not os.path.exists(path):
         return None
     rec = {}
-    for line in open(COUNTERS):
+    for line in open(path):
         if line.startswith("#") or "=" not in line:
             continue
         key, val = line.split("=", 1)
@@ -244,12 +251,34 @@ def main():
     torch.cuda.synchronize()
     ms_kpm = (time.perf_counter() - t0) / args.steps * 1e3
 
-    # dominant kernel: Chebyshev step of the CG operator (width k) on the graph
-    # in the community order the interpolation runs on, per-launch time
-    avg_s = step_time(api, gr, last.order, k, p, args.kernel_reps, dev)
-    per_launch = step_bytes(N, nnz, k, "clen")
-    achieved = per_launch / avg_s / 1e9
-    traffic = read_traffic(per_launch)
+    # candidate dominant kernels, per-launch times: the moment step of the
+    # eigencount passes (width n_c, natural order) and the Clenshaw step of the
+    # CG operator (width k, on the graph in the order the interpolation used)
+    cands = {}
+    for which, w, order, kind, bkind, launches in (
+            ("count", n_c, None, 1, "mom", last.bisection.steps * p),
+            ("cg", k, last.order, 3, "clen", int(last.interp.iters.max()) * p)):
+        avg_s = step_time(api, gr, order, w, p, args.kernel_reps, dev, kind=kind)
+        per_launch = step_bytes(N, nnz, w, bkind)
+        achieved = per_launch / avg_s / 1e9
+        name = ("k_cheb_step<EPI_MOM> (moment step of the eigencount passes" if which == "count"
+                else "k_cheb_step<EPI_CLEN> (Clenshaw step of the CG operator pass")
+        cands[which] = {
+            "kernel": f"{name}, w={w}, panel width {api.panel_width(N, w, nnz)}"
+                      f"{', community order' if order is not None else ', natural order'})",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": read_traffic(which),
+            "alg_bytes_per_launch": per_launch,
+            "avg_launch_us": round(avg_s * 1e6, 2),
+            "launches_per_step": launches,
+            "ms_per_step": round(launches * avg_s * 1e3, 3),
+        }
+    dom = max(cands, key=lambda c: cands[c]["ms_per_step"])
+    other = "cg" if dom == "count" else "count"
     large = None if args.no_large else large_shapes(api, args, dev)
 
     out = {
@@ -294,19 +323,8 @@ def main():
             "ari_vs_truth": round(float(adjusted_rand_index(kres[-1].labels.cpu().numpy(),
                                                             gr.truth)), 4),
         },
-        "roofline": {
-            "kernel": f"k_cheb_step<EPI_CLEN> (Clenshaw step of the CG operator pass, w={k}, "
-                      f"panel width {api.panel_width(N, k, nnz)}"
-                      f"{', community order' if last.order is not None else ''})",
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": PEAK_HBM_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": traffic,
-            "alg_bytes_per_launch": per_launch,
-            "avg_launch_us": round(avg_s * 1e6, 2),
-        },
+        "roofline": cands[dom],
+        f"roofline_{other}_step": cands[other],
     }
     if large is not None:
         out["chunglu_1e6"] = large
@@ -341,8 +359,9 @@ def step_time(api, gr, order, w, p, reps, dev, kind=3):
 
 def large_shapes(api, args, dev):
     """The 1e6-node Chung-Lu configuration (k = 250, d = 56, p = 60): one
-    end-to-end run and the per-launch Clenshaw step at the filter width d
-    (natural order) and the CG width k (the community order of that run)."""
+    end-to-end run and the per-launch step kernels: the moment step at the
+    count width n_c, the Clenshaw step at the filter width d (natural order)
+    and at the CG width k (in the order that run's interpolation used)."""
     import torch
 
     from oracle.metrics import adjusted_rand_index  # ARI of the labels only
@@ -360,11 +379,15 @@ def large_shapes(api, args, dev):
     out = {"workload": f"chunglu N={N} nnz={nnz} k={k} d={d} p={p} n={api.default_n(k)}",
            "s_per_graph": round(secs, 3),
            "phases_s": {kk: round(v, 4) for kk, v in r.timings.items()},
+           "bisection_steps": r.bisection.steps,
            "cg_iters_max": int(r.interp.iters.max()),
            "ari_vs_truth": round(float(adjusted_rand_index(r.labels.cpu().numpy(), gr.truth)), 4)}
-    for name, w, order in (("filter_step", d, None), ("cg_step", k, r.order)):
-        avg = step_time(api, gr, order, w, p, max(2, args.kernel_reps // 5), dev)
-        by = step_bytes(N, nnz, w, "clen")
+    n_c = api.count_signals(N)
+    for name, w, order, kind, bkind in (("count_step", n_c, None, 1, "mom"),
+                                        ("filter_step", d, None, 3, "clen"),
+                                        ("cg_step", k, r.order, 3, "clen")):
+        avg = step_time(api, gr, order, w, p, max(2, args.kernel_reps // 5), dev, kind=kind)
+        by = step_bytes(N, nnz, w, bkind)
         out[name] = {"w": w, "panel_width": api.panel_width(N, w, nnz),
                      "order": "community" if order is not None else "natural",
                      "avg_launch_us": round(avg * 1e6, 1), "alg_bytes_per_launch": by,
@@ -431,6 +454,13 @@ def bench_batch(args, wl, dev):
         "s_per_graph": {"plain": round(t_plain / len(gs), 4), "batched": round(t_batched / len(gs), 4),
                         "batched_learned": round(t_both / len(gs), 4)},
         "speedup_vs_plain": round(t_plain / t_both, 3),
+        "phases_s": {
+            "plain_sum": {kk: round(sum(r.timings[kk] for r in plain), 4) for kk in plain[0].timings},
+            "batched": {kk: round(v, 4) for kk, v in batched[0].timings.items()},
+            "batched_learned": {kk: round(v, 4) for kk, v in both[0].timings.items()},
+        },
+        "cg_iters_sum": {"plain": int(sum(r.interp.iters.max() for r in plain)),
+                         "batched": int(sum(r.interp.iters.max() for r in batched))},
         "bisection_passes": {"plain": int(sum(r.bisection.steps for r in plain)),
                              "batched_learned": int(sum(r.bisection.steps for r in both))},
         "ari_vs_truth_mean": {"plain": round(float(np.mean(a_plain)), 4),

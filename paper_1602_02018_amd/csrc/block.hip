@@ -2,10 +2,14 @@
 // of the interpolation: Gram matrices A^T B (float32 entries, float64 sums)
 // and right products by a small float64 matrix.
 //
-// Both are memory-light next to a Chebyshev pass (k x k work per node for an
-// N x k block, against p gathered steps), so they use plain float64 FMAs on
-// LDS tiles rather than matrix cores: float64 accumulation keeps the
-// orthonormalisation and the step sizes of the block CG accurate.
+// Both run on the float64 matrix cores (v_mfma_f64_16x16x4f64: a 16 x 16
+// float64 tile += a 16 x 4 by 4 x 16 product, one element of each operand per
+// lane).  Float32 entries are widened exactly, so every product is exact and
+// only the float64 sums round: the orthonormalisation and the step sizes of
+// the block CG keep float64 accuracy.  Operand lanes: lane l supplies row
+// (l mod 16), inner index (l / 16) of the left operand and inner index
+// (l / 16), column (l mod 16) of the right one; the result tile leaves lane l
+// holding rows (l / 16) + 4 v, v = 0..3, of column (l mod 16).
 #include <algorithm>
 
 #include "device.hpp"
@@ -13,8 +17,11 @@
 namespace csc {
 namespace {
 
-constexpr int kT = 64;   // output tile (64 x 64 per workgroup)
-constexpr int kR = 32;   // rows (Gram) or inner columns (product) staged per round
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kGT = 128;  // Gram output tile per workgroup (4 waves of 64 x 64)
+constexpr int kMR = 128;  // block product: rows per workgroup (2 waves of 64)
+constexpr int kMC = 128;  // block product: columns per workgroup (2 waves of 64)
 
 // Offset of column c within row 0 of a panel-major block: element (i, c) is at
 // col_base(L, c) + i * pw.
@@ -23,139 +30,229 @@ __device__ inline size_t col_base(const Layout& L, int c) {
   return (size_t)pan * L.panel_elems() + (size_t)(c - pan * L.pw);
 }
 
-// part[chunk][ti*64 + r][tj*64 + c] = sum over the chunk's rows i of
-// A[i, ti*64 + r] * B[i, tj*64 + c], rows in increasing order.
+__device__ inline v4d mfma64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Columns c..c+3 (c a multiple of 4) of row i of a panel-major block, in two
+// halves so that the load is issued without a branch and its wait lands where
+// the value is used: cols4_load reads the four columns (or, when none of them
+// is live, a stand-in at the block's start) and returns how many are live,
+// cols4_mask zeroes the rest.  c < kvalid <= stored width keeps the four
+// inside one panel (panel widths are multiples of 4).
+__device__ inline float4 cols4_load(const Layout& L, const float* X, int i, int c, int kvalid,
+                                    bool row_ok, int& live) {
+  const bool ok = row_ok && c < kvalid;
+  live = ok ? min(4, kvalid - c) : 0;
+  return *reinterpret_cast<const float4*>(X + (ok ? col_base(L, c) + (size_t)i * L.pw : 0));
+}
+
+__device__ inline float4 cols4_mask(float4 v, int live) {
+  v.x = live > 0 ? v.x : 0.f;
+  v.y = live > 1 ? v.y : 0.f;
+  v.z = live > 2 ? v.z : 0.f;
+  v.w = live > 3 ? v.w : 0.f;
+  return v;
+}
+
+constexpr int kGS = 32;         // Gram: rows per LDS stage
+constexpr int kGLD = kGT + 16;  // LDS row stride (floats): the 4 rows a wave reads at once
+                                // fall on disjoint banks
+
+// part[chunk][r][c] = sum over the chunk's rows i of A[i, r] * B[i, c] for the
+// 128 x 128 output tile (ti, tj).  The workgroup stages 32 rows of both
+// column ranges in LDS (double-buffered, the next stage's global loads in
+// flight during the products); wave w takes the 64 x 64 quarter
+// (w / 2, w mod 2), four rows per matrix-core step.
 __global__ __launch_bounds__(256) void k_gram(Layout L, const float* A, const float* B, int ka,
                                               int kb, int rows_per_chunk, int tiles_b,
-                                              double* part) {
-  __shared__ float As[kR][kT + 1];
-  __shared__ float Bs[kR][kT + 1];
+                                              int rows_pad, double* part) {
+  __shared__ float As[2][kGS][kGLD];
+  __shared__ float Bs[2][kGS][kGLD];
   const int ti = blockIdx.x / tiles_b, tj = blockIdx.x - ti * tiles_b;
   const int chunk = blockIdx.y;
   const int r0 = chunk * rows_per_chunk;
   const int r1 = min(L.n, r0 + rows_per_chunk);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[4][4];
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int q = lane >> 4, c16 = lane & 15;
+  const int wa = (wave >> 1) * 64, wb = (wave & 1) * 64;
+  const int ca0 = ti * kGT, cb0 = tj * kGT;
+  float4 ra[4], rb[4];
+  int la[4], lb[4];
+  auto fetch = [&](int base) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  // a thread always stages the same column (256 is a multiple of 64)
-  const int c = threadIdx.x & (kT - 1), r_0 = threadIdx.x >> 6;
-  const int ca = ti * kT + c, cb = tj * kT + c;
-  const bool va = ca < ka, vb = cb < kb;
-  const float* Ac = A + (va ? col_base(L, ca) : 0);
-  const float* Bc = B + (vb ? col_base(L, cb) : 0);
-  for (int rb = r0; rb < r1; rb += kR) {
-#pragma unroll
-    for (int r = r_0; r < kR; r += 256 / kT) {
-      const int gi = rb + r;
-      const bool in = gi < r1;
-      As[r][c] = (in && va) ? Ac[(size_t)gi * L.pw] : 0.f;
-      Bs[r][c] = (in && vb) ? Bc[(size_t)gi * L.pw] : 0.f;
+    for (int u = 0; u < 4; ++u) {
+      const int f = t + 256 * u, row = f >> 5, c = (f & 31) * 4, i = base + row;
+      ra[u] = cols4_load(L, A, i, ca0 + c, ka, i < r1, la[u]);
+      rb[u] = cols4_load(L, B, i, cb0 + c, kb, i < r1, lb[u]);
     }
-    __syncthreads();
-#pragma unroll 4
-    for (int r = 0; r < kR; ++r) {
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int f = t + 256 * u, row = f >> 5, c = (f & 31) * 4;
+      *reinterpret_cast<float4*>(&As[buf][row][c]) = cols4_mask(ra[u], la[u]);
+      *reinterpret_cast<float4*>(&Bs[buf][row][c]) = cols4_mask(rb[u], lb[u]);
+    }
+  };
+  v4d acc[4][4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int h = 0; h < 4; ++h) acc[g][h] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int nst = (r1 - r0 + kGS - 1) / kGS;
+  fetch(r0);
+  stash(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst) fetch(r0 + (st + 1) * kGS);
+#pragma unroll 2
+    for (int ks = 0; ks < kGS / 4; ++ks) {
       double a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = (double)As[r][ty * 4 + i];
+      for (int g = 0; g < 4; ++g) {
+        a[g] = (double)As[buf][4 * ks + q][wa + 16 * g + c16];
+        b[g] = (double)Bs[buf][4 * ks + q][wb + 16 * g + c16];
+      }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = (double)Bs[r][tx * 4 + j];
+      for (int g = 0; g < 4; ++g)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        for (int h = 0; h < 4; ++h) acc[g][h] = mfma64(a[g], b[h], acc[g][h]);
     }
+    if (st + 1 < nst) stash(buf ^ 1);
     __syncthreads();
   }
-  const int ldp = tiles_b * kT;
-  double* out = part + (size_t)chunk * (gridDim.x / tiles_b) * kT * ldp;
+  const int ldp = tiles_b * kGT;
+  double* out = part + (size_t)chunk * rows_pad * ldp;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int g = 0; g < 4; ++g)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      out[(size_t)(ti * kT + ty * 4 + i) * ldp + tj * kT + tx * 4 + j] = acc[i][j];
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        out[(size_t)(ca0 + wa + 16 * g + q + 4 * v) * ldp + cb0 + wb + 16 * h + c16] =
+            acc[g][h][v];
 }
 
-// G[i * ldg + j] = sum over chunks (in order) of the partial tiles.
-__global__ void k_gram_reduce(const double* part, int chunks, int rows_pad, int cols_pad, int ka,
-                              int kb, double* G, int ldg) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ka * kb) return;
-  const int i = e / kb, j = e - i * kb;
+// G[i * ldg + j] = sum over chunks of the partial tiles: 16 entries per
+// workgroup, 16 threads per entry summing chunks s, s + 16, ... in order,
+// then the 16 slices in order.
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* part, int chunks, int rows_pad,
+                                                     int cols_pad, int ka, int kb, double* G,
+                                                     int ldg) {
+  __shared__ double sh[16][17];
+  const int slice = threadIdx.x >> 4, el = threadIdx.x & 15;
+  const int e = blockIdx.x * 16 + el;
+  const bool ok = e < ka * kb;
+  const int i = ok ? e / kb : 0, j = ok ? e - i * kb : 0;
   double s = 0.0;
-  for (int c = 0; c < chunks; ++c) s += part[((size_t)c * rows_pad + i) * cols_pad + j];
-  G[(size_t)i * ldg + j] = s;
+  if (ok)
+    for (int c = slice; c < chunks; c += 16) s += part[((size_t)c * rows_pad + i) * cols_pad + j];
+  sh[slice][el] = s;
+  __syncthreads();
+  if (slice == 0 && ok) {
+    double t = 0.0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) t += sh[r][el];
+    G[(size_t)i * ldg + j] = t;
+  }
 }
+
+constexpr int kBS = 32;          // block product: inner columns per LDS stage
+constexpr int kXLD = kBS + 4;    // In1 tile stride (floats): a wave's 64 reads hit 64 banks
+constexpr int kSLD = kMC + 16;   // S tile stride (doubles)
 
 // Out[i, j] = c0 * In0[i, j] + sum_{l < kin} In1[i, l] * S[l * lds + j] for
 // every stored column j of the layout (S is zero beyond its live columns, so
-// padding columns stay zero); float64 sums, rounded once to float32.  Out may
-// be In0, never In1.
+// padding columns stay c0 * In0); float64 sums, rounded once to float32.
+// Workgroup: 128 rows x 128 columns; the inner dimension is staged 32 at a
+// time in LDS (In1 rows and S rows, double-buffered); wave w takes the
+// 64 x 64 quarter (w / 2, w mod 2).  Out may be In0 (each element is read and
+// written by the same lane), never In1.
 __global__ __launch_bounds__(256) void k_block_mul(Layout L, float c0, const float* In0,
                                                    const float* In1, const double* S, int kin,
                                                    int kout, int lds, float* Out) {
-  __shared__ float Xs[kT][kR + 1];
-  __shared__ double Ss[kR][kT + 1];
+  __shared__ float Xs[2][kMR][kXLD];
+  __shared__ double Ss[2][kBS][kSLD];
   const int W = L.np * L.pw;
-  const int i0 = blockIdx.x * kT, j0 = blockIdx.y * kT;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[4][4];
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int q = lane >> 4, c16 = lane & 15;
+  const int bi0 = blockIdx.x * kMR, bj0 = blockIdx.y * kMC;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  float4 rx[4];
+  int lx[4];
+  double rs[16];
+  unsigned sok = 0;  // bit u: element u of the S stage is live
+  auto fetch = [&](int l0) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int u = 0; u < 4; ++u) {
+      const int f = t + 256 * u, row = f >> 3, c = (f & 7) * 4, i = bi0 + row;
+      rx[u] = cols4_load(L, In1, i, l0 + c, kin, i < L.n, lx[u]);
+    }
+    sok = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  // a thread always stages the same inner column of In1 and output column of S
-  const int xl = threadIdx.x & (kR - 1), xr0 = threadIdx.x >> 5;
-  const int sc = threadIdx.x & (kT - 1), sl0 = threadIdx.x >> 6;
-  const int gj_s = j0 + sc;
-  for (int lb = 0; lb < kin; lb += kR) {
-    const int gl = lb + xl;
-    const bool vl = gl < kin;
-    const float* Xc = In1 + (vl ? col_base(L, gl) : 0);
+    for (int u = 0; u < 16; ++u) {
+      const int f = t + 256 * u, r = f >> 7, c = f & 127, l = l0 + r, j = bj0 + c;
+      const bool ok = l < kin && j < kout;
+      sok |= (ok ? 1u : 0u) << u;
+      rs[u] = S[ok ? (size_t)l * lds + j : 0];
+    }
+  };
+  auto stash = [&](int buf) {
 #pragma unroll
-    for (int r = xr0; r < kT; r += 256 / kR) {
-      const int gi = i0 + r;
-      Xs[r][xl] = (vl && gi < L.n) ? Xc[(size_t)gi * L.pw] : 0.f;
+    for (int u = 0; u < 4; ++u) {
+      const int f = t + 256 * u, row = f >> 3, c = (f & 7) * 4;
+      *reinterpret_cast<float4*>(&Xs[buf][row][c]) = cols4_mask(rx[u], lx[u]);
     }
 #pragma unroll
-    for (int l = sl0; l < kR; l += 256 / kT) {
-      const int g2 = lb + l;
-      Ss[l][sc] = (g2 < kin && gj_s < kout) ? S[(size_t)g2 * lds + gj_s] : 0.0;
+    for (int u = 0; u < 16; ++u) {
+      const int f = t + 256 * u;
+      Ss[buf][f >> 7][f & 127] = ((sok >> u) & 1u) ? rs[u] : 0.0;
     }
-    __syncthreads();
-#pragma unroll 4
-    for (int l = 0; l < kR; ++l) {
-      double x[4], sv[4];
+  };
+  v4d acc[4][4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) x[i] = (double)Xs[ty * 4 + i][l];
+  for (int g = 0; g < 4; ++g)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) sv[j] = Ss[l][tx * 4 + j];
+    for (int h = 0; h < 4; ++h) acc[g][h] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int nst = (kin + kBS - 1) / kBS;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1, l0 = st * kBS;
+    if (st + 1 < nst) fetch(l0 + kBS);
+    const int ksn = min(kBS, kin - l0 + 3) / 4;  // steps holding live inner columns
+    for (int ks = 0; ks < ksn; ++ks) {
+      double a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int g = 0; g < 4; ++g) a[g] = (double)Xs[buf][wr + 16 * g + c16][4 * ks + q];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(x[i], sv[j], acc[i][j]);
+      for (int h = 0; h < 4; ++h) b[h] = Ss[buf][4 * ks + q][wc + 16 * h + c16];
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int h = 0; h < 4; ++h) acc[g][h] = mfma64(a[g], b[h], acc[g][h]);
     }
+    if (st + 1 < nst) stash(buf ^ 1);
     __syncthreads();
   }
-  // four consecutive columns of one panel (pw is a multiple of 4): float4 access
-  const int gj = j0 + tx * 4;
-  if (gj >= W) return;
-  const size_t cb = col_base(L, gj);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int gi = i0 + ty * 4 + i;
-    if (gi >= L.n) continue;
-    const size_t o = cb + (size_t)gi * L.pw;
-    float4 base = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (c0 != 0.f) base = *reinterpret_cast<const float4*>(In0 + o);
-    float4 out;
-    out.x = (float)((double)c0 * (double)base.x + acc[i][0]);
-    out.y = (float)((double)c0 * (double)base.y + acc[i][1]);
-    out.z = (float)((double)c0 * (double)base.z + acc[i][2]);
-    out.w = (float)((double)c0 * (double)base.w + acc[i][3]);
-    *reinterpret_cast<float4*>(Out + o) = out;
+  for (int h = 0; h < 4; ++h) {
+    const int j = bj0 + wc + 16 * h + c16;
+    if (j >= W) continue;
+    const size_t cbj = col_base(L, j);
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = bi0 + wr + 16 * g + q + 4 * v;
+        if (i >= L.n) continue;
+        const size_t o = cbj + (size_t)i * L.pw;
+        const double base = c0 != 0.f ? (double)c0 * (double)In0[o] : 0.0;
+        Out[o] = (float)(base + acc[g][h][v]);
+      }
   }
 }
 
@@ -185,14 +282,14 @@ hipError_t launch_jacobi(const Layout& L, const float* R, const float* mask, flo
 
 GramPlan gram_plan(const Layout& L, int ka, int kb) {
   GramPlan g;
-  g.tiles_a = (ka + kT - 1) / kT;
-  g.tiles_b = (kb + kT - 1) / kT;
+  g.tiles_a = (ka + kGT - 1) / kGT;
+  g.tiles_b = (kb + kGT - 1) / kGT;
   const int tiles = g.tiles_a * g.tiles_b;
-  int chunks = std::max(1, 512 / tiles);
-  const int max_chunks = (L.n + kR - 1) / kR;
-  chunks = std::min(chunks, max_chunks);
+  // about one workgroup per CU, chunks of at least 512 rows
+  int chunks = std::max(1, 256 / tiles);
+  chunks = std::min(chunks, std::max(1, L.n / 512));
   int rows = (L.n + chunks - 1) / chunks;
-  rows = (rows + kR - 1) / kR * kR;
+  rows = (rows + 3) / 4 * 4;
   g.rows_per_chunk = rows;
   g.chunks = (L.n + rows - 1) / rows;
   return g;
@@ -200,10 +297,10 @@ GramPlan gram_plan(const Layout& L, int ka, int kb) {
 
 size_t gram_part_elems(const Layout& L, int kmax) {
   size_t m = 0;
-  for (int ka = kT; ka < kmax + kT; ka += kT)
-    for (int kb = kT; kb < kmax + kT; kb += kT) {
+  for (int ka = kGT; ka < kmax + kGT; ka += kGT)
+    for (int kb = kGT; kb < kmax + kGT; kb += kGT) {
       const GramPlan g = gram_plan(L, std::min(ka, kmax), std::min(kb, kmax));
-      m = std::max(m, (size_t)g.chunks * g.tiles_a * kT * g.tiles_b * kT);
+      m = std::max(m, (size_t)g.chunks * g.tiles_a * kGT * g.tiles_b * kGT);
     }
   return m;
 }
@@ -212,12 +309,12 @@ hipError_t launch_gram(const Layout& L, const float* A, const float* B, int ka, 
                        double* part, double* G, int ldg, hipStream_t s) {
   const GramPlan g = gram_plan(L, ka, kb);
   hipLaunchKernelGGL(k_gram, dim3((unsigned)(g.tiles_a * g.tiles_b), (unsigned)g.chunks), dim3(256),
-                     0, s, L, A, B, ka, kb, g.rows_per_chunk, g.tiles_b, part);
+                     0, s, L, A, B, ka, kb, g.rows_per_chunk, g.tiles_b, g.tiles_a * kGT, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n = ka * kb;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
-                     g.chunks, g.tiles_a * kT, g.tiles_b * kT, ka, kb, G, ldg);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, s, part,
+                     g.chunks, g.tiles_a * kGT, g.tiles_b * kGT, ka, kb, G, ldg);
   return hipGetLastError();
 }
 
@@ -225,7 +322,7 @@ hipError_t launch_block_mul(const Layout& L, float c0, const float* In0, const f
                             const double* S, int kin, int kout, int lds, float* Out,
                             hipStream_t s) {
   const int W = L.np * L.pw;
-  const dim3 grid((unsigned)((L.n + kT - 1) / kT), (unsigned)((W + kT - 1) / kT));
+  const dim3 grid((unsigned)((L.n + kMR - 1) / kMR), (unsigned)((W + kMC - 1) / kMC));
   hipLaunchKernelGGL(k_block_mul, grid, dim3(256), 0, s, L, c0, In0, In1, S, kin, kout, lds, Out);
   return hipGetLastError();
 }
