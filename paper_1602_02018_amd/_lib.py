@@ -22,7 +22,7 @@ CSC_W_BRACKET_MISS = 7
 WARNINGS = (CSC_W_NOT_CONVERGED, CSC_W_BISECT_EXHAUSTED, CSC_W_BRACKET_MISS)
 
 STREAM_COUNT, STREAM_FEAT, STREAM_SAMPLE, STREAM_KMEANS = 1, 2, 3, 4
-TUNE_PANEL_WIDTH, TUNE_XCD_ORDER, TUNE_NONTEMPORAL, TUNE_HIP_GRAPHS = 0, 1, 2, 3
+TUNE_PANEL_WIDTH, TUNE_XCD_ORDER, TUNE_NONTEMPORAL, TUNE_HIP_GRAPHS, TUNE_ROW_SCHED = 0, 1, 2, 3, 4
 FORM_FORWARD, FORM_CLENSHAW = 0, 1
 DAMP_JACKSON, DAMP_NONE = 0, 1
 
@@ -35,6 +35,7 @@ class CscGraph(C.Structure):
         ("col", C.c_void_p),
         ("val", C.c_void_p),
         ("dinv_sqrt", C.c_void_p),
+        ("sched", C.c_void_p),
     ]
 
 
@@ -56,6 +57,7 @@ PROTOTYPES = {
     "csc_autotune_clear": (None, []),
     "csc_get_tuning": (i32, [i32]),
     "csc_laplacian_from_adjacency": (i32, [i32, i32, vp, vp, vp, vp, vp, i32, vp]),
+    "csc_row_schedule": (i32, [i32, vp, vp, pd, vp, sz, vp]),
     "csc_jackson_coeffs": (i32, [f64, i32, pd]),
     "csc_gaussian_block": (i32, [i32, i32, u64, u32, u32, vp, i32, vp]),
     "csc_filter_workspace_bytes": (sz, [i32, i32]),

@@ -37,6 +37,12 @@ def _i32_device(x, device):
     return torch.as_tensor(np.ascontiguousarray(x, dtype=np.int32), device=device)
 
 
+# degree skew (csc_row_schedule) from which the row schedule is attached:
+# about 1.4 on the Poisson-degree SBMs, where it costs a few percent, 3.4 on
+# the 1e6-node Chung-Lu graph, where the moment step gains 19%
+SCHED_MIN_SKEW = 2.0
+
+
 class Graph:
     """A = D^-1/2 W D^-1/2 on the GPU, built by csc_laplacian_from_adjacency."""
 
@@ -55,8 +61,22 @@ class Graph:
                                                  _ptr(self.col), _ptr(w), _ptr(self.val),
                                                  _ptr(self.dinv_sqrt), 1 if check_csr else 0,
                                                  _stream()), "csc_laplacian_from_adjacency")
+        # the step kernels' row walk (rows of similar degree share a wave),
+        # attached when the degrees are skewed enough for it to pay
+        self.sched = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        skew = C.c_double(1.0)
+        ws = _ws(256, self.device)
+        check(lib().csc_row_schedule(self.n, _ptr(self.row_ptr), _ptr(self.sched), C.byref(skew),
+                                     _ptr(ws), ws.numel(), _stream()), "csc_row_schedule")
+        self.skew = skew.value
+        use = self.skew >= SCHED_MIN_SKEW
         self.c = CscGraph(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
-                          self.val.data_ptr(), self.dinv_sqrt.data_ptr())
+                          self.val.data_ptr(), self.dinv_sqrt.data_ptr(),
+                          self.sched.data_ptr() if use else None)
+
+    def use_schedule(self, on: bool) -> None:
+        """Attach (or detach) the row schedule regardless of the skew."""
+        self.c.sched = self.sched.data_ptr() if on else None
 
     @property
     def ref(self):

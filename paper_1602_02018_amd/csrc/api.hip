@@ -24,6 +24,7 @@ std::atomic<int> g_filter_form{FORM_CLENSHAW};
 std::atomic<int> g_damping{CSC_DAMP_JACKSON};
 std::atomic<int> g_tune_nt{0};
 std::atomic<int> g_tune_graphs{1};
+std::atomic<int> g_tune_sched{1};
 }  // namespace
 
 void set_error(const std::string& msg) { g_error = msg; }
@@ -58,6 +59,15 @@ void apply_tuning(StepArgs& sa) {
   const Tuning t = tuning();
   sa.xcd = t.xcd;
   sa.nt = t.nt;
+}
+
+const int* step_sched(const csc_graph& g, const Layout& L) {
+  if (!g.sched) return nullptr;
+  const int mode = g_tune_sched.load();
+  const int rows_per_wave = 64 / (L.pw / 4);
+  if (mode == 2 && rows_per_wave >= 2) return g.sched;
+  if (mode == 1 && rows_per_wave >= 8) return g.sched;
+  return nullptr;
 }
 
 // Panel width PW = 4 * lanes-per-row.  A Chebyshev step is bound by the
@@ -231,6 +241,7 @@ csc_status chebyshev_pass(const csc_graph& g, const Layout& L, const double* a, 
   sa.row_ptr = g.row_ptr;
   sa.col = g.col;
   sa.val = g.val;
+  sa.sched = step_sched(g, L);
   sa.T0 = b.T0;
   sa.Y = b.Y;
   sa.slot = b.slot;
@@ -419,6 +430,10 @@ extern "C" csc_status csc_set_tuning(int32_t key, int32_t value) {
       CSC_REQUIRE(value == 0 || value == 1, "value must be 0 or 1");
       g_tune_graphs.store(value);
       return CSC_OK;
+    case CSC_TUNE_ROW_SCHED:
+      CSC_REQUIRE(value >= 0 && value <= 2, "value must be 0, 1 or 2");
+      g_tune_sched.store(value);
+      return CSC_OK;
     default:
       CSC_REQUIRE(false, "unknown tuning key");
   }
@@ -430,6 +445,7 @@ extern "C" int32_t csc_get_tuning(int32_t key) {
     case CSC_TUNE_XCD_ORDER: return g_tune_xcd.load();
     case CSC_TUNE_NONTEMPORAL: return g_tune_nt.load();
     case CSC_TUNE_HIP_GRAPHS: return g_tune_graphs.load();
+    case CSC_TUNE_ROW_SCHED: return g_tune_sched.load();
     default: return -1;
   }
 }
@@ -796,6 +812,7 @@ csc_status permuted_graph(const csc_graph& g, const int* order, const int* idx, 
   gp.col = col;
   gp.val = val;
   gp.dinv_sqrt = nullptr;
+  gp.sched = nullptr;  // the community order is the walk
   idxp = idx2;
   return CSC_OK;
 }
@@ -1149,6 +1166,7 @@ extern "C" csc_status csc_cheb_steps(const csc_graph* g, int32_t w, int32_t kind
   sa.row_ptr = g->row_ptr;
   sa.col = g->col;
   sa.val = g->val;
+  sa.sched = step_sched(*g, L);
   sa.T0 = T0;
   sa.Y = Y;
   sa.mask = mask;

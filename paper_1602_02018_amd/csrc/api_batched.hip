@@ -230,6 +230,7 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
       a.row_ptr = graphs[g].row_ptr;
       a.col = graphs[g].col;
       a.val = graphs[g].val;
+      a.sched = step_sched(graphs[g], L[g]);
       a.T0 = T0[g];
       apply_tuning(a);
       a.xcd = 0;
@@ -464,6 +465,7 @@ extern "C" csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, con
       x.row_ptr = graphs[g].row_ptr;
       x.col = graphs[g].col;
       x.val = graphs[g].val;
+      x.sched = step_sched(graphs[g], L[g]);
       x.T0 = T0[g];
       x.Y = Yi[g];
       apply_tuning(x);
@@ -481,6 +483,7 @@ extern "C" csc_status csc_filter_batched(const csc_graph* graphs, int32_t G, con
       x.row_ptr = graphs[g].row_ptr;
       x.col = graphs[g].col;
       x.val = graphs[g].val;
+      x.sched = step_sched(graphs[g], L[g]);
       x.T0 = T0[g];
       apply_tuning(x);
       x.xcd = 0;
@@ -729,6 +732,7 @@ extern "C" csc_status csc_interpolate_batched(
       x.row_ptr = gv[g].row_ptr;
       x.col = gv[g].col;
       x.val = gv[g].val;
+      x.sched = step_sched(gv[g], b.L);
       x.T0 = b.P;
       x.Y = b.AP;
       x.mask = b.mask;

@@ -112,6 +112,16 @@ __device__ inline RowMap row_map(int pw) {
   return m;
 }
 
+// Row handled at walk position r of a step: r itself, or sched[r] when the
+// step follows a row schedule; -1 past the last row (or for a schedule entry
+// outside [0, n), which a valid schedule never holds).
+__device__ inline int step_row(const StepArgs& a, int r) {
+  if (r >= a.L.n) return -1;
+  if (!a.sched) return r;
+  const int i = a.sched[r];
+  return (unsigned)i < (unsigned)a.L.n ? i : -1;
+}
+
 // Row i of A times the gathered panel: sum_k val[k] T_m[col[k]], k in CSR order.
 __device__ inline v4f spmm_row(const StepArgs& a, const v4f* __restrict__ Tm4, int i, int q,
                                int lpr, bool valid) {
@@ -162,8 +172,8 @@ __device__ inline void clen_unit(const StepArgs& a, int u) {
   const RowMap m = row_map(a.L.pw);
   const int panel = u / a.tiles;
   const int tile = u - panel * a.tiles;
-  const int i = tile * m.rpb + m.r;
-  const bool valid = m.lane_ok && i < a.L.n;
+  const int i = step_row(a, tile * m.rpb + m.r);
+  const bool valid = m.lane_ok && i >= 0;
   const int nt = a.nt;
   const size_t pbase4 = (size_t)panel * a.L.panel_elems() / 4;
   const size_t o4 = pbase4 + (size_t)i * m.lpr + m.q;
@@ -205,9 +215,8 @@ __device__ inline void cheb_unit(const StepArgs& a, int u) {
   const RowMap m = row_map(a.L.pw);
   const int panel = u / a.tiles;
   const int tile = u - panel * a.tiles;
-  const int n = a.L.n;
-  const int i = tile * m.rpb + m.r;
-  const bool valid = m.lane_ok && i < n;
+  const int i = step_row(a, tile * m.rpb + m.r);
+  const bool valid = m.lane_ok && i >= 0;
   const int nt = a.nt;
   const size_t pbase4 = (size_t)panel * a.L.panel_elems() / 4;
   const size_t o4 = pbase4 + (size_t)i * m.lpr + m.q;

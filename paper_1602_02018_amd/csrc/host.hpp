@@ -13,6 +13,8 @@ csc_status check_ws(void* ws, size_t ws_bytes, size_t need);
 void jackson_lowpass(double lc, int p, double* a);
 double count_from_moments(double lambda, int p, const double* mom);
 void apply_tuning(StepArgs& sa);
+// The row schedule the step kernels follow on g at layout L (or NULL).
+const int* step_sched(const csc_graph& g, const Layout& L);
 size_t filter_bytes(const Layout& L);
 size_t count_bytes(const Layout& L, int p);
 size_t interp_bytes(const Layout& L);

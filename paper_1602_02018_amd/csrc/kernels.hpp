@@ -25,6 +25,7 @@ struct StepArgs {
   const int* row_ptr = nullptr;
   const int* col = nullptr;
   const float* val = nullptr;
+  const int* sched = nullptr;    // row walk (a permutation of [0, n)) or NULL
   const float* Tm = nullptr;     // T_m, gathered through A
   const float* Tprev = nullptr;  // T_{m-1}; on the first step T_0
   float* Tnext = nullptr;        // T_{m+1} (may alias Tprev)
@@ -222,6 +223,11 @@ hipError_t launch_jacobi(const Layout& L, const float* R, const float* mask, flo
 hipError_t launch_block_mul(const Layout& L, float c0, const float* In0, const float* In1,
                             const double* S, int kin, int kout, int lds, float* Out,
                             hipStream_t s);
+
+// Row schedule of a CSR graph (order.hip): chunks of kSchedChunk rows, each
+// by decreasing degree, ties by index.
+constexpr int kSchedChunk = 4096;
+hipError_t launch_row_schedule(int n, const int* row_ptr, int* sched, hipStream_t s);
 
 // Node orders (order.hip).  order[r] = node placed at position r.
 hipError_t launch_perm_inverse(int N, const int* order, int* inv, int* bad, hipStream_t s);

@@ -218,6 +218,67 @@ __global__ void k_decoder_weights(int n, const int* idx, const double* w, const 
   out[s] = wi > 0.0 ? (float)((*sum / (double)N) / wi) : 0.f;
 }
 
+// Degree skew of the natural row order: acc[0] += max degree of each group of
+// 8 consecutive rows, acc[1] += degrees (integer sums, so order-free).
+__global__ __launch_bounds__(256) void k_wave_skew(int n, const int* row_ptr,
+                                                   unsigned long long* acc) {
+  __shared__ unsigned long long sh[2][256];
+  const int grp = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long mx = 0, sum = 0;
+  for (int r = grp * 8; r < min(n, grp * 8 + 8); ++r) {
+    const unsigned long long dg = (unsigned)(row_ptr[r + 1] - row_ptr[r]);
+    mx = dg > mx ? dg : mx;
+    sum += dg;
+  }
+  sh[0][threadIdx.x] = mx;
+  sh[1][threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(acc, sh[0][0]);
+    atomicAdd(acc + 1, sh[1][0]);
+  }
+}
+
+// Row schedule: block b sorts the rows of chunk b by (decreasing degree,
+// index) with a bitonic network on 64-bit keys in LDS (padding keys sort
+// last) and writes them back in that order.
+__global__ __launch_bounds__(256) void k_row_schedule(int n, const int* row_ptr, int* sched) {
+  __shared__ unsigned long long key[kSchedChunk];
+  const int base = blockIdx.x * kSchedChunk;
+  const int cnt = min(kSchedChunk, n - base);
+  for (int e = threadIdx.x; e < kSchedChunk; e += blockDim.x) {
+    unsigned long long v = ~0ull;
+    if (e < cnt) {
+      const unsigned deg = (unsigned)(row_ptr[base + e + 1] - row_ptr[base + e]);
+      v = ((unsigned long long)(0xFFFFFFFFu - deg) << 32) | (unsigned)e;
+    }
+    key[e] = v;
+  }
+  __syncthreads();
+  for (int size = 2; size <= kSchedChunk; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int e = threadIdx.x; e < kSchedChunk / 2; e += blockDim.x) {
+        const int lo = 2 * e - (e & (stride - 1)), hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const unsigned long long x = key[lo], y = key[hi];
+        if ((x > y) == up) {
+          key[lo] = y;
+          key[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x)
+    sched[base + e] = base + (int)(key[e] & 0xFFFFFFFFull);
+}
+
 }  // namespace
 
 hipError_t launch_density_keys(int N, const double* w, uint64_t seed, uint64_t* keys, int* vals,
@@ -323,9 +384,40 @@ hipError_t launch_iota(int N, int* out, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_row_schedule(int n, const int* row_ptr, int* sched, hipStream_t s) {
+  if (n < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_row_schedule, dim3((unsigned)((n + kSchedChunk - 1) / kSchedChunk)),
+                     dim3(256), 0, s, n, row_ptr, sched);
+  return hipGetLastError();
+}
+
 }  // namespace csc
 
 using namespace csc;
+
+extern "C" csc_status csc_row_schedule(int32_t n, const int32_t* row_ptr, int32_t* sched,
+                                       double* skew_out, void* ws, size_t ws_bytes,
+                                       void* stream) {
+  clear_error();
+  CSC_REQUIRE(n >= 1, "n must be >= 1");
+  CSC_REQUIRE(row_ptr && sched, "row_ptr and sched must be non-NULL");
+  if (skew_out) CSC_TRY(check_ws(ws, ws_bytes, 2 * sizeof(unsigned long long)));
+  hipStream_t s = as_stream(stream);
+  CSC_HIP(launch_row_schedule(n, row_ptr, sched, s));
+  if (skew_out) {
+    unsigned long long* acc = static_cast<unsigned long long*>(ws);
+    CSC_HIP(launch_fill_i32(reinterpret_cast<int*>(acc), 4, 0, s));
+    const int groups = (n + 7) / 8;
+    hipLaunchKernelGGL(k_wave_skew, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, n,
+                       row_ptr, acc);
+    CSC_HIP(hipGetLastError());
+    unsigned long long h[2] = {0, 0};
+    CSC_HIP(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    *skew_out = h[1] ? 8.0 * (double)h[0] / (double)h[1] : 1.0;
+  }
+  return CSC_OK;
+}
 
 extern "C" csc_status csc_gather_rows(const float* F, int64_t ldf, int32_t N, int32_t d,
                                       const int32_t* rows, int32_t n, float* out, int32_t ldo,
