@@ -24,7 +24,9 @@ namespace csc {
 namespace {
 
 constexpr int kKmBlock = 1024;
-constexpr int kLdsDoubles = 6144;  // 48 KB of LDS per workgroup, reused by the phases
+// 144 KB of LDS per workgroup (of the 160 KB of a CU), reused by the phases: the
+// centroids of k = 250 clusters in 56 dimensions stay in LDS during Lloyd
+constexpr int kLdsDoubles = 18432;
 
 struct KmItem {
   const double* X;   // n x d, row-major
