@@ -60,12 +60,13 @@ def step_bytes(N, nnz, w, kind):
 
     CSR read once (4(N+1) + 8 nnz) plus, per node and column, 4 bytes for each
     block touched: forward recurrence with a running sum, gathered T_m,
-    T_{m-1}, T_{m+1} and the sum read + write (kind "y": 20); the moment form
-    reads T_0 instead of the sum ("mom": 16); Clenshaw's step reads the
-    gathered b_{m+1}, b_{m+2} and R and writes b_m ("clen": 16).
+    T_{m-1}, T_{m+1} and the sum read + write (kind "y": 20); the moment step
+    touches T_m (gathered, and its own row for the products), T_{m-1} and
+    T_{m+1} ("mom": 12); Clenshaw's step reads the gathered b_{m+1}, b_{m+2}
+    and R and writes b_m ("clen": 16).
     """
     csr = 4 * (N + 1) + 8 * nnz
-    per = {"y": 20, "mom": 16, "ys": 12, "clen": 16}[kind]
+    per = {"y": 20, "mom": 12, "ys": 12, "clen": 16}[kind]
     return csr + per * N * w
 
 
@@ -75,9 +76,15 @@ def step_bytes(N, nnz, w, kind):
 BLOCK_CG_BLOCKS = 21
 
 
+def moment_steps(p):
+    """Steps of an eigencount pass of order p: the doubling identities give
+    p + 1 moments from T_0 .. T_ceil(p/2)."""
+    return (p + 1) // 2
+
+
 def job_bytes(N, nnz, k, d, n_c, p, bis_steps, cg_iters):
     gauss = 4 * N
-    count = bis_steps * (gauss * n_c + p * step_bytes(N, nnz, n_c, "mom"))
+    count = bis_steps * (gauss * n_c + moment_steps(p) * step_bytes(N, nnz, n_c, "mom"))
     feat = gauss * d + p * step_bytes(N, nnz, d, "clen") + 8 * N * d
     cg = cg_iters * (p * step_bytes(N, nnz, k, "clen") + BLOCK_CG_BLOCKS * 4 * N * k)
     return count + feat + cg
@@ -256,7 +263,7 @@ def main():
     # CG operator (width k, on the graph in the order the interpolation used)
     cands = {}
     for which, w, order, kind, bkind, launches in (
-            ("count", n_c, None, 1, "mom", last.bisection.steps * p),
+            ("count", n_c, None, 1, "mom", last.bisection.steps * moment_steps(p)),
             ("cg", k, last.order, 3, "clen", int(last.interp.iters.max()) * p)):
         avg_s = step_time(api, gr, order, w, p, args.kernel_reps, dev, kind=kind)
         per_launch = step_bytes(N, nnz, w, bkind)

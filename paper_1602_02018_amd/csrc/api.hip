@@ -178,7 +178,7 @@ struct Pass {
   float* Ta = nullptr;
   float* Tb = nullptr;
   float* Y = nullptr;
-  double* part = nullptr;  // EPI_MOM: (p+1) x nblocks; EPI_CG: columns x tiles
+  double* part = nullptr;  // EPI_MOM: moment_raw(p) x nblocks; EPI_CG: columns x tiles
   const int* slot = nullptr;
   float* Ys = nullptr;
   int lds = 0;
@@ -263,8 +263,9 @@ csc_status chebyshev_pass(const csc_graph& g, const Layout& L, const double* a, 
     }
     return CSC_OK;
   }
-  for (int m = 0; m < p; ++m) {  // step m produces T_{m+1}
-    const bool first = m == 0, last = m + 1 == p;
+  const int steps = epi == EPI_MOM ? moment_steps(p) : p;
+  for (int m = 0; m < steps; ++m) {  // step m produces T_{m+1}
+    const bool first = m == 0, last = m + 1 == steps;
     sa.Tm = first ? b.T0 : ((m & 1) ? b.Ta : b.Tb);
     sa.Tprev = first ? b.T0 : ((m - 1) == 0 ? b.T0 : (((m - 1) & 1) ? b.Ta : b.Tb));
     sa.Tnext = ((m + 1) & 1) ? b.Ta : b.Tb;
@@ -272,8 +273,9 @@ csc_status chebyshev_pass(const csc_graph& g, const Layout& L, const double* a, 
     sa.c1 = (float)a[m + 1];
     int e = epi;
     if (epi == EPI_MOM) {
-      sa.part = b.part + (size_t)(m + 1) * nblocks;
-      sa.part2 = b.part;
+      sa.part = b.part + (size_t)(2 * m + 1) * nblocks;
+      sa.part2 = b.part + (size_t)(2 * m + 2) * nblocks;
+      sa.part0 = b.part;
     } else if (epi == EPI_CG) {
       e = last ? EPI_CG : EPI_Y;
       sa.part = b.part;
@@ -294,11 +296,21 @@ size_t filter_bytes(const Layout& L) {
   return b + 256;
 }
 
+int moment_steps(int p) { return (p + 1) / 2; }
+int moment_raw(int p) { return 2 * moment_steps(p) + 1; }
+
+void moments_from_raw(const double* raw, int p, double* mom) {
+  mom[0] = raw[0];
+  if (p >= 1) mom[1] = raw[1];
+  for (int m = 2; m <= p; ++m)
+    mom[m] = (m & 1) ? 2.0 * raw[m] - raw[1] : 2.0 * raw[m] - raw[0];
+}
+
 size_t count_bytes(const Layout& L, int p) {
   const size_t nblocks = (size_t)L.np * tiles_for(L);
   size_t b = 3 * align_up(L.bytes());
-  b += align_up((size_t)(p + 1) * nblocks * sizeof(double));
-  b += align_up((size_t)(p + 1) * sizeof(double));
+  b += align_up((size_t)moment_raw(p) * nblocks * sizeof(double));
+  b += align_up((size_t)moment_raw(p) * sizeof(double));
   return b + 256;
 }
 
@@ -340,8 +352,8 @@ CountBuffers carve_count(Arena& ar, const Layout& L, int p) {
   c.T0 = ar.take<float>(L.elems());
   c.Ta = ar.take<float>(L.elems());
   c.Tb = ar.take<float>(L.elems());
-  c.part = ar.take<double>((size_t)(p + 1) * nblocks);
-  c.mom = ar.take<double>(p + 1);
+  c.part = ar.take<double>((size_t)moment_raw(p) * nblocks);
+  c.mom = ar.take<double>(moment_raw(p));
   return c;
 }
 
@@ -356,9 +368,12 @@ csc_status moments_pass(const csc_graph& g, const Layout& L, int p, uint64_t see
   b.part = c.part;
   std::vector<double> zero(p + 1, 0.0);
   CSC_TRY(chebyshev_pass(g, L, zero.data(), p, EPI_MOM, b, s));
-  CSC_HIP(launch_reduce(c.part, (int)nblocks, p + 1, c.mom, s));
-  CSC_HIP(hipMemcpyAsync(mom_host, c.mom, (p + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+  const int nraw = moment_raw(p);
+  CSC_HIP(launch_reduce(c.part, (int)nblocks, nraw, c.mom, s));
+  std::vector<double> raw(nraw);
+  CSC_HIP(hipMemcpyAsync(raw.data(), c.mom, nraw * sizeof(double), hipMemcpyDeviceToHost, s));
   CSC_HIP(hipStreamSynchronize(s));
+  moments_from_raw(raw.data(), p, mom_host);
   return CSC_OK;
 }
 
@@ -1175,6 +1190,7 @@ extern "C" csc_status csc_cheb_steps(const csc_graph* g, int32_t w, int32_t kind
   sa.c1 = 0.25f;
   sa.part = part;
   sa.part2 = part;
+  sa.part0 = part;
   apply_tuning(sa);
   const int epi = kind == 0 ? EPI_Y : (kind == 1 ? EPI_MOM : (kind == 2 ? EPI_CG : EPI_CLEN));
   for (int m = 1; m <= steps; ++m) {

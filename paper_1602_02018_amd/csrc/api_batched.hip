@@ -157,9 +157,9 @@ using namespace csc;
 extern "C" size_t csc_estimate_workspace_bytes_batched(const csc_graph* graphs, int32_t G,
                                                        const int32_t* n_signals, int32_t p) {
   if (!graphs || G < 1 || !n_signals || p < 1) return 0;
-  size_t b = desc_bytes(G, p) + align_up((size_t)G * (p + 1) * sizeof(double));
+  size_t b = desc_bytes(G, p) + align_up((size_t)G * moment_raw(p) * sizeof(double));
   b += mlp_workspace(G) + align_up((size_t)G * 54 * sizeof(float)) + 1024;  // learned mode
-  std::vector<int> u(G), gu(G), rv(G, p + 1);
+  std::vector<int> u(G), gu(G), rv(G, moment_raw(p));
   for (int g = 0; g < G; ++g) {
     b += max_widths(graphs[g].n, n_signals[g], [p](const Layout& L) { return count_bytes(L, p); });
     u[g] = (int)std::min<size_t>(max_units(graphs[g].n, n_signals[g]), 1u << 30);
@@ -195,7 +195,8 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
   Arena ar(ws, ws_bytes);
 
   std::vector<Layout> L(G);
-  std::vector<int> tiles(G), units(G), gunits(G), rvec(G, p + 1);
+  const int msteps = moment_steps(p), nraw = moment_raw(p);
+  std::vector<int> tiles(G), units(G), gunits(G), rvec(G, nraw);
   std::vector<float*> T0(G), Ta(G), Tb(G);
   std::vector<double*> part(G);
   for (int g = 0; g < G; ++g) {
@@ -207,10 +208,10 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
     T0[g] = ar.take<float>(L[g].elems());
     Ta[g] = ar.take<float>(L[g].elems());
     Tb[g] = ar.take<float>(L[g].elems());
-    part[g] = ar.take<double>((size_t)(p + 1) * units[g]);
+    part[g] = ar.take<double>((size_t)nraw * units[g]);
   }
-  double* mom = ar.take<double>((size_t)G * (p + 1));
-  StepArgs* d_steps = ar.take<StepArgs>((size_t)p * G);
+  double* mom = ar.take<double>((size_t)G * nraw);
+  StepArgs* d_steps = ar.take<StepArgs>((size_t)msteps * G);
   GaussItem* d_gauss = ar.take<GaussItem>(G);
   ReduceItem* d_red = ar.take<ReduceItem>(G);
   int* d_live = ar.take<int>(G);
@@ -227,11 +228,11 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
   }
 
   // per-step descriptors never change between passes
-  std::vector<StepArgs> h_steps((size_t)p * G);
+  std::vector<StepArgs> h_steps((size_t)msteps * G);
   std::vector<ReduceItem> h_red(G);
   std::vector<GaussItem> h_gauss(G);
   for (int g = 0; g < G; ++g) {
-    for (int m = 0; m < p; ++m) {
+    for (int m = 0; m < msteps; ++m) {
       StepArgs& a = h_steps[(size_t)m * G + g];
       a.L = L[g];
       a.tiles = tiles[g];
@@ -247,12 +248,13 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
       a.Tm = first ? T0[g] : ((m & 1) ? Ta[g] : Tb[g]);
       a.Tprev = first ? T0[g] : ((m - 1) == 0 ? T0[g] : (((m - 1) & 1) ? Ta[g] : Tb[g]));
       a.Tnext = ((m + 1) & 1) ? Ta[g] : Tb[g];
-      a.part = part[g] + (size_t)(m + 1) * units[g];
-      a.part2 = part[g];
+      a.part = part[g] + (size_t)(2 * m + 1) * units[g];
+      a.part2 = part[g] + (size_t)(2 * m + 2) * units[g];
+      a.part0 = part[g];
     }
     h_red[g].part = part[g];
     h_red[g].len = units[g];
-    h_red[g].out = mom + (size_t)g * (p + 1);
+    h_red[g].out = mom + (size_t)g * nraw;
     h_red[g].live = d_live + g;
     h_gauss[g].L = L[g];
     h_gauss[g].seed = seeds[g];
@@ -268,9 +270,9 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
 
   auto pass = [&](hipStream_t st) -> csc_status {
     CSC_HIP(launch_gaussian_batched(d_gauss, w_gauss.table(), st));
-    for (int m = 0; m < p; ++m)
+    for (int m = 0; m < msteps; ++m)
       CSC_HIP(launch_cheb_step_batched(d_steps + (size_t)m * G, w_step.table(), EPI_MOM, m == 0,
-                                       m + 1 == p, st));
+                                       m + 1 == msteps, st));
     CSC_HIP(launch_reduce_batched(d_red, w_red.table(), st));
     return CSC_OK;
   };
@@ -288,7 +290,7 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
       st[g].hi = brackets[2 * g + 1];
     }
   std::vector<int> live(G);
-  std::vector<double> hmom((size_t)G * (p + 1));
+  std::vector<double> hraw((size_t)G * nraw), hmom((size_t)G * (p + 1));
   std::vector<float> hx((size_t)G * 52, 0.f), hy((size_t)G * 2, 0.f);
   Captured cap;
   const int rounds = mlp_params ? max_steps : 2 * max_steps;
@@ -303,9 +305,11 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
     CSC_TRY(upload(d_live, live, s));
     CSC_TRY(upload(d_gauss, h_gauss, s));
     CSC_TRY(run_pass(pass, cap, s));
-    CSC_HIP(hipMemcpyAsync(hmom.data(), mom, hmom.size() * sizeof(double), hipMemcpyDeviceToHost,
+    CSC_HIP(hipMemcpyAsync(hraw.data(), mom, hraw.size() * sizeof(double), hipMemcpyDeviceToHost,
                            s));
     CSC_HIP(hipStreamSynchronize(s));
+    for (int g = 0; g < G; ++g)
+      if (live[g]) moments_from_raw(hraw.data() + (size_t)g * nraw, p, hmom.data() + (size_t)g * (p + 1));
     bool need_mlp = false;
     for (int g = 0; g < G; ++g) {
       if (!live[g]) continue;

@@ -266,19 +266,26 @@ __device__ inline void cheb_unit(const StepArgs& a, int u) {
       }
     }
   } else if constexpr (EPI == EPI_MOM) {
+    // products for the Chebyshev doubling identities T_{2m} = 2 T_m^2 - 1 and
+    // T_{2m+1} = 2 T_m T_{m+1} - T_1: <T_m, T_{m+1}> and <T_{m+1}, T_{m+1}>
+    // (and <T_0, T_0> on the first step), so that p moments take p/2 steps
     __shared__ double sh[8];
-    double s1 = 0.0, s0 = 0.0;
+    double sx = 0.0, sq = 0.0, s0 = 0.0;
     if (valid) {
-      const v4f r0 = FIRST ? x0 : ld4(a.T0, o4, nt);
-      s1 = dot4v(r0, tn);
-      if (FIRST) s0 = dot4v(r0, r0);
+      const v4f tm = FIRST ? x0 : ld4(a.Tm, o4, nt);
+      sx = dot4v(tm, tn);
+      sq = dot4v(tn, tn);
+      if (FIRST) s0 = dot4v(tm, tm);
     }
-    const double b1 = block_sum(s1, sh);
-    if (threadIdx.x == 0) a.part[u] = b1;
+    const double bx = block_sum(sx, sh);
+    if (threadIdx.x == 0) a.part[u] = bx;
+    __syncthreads();
+    const double bq = block_sum(sq, sh);
+    if (threadIdx.x == 0) a.part2[u] = bq;
     if (FIRST) {
       __syncthreads();
       const double b0 = block_sum(s0, sh);
-      if (threadIdx.x == 0) a.part2[u] = b0;
+      if (threadIdx.x == 0) a.part0[u] = b0;
     }
     __syncthreads();  // shared memory is reused by the next unit of a grid-stride loop
   } else if constexpr (EPI == EPI_CG) {

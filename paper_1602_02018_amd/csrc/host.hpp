@@ -17,6 +17,14 @@ void apply_tuning(StepArgs& sa);
 const int* step_sched(const csc_graph& g, const Layout& L);
 size_t filter_bytes(const Layout& L);
 size_t count_bytes(const Layout& L, int p);
+// A moment pass of order p runs moment_steps(p) = ceil(p/2) Chebyshev steps
+// and leaves moment_raw(p) = 2 ceil(p/2) + 1 float64 products: raw[0] =
+// <T_0, T_0>, raw[2j-1] = <T_{j-1}, T_j>, raw[2j] = <T_j, T_j>.
+// moments_from_raw turns them into mu_0..mu_p by the doubling identities
+// mu_{2j} = 2 <T_j, T_j> - mu_0 and mu_{2j+1} = 2 <T_j, T_{j+1}> - mu_1.
+int moment_steps(int p);
+int moment_raw(int p);
+void moments_from_raw(const double* raw, int p, double* mom);
 size_t interp_bytes(const Layout& L);
 int use_hip_graphs();
 // Batched step work lists follow the single kernels' XCD-aware order (order != 0).

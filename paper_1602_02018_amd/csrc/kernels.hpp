@@ -9,7 +9,7 @@ namespace csc {
 
 enum Epi : int {
   EPI_Y = 0,    // Y (panel-major) accumulates coefficient * T_{m+1}
-  EPI_MOM = 1,  // float64 partial of <T_0, T_{m+1}> per workgroup
+  EPI_MOM = 1,  // float64 partials of <T_m, T_{m+1}> and <T_{m+1}, T_{m+1}> per workgroup
   EPI_YS = 2,   // only sampled rows accumulate, straight into a node-major output
   EPI_CG = 3,   // last step of the CG operator: AP = mask*P + gamma*(P - h~(L)P)
   // Clenshaw's backward recurrence (b_m = c0 R + c1 A b_{m+1} - b_{m+2}, with
@@ -33,7 +33,8 @@ struct StepArgs {
   float* Y = nullptr;            // accumulator (EPI_Y, EPI_CG)
   float c0 = 0.f, c1 = 0.f;      // first step: Y = c0 T_0 + c1 T_1; later: Y += c1 T_{m+1}
   double* part = nullptr;        // partial sums
-  double* part2 = nullptr;       // second partial on the first moment step (mu_0)
+  double* part2 = nullptr;       // EPI_MOM: partial of <T_{m+1}, T_{m+1}>
+  double* part0 = nullptr;       // EPI_MOM, first step: partial of <T_0, T_0>
   const int* slot = nullptr;     // EPI_YS: output row of node i or -1
   float* Ys = nullptr;
   int lds = 0;

@@ -489,3 +489,22 @@ def test_one_pass_kpm_dichotomy():
     R = philox.gaussian_block(0, g.n, 400, 1, philox.COUNT)
     for lt, ct in trace[:4]:
         assert abs(eigencount.eigencount(A, lt, 50, R) - ct) <= 1e-9 * max(1.0, abs(ct))
+
+
+def test_chebyshev_doubling_identities_for_moments():
+    """The GPU's eigencount pass forms mu_0..mu_p from T_0..T_ceil(p/2) by
+    T_{2j} = 2 T_j^2 - 1 and T_{2j+1} = 2 T_j T_{j+1} - T_1 (A symmetric, so
+    <R, T_{2j} R> = 2 <T_j R, T_j R> - <R, R> and likewise for odd orders);
+    check the identities on the oracle's own terms."""
+    gr = synth.sbm_config(300, 3, seed=5)
+    A, _ = laplacian.normalized_adjacency(gr.row_ptr, gr.col)
+    R = philox.gaussian_block(3, gr.n, 6, 1, philox.COUNT)
+    p = 21
+    T = list(cheb.chebyshev_terms(A, R, p))
+    mu = cheb.moments(A, R, p)
+    dot = lambda X, Y: float(np.sum(X * Y))
+    for m in range(p + 1):
+        j = m // 2
+        est = (2 * dot(T[j], T[j]) - dot(T[0], T[0])) if m % 2 == 0 and m > 0 else \
+              (2 * dot(T[j], T[j + 1]) - dot(T[0], T[1])) if m % 2 == 1 and m > 1 else mu[m]
+        assert abs(est - mu[m]) <= 1e-12 * mu[0], (m, est, mu[m])
