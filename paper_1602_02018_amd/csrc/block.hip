@@ -159,18 +159,25 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* part, int chu
   }
 }
 
-constexpr int kBS = 32;          // block product: inner columns per LDS stage
+// Block product stages: 16 inner columns per LDS stage keep a workgroup at
+// 57 KB of LDS, so two workgroups share a CU (at 32 columns, 108 KB, one did,
+// and the product ran at half the matrix-core rate).
+constexpr int kBS = 16;          // inner columns per LDS stage
 constexpr int kXLD = kBS + 4;    // In1 tile stride (floats): a wave's 64 reads hit 64 banks
 constexpr int kSLD = kMC + 16;   // S tile stride (doubles)
+constexpr int kXV = kBS / 4;     // float4 per staged In1 row
+constexpr int kXU = kMR * kXV / 256;  // staged float4 of In1 per thread
+constexpr int kSU = kBS * kMC / 256;  // staged doubles of S per thread
+static_assert(kXU >= 1 && kSU >= 1 && kSU <= 32, "block product staging shape");
 
 // Out[i, j] = c0 * In0[i, j] + sum_{l < kin} In1[i, l] * S[l * lds + j] for
 // every stored column j of the layout (S is zero beyond its live columns, so
 // padding columns stay c0 * In0); float64 sums, rounded once to float32.
-// Workgroup: 128 rows x 128 columns; the inner dimension is staged 32 at a
+// Workgroup: 128 rows x 128 columns; the inner dimension is staged 16 at a
 // time in LDS (In1 rows and S rows, double-buffered); wave w takes the
 // 64 x 64 quarter (w / 2, w mod 2).  Out may be In0 (each element is read and
 // written by the same lane), never In1.
-__global__ __launch_bounds__(256) void k_block_mul(Layout L, float c0, const float* In0,
+__global__ __launch_bounds__(256, 2) void k_block_mul(Layout L, float c0, const float* In0,
                                                    const float* In1, const double* S, int kin,
                                                    int kout, int lds, float* Out) {
   __shared__ float Xs[2][kMR][kXLD];
@@ -180,19 +187,19 @@ __global__ __launch_bounds__(256) void k_block_mul(Layout L, float c0, const flo
   const int q = lane >> 4, c16 = lane & 15;
   const int bi0 = blockIdx.x * kMR, bj0 = blockIdx.y * kMC;
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-  float4 rx[4];
-  int lx[4];
-  double rs[16];
+  float4 rx[kXU];
+  int lx[kXU];
+  double rs[kSU];
   unsigned sok = 0;  // bit u: element u of the S stage is live
   auto fetch = [&](int l0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int f = t + 256 * u, row = f >> 3, c = (f & 7) * 4, i = bi0 + row;
+    for (int u = 0; u < kXU; ++u) {
+      const int f = t + 256 * u, row = f / kXV, c = (f % kXV) * 4, i = bi0 + row;
       rx[u] = cols4_load(L, In1, i, l0 + c, kin, i < L.n, lx[u]);
     }
     sok = 0;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < kSU; ++u) {
       const int f = t + 256 * u, r = f >> 7, c = f & 127, l = l0 + r, j = bj0 + c;
       const bool ok = l < kin && j < kout;
       sok |= (ok ? 1u : 0u) << u;
@@ -201,12 +208,12 @@ __global__ __launch_bounds__(256) void k_block_mul(Layout L, float c0, const flo
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int f = t + 256 * u, row = f >> 3, c = (f & 7) * 4;
+    for (int u = 0; u < kXU; ++u) {
+      const int f = t + 256 * u, row = f / kXV, c = (f % kXV) * 4;
       *reinterpret_cast<float4*>(&Xs[buf][row][c]) = cols4_mask(rx[u], lx[u]);
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < kSU; ++u) {
       const int f = t + 256 * u;
       Ss[buf][f >> 7][f & 127] = ((sok >> u) & 1u) ? rs[u] : 0.0;
     }
