@@ -27,6 +27,7 @@ constexpr int kKmBlock = 1024;
 // 144 KB of LDS per workgroup (of the 160 KB of a CU), reused by the phases: the
 // centroids of k = 250 clusters in 56 dimensions stay in LDS during Lloyd
 constexpr int kLdsDoubles = 18432;
+constexpr int kCcLds = 256;  // the newest seed centroid in LDS when d <= 256
 
 struct KmItem {
   const double* X;   // n x d, row-major
@@ -55,10 +56,22 @@ __device__ inline double sqd(const double* x, const double* c, int d) {
 }
 
 // the same sum with the point read from the transposed block (coalesced
-// across the threads of a wave, one point per thread)
+// across the threads of a wave, one point per thread); the coordinate loads
+// of eight terms are issued before their additions, which stay in order
 __device__ inline double sqd_t(const double* Xt, int n, int i, const double* c, int d) {
   double acc = 0.0;
-  for (int j = 0; j < d; ++j) {
+  int j = 0;
+  for (; j + 8 <= d; j += 8) {
+    double xv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xv[q] = Xt[(size_t)(j + q) * n + i];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double diff = xv[q] - c[j + q];
+      acc = acc + diff * diff;
+    }
+  }
+  for (; j < d; ++j) {
     const double diff = Xt[(size_t)j * n + i] - c[j];
     acc = acc + diff * diff;
   }
@@ -122,21 +135,36 @@ __device__ void assign(const KmItem& t, const double* C, int* out) {
     double best = 0.0;
     int arg = 0;
     int c = 0;
-    for (; c + 4 <= k; c += 4) {
-      const double *c0 = C + (size_t)c * d, *c1 = c0 + d, *c2 = c1 + d, *c3 = c2 + d;
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      for (int j = 0; j < d; ++j) {
-        const double xj = x[(size_t)j * n];
-        const double e0 = xj - c0[j], e1 = xj - c1[j], e2 = xj - c2[j], e3 = xj - c3[j];
-        a0 = a0 + e0 * e0;
-        a1 = a1 + e1 * e1;
-        a2 = a2 + e2 * e2;
-        a3 = a3 + e3 * e3;
+    for (; c + 8 <= k; c += 8) {
+      const double* cb = C + (size_t)c * d;
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = 0.0;
+      int j = 0;
+      for (; j + 4 <= d; j += 4) {
+        double xv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xv[q] = x[(size_t)(j + q) * n];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const double e = xv[q] - cb[(size_t)u * d + j + q];
+            a[u] = a[u] + e * e;
+          }
       }
-      const double v[4] = {a0, a1, a2, a3};
-      for (int u = 0; u < 4; ++u)
-        if (c + u == 0 || v[u] < best) {
-          best = v[u];
+      for (; j < d; ++j) {
+        const double xj = x[(size_t)j * n];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double e = xj - cb[(size_t)u * d + j];
+          a[u] = a[u] + e * e;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c + u == 0 || a[u] < best) {
+          best = a[u];
           arg = c + u;
         }
     }
@@ -160,6 +188,7 @@ __global__ __launch_bounds__(kKmBlock) void k_kmeans(const KmItem* items) {
   const int n = t.n, d = t.d, k = t.k;
   __shared__ VI sh_vi[kKmBlock / 64];
   __shared__ int sh_i;
+  __shared__ double sh_cc[kCcLds];
 
   // ---- k-means++ seeding.  The D^2 weights and their running sums live in
   // LDS when they fit; one thread forms the running sum in point order,
@@ -216,10 +245,15 @@ __global__ __launch_bounds__(kKmBlock) void k_kmeans(const KmItem* items) {
       }
     }
     double* cc = t.C + (size_t)c * d;
-    for (int j = threadIdx.x; j < d; j += blockDim.x) cc[j] = t.X[(size_t)pick * d + j];
+    const double* ccr = d <= kCcLds ? sh_cc : cc;  // the new centroid, read by every thread
+    for (int j = threadIdx.x; j < d; j += blockDim.x) {
+      const double v = t.X[(size_t)pick * d + j];
+      cc[j] = v;
+      if (d <= kCcLds) sh_cc[j] = v;
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const double v = sqd_t(t.Xt, n, i, cc, d);
+      const double v = sqd_t(t.Xt, n, i, ccr, d);
       mind[i] = v < mind[i] ? v : mind[i];
     }
     __syncthreads();
