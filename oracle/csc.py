@@ -32,7 +32,9 @@ from .sampling import sample, sample_density
 
 
 def default_n(k: int) -> int:
-    return int(math.ceil(2.0 * k * math.log(k)))
+    """n = ceil(2 k ln k) sampled nodes (Alg. 2), at least k (the formula gives
+    none for k = 1)."""
+    return max(k, int(math.ceil(2.0 * k * math.log(k))))
 
 
 def features(A, lam: float, p: int, d: int, seed: int, with_norms: bool = False,

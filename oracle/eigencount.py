@@ -27,8 +27,9 @@ from .philox import COUNT, gaussian_block
 
 
 def count_signals(N: int) -> int:
-    """n_c = ceil(2 ln N) random signals per tested lambda."""
-    return int(math.ceil(2.0 * math.log(N)))
+    """n_c = ceil(2 ln N) random signals per tested lambda (Sec. 4.3), at least
+    one (the formula gives none for N = 1)."""
+    return max(1, int(math.ceil(2.0 * math.log(N))))
 
 
 def eigencount(A, lam: float, p: int, R: np.ndarray, damping: bool = True) -> float:

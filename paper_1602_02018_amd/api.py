@@ -410,11 +410,13 @@ class StepTimer:
 # ------------------------------------------------------------ Alg. 2 ---------
 
 def default_n(k: int) -> int:
-    return int(math.ceil(2.0 * k * math.log(k)))
+    """n = ceil(2 k ln k) sampled nodes (Alg. 2), at least k."""
+    return max(k, int(math.ceil(2.0 * k * math.log(k))))
 
 
 def count_signals(N: int) -> int:
-    return int(math.ceil(2.0 * math.log(N)))
+    """n_c = ceil(2 ln N) eigencount signals (Sec. 4.3), at least one."""
+    return max(1, int(math.ceil(2.0 * math.log(N))))
 
 
 @dataclass

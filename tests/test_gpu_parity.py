@@ -401,3 +401,37 @@ def test_jacobi_block_cg_needs_no_more_iterations(api, cfg1):
     assert a.status == 0 and b.status == 0
     assert b.iters.max() <= a.iters.max()
     assert _relfro(b.X.cpu().numpy(), a.X.cpu().numpy()) <= 1e-3
+
+
+def _tiny(N, kind):
+    """Small graphs: a path, a cycle, two disjoint triangles, an edgeless set."""
+    if kind == "path":
+        u = np.arange(N - 1)
+        v = u + 1
+    elif kind == "cycle":
+        u = np.arange(N)
+        v = (u + 1) % N
+    elif kind == "triangles":
+        u = np.array([0, 1, 2, 3, 4, 5])
+        v = np.array([1, 2, 0, 4, 5, 3])
+    else:
+        u = v = np.zeros(0, np.int64)
+    return synth.csr_from_edges(N, u, v)
+
+
+@pytest.mark.parametrize("N,kind,k", [(1, "none", 1), (2, "path", 1), (2, "path", 2), (5, "cycle", 2),
+                                      (6, "triangles", 2), (13, "path", 3), (7, "none", 3)])
+def test_end_to_end_tiny_graphs(api, N, kind, k):
+    """Degenerate sizes run through every step: the same lambda_k, samples and
+    labels (up to relabelling) as the oracle, with n = N sampled nodes."""
+    row_ptr, col = _tiny(N, kind)
+    g = api.Graph(row_ptr, col)
+    d, n = 3, N
+    res = api.run(g, k, d, 0, n=n, replicates=3)
+    ref = ocsc.run(row_ptr, col, k, d, 0, n=n, replicates=3)
+    assert abs(res.lam - ref.lam) <= 2.0 / 2 ** min(res.bisection.steps, ref.bisect_steps)
+    assert np.array_equal(res.omega.cpu().numpy(), ref.omega)
+    lab = res.labels.cpu().numpy()
+    assert lab.shape == (N,) and lab.min() >= 0 and lab.max() < k
+    if N > 1:
+        assert metrics.adjusted_rand_index(lab, ref.labels) >= 0.99
