@@ -907,11 +907,16 @@ csc_status block_post(BlockState& st, int it, int max_iter, hipStream_t s) {
   const BlockBufs& b = st.b;
   const Layout& L = st.L;
   const int k = st.k, sr = st.sr;
-  // W = P^T Q (s x s), alpha = W^{-1} P^T R (s x k)
+  // W = P^T Q (s x s), alpha = W^{-1} P^T R (s x k); both Gram matrices come
+  // back in one round trip (P^T R is parked in S_b, which is free until beta)
   CSC_HIP(launch_gram(L, b.P, b.Q, sr, sr, b.gpart, b.G, sr, s));
-  CSC_TRY(download(st.W, b.G, (size_t)sr * sr, s));
-  CSC_HIP(launch_gram(L, b.P, b.R, sr, k, b.gpart, b.G, k, s));
-  CSC_TRY(download(st.C, b.G, (size_t)sr * k, s));
+  CSC_HIP(launch_gram(L, b.P, b.R, sr, k, b.gpart, b.S_b, k, s));
+  st.W.resize((size_t)sr * sr);
+  st.C.resize((size_t)sr * k);
+  CSC_HIP(hipMemcpyAsync(st.W.data(), b.G, st.W.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipMemcpyAsync(st.C.data(), b.S_b, st.C.size() * sizeof(double), hipMemcpyDeviceToHost,
+                         s));
+  CSC_HIP(hipStreamSynchronize(s));
   if (!dense::cholesky(st.W, sr, sr)) {
     st.finished = true;
     st.broke = true;
@@ -924,10 +929,23 @@ csc_status block_post(BlockState& st, int it, int max_iter, hipStream_t s) {
   CSC_TRY(upload_d(b.S_na, st.N, s));
   CSC_HIP(launch_block_mul(L, 1.f, b.X, b.P, b.S_a, sr, k, k, b.X, s));
   CSC_HIP(launch_block_mul(L, 1.f, b.R, b.Q, b.S_na, sr, k, k, b.R, s));
-  // every column: ||r_j|| <= tol ||b_j||
+  // every column: ||r_j|| <= tol ||b_j||.  The next search block's Gram
+  // Q^T Z is formed before the check so that both come back in one round trip
+  // (after the last iteration it goes unused).
   CSC_HIP(launch_col_dot(L, b.R, b.R, b.part, s));
   CSC_HIP(launch_reduce(b.part, tiles_for(L), k, b.rn2, s));
-  CSC_TRY(download(st.rn2, b.rn2, (size_t)k, s));
+  const float* Zr = b.R;
+  if (st.jacobi) {
+    CSC_HIP(launch_jacobi(L, b.R, b.mask, st.gamma, b.Z, s));
+    Zr = b.Z;
+  }
+  CSC_HIP(launch_gram(L, b.Q, Zr, sr, k, b.gpart, b.G, k, s));
+  st.rn2.resize(k);
+  st.C.resize((size_t)sr * k);
+  CSC_HIP(hipMemcpyAsync(st.rn2.data(), b.rn2, (size_t)k * sizeof(double), hipMemcpyDeviceToHost,
+                         s));
+  CSC_HIP(hipMemcpyAsync(st.C.data(), b.G, st.C.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CSC_HIP(hipStreamSynchronize(s));
   for (int j = 0; j < k; ++j) {
     if (st.bn2[j] <= 0.0) continue;
     st.relres[j] = std::sqrt(st.rn2[j] / st.bn2[j]);
@@ -945,14 +963,7 @@ csc_status block_post(BlockState& st, int it, int max_iter, hipStream_t s) {
     st.finished = true;
     return CSC_OK;
   }
-  // Z = R (or D^-1 R);  beta = -W^{-1} Q^T Z;  Z = Z + P beta
-  const float* Zr = b.R;
-  if (st.jacobi) {
-    CSC_HIP(launch_jacobi(L, b.R, b.mask, st.gamma, b.Z, s));
-    Zr = b.Z;
-  }
-  CSC_HIP(launch_gram(L, b.Q, Zr, sr, k, b.gpart, b.G, k, s));
-  CSC_TRY(download(st.C, b.G, (size_t)sr * k, s));
+  // beta = -W^{-1} Q^T Z;  Z = Z + P beta  (Z = R, or D^-1 R)
   dense::chol_solve(st.W, sr, sr, st.C, k, -1.0);
   CSC_TRY(upload_d(b.S_b, st.C, s));
   CSC_HIP(launch_block_mul(L, 1.f, Zr, b.P, b.S_b, sr, k, k, b.Z, s));
