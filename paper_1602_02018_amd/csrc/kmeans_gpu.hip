@@ -28,6 +28,10 @@ constexpr int kKmBlock = 1024;
 // centroids of k = 250 clusters in 56 dimensions stay in LDS during Lloyd
 constexpr int kLdsDoubles = 18432;
 constexpr int kCcLds = 256;  // the newest seed centroid in LDS when d <= 256
+constexpr int kStripe = 8;       // centroids per assignment workgroup
+constexpr int kStripeMaxD = 512;  // stripe centroids staged in LDS up to this d
+constexpr int kChecks = 4;       // Lloyd iterations launched between convergence checks
+constexpr int kUpdLds = 8192;    // update step: labels and members in LDS up to this n
 
 struct KmItem {
   const double* X;   // n x d, row-major
@@ -44,6 +48,9 @@ struct KmItem {
   int* members;     // n
   int* out_labels;  // n
   double* out_inertia;
+  double* pbest;    // ceil(k / kStripe) x n: nearest centroid distance per stripe
+  int* parg;        // ceil(k / kStripe) x n: its index
+  int* flags;       // 4: Lloyd state between launches
 };
 
 __device__ inline double sqd(const double* x, const double* c, int d) {
@@ -179,22 +186,26 @@ __device__ void assign(const KmItem& t, const double* C, int* out) {
   }
 }
 
-// SEED_LDS: D^2 weights and running sums in LDS; C_LDS: centroids in LDS
-// during Lloyd; LAB_LDS: labels in LDS during Lloyd (after the centroids
-// when both are).
-template <bool SEED_LDS, bool C_LDS, bool LAB_LDS>
-__global__ __launch_bounds__(kKmBlock) void k_kmeans(const KmItem* items) {
+// Lloyd state of one replicate between launches (flags[]): whether the last
+// assignment changed a label, whether the replicate has finished, whether the
+// last update re-seeded an empty cluster, and whether labels exist yet.
+enum { KM_CHANGED = 0, KM_DONE = 1, KM_RESEEDED = 2, KM_HAVE = 3 };
+
+// k-means++ seeding of one replicate per workgroup (SEED_LDS: the D^2
+// weights and their running sums in LDS); leaves the k seeds in t.C, every
+// label at -1 and the Lloyd state cleared.
+template <bool SEED_LDS>
+__global__ __launch_bounds__(kKmBlock) void k_km_seed(const KmItem* items) {
   const KmItem t = items[blockIdx.x];
   const int n = t.n, d = t.d, k = t.k;
   __shared__ VI sh_vi[kKmBlock / 64];
-  __shared__ int sh_i;
   __shared__ double sh_cc[kCcLds];
 
   // ---- k-means++ seeding.  The D^2 weights and their running sums live in
   // LDS when they fit; one thread forms the running sum in point order,
   // exactly as the host loop, and the first point whose running sum passes
   // u * total is found by an index reduction.
-  __shared__ double smem[kLdsDoubles];
+  __shared__ double smem[SEED_LDS ? kLdsDoubles : 1];
   double* mind = SEED_LDS ? smem : t.mind;
   double* cum = SEED_LDS ? smem + n : t.cum;
   {
@@ -259,91 +270,205 @@ __global__ __launch_bounds__(kKmBlock) void k_kmeans(const KmItem* items) {
     __syncthreads();
   }
 
-  // ---- Lloyd iterations.  Centroids and labels move to LDS when they fit.
-  const size_t kd = (size_t)k * d;
-  double* C = C_LDS ? smem : t.C;
-  int* lab = LAB_LDS ? reinterpret_cast<int*>(smem + (C_LDS ? kd : 0)) : t.lab;
-  if (C_LDS)
-    for (size_t e = threadIdx.x; e < kd; e += blockDim.x) C[e] = t.C[e];
-  for (int i = threadIdx.x; i < n; i += blockDim.x) lab[i] = -1;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) t.lab[i] = -1;
+  if (threadIdx.x < 4) t.flags[threadIdx.x] = 0;
+}
+
+// Assignment step, spread over the GPU: workgroup (s, r) finds, for every
+// point of replicate r, the nearest of the centroids s*8 .. s*8+7 (squared
+// distances summed over coordinates in order, ties to the lowest index) and
+// leaves (distance, index) for the update to merge stripe by stripe.
+__global__ __launch_bounds__(256) void k_km_assign(const KmItem* items, int count) {
+  if ((int)blockIdx.y >= count) return;
+  const KmItem t = items[blockIdx.y];
+  if (t.flags[KM_DONE]) return;
+  const int s = blockIdx.x, c0 = s * kStripe;
+  if (c0 >= t.k) return;
+  const int n = t.n, d = t.d, nc = min(kStripe, t.k - c0);
+  __shared__ double cs[kStripe * kStripeMaxD];
+  const double* cb = t.C + (size_t)c0 * d;
+  if (d <= kStripeMaxD) {
+    for (int e = threadIdx.x; e < nc * d; e += blockDim.x) cs[e] = cb[e];
+    __syncthreads();
+    cb = cs;
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double* x = t.Xt + i;
+    double a[kStripe];
+#pragma unroll
+    for (int u = 0; u < kStripe; ++u) a[u] = 0.0;
+    int j = 0;
+    for (; j + 4 <= d; j += 4) {
+      double xv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xv[q] = x[(size_t)(j + q) * n];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int u = 0; u < kStripe; ++u)
+          if (u < nc) {
+            const double e = xv[q] - cb[(size_t)u * d + j + q];
+            a[u] = a[u] + e * e;
+          }
+    }
+    for (; j < d; ++j) {
+      const double xj = x[(size_t)j * n];
+#pragma unroll
+      for (int u = 0; u < kStripe; ++u)
+        if (u < nc) {
+          const double e = xj - cb[(size_t)u * d + j];
+          a[u] = a[u] + e * e;
+        }
+    }
+    double best = a[0];
+    int arg = c0;
+#pragma unroll
+    for (int u = 1; u < kStripe; ++u)
+      if (u < nc && a[u] < best) {
+        best = a[u];
+        arg = c0 + u;
+      }
+    t.pbest[(size_t)s * n + i] = best;
+    t.parg[(size_t)s * n + i] = arg;
+  }
+}
+
+// Update step of one replicate per workgroup: merge the stripes (in centroid
+// order, so ties keep the lowest index), stop when nothing changed after a
+// step without re-seeding, else move the labels, recompute the centroids
+// (members summed in index order) and re-seed empty clusters with the
+// farthest point.
+__global__ __launch_bounds__(kKmBlock) void k_km_update(const KmItem* items) {
+  const KmItem t = items[blockIdx.x];
+  if (t.flags[KM_DONE]) return;
+  const int n = t.n, d = t.d, k = t.k, ns = (k + kStripe - 1) / kStripe;
+  __shared__ VI sh_vi[kKmBlock / 64];
+  __shared__ int sh_i;
+  __shared__ int s_lab[kUpdLds], s_mem[kUpdLds];
+  const bool in_lds = n <= kUpdLds;  // labels and member lists in LDS for the scans
+  double* C = t.C;
+  int* lab = in_lds ? s_lab : t.lab;
+  int* members = in_lds ? s_mem : t.members;
+  int diff = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double best = t.pbest[i];
+    int arg = t.parg[i];
+    for (int s0 = 1; s0 < ns; s0 += 8) {  // eight stripes' loads in flight, merged in order
+      double v[8];
+      int a[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const bool ok = s0 + q < ns;
+        v[q] = ok ? t.pbest[(size_t)(s0 + q) * n + i] : 0.0;
+        a[q] = ok ? t.parg[(size_t)(s0 + q) * n + i] : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (s0 + q < ns && v[q] < best) {
+          best = v[q];
+          arg = a[q];
+        }
+    }
+    t.fresh[i] = arg;
+    diff |= arg != t.lab[i];
+  }
+  const int changed = block_or(diff, &sh_i);
+  const bool have = t.flags[KM_HAVE] != 0, was_reseeded = t.flags[KM_RESEEDED] != 0;
   __syncthreads();
-  bool have = false, reseeded = false;
-  for (int it = 0; it < t.max_iter; ++it) {
-    assign(t, C, t.fresh);
-    __syncthreads();
-    int diff = 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) diff |= t.fresh[i] != lab[i];
-    const int changed = block_or(diff, &sh_i);
-    if (have && !reseeded && !changed) break;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) lab[i] = t.fresh[i];
-    have = true;
-    __syncthreads();
-    // members of every cluster in index order
-    for (int c = threadIdx.x; c < k; c += blockDim.x) {
-      int m = 0;
-      for (int i = 0; i < n; ++i) m += lab[i] == c;
-      t.counts[c] = m;
+  if (have && !was_reseeded && !changed) {
+    if (threadIdx.x == 0) t.flags[KM_DONE] = 1;
+    return;
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lab[i] = t.fresh[i];
+  __syncthreads();
+  // members of every cluster in index order
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    int m = 0;
+    for (int i = 0; i < n; ++i) m += lab[i] == c;
+    t.counts[c] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int sum = 0;
+    for (int c = 0; c < k; ++c) {
+      t.mstart[c] = sum;
+      sum += t.counts[c];
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int sum = 0;
-      for (int c = 0; c < k; ++c) {
-        t.mstart[c] = sum;
-        sum += t.counts[c];
+    t.mstart[k] = sum;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    int w = t.mstart[c];
+    for (int i = 0; i < n; ++i)
+      if (lab[i] == c) members[w++] = i;
+  }
+  __syncthreads();
+  // centroid sums over members in index order; the d threads of one cluster
+  // read one member row of X together, four members' loads in flight
+  for (int e = threadIdx.x; e < k * d; e += blockDim.x) {
+    const int c = e / d, j = e - c * d;
+    const int cnt = t.counts[c];
+    if (cnt == 0) continue;
+    double acc = 0.0;
+    const double* xj = t.X + j;
+    int m = t.mstart[c];
+    const int m1 = t.mstart[c + 1];
+    for (; m + 4 <= m1; m += 4) {
+      double v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = xj[(size_t)members[m + q] * d];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc = acc + v[q];
+    }
+    for (; m < m1; ++m) acc = acc + xj[(size_t)members[m] * d];
+    C[(size_t)c * d + j] = acc / (double)cnt;
+  }
+  __syncthreads();
+  int empty = 0;
+  for (int c = threadIdx.x; c < k; c += blockDim.x) empty |= t.counts[c] == 0;
+  const bool reseeded = block_or(empty, &sh_i) != 0;
+  if (reseeded) {
+    for (int c = 0; c < k; ++c) {
+      if (t.counts[c] != 0) continue;  // uniform: every thread reads the same value
+      VI x{-1.0, n};
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double v = sqd_t(t.Xt, n, i, C + (size_t)lab[i] * d, d);
+        x = better_max(x, VI{v, i});
       }
-      t.mstart[k] = sum;
-    }
-    __syncthreads();
-    for (int c = threadIdx.x; c < k; c += blockDim.x) {
-      int w = t.mstart[c];
-      for (int i = 0; i < n; ++i)
-        if (lab[i] == c) t.members[w++] = i;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < k * d; e += blockDim.x) {
-      const int c = e / d, j = e - c * d;
-      const int cnt = t.counts[c];
-      if (cnt == 0) continue;
-      double acc = 0.0;
-      const double* xj = t.Xt + (size_t)j * n;
-      for (int m = t.mstart[c]; m < t.mstart[c + 1]; ++m) acc = acc + xj[t.members[m]];
-      C[(size_t)c * d + j] = acc / (double)cnt;
-    }
-    __syncthreads();
-    int empty = 0;
-    for (int c = threadIdx.x; c < k; c += blockDim.x) empty |= t.counts[c] == 0;
-    reseeded = block_or(empty, &sh_i) != 0;
-    if (reseeded) {
-      for (int c = 0; c < k; ++c) {
-        if (t.counts[c] != 0) continue;  // uniform: every thread reads the same value
-        VI x{-1.0, n};
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-          const double v = sqd_t(t.Xt, n, i, C + (size_t)lab[i] * d, d);
-          x = better_max(x, VI{v, i});
-        }
-        const int far = block_reduce<true>(x, sh_vi).i;
-        for (int j = threadIdx.x; j < d; j += blockDim.x) C[(size_t)c * d + j] = t.X[(size_t)far * d + j];
-        __syncthreads();
-        if (threadIdx.x == 0) {
-          --t.counts[lab[far]];
-          lab[far] = c;
-          t.counts[c] = 1;
-        }
-        __syncthreads();
+      const int far = block_reduce<true>(x, sh_vi).i;
+      for (int j = threadIdx.x; j < d; j += blockDim.x) C[(size_t)c * d + j] = t.X[(size_t)far * d + j];
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        --t.counts[lab[far]];
+        lab[far] = c;
+        t.counts[c] = 1;
       }
+      __syncthreads();
     }
   }
+  if (in_lds) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) t.lab[i] = lab[i];
+  }
+  if (threadIdx.x == 0) {
+    t.flags[KM_HAVE] = 1;
+    t.flags[KM_RESEEDED] = reseeded ? 1 : 0;
+  }
+}
 
-  // ---- inertia (points in order) and labels
+// Inertia (points in order) and labels of one replicate per workgroup.
+__global__ __launch_bounds__(kKmBlock) void k_km_finish(const KmItem* items) {
+  const KmItem t = items[blockIdx.x];
+  const int n = t.n, d = t.d;
   for (int i = threadIdx.x; i < n; i += blockDim.x)
-    t.mind[i] = sqd_t(t.Xt, n, i, C + (size_t)lab[i] * d, d);
+    t.mind[i] = sqd_t(t.Xt, n, i, t.C + (size_t)t.lab[i] * d, d);
   __syncthreads();
   if (threadIdx.x == 0) {
     double acc = 0.0;
     for (int i = 0; i < n; ++i) acc = acc + t.mind[i];
     *t.out_inertia = acc;
   }
-  for (int i = threadIdx.x; i < n; i += blockDim.x) t.out_labels[i] = lab[i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) t.out_labels[i] = t.lab[i];
 }
 
 __global__ void k_to_f64(int n, int d, const float* F, int ld, double* X, double* Xt) {
@@ -357,42 +482,57 @@ __global__ void k_to_f64(int n, int d, const float* F, int ld, double* X, double
   }
 }
 
-// which k_kmeans variant a (n, d, k) input takes
-int km_variant(int n, int d, int k) {
-  const size_t kd = (size_t)k * d, lab = ((size_t)n + 1) / 2;
-  const bool seed = 2 * (size_t)n <= (size_t)kLdsDoubles;
-  const bool c = kd + lab <= (size_t)kLdsDoubles;
-  const bool l = c || lab <= (size_t)kLdsDoubles;
-  return (seed ? 4 : 0) | (c ? 2 : 0) | (l ? 1 : 0);
-}
-
-hipError_t launch_km(int variant, const KmItem* items, int count, hipStream_t s) {
-  const dim3 grid((unsigned)count), block(kKmBlock);
-#define CSC_KM(A, B, C)                                                                 \
-  case (A ? 4 : 0) | (B ? 2 : 0) | (C ? 1 : 0):                                         \
-    hipLaunchKernelGGL((k_kmeans<A, B, C>), grid, block, 0, s, items);                  \
-    break;
-  switch (variant) {
-    CSC_KM(true, true, true)
-    CSC_KM(true, false, true)
-    CSC_KM(true, false, false)
-    CSC_KM(false, true, true)
-    CSC_KM(false, false, true)
-    CSC_KM(false, false, false)
-    default:
-      return hipErrorInvalidValue;
-  }
-#undef CSC_KM
+// Launches the seeding of `count` replicates (SEED_LDS when the D^2 weights fit).
+hipError_t launch_seed(bool seed_lds, const KmItem* items, int count, hipStream_t s) {
+  if (seed_lds)
+    hipLaunchKernelGGL(k_km_seed<true>, dim3((unsigned)count), dim3(kKmBlock), 0, s, items);
+  else
+    hipLaunchKernelGGL(k_km_seed<false>, dim3((unsigned)count), dim3(kKmBlock), 0, s, items);
   return hipGetLastError();
 }
 
+bool seed_in_lds(int n) { return 2 * (size_t)n <= (size_t)kLdsDoubles; }
+
+int stripes(int k) { return (k + kStripe - 1) / kStripe; }
+
+// Lloyd iterations of `count` seeded replicates (items on the device, flags
+// of replicate r at flags + 4 r): kChecks iterations of assign + update per
+// round, then a look at the done flags; at most max_iter iterations.
+csc_status run_lloyd(const KmItem* items, int count, int max_stripes, int max_iter, int* flags,
+                     hipStream_t s) {
+  std::vector<int> h((size_t)count * 4);
+  for (int it = 0; it < max_iter;) {
+    const int round = std::min(kChecks, max_iter - it);
+    for (int q = 0; q < round; ++q) {
+      hipLaunchKernelGGL(k_km_assign, dim3((unsigned)max_stripes, (unsigned)count), dim3(256), 0, s,
+                         items, count);
+      CSC_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_km_update, dim3((unsigned)count), dim3(kKmBlock), 0, s, items);
+      CSC_HIP(hipGetLastError());
+    }
+    it += round;
+    if (it >= max_iter) break;
+    CSC_HIP(hipMemcpyAsync(h.data(), flags, h.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    bool all = true;
+    for (int r = 0; r < count && all; ++r) all = h[(size_t)r * 4 + KM_DONE] != 0;
+    if (all) break;
+  }
+  hipLaunchKernelGGL(k_km_finish, dim3((unsigned)count), dim3(kKmBlock), 0, s, items);
+  CSC_HIP(hipGetLastError());
+  return CSC_OK;
+}
+
 // workspace of one input: X (n x d doubles) + per replicate C, mind, cum,
-// lab, fresh, counts, mstart, members, labels; plus inertias
+// lab, fresh, counts, mstart, members, labels, stripe results, Lloyd flags;
+// plus inertias
 size_t km_bytes(int n, int d, int k, int reps) {
   size_t b = 2 * align_up((size_t)n * d * sizeof(double));
+  const size_t ns = (size_t)stripes(k);
   const size_t per = align_up((size_t)k * d * sizeof(double)) + 2 * align_up((size_t)n * sizeof(double)) +
-                     4 * align_up((size_t)n * sizeof(int)) + 2 * align_up(((size_t)k + 1) * sizeof(int));
-  b += per * reps + align_up((size_t)reps * sizeof(double));
+                     4 * align_up((size_t)n * sizeof(int)) + 2 * align_up(((size_t)k + 1) * sizeof(int)) +
+                     align_up(ns * n * sizeof(double)) + align_up(ns * n * sizeof(int));
+  b += per * reps + align_up((size_t)reps * sizeof(double)) + align_up((size_t)reps * 4 * sizeof(int));
   return b;
 }
 
@@ -431,6 +571,8 @@ csc_status plan_km(Arena& ar, const float* F, int n, int d, int ld, int k, int r
     t.mstart = ar.take<int>((size_t)k + 1);
     t.out_labels = ar.take<int>(n);
     t.out_inertia = P.inertia + r;
+    t.pbest = ar.take<double>((size_t)stripes(k) * n);
+    t.parg = ar.take<int>((size_t)stripes(k) * n);
   }
   if (!ar.ok()) {
     set_error("internal: k-means workspace overflow");
@@ -491,13 +633,16 @@ extern "C" csc_status csc_kmeans_reduced_device(const float* F, int32_t n, int32
   KmPlan P;
   CSC_TRY(plan_km(ar, F, n, d, ld, k, replicates, max_iter, seed, P, s));
   KmItem* d_items = ar.take<KmItem>(replicates);
+  int* flags = ar.take<int>((size_t)replicates * 4);
   if (!ar.ok()) {
     set_error("internal: k-means workspace overflow");
     return CSC_E_INVALID_ARG;
   }
+  for (int r = 0; r < replicates; ++r) P.items[r].flags = flags + 4 * r;
   CSC_HIP(hipMemcpyAsync(d_items, P.items.data(), replicates * sizeof(KmItem),
                          hipMemcpyHostToDevice, s));
-  CSC_HIP(launch_km(km_variant(n, d, k), d_items, replicates, s));
+  CSC_HIP(launch_seed(seed_in_lds(n), d_items, replicates, s));
+  CSC_TRY(run_lloyd(d_items, replicates, stripes(k), max_iter, flags, s));
   return finish_km(P, n, replicates, labels, inertia_out, s);
 }
 
@@ -526,31 +671,30 @@ extern "C" csc_status csc_kmeans_reduced_device_batched(int32_t G, const float* 
   Arena ar(ws, ws_bytes);
   std::vector<KmPlan> P(G);
   std::vector<KmItem> all;
-  std::vector<int> var;  // inputs grouped by kernel variant, one launch per group
-  for (int v = 7; v >= 0; --v)
+  std::vector<int> order;  // inputs whose seeding fits in LDS first, one seed launch per group
+  for (int pass = 0; pass < 2; ++pass)
     for (int g = 0; g < G; ++g)
-      if (km_variant(n[g], d[g], k[g]) == v) var.push_back(g);
-  std::vector<std::pair<int, int>> launches;  // (variant, item count)
-  for (int g : var) {
+      if (seed_in_lds(n[g]) == (pass == 0)) order.push_back(g);
+  int n_lds = 0, max_stripes = 1;
+  for (int g : order) {
     CSC_TRY(plan_km(ar, F[g], n[g], d[g], d[g], k[g], replicates, max_iter, seeds[g], P[g], s));
     all.insert(all.end(), P[g].items.begin(), P[g].items.end());
-    const int v = km_variant(n[g], d[g], k[g]);
-    if (launches.empty() || launches.back().first != v)
-      launches.push_back({v, 0});
-    launches.back().second += replicates;
+    if (seed_in_lds(n[g])) n_lds += replicates;
+    max_stripes = std::max(max_stripes, stripes(k[g]));
   }
+  const int total = (int)all.size();
   KmItem* d_items = ar.take<KmItem>(all.size());
+  int* flags = ar.take<int>((size_t)total * 4);
   if (!ar.ok()) {
     set_error("internal: k-means workspace overflow");
     return CSC_E_INVALID_ARG;
   }
+  for (int r = 0; r < total; ++r) all[r].flags = flags + 4 * r;
   CSC_HIP(hipMemcpyAsync(d_items, all.data(), all.size() * sizeof(KmItem), hipMemcpyHostToDevice,
                          s));
-  size_t off = 0;
-  for (const auto& l : launches) {
-    CSC_HIP(launch_km(l.first, d_items + off, l.second, s));
-    off += l.second;
-  }
+  if (n_lds > 0) CSC_HIP(launch_seed(true, d_items, n_lds, s));
+  if (total > n_lds) CSC_HIP(launch_seed(false, d_items + n_lds, total - n_lds, s));
+  CSC_TRY(run_lloyd(d_items, total, max_stripes, max_iter, flags, s));
   for (int g = 0; g < G; ++g)
     CSC_TRY(finish_km(P[g], n[g], replicates, labels[g], inertia_out ? inertia_out + g : nullptr,
                       s));
