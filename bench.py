@@ -41,6 +41,9 @@ KERNEL_SRC = [os.path.join(ROOT, "paper_1602_02018_amd", "csrc", f)
 COUNTERS = {
     "count": os.path.join(ROOT, "profiles", "cheb_step_count_sbm_N1e5_w24_counters.txt"),
     "cg": os.path.join(ROOT, "profiles", "cheb_step_cg_sbm_N1e5_k100_counters.txt"),
+    "cl_count_step": os.path.join(ROOT, "profiles", "cheb_step_count_chunglu_N1e6_w28_counters.txt"),
+    "cl_filter_step": os.path.join(ROOT, "profiles", "cheb_step_filter_chunglu_N1e6_w56_counters.txt"),
+    "cl_cg_step": os.path.join(ROOT, "profiles", "cheb_step_cg_chunglu_N1e6_k250_counters.txt"),
 }
 
 WORKLOADS = {
@@ -270,6 +273,7 @@ def main():
         achieved = per_launch / avg_s / 1e9
         name = ("k_cheb_step<EPI_MOM> (moment step of the eigencount passes" if which == "count"
                 else "k_cheb_step<EPI_CLEN> (Clenshaw step of the CG operator pass")
+        traffic = read_traffic(which)
         cands[which] = {
             "kernel": f"{name}, w={w}, panel width {api.panel_width(N, w, nnz)}"
                       f"{', community order' if order is not None else ', natural order'})",
@@ -278,7 +282,9 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": read_traffic(which),
+            "traffic": traffic,
+            # bytes below L2 per launch (counters) over the launch time
+            "traffic_GBs": None if traffic is None else round(traffic / avg_s / 1e9, 1),
             "alg_bytes_per_launch": per_launch,
             "avg_launch_us": round(avg_s * 1e6, 2),
             "launches_per_step": launches,
@@ -395,11 +401,14 @@ def large_shapes(api, args, dev):
                                         ("cg_step", k, r.order, 3, "clen")):
         avg = step_time(api, gr, order, w, p, max(2, args.kernel_reps // 5), dev, kind=kind)
         by = step_bytes(N, nnz, w, bkind)
+        traffic = read_traffic("cl_" + name)
         out[name] = {"w": w, "panel_width": api.panel_width(N, w, nnz),
                      "order": "community" if order is not None else "natural",
                      "avg_launch_us": round(avg * 1e6, 1), "alg_bytes_per_launch": by,
                      "achieved_GBs": round(by / avg / 1e9, 1),
-                     "frac": round(by / avg / 1e9 / PEAK_HBM_GBS, 4)}
+                     "frac": round(by / avg / 1e9 / PEAK_HBM_GBS, 4),
+                     "traffic": traffic,
+                     "traffic_GBs": None if traffic is None else round(traffic / avg / 1e9, 1)}
     return out
 
 
