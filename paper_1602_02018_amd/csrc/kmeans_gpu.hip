@@ -8,10 +8,13 @@
 // compiled without floating-point contraction, so labels and inertia are
 // bit-identical to the host's.
 //
-// One workgroup runs one replicate of one input; the parallel parts are the
-// distance evaluations (independent per point and centroid), the centroid
-// sums (independent per centroid and coordinate) and order-free reductions
-// (argmin / argmax with index ties, integer counts).
+// The seeding runs one workgroup per replicate (its rounds are sequential);
+// each Lloyd step is an assignment spread over the GPU (a workgroup per
+// replicate and stripe of 8 centroids) and an update with one workgroup per
+// replicate.  The parallel parts are the distance evaluations (independent
+// per point and centroid), the centroid sums (independent per centroid and
+// coordinate) and order-free reductions (argmin / argmax with index ties,
+// integer counts).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -24,8 +27,8 @@ namespace csc {
 namespace {
 
 constexpr int kKmBlock = 1024;
-// 144 KB of LDS per workgroup (of the 160 KB of a CU), reused by the phases: the
-// centroids of k = 250 clusters in 56 dimensions stay in LDS during Lloyd
+// Seeding: the D^2 weights and their running sums (2 n doubles) stay in LDS
+// up to n = 9216 (144 KB of the CU's 160 KB)
 constexpr int kLdsDoubles = 18432;
 constexpr int kCcLds = 256;  // the newest seed centroid in LDS when d <= 256
 constexpr int kStripe = 8;       // centroids per assignment workgroup
