@@ -8,7 +8,9 @@
 // compiled without floating-point contraction, so labels and inertia are
 // bit-identical to the host's.
 //
-// The seeding runs one workgroup per replicate (its rounds are sequential);
+// The seeding runs one workgroup per replicate (its rounds are sequential;
+// each thread keeps one point's coordinates in registers when n <= 1024 and
+// d <= 48);
 // each Lloyd step is an assignment spread over the GPU (a workgroup per
 // replicate and stripe of 8 centroids) and an update with one workgroup per
 // replicate.  The parallel parts are the distance evaluations (independent
@@ -83,6 +85,24 @@ __device__ inline double sqd_t(const double* Xt, int n, int i, const double* c, 
   }
   for (; j < d; ++j) {
     const double diff = Xt[(size_t)j * n + i] - c[j];
+    acc = acc + diff * diff;
+  }
+  return acc;
+}
+
+// The same sum with the point's coordinates held in registers (d <= kSeedRegD).
+// The blocks k-means runs on are float32 features widened exactly to float64,
+// so a float copy of a coordinate is exact.  Coordinates d..kSeedRegD-1 are
+// zero in x and in c, so their terms add exact zeros and the sum is unchanged.
+constexpr int kSeedRegD = 48;
+
+__device__ inline double sqd_reg(const float (&x)[kSeedRegD], const double* c) {
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < kSeedRegD; ++j) {
+    float xj = x[j];
+    asm volatile("" : "+v"(xj));  // widen at the use: a hoisted float64 copy would not fit
+    const double diff = (double)xj - c[j];
     acc = acc + diff * diff;
   }
   return acc;
@@ -211,12 +231,26 @@ __global__ __launch_bounds__(kKmBlock) void k_km_seed(const KmItem* items) {
   __shared__ double smem[SEED_LDS ? kLdsDoubles : 1];
   double* mind = SEED_LDS ? smem : t.mind;
   double* cum = SEED_LDS ? smem + n : t.cum;
+  // one point per thread with its coordinates in registers when they fit
+  const bool reg = n <= (int)blockDim.x && d <= kSeedRegD;
+  float xr[kSeedRegD];
+  if (reg && (int)threadIdx.x < n) {
+#pragma unroll
+    for (int j = 0; j < kSeedRegD; ++j)
+      xr[j] = j < d ? (float)t.Xt[(size_t)j * n + threadIdx.x] : 0.f;
+  }
   {
     const double u = draw_uniform(t.seed, 0, (uint64_t)t.r);
     const int first = min((int)floor(u * n), n - 1);
     for (int j = threadIdx.x; j < d; j += blockDim.x) t.C[j] = t.X[(size_t)first * d + j];
+    if (reg && (int)threadIdx.x < kSeedRegD)  // the centroid zero-padded to kSeedRegD
+      sh_cc[threadIdx.x] = (int)threadIdx.x < d ? t.X[(size_t)first * d + threadIdx.x] : 0.0;
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) mind[i] = sqd_t(t.Xt, n, i, t.C, d);
+    if (reg) {
+      if ((int)threadIdx.x < n) mind[threadIdx.x] = sqd_reg(xr, sh_cc);
+    } else {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) mind[i] = sqd_t(t.Xt, n, i, t.C, d);
+    }
     __syncthreads();
   }
   for (int c = 1; c < k; ++c) {
@@ -266,9 +300,17 @@ __global__ __launch_bounds__(kKmBlock) void k_km_seed(const KmItem* items) {
       if (d <= kCcLds) sh_cc[j] = v;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const double v = sqd_t(t.Xt, n, i, ccr, d);
-      mind[i] = v < mind[i] ? v : mind[i];
+    if (reg) {
+      const int i = threadIdx.x;
+      if (i < n) {
+        const double v = sqd_reg(xr, sh_cc);
+        mind[i] = v < mind[i] ? v : mind[i];
+      }
+    } else {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double v = sqd_t(t.Xt, n, i, ccr, d);
+        mind[i] = v < mind[i] ? v : mind[i];
+      }
     }
     __syncthreads();
   }

@@ -32,6 +32,9 @@ def _blobs(seed, n, d, k, spread=0.3):
     (7, 2761, 56, 250, 4),    # 1e6-node configuration
     (1, 5000, 8, 20, 3),      # more points than the LDS copy of the D^2 weights
     (2, 33, 5, 33, 5),        # k = n
+    (4, 1024, 48, 64, 6),     # largest seeding with the points in registers
+    (6, 1025, 49, 40, 4),     # just past it in both n and d
+    (8, 700, 49, 30, 4),      # past it in d only
 ])
 def test_device_kmeans_is_bit_identical_to_host(api, seed, n, d, k, reps):
     X = _blobs(seed, n, d, k)
