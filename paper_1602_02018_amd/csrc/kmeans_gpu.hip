@@ -37,6 +37,7 @@ constexpr int kStripe = 8;       // centroids per assignment workgroup
 constexpr int kStripeMaxD = 512;  // stripe centroids staged in LDS up to this d
 constexpr int kChecks = 4;       // Lloyd iterations launched between convergence checks
 constexpr int kUpdLds = 8192;    // update step: labels and members in LDS up to this n
+constexpr int kUpdK = 1024;      // update step: cluster sizes and offsets in LDS up to this k
 
 struct KmItem {
   const double* X;   // n x d, row-major
@@ -337,7 +338,8 @@ __global__ __launch_bounds__(256) void k_km_assign(const KmItem* items, int coun
     __syncthreads();
     cb = cs;
   }
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  // one point per thread, the points spread over the z blocks
+  for (int i = blockIdx.z * blockDim.x + threadIdx.x; i < n; i += blockDim.x * gridDim.z) {
     const double* x = t.Xt + i;
     double a[kStripe];
 #pragma unroll
@@ -389,11 +391,16 @@ __global__ __launch_bounds__(kKmBlock) void k_km_update(const KmItem* items) {
   const int n = t.n, d = t.d, k = t.k, ns = (k + kStripe - 1) / kStripe;
   __shared__ VI sh_vi[kKmBlock / 64];
   __shared__ int sh_i;
-  __shared__ int s_lab[kUpdLds], s_mem[kUpdLds];
+  __shared__ __align__(16) int s_lab[kUpdLds];
+  __shared__ int s_mem[kUpdLds];
+  __shared__ int s_cnt[kUpdK], s_start[kUpdK + 1];
   const bool in_lds = n <= kUpdLds;  // labels and member lists in LDS for the scans
+  const bool k_lds = k <= kUpdK;     // cluster sizes and list offsets likewise
   double* C = t.C;
   int* lab = in_lds ? s_lab : t.lab;
   int* members = in_lds ? s_mem : t.members;
+  int* counts = k_lds ? s_cnt : t.counts;
+  int* mstart = k_lds ? s_start : t.mstart;
   int diff = 0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double best = t.pbest[i];
@@ -426,25 +433,35 @@ __global__ __launch_bounds__(kKmBlock) void k_km_update(const KmItem* items) {
   }
   for (int i = threadIdx.x; i < n; i += blockDim.x) lab[i] = t.fresh[i];
   __syncthreads();
+  // cluster sizes (integer atomics, so their order does not matter), then the
   // members of every cluster in index order
-  for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    int m = 0;
-    for (int i = 0; i < n; ++i) m += lab[i] == c;
-    t.counts[c] = m;
-  }
+  for (int c = threadIdx.x; c < k; c += blockDim.x) counts[c] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&counts[lab[i]], 1);
   __syncthreads();
   if (threadIdx.x == 0) {
     int sum = 0;
     for (int c = 0; c < k; ++c) {
-      t.mstart[c] = sum;
-      sum += t.counts[c];
+      mstart[c] = sum;
+      sum += counts[c];
     }
-    t.mstart[k] = sum;
+    mstart[k] = sum;
   }
   __syncthreads();
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    int w = t.mstart[c];
-    for (int i = 0; i < n; ++i)
+    int w = mstart[c];
+    int i = 0;
+    if (in_lds) {  // four labels per LDS read
+      const int4* l4 = reinterpret_cast<const int4*>(lab);
+      for (; i + 4 <= n; i += 4) {
+        const int4 q = l4[i >> 2];
+        if (q.x == c) members[w++] = i;
+        if (q.y == c) members[w++] = i + 1;
+        if (q.z == c) members[w++] = i + 2;
+        if (q.w == c) members[w++] = i + 3;
+      }
+    }
+    for (; i < n; ++i)
       if (lab[i] == c) members[w++] = i;
   }
   __syncthreads();
@@ -452,29 +469,29 @@ __global__ __launch_bounds__(kKmBlock) void k_km_update(const KmItem* items) {
   // read one member row of X together, four members' loads in flight
   for (int e = threadIdx.x; e < k * d; e += blockDim.x) {
     const int c = e / d, j = e - c * d;
-    const int cnt = t.counts[c];
+    const int cnt = counts[c];
     if (cnt == 0) continue;
     double acc = 0.0;
     const double* xj = t.X + j;
-    int m = t.mstart[c];
-    const int m1 = t.mstart[c + 1];
-    for (; m + 4 <= m1; m += 4) {
-      double v[4];
+    int m = mstart[c];
+    const int m1 = mstart[c + 1];
+    for (; m + 8 <= m1; m += 8) {
+      double v[8];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = xj[(size_t)members[m + q] * d];
+      for (int q = 0; q < 8; ++q) v[q] = xj[(size_t)members[m + q] * d];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc = acc + v[q];
+      for (int q = 0; q < 8; ++q) acc = acc + v[q];
     }
     for (; m < m1; ++m) acc = acc + xj[(size_t)members[m] * d];
     C[(size_t)c * d + j] = acc / (double)cnt;
   }
   __syncthreads();
   int empty = 0;
-  for (int c = threadIdx.x; c < k; c += blockDim.x) empty |= t.counts[c] == 0;
+  for (int c = threadIdx.x; c < k; c += blockDim.x) empty |= counts[c] == 0;
   const bool reseeded = block_or(empty, &sh_i) != 0;
   if (reseeded) {
     for (int c = 0; c < k; ++c) {
-      if (t.counts[c] != 0) continue;  // uniform: every thread reads the same value
+      if (counts[c] != 0) continue;  // uniform: every thread reads the same value
       VI x{-1.0, n};
       for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const double v = sqd_t(t.Xt, n, i, C + (size_t)lab[i] * d, d);
@@ -484,9 +501,9 @@ __global__ __launch_bounds__(kKmBlock) void k_km_update(const KmItem* items) {
       for (int j = threadIdx.x; j < d; j += blockDim.x) C[(size_t)c * d + j] = t.X[(size_t)far * d + j];
       __syncthreads();
       if (threadIdx.x == 0) {
-        --t.counts[lab[far]];
+        --counts[lab[far]];
         lab[far] = c;
-        t.counts[c] = 1;
+        counts[c] = 1;
       }
       __syncthreads();
     }
@@ -543,14 +560,15 @@ int stripes(int k) { return (k + kStripe - 1) / kStripe; }
 // Lloyd iterations of `count` seeded replicates (items on the device, flags
 // of replicate r at flags + 4 r): kChecks iterations of assign + update per
 // round, then a look at the done flags; at most max_iter iterations.
-csc_status run_lloyd(const KmItem* items, int count, int max_stripes, int max_iter, int* flags,
-                     hipStream_t s) {
+csc_status run_lloyd(const KmItem* items, int count, int max_stripes, int max_n, int max_iter,
+                     int* flags, hipStream_t s) {
   std::vector<int> h((size_t)count * 4);
+  const unsigned chunks = (unsigned)std::min(64, std::max(1, (max_n + 255) / 256));
   for (int it = 0; it < max_iter;) {
     const int round = std::min(kChecks, max_iter - it);
     for (int q = 0; q < round; ++q) {
-      hipLaunchKernelGGL(k_km_assign, dim3((unsigned)max_stripes, (unsigned)count), dim3(256), 0, s,
-                         items, count);
+      hipLaunchKernelGGL(k_km_assign, dim3((unsigned)max_stripes, (unsigned)count, chunks), dim3(256),
+                         0, s, items, count);
       CSC_HIP(hipGetLastError());
       hipLaunchKernelGGL(k_km_update, dim3((unsigned)count), dim3(kKmBlock), 0, s, items);
       CSC_HIP(hipGetLastError());
@@ -687,7 +705,7 @@ extern "C" csc_status csc_kmeans_reduced_device(const float* F, int32_t n, int32
   CSC_HIP(hipMemcpyAsync(d_items, P.items.data(), replicates * sizeof(KmItem),
                          hipMemcpyHostToDevice, s));
   CSC_HIP(launch_seed(seed_in_lds(n), d_items, replicates, s));
-  CSC_TRY(run_lloyd(d_items, replicates, stripes(k), max_iter, flags, s));
+  CSC_TRY(run_lloyd(d_items, replicates, stripes(k), n, max_iter, flags, s));
   return finish_km(P, n, replicates, labels, inertia_out, s);
 }
 
@@ -720,12 +738,13 @@ extern "C" csc_status csc_kmeans_reduced_device_batched(int32_t G, const float* 
   for (int pass = 0; pass < 2; ++pass)
     for (int g = 0; g < G; ++g)
       if (seed_in_lds(n[g]) == (pass == 0)) order.push_back(g);
-  int n_lds = 0, max_stripes = 1;
+  int n_lds = 0, max_stripes = 1, max_n = 1;
   for (int g : order) {
     CSC_TRY(plan_km(ar, F[g], n[g], d[g], d[g], k[g], replicates, max_iter, seeds[g], P[g], s));
     all.insert(all.end(), P[g].items.begin(), P[g].items.end());
     if (seed_in_lds(n[g])) n_lds += replicates;
     max_stripes = std::max(max_stripes, stripes(k[g]));
+    max_n = std::max(max_n, n[g]);
   }
   const int total = (int)all.size();
   KmItem* d_items = ar.take<KmItem>(all.size());
@@ -739,7 +758,7 @@ extern "C" csc_status csc_kmeans_reduced_device_batched(int32_t G, const float* 
                          s));
   if (n_lds > 0) CSC_HIP(launch_seed(true, d_items, n_lds, s));
   if (total > n_lds) CSC_HIP(launch_seed(false, d_items + n_lds, total - n_lds, s));
-  CSC_TRY(run_lloyd(d_items, total, max_stripes, max_iter, flags, s));
+  CSC_TRY(run_lloyd(d_items, total, max_stripes, max_n, max_iter, flags, s));
   for (int g = 0; g < G; ++g)
     CSC_TRY(finish_km(P[g], n[g], replicates, labels[g], inertia_out ? inertia_out + g : nullptr,
                       s));
