@@ -14,6 +14,7 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libcsc.so")
 BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CXX = os.environ.get("CSC_CXX", "/opt/rocm/llvm/bin/clang++")
 ARCH = "gfx950"
 
 SOURCES = {
@@ -27,6 +28,12 @@ SOURCES = {
     "kmeans.hip": ["-ffp-contract=off"],
     "kmeans_gpu.hip": ["-ffp-contract=off"],
 }
+
+# host-only C++ (no device code), compiled by the host compiler
+HOST_SOURCES = {
+    "dense.cpp": ["-ffp-contract=off"],
+}
+HOST_COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall"]
 
 COMMON = [
     f"--offload-arch={ARCH}",
@@ -55,11 +62,16 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     jobs = []
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=len(SOURCES) + len(HOST_SOURCES)) as ex:
         for src, extra in SOURCES.items():
             obj = os.path.join(BUILD, src.replace(".hip", ".o"))
             objs.append(obj)
             cmd = [HIPCC, *COMMON, *extra, "-c", os.path.join(HERE, "csrc", src), "-o", obj]
+            jobs.append(ex.submit(_run, cmd, verbose))
+        for src, extra in HOST_SOURCES.items():
+            obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
+            objs.append(obj)
+            cmd = [CXX, *HOST_COMMON, *extra, "-c", os.path.join(HERE, "csrc", src), "-o", obj]
             jobs.append(ex.submit(_run, cmd, verbose))
         for j in jobs:
             j.result()

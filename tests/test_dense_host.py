@@ -17,8 +17,10 @@ def dense(tmp_path_factory):
     if cxx is None:
         pytest.skip("no C++ compiler")
     out = tmp_path_factory.mktemp("dense") / "libdense.so"
-    subprocess.run([cxx, "-O2", "-shared", "-fPIC", "-o", str(out),
-                    os.path.join(HERE, "dense_host.cpp")], check=True)
+    subprocess.run([cxx, "-O2", "-ffp-contract=off", "-shared", "-fPIC", "-o", str(out),
+                    os.path.join(HERE, "dense_host.cpp"),
+                    os.path.join(HERE, "..", "paper_1602_02018_amd", "csrc", "dense.cpp")],
+                   check=True)
     lib = C.CDLL(str(out))
     pd = C.POINTER(C.c_double)
     lib.dense_orth.argtypes = [pd, C.c_int, C.c_double, pd]
