@@ -8,9 +8,11 @@ independent implementation can reproduce it exactly from the same inputs:
 * k-means++ seeding per replicate r: draw u_0 at counter (0, r, KMEANS, 0) and
   take point floor(u_0 n) as the first centre; then for centre c = 1..k-1 draw
   u_c, form the running sums of each point's squared distance to its nearest
-  chosen centre in index order, and take the first point whose running sum
-  exceeds u_c times the total (the last point with a non-zero distance if none
-  does; point floor(u_c n) if the total is 0);
+  chosen centre (``running_sums``: in blocks of SEED_BLOCK points, a block's
+  offset plus the running sum inside the block, both in index order), and
+  take the first point whose running sum exceeds u_c times the total (the
+  last point with a non-zero distance if none does; point floor(u_c n) if the
+  total is 0);
 * Lloyd iterations, at most ``max_iter`` (Matlab's default is 100): assign each
   point to its nearest centre (lowest index on ties); stop when no assignment
   changed (and the previous update re-seeded nothing); otherwise recompute each
@@ -37,6 +39,25 @@ def sqdist(X: np.ndarray, c: np.ndarray) -> np.ndarray:
     return acc
 
 
+SEED_BLOCK = 32
+
+
+def running_sums(w: np.ndarray) -> np.ndarray:
+    """Cumulative k-means++ weights in a fixed two-level order: the running sum
+    of the weights inside each block of SEED_BLOCK consecutive points, plus the
+    block's offset, the running sum of the earlier blocks' totals in block
+    order (real-arithmetic value: the plain prefix sums of w)."""
+    n = w.size
+    nb = -(-n // SEED_BLOCK)
+    pad = np.zeros(nb * SEED_BLOCK)
+    pad[:n] = w
+    inner = np.cumsum(pad.reshape(nb, SEED_BLOCK), axis=1)  # in index order per block
+    off = np.zeros(nb)
+    for b in range(1, nb):
+        off[b] = off[b - 1] + inner[b - 1, -1]
+    return (off[:, None] + inner).reshape(-1)[:n]
+
+
 def seed_plusplus(X: np.ndarray, k: int, seed: int, r: int) -> np.ndarray:
     n = X.shape[0]
     u = uniform(seed, 0, r, KMEANS)
@@ -45,7 +66,7 @@ def seed_plusplus(X: np.ndarray, k: int, seed: int, r: int) -> np.ndarray:
     mind = sqdist(X, centres[0])
     for c in range(1, k):
         u = uniform(seed, c, r, KMEANS)
-        cum = np.cumsum(mind)
+        cum = running_sums(mind)
         total = cum[-1]
         if total == 0.0:
             pick = min(int(math.floor(u * n)), n - 1)

@@ -2,9 +2,10 @@
 //
 // The paper runs Matlab's kmeans with 20 replicates and a 100-iteration cap
 // (Sec. 5).  This implementation fixes every rounding so that it is
-// reproducible: squared distances sum coordinates in increasing order,
-// centroids sum member points in increasing index order, and ties go to the
-// lowest index.  Replicates run on worker threads; the winner is chosen in
+// reproducible: squared distances sum coordinates in increasing order, the
+// k-means++ weights are summed in blocks of kSeedBlock points (block offset
+// plus in-block running sum, each in order), centroids sum member points in
+// increasing index order, and ties go to the lowest index.  Replicates run on worker threads; the winner is chosen in
 // replicate order, so the result does not depend on scheduling.  This file is
 // compiled with floating-point contraction disabled.
 #include <algorithm>
@@ -106,10 +107,17 @@ void seed_plusplus(const Points& P, int k, uint64_t seed, int r, double* C) {
   dist_to(P, C, mind.data());
   for (int c = 1; c < k; ++c) {
     u = draw_uniform(seed, (uint64_t)c, (uint64_t)r);
-    double run = 0.0;
-    for (int i = 0; i < n; ++i) {
-      run = run + mind[i];
-      cum[i] = run;
+    // running sums in blocks of kSeedBlock points: block offset plus the
+    // running sum inside the block, both in index order
+    double off = 0.0;
+    for (int b0 = 0; b0 < n; b0 += kSeedBlock) {
+      const int b1 = std::min(n, b0 + kSeedBlock);
+      double in = 0.0;
+      for (int i = b0; i < b1; ++i) {
+        in = in + mind[i];
+        cum[i] = off + in;
+      }
+      off = off + in;
     }
     const double total = cum[n - 1];
     int pick;

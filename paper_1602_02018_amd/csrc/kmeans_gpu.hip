@@ -3,7 +3,7 @@
 // Philox draws, Lloyd iterations, empty clusters re-seeded with the farthest
 // point, the lowest inertia over replicates kept.  Every sum keeps the host's
 // order (squared distances over coordinates in order, the k-means++ running
-// sum over points in order, centroids over members in index order, inertia
+// sum over points in blocks of kSeedBlock, centroids over members in index order, inertia
 // over points in order), every tie goes to the lowest index, and this file is
 // compiled without floating-point contraction, so labels and inertia are
 // bit-identical to the host's.
@@ -47,6 +47,7 @@ struct KmItem {
   double* C;        // k x d
   double* mind;     // n (used when the weights do not fit in LDS)
   double* cum;      // n (likewise)
+  double* blk;      // ceil(n / kSeedBlock): block offsets (when the weights are not in LDS)
   int* lab;         // n
   int* fresh;       // n
   int* counts;      // k
@@ -226,12 +227,17 @@ __global__ __launch_bounds__(kKmBlock) void k_km_seed(const KmItem* items) {
   __shared__ double sh_cc[kCcLds];
 
   // ---- k-means++ seeding.  The D^2 weights and their running sums live in
-  // LDS when they fit; one thread forms the running sum in point order,
-  // exactly as the host loop, and the first point whose running sum passes
-  // u * total is found by an index reduction.
+  // LDS when they fit.  The running sums take the host's two-level order: one
+  // thread per block of kSeedBlock points forms the in-block running sums,
+  // one thread the block offsets, and every point adds its block's offset;
+  // the first point whose running sum passes u * total is found by an index
+  // reduction.
   __shared__ double smem[SEED_LDS ? kLdsDoubles : 1];
+  __shared__ double sh_blk[SEED_LDS ? kLdsDoubles / (2 * kSeedBlock) : 1];
   double* mind = SEED_LDS ? smem : t.mind;
   double* cum = SEED_LDS ? smem + n : t.cum;
+  double* blk = SEED_LDS ? sh_blk : t.blk;
+  const int nb = (n + kSeedBlock - 1) / kSeedBlock;
   // one point per thread with its coordinates in registers when they fit
   const bool reg = n <= (int)blockDim.x && d <= kSeedRegD;
   float xr[kSeedRegD];
@@ -256,24 +262,26 @@ __global__ __launch_bounds__(kKmBlock) void k_km_seed(const KmItem* items) {
   }
   for (int c = 1; c < k; ++c) {
     const double u = draw_uniform(t.seed, (uint64_t)c, (uint64_t)t.r);
-    if (threadIdx.x == 0) {
-      double run = 0.0;
-      int i = 0;
-      for (; i + 8 <= n; i += 8) {
-        double v[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = mind[i + q];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          run = run + v[q];
-          cum[i + q] = run;
-        }
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+      const int i0 = q * kSeedBlock, i1 = min(n, i0 + kSeedBlock);
+      double in = 0.0;
+      for (int i = i0; i < i1; ++i) {
+        in = in + mind[i];
+        cum[i] = in;
       }
-      for (; i < n; ++i) {
-        run = run + mind[i];
-        cum[i] = run;
+      blk[q] = in;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // block totals -> block offsets, in block order
+      double off = 0.0;
+      for (int q = 0; q < nb; ++q) {
+        const double tq = blk[q];
+        blk[q] = off;
+        off = off + tq;
       }
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) cum[i] = blk[i / kSeedBlock] + cum[i];
     __syncthreads();
     const double total = cum[n - 1];
     int pick;
@@ -587,14 +595,16 @@ csc_status run_lloyd(const KmItem* items, int count, int max_stripes, int max_n,
 }
 
 // workspace of one input: X (n x d doubles) + per replicate C, mind, cum,
-// lab, fresh, counts, mstart, members, labels, stripe results, Lloyd flags;
+// lab, fresh, counts, mstart, members, labels, stripe results, seeding block
+// offsets, Lloyd flags;
 // plus inertias
 size_t km_bytes(int n, int d, int k, int reps) {
   size_t b = 2 * align_up((size_t)n * d * sizeof(double));
   const size_t ns = (size_t)stripes(k);
   const size_t per = align_up((size_t)k * d * sizeof(double)) + 2 * align_up((size_t)n * sizeof(double)) +
                      4 * align_up((size_t)n * sizeof(int)) + 2 * align_up(((size_t)k + 1) * sizeof(int)) +
-                     align_up(ns * n * sizeof(double)) + align_up(ns * n * sizeof(int));
+                     align_up(ns * n * sizeof(double)) + align_up(ns * n * sizeof(int)) +
+                     align_up((size_t)((n + kSeedBlock - 1) / kSeedBlock) * sizeof(double));
   b += per * reps + align_up((size_t)reps * sizeof(double)) + align_up((size_t)reps * 4 * sizeof(int));
   return b;
 }
@@ -627,6 +637,7 @@ csc_status plan_km(Arena& ar, const float* F, int n, int d, int ld, int k, int r
     t.C = ar.take<double>((size_t)k * d);
     t.mind = ar.take<double>(n);
     t.cum = ar.take<double>(n);
+    t.blk = ar.take<double>((n + kSeedBlock - 1) / kSeedBlock);
     t.lab = ar.take<int>(n);
     t.fresh = ar.take<int>(n);
     t.members = ar.take<int>(n);

@@ -329,6 +329,22 @@ def test_plusplus_second_centre_weights_are_squared_distances():
     assert abs(hits[2] / tot - 0.9) < 0.03  # D^2 weights 1 : 9; D weights would give 0.75
 
 
+@pytest.mark.parametrize("n", [1, 2, 31, 32, 33, 64, 65, 100, 922])
+def test_plusplus_running_sums_are_the_prefix_sums(n):
+    """The two-level order of the seeding's cumulative weights changes only
+    the rounding: with integer weights (exact in float64) it is the exact
+    prefix sum, across every block boundary; with real weights it stays
+    within n ulps of the exactly rounded prefix sums."""
+    rng = np.random.default_rng(n)
+    w = rng.integers(0, 1000, n)
+    assert np.array_equal(kmeans.running_sums(w.astype(np.float64)), np.cumsum(w).astype(np.float64))
+    x = rng.random(n) ** 3
+    exact = np.array([math.fsum(x[: i + 1]) for i in range(n)])
+    got = kmeans.running_sums(x)
+    assert np.all(np.abs(got - exact) <= n * np.finfo(float).eps * exact[-1])
+    assert np.all(np.diff(got) >= 0.0)
+
+
 def test_kmeans_recovers_blobs_and_picks_lowest_inertia():
     X, lab = _blobs(seed=3, k=6, spread=0.02)
     out, C, inertia = kmeans.kmeans(X, 6, seed=1, replicates=5)
