@@ -887,65 +887,90 @@ csc_status block_init(BlockState& st, const Layout& L, int k, double tol, bool j
   return CSC_OK;
 }
 
-csc_status block_pre(BlockState& st, hipStream_t s) {
+// Each iteration runs in stages: a launch stage only enqueues device work
+// and copies into st's host vectors, a host stage runs the k x k algebra on
+// what the previous launch stage brought back (the caller synchronises the
+// stream in between).  block_pre and block_post chain the stages of one
+// graph; the batched form runs each stage for all graphs, one
+// synchronisation per stage and the host stages in parallel.
+csc_status pre_launch(BlockState& st, hipStream_t s) {
   const BlockBufs& b = st.b;
   const int k = st.k;
   CSC_HIP(launch_gram(st.L, b.Z, b.Z, k, k, b.gpart, b.G, k, s));
-  CSC_TRY(download(st.G, b.G, (size_t)k * k, s));
-  st.sr = dense::orth_transform(st.G, k, 1e-10, st.T);
+  st.G.resize((size_t)k * k);
+  CSC_HIP(hipMemcpyAsync(st.G.data(), b.G, st.G.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  return CSC_OK;
+}
+
+void pre_host(BlockState& st) {
+  st.sr = dense::orth_transform(st.G, st.k, 1e-10, st.T);
   if (st.sr == 0) {  // Z = 0: every residual column vanished
     st.finished = true;
     st.converged = true;
-    return CSC_OK;
   }
+}
+
+csc_status pre_finish(BlockState& st, hipStream_t s) {
+  const BlockBufs& b = st.b;
+  const int k = st.k;
   CSC_TRY(upload_d(b.S_t, st.T, s));
   CSC_HIP(launch_block_mul(st.L, 0.f, nullptr, b.Z, b.S_t, k, st.sr, k, b.P, s));
   return CSC_OK;
 }
 
-csc_status block_post(BlockState& st, int it, int max_iter, hipStream_t s) {
+// W = P^T Q (s x s) and P^T R (s x k, parked in S_b, which is free until beta)
+csc_status post_launch_a(BlockState& st, hipStream_t s) {
   const BlockBufs& b = st.b;
-  const Layout& L = st.L;
   const int k = st.k, sr = st.sr;
-  // W = P^T Q (s x s), alpha = W^{-1} P^T R (s x k); both Gram matrices come
-  // back in one round trip (P^T R is parked in S_b, which is free until beta)
-  CSC_HIP(launch_gram(L, b.P, b.Q, sr, sr, b.gpart, b.G, sr, s));
-  CSC_HIP(launch_gram(L, b.P, b.R, sr, k, b.gpart, b.S_b, k, s));
+  CSC_HIP(launch_gram(st.L, b.P, b.Q, sr, sr, b.gpart, b.G, sr, s));
+  CSC_HIP(launch_gram(st.L, b.P, b.R, sr, k, b.gpart, b.S_b, k, s));
   st.W.resize((size_t)sr * sr);
   st.C.resize((size_t)sr * k);
   CSC_HIP(hipMemcpyAsync(st.W.data(), b.G, st.W.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   CSC_HIP(hipMemcpyAsync(st.C.data(), b.S_b, st.C.size() * sizeof(double), hipMemcpyDeviceToHost,
                          s));
-  CSC_HIP(hipStreamSynchronize(s));
+  return CSC_OK;
+}
+
+// alpha = W^{-1} P^T R (and -alpha); a W that is not positive definite ends the solve
+void post_host_a(BlockState& st) {
+  const int k = st.k, sr = st.sr;
   if (!dense::cholesky(st.W, sr, sr)) {
     st.finished = true;
     st.broke = true;
-    return CSC_OK;
+    return;
   }
   dense::chol_solve(st.W, sr, sr, st.C, k, 1.0);
   st.N = st.C;
   for (auto& v : st.N) v = -v;
+}
+
+// X += P alpha, R -= Q alpha; the column norms of R, and the next search
+// block's Gram Q^T Z formed before the convergence check so that both come
+// back in one round trip (after the last iteration it goes unused)
+csc_status post_launch_b(BlockState& st, hipStream_t s) {
+  const BlockBufs& b = st.b;
+  const Layout& L = st.L;
+  const int k = st.k, sr = st.sr;
   CSC_TRY(upload_d(b.S_a, st.C, s));
   CSC_TRY(upload_d(b.S_na, st.N, s));
   CSC_HIP(launch_block_mul(L, 1.f, b.X, b.P, b.S_a, sr, k, k, b.X, s));
   CSC_HIP(launch_block_mul(L, 1.f, b.R, b.Q, b.S_na, sr, k, k, b.R, s));
-  // every column: ||r_j|| <= tol ||b_j||.  The next search block's Gram
-  // Q^T Z is formed before the check so that both come back in one round trip
-  // (after the last iteration it goes unused).
   CSC_HIP(launch_col_dot(L, b.R, b.R, b.part, s));
   CSC_HIP(launch_reduce(b.part, tiles_for(L), k, b.rn2, s));
-  const float* Zr = b.R;
-  if (st.jacobi) {
-    CSC_HIP(launch_jacobi(L, b.R, b.mask, st.gamma, b.Z, s));
-    Zr = b.Z;
-  }
-  CSC_HIP(launch_gram(L, b.Q, Zr, sr, k, b.gpart, b.G, k, s));
+  if (st.jacobi) CSC_HIP(launch_jacobi(L, b.R, b.mask, st.gamma, b.Z, s));
+  CSC_HIP(launch_gram(L, b.Q, st.jacobi ? b.Z : b.R, sr, k, b.gpart, b.G, k, s));
   st.rn2.resize(k);
   st.C.resize((size_t)sr * k);
   CSC_HIP(hipMemcpyAsync(st.rn2.data(), b.rn2, (size_t)k * sizeof(double), hipMemcpyDeviceToHost,
                          s));
   CSC_HIP(hipMemcpyAsync(st.C.data(), b.G, st.C.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  CSC_HIP(hipStreamSynchronize(s));
+  return CSC_OK;
+}
+
+// every column: ||r_j|| <= tol ||b_j||; then beta = -W^{-1} Q^T Z unless done
+void post_host_b(BlockState& st, int it, int max_iter) {
+  const int k = st.k;
   for (int j = 0; j < k; ++j) {
     if (st.bn2[j] <= 0.0) continue;
     st.relres[j] = std::sqrt(st.rn2[j] / st.bn2[j]);
@@ -957,17 +982,42 @@ csc_status block_post(BlockState& st, int it, int max_iter, hipStream_t s) {
   }
   if (st.ndone == st.nlive) {
     st.finished = st.converged = true;
-    return CSC_OK;
+    return;
   }
   if (it == max_iter) {
     st.finished = true;
-    return CSC_OK;
+    return;
   }
-  // beta = -W^{-1} Q^T Z;  Z = Z + P beta  (Z = R, or D^-1 R)
-  dense::chol_solve(st.W, sr, sr, st.C, k, -1.0);
+  dense::chol_solve(st.W, st.sr, st.sr, st.C, k, -1.0);
+}
+
+// Z = Z + P beta  (Z = R, or D^-1 R)
+csc_status post_finish(BlockState& st, hipStream_t s) {
+  const BlockBufs& b = st.b;
+  const int k = st.k, sr = st.sr;
   CSC_TRY(upload_d(b.S_b, st.C, s));
-  CSC_HIP(launch_block_mul(L, 1.f, Zr, b.P, b.S_b, sr, k, k, b.Z, s));
+  CSC_HIP(launch_block_mul(st.L, 1.f, st.jacobi ? b.Z : b.R, b.P, b.S_b, sr, k, k, b.Z, s));
   return CSC_OK;
+}
+
+csc_status block_pre(BlockState& st, hipStream_t s) {
+  CSC_TRY(pre_launch(st, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  pre_host(st);
+  if (st.finished) return CSC_OK;
+  return pre_finish(st, s);
+}
+
+csc_status block_post(BlockState& st, int it, int max_iter, hipStream_t s) {
+  CSC_TRY(post_launch_a(st, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  post_host_a(st);
+  if (st.finished) return CSC_OK;
+  CSC_TRY(post_launch_b(st, s));
+  CSC_HIP(hipStreamSynchronize(s));
+  post_host_b(st, it, max_iter);
+  if (st.finished) return CSC_OK;
+  return post_finish(st, s);
 }
 
 void block_finish(BlockState& st, int max_iter) {

@@ -5,15 +5,38 @@
 // replayed.  Each graph follows exactly the arithmetic of the single-graph
 // calls, so outputs are bit-identical to calling those graph by graph.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "host.hpp"
 
 namespace csc {
 namespace {
+
+// f(g) for every g in idx on up to 16 host threads (each call touches only
+// graph g's state); in order on the calling thread for a single graph.
+template <class F>
+void host_parallel(const std::vector<int>& idx, F f) {
+  const int n = (int)idx.size();
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nt = std::min({n, hw, 16});
+  if (nt <= 1) {
+    for (int g : idx) f(g);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::vector<std::thread> pool;
+  pool.reserve(nt);
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&] {
+      for (int i; (i = next.fetch_add(1)) < n;) f(idx[i]);
+    });
+  for (auto& th : pool) th.join();
+}
 
 struct Captured {
   hipGraphExec_t exec = nullptr;
@@ -815,19 +838,40 @@ extern "C" csc_status csc_interpolate_batched(
       }
       return CSC_OK;
     };
+    // each stage of the iteration runs for every graph before the next one:
+    // one synchronisation per stage, the host algebra of the graphs in parallel
+    auto unfinished = [&]() {
+      std::vector<int> v;
+      for (int g = 0; g < G; ++g)
+        if (!bs[g].finished) v.push_back(g);
+      return v;
+    };
     Captured cap_pass;
     for (int it = 1; it <= max_iter; ++it) {
+      std::vector<int> act = unfinished();
+      if (act.empty()) break;
+      for (int g : act) CSC_TRY(pre_launch(bs[g], s));
+      CSC_HIP(hipStreamSynchronize(s));
+      host_parallel(act, [&](int g) { pre_host(bs[g]); });
       bool any = false;
       for (int g = 0; g < G; ++g) {
-        if (!bs[g].finished) CSC_TRY(block_pre(bs[g], s));
         live[g] = bs[g].finished ? 0 : 1;
         any = any || live[g];
+        if (live[g]) CSC_TRY(pre_finish(bs[g], s));
       }
       if (!any) break;
       CSC_TRY(upload(d_live, live, s));
       CSC_TRY(run_pass(filter_pass, cap_pass, s));
-      for (int g = 0; g < G; ++g)
-        if (live[g]) CSC_TRY(block_post(bs[g], it, max_iter, s));
+      act = unfinished();
+      for (int g : act) CSC_TRY(post_launch_a(bs[g], s));
+      CSC_HIP(hipStreamSynchronize(s));
+      host_parallel(act, [&](int g) { post_host_a(bs[g]); });
+      act = unfinished();
+      if (act.empty()) continue;
+      for (int g : act) CSC_TRY(post_launch_b(bs[g], s));
+      CSC_HIP(hipStreamSynchronize(s));
+      host_parallel(act, [&](int g) { post_host_b(bs[g], it, max_iter); });
+      for (int g : unfinished()) CSC_TRY(post_finish(bs[g], s));
     }
     std::vector<ColDotItem> h_cd(G);
     std::vector<ReduceItem> h_cn(G);

@@ -68,6 +68,17 @@ csc_status block_init(BlockState& st, const Layout& L, int k, double tol, bool j
                       const BlockBufs& b, const double* bnorm2_dev, hipStream_t s);
 csc_status block_pre(BlockState& st, hipStream_t s);
 csc_status block_post(BlockState& st, int it, int max_iter, hipStream_t s);
+// The stages of block_pre and block_post: the launch stages enqueue device
+// work and copies into st's host vectors, the host stages (which touch only
+// st) need the stream synchronised after the preceding launch stage.
+csc_status pre_launch(BlockState& st, hipStream_t s);
+void pre_host(BlockState& st);
+csc_status pre_finish(BlockState& st, hipStream_t s);
+csc_status post_launch_a(BlockState& st, hipStream_t s);
+void post_host_a(BlockState& st);
+csc_status post_launch_b(BlockState& st, hipStream_t s);
+void post_host_b(BlockState& st, int it, int max_iter);
+csc_status post_finish(BlockState& st, hipStream_t s);
 void block_finish(BlockState& st, int max_iter);
 
 // Workspace of permuted_graph, and the graph g permuted to `order` (row r =

@@ -28,6 +28,7 @@ namespace {
 
 constexpr int kBlk = 256;
 constexpr int kLdsFloats = 12288;  // 48 KB of centroids per chunk
+constexpr int kUseMax = 2048;      // centroids per chunk at most (their usable flags)
 
 inline unsigned blocks_for(size_t n, size_t per) {
   size_t g = (n + per - 1) / per;
@@ -118,13 +119,16 @@ __global__ __launch_bounds__(kBlk) void k_nearest_centroid(int N, int d, const f
                                                            size_t ldf, const float* C,
                                                            const int* usable, int k,
                                                            int* labels) {
+  // centroids and their usable flags staged in LDS, kc at a time; two
+  // centroids per pass over the node's coordinates (independent sums)
   __shared__ float cs[kLdsFloats];
+  __shared__ int use[kUseMax];
   const int i = blockIdx.x * kBlk + threadIdx.x;
   const bool row = i < N;
   float f[DMAX];
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) f[j] = (row && j < d) ? F[(size_t)i * ldf + j] : 0.f;
-  const int kc = kLdsFloats / d;
+  const int kc = min(kUseMax, kLdsFloats / d);
   float best = 0.f;
   int arg = 0;
   bool found = false;
@@ -132,21 +136,29 @@ __global__ __launch_bounds__(kBlk) void k_nearest_centroid(int N, int d, const f
     const int nc = min(kc, k - c0);
     __syncthreads();
     for (int e = threadIdx.x; e < nc * d; e += kBlk) cs[e] = C[(size_t)c0 * d + e];
+    for (int e = threadIdx.x; e < nc; e += kBlk) use[e] = usable[c0 + e];
     __syncthreads();
     if (row) {
-      for (int c = 0; c < nc; ++c) {
-        if (!usable[c0 + c]) continue;
-        const float* cc = cs + c * d;
-        float dist = 0.f;
+      for (int c = 0; c < nc; c += 2) {
+        const bool two = c + 1 < nc;
+        const float* ca = cs + c * d;
+        const float* cb = cs + (two ? c + 1 : c) * d;
+        float da = 0.f, db = 0.f;
 #pragma unroll
         for (int j = 0; j < DMAX; ++j)
           if (j < d) {
-            const float t = f[j] - cc[j];
-            dist = fmaf(t, t, dist);
+            const float ta = f[j] - ca[j], tb = f[j] - cb[j];
+            da = fmaf(ta, ta, da);
+            db = fmaf(tb, tb, db);
           }
-        if (!found || dist < best) {
-          best = dist;
+        if (use[c] && (!found || da < best)) {
+          best = da;
           arg = c0 + c;
+          found = true;
+        }
+        if (two && use[c + 1] && (!found || db < best)) {
+          best = db;
+          arg = c0 + c + 1;
           found = true;
         }
       }
