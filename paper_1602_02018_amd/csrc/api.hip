@@ -8,6 +8,7 @@
 #include <tuple>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -45,6 +46,20 @@ bool xcd_batched() { return g_tune_xcd.load() != 0; }
 // Stream used only to record HIP graphs (kernels are captured, never run on
 // it); one per device, default priority, kept for the life of the process.
 hipStream_t capture_stream() {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+    streams[dev] = nullptr;
+  return streams[dev];
+}
+
+// Second stream for work that overlaps the caller's stream (the signals of
+// the next eigencount pass); one per device, default priority, kept for the
+// life of the process.  Ordering with the caller's stream goes through events.
+hipStream_t side_stream() {
   static std::mutex mu;
   static hipStream_t streams[64] = {};
   int dev = 0;
@@ -308,7 +323,7 @@ void moments_from_raw(const double* raw, int p, double* mom) {
 
 size_t count_bytes(const Layout& L, int p) {
   const size_t nblocks = (size_t)L.np * tiles_for(L);
-  size_t b = 3 * align_up(L.bytes());
+  size_t b = 4 * align_up(L.bytes());  // two signal blocks, two recurrence blocks
   b += align_up((size_t)moment_raw(p) * nblocks * sizeof(double));
   b += align_up((size_t)moment_raw(p) * sizeof(double));
   return b + 256;
@@ -340,6 +355,7 @@ size_t max_over_widths(int n, int w, F f) {
 // ------------------------------------------------------------ eigencount ---
 struct CountBuffers {
   float* T0;
+  float* T0n;  // the next pass's signals (dichotomy)
   float* Ta;
   float* Tb;
   double* part;
@@ -350,6 +366,7 @@ CountBuffers carve_count(Arena& ar, const Layout& L, int p) {
   const size_t nblocks = (size_t)L.np * tiles_for(L);
   CountBuffers c;
   c.T0 = ar.take<float>(L.elems());
+  c.T0n = ar.take<float>(L.elems());
   c.Ta = ar.take<float>(L.elems());
   c.Tb = ar.take<float>(L.elems());
   c.part = ar.take<double>((size_t)moment_raw(p) * nblocks);
@@ -357,12 +374,60 @@ CountBuffers carve_count(Arena& ar, const Layout& L, int p) {
   return c;
 }
 
+// Draws eigencount signal blocks on the side stream, ordered against the
+// caller's stream s by events: the side stream starts after s's earlier work
+// (the workspace may still be in use), s waits for a draw before the pass
+// that reads it and, when this object goes, for the last draw.  Off (draw()
+// does nothing and passes draw their own signals) without a side stream or
+// events.
+class SignalAhead {
+ public:
+  explicit SignalAhead(hipStream_t s) : s_(s), s2_(side_stream()) {
+    if (!s2_) return;
+    if (hipEventCreateWithFlags(&start_, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&drawn_, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(start_, s_) != hipSuccess || hipStreamWaitEvent(s2_, start_, 0) != hipSuccess)
+      s2_ = nullptr;
+  }
+  ~SignalAhead() {
+    if (s2_ && pending_) (void)hipStreamWaitEvent(s_, drawn_, 0);
+    if (start_) (void)hipEventDestroy(start_);
+    if (drawn_) (void)hipEventDestroy(drawn_);
+  }
+  SignalAhead(const SignalAhead&) = delete;
+  SignalAhead& operator=(const SignalAhead&) = delete;
+  bool on() const { return s2_ != nullptr; }
+  csc_status draw(const Layout& L, uint64_t seed, uint32_t t, float* out) {
+    if (!s2_) return CSC_OK;
+    CSC_HIP(launch_gaussian_panels(L, seed, t, CSC_STREAM_COUNT, out, s2_));
+    CSC_HIP(hipEventRecord(drawn_, s2_));
+    pending_ = true;
+    return CSC_OK;
+  }
+  // s waits for the last draw
+  csc_status wait() {
+    if (!s2_ || !pending_) return CSC_OK;
+    CSC_HIP(hipStreamWaitEvent(s_, drawn_, 0));
+    pending_ = false;
+    return CSC_OK;
+  }
+
+ private:
+  hipStream_t s_;
+  hipStream_t s2_;
+  hipEvent_t start_ = nullptr, drawn_ = nullptr;
+  bool pending_ = false;
+};
+
+// One eigencount pass on the signals of pass t: drawn into c.T0 first, or
+// already in T0 (drawn ahead by the caller) when T0 is given.
 csc_status moments_pass(const csc_graph& g, const Layout& L, int p, uint64_t seed, uint32_t t,
-                        const CountBuffers& c, double* mom_host, hipStream_t s) {
+                        const CountBuffers& c, double* mom_host, hipStream_t s,
+                        const float* T0 = nullptr) {
   const size_t nblocks = (size_t)L.np * tiles_for(L);
-  CSC_HIP(launch_gaussian_panels(L, seed, t, CSC_STREAM_COUNT, c.T0, s));
+  if (!T0) CSC_HIP(launch_gaussian_panels(L, seed, t, CSC_STREAM_COUNT, c.T0, s));
   Pass b;
-  b.T0 = c.T0;
+  b.T0 = T0 ? T0 : c.T0;
   b.Ta = c.Ta;
   b.Tb = c.Tb;
   b.part = c.part;
@@ -385,6 +450,28 @@ double count_from_moments(double lambda, int p, const double* mom) {
   double c = 0.0;
   for (int m = 0; m <= p; ++m) c += a[m] * mom[m];
   return c;
+}
+
+csc_status count_passes(const csc_graph& g, int n_signals, int p, uint64_t seed, uint32_t t0,
+                        void* ws, size_t ws_bytes, hipStream_t s,
+                        const std::function<bool(uint32_t, const double*)>& more) {
+  const Layout L = make_layout(g.n, n_signals, choose_panel_width(g.n, n_signals, g.nnz));
+  CSC_TRY(check_ws(ws, ws_bytes, count_bytes(L, p)));
+  Arena ar(ws, ws_bytes);
+  const CountBuffers c = carve_count(ar, L, p);
+  // the signals of pass t + 1 are drawn on a second stream while pass t runs
+  // (they do not depend on its count); the two signal blocks alternate
+  SignalAhead ahead(s);
+  float* blocks[2] = {c.T0, c.T0n};
+  CSC_TRY(ahead.draw(L, seed, t0, blocks[0]));
+  std::vector<double> mom(p + 1);
+  for (uint32_t t = t0;; ++t) {
+    const float* cur = blocks[(t - t0) & 1];
+    CSC_TRY(ahead.wait());
+    CSC_TRY(ahead.draw(L, seed, t + 1, blocks[(t - t0 + 1) & 1]));
+    CSC_TRY(moments_pass(g, L, p, seed, t, c, mom.data(), s, ahead.on() ? cur : nullptr));
+    if (!more(t, mom.data())) return CSC_OK;
+  }
 }
 
 }  // namespace csc
@@ -682,49 +769,50 @@ extern "C" csc_status csc_estimate_lambda_k(const csc_graph* g, int32_t k, int32
     lo = bracket[0];
     hi = bracket[1];
   }
-  const Layout L = make_layout(g->n, n_signals, choose_panel_width(g->n, n_signals, g->nnz));
-  CSC_TRY(check_ws(ws, ws_bytes, count_bytes(L, p)));
-  Arena ar(ws, ws_bytes);
-  const CountBuffers c = carve_count(ar, L, p);
-  hipStream_t s = as_stream(stream);
-  std::vector<double> mom(p + 1);
-  int used = 0;
-  bool below = false, above = false, missed = false;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    for (int t = 1; t <= max_steps; ++t) {
-      const double mid = 0.5 * (lo + hi);
-      CSC_TRY(moments_pass(*g, L, p, seed, (uint32_t)(used + 1), c, mom.data(), s));
-      if (used == 0 && moments_out) std::memcpy(moments_out, mom.data(), (p + 1) * sizeof(double));
-      const double cnt = count_from_moments(mid, p, mom.data());
-      if (trace_out) {
-        trace_out[2 * used] = mid;
-        trace_out[2 * used + 1] = cnt;
-      }
-      ++used;
-      if (std::floor(cnt + 0.5) == (double)k) {
-        *lambda_out = mid;
-        *steps_out = used;
-        return missed ? CSC_W_BRACKET_MISS : CSC_OK;
-      }
-      if (cnt < k) {
-        lo = mid;
-        below = true;
-      } else {
-        hi = mid;
-        above = true;
-      }
+  // pass `used + 1` tests the midpoint of the current bracket; with a caller
+  // bracket that the first max_steps passes never straddle, the search
+  // restarts once from [0, 2]
+  int used = 0, in_attempt = 0, attempt = 0;
+  bool below = false, above = false, missed = false, found = false;
+  double found_lambda = 0.0;
+  auto more = [&](uint32_t, const double* mom) -> bool {
+    const double mid = 0.5 * (lo + hi);
+    if (used == 0 && moments_out) std::memcpy(moments_out, mom, (p + 1) * sizeof(double));
+    const double cnt = count_from_moments(mid, p, mom);
+    if (trace_out) {
+      trace_out[2 * used] = mid;
+      trace_out[2 * used + 1] = cnt;
     }
+    ++used;
+    ++in_attempt;
+    if (std::floor(cnt + 0.5) == (double)k) {
+      found = true;
+      found_lambda = mid;
+      return false;
+    }
+    if (cnt < k) {
+      lo = mid;
+      below = true;
+    } else {
+      hi = mid;
+      above = true;
+    }
+    if (in_attempt < max_steps) return true;
     // exhausted: with a caller bracket, a one-sided history means lambda_k lies outside
     if (bracket && attempt == 0 && !(below && above)) {
       missed = true;
       lo = 0.0;
       hi = 2.0;
-      continue;
+      attempt = 1;
+      in_attempt = 0;
+      return true;
     }
-    break;
-  }
-  *lambda_out = hi;
+    return false;
+  };
+  CSC_TRY(count_passes(*g, n_signals, p, seed, 1, ws, ws_bytes, as_stream(stream), more));
+  *lambda_out = found ? found_lambda : hi;
   *steps_out = used;
+  if (found) return missed ? CSC_W_BRACKET_MISS : CSC_OK;
   return missed ? CSC_W_BRACKET_MISS : CSC_W_BISECT_EXHAUSTED;
 }
 

@@ -1,6 +1,7 @@
 // Host-side helpers shared by the single-graph and the batched C calls.
 #pragma once
 
+#include <functional>
 #include <vector>
 
 #include "kernels.hpp"
@@ -17,6 +18,13 @@ void apply_tuning(StepArgs& sa);
 const int* step_sched(const csc_graph& g, const Layout& L);
 size_t filter_bytes(const Layout& L);
 size_t count_bytes(const Layout& L, int p);
+// Eigencount passes t0, t0 + 1, ... (the dichotomy of Sec. 4.3) on a count
+// workspace (count_bytes): after each pass, more(t, moments) says whether
+// another follows.  Pass t + 1's signals are drawn on a second stream while
+// pass t runs.
+csc_status count_passes(const csc_graph& g, int n_signals, int p, uint64_t seed, uint32_t t0,
+                        void* ws, size_t ws_bytes, hipStream_t s,
+                        const std::function<bool(uint32_t, const double*)>& more);
 // A moment pass of order p runs moment_steps(p) = ceil(p/2) Chebyshev steps
 // and leaves moment_raw(p) = 2 ceil(p/2) + 1 float64 products: raw[0] =
 // <T_0, T_0>, raw[2j-1] = <T_{j-1}, T_j>, raw[2j] = <T_j, T_j>.

@@ -347,52 +347,61 @@ extern "C" csc_status csc_estimate_lambda_k_learned(const csc_graph* g, int32_t 
   float* dy = ar.take<float>(kOut);
   char* mws = ar.take<char>(mlp_ws(1));
 
-  // 1. the first pass of the plain dichotomy: lambda = 1, sub-stream 1
-  std::vector<double> mom(p + 1);
-  double c1 = 0.0;
-  CSC_TRY(csc_eigencount(g, 1.0, p, n_signals, seed, 1, &c1, mom.data(), est, est_ws, stream));
-  int used = 1;
-  if (trace_out) {
-    trace_out[0] = 1.0;
-    trace_out[1] = c1;
-  }
-  if (std::floor(c1 + 0.5) == (double)k) {
-    *lambda_out = 1.0;
-    *steps_out = 1;
-    if (bracket_out) bracket_out[0] = bracket_out[1] = 1.0;
-    return CSC_OK;
-  }
-  // 2. bracket from the network on the first pass's moments
-  float x[kIn], y[kOut];
-  features(mom.data(), g->n, k, x);
-  CSC_HIP(hipMemcpyAsync(dx, x, sizeof(x), hipMemcpyHostToDevice, s));
-  CSC_TRY(csc_mlp_forward(params, dx, 1, dy, mws, mlp_ws(1), stream));
-  CSC_HIP(hipMemcpyAsync(y, dy, sizeof(y), hipMemcpyDeviceToHost, s));
-  CSC_HIP(hipStreamSynchronize(s));
+  // Passes 1, 2, ... with fresh signals each: pass 1 is the first pass of the
+  // plain dichotomy (lambda = 1) and its moments give the network's bracket;
+  // the later ones bisect inside that bracket.
   LearnedState S;
-  learned_begin(S, mom.data(), p, k, n_signals, c1, y);
-  if (bracket_out) {
-    bracket_out[0] = S.lo;
-    bracket_out[1] = S.hi;
-  }
-  // 3. dichotomy inside the bracket with fresh signals (sub-streams 2, 3, ...)
-  while (used < max_steps) {
-    const double mid = 0.5 * (S.lo + S.hi);
-    double cnt = 0.0;
-    CSC_TRY(csc_eigencount(g, mid, p, n_signals, seed, (uint32_t)(used + 1), &cnt, nullptr, est,
-                           est_ws, stream));
+  int used = 0;
+  bool done = false;
+  double lam = 0.0;
+  csc_status st = CSC_OK;
+  // the bracket from the network on the first pass's moments (count c1 at 1)
+  auto network = [&](const double* mom, double c1) -> csc_status {
+    float x[kIn], y[kOut];
+    features(mom, g->n, k, x);
+    CSC_HIP(hipMemcpyAsync(dx, x, sizeof(x), hipMemcpyHostToDevice, s));
+    CSC_TRY(csc_mlp_forward(params, dx, 1, dy, mws, mlp_ws(1), stream));
+    CSC_HIP(hipMemcpyAsync(y, dy, sizeof(y), hipMemcpyDeviceToHost, s));
+    CSC_HIP(hipStreamSynchronize(s));
+    learned_begin(S, mom, p, k, n_signals, c1, y);
+    return CSC_OK;
+  };
+  auto more = [&](uint32_t, const double* mom) -> bool {
+    const double mid = used == 0 ? 1.0 : 0.5 * (S.lo + S.hi);
+    const double cnt = count_from_moments(mid, p, mom);
     if (trace_out) {
       trace_out[2 * used] = mid;
       trace_out[2 * used + 1] = cnt;
     }
     ++used;
-    if (learned_update(S, mid, cnt, k)) {
-      *lambda_out = mid;
-      *steps_out = used;
-      return S.status;
+    if (used == 1) {
+      if (std::floor(cnt + 0.5) == (double)k) {
+        done = true;
+        lam = 1.0;
+        if (bracket_out) bracket_out[0] = bracket_out[1] = 1.0;
+        return false;
+      }
+      if ((st = network(mom, cnt)) != CSC_OK) return false;
+      if (bracket_out) {
+        bracket_out[0] = S.lo;
+        bracket_out[1] = S.hi;
+      }
+      return used < max_steps;
     }
+    if (learned_update(S, mid, cnt, k)) {
+      done = true;
+      lam = mid;
+      return false;
+    }
+    return used < max_steps;
+  };
+  CSC_TRY(count_passes(*g, n_signals, p, seed, 1, est, est_ws, s, more));
+  CSC_TRY(st);
+  *steps_out = used;
+  if (done) {
+    *lambda_out = lam;
+    return used == 1 ? CSC_OK : S.status;
   }
   *lambda_out = S.hi;
-  *steps_out = used;
   return S.status == CSC_OK ? CSC_W_BISECT_EXHAUSTED : S.status;
 }
