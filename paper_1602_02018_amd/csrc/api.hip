@@ -421,9 +421,11 @@ class SignalAhead {
 
 // One eigencount pass on the signals of pass t: drawn into c.T0 first, or
 // already in T0 (drawn ahead by the caller) when T0 is given.
+// `between` runs on the host after the pass is enqueued, before the wait.
 csc_status moments_pass(const csc_graph& g, const Layout& L, int p, uint64_t seed, uint32_t t,
                         const CountBuffers& c, double* mom_host, hipStream_t s,
-                        const float* T0 = nullptr) {
+                        const float* T0 = nullptr,
+                        const std::function<csc_status()>& between = nullptr) {
   const size_t nblocks = (size_t)L.np * tiles_for(L);
   if (!T0) CSC_HIP(launch_gaussian_panels(L, seed, t, CSC_STREAM_COUNT, c.T0, s));
   Pass b;
@@ -437,6 +439,7 @@ csc_status moments_pass(const csc_graph& g, const Layout& L, int p, uint64_t see
   CSC_HIP(launch_reduce(c.part, (int)nblocks, nraw, c.mom, s));
   std::vector<double> raw(nraw);
   CSC_HIP(hipMemcpyAsync(raw.data(), c.mom, nraw * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (between) CSC_TRY(between());
   CSC_HIP(hipStreamSynchronize(s));
   moments_from_raw(raw.data(), p, mom_host);
   return CSC_OK;
@@ -468,8 +471,11 @@ csc_status count_passes(const csc_graph& g, int n_signals, int p, uint64_t seed,
   for (uint32_t t = t0;; ++t) {
     const float* cur = blocks[(t - t0) & 1];
     CSC_TRY(ahead.wait());
-    CSC_TRY(ahead.draw(L, seed, t + 1, blocks[(t - t0 + 1) & 1]));
-    CSC_TRY(moments_pass(g, L, p, seed, t, c, mom.data(), s, ahead.on() ? cur : nullptr));
+    // pass t is enqueued first, then the next draw, so that the pass starts
+    // as early as possible
+    CSC_TRY(moments_pass(g, L, p, seed, t, c, mom.data(), s, ahead.on() ? cur : nullptr, [&] {
+      return ahead.draw(L, seed, t + 1, blocks[(t - t0 + 1) & 1]);
+    }));
     if (!more(t, mom.data())) return CSC_OK;
   }
 }

@@ -38,11 +38,6 @@ void clear_error();
     if (s_ != CSC_OK) return s_;                                                    \
   } while (0)
 
-// k-means++ seeding: the cumulative D^2 weights are summed in blocks of this
-// many points (a block's offset plus the running sum inside it), on the host
-// and on the GPU alike.
-constexpr int kSeedBlock = 32;
-
 // --------------------------------------------------- Philox4x64-10 -------
 // Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3"
 // (SC'11): ten rounds of two 64x64->128-bit products on a 4-word counter,

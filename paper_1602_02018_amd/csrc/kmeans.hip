@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "kmeans.hpp"
 
 namespace csc {
 namespace {

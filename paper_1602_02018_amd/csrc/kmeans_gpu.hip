@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "host.hpp"
+#include "kmeans.hpp"
 
 namespace csc {
 namespace {
