@@ -272,7 +272,11 @@ csc_status csc_eigencount(const csc_graph* g, double lambda, int32_t p, int32_t 
  * lambda_out, steps_out: host scalars.  trace_out: host[2*max_steps] receiving
  * (mid, count) of every tested point, or NULL.  moments_out: host[p+1]
  * receiving the moments of the first tested point, or NULL.
- * ws: csc_estimate_workspace_bytes(N, n_signals, p).  Synchronises.
+ * ws: csc_estimate_workspace_bytes(N, n_signals, p).  Synchronises.  The
+ * signals of test t + 1 are drawn into ws on a library-owned second stream
+ * while test t runs; events order it after the caller's earlier work on
+ * `stream` and make `stream` wait for it before returning, so the caller sees
+ * the usual stream order (the same holds for csc_estimate_lambda_k_learned).
  */
 /* One-pass form of the dichotomy (kernel polynomial method).  The count of
  * Sec. 4.3 written in the Chebyshev basis, count(lambda) = sum_m a_m(lambda)
