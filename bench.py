@@ -24,6 +24,7 @@ labels.  Prints one JSON line:
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -175,6 +176,14 @@ def cpu_baseline(gr, k, p, budget_s=30.0):
     }
 
 
+def quiet_gc():
+    """Collect once and move every object alive after set-up out of the
+    collector's reach, so that a full collection (tens of ms with torch
+    loaded) does not land inside a timed run."""
+    gc.collect()
+    gc.freeze()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +232,7 @@ def main():
     g = api.Graph(gr.row_ptr, gr.col, dev)
     torch.cuda.synchronize()
 
+    quiet_gc()
     for _ in range(args.warmup):
         api.run(g, k, d, args.seed, p=p)
     torch.cuda.synchronize()
@@ -431,6 +441,7 @@ def bench_batch(args, wl, dev):
     api.run_batched(G[:4], ks[:4], ds[:4], seeds[:4], p=p, mlp_params=mlp)  # warm-up
     api.run(G[0], ks[0], ds[0], seeds[0], p=p)
     torch.cuda.synchronize()
+    quiet_gc()
 
     def timed(fn):
         torch.cuda.synchronize()
