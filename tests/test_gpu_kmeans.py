@@ -33,6 +33,9 @@ def _blobs(seed, n, d, k, spread=0.3):
     (1, 5000, 8, 20, 3),      # more points than the LDS copy of the D^2 weights
     (2, 33, 5, 33, 5),        # k = n
     (4, 1024, 48, 64, 6),     # largest seeding with the points in registers
+    (10, 32, 6, 5, 4),        # one full block of the seeding sums
+    (11, 64, 6, 7, 4),        # two full blocks
+    (12, 1, 3, 1, 2),         # one point, one cluster
     (6, 1025, 49, 40, 4),     # just past it in both n and d
     (8, 700, 49, 30, 4),      # past it in d only
 ])

@@ -227,6 +227,13 @@ def test_bisection_exhaustion_and_bracket_miss(api, cfg1):
     assert res.status == _lib.CSC_W_BRACKET_MISS
     assert all(c > 10 for _, c in res.trace[:4])
     assert res.trace[4][0] == 1.0
+    # every test t drew the signals of sub-stream t, across the restart too
+    # (the next test's signals are drawn ahead while a test runs)
+    for t in (1, 4, 5, 6):
+        mid, cnt = res.trace[t - 1]
+        R = philox.gaussian_block(0, cfg1.n, n_c, t, philox.COUNT)
+        ref = eigencount.eigencount(_A(cfg1), mid, 50, R)
+        assert abs(cnt - ref) <= 1e-3 * (1 + abs(ref)), (t, cnt, ref)
     # a bracket holding lambda_k gives the same decisions as the oracle inside it
     res = api.estimate_lambda_k(g, 10, 50, n_c, 0, bracket=(0.25, 0.75))
     lam, steps, trace, ok = eigencount.estimate_lambda_k(_A(cfg1), 10, 50, n_c, 0, bracket=(0.25, 0.75))
