@@ -11,8 +11,9 @@ labels.  Prints one JSON line:
   Chebyshev step, random block and CG update in the step divided by the wall
   time of the step;
 * roofline: the dominant kernel of the step, the Chebyshev-step kernel with
-  the largest launches x time: the moment step of the eigencount passes at
-  width n_c (natural node order) or the Clenshaw step of the CG operator at
+  the largest launches x time: the moment step of the eigencount passes (the
+  dichotomy runs 4 tests side by side, width 4 x n_c rounded to a multiple of
+  4 each, natural node order) or the Clenshaw step of the CG operator at
   width k (graph in community order), each timed per launch with HIP events on
   the stream it runs on, against the MI355X HBM peak (8 TB/s); its HBM traffic
   comes from rocprofv3 FETCH_SIZE / WRITE_SIZE counters recorded in profiles/
@@ -40,9 +41,9 @@ KERNEL_SRC = [os.path.join(ROOT, "paper_1602_02018_amd", "csrc", f)
               for f in ("kernels.hip", "device.hpp", "kernels.hpp", "common.hpp")]
 # rocprofv3 counter summaries of the two candidate dominant kernels
 COUNTERS = {
-    "count": os.path.join(ROOT, "profiles", "cheb_step_count_sbm_N1e5_w24_counters.txt"),
+    "count": os.path.join(ROOT, "profiles", "cheb_step_count_sbm_N1e5_4x24_counters.txt"),
     "cg": os.path.join(ROOT, "profiles", "cheb_step_cg_sbm_N1e5_k100_counters.txt"),
-    "cl_count_step": os.path.join(ROOT, "profiles", "cheb_step_count_chunglu_N1e6_w28_counters.txt"),
+    "cl_count_step": os.path.join(ROOT, "profiles", "cheb_step_count_chunglu_N1e6_4x28_counters.txt"),
     "cl_filter_step": os.path.join(ROOT, "profiles", "cheb_step_filter_chunglu_N1e6_w56_counters.txt"),
     "cl_cg_step": os.path.join(ROOT, "profiles", "cheb_step_cg_chunglu_N1e6_k250_counters.txt"),
 }
@@ -274,14 +275,19 @@ def main():
     # candidate dominant kernels, per-launch times: the moment step of the
     # eigencount passes (width n_c, natural order) and the Clenshaw step of the
     # CG operator (width k, on the graph in the order the interpolation used)
+    # (the dichotomy runs `group` tests' passes side by side, each test's
+    # n_c columns rounded up to a multiple of 4)
+    group, count_w, count_kind = count_shape(api, n_c)
     cands = {}
     for which, w, order, kind, bkind, launches in (
-            ("count", n_c, None, 1, "mom", last.bisection.steps * moment_steps(p)),
+            ("count", count_w, None, count_kind, "mom",
+             -(-last.bisection.steps // group) * moment_steps(p)),
             ("cg", k, last.order, 3, "clen", int(last.interp.iters.max()) * p)):
         avg_s = step_time(api, gr, order, w, p, args.kernel_reps, dev, kind=kind)
         per_launch = step_bytes(N, nnz, w, bkind)
         achieved = per_launch / avg_s / 1e9
-        name = ("k_cheb_step<EPI_MOM> (moment step of the eigencount passes" if which == "count"
+        name = (f"k_cheb_step<EPI_MOM> (moment step of the eigencount passes, {group} tests of "
+                f"{n_c} signals side by side" if which == "count"
                 else "k_cheb_step<EPI_CLEN> (Clenshaw step of the CG operator pass")
         traffic = read_traffic(which)
         cands[which] = {
@@ -356,6 +362,18 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def count_shape(api, n_c):
+    """(group size, block width, measurement-hook kind) of the dichotomy's
+    moment step: `group` tests of n_c signals side by side, each rounded up to
+    a multiple of 4 columns (one test: width n_c, kind 1)."""
+    from paper_1602_02018_amd import _lib
+
+    group = api.get_tuning(_lib.TUNE_COUNT_GROUP)
+    if group <= 1:
+        return 1, n_c, 1
+    return group, group * (-(-n_c // 4) * 4), 4
+
+
 def step_time(api, gr, order, w, p, reps, dev, kind=3):
     """Average seconds per launch of the Chebyshev step (kind 3: Clenshaw) at
     width w, on the graph in `order` (None: as given), timed with HIP events on
@@ -406,7 +424,8 @@ def large_shapes(api, args, dev):
            "cg_iters_max": int(r.interp.iters.max()),
            "ari_vs_truth": round(float(adjusted_rand_index(r.labels.cpu().numpy(), gr.truth)), 4)}
     n_c = api.count_signals(N)
-    for name, w, order, kind, bkind in (("count_step", n_c, None, 1, "mom"),
+    group, count_w, count_kind = count_shape(api, n_c)
+    for name, w, order, kind, bkind in (("count_step", count_w, None, count_kind, "mom"),
                                         ("filter_step", d, None, 3, "clen"),
                                         ("cg_step", k, r.order, 3, "clen")):
         avg = step_time(api, gr, order, w, p, max(2, args.kernel_reps // 5), dev, kind=kind)

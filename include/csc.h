@@ -135,17 +135,25 @@ int32_t csc_get_filter_form(void);
  * CSC_TUNE_HIP_GRAPHS (0/1, default 1): the batched calls record their
  *   repeated passes (eigencount passes, CG iterations) once as a HIP graph
  *   and replay it; 0 launches every kernel directly.
- * csc_get_tuning returns the current value (-1 for an unknown key). * CSC_TUNE_ROW_SCHED (0/1/2, default 1): when the step kernels follow the
+ * CSC_TUNE_ROW_SCHED (0/1/2, default 1): when the step kernels follow the
  *   graph's row schedule (csc_graph.sched, when set): 0 never, 1 when a wave
  *   holds 8 rows or more (panel widths up to 32), 2 whenever a wave holds
  *   several rows.
+ * CSC_TUNE_COUNT_GROUP (1..4, default 4): the dichotomies
+ *   (csc_estimate_lambda_k, csc_estimate_lambda_k_learned) run this many
+ *   consecutive tests' eigencount passes as one wider pass (their signals do
+ *   not depend on the earlier counts; each test's moments are kept apart), so
+ *   a search computes up to this many - 1 passes it does not use; tested
+ *   points, counts and the result are those of one pass per test.
+ * csc_get_tuning returns the current value (-1 for an unknown key).
  */
 enum {
   CSC_TUNE_PANEL_WIDTH = 0,
   CSC_TUNE_XCD_ORDER = 1,
   CSC_TUNE_NONTEMPORAL = 2,
   CSC_TUNE_HIP_GRAPHS = 3,
-  CSC_TUNE_ROW_SCHED = 4
+  CSC_TUNE_ROW_SCHED = 4,
+  CSC_TUNE_COUNT_GROUP = 5
 };
 csc_status csc_set_tuning(int32_t key, int32_t value);
 int32_t csc_get_tuning(int32_t key);
@@ -621,7 +629,9 @@ csc_status csc_estimate_lambda_k_learned(const csc_graph* g, int32_t k, int32_t 
  * kind 0: T_{m+1} = -2 A T_m - T_{m-1} with Y += c T_{m+1} (feature and CG
  *         passes), kind 1: the same recurrence with the float64 moment
  *         epilogue (eigencount passes), kind 2: the last CG step (operator
- *         and per-column p^T A p partials).
+ *         and per-column p^T A p partials), kind 3: a Clenshaw step, kind 4:
+ *         the moment step of a group of CSC_TUNE_COUNT_GROUP eigencount tests
+ *         side by side (w must be that group size times a multiple of 4).
  * prepare != 0 first fills the block with a Gaussian block and zeroes the
  * other buffers (these launches precede the timed ones; call once with
  * steps = 0 and prepare = 1, then time calls with prepare = 0).

@@ -26,6 +26,7 @@ std::atomic<int> g_damping{CSC_DAMP_JACKSON};
 std::atomic<int> g_tune_nt{0};
 std::atomic<int> g_tune_graphs{1};
 std::atomic<int> g_tune_sched{1};
+std::atomic<int> g_tune_group{4};
 }  // namespace
 
 void set_error(const std::string& msg) { g_error = msg; }
@@ -41,6 +42,7 @@ Tuning tuning() {
 }
 
 int use_hip_graphs() { return g_tune_graphs.load(); }
+int count_group() { return g_tune_group.load(); }
 bool xcd_batched() { return g_tune_xcd.load() != 0; }
 
 // Stream used only to record HIP graphs (kernels are captured, never run on
@@ -199,6 +201,8 @@ struct Pass {
   int lds = 0;
   const float* mask = nullptr;
   float gamma = 0.f;
+  int mgroup = 1;  // EPI_MOM: passes side by side, mnc4 columns each
+  int mnc4 = 0;
 };
 
 }  // namespace
@@ -291,6 +295,9 @@ csc_status chebyshev_pass(const csc_graph& g, const Layout& L, const double* a, 
       sa.part = b.part + (size_t)(2 * m + 1) * nblocks;
       sa.part2 = b.part + (size_t)(2 * m + 2) * nblocks;
       sa.part0 = b.part;
+      sa.mgroup = b.mgroup;
+      sa.mnc4 = b.mnc4;
+      sa.mstride = (size_t)moment_raw(p) * nblocks;
     } else if (epi == EPI_CG) {
       e = last ? EPI_CG : EPI_Y;
       sa.part = b.part;
@@ -321,11 +328,11 @@ void moments_from_raw(const double* raw, int p, double* mom) {
     mom[m] = (m & 1) ? 2.0 * raw[m] - raw[1] : 2.0 * raw[m] - raw[0];
 }
 
-size_t count_bytes(const Layout& L, int p) {
+size_t count_bytes(const Layout& L, int p, int group) {
   const size_t nblocks = (size_t)L.np * tiles_for(L);
   size_t b = 4 * align_up(L.bytes());  // two signal blocks, two recurrence blocks
-  b += align_up((size_t)moment_raw(p) * nblocks * sizeof(double));
-  b += align_up((size_t)moment_raw(p) * sizeof(double));
+  b += align_up((size_t)group * moment_raw(p) * nblocks * sizeof(double));
+  b += align_up((size_t)group * moment_raw(p) * sizeof(double));
   return b + 256;
 }
 
@@ -362,15 +369,15 @@ struct CountBuffers {
   double* mom;
 };
 
-CountBuffers carve_count(Arena& ar, const Layout& L, int p) {
+CountBuffers carve_count(Arena& ar, const Layout& L, int p, int group = 1) {
   const size_t nblocks = (size_t)L.np * tiles_for(L);
   CountBuffers c;
   c.T0 = ar.take<float>(L.elems());
   c.T0n = ar.take<float>(L.elems());
   c.Ta = ar.take<float>(L.elems());
   c.Tb = ar.take<float>(L.elems());
-  c.part = ar.take<double>((size_t)moment_raw(p) * nblocks);
-  c.mom = ar.take<double>(moment_raw(p));
+  c.part = ar.take<double>((size_t)group * moment_raw(p) * nblocks);
+  c.mom = ar.take<double>((size_t)group * moment_raw(p));
   return c;
 }
 
@@ -380,6 +387,19 @@ CountBuffers carve_count(Arena& ar, const Layout& L, int p) {
 // that reads it and, when this object goes, for the last draw.  Off (draw()
 // does nothing and passes draw their own signals) without a side stream or
 // events.
+// How a count pass lays out its signals: one test (g == 1: n_signals
+// columns, drawn by launch_gaussian_panels) or g consecutive tests side by
+// side, nc4 columns each.
+struct CountGroup {
+  int g = 1, nc = 1, nc4 = 1;
+};
+
+hipError_t draw_count_signals(const Layout& L, const CountGroup& cg, uint64_t seed, uint32_t t,
+                              float* out, hipStream_t s) {
+  if (cg.g == 1) return launch_gaussian_panels(L, seed, t, CSC_STREAM_COUNT, out, s);
+  return launch_gaussian_group(L, seed, t, CSC_STREAM_COUNT, cg.nc, cg.nc4, out, s);
+}
+
 class SignalAhead {
  public:
   explicit SignalAhead(hipStream_t s) : s_(s), s2_(side_stream()) {
@@ -397,9 +417,9 @@ class SignalAhead {
   SignalAhead(const SignalAhead&) = delete;
   SignalAhead& operator=(const SignalAhead&) = delete;
   bool on() const { return s2_ != nullptr; }
-  csc_status draw(const Layout& L, uint64_t seed, uint32_t t, float* out) {
+  csc_status draw(const Layout& L, const CountGroup& cg, uint64_t seed, uint32_t t, float* out) {
     if (!s2_) return CSC_OK;
-    CSC_HIP(launch_gaussian_panels(L, seed, t, CSC_STREAM_COUNT, out, s2_));
+    CSC_HIP(draw_count_signals(L, cg, seed, t, out, s2_));
     CSC_HIP(hipEventRecord(drawn_, s2_));
     pending_ = true;
     return CSC_OK;
@@ -421,27 +441,33 @@ class SignalAhead {
 
 // One eigencount pass on the signals of pass t: drawn into c.T0 first, or
 // already in T0 (drawn ahead by the caller) when T0 is given.
-// `between` runs on the host after the pass is enqueued, before the wait.
+// With a group, the passes of tests t .. t + g - 1 at once, moments of test
+// t + j in mom_host[j (p + 1) ..].  `between` runs on the host after the pass
+// is enqueued, before the wait.
 csc_status moments_pass(const csc_graph& g, const Layout& L, int p, uint64_t seed, uint32_t t,
                         const CountBuffers& c, double* mom_host, hipStream_t s,
                         const float* T0 = nullptr,
-                        const std::function<csc_status()>& between = nullptr) {
+                        const std::function<csc_status()>& between = nullptr,
+                        const CountGroup& cg = CountGroup{}) {
   const size_t nblocks = (size_t)L.np * tiles_for(L);
-  if (!T0) CSC_HIP(launch_gaussian_panels(L, seed, t, CSC_STREAM_COUNT, c.T0, s));
+  if (!T0) CSC_HIP(draw_count_signals(L, cg, seed, t, c.T0, s));
   Pass b;
   b.T0 = T0 ? T0 : c.T0;
   b.Ta = c.Ta;
   b.Tb = c.Tb;
   b.part = c.part;
+  b.mgroup = cg.g;
+  b.mnc4 = cg.nc4;
   std::vector<double> zero(p + 1, 0.0);
   CSC_TRY(chebyshev_pass(g, L, zero.data(), p, EPI_MOM, b, s));
   const int nraw = moment_raw(p);
-  CSC_HIP(launch_reduce(c.part, (int)nblocks, nraw, c.mom, s));
-  std::vector<double> raw(nraw);
-  CSC_HIP(hipMemcpyAsync(raw.data(), c.mom, nraw * sizeof(double), hipMemcpyDeviceToHost, s));
+  CSC_HIP(launch_reduce(c.part, (int)nblocks, cg.g * nraw, c.mom, s));
+  std::vector<double> raw((size_t)cg.g * nraw);
+  CSC_HIP(hipMemcpyAsync(raw.data(), c.mom, raw.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   if (between) CSC_TRY(between());
   CSC_HIP(hipStreamSynchronize(s));
-  moments_from_raw(raw.data(), p, mom_host);
+  for (int j = 0; j < cg.g; ++j)
+    moments_from_raw(raw.data() + (size_t)j * nraw, p, mom_host + (size_t)j * (p + 1));
   return CSC_OK;
 }
 
@@ -458,25 +484,32 @@ double count_from_moments(double lambda, int p, const double* mom) {
 csc_status count_passes(const csc_graph& g, int n_signals, int p, uint64_t seed, uint32_t t0,
                         void* ws, size_t ws_bytes, hipStream_t s,
                         const std::function<bool(uint32_t, const double*)>& more) {
-  const Layout L = make_layout(g.n, n_signals, choose_panel_width(g.n, n_signals, g.nnz));
-  CSC_TRY(check_ws(ws, ws_bytes, count_bytes(L, p)));
+  CountGroup cg;
+  cg.g = count_group();
+  cg.nc = n_signals;
+  cg.nc4 = cg.g > 1 ? round4(n_signals) : n_signals;
+  const int w = cg.g * cg.nc4;
+  const Layout L = make_layout(g.n, w, choose_panel_width(g.n, w, g.nnz));
+  CSC_TRY(check_ws(ws, ws_bytes, count_bytes(L, p, cg.g)));
   Arena ar(ws, ws_bytes);
-  const CountBuffers c = carve_count(ar, L, p);
-  // the signals of pass t + 1 are drawn on a second stream while pass t runs
-  // (they do not depend on its count); the two signal blocks alternate
+  const CountBuffers c = carve_count(ar, L, p, cg.g);
+  // the signals of the next group of tests are drawn on a second stream
+  // while the current group runs (they do not depend on its counts); the two
+  // signal blocks alternate
   SignalAhead ahead(s);
   float* blocks[2] = {c.T0, c.T0n};
-  CSC_TRY(ahead.draw(L, seed, t0, blocks[0]));
-  std::vector<double> mom(p + 1);
-  for (uint32_t t = t0;; ++t) {
-    const float* cur = blocks[(t - t0) & 1];
+  CSC_TRY(ahead.draw(L, cg, seed, t0, blocks[0]));
+  std::vector<double> mom((size_t)cg.g * (p + 1));
+  for (uint32_t t = t0, k = 0;; t += (uint32_t)cg.g, ++k) {
+    const float* cur = blocks[k & 1];
     CSC_TRY(ahead.wait());
-    // pass t is enqueued first, then the next draw, so that the pass starts
-    // as early as possible
-    CSC_TRY(moments_pass(g, L, p, seed, t, c, mom.data(), s, ahead.on() ? cur : nullptr, [&] {
-      return ahead.draw(L, seed, t + 1, blocks[(t - t0 + 1) & 1]);
-    }));
-    if (!more(t, mom.data())) return CSC_OK;
+    // the group is enqueued first, then the next draw, so that it starts as
+    // early as possible
+    CSC_TRY(moments_pass(g, L, p, seed, t, c, mom.data(), s, ahead.on() ? cur : nullptr,
+                         [&] { return ahead.draw(L, cg, seed, t + cg.g, blocks[(k + 1) & 1]); },
+                         cg));
+    for (int j = 0; j < cg.g; ++j)
+      if (!more(t + (uint32_t)j, mom.data() + (size_t)j * (p + 1))) return CSC_OK;
   }
 }
 
@@ -542,6 +575,10 @@ extern "C" csc_status csc_set_tuning(int32_t key, int32_t value) {
       CSC_REQUIRE(value >= 0 && value <= 2, "value must be 0, 1 or 2");
       g_tune_sched.store(value);
       return CSC_OK;
+    case CSC_TUNE_COUNT_GROUP:
+      CSC_REQUIRE(value >= 1 && value <= kMaxCountGroup, "value must lie in 1..4");
+      g_tune_group.store(value);
+      return CSC_OK;
     default:
       CSC_REQUIRE(false, "unknown tuning key");
   }
@@ -554,6 +591,7 @@ extern "C" int32_t csc_get_tuning(int32_t key) {
     case CSC_TUNE_NONTEMPORAL: return g_tune_nt.load();
     case CSC_TUNE_HIP_GRAPHS: return g_tune_graphs.load();
     case CSC_TUNE_ROW_SCHED: return g_tune_sched.load();
+    case CSC_TUNE_COUNT_GROUP: return g_tune_group.load();
     default: return -1;
   }
 }
@@ -691,7 +729,11 @@ extern "C" csc_status csc_filter(const csc_graph* g, double lambda_c, int32_t p,
 
 extern "C" size_t csc_estimate_workspace_bytes(int32_t n, int32_t n_signals, int32_t p) {
   if (n < 1 || n_signals < 1 || p < 1) return 0;
-  return max_over_widths(n, n_signals, [p](const Layout& L) { return count_bytes(L, p); });
+  size_t b = max_over_widths(n, n_signals, [p](const Layout& L) { return count_bytes(L, p); });
+  for (int g = 2; g <= kMaxCountGroup; ++g)  // grouped dichotomy passes
+    b = std::max(b, max_over_widths(n, g * round4(n_signals),
+                                    [p, g](const Layout& L) { return count_bytes(L, p, g); }));
+  return b;
 }
 
 extern "C" csc_status csc_eigencount(const csc_graph* g, double lambda, int32_t p,
@@ -1311,7 +1353,10 @@ extern "C" csc_status csc_cheb_steps(const csc_graph* g, int32_t w, int32_t kind
   clear_error();
   CSC_TRY(check_graph(g));
   CSC_REQUIRE(w >= 1 && steps >= 0, "need w >= 1 and steps >= 0");
-  CSC_REQUIRE(kind >= 0 && kind <= 3, "kind must be 0, 1, 2 or 3");
+  CSC_REQUIRE(kind >= 0 && kind <= 4, "kind must be 0, 1, 2, 3 or 4");
+  const int group = kind == 4 ? count_group() : 1;
+  CSC_REQUIRE(w % (4 * group) == 0 || kind != 4,
+              "kind 4 needs w = group size x a multiple of 4");
   const Layout L = make_layout(g->n, w, choose_panel_width(g->n, w, g->nnz));
   CSC_TRY(check_ws(ws, ws_bytes, steps_bytes(L)));
   hipStream_t s = as_stream(stream);
@@ -1346,8 +1391,13 @@ extern "C" csc_status csc_cheb_steps(const csc_graph* g, int32_t w, int32_t kind
   sa.part = part;
   sa.part2 = part;
   sa.part0 = part;
+  sa.mgroup = group;  // kind 4: pass j's partials at part + j * units (part holds pw >= 4 per unit)
+  sa.mnc4 = w / group;
+  sa.mstride = (size_t)L.np * tiles;
   apply_tuning(sa);
-  const int epi = kind == 0 ? EPI_Y : (kind == 1 ? EPI_MOM : (kind == 2 ? EPI_CG : EPI_CLEN));
+  const int epi = kind == 0 ? EPI_Y
+                  : (kind == 1 || kind == 4) ? EPI_MOM
+                  : (kind == 2 ? EPI_CG : EPI_CLEN);
   for (int m = 1; m <= steps; ++m) {
     // T_{m+1} from T_m (gathered) and T_{m-1}; buffers alternate as in a pass
     sa.Tm = (m & 1) ? Ta : Tb;

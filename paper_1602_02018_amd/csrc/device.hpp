@@ -277,15 +277,42 @@ __device__ inline void cheb_unit(const StepArgs& a, int u) {
       sq = dot4v(tn, tn);
       if (FIRST) s0 = dot4v(tm, tm);
     }
-    const double bx = block_sum(sx, sh);
-    if (threadIdx.x == 0) a.part[u] = bx;
-    __syncthreads();
-    const double bq = block_sum(sq, sh);
-    if (threadIdx.x == 0) a.part2[u] = bq;
-    if (FIRST) {
+    if (a.mgroup <= 1) {
+      const double bx = block_sum(sx, sh);
+      if (threadIdx.x == 0) a.part[u] = bx;
       __syncthreads();
-      const double b0 = block_sum(s0, sh);
-      if (threadIdx.x == 0) a.part0[u] = b0;
+      const double bq = block_sum(sq, sh);
+      if (threadIdx.x == 0) a.part2[u] = bq;
+      if (FIRST) {
+        __syncthreads();
+        const double b0 = block_sum(s0, sh);
+        if (threadIdx.x == 0) a.part0[u] = b0;
+      }
+    } else {
+      // one set of sums per test of the group: this lane's four columns lie
+      // in test (panel pw + 4 q) / mnc4 (lanes past the group's columns hold
+      // zeros); wave sums per test, then the four waves in a fixed order
+      __shared__ double shg[4][3 * kMaxCountGroup];
+      const int jl = (panel * a.L.pw + m.q * 4) / a.mnc4;
+      const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+      for (int j = 0; j < a.mgroup; ++j) {
+        const bool mine = jl == j;
+        const double wx = wave_sum(mine ? sx : 0.0);
+        const double wq = wave_sum(mine ? sq : 0.0);
+        const double w0 = FIRST ? wave_sum(mine ? s0 : 0.0) : 0.0;
+        if (lane == 0) {
+          shg[wave][3 * j] = wx;
+          shg[wave][3 * j + 1] = wq;
+          shg[wave][3 * j + 2] = w0;
+        }
+      }
+      __syncthreads();
+      const int e = threadIdx.x;
+      if (e < 3 * a.mgroup && (e % 3 < 2 || FIRST)) {
+        const double v = (shg[0][e] + shg[1][e]) + (shg[2][e] + shg[3][e]);
+        double* dst = e % 3 == 0 ? a.part : (e % 3 == 1 ? a.part2 : a.part0);
+        dst[(size_t)(e / 3) * a.mstride + u] = v;
+      }
     }
     __syncthreads();  // shared memory is reused by the next unit of a grid-stride loop
   } else if constexpr (EPI == EPI_CG) {

@@ -17,7 +17,7 @@ void apply_tuning(StepArgs& sa);
 // The row schedule the step kernels follow on g at layout L (or NULL).
 const int* step_sched(const csc_graph& g, const Layout& L);
 size_t filter_bytes(const Layout& L);
-size_t count_bytes(const Layout& L, int p);
+size_t count_bytes(const Layout& L, int p, int group = 1);
 // Eigencount passes t0, t0 + 1, ... (the dichotomy of Sec. 4.3) on a count
 // workspace (count_bytes): after each pass, more(t, moments) says whether
 // another follows.  Pass t + 1's signals are drawn on a second stream while
@@ -32,6 +32,10 @@ csc_status count_passes(const csc_graph& g, int n_signals, int p, uint64_t seed,
 // mu_{2j} = 2 <T_j, T_j> - mu_0 and mu_{2j+1} = 2 <T_j, T_{j+1}> - mu_1.
 int moment_steps(int p);
 int moment_raw(int p);
+// Eigencount passes run together by the dichotomies (at most kMaxCountGroup,
+// each n_signals columns rounded up to a multiple of 4).
+int count_group();
+inline int round4(int x) { return (x + 3) / 4 * 4; }
 void moments_from_raw(const double* raw, int p, double* mom);
 size_t interp_bytes(const Layout& L);
 int use_hip_graphs();

@@ -109,6 +109,20 @@ __global__ void k_gaussian_panels(Layout L, uint64_t seed, uint32_t t, uint32_t 
     gaussian_elem(L, seed, t, sid, out, idx);
 }
 
+__global__ void k_gaussian_group(Layout L, uint64_t seed, uint32_t t, uint32_t sid, int nc,
+                                 int nc4, float* out) {
+  const size_t total = L.elems(), pe = L.panel_elems();
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t q = idx / pe, rem = idx - q * pe;
+    const int i = (int)(rem / L.pw), c = (int)(rem - (size_t)i * L.pw);
+    const int cg = (int)q * L.pw + c, j = cg / nc4, cc = cg - j * nc4;
+    out[idx] = (cg < L.w && cc < nc)
+                   ? gauss_entry((uint64_t)i * nc + cc, t + (uint32_t)j, sid, seed, nc)
+                   : 0.f;
+  }
+}
+
 __global__ void k_gaussian_rows(int n_rows, int w, uint64_t seed, uint32_t t, uint32_t sid,
                                 float* R, int ld) {
   const size_t total = (size_t)n_rows * w;
@@ -347,6 +361,14 @@ hipError_t launch_gaussian_panels(const Layout& L, uint64_t seed, uint32_t t, ui
                                   float* out, hipStream_t s) {
   hipLaunchKernelGGL(k_gaussian_panels, dim3(grid_for(L.elems())), dim3(kBlock), 0, s, L, seed, t,
                      sid, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gaussian_group(const Layout& L, uint64_t seed, uint32_t t, uint32_t sid, int nc,
+                                 int nc4, float* out, hipStream_t s) {
+  if (nc < 1 || nc4 < nc || (nc4 & 3)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gaussian_group, dim3(grid_for(L.elems())), dim3(kBlock), 0, s, L, seed, t,
+                     sid, nc, nc4, out);
   return hipGetLastError();
 }
 

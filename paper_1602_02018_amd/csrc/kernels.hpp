@@ -19,6 +19,9 @@ enum Epi : int {
   EPI_CLEN_CG = 6,  // final step of the CG operator, as EPI_CG
 };
 
+// Eigencount tests whose passes one EPI_MOM launch may carry side by side.
+constexpr int kMaxCountGroup = 4;
+
 struct StepArgs {
   Layout L;
   int tiles = 0;  // row tiles per panel
@@ -43,6 +46,12 @@ struct StepArgs {
   int xcd = 0;                   // XCD-aware work-unit order
   int nt = 0;                    // non-temporal loads/stores for streamed blocks
   const int* live = nullptr;     // batched launches: skip the graph when *live == 0
+  // EPI_MOM over a group of mgroup eigencount passes side by side (pass j in
+  // columns [j mnc4, (j + 1) mnc4), mnc4 a multiple of 4): pass j's partial
+  // sums go to part / part2 / part0 + j mstride
+  int mgroup = 1;
+  int mnc4 = 0;
+  size_t mstride = 0;
 };
 
 // ------------------------------------------------------- batched launches --
@@ -156,6 +165,12 @@ hipError_t launch_check_csr(int n, int nnz, const int* row_ptr, const int* col, 
                             hipStream_t s);
 
 // Random blocks.
+// The signals of passes t, t + 1, ..., t + G - 1 (each an n x nc block of
+// sub-stream t + j, exactly as launch_gaussian_panels draws it) side by side:
+// pass j in columns [j nc4, j nc4 + nc) of the G nc4-column layout L, the
+// other columns zero.
+hipError_t launch_gaussian_group(const Layout& L, uint64_t seed, uint32_t t, uint32_t stream_id,
+                                 int nc, int nc4, float* out, hipStream_t s);
 hipError_t launch_gaussian_panels(const Layout& L, uint64_t seed, uint32_t t, uint32_t stream_id,
                                   float* out, hipStream_t s);
 hipError_t launch_gaussian_rows(int n_rows, int w, uint64_t seed, uint32_t t, uint32_t stream_id,

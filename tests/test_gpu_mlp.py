@@ -7,6 +7,7 @@ import pytest
 import torch
 
 import synth
+from paper_1602_02018_amd import _lib
 from oracle import mlp as omlp
 
 pytestmark = pytest.mark.gpu
@@ -91,10 +92,16 @@ def test_learned_batched_matches_single(api):
     ncs = [api.count_signals(g.n) for g in gs]
     res = api.estimate_lambda_k_batched(G, ks, 50, ncs, [5, 6, 7], mlp_params=params)
     for i, g in enumerate(G):
-        ref = api.estimate_lambda_k_learned(g, ks[i], 50, ncs[i], 5 + i, params)
+        # the batched dichotomy runs one eigencount pass per test: compare with
+        # the single call's one-pass-per-test form, which it equals bit for bit
+        api.set_tuning(_lib.TUNE_COUNT_GROUP, 1)
+        try:
+            ref = api.estimate_lambda_k_learned(g, ks[i], 50, ncs[i], 5 + i, params)
+            plain = api.estimate_lambda_k(g, ks[i], 50, ncs[i], 5 + i)
+        finally:
+            api.set_tuning(_lib.TUNE_COUNT_GROUP, 4)
         assert (res[i].lam, res[i].steps, res[i].status) == (ref.lam, ref.steps, ref.status)
         assert [tuple(t) for t in res[i].trace] == [tuple(t) for t in ref.trace]
         # the first pass is the plain dichotomy's first test
-        plain = api.estimate_lambda_k(g, ks[i], 50, ncs[i], 5 + i)
         assert ref.trace[0] == plain.trace[0]
         assert abs(round(ref.trace[-1][1]) - ks[i]) == 0 or ref.status != 0
