@@ -282,7 +282,8 @@ csc_status chebyshev_pass(const csc_graph& g, const Layout& L, const double* a, 
     }
     return CSC_OK;
   }
-  const int steps = epi == EPI_MOM ? moment_steps(p) : p;
+  if (epi == EPI_MOM && b.mgroup > 1) epi = EPI_MOMG;
+  const int steps = (epi == EPI_MOM || epi == EPI_MOMG) ? moment_steps(p) : p;
   for (int m = 0; m < steps; ++m) {  // step m produces T_{m+1}
     const bool first = m == 0, last = m + 1 == steps;
     sa.Tm = first ? b.T0 : ((m & 1) ? b.Ta : b.Tb);
@@ -291,7 +292,7 @@ csc_status chebyshev_pass(const csc_graph& g, const Layout& L, const double* a, 
     sa.c0 = (float)a[0];
     sa.c1 = (float)a[m + 1];
     int e = epi;
-    if (epi == EPI_MOM) {
+    if (epi == EPI_MOM || epi == EPI_MOMG) {
       sa.part = b.part + (size_t)(2 * m + 1) * nblocks;
       sa.part2 = b.part + (size_t)(2 * m + 2) * nblocks;
       sa.part0 = b.part;
@@ -1395,8 +1396,9 @@ extern "C" csc_status csc_cheb_steps(const csc_graph* g, int32_t w, int32_t kind
   sa.mnc4 = w / group;
   sa.mstride = (size_t)L.np * tiles;
   apply_tuning(sa);
-  const int epi = kind == 0 ? EPI_Y
-                  : (kind == 1 || kind == 4) ? EPI_MOM
+  const int epi = kind == 0   ? EPI_Y
+                  : kind == 1 ? EPI_MOM
+                  : kind == 4 ? (group > 1 ? EPI_MOMG : EPI_MOM)
                   : (kind == 2 ? EPI_CG : EPI_CLEN);
   for (int m = 1; m <= steps; ++m) {
     // T_{m+1} from T_m (gathered) and T_{m-1}; buffers alternate as in a pass

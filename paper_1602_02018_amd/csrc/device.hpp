@@ -208,7 +208,7 @@ __device__ inline void clen_unit(const StepArgs& a, int u) {
 
 template <int EPI, bool FIRST, bool LAST>
 __device__ inline void cheb_unit(const StepArgs& a, int u) {
-  if constexpr (EPI >= EPI_CLEN) {
+  if constexpr (EPI >= EPI_CLEN && EPI <= EPI_CLEN_CG) {
     clen_unit<EPI, !FIRST>(a, u);
     return;
   }
@@ -277,21 +277,30 @@ __device__ inline void cheb_unit(const StepArgs& a, int u) {
       sq = dot4v(tn, tn);
       if (FIRST) s0 = dot4v(tm, tm);
     }
-    if (a.mgroup <= 1) {
-      const double bx = block_sum(sx, sh);
-      if (threadIdx.x == 0) a.part[u] = bx;
+    const double bx = block_sum(sx, sh);
+    if (threadIdx.x == 0) a.part[u] = bx;
+    __syncthreads();
+    const double bq = block_sum(sq, sh);
+    if (threadIdx.x == 0) a.part2[u] = bq;
+    if (FIRST) {
       __syncthreads();
-      const double bq = block_sum(sq, sh);
-      if (threadIdx.x == 0) a.part2[u] = bq;
-      if (FIRST) {
-        __syncthreads();
-        const double b0 = block_sum(s0, sh);
-        if (threadIdx.x == 0) a.part0[u] = b0;
-      }
-    } else {
-      // one set of sums per test of the group: this lane's four columns lie
-      // in test (panel pw + 4 q) / mnc4 (lanes past the group's columns hold
-      // zeros); wave sums per test, then the four waves in a fixed order
+      const double b0 = block_sum(s0, sh);
+      if (threadIdx.x == 0) a.part0[u] = b0;
+    }
+    __syncthreads();  // shared memory is reused by the next unit of a grid-stride loop
+  } else if constexpr (EPI == EPI_MOMG) {
+    // the same products for a group of eigencount tests side by side, one set
+    // of sums per test: this lane's four columns lie in test
+    // (panel pw + 4 q) / mnc4 (lanes past the group's columns hold zeros);
+    // wave sums per test, then the four waves in a fixed order
+    double sx = 0.0, sq = 0.0, s0 = 0.0;
+    if (valid) {
+      const v4f tm = FIRST ? x0 : ld4(a.Tm, o4, nt);
+      sx = dot4v(tm, tn);
+      sq = dot4v(tn, tn);
+      if (FIRST) s0 = dot4v(tm, tm);
+    }
+    {
       __shared__ double shg[4][3 * kMaxCountGroup];
       const int jl = (panel * a.L.pw + m.q * 4) / a.mnc4;
       const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;

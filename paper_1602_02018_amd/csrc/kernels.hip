@@ -35,6 +35,12 @@ hipError_t launch_step(const StepArgs& a, int epi, bool first, bool last, hipStr
       if (first) { if (last) CSC_STEP(EPI_MOM, true, true); else CSC_STEP(EPI_MOM, true, false); }
       else { if (last) CSC_STEP(EPI_MOM, false, true); else CSC_STEP(EPI_MOM, false, false); }
       break;
+    case EPI_MOMG:
+      if (a.mgroup < 2 || a.mgroup > kMaxCountGroup || a.mnc4 < 4 || (a.mnc4 & 3))
+        return hipErrorInvalidValue;
+      if (first) { if (last) CSC_STEP(EPI_MOMG, true, true); else CSC_STEP(EPI_MOMG, true, false); }
+      else { if (last) CSC_STEP(EPI_MOMG, false, true); else CSC_STEP(EPI_MOMG, false, false); }
+      break;
     case EPI_YS:
       if (first) { if (last) CSC_STEP(EPI_YS, true, true); else CSC_STEP(EPI_YS, true, false); }
       else { if (last) CSC_STEP(EPI_YS, false, true); else CSC_STEP(EPI_YS, false, false); }

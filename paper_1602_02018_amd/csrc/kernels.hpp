@@ -17,9 +17,10 @@ enum Epi : int {
   EPI_CLEN = 4,     // intermediate b_m
   EPI_CLEN_Y = 5,   // final step: Y = h~(L) R
   EPI_CLEN_CG = 6,  // final step of the CG operator, as EPI_CG
+  EPI_MOMG = 7,     // EPI_MOM for a group of eigencount tests side by side (mgroup > 1)
 };
 
-// Eigencount tests whose passes one EPI_MOM launch may carry side by side.
+// Eigencount tests whose passes one EPI_MOMG launch may carry side by side.
 constexpr int kMaxCountGroup = 4;
 
 struct StepArgs {
@@ -46,9 +47,9 @@ struct StepArgs {
   int xcd = 0;                   // XCD-aware work-unit order
   int nt = 0;                    // non-temporal loads/stores for streamed blocks
   const int* live = nullptr;     // batched launches: skip the graph when *live == 0
-  // EPI_MOM over a group of mgroup eigencount passes side by side (pass j in
-  // columns [j mnc4, (j + 1) mnc4), mnc4 a multiple of 4): pass j's partial
-  // sums go to part / part2 / part0 + j mstride
+  // EPI_MOMG: mgroup eigencount passes side by side (pass j in columns
+  // [j mnc4, (j + 1) mnc4), mnc4 a multiple of 4); pass j's partial sums go
+  // to part / part2 / part0 + j mstride
   int mgroup = 1;
   int mnc4 = 0;
   size_t mstride = 0;
