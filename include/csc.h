@@ -145,6 +145,11 @@ int32_t csc_get_filter_form(void);
  *   not depend on the earlier counts; each test's moments are kept apart), so
  *   a search computes up to this many - 1 passes it does not use; tested
  *   points, counts and the result are those of one pass per test.
+ * CSC_TUNE_BATCH_COUNT_GROUP (1..4, default 1): the same for the batched
+ *   dichotomy (csc_estimate_lambda_k_batched); a batch already fills the GPU
+ *   with one test per graph per pass, so by default no passes are computed
+ *   ahead there.  With equal group sizes the batched and the single calls
+ *   give the same results bit for bit.
  * csc_get_tuning returns the current value (-1 for an unknown key).
  */
 enum {
@@ -153,7 +158,8 @@ enum {
   CSC_TUNE_NONTEMPORAL = 2,
   CSC_TUNE_HIP_GRAPHS = 3,
   CSC_TUNE_ROW_SCHED = 4,
-  CSC_TUNE_COUNT_GROUP = 5
+  CSC_TUNE_COUNT_GROUP = 5,
+  CSC_TUNE_BATCH_COUNT_GROUP = 6
 };
 csc_status csc_set_tuning(int32_t key, int32_t value);
 int32_t csc_get_tuning(int32_t key);

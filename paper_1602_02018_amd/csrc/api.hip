@@ -27,6 +27,7 @@ std::atomic<int> g_tune_nt{0};
 std::atomic<int> g_tune_graphs{1};
 std::atomic<int> g_tune_sched{1};
 std::atomic<int> g_tune_group{4};
+std::atomic<int> g_tune_bgroup{1};
 }  // namespace
 
 void set_error(const std::string& msg) { g_error = msg; }
@@ -43,6 +44,7 @@ Tuning tuning() {
 
 int use_hip_graphs() { return g_tune_graphs.load(); }
 int count_group() { return g_tune_group.load(); }
+int batch_count_group() { return g_tune_bgroup.load(); }
 bool xcd_batched() { return g_tune_xcd.load() != 0; }
 
 // Stream used only to record HIP graphs (kernels are captured, never run on
@@ -580,6 +582,10 @@ extern "C" csc_status csc_set_tuning(int32_t key, int32_t value) {
       CSC_REQUIRE(value >= 1 && value <= kMaxCountGroup, "value must lie in 1..4");
       g_tune_group.store(value);
       return CSC_OK;
+    case CSC_TUNE_BATCH_COUNT_GROUP:
+      CSC_REQUIRE(value >= 1 && value <= kMaxCountGroup, "value must lie in 1..4");
+      g_tune_bgroup.store(value);
+      return CSC_OK;
     default:
       CSC_REQUIRE(false, "unknown tuning key");
   }
@@ -593,6 +599,7 @@ extern "C" int32_t csc_get_tuning(int32_t key) {
     case CSC_TUNE_HIP_GRAPHS: return g_tune_graphs.load();
     case CSC_TUNE_ROW_SCHED: return g_tune_sched.load();
     case CSC_TUNE_COUNT_GROUP: return g_tune_group.load();
+    case CSC_TUNE_BATCH_COUNT_GROUP: return g_tune_bgroup.load();
     default: return -1;
   }
 }

@@ -157,6 +157,10 @@ size_t max_elems(int n, int w) {
 
 int elem_units(size_t elems) { return (int)((elems + kElemsPerUnit - 1) / kElemsPerUnit); }
 
+// Block width of a dichotomy pass carrying `group` tests of nc signals each
+// (rounded up to a multiple of 4 when several share the pass).
+int count_width(int nc, int group) { return group > 1 ? group * round4(nc) : nc; }
+
 csc_status check_graphs(const csc_graph* graphs, int G) {
   CSC_REQUIRE(graphs != nullptr && G >= 1, "need at least one graph");
   for (int g = 0; g < G; ++g) CSC_TRY(check_graph(&graphs[g]));
@@ -180,13 +184,23 @@ using namespace csc;
 extern "C" size_t csc_estimate_workspace_bytes_batched(const csc_graph* graphs, int32_t G,
                                                        const int32_t* n_signals, int32_t p) {
   if (!graphs || G < 1 || !n_signals || p < 1) return 0;
-  size_t b = desc_bytes(G, p) + align_up((size_t)G * moment_raw(p) * sizeof(double));
+  // every group size of the dichotomy's tests (1 .. kMaxCountGroup) fits
+  size_t b = desc_bytes(G, p) +
+             align_up((size_t)G * kMaxCountGroup * moment_raw(p) * sizeof(double));
   b += mlp_workspace(G) + align_up((size_t)G * 54 * sizeof(float)) + 1024;  // learned mode
-  std::vector<int> u(G), gu(G), rv(G, moment_raw(p));
+  std::vector<int> u(G), gu(G), rv(G, kMaxCountGroup * moment_raw(p));
   for (int g = 0; g < G; ++g) {
-    b += max_widths(graphs[g].n, n_signals[g], [p](const Layout& L) { return count_bytes(L, p); });
-    u[g] = (int)std::min<size_t>(max_units(graphs[g].n, n_signals[g]), 1u << 30);
-    gu[g] = (int)((max_elems(graphs[g].n, n_signals[g]) + kElemsPerUnit - 1) / kElemsPerUnit);
+    size_t cb = 0, mu = 0, me = 0;
+    for (int gs = 1; gs <= kMaxCountGroup; ++gs) {
+      const int w = count_width(n_signals[g], gs);
+      cb = std::max(cb, max_widths(graphs[g].n, w,
+                                   [p, gs](const Layout& L) { return count_bytes(L, p, gs); }));
+      mu = std::max(mu, max_units(graphs[g].n, w));
+      me = std::max(me, max_elems(graphs[g].n, w));
+    }
+    b += cb;
+    u[g] = (int)std::min<size_t>(mu, 1u << 30);
+    gu[g] = (int)((me + kElemsPerUnit - 1) / kElemsPerUnit);
   }
   return b + work_bytes(u) + work_bytes(gu) + work_bytes(rv);
 }
@@ -217,23 +231,26 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
   hipStream_t s = as_stream(stream);
   Arena ar(ws, ws_bytes);
 
+  // each round runs `gc` consecutive tests of every graph still searching in
+  // one pass (their signals side by side), as the single-graph dichotomy does
+  const int gc = batch_count_group();
   std::vector<Layout> L(G);
   const int msteps = moment_steps(p), nraw = moment_raw(p);
-  std::vector<int> tiles(G), units(G), gunits(G), rvec(G, nraw);
+  std::vector<int> tiles(G), units(G), gunits(G), rvec(G, gc * nraw);
   std::vector<float*> T0(G), Ta(G), Tb(G);
   std::vector<double*> part(G);
   for (int g = 0; g < G; ++g) {
-    L[g] = make_layout(graphs[g].n, n_signals[g],
-                       choose_panel_width(graphs[g].n, n_signals[g], graphs[g].nnz));
+    const int w = count_width(n_signals[g], gc);
+    L[g] = make_layout(graphs[g].n, w, choose_panel_width(graphs[g].n, w, graphs[g].nnz));
     tiles[g] = tiles_for(L[g]);
     units[g] = L[g].np * tiles[g];
     gunits[g] = elem_units(L[g].elems());
     T0[g] = ar.take<float>(L[g].elems());
     Ta[g] = ar.take<float>(L[g].elems());
     Tb[g] = ar.take<float>(L[g].elems());
-    part[g] = ar.take<double>((size_t)nraw * units[g]);
+    part[g] = ar.take<double>((size_t)gc * nraw * units[g]);
   }
-  double* mom = ar.take<double>((size_t)G * nraw);
+  double* mom = ar.take<double>((size_t)G * gc * nraw);
   StepArgs* d_steps = ar.take<StepArgs>((size_t)msteps * G);
   GaussItem* d_gauss = ar.take<GaussItem>(G);
   ReduceItem* d_red = ar.take<ReduceItem>(G);
@@ -274,16 +291,23 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
       a.part = part[g] + (size_t)(2 * m + 1) * units[g];
       a.part2 = part[g] + (size_t)(2 * m + 2) * units[g];
       a.part0 = part[g];
+      a.mgroup = gc;
+      a.mnc4 = gc > 1 ? round4(n_signals[g]) : n_signals[g];
+      a.mstride = (size_t)nraw * units[g];
     }
     h_red[g].part = part[g];
     h_red[g].len = units[g];
-    h_red[g].out = mom + (size_t)g * nraw;
+    h_red[g].out = mom + (size_t)g * gc * nraw;
     h_red[g].live = d_live + g;
     h_gauss[g].L = L[g];
     h_gauss[g].seed = seeds[g];
     h_gauss[g].sid = CSC_STREAM_COUNT;
     h_gauss[g].out = T0[g];
     h_gauss[g].live = d_live + g;
+    if (gc > 1) {
+      h_gauss[g].nc = n_signals[g];
+      h_gauss[g].nc4 = round4(n_signals[g]);
+    }
   }
   CSC_TRY(upload(d_steps, h_steps, s));
   CSC_TRY(upload(d_red, h_red, s));
@@ -294,8 +318,8 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
   auto pass = [&](hipStream_t st) -> csc_status {
     CSC_HIP(launch_gaussian_batched(d_gauss, w_gauss.table(), st));
     for (int m = 0; m < msteps; ++m)
-      CSC_HIP(launch_cheb_step_batched(d_steps + (size_t)m * G, w_step.table(), EPI_MOM, m == 0,
-                                       m + 1 == msteps, st));
+      CSC_HIP(launch_cheb_step_batched(d_steps + (size_t)m * G, w_step.table(),
+                                       gc > 1 ? EPI_MOMG : EPI_MOM, m == 0, m + 1 == msteps, st));
     CSC_HIP(launch_reduce_batched(d_red, w_red.table(), st));
     return CSC_OK;
   };
@@ -313,7 +337,7 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
       st[g].hi = brackets[2 * g + 1];
     }
   std::vector<int> live(G);
-  std::vector<double> hraw((size_t)G * nraw), hmom((size_t)G * (p + 1));
+  std::vector<double> hraw((size_t)G * gc * nraw), hmom((size_t)G * gc * (p + 1));
   std::vector<float> hx((size_t)G * 52, 0.f), hy((size_t)G * 2, 0.f);
   Captured cap;
   const int rounds = mlp_params ? max_steps : 2 * max_steps;
@@ -332,85 +356,94 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
                            s));
     CSC_HIP(hipStreamSynchronize(s));
     for (int g = 0; g < G; ++g)
-      if (live[g]) moments_from_raw(hraw.data() + (size_t)g * nraw, p, hmom.data() + (size_t)g * (p + 1));
-    bool need_mlp = false;
-    for (int g = 0; g < G; ++g) {
-      if (!live[g]) continue;
-      State& S = st[g];
-      const double* mg = hmom.data() + (size_t)g * (p + 1);
-      const double mid = (mlp_params && S.used > 0) ? 0.5 * (S.ls.lo + S.ls.hi) : 0.5 * (S.lo + S.hi);
-      const double cnt = count_from_moments(mid, p, mg);
-      if (S.used == 0 && moments_out)
-        std::memcpy(moments_out + (size_t)g * (p + 1), mg, (p + 1) * sizeof(double));
-      if (trace_out) {
-        trace_out[((size_t)g * 2 * max_steps + S.used) * 2] = mid;
-        trace_out[((size_t)g * 2 * max_steps + S.used) * 2 + 1] = cnt;
-      }
-      ++S.used;
-      ++S.t_in;
-      if (mlp_params) {
-        // learned mode: the first pass picks the half and feeds the network
-        if (S.used == 1) {
-          if (std::floor(cnt + 0.5) == (double)k[g]) {
+      if (live[g])
+        for (int j = 0; j < gc; ++j)
+          moments_from_raw(hraw.data() + ((size_t)g * gc + j) * nraw, p,
+                           hmom.data() + ((size_t)g * gc + j) * (p + 1));
+    // the round's tests one position at a time, every graph in turn (a graph
+    // that finishes leaves the rest of its group unused)
+    for (int j = 0; j < gc; ++j) {
+      bool need_mlp = false;
+      for (int g = 0; g < G; ++g) {
+        if (!live[g] || st[g].done) continue;
+        State& S = st[g];
+        const double* mg = hmom.data() + ((size_t)g * gc + j) * (p + 1);
+        const double mid = (mlp_params && S.used > 0) ? 0.5 * (S.ls.lo + S.ls.hi)
+                                                      : 0.5 * (S.lo + S.hi);
+        const double cnt = count_from_moments(mid, p, mg);
+        if (S.used == 0 && moments_out)
+          std::memcpy(moments_out + (size_t)g * (p + 1), mg, (p + 1) * sizeof(double));
+        if (trace_out) {
+          trace_out[((size_t)g * 2 * max_steps + S.used) * 2] = mid;
+          trace_out[((size_t)g * 2 * max_steps + S.used) * 2 + 1] = cnt;
+        }
+        ++S.used;
+        ++S.t_in;
+        if (mlp_params) {
+          // learned mode: the first pass picks the half and feeds the network
+          if (S.used == 1) {
+            if (std::floor(cnt + 0.5) == (double)k[g]) {
+              lambda_out[g] = mid;
+              status_out[g] = CSC_OK;
+              S.done = true;
+            } else {
+              learned_features(mg, graphs[g].n, k[g], hx.data() + (size_t)g * 52);
+              S.ls.half_lo = cnt;  // first count, consumed by learned_begin below
+              need_mlp = true;
+            }
+            continue;
+          }
+          if (learned_update(S.ls, mid, cnt, k[g])) {
             lambda_out[g] = mid;
-            status_out[g] = CSC_OK;
+            status_out[g] = S.ls.status;
             S.done = true;
-          } else {
-            learned_features(mg, graphs[g].n, k[g], hx.data() + (size_t)g * 52);
-            S.ls.half_lo = cnt;  // first count, consumed by learned_begin below
-            need_mlp = true;
+          } else if (S.used == max_steps) {
+            lambda_out[g] = S.ls.hi;
+            status_out[g] = S.ls.status == CSC_OK ? CSC_W_BISECT_EXHAUSTED : S.ls.status;
+            S.done = true;
           }
           continue;
         }
-        if (learned_update(S.ls, mid, cnt, k[g])) {
+        if (std::floor(cnt + 0.5) == (double)k[g]) {
           lambda_out[g] = mid;
-          status_out[g] = S.ls.status;
+          status_out[g] = S.missed ? CSC_W_BRACKET_MISS : CSC_OK;
           S.done = true;
-        } else if (S.used == max_steps) {
-          lambda_out[g] = S.ls.hi;
-          status_out[g] = S.ls.status == CSC_OK ? CSC_W_BISECT_EXHAUSTED : S.ls.status;
-          S.done = true;
+          continue;
         }
-        continue;
-      }
-      if (std::floor(cnt + 0.5) == (double)k[g]) {
-        lambda_out[g] = mid;
-        status_out[g] = S.missed ? CSC_W_BRACKET_MISS : CSC_OK;
-        S.done = true;
-        continue;
-      }
-      if (cnt < k[g]) {
-        S.lo = mid;
-        S.below = true;
-      } else {
-        S.hi = mid;
-        S.above = true;
-      }
-      if (S.t_in == max_steps) {
-        if (brackets && S.attempt == 0 && !(S.below && S.above)) {
-          S.missed = true;
-          S.attempt = 1;
-          S.t_in = 0;
-          S.lo = 0.0;
-          S.hi = 2.0;
+        if (cnt < k[g]) {
+          S.lo = mid;
+          S.below = true;
         } else {
-          lambda_out[g] = S.hi;
-          status_out[g] = S.missed ? CSC_W_BRACKET_MISS : CSC_W_BISECT_EXHAUSTED;
-          S.done = true;
+          S.hi = mid;
+          S.above = true;
+        }
+        if (S.t_in == max_steps) {
+          if (brackets && S.attempt == 0 && !(S.below && S.above)) {
+            S.missed = true;
+            S.attempt = 1;
+            S.t_in = 0;
+            S.lo = 0.0;
+            S.hi = 2.0;
+          } else {
+            lambda_out[g] = S.hi;
+            status_out[g] = S.missed ? CSC_W_BRACKET_MISS : CSC_W_BISECT_EXHAUSTED;
+            S.done = true;
+          }
         }
       }
-    }
-    if (need_mlp) {
-      CSC_TRY(upload(d_x, hx, s));
-      CSC_TRY(csc_mlp_forward(mlp_params, d_x, G, d_y, d_mws, mlp_workspace(G), stream));
-      CSC_HIP(hipMemcpyAsync(hy.data(), d_y, hy.size() * sizeof(float), hipMemcpyDeviceToHost, s));
-      CSC_HIP(hipStreamSynchronize(s));
-      for (int g = 0; g < G; ++g) {
-        State& S = st[g];
-        if (!live[g] || S.done || S.used != 1) continue;
-        const double c1 = S.ls.half_lo;
-        learned_begin(S.ls, hmom.data() + (size_t)g * (p + 1), p, k[g], n_signals[g], c1,
-                      hy.data() + (size_t)g * 2);
+      if (need_mlp) {
+        CSC_TRY(upload(d_x, hx, s));
+        CSC_TRY(csc_mlp_forward(mlp_params, d_x, G, d_y, d_mws, mlp_workspace(G), stream));
+        CSC_HIP(hipMemcpyAsync(hy.data(), d_y, hy.size() * sizeof(float),
+                               hipMemcpyDeviceToHost, s));
+        CSC_HIP(hipStreamSynchronize(s));
+        for (int g = 0; g < G; ++g) {
+          State& S = st[g];
+          if (!live[g] || S.done || S.used != 1) continue;
+          const double c1 = S.ls.half_lo;
+          learned_begin(S.ls, hmom.data() + ((size_t)g * gc + j) * (p + 1), p, k[g], n_signals[g],
+                        c1, hy.data() + (size_t)g * 2);
+        }
       }
     }
   }

@@ -30,7 +30,12 @@ __global__ __launch_bounds__(kBlock) void kb_gaussian(const GaussItem* items, co
   for (int u = w.u0; u < w.u0 + w.cnt; ++u) {
     const size_t base = (size_t)u * kElemsPerUnit;
     for (int e = threadIdx.x; e < kElemsPerUnit; e += kBlock)
-      if (base + e < total) gaussian_elem(it.L, it.seed, it.t, it.sid, it.out, base + e);
+      if (base + e < total) {
+        if (it.nc4 > 0)
+          gaussian_group_elem(it.L, it.seed, it.t, it.sid, it.nc, it.nc4, it.out, base + e);
+        else
+          gaussian_elem(it.L, it.seed, it.t, it.sid, it.out, base + e);
+      }
   }
 }
 
@@ -141,6 +146,10 @@ hipError_t launch_cheb_step_batched(const StepArgs* items, BTable t, int epi, bo
     case EPI_MOM:
       if (first) { if (last) CSC_BSTEP(EPI_MOM, true, true); else CSC_BSTEP(EPI_MOM, true, false); }
       else { if (last) CSC_BSTEP(EPI_MOM, false, true); else CSC_BSTEP(EPI_MOM, false, false); }
+      break;
+    case EPI_MOMG:
+      if (first) { if (last) CSC_BSTEP(EPI_MOMG, true, true); else CSC_BSTEP(EPI_MOMG, true, false); }
+      else { if (last) CSC_BSTEP(EPI_MOMG, false, true); else CSC_BSTEP(EPI_MOMG, false, false); }
       break;
     case EPI_YS:
       if (first) { if (last) CSC_BSTEP(EPI_YS, true, true); else CSC_BSTEP(EPI_YS, true, false); }

@@ -358,6 +358,19 @@ __device__ inline void gaussian_elem(const Layout& L, uint64_t seed, uint32_t t,
   out[idx] = cg < L.w ? gauss_entry((uint64_t)i * L.w + cg, t, sid, seed, L.w) : 0.f;
 }
 
+// Element idx of the signals of tests t, t + 1, ... side by side (test j in
+// columns [j nc4, j nc4 + nc), each drawn as the n x nc block of sub-stream
+// t + j), the other columns zero.
+__device__ inline void gaussian_group_elem(const Layout& L, uint64_t seed, uint32_t t, uint32_t sid,
+                                           int nc, int nc4, float* out, size_t idx) {
+  const size_t pe = L.panel_elems();
+  const size_t q = idx / pe, rem = idx - q * pe;
+  const int i = (int)(rem / L.pw), c = (int)(rem - (size_t)i * L.pw);
+  const int cg = (int)q * L.pw + c, j = cg / nc4, cc = cg - j * nc4;
+  out[idx] = (cg < L.w && cc < nc) ? gauss_entry((uint64_t)i * nc + cc, t + (uint32_t)j, sid, seed, nc)
+                                   : 0.f;
+}
+
 // ---------------------------------------------------------- reductions ---
 // out[0] = sum_t part[t], t < len, by one workgroup in a fixed order.
 __device__ inline void reduce_vec(const double* part, int len, double* out) {

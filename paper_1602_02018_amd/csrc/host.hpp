@@ -35,6 +35,7 @@ int moment_raw(int p);
 // Eigencount passes run together by the dichotomies (at most kMaxCountGroup,
 // each n_signals columns rounded up to a multiple of 4).
 int count_group();
+int batch_count_group();  // tests per pass of the batched dichotomy
 inline int round4(int x) { return (x + 3) / 4 * 4; }
 void moments_from_raw(const double* raw, int p, double* mom);
 size_t interp_bytes(const Layout& L);

@@ -117,16 +117,10 @@ __global__ void k_gaussian_panels(Layout L, uint64_t seed, uint32_t t, uint32_t 
 
 __global__ void k_gaussian_group(Layout L, uint64_t seed, uint32_t t, uint32_t sid, int nc,
                                  int nc4, float* out) {
-  const size_t total = L.elems(), pe = L.panel_elems();
+  const size_t total = L.elems();
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const size_t q = idx / pe, rem = idx - q * pe;
-    const int i = (int)(rem / L.pw), c = (int)(rem - (size_t)i * L.pw);
-    const int cg = (int)q * L.pw + c, j = cg / nc4, cc = cg - j * nc4;
-    out[idx] = (cg < L.w && cc < nc)
-                   ? gauss_entry((uint64_t)i * nc + cc, t + (uint32_t)j, sid, seed, nc)
-                   : 0.f;
-  }
+       idx += (size_t)gridDim.x * blockDim.x)
+    gaussian_group_elem(L, seed, t, sid, nc, nc4, out, idx);
 }
 
 __global__ void k_gaussian_rows(int n_rows, int w, uint64_t seed, uint32_t t, uint32_t sid,

@@ -75,6 +75,7 @@ struct GaussItem {
   uint32_t t = 0, sid = 0;
   float* out = nullptr;
   const int* live = nullptr;
+  int nc = 0, nc4 = 0;  // nc4 > 0: tests t, t + 1, ... side by side, nc4 columns each
 };
 
 // one item per graph; its units are its nvec vectors

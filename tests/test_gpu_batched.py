@@ -38,17 +38,17 @@ def _graphs(api, batch):
 
 
 @contextlib.contextmanager
-def _one_pass_per_test(api):
-    """The batched dichotomy runs one eigencount pass per test; the single
-    call equals it bit for bit with its grouped passes off (with them on the
-    decisions are the same and the counts agree to float64 grouping)."""
+def _count_group(api, size):
+    """Both dichotomies run `size` tests per eigencount pass."""
     from paper_1602_02018_amd import _lib
 
-    api.set_tuning(_lib.TUNE_COUNT_GROUP, 1)
+    api.set_tuning(_lib.TUNE_COUNT_GROUP, size)
+    api.set_tuning(_lib.TUNE_BATCH_COUNT_GROUP, size)
     try:
         yield
     finally:
         api.set_tuning(_lib.TUNE_COUNT_GROUP, 4)
+        api.set_tuning(_lib.TUNE_BATCH_COUNT_GROUP, 1)
 
 
 def _set_graphs(api, on):
@@ -58,7 +58,8 @@ def _set_graphs(api, on):
 
 
 @pytest.mark.parametrize("use_graphs", [1, 0])
-def test_batched_dichotomy_matches_single(api, batch, use_graphs):
+@pytest.mark.parametrize("group", [1, 4])
+def test_batched_dichotomy_matches_single(api, batch, use_graphs, group):
     _set_graphs(api, use_graphs)
     try:
         G = _graphs(api, batch)
@@ -66,10 +67,12 @@ def test_batched_dichotomy_matches_single(api, batch, use_graphs):
         ncs = [api.count_signals(g.n) for g in batch]
         seeds = list(range(10, 10 + len(batch)))
         for _ in range(2):  # two calls in a row
-            res = api.estimate_lambda_k_batched(G, ks, 50, ncs, seeds)
+            with _count_group(api, group):
+                res = api.estimate_lambda_k_batched(G, ks, 50, ncs, seeds)
+                refs = [api.estimate_lambda_k(g, ks[i], 50, ncs[i], seeds[i])
+                        for i, g in enumerate(G)]
             for i, g in enumerate(G):
-                with _one_pass_per_test(api):
-                    ref = api.estimate_lambda_k(g, ks[i], 50, ncs[i], seeds[i])
+                ref = refs[i]
                 assert res[i].lam == ref.lam and res[i].steps == ref.steps
                 assert res[i].status == ref.status
                 assert [tuple(t) for t in res[i].trace] == [tuple(t) for t in ref.trace]

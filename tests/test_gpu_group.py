@@ -93,3 +93,7 @@ def test_group_knob_range(api):
     assert api.get_tuning(_lib.TUNE_COUNT_GROUP) == 4
     assert lib.csc_set_tuning(_lib.TUNE_COUNT_GROUP, 0) == _lib.CSC_E_INVALID_ARG
     assert lib.csc_set_tuning(_lib.TUNE_COUNT_GROUP, 5) == _lib.CSC_E_INVALID_ARG
+    assert api.get_tuning(_lib.TUNE_BATCH_COUNT_GROUP) == 1
+    assert lib.csc_set_tuning(_lib.TUNE_BATCH_COUNT_GROUP, 0) == _lib.CSC_E_INVALID_ARG
+    assert lib.csc_set_tuning(_lib.TUNE_BATCH_COUNT_GROUP, 5) == _lib.CSC_E_INVALID_ARG
+    assert api.get_tuning(_lib.TUNE_BATCH_COUNT_GROUP) == 1

@@ -90,16 +90,21 @@ def test_learned_batched_matches_single(api):
     params = torch.tensor(learned.init_params(1), device="cuda")
     ks = [g.k for g in gs]
     ncs = [api.count_signals(g.n) for g in gs]
-    res = api.estimate_lambda_k_batched(G, ks, 50, ncs, [5, 6, 7], mlp_params=params)
-    for i, g in enumerate(G):
-        # the batched dichotomy runs one eigencount pass per test: compare with
-        # the single call's one-pass-per-test form, which it equals bit for bit
-        api.set_tuning(_lib.TUNE_COUNT_GROUP, 1)
+    for group in (1, 4):  # tests per eigencount pass, the same in both forms
+        api.set_tuning(_lib.TUNE_COUNT_GROUP, group)
+        api.set_tuning(_lib.TUNE_BATCH_COUNT_GROUP, group)
         try:
-            ref = api.estimate_lambda_k_learned(g, ks[i], 50, ncs[i], 5 + i, params)
-            plain = api.estimate_lambda_k(g, ks[i], 50, ncs[i], 5 + i)
+            res = api.estimate_lambda_k_batched(G, ks, 50, ncs, [5, 6, 7], mlp_params=params)
+            refs = [(api.estimate_lambda_k_learned(g, ks[i], 50, ncs[i], 5 + i, params),
+                     api.estimate_lambda_k(g, ks[i], 50, ncs[i], 5 + i)) for i, g in enumerate(G)]
         finally:
             api.set_tuning(_lib.TUNE_COUNT_GROUP, 4)
+            api.set_tuning(_lib.TUNE_BATCH_COUNT_GROUP, 1)
+        _check_learned_batched(res, refs, ks)
+
+
+def _check_learned_batched(res, refs, ks):
+    for i, (ref, plain) in enumerate(refs):
         assert (res[i].lam, res[i].steps, res[i].status) == (ref.lam, ref.steps, ref.status)
         assert [tuple(t) for t in res[i].trace] == [tuple(t) for t in ref.trace]
         # the first pass is the plain dichotomy's first test
