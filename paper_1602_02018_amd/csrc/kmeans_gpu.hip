@@ -148,6 +148,20 @@ __device__ VI block_reduce(VI x, VI* sh) {
   return out;
 }
 
+// Smallest v over the workgroup (sh: one int per wave): the seeding's pick
+// needs only an index, and this takes two barriers where the (value, index)
+// reduction takes four.
+__device__ inline int block_min(int v, int* sh) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  int m = sh[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = min(m, sh[w]);
+  __syncthreads();
+  return m;
+}
+
 __device__ inline int block_or(int v, int* sh) {
   __syncthreads();
   if (threadIdx.x == 0) *sh = 0;
@@ -225,6 +239,7 @@ __global__ __launch_bounds__(kKmBlock) void k_km_seed(const KmItem* items) {
   const KmItem t = items[blockIdx.x];
   const int n = t.n, d = t.d, k = t.k;
   __shared__ VI sh_vi[kKmBlock / 64];
+  __shared__ int sh_min[kKmBlock / 64];
   __shared__ double sh_cc[kCcLds];
 
   // ---- k-means++ seeding.  The D^2 weights and their running sums live in
@@ -290,10 +305,10 @@ __global__ __launch_bounds__(kKmBlock) void k_km_seed(const KmItem* items) {
       pick = min((int)floor(u * n), n - 1);
     } else {
       const double target = u * total;
-      VI x{0.0, n};
+      int first = n;
       for (int i = threadIdx.x; i < n; i += blockDim.x)
-        if (cum[i] > target && i < x.i) x.i = i;
-      pick = block_reduce<false>(x, sh_vi).i;
+        if (cum[i] > target && i < first) first = i;
+      pick = block_min(first, sh_min);
       if (pick >= n) {  // rounding left the target at the total: last point with mass
         VI z{0.0, n};   // n - 1 - i of the largest such i, under the lowest-index rule
         for (int i = threadIdx.x; i < n; i += blockDim.x)
