@@ -497,6 +497,10 @@ csc_status csc_gather_rows(const float* F, int64_t ldf, int32_t N, int32_t d, co
  * graphs still searching (and one batched network evaluation after the
  * first).  lambda_out, steps_out, status_out: host[G]; trace_out:
  * host[G][2*max_steps][2] or NULL; moments_out: host[G][p+1] or NULL.
+ * Its workspace size depends on CSC_TUNE_BATCH_COUNT_GROUP (a pass carries
+ * that many tests per graph): query it after setting the knob; a call whose
+ * workspace is smaller than the current setting needs returns
+ * CSC_E_INVALID_ARG.
  * Synchronises.
  */
 size_t csc_estimate_workspace_bytes_batched(const csc_graph* graphs, int32_t G,

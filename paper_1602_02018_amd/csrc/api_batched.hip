@@ -184,23 +184,16 @@ using namespace csc;
 extern "C" size_t csc_estimate_workspace_bytes_batched(const csc_graph* graphs, int32_t G,
                                                        const int32_t* n_signals, int32_t p) {
   if (!graphs || G < 1 || !n_signals || p < 1) return 0;
-  // every group size of the dichotomy's tests (1 .. kMaxCountGroup) fits
-  size_t b = desc_bytes(G, p) +
-             align_up((size_t)G * kMaxCountGroup * moment_raw(p) * sizeof(double));
+  // sized for the current number of tests per pass
+  const int gs = batch_count_group();
+  size_t b = desc_bytes(G, p) + align_up((size_t)G * gs * moment_raw(p) * sizeof(double));
   b += mlp_workspace(G) + align_up((size_t)G * 54 * sizeof(float)) + 1024;  // learned mode
-  std::vector<int> u(G), gu(G), rv(G, kMaxCountGroup * moment_raw(p));
+  std::vector<int> u(G), gu(G), rv(G, gs * moment_raw(p));
   for (int g = 0; g < G; ++g) {
-    size_t cb = 0, mu = 0, me = 0;
-    for (int gs = 1; gs <= kMaxCountGroup; ++gs) {
-      const int w = count_width(n_signals[g], gs);
-      cb = std::max(cb, max_widths(graphs[g].n, w,
-                                   [p, gs](const Layout& L) { return count_bytes(L, p, gs); }));
-      mu = std::max(mu, max_units(graphs[g].n, w));
-      me = std::max(me, max_elems(graphs[g].n, w));
-    }
-    b += cb;
-    u[g] = (int)std::min<size_t>(mu, 1u << 30);
-    gu[g] = (int)((me + kElemsPerUnit - 1) / kElemsPerUnit);
+    const int w = count_width(n_signals[g], gs);
+    b += max_widths(graphs[g].n, w, [p, gs](const Layout& L) { return count_bytes(L, p, gs); });
+    u[g] = (int)std::min<size_t>(max_units(graphs[g].n, w), 1u << 30);
+    gu[g] = (int)((max_elems(graphs[g].n, w) + kElemsPerUnit - 1) / kElemsPerUnit);
   }
   return b + work_bytes(u) + work_bytes(gu) + work_bytes(rv);
 }

@@ -81,6 +81,37 @@ def test_batched_dichotomy_matches_single(api, batch, use_graphs, group):
         _set_graphs(api, 1)
 
 
+def test_batched_dichotomy_workspace_follows_group_size(api, batch):
+    """The workspace is sized for the current tests per pass; a call given the
+    size for one test per pass after the knob went up is refused, unlaunched."""
+    from paper_1602_02018_amd import _lib
+
+    lib = _lib.lib()
+    G = _graphs(api, batch)
+    ga = api._graphs(G)
+    ns = np.ascontiguousarray([api.count_signals(g.n) for g in batch], dtype=np.int32)
+    ks = np.ascontiguousarray([g.k for g in batch], dtype=np.int32)
+    sd = np.arange(len(batch), dtype=np.uint64)
+    size = {}
+    try:
+        for gsize in (1, 4):
+            api.set_tuning(_lib.TUNE_BATCH_COUNT_GROUP, gsize)
+            size[gsize] = lib.csc_estimate_workspace_bytes_batched(
+                ga, len(G), ns.ctypes.data_as(_lib.pi), 50)
+        assert size[4] > size[1] > 0
+        ws = torch.empty(size[1], dtype=torch.uint8, device="cuda")
+        Gn = len(G)
+        lam, steps, status = np.zeros(Gn), np.zeros(Gn, np.int32), np.zeros(Gn, np.int32)
+        rc = lib.csc_estimate_lambda_k_batched(
+            ga, Gn, ks.ctypes.data_as(_lib.pi), 50, ns.ctypes.data_as(_lib.pi),
+            sd.ctypes.data_as(_lib.pu), 30, None, None, lam.ctypes.data_as(_lib.pd),
+            steps.ctypes.data_as(_lib.pi), None, None, status.ctypes.data_as(_lib.pi),
+            ws.data_ptr(), ws.numel(), None)
+        assert rc == _lib.CSC_E_INVALID_ARG
+    finally:
+        api.set_tuning(_lib.TUNE_BATCH_COUNT_GROUP, 1)
+
+
 def test_batched_dichotomy_with_brackets(api, batch):
     G = _graphs(api, batch)
     ks = [g.k for g in batch]
