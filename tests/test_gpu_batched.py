@@ -112,16 +112,23 @@ def test_batched_dichotomy_workspace_follows_group_size(api, batch):
         api.set_tuning(_lib.TUNE_BATCH_COUNT_GROUP, 1)
 
 
-def test_batched_dichotomy_with_brackets(api, batch):
+@pytest.mark.parametrize("group", [1, 4])
+def test_batched_dichotomy_with_brackets(api, batch, group):
+    """Missed brackets restart on [0, 2] (with 6 tests per attempt a restart
+    falls inside a group of 4); tested points and counts equal the single
+    call's at the same group size."""
     G = _graphs(api, batch)
     ks = [g.k for g in batch]
     ncs = [api.count_signals(g.n) for g in batch]
     seeds = [3] * len(batch)
     brackets = [(1.5, 2.0) if i % 2 else (0.0, 1.0) for i in range(len(batch))]
-    res = api.estimate_lambda_k_batched(G, ks, 50, ncs, seeds, max_steps=6, brackets=brackets)
-    for i, g in enumerate(G):
-        ref = api.estimate_lambda_k(g, ks[i], 50, ncs[i], seeds[i], max_steps=6, bracket=brackets[i])
+    with _count_group(api, group):
+        res = api.estimate_lambda_k_batched(G, ks, 50, ncs, seeds, max_steps=6, brackets=brackets)
+        refs = [api.estimate_lambda_k(g, ks[i], 50, ncs[i], seeds[i], max_steps=6,
+                                      bracket=brackets[i]) for i, g in enumerate(G)]
+    for i, ref in enumerate(refs):
         assert (res[i].lam, res[i].steps, res[i].status) == (ref.lam, ref.steps, ref.status)
+        assert [tuple(t) for t in res[i].trace] == [tuple(t) for t in ref.trace]
 
 
 def test_batched_features_match_single(api, batch):
