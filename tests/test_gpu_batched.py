@@ -112,6 +112,38 @@ def test_batched_dichotomy_workspace_follows_group_size(api, batch):
         api.set_tuning(_lib.TUNE_BATCH_COUNT_GROUP, 1)
 
 
+def _tiny_batch():
+    """Degenerate graphs (an isolated node, a 2-path, a 5-cycle, a 13-path)
+    beside one ordinary SBM, with their k."""
+    def path(N, cyc=False):
+        u = np.arange(N if cyc else N - 1)
+        return synth.csr_from_edges(N, u, (u + 1) % N)
+
+    tiny = [(synth.csr_from_edges(1, np.zeros(0, np.int64), np.zeros(0, np.int64)), 1),
+            (path(2), 2), (path(5, cyc=True), 2), (path(13), 3)]
+    sb = synth.sbm(700, 5, 12.0, 0.25 * synth.eps_critical(12.0, 5), seed=9)
+    return tiny + [((sb.row_ptr, sb.col), sb.k)]
+
+
+@pytest.mark.parametrize("group", [1, 4])
+def test_batched_dichotomy_tiny_graphs(api, group):
+    """Degenerate sizes in a batch: each graph's search equals its single call
+    at the same group size, bit for bit."""
+    items = _tiny_batch()
+    G = [api.Graph(rp, cl) for (rp, cl), _ in items]
+    ks = [k for _, k in items]
+    ns = [len(rp) - 1 for (rp, _), _ in items]
+    ncs = [api.count_signals(n) for n in ns]
+    seeds = list(range(20, 20 + len(items)))
+    with _count_group(api, group):
+        res = api.estimate_lambda_k_batched(G, ks, 50, ncs, seeds)
+        refs = [api.estimate_lambda_k(g, ks[i], 50, ncs[i], seeds[i]) for i, g in enumerate(G)]
+    for i, ref in enumerate(refs):
+        assert (res[i].lam, res[i].steps, res[i].status) == (ref.lam, ref.steps, ref.status)
+        assert [tuple(t) for t in res[i].trace] == [tuple(t) for t in ref.trace]
+        assert np.array_equal(res[i].moments, ref.moments)
+
+
 @pytest.mark.parametrize("group", [1, 4])
 def test_batched_dichotomy_with_brackets(api, batch, group):
     """Missed brackets restart on [0, 2] (with 6 tests per attempt a restart
