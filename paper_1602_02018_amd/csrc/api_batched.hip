@@ -181,11 +181,11 @@ size_t desc_bytes(int G, int p) {
 using namespace csc;
 
 // ------------------------------------------------------------ dichotomy ---
-extern "C" size_t csc_estimate_workspace_bytes_batched(const csc_graph* graphs, int32_t G,
-                                                       const int32_t* n_signals, int32_t p) {
-  if (!graphs || G < 1 || !n_signals || p < 1) return 0;
-  // sized for the current number of tests per pass
-  const int gs = batch_count_group();
+namespace csc {
+namespace {
+// Workspace of the batched dichotomy with gs tests per pass.
+size_t estimate_bytes_batched(const csc_graph* graphs, int G, const int32_t* n_signals, int p,
+                              int gs) {
   size_t b = desc_bytes(G, p) + align_up((size_t)G * gs * moment_raw(p) * sizeof(double));
   b += mlp_workspace(G) + align_up((size_t)G * 54 * sizeof(float)) + 1024;  // learned mode
   std::vector<int> u(G), gu(G), rv(G, gs * moment_raw(p));
@@ -196,6 +196,14 @@ extern "C" size_t csc_estimate_workspace_bytes_batched(const csc_graph* graphs, 
     gu[g] = (int)((max_elems(graphs[g].n, w) + kElemsPerUnit - 1) / kElemsPerUnit);
   }
   return b + work_bytes(u) + work_bytes(gu) + work_bytes(rv);
+}
+}  // namespace
+}  // namespace csc
+
+extern "C" size_t csc_estimate_workspace_bytes_batched(const csc_graph* graphs, int32_t G,
+                                                       const int32_t* n_signals, int32_t p) {
+  if (!graphs || G < 1 || !n_signals || p < 1) return 0;
+  return estimate_bytes_batched(graphs, G, n_signals, p, batch_count_group());
 }
 
 extern "C" csc_status csc_estimate_lambda_k_batched(
@@ -219,14 +227,14 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
                       brackets[2 * g] < brackets[2 * g + 1],
                   "brackets must satisfy 0 <= lo < hi <= 2");
   }
-  CSC_TRY(check_ws(ws, ws_bytes,
-                   csc_estimate_workspace_bytes_batched(graphs, G, n_signals, p)));
+  // each round runs `gc` consecutive tests of every graph still searching in
+  // one pass (their signals side by side), as the single-graph dichotomy does;
+  // the setting is read once, and the workspace is checked against it
+  const int gc = batch_count_group();
+  CSC_TRY(check_ws(ws, ws_bytes, estimate_bytes_batched(graphs, G, n_signals, p, gc)));
   hipStream_t s = as_stream(stream);
   Arena ar(ws, ws_bytes);
 
-  // each round runs `gc` consecutive tests of every graph still searching in
-  // one pass (their signals side by side), as the single-graph dichotomy does
-  const int gc = batch_count_group();
   std::vector<Layout> L(G);
   const int msteps = moment_steps(p), nraw = moment_raw(p);
   std::vector<int> tiles(G), units(G), gunits(G), rvec(G, gc * nraw);
