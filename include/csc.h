@@ -35,7 +35,11 @@
  *   z = sqrt(-2 ln u1) cos(2 pi u2) / sqrt(w), rounded to float32.
  *   Streams: COUNT = 1 (eigencount signals, t = dichotomy step), FEAT = 2
  *   (feature signals, t = 0), SAMPLE = 3 (sampling keys), KMEANS = 4.
- * Thread safety: calls are reentrant when they use distinct workspaces.
+ * Thread safety: calls are reentrant when they use distinct workspaces (the
+ *   batched calls take turns while recording a HIP graph on the library's
+ *   capture stream).  Tuning, damping and filter-form settings are
+ *   process-wide and read when a call starts; changing them while another
+ *   thread's call runs is not supported.
  */
 #ifndef CSC_H
 #define CSC_H
@@ -143,13 +147,17 @@ int32_t csc_get_filter_form(void);
  *   (csc_estimate_lambda_k, csc_estimate_lambda_k_learned) run this many
  *   consecutive tests' eigencount passes as one wider pass (their signals do
  *   not depend on the earlier counts; each test's moments are kept apart), so
- *   a search computes up to this many - 1 passes it does not use; tested
- *   points, counts and the result are those of one pass per test.
+ *   a search computes up to this many - 1 passes it does not use.  Each
+ *   test keeps its own signals, tested point and decision rule; its count
+ *   equals the count of one pass per test up to the order of the float64
+ *   moment sums (a wider pass groups them differently), so only a count
+ *   within that rounding of k - 1/2 or k + 1/2 can decide differently.
  * CSC_TUNE_BATCH_COUNT_GROUP (1..4, default 1): the same for the batched
  *   dichotomy (csc_estimate_lambda_k_batched); a batch already fills the GPU
  *   with one test per graph per pass, so by default no passes are computed
  *   ahead there.  With equal group sizes the batched and the single calls
- *   give the same results bit for bit.
+ *   give the same results bit for bit; at the defaults (4 and 1) their
+ *   counts agree up to the order of float64 sums, as above.
  * csc_get_tuning returns the current value (-1 for an unknown key).
  */
 enum {
@@ -189,7 +197,12 @@ void csc_autotune_clear(void);
  * row_ptr, col, w, val_out, dinv_sqrt_out: device.  w = NULL means W_ij = 1.
  * When `check` is non-zero the CSR is validated first (row_ptr monotone,
  * row_ptr[0] = 0, row_ptr[n] = nnz, columns in range) and CSC_E_GRAPH is
- * returned on failure; this synchronises the stream.
+ * returned on failure; this synchronises the stream.  check = 2 also
+ * requires the undirected graph of Sec. 2.1 without self-loops: no stored
+ * diagonal entry, columns strictly increasing in each row, and W symmetric
+ * (every stored (i, j) has a stored (j, i) of the same weight); without it a
+ * stored diagonal entry is accepted and its value set to 0, and symmetry is
+ * the caller's promise.
  */
 csc_status csc_laplacian_from_adjacency(int32_t n, int32_t nnz, const int32_t* row_ptr,
                                         const int32_t* col, const float* w, float* val_out,
@@ -283,8 +296,9 @@ csc_status csc_eigencount(const csc_graph* g, double lambda, int32_t p, int32_t 
  * tests whose counts all fell on one side of k (lambda_k lies outside the
  * bracket), it restarts from [0, 2] with the next sub-streams and returns
  * CSC_W_BRACKET_MISS (steps_out counts the tests of both searches).
- * lambda_out, steps_out: host scalars.  trace_out: host[2*max_steps] receiving
- * (mid, count) of every tested point, or NULL.  moments_out: host[p+1]
+ * lambda_out, steps_out: host scalars.  trace_out: host[4*max_steps] receiving
+ * (mid, count) of every tested point (up to 2*max_steps tests when a caller
+ * bracket misses), or NULL.  moments_out: host[p+1]
  * receiving the moments of the first tested point, or NULL.
  * ws: csc_estimate_workspace_bytes(N, n_signals, p).  Synchronises.  The
  * signals of test t + 1 are drawn into ws on a library-owned second stream
@@ -339,6 +353,24 @@ csc_status csc_kmeans_reduced(const float* F, int32_t n, int32_t d, int32_t ld, 
 csc_status csc_kmeans_reduced_f64(const double* F, int32_t n, int32_t d, int32_t ld, int32_t k,
                                   int32_t replicates, int32_t max_iter, uint64_t seed,
                                   int32_t* labels, double* inertia_out);
+
+/* The k-means++ seeding alone (the first phase of csc_kmeans_reduced /
+ * csc_kmeans_reduced_device, same draws and sums): picks[r*k + c] (host
+ * int32[replicates*k]) receives the index of the point chosen as centre c of
+ * replicate r.  The library forms the seeding's running sums of the D^2
+ * weights in blocks of 32 points (the block's offset plus the running sum
+ * inside it), which is the index-order prefix sum up to rounding, so a pick
+ * can differ from one made with the plain prefix sum only where u_c times
+ * the total lies within that rounding (at most 4 n 2^-53 of the total) of a
+ * running sum.  csc_kmeans_seeds works on host float64 F (n x d, leading
+ * dimension ld); csc_kmeans_seeds_device on device float32 F with the
+ * workspace of csc_kmeans_device_workspace_bytes(n, d, k, replicates), and
+ * synchronises. */
+csc_status csc_kmeans_seeds(const double* F, int32_t n, int32_t d, int32_t ld, int32_t k,
+                            int32_t replicates, uint64_t seed, int32_t* picks);
+csc_status csc_kmeans_seeds_device(const float* F, int32_t n, int32_t d, int32_t ld, int32_t k,
+                                   int32_t replicates, uint64_t seed, int32_t* picks, void* ws,
+                                   size_t ws_bytes, void* stream);
 
 /* Community cores (the paper's conclusion: repeat the filtering with new
  * signals and the clustering of the sampled nodes, keep the nodes always
@@ -483,7 +515,10 @@ csc_status csc_gather_rows(const float* F, int64_t ldf, int32_t N, int32_t d, co
  * repeated passes (one eigencount pass per dichotomy step, one CG iteration)
  * are recorded once as a HIP graph and replayed (CSC_TUNE_HIP_GRAPHS).
  * Graph g follows exactly the arithmetic of the single-graph call with the
- * same arguments, so its outputs are bit-identical to that call's.
+ * same arguments, so its outputs are bit-identical to that call's; for the
+ * dichotomy this holds when CSC_TUNE_BATCH_COUNT_GROUP equals
+ * CSC_TUNE_COUNT_GROUP (at the defaults, 1 and 4, counts agree up to the
+ * order of float64 sums; see CSC_TUNE_COUNT_GROUP).
  * `graphs` is a host array of G csc_graph (device pointers inside); every
  * other per-graph array below is a host array indexed by g, and "device
  * per-graph" means a host array of G device pointers.  Workspaces: device, at
@@ -617,10 +652,15 @@ csc_status csc_mlp_adam_step(float* params, const float* grad, float* m, float* 
  * the network maps that pass's moments to offsets around the pass's own count
  * root (csc_count_root), giving [lo, hi], intersected with the half of [0, 2]
  * the first count selects.  The dichotomy then runs inside with fresh
- * signals (sub-streams 2, 3, ...), stopping as the plain one does; if every
- * count falls on one side of k until the interval is an eighth of the
- * bracket, the interval reopens once towards the rest of the half
- * (CSC_W_BRACKET_MISS).  steps_out counts every pass (max_steps in total).
+ * signals (sub-streams 2, 3, ...), stopping as the plain one does; if the
+ * first four tests inside the bracket all fall on one side of k (the
+ * interval is then a sixteenth of the bracket), the interval reopens once
+ * towards the rest of the half: from the bracket's upper end to the top of
+ * the half when the counts were below k, from the bottom of the half to its
+ * lower end when above (CSC_W_BRACKET_MISS).  If the network's bracket cut
+ * to the half is narrower than 1/1024, the bracket is lambda_0 (moved into
+ * the half) plus or minus max(s, 1/1024), cut to the half.  steps_out counts
+ * every pass (max_steps in total).
  * params: device.  trace_out: host[2*max_steps] or NULL; bracket_out: host[2]
  * or NULL.  p >= 50.  ws: csc_estimate_workspace_bytes_learned.  Synchronises.
  */

@@ -7,12 +7,10 @@ independent implementation can reproduce it exactly from the same inputs:
 * squared distances sum (x_j - c_j)^2 over coordinates j in increasing order;
 * k-means++ seeding per replicate r: draw u_0 at counter (0, r, KMEANS, 0) and
   take point floor(u_0 n) as the first centre; then for centre c = 1..k-1 draw
-  u_c, form the running sums of each point's squared distance to its nearest
-  chosen centre (``running_sums``: in blocks of SEED_BLOCK points, a block's
-  offset plus the running sum inside the block, both in index order), and
-  take the first point whose running sum exceeds u_c times the total (the
-  last point with a non-zero distance if none does; point floor(u_c n) if the
-  total is 0);
+  u_c, form the running sums, in index order, of each point's squared distance
+  to its nearest chosen centre (D^2 weighting), and take the first point whose
+  running sum exceeds u_c times the total (the last point with a non-zero
+  distance if none does; point floor(u_c n) if the total is 0);
 * Lloyd iterations, at most ``max_iter`` (Matlab's default is 100): assign each
   point to its nearest centre (lowest index on ties); stop when no assignment
   changed (and the previous update re-seeded nothing); otherwise recompute each
@@ -39,41 +37,32 @@ def sqdist(X: np.ndarray, c: np.ndarray) -> np.ndarray:
     return acc
 
 
-SEED_BLOCK = 32
-
-
-def running_sums(w: np.ndarray) -> np.ndarray:
-    """Cumulative k-means++ weights in a fixed two-level order: the running sum
-    of the weights inside each block of SEED_BLOCK consecutive points, plus the
-    block's offset, the running sum of the earlier blocks' totals in block
-    order (real-arithmetic value: the plain prefix sums of w)."""
-    n = w.size
-    nb = -(-n // SEED_BLOCK)
-    pad = np.zeros(nb * SEED_BLOCK)
-    pad[:n] = w
-    inner = np.cumsum(pad.reshape(nb, SEED_BLOCK), axis=1)  # in index order per block
-    off = np.zeros(nb)
-    for b in range(1, nb):
-        off[b] = off[b - 1] + inner[b - 1, -1]
-    return (off[:, None] + inner).reshape(-1)[:n]
-
-
-def seed_plusplus(X: np.ndarray, k: int, seed: int, r: int) -> np.ndarray:
+def seed_plusplus(X: np.ndarray, k: int, seed: int, r: int, record: list | None = None) -> np.ndarray:
+    """k-means++ centres of replicate r.  With ``record`` (a list), appends for
+    every centre c the tuple (pick, target, cum): the chosen point, u_c times
+    the total and the running sums it was compared with (None for c = 0 and
+    for a zero total, where no sum decides the pick)."""
     n = X.shape[0]
     u = uniform(seed, 0, r, KMEANS)
     first = min(int(math.floor(u * n)), n - 1)
     centres = [X[first].copy()]
+    if record is not None:
+        record.append((first, None, None))
     mind = sqdist(X, centres[0])
     for c in range(1, k):
         u = uniform(seed, c, r, KMEANS)
-        cum = running_sums(mind)
+        cum = np.cumsum(mind)  # plain running sums in index order
         total = cum[-1]
+        target = None
         if total == 0.0:
             pick = min(int(math.floor(u * n)), n - 1)
         else:
-            pick = int(np.searchsorted(cum, u * total, side="right"))
+            target = u * total
+            pick = int(np.searchsorted(cum, target, side="right"))
             if pick >= n:
                 pick = int(np.nonzero(mind > 0.0)[0][-1])
+        if record is not None:
+            record.append((pick, target, cum if target is not None else None))
         centres.append(X[pick].copy())
         mind = np.minimum(mind, sqdist(X, centres[-1]))
     return np.array(centres)
@@ -123,13 +112,19 @@ def lloyd(X: np.ndarray, C: np.ndarray, max_iter: int):
     return labels, C, inertia
 
 
-def kmeans(X: np.ndarray, k: int, seed: int, replicates: int = 20, max_iter: int = 100):
-    """Returns (labels, centres, inertia) of the best replicate."""
+def best_of(X: np.ndarray, seeds, max_iter: int = 100):
+    """Lloyd from each replicate's initial centres (in replicate order); returns
+    (labels, centres, inertia) of the smallest inertia, the earliest on ties."""
     X = np.asarray(X, dtype=np.float64)
     best = None
-    for r in range(replicates):
-        C0 = seed_plusplus(X, k, seed, r)
-        lab, C, inertia = lloyd(X, C0, max_iter)
+    for C0 in seeds:
+        lab, C, inertia = lloyd(X, np.asarray(C0, dtype=np.float64), max_iter)
         if best is None or inertia < best[2]:
             best = (lab, C, inertia)
     return best
+
+
+def kmeans(X: np.ndarray, k: int, seed: int, replicates: int = 20, max_iter: int = 100):
+    """Returns (labels, centres, inertia) of the best replicate."""
+    X = np.asarray(X, dtype=np.float64)
+    return best_of(X, (seed_plusplus(X, k, seed, r) for r in range(replicates)), max_iter)

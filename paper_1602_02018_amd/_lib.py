@@ -73,6 +73,8 @@ PROTOTYPES = {
     "csc_sample": (i32, [i32, i32, u64, vp, vp, sz, vp]),
     "csc_kmeans_reduced": (i32, [vp, i32, i32, i32, i32, i32, i32, u64, pi, pd]),
     "csc_kmeans_reduced_f64": (i32, [vp, i32, i32, i32, i32, i32, i32, u64, pi, pd]),
+    "csc_kmeans_seeds": (i32, [vp, i32, i32, i32, i32, i32, u64, pi]),
+    "csc_kmeans_seeds_device": (i32, [vp, i32, i32, i32, i32, i32, u64, pi, vp, sz, vp]),
     "csc_interpolate_workspace_bytes": (sz, [i32, i64, i32, i32]),
     "csc_interpolate": (i32, [pg, vp, i32, f64, i32, f64, vp, vp, vp, i32, i32, f64, i32, vp, i32,
                               vp, pi, pd, vp, sz, vp]),

@@ -46,7 +46,8 @@ SCHED_MIN_SKEW = 2.0
 class Graph:
     """A = D^-1/2 W D^-1/2 on the GPU, built by csc_laplacian_from_adjacency."""
 
-    def __init__(self, row_ptr, col, device="cuda", weights=None, check_csr: bool = True):
+    def __init__(self, row_ptr, col, device="cuda", weights=None, check_csr: int = 1):
+        """check_csr: 0 no check, 1 CSR form, 2 also no self-loops, sorted rows, symmetric W."""
         self.device = torch.device(device)
         self.row_ptr = _i32_device(row_ptr, self.device)
         self.col = _i32_device(col, self.device)
@@ -59,7 +60,7 @@ class Graph:
         self.dinv_sqrt = torch.empty(self.n, dtype=torch.float32, device=self.device)
         check(lib().csc_laplacian_from_adjacency(self.n, self.nnz, _ptr(self.row_ptr),
                                                  _ptr(self.col), _ptr(w), _ptr(self.val),
-                                                 _ptr(self.dinv_sqrt), 1 if check_csr else 0,
+                                                 _ptr(self.dinv_sqrt), int(check_csr),
                                                  _stream()), "csc_laplacian_from_adjacency")
         # the step kernels' row walk (rows of similar degree share a wave),
         # attached when the degrees are skewed enough for it to pay
@@ -265,6 +266,30 @@ def kmeans_reduced_device(F: torch.Tensor, k: int, seed: int, replicates: int = 
                                           _ptr(ws), ws.numel(), _stream()),
           "csc_kmeans_reduced_device")
     return labels, inertia.value
+
+
+def kmeans_seeds(F, k: int, seed: int, replicates: int = 20) -> np.ndarray:
+    """csc_kmeans_seeds: the host k-means++ picks, replicates x k point indices."""
+    if isinstance(F, torch.Tensor):
+        F = F.detach().cpu().numpy()
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    n, d = F.shape
+    picks = np.zeros((replicates, k), dtype=np.int32)
+    check(lib().csc_kmeans_seeds(C.c_void_p(F.ctypes.data), n, d, d, k, replicates, seed,
+                                 picks.ctypes.data_as(_lib.pi)), "csc_kmeans_seeds")
+    return picks
+
+
+def kmeans_seeds_device(F: torch.Tensor, k: int, seed: int, replicates: int = 20) -> np.ndarray:
+    """csc_kmeans_seeds_device: the GPU k-means++ picks, replicates x k point indices."""
+    assert F.is_cuda and F.dtype == torch.float32 and F.dim() == 2 and F.stride(1) == 1
+    n, d = F.shape
+    picks = np.zeros((replicates, k), dtype=np.int32)
+    ws = _ws(lib().csc_kmeans_device_workspace_bytes(n, d, k, replicates), F.device)
+    check(lib().csc_kmeans_seeds_device(_ptr(F), n, d, F.stride(0), k, replicates, seed,
+                                        picks.ctypes.data_as(_lib.pi), _ptr(ws), ws.numel(),
+                                        _stream()), "csc_kmeans_seeds_device")
+    return picks
 
 
 GOLDEN = 0x9E3779B97F4A7C15

@@ -627,6 +627,20 @@ extern "C" csc_status csc_laplacian_from_adjacency(int32_t n, int32_t nnz, const
                 "): row_ptr must start at 0, end at nnz and be non-decreasing; columns in [0, n)");
       return CSC_E_GRAPH;
     }
+    if (check >= 2 && nnz > 0) {
+      CSC_HIP(launch_fill_i32(flag, 1, 0, s));
+      CSC_HIP(launch_check_graph_strict(n, row_ptr, col, w, flag, s));
+      CSC_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+      CSC_HIP(hipStreamSynchronize(s));
+      if (h) {
+        std::string why;
+        if (h & 16) why += " a self-loop (stored diagonal entry);";
+        if (h & 32) why += " a row whose columns are not strictly increasing;";
+        if (h & 64) why += " W not symmetric (entry (j, i) missing or with another weight);";
+        set_error("graph rejected:" + why);
+        return CSC_E_GRAPH;
+      }
+    }
   }
   CSC_HIP(launch_degree_scale(n, row_ptr, col, w, dinv_sqrt_out, s));
   if (nnz > 0) CSC_HIP(launch_adjacency_values(n, row_ptr, col, w, dinv_sqrt_out, val_out, s));

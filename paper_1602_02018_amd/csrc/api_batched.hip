@@ -10,6 +10,7 @@
 #include <cstring>
 #include <string>
 #include <thread>
+#include <mutex>
 #include <vector>
 
 #include "host.hpp"
@@ -48,9 +49,15 @@ struct Captured {
   }
 };
 
-// Records launch(stream) as a HIP graph on the capture stream.
+// Records launch(stream) as a HIP graph on the capture stream.  The stream is
+// one per device and process, so concurrent batched calls (distinct
+// workspaces, other threads) take turns: the lock spans begin-capture,
+// the recorded launches, end-capture and instantiation.
+std::mutex g_capture_mu;
+
 template <class F>
 csc_status capture(F&& launch, Captured& out) {
+  std::lock_guard<std::mutex> lock(g_capture_mu);
   hipStream_t cs = capture_stream();
   if (!cs) {
     set_error("could not create the graph-capture stream");

@@ -106,6 +106,7 @@ csc_status permuted_graph(const csc_graph& g, const int* order, const int* idx, 
 // update after each later count (true once the count rounds to k).
 struct LearnedState {
   double lo = 0, hi = 2, lo0 = 0, hi0 = 2, half_lo = 0, half_hi = 2;
+  int inside = 0;  // tests run inside the bracket so far
   bool below = false, above = false, widened = false;
   int status = CSC_OK;
 };

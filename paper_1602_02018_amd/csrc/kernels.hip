@@ -107,6 +107,38 @@ __global__ void k_check_csr(int n, int nnz, const int* row_ptr, const int* col, 
     }
 }
 
+// Stricter checks on a CSR that passed k_check_csr: no stored diagonal entry
+// (16), columns strictly increasing within each row (32), and W symmetric,
+// entry (j, i) present with the same weight for every stored (i, j) (64),
+// found by binary search in row j.
+__global__ void k_check_graph_strict(int n, const int* row_ptr, const int* col, const float* w,
+                                     int* flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = row_ptr[i], e = row_ptr[i + 1];
+  int bits = 0;
+  for (int k = b; k < e; ++k) {
+    const int j = col[k];
+    if (j == i) bits |= 16;
+    if (k > b && col[k - 1] >= j) bits |= 32;
+    int lo = row_ptr[j], hi = row_ptr[j + 1] - 1, at = -1;
+    while (lo <= hi) {
+      const int m = lo + ((hi - lo) >> 1);
+      const int cm = col[m];
+      if (cm == i) {
+        at = m;
+        break;
+      }
+      if (cm < i)
+        lo = m + 1;
+      else
+        hi = m - 1;
+    }
+    if (at < 0 || (w && w[at] != w[k])) bits |= 64;
+  }
+  if (bits) atomicOr(flag, bits);
+}
+
 // -------------------------------------------------------------- random ---
 __global__ void k_gaussian_panels(Layout L, uint64_t seed, uint32_t t, uint32_t sid, float* out) {
   const size_t total = L.elems();
@@ -347,6 +379,13 @@ hipError_t launch_adjacency_values(int n, const int* row_ptr, const int* col, co
                                    const float* dinv_sqrt, float* val, hipStream_t s) {
   hipLaunchKernelGGL(k_adjacency_values, dim3(grid_for(n, kBlock, 1u << 30)), dim3(kBlock), 0, s,
                      n, row_ptr, col, w, dinv_sqrt, val);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_graph_strict(int n, const int* row_ptr, const int* col, const float* w,
+                                     int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_graph_strict, dim3(grid_for((size_t)n, kBlock, 1u << 30)), dim3(kBlock),
+                     0, s, n, row_ptr, col, w, flag);
   return hipGetLastError();
 }
 

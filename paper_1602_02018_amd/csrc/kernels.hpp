@@ -163,6 +163,8 @@ hipError_t launch_degree_scale(int n, const int* row_ptr, const int* col, const 
                                float* dinv_sqrt, hipStream_t s);
 hipError_t launch_adjacency_values(int n, const int* row_ptr, const int* col, const float* w,
                                    const float* dinv_sqrt, float* val, hipStream_t s);
+hipError_t launch_check_graph_strict(int n, const int* row_ptr, const int* col, const float* w,
+                                     int* flag, hipStream_t s);
 hipError_t launch_check_csr(int n, int nnz, const int* row_ptr, const int* col, int* flag,
                             hipStream_t s);
 

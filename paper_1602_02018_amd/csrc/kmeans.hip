@@ -98,12 +98,13 @@ struct Run {
   double inertia = 0.0;
 };
 
-void seed_plusplus(const Points& P, int k, uint64_t seed, int r, double* C) {
+void seed_plusplus(const Points& P, int k, uint64_t seed, int r, double* C, int32_t* picks = nullptr) {
   const int n = P.n, d = P.d;
   const double* X = P.X;
   std::vector<double> mind(n), cum(n), dist(n);
   double u = draw_uniform(seed, 0, (uint64_t)r);
   int first = std::min((int)std::floor(u * n), n - 1);
+  if (picks) picks[0] = first;
   std::memcpy(C, X + (size_t)first * d, d * sizeof(double));
   dist_to(P, C, mind.data());
   for (int c = 1; c < k; ++c) {
@@ -140,6 +141,7 @@ void seed_plusplus(const Points& P, int k, uint64_t seed, int r, double* C) {
           }
     }
     if (pick >= n) pick = n - 1;  // only with non-finite weights
+    if (picks) picks[c] = pick;
     double* cc = C + (size_t)c * d;
     std::memcpy(cc, X + (size_t)pick * d, d * sizeof(double));
     dist_to(P, cc, dist.data());
@@ -319,6 +321,19 @@ extern "C" csc_status csc_kmeans_reduced_f64(const double* F, int32_t n, int32_t
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < d; ++j) X[(size_t)i * d + j] = F[(size_t)i * ld + j];
   return kmeans_f64(X.data(), n, d, k, replicates, max_iter, seed, labels, inertia_out);
+}
+
+extern "C" csc_status csc_kmeans_seeds(const double* F, int32_t n, int32_t d, int32_t ld, int32_t k,
+                                       int32_t replicates, uint64_t seed, int32_t* picks) {
+  clear_error();
+  CSC_TRY(check_kmeans_args(F, n, d, ld, k, replicates, 1, picks));
+  std::vector<double> X((size_t)n * d);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < d; ++j) X[(size_t)i * d + j] = F[(size_t)i * ld + j];
+  const Points P(X.data(), n, d);
+  std::vector<double> C((size_t)k * d);
+  for (int r = 0; r < replicates; ++r) seed_plusplus(P, k, seed, r, C.data(), picks + (size_t)r * k);
+  return CSC_OK;
 }
 
 extern "C" csc_status csc_kmeans_reduced_batched(int32_t G, const float* const* F, const int32_t* n,

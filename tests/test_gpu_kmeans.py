@@ -1,10 +1,13 @@
-"""k-means on the GPU against the host form (and the float64 oracle): the
-same sums in the same order, so labels and inertia must be bit-identical."""
+"""k-means on the GPU against the host form and the float64 oracle.  The host
+and GPU forms run the same sums in the same order, so their labels and
+inertia must be bit-identical; against the oracle (plain prefix sums in the
+seeding) the picks agree up to near-ties of the running sums and Lloyd from
+the same picks agrees exactly (tests/kmeans_parity.py)."""
 import numpy as np
 import pytest
 import torch
 
-from oracle import kmeans
+from kmeans_parity import check_kmeans
 
 pytestmark = pytest.mark.gpu
 
@@ -42,9 +45,13 @@ def _blobs(seed, n, d, k, spread=0.3):
 def test_device_kmeans_is_bit_identical_to_host(api, seed, n, d, k, reps):
     X = _blobs(seed, n, d, k)
     lab_h, in_h = api.kmeans_reduced(X, k, seed, replicates=reps)
-    lab_d, in_d = api.kmeans_reduced_device(torch.as_tensor(X, device="cuda"), k, seed, replicates=reps)
+    Xd = torch.as_tensor(X, device="cuda")
+    lab_d, in_d = api.kmeans_reduced_device(Xd, k, seed, replicates=reps)
     assert np.array_equal(lab_h, lab_d)
     assert in_h == in_d
+    picks = api.kmeans_seeds_device(Xd, k, seed, replicates=reps)
+    assert np.array_equal(picks, api.kmeans_seeds(X, k, seed, replicates=reps))
+    check_kmeans(X, k, seed, picks, lab_d, in_d)
 
 
 def test_device_kmeans_duplicates_ties_and_reseeds(api):
@@ -57,15 +64,16 @@ def test_device_kmeans_duplicates_ties_and_reseeds(api):
         lab_d, in_d = api.kmeans_reduced_device(torch.as_tensor(X, device="cuda"), k, 4,
                                                 replicates=6)
         assert np.array_equal(lab_h, lab_d) and in_h == in_d
-        lab_o, _, in_o = kmeans.kmeans(X.astype(np.float64), k, 4, replicates=6)
-        assert np.array_equal(lab_o, lab_d) and in_o == in_d
+        picks = api.kmeans_seeds_device(torch.as_tensor(X, device="cuda"), k, 4, replicates=6)
+        check_kmeans(X, k, 4, picks, lab_d, in_d)
 
 
 def test_device_kmeans_matches_oracle(api):
     X = _blobs(9, 200, 16, 12)
-    lab_o, _, in_o = kmeans.kmeans(X.astype(np.float64), 12, 9)
-    lab_d, in_d = api.kmeans_reduced_device(torch.as_tensor(X, device="cuda"), 12, 9)
-    assert np.array_equal(lab_o, lab_d) and in_o == in_d
+    Xd = torch.as_tensor(X, device="cuda")
+    lab_d, in_d = api.kmeans_reduced_device(Xd, 12, 9)
+    same = check_kmeans(X, 12, 9, api.kmeans_seeds_device(Xd, 12, 9), lab_d, in_d)
+    assert all(same)
 
 
 def test_device_kmeans_iteration_cap(api):
@@ -75,6 +83,8 @@ def test_device_kmeans_iteration_cap(api):
         lab_d, in_d = api.kmeans_reduced_device(torch.as_tensor(X, device="cuda"), 30, 2,
                                                 replicates=3, max_iter=mi)
         assert np.array_equal(lab_h, lab_d) and in_h == in_d
+        picks = api.kmeans_seeds(X, 30, 2, replicates=3)
+        check_kmeans(X, 30, 2, picks, lab_d, in_d, max_iter=mi)
 
 
 def test_batched_device_kmeans_matches_single(api):

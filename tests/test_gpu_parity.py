@@ -21,6 +21,7 @@ import torch
 import synth
 from oracle import cheb, eigencount, interp, jackson, kmeans, laplacian, metrics, philox, sampling
 from oracle import csc as ocsc
+from kmeans_parity import check_kmeans
 
 pytestmark = pytest.mark.gpu
 
@@ -88,6 +89,31 @@ def test_laplacian_rejects_malformed_csr(api):
         api.Graph(np.array([0, 2, 1], np.int32), np.array([1, 0], np.int32))
     with pytest.raises(CscError):
         api.Graph(np.array([0, 1, 2], np.int32), np.array([1, 5], np.int32))
+
+
+def test_laplacian_strict_check_rejects_loops_asymmetry_and_unsorted_rows(api, ragged, cfg1):
+    """check = 2: the undirected graph without self-loops of Sec. 2.1."""
+    from paper_1602_02018_amd import CscError, _lib
+
+    for gr in (ragged, cfg1):  # the synthetic workloads pass
+        api.Graph(gr.row_ptr, gr.col, check_csr=2)
+    loop = (np.array([0, 2, 3], np.int32), np.array([0, 1, 0], np.int32))  # (0,0) stored
+    api.Graph(*loop, check_csr=1)  # accepted, its value set to 0
+    cases = {
+        "self-loop": loop,
+        "asymmetric": (np.array([0, 1, 2, 2], np.int32), np.array([1, 2], np.int32)),
+        "unsorted": (np.array([0, 2, 3, 4], np.int32), np.array([2, 1, 0, 0], np.int32)),
+        "duplicate": (np.array([0, 2, 4], np.int32), np.array([1, 1, 0, 0], np.int32)),
+    }
+    for name, (rp, cl) in cases.items():
+        with pytest.raises(CscError) as e:
+            api.Graph(rp, cl, check_csr=2)
+        assert e.value.status == _lib.CSC_E_GRAPH, name
+    # symmetric structure with unequal weights
+    rp, cl = np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32)
+    api.Graph(rp, cl, weights=np.array([2.0, 2.0], np.float32), check_csr=2)
+    with pytest.raises(CscError):
+        api.Graph(rp, cl, weights=np.array([2.0, 3.0], np.float32), check_csr=2)
 
 
 # --------------------------------------------------------------- random ----
@@ -256,10 +282,11 @@ def test_sampling_bit_exact(api, N, n, seed):
 def test_kmeans_on_gpu_features_matches_oracle_given_same_input(api, cfg1):
     g = api.Graph(cfg1.row_ptr, cfg1.col)
     omega = api.sample(cfg1.n, 47, 0)
-    F = api.filter(g, 0.46875, 50, 28, 0, rows=omega).cpu().numpy()
-    lab, inertia = api.kmeans_reduced(F.astype(np.float64), 10, 0)
-    lab_ref, _, inertia_ref = kmeans.kmeans(F.astype(np.float64), 10, 0)
-    assert np.array_equal(lab, lab_ref) and inertia == inertia_ref
+    Fd = api.filter(g, 0.46875, 50, 28, 0, rows=omega)
+    F = Fd.cpu().numpy()
+    lab, inertia = api.kmeans_reduced_device(Fd.contiguous(), 10, 0)
+    same = check_kmeans(F, 10, 0, api.kmeans_seeds_device(Fd.contiguous(), 10, 0), lab, inertia)
+    assert all(same)
     # and the float64 oracle features give the same clustering
     Fo = ocsc.features(_A(cfg1), 0.46875, 50, 28, 0)[sampling.sample(cfg1.n, 47, 0)]
     lab_o, _, _ = kmeans.kmeans(Fo, 10, 0)

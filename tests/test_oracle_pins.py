@@ -329,20 +329,29 @@ def test_plusplus_second_centre_weights_are_squared_distances():
     assert abs(hits[2] / tot - 0.9) < 0.03  # D^2 weights 1 : 9; D weights would give 0.75
 
 
-@pytest.mark.parametrize("n", [1, 2, 31, 32, 33, 64, 65, 100, 922])
-def test_plusplus_running_sums_are_the_prefix_sums(n):
-    """The two-level order of the seeding's cumulative weights changes only
-    the rounding: with integer weights (exact in float64) it is the exact
-    prefix sum, across every block boundary; with real weights it stays
-    within n ulps of the exactly rounded prefix sums."""
+@pytest.mark.parametrize("n,k", [(2, 2), (33, 5), (100, 10), (922, 40)])
+def test_plusplus_pick_is_where_the_exact_prefix_sum_passes_the_target(n, k):
+    """Each k-means++ pick is the first point whose running D^2 weight exceeds
+    u_c times the total: checked against exactly rounded prefix sums (fsum)
+    of squared distances recomputed from the chosen centres, away from
+    rounding-level ties."""
     rng = np.random.default_rng(n)
-    w = rng.integers(0, 1000, n)
-    assert np.array_equal(kmeans.running_sums(w.astype(np.float64)), np.cumsum(w).astype(np.float64))
-    x = rng.random(n) ** 3
-    exact = np.array([math.fsum(x[: i + 1]) for i in range(n)])
-    got = kmeans.running_sums(x)
-    assert np.all(np.abs(got - exact) <= n * np.finfo(float).eps * exact[-1])
-    assert np.all(np.diff(got) >= 0.0)
+    X = rng.normal(size=(n, 3))
+    rec = []
+    kmeans.seed_plusplus(X, k, 7, 0, record=rec)
+    picks = [p for p, _, _ in rec]
+    for c in range(1, k):
+        pick, target, cum = rec[c]
+        C = X[picks[:c]]
+        w = np.min(((X[:, None, :] - C[None, :, :]) ** 2).sum(-1), axis=1)
+        exact = np.array([math.fsum(w[: i + 1]) for i in range(n)])
+        assert np.all(np.abs(cum - exact) <= n * np.finfo(float).eps * exact[-1])
+        u = target / cum[-1]
+        t = u * exact[-1]
+        above = np.nonzero(exact > t)[0]
+        ref = int(above[0]) if above.size else int(np.nonzero(w > 0)[0][-1])
+        near = np.min(np.abs(exact - t)) <= 4 * n * np.finfo(float).eps * exact[-1]
+        assert pick == ref or near, (c, pick, ref)
 
 
 def test_kmeans_recovers_blobs_and_picks_lowest_inertia():
