@@ -273,6 +273,27 @@ csc_status csc_filter(const csc_graph* g, double lambda_c, int32_t p, int32_t d,
                       int32_t ld, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * csc_filter without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, outputs and errors as csc_filter; the
+ * scratch memory is a fixed array inside the library, one per device
+ * (csc_filter_noalloc_max_bytes() = 128 MiB), held from the first call on
+ * that device until the process ends.  The call allocates no device memory
+ * and calls no allocating routine.  A call whose workspace need (the
+ * csc_filter layout at the chosen panel width, about 16 N d bytes, e.g.
+ * N = 1e5 with d = 47 needs 77 MB) exceeds the array returns
+ * CSC_E_INVALID_ARG before any device work; p must lie in [1, 4096].  Every
+ * call on a device shares that device's array: calls that overlap on one
+ * device (other threads or streams) race and give undefined results; the
+ * array keeps the last call's contents and each call initialises what it
+ * reads.  The results are bit-identical to csc_filter's.
+ */
+size_t csc_filter_noalloc_max_bytes(void);
+csc_status csc_filter_noalloc(const csc_graph* g, double lambda_c, int32_t p, int32_t d,
+                              uint64_t seed, const int32_t* rows, int32_t n_rows,
+                              int32_t normalize, float* Y, int32_t ld, void* stream);
+
+/* ------------------------------------------------------------------------
  * Eigencount (Sec. 4.3): Hutchinson estimate of the number of eigenvalues of
  * L in [0, lambda], count = sum_{i,l} R_il (h~_lambda(L) R)_il, with R the
  * N x n_signals block of stream COUNT, sub-stream t.  It is evaluated as

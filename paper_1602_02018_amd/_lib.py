@@ -65,6 +65,8 @@ PROTOTYPES = {
     "csc_filter_workspace_bytes": (sz, [i32, i32]),
     "csc_filter_block": (i32, [pg, pd, i32, vp, i32, i32, vp, vp, sz, vp]),
     "csc_filter": (i32, [pg, f64, i32, i32, u64, vp, i32, i32, vp, i32, vp, sz, vp]),
+    "csc_filter_noalloc_max_bytes": (sz, []),
+    "csc_filter_noalloc": (i32, [pg, f64, i32, i32, u64, vp, i32, i32, vp, i32, vp]),
     "csc_estimate_workspace_bytes": (sz, [i32, i32, i32]),
     "csc_eigencount": (i32, [pg, f64, i32, i32, u64, u32, pd, pd, vp, sz, vp]),
     "csc_estimate_lambda_k": (i32, [pg, i32, i32, i32, u64, i32, pd, pd, pi, pd, pd, vp, sz, vp]),

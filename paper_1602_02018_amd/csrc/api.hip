@@ -17,6 +17,9 @@
 
 namespace csc {
 
+// largest polynomial order of csc_filter_noalloc (its coefficients live on the stack)
+constexpr int kNoallocMaxOrder = 4096;
+
 namespace {
 thread_local std::string g_error;
 std::atomic<int> g_panel_override{0};
@@ -747,6 +750,67 @@ extern "C" csc_status csc_filter(const csc_graph* g, double lambda_c, int32_t p,
   jackson_lowpass(lambda_c, p, a.data());
   return filter_common(g, a.data(), p, d, nullptr, 0, true, seed, rows, n_rows, normalize, Y, ld,
                        ws, ws_bytes, as_stream(stream));
+}
+
+// ----------------------------------------------- feature pass, no alloc ---
+namespace {
+// Scratch of csc_filter_noalloc: one array per device, held for the life of
+// the process.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in for the symbol); it uses the device address
+// returned by hipGetSymbolAddress, looked up once per device.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+csc_status scratch_for_current_device(void** out) {
+  int dev = 0;
+  CSC_HIP(hipGetDevice(&dev));
+  CSC_REQUIRE(dev >= 0 && dev < kMaxDevices, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error(std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+      return CSC_E_HIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return CSC_OK;
+}
+}  // namespace
+
+extern "C" size_t csc_filter_noalloc_max_bytes(void) { return kScratchBytes; }
+
+extern "C" csc_status csc_filter_noalloc(const csc_graph* g, double lambda_c, int32_t p, int32_t d,
+                                         uint64_t seed, const int32_t* rows, int32_t n_rows,
+                                         int32_t normalize, float* Y, int32_t ld, void* stream) {
+  clear_error();
+  CSC_TRY(check_graph(g));
+  CSC_REQUIRE(Y != nullptr, "Y is NULL");
+  CSC_REQUIRE(p >= 1 && p <= kNoallocMaxOrder, "p must lie in [1, 4096]");
+  CSC_REQUIRE(d >= 1 && ld >= d, "need d >= 1 and ld >= d");
+  CSC_REQUIRE(lambda_c >= 0.0 && lambda_c <= 2.0, "lambda_c must lie in [0, 2]");
+  CSC_REQUIRE(rows == nullptr || (n_rows >= 1 && n_rows <= g->n),
+              "n_rows must lie in [1, N] when rows is given");
+  const Layout L = make_layout(g->n, d, choose_panel_width(g->n, d, g->nnz));
+  const size_t need = filter_bytes(L);
+  if (need > kScratchBytes) {
+    set_error("csc_filter_noalloc: this graph and width need " + std::to_string(need) +
+              " bytes of scratch, more than the library's fixed " + std::to_string(kScratchBytes) +
+              "; use csc_filter with a workspace");
+    return CSC_E_INVALID_ARG;
+  }
+  void* ws = nullptr;
+  CSC_TRY(scratch_for_current_device(&ws));
+  double a[kNoallocMaxOrder + 1];
+  jackson_lowpass(lambda_c, p, a);
+  return filter_common(g, a, p, d, nullptr, 0, true, seed, rows, n_rows, normalize, Y, ld, ws,
+                       kScratchBytes, as_stream(stream));
 }
 
 extern "C" size_t csc_estimate_workspace_bytes(int32_t n, int32_t n_signals, int32_t p) {
