@@ -15,5 +15,6 @@ from .graphs import (  # noqa: F401
     chung_lu_blocks,
     disconnected_regular,
     sbm_batch,
+    sbm_batch_specs,
     csr_from_edges,
 )

@@ -264,15 +264,25 @@ def disconnected_regular(k: int, block_size: int, degree: int, seed: int = 0,
                  dict(model="disconnected_regular", degree=degree, block_size=block_size, seed=seed))
 
 
-def sbm_batch(G: int = 64, seed: int = 0, n_range=(2000, 200000), k_range=(10, 100),
-              s_range=(8.0, 32.0), eps_factor: float = 0.25):
-    """Batch of SBMs with N, k, s drawn uniformly per graph; graph g uses seed + g."""
+def sbm_batch_specs(G: int = 64, seed: int = 0, n_range=(2000, 200000), k_range=(10, 100),
+                    s_range=(8.0, 32.0), eps_factor: float = 0.25):
+    """(N, k, s, eps, graph seed) of every graph of ``sbm_batch``, without drawing edges."""
     rng = _rng(seed, 0xBA7C)
     out = []
     for g in range(G):
         N = int(rng.integers(n_range[0], n_range[1] + 1))
         k = int(rng.integers(k_range[0], k_range[1] + 1))
         s = float(rng.uniform(s_range[0], s_range[1]))
-        eps = eps_factor * eps_critical(s, k)
-        out.append(sbm(N, k, s, eps, seed + g, name=f"batch{g}_N{N}_k{k}"))
+        out.append((N, k, s, eps_factor * eps_critical(s, k), seed + g))
     return out
+
+
+def sbm_batch(G: int = 64, seed: int = 0, n_range=(2000, 200000), k_range=(10, 100),
+              s_range=(8.0, 32.0), eps_factor: float = 0.25, only=None):
+    """Batch of SBMs with N, k, s drawn uniformly per graph; graph g uses seed + g.
+    ``only`` (a list of positions in the batch) draws just those graphs, the
+    same as the full batch holds at those positions."""
+    specs = sbm_batch_specs(G, seed, n_range, k_range, s_range, eps_factor)
+    pick = range(G) if only is None else only
+    return [sbm(*specs[g][:4], specs[g][4], name=f"batch{g}_N{specs[g][0]}_k{specs[g][1]}")
+            for g in pick]

@@ -1,0 +1,231 @@
+"""Writes the oracle's results on the full-size workloads into tests/golden/.
+
+Only the float64 oracle (``oracle/``) and the seeded graph generator
+(``synth/``) run here; nothing of the HIP library is imported.  The GPU parity
+tests in ``tests/test_gpu_scale_golden.py`` compare the library with these
+files.
+
+    python tests/golden/make_scale_goldens.py sbm-1e5
+    python tests/golden/make_scale_goldens.py chunglu-1e6
+    python tests/golden/make_scale_goldens.py batch8 [--workers 6]
+
+Workloads (Alg. 2 with p Chebyshev steps, d = ceil(4 ln N) signals,
+n = ceil(2 k ln k) samples, n_c = ceil(2 ln N) count signals, gamma = 1e-3):
+
+* ``sbm-1e5``: SBM N = 1e5, k = 100, mean degree 16, eps = eps_c / 4, seed 0,
+  p = 50.  Whole pipeline: dichotomy trace and lambda_hat, the moments of the
+  first test's pass, sampled nodes, sampled features, k-means labels, the
+  interpolated columns 0 and k-1 at a fixed set of rows (the oracle's CG
+  iterate at 1e-6, and the same columns solved to 1e-10), final labels.
+* ``chunglu-1e6``: Chung-Lu N = 1e6, k = 250 planted blocks, p = 60, seed 0.
+  Dichotomy trace and lambda_hat, first-pass moments, sampled nodes, features
+  of the sampled nodes, k-means labels, and columns 0 and k-1 of the
+  interpolation solved per column by CG to 1e-10 from the oracle's own
+  lambda_hat, samples and labels (the full N x 250 solve would take the
+  float64 oracle hours; columns never mix in it).
+* ``batch8``: 8 of the 64 graphs of the batched SBM workload (N ~ U[2e3, 2e5],
+  k ~ U[10, 100], s ~ U[8, 32], eps = eps_c / 4, graph g seeded g), the ones
+  at ranks 0, 9, ..., 63 by N (smallest to largest), p = 50.  For each, the
+  plain pipeline (trace, lambda_hat, samples, k-means labels, final labels)
+  and the learned-bracket search with the network parameters in
+  ``paper_1602_02018_amd/data/lambda_bracket_mlp.npy`` (a data file: the same
+  parameters are an input of both sides) followed by the rest of the pipeline
+  at its lambda_hat.
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import os
+import sys
+import time
+
+os.environ.setdefault("OMP_NUM_THREADS", "1")
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import synth  # noqa: E402
+from oracle import cheb, eigencount, interp, jackson, kmeans, laplacian, philox, sampling  # noqa: E402
+from oracle import csc as ocsc  # noqa: E402
+
+X_ROWS = 8192  # rows at which interpolated columns are stored
+BATCH_RANKS = list(range(0, 64, 9))  # ranks by N: 0, 9, ..., 63
+WEIGHTS = os.path.join(ROOT, "paper_1602_02018_amd", "data", "lambda_bracket_mlp.npy")
+
+
+def log(msg):
+    print(f"[{time.strftime('%H:%M:%S')}] {msg}", flush=True)
+
+
+def x_rows(N, omega):
+    """Fixed rows: 8192 drawn without replacement (numpy seed 12345) plus the
+    sampled nodes, sorted."""
+    rows = np.random.default_rng(12345).choice(N, size=min(X_ROWS, N), replace=False)
+    return np.unique(np.concatenate([rows, np.asarray(omega)])).astype(np.int64)
+
+
+def search_arrays(prefix, s):
+    out = {
+        f"{prefix}lam": np.float64(s.lam),
+        f"{prefix}steps": np.int64(s.steps),
+        f"{prefix}found": np.bool_(s.found),
+        f"{prefix}missed": np.bool_(s.missed),
+        f"{prefix}trace": np.array(s.trace, dtype=np.float64).reshape(-1, 2),
+        f"{prefix}intervals": np.array(s.intervals, dtype=np.float64).reshape(-1, 2),
+    }
+    if s.bracket is not None:
+        out[f"{prefix}bracket"] = np.array(s.bracket, dtype=np.float64)
+    return out
+
+
+def pipeline_after_lambda(A, lam, k, d, p, seed, gamma=1e-3, tol=1e-6, full_cg=True):
+    """Alg. 2 steps 2-7 at a given lambda_hat (the oracle's own functions)."""
+    N = A.shape[0]
+    n = ocsc.default_n(k)
+    F = ocsc.features(A, lam, p, d, seed)
+    omega = sampling.sample(N, n, seed)
+    Fr = F[omega]
+    labels_r, _, inertia = kmeans.kmeans(Fr, k, seed)
+    out = {"omega": omega.astype(np.int32), "features_sampled": Fr,
+           "labels_r": labels_r.astype(np.int32), "inertia": np.float64(inertia)}
+    if full_cg:
+        X, labels, iters, relres = interp.interpolate(A, lam, p, gamma, omega, labels_r, k, tol)
+        out.update(labels=labels.astype(np.uint16), cg_iters=iters, cg_relres=relres, X=X)
+    return out
+
+
+def exact_columns(A, lam, p, omega, labels_r, k, cols, gamma=1e-3):
+    """Columns `cols` of the interpolation, Eq. (5), solved by the oracle's CG
+    to a relative residual of 1e-10 (columns never mix in it)."""
+    N = A.shape[0]
+    mask = interp.sample_mask(N, omega)
+    B = interp.rhs(N, omega, labels_r, k)[:, cols]
+    return interp.cg(A, mask, gamma, jackson.lowpass_coeffs(lam, p), B, tol=1e-10, max_iter=1000)
+
+
+def make_sbm_1e5(path):
+    N, k, p, seed = 100000, 100, 50, 0
+    gr = synth.sbm_config(N, k, seed=seed)
+    A, _ = laplacian.normalized_adjacency(gr.row_ptr, gr.col)
+    d = int(math.ceil(4 * math.log(N)))
+    n_c = eigencount.count_signals(N)
+    log(f"sbm-1e5: N={N} nnz={gr.nnz} d={d} n_c={n_c}")
+    s = eigencount.dichotomy(A, k, p, n_c, seed)
+    log(f"dichotomy: lam={s.lam} steps={s.steps}")
+    mu1 = cheb.moments(A, philox.gaussian_block(seed, N, n_c, 1, philox.COUNT), p)
+    rest = pipeline_after_lambda(A, s.lam, k, d, p, seed)
+    log(f"pipeline: cg iters max {int(rest['cg_iters'].max())}")
+    X = rest.pop("X")
+    rows = x_rows(N, rest["omega"])
+    cols = np.array([0, k - 1])
+    Xe, iters_e, relres_e = exact_columns(A, s.lam, p, rest["omega"], rest["labels_r"], k, cols)
+    log(f"columns {cols.tolist()} to 1e-10: iters {iters_e.tolist()}")
+    np.savez_compressed(
+        path, N=np.int64(N), k=np.int64(k), p=np.int64(p), d=np.int64(d), n_c=np.int64(n_c),
+        seed=np.int64(seed), nnz=np.int64(gr.nnz), moments1=mu1, x_rows=rows, x_cols=cols,
+        X_at_rows=X[rows][:, cols], X_col_norms=np.linalg.norm(X[:, cols], axis=0),
+        X_exact_at_rows=Xe[rows], X_exact_col_norms=np.linalg.norm(Xe, axis=0),
+        x_cg_iters=iters_e, x_cg_relres=relres_e, **search_arrays("", s), **rest)
+    log(f"wrote {path}")
+
+
+def make_chunglu_1e6(path):
+    N, k, p, seed = 1000000, 250, 60, 0
+    gr = synth.chung_lu_blocks(N, k, seed=seed)
+    A, _ = laplacian.normalized_adjacency(gr.row_ptr, gr.col)
+    d = int(math.ceil(4 * math.log(N)))
+    n_c = eigencount.count_signals(N)
+    log(f"chunglu-1e6: N={N} nnz={gr.nnz} d={d} n_c={n_c}")
+    s = eigencount.dichotomy(A, k, p, n_c, seed)
+    log(f"dichotomy: lam={s.lam} steps={s.steps} trace={s.trace}")
+    mu1 = cheb.moments(A, philox.gaussian_block(seed, N, n_c, 1, philox.COUNT), p)
+    rest = pipeline_after_lambda(A, s.lam, k, d, p, seed, full_cg=False)
+    log("features and k-means done")
+    cols = np.array([0, k - 1])
+    omega, labels_r = rest["omega"], rest["labels_r"]
+    Xc, iters, relres = exact_columns(A, s.lam, p, omega, labels_r, k, cols)
+    log(f"columns {cols.tolist()}: iters {iters.tolist()} relres {relres.tolist()}")
+    rows = x_rows(N, omega)
+    np.savez_compressed(
+        path, N=np.int64(N), k=np.int64(k), p=np.int64(p), d=np.int64(d), n_c=np.int64(n_c),
+        seed=np.int64(seed), nnz=np.int64(gr.nnz), moments1=mu1, x_rows=rows, x_cols=cols,
+        X_at_rows=Xc[rows], X_col_norms=np.linalg.norm(Xc, axis=0), x_cg_iters=iters,
+        x_cg_relres=relres, **search_arrays("", s), **rest)
+    log(f"wrote {path}")
+
+
+def batch_positions():
+    specs = synth.sbm_batch_specs()
+    by_n = sorted(range(len(specs)), key=lambda g: specs[g][0])
+    return [by_n[r] for r in BATCH_RANKS]
+
+
+def one_batch_graph(g):
+    p = 50
+    gr = synth.sbm_batch(only=[g])[0]
+    A, _ = laplacian.normalized_adjacency(gr.row_ptr, gr.col)
+    N, k, seed = gr.n, gr.k, g
+    d = int(math.ceil(4 * math.log(N)))
+    n_c = eigencount.count_signals(N)
+    theta = np.load(WEIGHTS)
+    t0 = time.time()
+    plain = eigencount.dichotomy(A, k, p, n_c, seed)
+    lrn = eigencount.estimate_lambda_k_learned(A, k, p, n_c, seed, theta)
+    out = {"N": np.int64(N), "k": np.int64(k), "d": np.int64(d), "n_c": np.int64(n_c),
+           "seed": np.int64(seed), "nnz": np.int64(gr.nnz)}
+    out.update(search_arrays("plain_", plain))
+    out.update(search_arrays("learned_", lrn))
+    rest = pipeline_after_lambda(A, plain.lam, k, d, p, seed)
+    for key in ("omega", "labels_r", "labels", "cg_iters"):
+        out[f"plain_{key}"] = rest[key]
+    if lrn.lam == plain.lam:
+        rest_l = rest
+    else:
+        rest_l = pipeline_after_lambda(A, lrn.lam, k, d, p, seed)
+    for key in ("labels_r", "labels"):
+        out[f"learned_{key}"] = rest_l[key]
+    print(f"graph {g}: N={N} k={k} plain lam {plain.lam} ({plain.steps} tests), learned lam "
+          f"{lrn.lam} ({lrn.steps} tests), {time.time() - t0:.0f} s", flush=True)
+    return g, out
+
+
+def make_batch8(path, workers):
+    import multiprocessing as mp
+
+    pos = batch_positions()
+    log(f"batch8: graphs {pos}")
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = dict(pool.map(one_batch_graph, sorted(pos, key=lambda g: -synth.sbm_batch_specs()[g][0]),
+                            chunksize=1))
+    arrays = {"positions": np.array(pos, dtype=np.int64)}
+    for g in pos:
+        for key, v in res[g].items():
+            arrays[f"g{g}_{key}"] = v
+    np.savez_compressed(path, **arrays)
+    log(f"wrote {path}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", choices=["sbm-1e5", "chunglu-1e6", "batch8"])
+    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--out", default=HERE)
+    args = ap.parse_args()
+    name = {"sbm-1e5": "scale_sbm_1e5.npz", "chunglu-1e6": "scale_chunglu_1e6.npz",
+            "batch8": "scale_batch8.npz"}[args.which]
+    path = os.path.join(args.out, name)
+    if args.which == "sbm-1e5":
+        make_sbm_1e5(path)
+    elif args.which == "chunglu-1e6":
+        make_chunglu_1e6(path)
+    else:
+        make_batch8(path, args.workers)
+
+
+if __name__ == "__main__":
+    main()

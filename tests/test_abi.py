@@ -198,3 +198,51 @@ def test_count_root_host_call_matches_oracle():
         l0, s = api.count_root(mu, k, nc)
         r0, rs = mlp.count_root(mu, 50, k, nc)
         assert abs(l0 - r0) < 1e-12 and abs(s - rs) <= 1e-9 * rs
+
+
+def test_argument_checks_from_two_threads_keep_their_own_errors():
+    """Calls are reentrant on the host side: two threads hitting different
+    argument errors at once each get their own status and csc_last_error
+    message (the message is per thread)."""
+    import threading
+
+    lib = _lib.lib()
+    g = _lib.CscGraph(10, 0, 16, 0, 0, 0)
+    F = np.ones((4, 3))
+    lab = np.zeros(4, dtype=np.int32)
+    errors = []
+    barrier = threading.Barrier(2)
+
+    def panel():
+        barrier.wait()
+        for _ in range(2000):
+            if lib.csc_set_panel_width(3) != _lib.CSC_E_INVALID_ARG or b"panel width" not in lib.csc_last_error():
+                errors.append("panel")
+                return
+
+    def filt():
+        barrier.wait()
+        for _ in range(2000):
+            st = lib.csc_filter(C.byref(g), 2.5, 50, 4, 0, None, 0, 1, C.c_void_p(16), 4, None, 0, None)
+            if st != _lib.CSC_E_INVALID_ARG or b"lambda_c" not in lib.csc_last_error():
+                errors.append("filter")
+                return
+
+    def kmeans():
+        barrier.wait()
+        for _ in range(2000):
+            st = lib.csc_kmeans_reduced_f64(F.ctypes.data_as(_lib.pd), 4, 3, 3, 0, 1, 10, 0,
+                                            lab.ctypes.data_as(_lib.pi), None)
+            if st != _lib.CSC_E_INVALID_ARG or b"k must" not in lib.csc_last_error():
+                errors.append("kmeans")
+                return
+
+    for pair in ((panel, filt), (filt, kmeans), (panel, kmeans)):
+        barrier.reset()
+        ts = [threading.Thread(target=f) for f in pair]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+    assert not errors, errors
+    assert lib.csc_set_panel_width(0) == _lib.CSC_OK
