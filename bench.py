@@ -1,26 +1,34 @@
 """Benchmark of the compressive spectral clustering hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sbm-1e5]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload chunglu-1e6]
 
-A step is one pass of the whole path over one synthetic graph already
+A step is one pass of the whole path (Alg. 2) over one synthetic graph already
 resident in HBM: lambda_k dichotomy (eigencount passes), feature pass,
-sampling, k-means on the sampled features, interpolation by CG and the hard
-labels.  Prints one JSON line:
+sampling, k-means on the sampled features, interpolation by block CG and the
+hard labels.  The default workload is the largest single-GPU configuration:
+a Chung-Lu graph with N = 1e6 nodes, power-law expected degrees (exponent
+2.5, mean 20, maximum 2000), k = 250 planted blocks, d = 56, p = 60.
 
-* value: whole-job throughput in GB/s, the algorithmic bytes of every
-  Chebyshev step, random block and CG update in the step divided by the wall
-  time of the step;
-* roofline: the dominant kernel of the step, the Chebyshev-step kernel with
-  the largest launches x time: the moment step of the eigencount passes (the
-  dichotomy runs 4 tests side by side, width 4 x n_c rounded to a multiple of
-  4 each, natural node order) or the Clenshaw step of the CG operator at
-  width k (graph in community order), each timed per launch with HIP events on
-  the stream it runs on, against the MI355X HBM peak (8 TB/s); its HBM traffic
-  comes from rocprofv3 FETCH_SIZE / WRITE_SIZE counters recorded in profiles/
-  and is null when the kernel source changed since they were taken (the other
-  kernel is reported beside it);
-* cpu_baseline: the float64 CPU oracle's filter pass (p products of the CSR
-  matrix with an N x k block) on the same graph, in the same unit.
+Prints one JSON line:
+
+* value: whole-job throughput in GB/s: the algorithmic bytes of every
+  Chebyshev step, random block and CG update of the timed steps divided by
+  their wall time (a whole-pipeline rate, not the rate of one SpMM kernel);
+* roofline: the dominant step kernel of the pipeline (the largest launches x
+  time per launch among the eigencount moment step, the feature step and the
+  Clenshaw step of the CG operator), timed per launch with HIP events on the
+  stream it runs on, against the MI355X HBM peak (8 TB/s); its traffic comes
+  from rocprofv3 FETCH_SIZE / WRITE_SIZE counters recorded in profiles/ and is
+  null when the kernel sources changed since they were taken; the other two
+  step kernels are reported beside it;
+* sbm_1e5 / batch64 (secondary workloads, unless --no-secondary): the
+  1e5-node SBM (plain, learned bracket, one-pass KPM) and the batch of 64 SBMs
+  (plain graph by graph, batched, batched + learned bracket) with the
+  agreement of their labels;
+* cpu_baseline: the float64 CPU oracle timed on the host: the filter pass on
+  the headline graph (bounded sample, one core and all cores over column
+  panels) and, per phase of Alg. 2, the 1e5-node SBM (bounded samples scaled
+  to one graph).
 """
 from __future__ import annotations
 
@@ -37,22 +45,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+METRIC = "filter SpMM HBM GB/s (% peak) + end-to-end CSC s/graph vs plain at ARI>=0.99"
 KERNEL_SRC = [os.path.join(ROOT, "paper_1602_02018_amd", "csrc", f)
               for f in ("kernels.hip", "device.hpp", "kernels.hpp", "common.hpp")]
-# rocprofv3 counter summaries of the two candidate dominant kernels
+PROF = os.path.join(ROOT, "profiles")
+# rocprofv3 counter summaries of the step kernels, per workload
 COUNTERS = {
-    "count": os.path.join(ROOT, "profiles", "cheb_step_count_sbm_N1e5_4x24_counters.txt"),
-    "cg": os.path.join(ROOT, "profiles", "cheb_step_cg_sbm_N1e5_k100_counters.txt"),
-    "cl_count_step": os.path.join(ROOT, "profiles", "cheb_step_count_chunglu_N1e6_4x28_counters.txt"),
-    "cl_filter_step": os.path.join(ROOT, "profiles", "cheb_step_filter_chunglu_N1e6_w56_counters.txt"),
-    "cl_cg_step": os.path.join(ROOT, "profiles", "cheb_step_cg_chunglu_N1e6_k250_counters.txt"),
+    ("sbm-1e5", "count"): os.path.join(PROF, "cheb_step_count_sbm_N1e5_4x24_counters.txt"),
+    ("sbm-1e5", "cg"): os.path.join(PROF, "cheb_step_cg_sbm_N1e5_k100_counters.txt"),
+    ("chunglu-1e6", "count"): os.path.join(PROF, "cheb_step_count_chunglu_N1e6_4x28_counters.txt"),
+    ("chunglu-1e6", "filter"): os.path.join(PROF, "cheb_step_filter_chunglu_N1e6_w56_counters.txt"),
+    ("chunglu-1e6", "cg"): os.path.join(PROF, "cheb_step_cg_chunglu_N1e6_k250_counters.txt"),
 }
+GOLDEN_BATCH = os.path.join(ROOT, "tests", "golden", "scale_batch8.npz")
 
 WORKLOADS = {
-    # SBM N = 1e5, k = 100, mean degree 16, eps = eps_c / 4; d = ceil(4 ln N), p = 50
-    "sbm-1e5": dict(N=100000, k=100, s=16.0, p=50, model="sbm"),
     # Chung-Lu N = 1e6, power-law degrees (exponent 2.5, mean 20, max 2000), k = 250 blocks
     "chunglu-1e6": dict(N=1000000, k=250, p=60, model="chunglu"),
+    # SBM N = 1e5, k = 100, mean degree 16, eps = eps_c / 4; d = ceil(4 ln N), p = 50
+    "sbm-1e5": dict(N=100000, k=100, s=16.0, p=50, model="sbm"),
     # SBM N = 1000, k = 10 (oracle-sized)
     "sbm-1e3": dict(N=1000, k=10, s=16.0, p=50, model="sbm"),
     # 64 SBMs, N ~ U[2e3, 2e5], k ~ U[10, 100], s ~ U[8, 32], eps = eps_c / 4
@@ -118,10 +129,11 @@ def permuted_csr(gr, order):
     return rp.astype(np.int32), inv[gr.col[src]].astype(np.int32)
 
 
-def read_traffic(which):
-    """HBM bytes per launch from the committed counter summary, or None."""
-    path = COUNTERS[which]
-    if not os.path.exists(path):
+def read_traffic(workload, which):
+    """Bytes below L2 per launch from the committed counter summary, or None
+    (no summary, or the kernel sources changed since it was taken)."""
+    path = COUNTERS.get((workload, which))
+    if path is None or not os.path.exists(path):
         return None
     rec = {}
     for line in open(path):
@@ -145,38 +157,6 @@ def make_graph(wl, seed):
     return synth.chung_lu_blocks(wl["N"], wl["k"], seed=seed)
 
 
-def cpu_baseline(gr, k, p, budget_s=30.0):
-    """Oracle filter pass on an N x k block; fewer columns if it would run long."""
-    import numpy as np
-
-    from oracle import cheb, jackson, laplacian, philox
-
-    A, _ = laplacian.normalized_adjacency(gr.row_ptr, gr.col)
-    a = jackson.lowpass_coeffs(0.4, p)
-    # time one product to bound the sample at ~budget_s of CPU work
-    X1 = philox.gaussian_block(0, gr.n, k, 0, philox.FEAT)
-    t0 = time.perf_counter()
-    _ = A @ X1
-    one = time.perf_counter() - t0
-    w = k
-    if one * p > budget_s:
-        w = max(1, int(k * budget_s / (one * p)))
-    X = X1[:, :w].copy()
-    t0 = time.perf_counter()
-    cheb.filter_block(A, X, a)
-    t = time.perf_counter() - t0
-    by = p * step_bytes(gr.n, gr.nnz, w, "y")
-    return {
-        "value": round(by / t / 1e9, 3),
-        "unit": "GB/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"float64 oracle filter pass, p={p} products of the {gr.n}-node CSR matrix "
-                  f"with an N x {w} block (the CG operator's filter), {t:.1f} s; scipy's CSR "
-                  f"product runs on one thread; host reports {os.cpu_count()} CPUs",
-    }
-
-
 def quiet_gc():
     """Collect once and move every object alive after set-up out of the
     collector's reach, so that a full collection (tens of ms with torch
@@ -185,182 +165,170 @@ def quiet_gc():
     gc.freeze()
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sbm-1e5", choices=sorted(WORKLOADS))
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the 1e6-node Chung-Lu run and its step timings")
-    ap.add_argument("--kernel-reps", type=int, default=20)
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="run only a plain 256 MiB device copy (for scaling memory counters)")
-    args = ap.parse_args()
-    if args.calibrate_copy:
-        import torch
+# ------------------------------------------------------------ CPU oracle ---
+# The float64 oracle timed on the host, before the GPU is touched (the
+# process pool forks).  Every column of a block is independent in every
+# phase, so the all-core form splits the columns into panels over a pool.
 
-        x = torch.ones(64 * 2**20, dtype=torch.float32, device="cuda:0")
-        y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4,
-                          "dispatches": 3}), flush=True)
-        return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(the path shards by columns across GPUs, which this build does not run)",
-              file=sys.stderr)
-        sys.exit(2)
+_POOL = {}
+
+
+def _pool_filter(task):
+    """One panel of a filter pass in a pool worker: `steps` products of the
+    shared CSR matrix with an N x w block (the oracle's recurrence)."""
+    import numpy as np
+
+    from oracle import cheb
+
+    w, steps, salt = task
+    A, a = _POOL["A"], _POOL["coeffs"][: steps + 1]
+    X = np.random.default_rng(salt).standard_normal((A.shape[0], w))
+    Y = cheb.filter_block(A, X, a)
+    return float(Y[0, 0])
+
+
+def _pool_kmeans(task):
+    from oracle import kmeans
+
+    Fr, k, seed, r = _POOL["km"]
+    lab, C, inertia = kmeans.lloyd(Fr, kmeans.seed_plusplus(Fr, k, seed, task), 100)
+    return inertia
+
+
+def _timed_pool_map(pool, fn, tasks):
+    t0 = time.perf_counter()
+    pool.map(fn, tasks, chunksize=1)
+    return time.perf_counter() - t0
+
+
+def _panels(w, parts):
+    base, extra = divmod(w, parts)
+    return [base + (1 if i < extra else 0) for i in range(parts) if base + (1 if i < extra else 0) > 0]
+
+
+def cpu_baseline(head_gr, head_wl, sbm_gr, sbm_wl, workers):
+    """The oracle on the host: the headline graph's filter pass (sample: a few
+    of its p products, scaled to the pass) on 1 core and on `workers` cores,
+    and the 1e5-node SBM per phase of Alg. 2 (bounded samples scaled to one
+    graph: one dichotomy test, the feature pass, sampling, k-means replicates,
+    one CG iteration on a column panel, labels)."""
+    import multiprocessing as mp
 
     import numpy as np
-    import torch
 
-    from oracle.metrics import adjusted_rand_index  # ARI of the labels only
-    from paper_1602_02018_amd import api
+    from oracle import cheb, eigencount, interp, jackson, kmeans, laplacian, philox, sampling
+    from oracle import csc as ocsc
 
-    wl = WORKLOADS[args.workload]
-    dev = torch.device("cuda:0")
-    if args.workload == "batch64":
-        return bench_batch(args, wl, dev)
-    gr = make_graph(wl, args.seed)
-    N, nnz, k, p = gr.n, gr.nnz, wl["k"], wl["p"]
+    out = {"kind": "oracle", "unit": "GB/s", "host_cpus": os.cpu_count()}
+    # headline graph: filter pass at d columns, `hsteps` of its p products
+    A, _ = laplacian.normalized_adjacency(head_gr.row_ptr, head_gr.col)
+    N, nnz, p = head_gr.n, head_gr.nnz, head_wl["p"]
     d = int(math.ceil(4 * math.log(N)))
-    n_c = api.count_signals(N)
-    g = api.Graph(gr.row_ptr, gr.col, dev)
-    torch.cuda.synchronize()
-
-    quiet_gc()
-    for _ in range(args.warmup):
-        api.run(g, k, d, args.seed, p=p)
-    torch.cuda.synchronize()
-    results = []
+    a = jackson.lowpass_coeffs(0.4, p)
+    hsteps = 2
+    X = philox.gaussian_block(0, N, d, 0, philox.FEAT)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        results.append(api.run(g, k, d, args.seed, p=p))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed / args.steps * 1e3
-
-    total = 0.0
-    for r in results:
-        total += job_bytes(N, nnz, k, d, n_c, p, r.bisection.steps, int(r.interp.iters.max()))
-    value = total / elapsed / 1e9
-    last = results[-1]
-    ari = adjusted_rand_index(last.labels.cpu().numpy(), gr.truth)
-
-    # the same graph with the learned lambda_k bracket
-    from paper_1602_02018_amd import learned
-
-    mlp = learned.load_params(dev)
-    api.run(g, k, d, args.seed, p=p, mlp_params=mlp)
-    torch.cuda.synchronize()
+    cheb.filter_block(A, X, a[: hsteps + 1])
+    t1 = time.perf_counter() - t0
+    del X
+    by = hsteps * step_bytes(N, nnz, d, "y")
+    # SBM phases
+    As, _ = laplacian.normalized_adjacency(sbm_gr.row_ptr, sbm_gr.col)
+    Ns, ks, ps = sbm_gr.n, sbm_wl["k"], sbm_wl["p"]
+    ds, ncs, ns = int(math.ceil(4 * math.log(Ns))), eigencount.count_signals(Ns), ocsc.default_n(ks)
+    one = {}
     t0 = time.perf_counter()
-    lres = [api.run(g, k, d, args.seed, p=p, mlp_params=mlp) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    ms_learned = (time.perf_counter() - t0) / args.steps * 1e3
-    ari_lp = adjusted_rand_index(lres[-1].labels.cpu().numpy(), last.labels.cpu().numpy())
-
-    # the same graph with the one-pass KPM dichotomy
-    api.run(g, k, d, args.seed, p=p, lambda_method="kpm")
-    torch.cuda.synchronize()
+    R = philox.gaussian_block(0, Ns, ncs, 1, philox.COUNT)
+    eigencount.eigencount(As, 0.5, ps, R)
+    one["dichotomy_per_test"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    kres = [api.run(g, k, d, args.seed, p=p, lambda_method="kpm") for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    ms_kpm = (time.perf_counter() - t0) / args.steps * 1e3
+    F = ocsc.features(As, 0.4, ps, ds, 0)
+    one["features"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    omega = sampling.sample(Ns, ns, 0)
+    one["sampling"] = time.perf_counter() - t0
+    Fr = F[omega]
+    km_reps = 2
+    t0 = time.perf_counter()
+    for r in range(km_reps):
+        kmeans.lloyd(Fr, kmeans.seed_plusplus(Fr, ks, 0, r), 100)
+    one["kmeans_per_replicate"] = (time.perf_counter() - t0) / km_reps
+    labels_r = kmeans.lloyd(Fr, kmeans.seed_plusplus(Fr, ks, 0, 0), 100)[0]
+    cg_cols = 10
+    mask = interp.sample_mask(Ns, omega)
+    B = interp.rhs(Ns, omega, labels_r, ks)[:, :cg_cols]
+    t0 = time.perf_counter()
+    interp.cg(As, mask, 1e-3, jackson.lowpass_coeffs(0.4, ps), B, tol=0.0, max_iter=1)
+    one["cg_iteration_per_column"] = (time.perf_counter() - t0) / cg_cols
+    Xl = np.random.default_rng(0).standard_normal((Ns, ks))
+    t0 = time.perf_counter()
+    interp.hard_labels(Xl)
+    one["labels"] = time.perf_counter() - t0
 
-    # candidate dominant kernels, per-launch times: the moment step of the
-    # eigencount passes (width n_c, natural order) and the Clenshaw step of the
-    # CG operator (width k, on the graph in the order the interpolation used)
-    # (the dichotomy runs `group` tests' passes side by side, each test's
-    # n_c columns rounded up to a multiple of 4)
-    group, count_w, count_kind = count_shape(api, n_c)
-    cands = {}
-    for which, w, order, kind, bkind, launches in (
-            ("count", count_w, None, count_kind, "mom",
-             -(-last.bisection.steps // group) * moment_steps(p)),
-            ("cg", k, last.order, 3, "clen", int(last.interp.iters.max()) * p)):
-        avg_s = step_time(api, gr, order, w, p, args.kernel_reps, dev, kind=kind)
-        per_launch = step_bytes(N, nnz, w, bkind)
-        achieved = per_launch / avg_s / 1e9
-        name = (f"k_cheb_step<EPI_MOM> (moment step of the eigencount passes, {group} tests of "
-                f"{n_c} signals side by side" if which == "count"
-                else "k_cheb_step<EPI_CLEN> (Clenshaw step of the CG operator pass")
-        traffic = read_traffic(which)
-        cands[which] = {
-            "kernel": f"{name}, w={w}, panel width {api.panel_width(N, w, nnz)}"
-                      f"{', community order' if order is not None else ', natural order'})",
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": PEAK_HBM_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": traffic,
-            # bytes below L2 per launch (counters) over the launch time
-            "traffic_GBs": None if traffic is None else round(traffic / avg_s / 1e9, 1),
-            "alg_bytes_per_launch": per_launch,
-            "avg_launch_us": round(avg_s * 1e6, 2),
-            "launches_per_step": launches,
-            "ms_per_step": round(launches * avg_s * 1e3, 3),
-        }
-    dom = max(cands, key=lambda c: cands[c]["ms_per_step"])
-    other = "cg" if dom == "count" else "count"
-    large = None if args.no_large else large_shapes(api, args, dev)
+    # all cores: the same samples with the columns (replicates) over a pool
+    ctx = mp.get_context("fork")
+    _POOL.update(A=A, coeffs=a)
+    with ctx.Pool(workers) as pool:
+        pool.map(abs, range(workers))  # start every worker before timing
+        tN = _timed_pool_map(pool, _pool_filter, [(w, hsteps, i) for i, w in enumerate(_panels(d, workers))])
+    _POOL.update(A=As, coeffs=jackson.lowpass_coeffs(0.5, ps), km=(Fr, ks, 0, 0))
+    allc = {}
+    with ctx.Pool(workers) as pool:
+        pool.map(abs, range(workers))
+        allc["dichotomy_per_test"] = _timed_pool_map(
+            pool, _pool_filter, [(w, ps, i) for i, w in enumerate(_panels(ncs, workers))])
+        allc["features"] = _timed_pool_map(
+            pool, _pool_filter, [(w, ps, i) for i, w in enumerate(_panels(ds, workers))])
+        allc["kmeans_20_replicates"] = _timed_pool_map(pool, _pool_kmeans, list(range(20)))
+        allc["cg_iteration_all_columns"] = _timed_pool_map(
+            pool, _pool_filter, [(w, ps, i) for i, w in enumerate(_panels(ks, workers))])
+    _POOL.clear()
 
-    out = {
-        "metric": "filter SpMM HBM GB/s (% peak) + end-to-end CSC s/graph vs plain at ARI>=0.99",
-        "value": round(value, 3),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": f"{args.workload}: {wl['model']} N={N} nnz={nnz} k={k} d={d} p={p} "
-                        f"n={api.default_n(k)} n_c={n_c} gamma=1e-3 tol=1e-6",
-            "plain": True,
-        },
-        "s_per_graph": round(ms_per_step / 1e3, 4),
-        "phases_s": {kk: round(v, 4) for kk, v in last.timings.items()},
-        "bisection_steps": last.bisection.steps,
-        "lambda_k": last.lam,
-        "cg_iters_max": int(last.interp.iters.max()),
-        "ari_vs_truth": round(float(ari), 4),
-        "learned": {
-            "s_per_graph": round(ms_learned / 1e3, 4),
-            "bisection_steps": lres[-1].bisection.steps,
-            "lambda_k": lres[-1].lam,
-            "ari_vs_plain": round(float(ari_lp), 4),
-            "ari_vs_truth": round(float(adjusted_rand_index(lres[-1].labels.cpu().numpy(),
-                                                            gr.truth)), 4),
-        },
-        "kpm": {
-            "s_per_graph": round(ms_kpm / 1e3, 4),
-            "moment_passes": 1,
-            "tested_points": kres[-1].bisection.steps,
-            "lambda_k": kres[-1].lam,
-            "ari_vs_plain": round(float(adjusted_rand_index(kres[-1].labels.cpu().numpy(),
-                                                            last.labels.cpu().numpy())), 4),
-            "ari_vs_truth": round(float(adjusted_rand_index(kres[-1].labels.cpu().numpy(),
-                                                            gr.truth)), 4),
-        },
-        "roofline": cands[dom],
-        f"roofline_{other}_step": cands[other],
+    tests, cg_iters = 9, 13  # the oracle's dichotomy tests and CG iterations on this graph
+    if os.path.exists(os.path.join(ROOT, "tests", "golden", "scale_sbm_1e5.npz")):
+        g = np.load(os.path.join(ROOT, "tests", "golden", "scale_sbm_1e5.npz"))
+        tests, cg_iters = int(g["steps"]), int(g["cg_iters"].max())
+    per_graph_1 = {
+        "dichotomy": one["dichotomy_per_test"] * tests,
+        "features": one["features"],
+        "sampling": one["sampling"],
+        "kmeans": one["kmeans_per_replicate"] * 20,
+        "interpolation": one["cg_iteration_per_column"] * ks * cg_iters,
+        "labels": one["labels"],
     }
-    if large is not None:
-        out["chunglu_1e6"] = large
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(gr, k, p)
-    print(json.dumps(out), flush=True)
+    per_graph_n = {
+        "dichotomy": allc["dichotomy_per_test"] * tests,
+        "features": allc["features"],
+        "sampling": one["sampling"],
+        "kmeans": allc["kmeans_20_replicates"],
+        "interpolation": allc["cg_iteration_all_columns"] * cg_iters,
+        "labels": one["labels"],
+    }
+    out.update({
+        "value": round(by / tN / 1e9, 3),
+        "cores": workers,
+        "sample": (f"float64 oracle filter pass on the {N}-node headline graph at d={d} columns: "
+                   f"{hsteps} of its p={p} CSR products, columns split over {workers} worker "
+                   f"processes ({tN:.2f} s); the host reports {os.cpu_count()} CPUs"),
+        "one_core": {"value": round(by / t1 / 1e9, 3), "cores": 1,
+                     "sample": f"the same {hsteps} products on one core ({t1:.2f} s)"},
+        "sbm_1e5_s_per_graph": {
+            "one_core": {kk: round(v, 3) for kk, v in per_graph_1.items()},
+            "all_cores": {kk: round(v, 3) for kk, v in per_graph_n.items()},
+            "total_one_core": round(sum(per_graph_1.values()), 2),
+            "total_all_cores": round(sum(per_graph_n.values()), 2),
+            "sample": (f"N={Ns}, k={ks}, d={ds}, n_c={ncs}, p={ps}: one dichotomy test x {tests} "
+                       f"tests, one feature pass, sampling, k-means replicates (2 on one core, "
+                       f"x10; 20 over the pool), one CG iteration ({cg_cols} columns on one "
+                       f"core, x{ks // cg_cols}; all {ks} over the pool) x {cg_iters} iterations "
+                       f"(the oracle's counts on this graph), labels; graph generation "
+                       f"excluded"),
+        },
+    })
+    return out
 
+
+# ------------------------------------------------------------ GPU timing ---
 
 def count_shape(api, n_c):
     """(group size, block width, measurement-hook kind) of the dichotomy's
@@ -398,57 +366,129 @@ def step_time(api, gr, order, w, p, reps, dev, kind=3):
     return e0.elapsed_time(e1) / 1e3 / (reps * p)
 
 
-def large_shapes(api, args, dev):
-    """The 1e6-node Chung-Lu configuration (k = 250, d = 56, p = 60): one
-    end-to-end run and the per-launch step kernels: the moment step at the
-    count width n_c, the Clenshaw step at the filter width d (natural order)
-    and at the CG width k (in the order that run's interpolation used)."""
+def step_kernels(api, name, gr, wl, last, reps, dev):
+    """Per-launch figures of the three step kernels of the pipeline run
+    `last`: the eigencount moment step (natural order), the feature step
+    (Clenshaw at width d, natural order) and the CG operator's Clenshaw step
+    at width k (in the order the interpolation used)."""
+    N, nnz, k, p = gr.n, gr.nnz, wl["k"], wl["p"]
+    d = int(math.ceil(4 * math.log(N)))
+    n_c = api.count_signals(N)
+    group, count_w, count_kind = count_shape(api, n_c)
+    out = {}
+    for which, w, order, kind, bkind, launches, label in (
+            ("count", count_w, None, count_kind, "mom",
+             -(-last.bisection.steps // group) * moment_steps(p),
+             f"k_cheb_step<EPI_MOMG> (moment step of the eigencount passes, {group} tests of "
+             f"{n_c} signals side by side" if group > 1 else
+             f"k_cheb_step<EPI_MOM> (moment step of the eigencount passes, {n_c} signals"),
+            ("filter", d, None, 3, "clen", p, "k_cheb_step<EPI_CLEN> (Clenshaw step of the feature pass"),
+            ("cg", k, last.order, 3, "clen", int(last.interp.iters.max()) * p,
+             "k_cheb_step<EPI_CLEN> (Clenshaw step of the CG operator pass")):
+        avg_s = step_time(api, gr, order, w, p, reps, dev, kind=kind)
+        # the sparse product alone at this width and order (CSR read, gathered
+        # rows, one block written): the floor under any step of this shape
+        floor_s = step_time(api, gr, order, w, p, reps, dev, kind=5)
+        per_launch = step_bytes(N, nnz, w, bkind)
+        achieved = per_launch / avg_s / 1e9
+        traffic = read_traffic(name, which)
+        out[which] = {
+            "kernel": f"{label}, w={w}, panel width {api.panel_width(N, w, nnz)}"
+                      f"{', community order' if order is not None else ', natural order'})",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            # bytes below L2 per launch (counters) over the launch time
+            "traffic_GBs": None if traffic is None else round(traffic / avg_s / 1e9, 1),
+            "alg_bytes_per_launch": per_launch,
+            "avg_launch_us": round(avg_s * 1e6, 2),
+            "spmm_floor_us": round(floor_s * 1e6, 2),
+            "launches_per_step": launches,
+            "ms_per_step": round(launches * avg_s * 1e3, 3),
+        }
+    return out
+
+
+def timed_runs(api, g, k, d, seed, p, steps, warmup, **kw):
+    import torch
+
+    for _ in range(warmup):
+        api.run(g, k, d, seed, p=p, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [api.run(g, k, d, seed, p=p, **kw) for _ in range(steps)]
+    torch.cuda.synchronize()
+    return res, time.perf_counter() - t0
+
+
+def bench_single(api, name, gr, wl, args, dev, variants):
+    """Timed steps of the plain pipeline on one graph; with `variants`, the
+    learned-bracket and one-pass KPM forms beside it."""
     import torch
 
     from oracle.metrics import adjusted_rand_index  # ARI of the labels only
 
-    wl = WORKLOADS["chunglu-1e6"]
-    gr = make_graph(wl, args.seed)
     N, nnz, k, p = gr.n, gr.nnz, wl["k"], wl["p"]
     d = int(math.ceil(4 * math.log(N)))
+    n_c = api.count_signals(N)
     g = api.Graph(gr.row_ptr, gr.col, dev)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r = api.run(g, k, d, args.seed, p=p)
-    torch.cuda.synchronize()
-    secs = time.perf_counter() - t0
-    out = {"workload": f"chunglu N={N} nnz={nnz} k={k} d={d} p={p} n={api.default_n(k)}",
-           "s_per_graph": round(secs, 3),
-           "phases_s": {kk: round(v, 4) for kk, v in r.timings.items()},
-           "bisection_steps": r.bisection.steps,
-           "cg_iters_max": int(r.interp.iters.max()),
-           "ari_vs_truth": round(float(adjusted_rand_index(r.labels.cpu().numpy(), gr.truth)), 4)}
-    n_c = api.count_signals(N)
-    group, count_w, count_kind = count_shape(api, n_c)
-    for name, w, order, kind, bkind in (("count_step", count_w, None, count_kind, "mom"),
-                                        ("filter_step", d, None, 3, "clen"),
-                                        ("cg_step", k, r.order, 3, "clen")):
-        avg = step_time(api, gr, order, w, p, max(2, args.kernel_reps // 5), dev, kind=kind)
-        by = step_bytes(N, nnz, w, bkind)
-        traffic = read_traffic("cl_" + name)
-        out[name] = {"w": w, "panel_width": api.panel_width(N, w, nnz),
-                     "order": "community" if order is not None else "natural",
-                     "avg_launch_us": round(avg * 1e6, 1), "alg_bytes_per_launch": by,
-                     "achieved_GBs": round(by / avg / 1e9, 1),
-                     "frac": round(by / avg / 1e9 / PEAK_HBM_GBS, 4),
-                     "traffic": traffic,
-                     "traffic_GBs": None if traffic is None else round(traffic / avg / 1e9, 1)}
+    results, elapsed = timed_runs(api, g, k, d, args.seed, p, args.steps, args.warmup)
+    total = sum(job_bytes(N, nnz, k, d, n_c, p, r.bisection.steps, int(r.interp.iters.max()))
+                for r in results)
+    last = results[-1]
+    lab = last.labels.cpu().numpy()
+    out = {
+        "workload": f"{name}: {wl['model']} N={N} nnz={nnz} k={k} d={d} p={p} "
+                    f"n={api.default_n(k)} n_c={n_c} gamma=1e-3 tol=1e-6",
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "value": round(total / elapsed / 1e9, 3),
+        "s_per_graph": round(elapsed / args.steps, 4),
+        "phases_s": {kk: round(v, 4) for kk, v in last.timings.items()},
+        "bisection_steps": last.bisection.steps,
+        "lambda_k": last.lam,
+        "cg_iters_max": int(last.interp.iters.max()),
+        "ari_vs_truth": round(float(adjusted_rand_index(lab, gr.truth)), 4),
+    }
+    if variants:
+        from paper_1602_02018_amd import learned
+
+        mlp = learned.load_params(dev)
+        for key, kw in (("learned", dict(mlp_params=mlp)), ("kpm", dict(lambda_method="kpm"))):
+            res, el = timed_runs(api, g, k, d, args.seed, p, args.steps, 1, **kw)
+            lv = res[-1].labels.cpu().numpy()
+            out[key] = {
+                "s_per_graph": round(el / args.steps, 4),
+                "tested_points": res[-1].bisection.steps,
+                "lambda_k": res[-1].lam,
+                "ari_vs_plain": round(float(adjusted_rand_index(lv, lab)), 4),
+                "ari_vs_truth": round(float(adjusted_rand_index(lv, gr.truth)), 4),
+            }
+    steps_k = step_kernels(api, name, gr, wl, last, args.kernel_reps, dev)
+    dom = max(steps_k, key=lambda c: steps_k[c]["ms_per_step"])
+    out["roofline"] = steps_k[dom]
+    for other in steps_k:
+        if other != dom:
+            out[f"roofline_{other}_step"] = steps_k[other]
+    del g
+    torch.cuda.empty_cache()
     return out
 
 
-def bench_batch(args, wl, dev):
-    """64 SBMs: plain form graph by graph vs batched vs batched + learned bracket."""
+def bench_batch(api, wl, args, dev):
+    """64 SBMs: plain form graph by graph vs batched vs batched + learned
+    bracket, and the agreement of their labels (with each other, with the
+    planted communities and, on the graphs the oracle's results are stored
+    for, with the oracle)."""
     import numpy as np
     import torch
 
     import synth
     from oracle.metrics import adjusted_rand_index
-    from paper_1602_02018_amd import api, learned
+    from paper_1602_02018_amd import learned
 
     gs = synth.sbm_batch(wl["G"], seed=args.seed)
     p = wl["p"]
@@ -460,7 +500,6 @@ def bench_batch(args, wl, dev):
     api.run_batched(G[:4], ks[:4], ds[:4], seeds[:4], p=p, mlp_params=mlp)  # warm-up
     api.run(G[0], ks[0], ds[0], seeds[0], p=p)
     torch.cuda.synchronize()
-    quiet_gc()
 
     def timed(fn):
         torch.cuda.synchronize()
@@ -472,31 +511,26 @@ def bench_batch(args, wl, dev):
     plain, t_plain = timed(lambda: [api.run(g, k, d, s, p=p) for g, k, d, s in zip(G, ks, ds, seeds)])
     batched, t_batched = timed(lambda: api.run_batched(G, ks, ds, seeds, p=p))
     both, t_both = timed(lambda: api.run_batched(G, ks, ds, seeds, p=p, mlp_params=mlp))
+    # the method's own spread: the plain form with other random signals
+    other = api.run_batched(G, ks, ds, [s + 1000 for s in seeds], p=p)
+    lab = {key: [r.labels.cpu().numpy() for r in res]
+           for key, res in (("plain", plain), ("batched", batched), ("both", both), ("other", other))}
 
-    def ari_truth(res):
-        return [adjusted_rand_index(r.labels.cpu().numpy(), g.truth) for r, g in zip(res, gs)]
+    def ari_list(xs, ys):
+        return np.array([adjusted_rand_index(x, y) for x, y in zip(xs, ys)])
 
-    a_plain, a_both = ari_truth(plain), ari_truth(both)
-    a_pair = [adjusted_rand_index(x.labels.cpu().numpy(), y.labels.cpu().numpy())
-              for x, y in zip(both, plain)]
+    a_plain = ari_list(lab["plain"], [g.truth for g in gs])
+    a_both = ari_list(lab["both"], [g.truth for g in gs])
+    a_pair = ari_list(lab["both"], lab["plain"])
+    a_self = ari_list(lab["other"], lab["plain"])
+    a_other = ari_list(lab["other"], [g.truth for g in gs])
+    same_lam = np.array([x.lam == y.lam for x, y in zip(both, plain)])
     total = sum(job_bytes(g.n, g.nnz, k, d, api.count_signals(g.n), p, r.bisection.steps,
                           int(r.interp.iters.max())) for g, k, d, r in zip(gs, ks, ds, both))
     out = {
-        "metric": "filter SpMM HBM GB/s (% peak) + end-to-end CSC s/graph vs plain at ARI>=0.99",
-        "value": round(total / t_both / 1e9, 3),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": 1,
-        "warmup": 1,
-        "ms_per_step": round(t_both * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"batch64: {len(gs)} SBMs, sum N={sum(g.n for g in gs)}, "
-                               f"sum nnz={sum(g.nnz for g in gs)}, k in [10,100], p={p}",
-                   "form": "batched + learned"},
+        "workload": (f"batch64: {len(gs)} SBMs, sum N={sum(g.n for g in gs)}, "
+                     f"sum nnz={sum(g.nnz for g in gs)}, k in [10,100], p={p}"),
+        "value_batched_learned": round(total / t_both / 1e9, 3),
         "s_per_graph": {"plain": round(t_plain / len(gs), 4), "batched": round(t_batched / len(gs), 4),
                         "batched_learned": round(t_both / len(gs), 4)},
         "speedup_vs_plain": round(t_plain / t_both, 3),
@@ -509,13 +543,133 @@ def bench_batch(args, wl, dev):
                          "batched": int(sum(r.interp.iters.max() for r in batched))},
         "bisection_passes": {"plain": int(sum(r.bisection.steps for r in plain)),
                              "batched_learned": int(sum(r.bisection.steps for r in both))},
-        "ari_vs_truth_mean": {"plain": round(float(np.mean(a_plain)), 4),
-                              "batched_learned": round(float(np.mean(a_both)), 4)},
-        "ari_batched_learned_vs_plain": {"median": round(float(np.median(a_pair)), 4),
-                                         "frac_ge_0.99": round(float(np.mean(np.array(a_pair) >= 0.99)), 4)},
-        "batched_identical_to_plain": int(sum(torch.equal(x.labels, y.labels)
-                                              for x, y in zip(batched, plain))),
+        "batched_labels_identical_to_plain": int(sum(np.array_equal(x, y)
+                                                     for x, y in zip(lab["batched"], lab["plain"]))),
+        # equal-ARI criterion of the speed-up: the learned search stops at another
+        # point of the interval where the count rounds to k, so its labels move
+        # against the plain ones; what must not move is the recovery
+        "ari_vs_truth_mean": {"plain": round(float(a_plain.mean()), 4),
+                              "batched_learned": round(float(a_both.mean()), 4)},
+        "ari_vs_truth_delta": {"median": round(float(np.median(a_both - a_plain)), 4),
+                               "min": round(float((a_both - a_plain).min()), 4),
+                               "frac_within_0.01": round(float(np.mean(np.abs(a_both - a_plain) <= 0.01)), 4)},
+        # two plain runs differing only in the random signals (seed + 1000)
+        "ari_plain_other_signals_vs_plain": {
+            "median": round(float(np.median(a_self)), 4),
+            "frac_ge_0.99": round(float(np.mean(a_self >= 0.99)), 4),
+            "ari_vs_truth_mean": round(float(a_other.mean()), 4)},
+        "ari_batched_learned_vs_plain": {
+            "median": round(float(np.median(a_pair)), 4),
+            "frac_ge_0.99": round(float(np.mean(a_pair >= 0.99)), 4),
+            "same_lambda": int(same_lam.sum()),
+            "frac_ge_0.99_same_lambda": (round(float(np.mean(a_pair[same_lam] >= 0.99)), 4)
+                                         if same_lam.any() else None),
+        },
     }
+    if os.path.exists(GOLDEN_BATCH):
+        gold = np.load(GOLDEN_BATCH)
+        vs = {"plain": [], "batched": [], "batched_learned": []}
+        for gi in gold["positions"]:
+            gi = int(gi)
+            vs["plain"].append(adjusted_rand_index(lab["plain"][gi], gold[f"g{gi}_plain_labels"]))
+            vs["batched"].append(adjusted_rand_index(lab["batched"][gi], gold[f"g{gi}_plain_labels"]))
+            vs["batched_learned"].append(adjusted_rand_index(lab["both"][gi], gold[f"g{gi}_learned_labels"]))
+        out["ari_vs_oracle_8_graphs"] = {kk: {"min": round(float(min(v)), 4),
+                                              "frac_ge_0.99": round(float(np.mean(np.array(v) >= 0.99)), 4)}
+                                         for kk, v in vs.items()}
+    del G
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="chunglu-1e6", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the secondary workloads (1e5-node SBM forms, batch of 64)")
+    ap.add_argument("--kernel-reps", type=int, default=4)
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="processes of the all-core CPU baseline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 256 MiB device copy (for scaling memory counters)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        x = torch.ones(64 * 2**20, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4,
+                          "dispatches": 3}), flush=True)
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the path shards by columns across GPUs, which this build does not run)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    wl = WORKLOADS[args.workload]
+    head_gr = None if args.workload == "batch64" else make_graph(wl, args.seed)
+    sbm_wl = WORKLOADS["sbm-1e5"]
+    sbm_gr = head_gr if args.workload == "sbm-1e5" else None
+    if sbm_gr is None and not (args.no_secondary and args.no_cpu_baseline):
+        sbm_gr = make_graph(sbm_wl, args.seed)
+    cpu = None
+    if not args.no_cpu_baseline and head_gr is not None:
+        print(f"cpu baseline ({args.workers} workers) ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(head_gr, wl, sbm_gr, sbm_wl, args.workers)
+
+    import torch
+
+    from paper_1602_02018_amd import api
+
+    dev = torch.device("cuda:0")
+    quiet_gc()
+    out = {"metric": METRIC}
+    if args.workload == "batch64":
+        b = bench_batch(api, wl, args, dev)
+        out.update(value=b.pop("value_batched_learned"), unit="GB/s", n_gpus=1, steps=1, warmup=1,
+                   ms_per_step=round(b["s_per_graph"]["batched_learned"] * 64e3, 3),
+                   higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+                   data="synthetic", config={"workload": b.pop("workload"), "form": "batched + learned"})
+        out.update(b)
+        print(json.dumps(out), flush=True)
+        return
+    print(f"headline {args.workload} ...", file=sys.stderr, flush=True)
+    head = bench_single(api, args.workload, head_gr, wl, args, dev,
+                        variants=args.workload != "chunglu-1e6")
+    out.update({
+        "value": head.pop("value"),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head.pop("ms_per_step"),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": head.pop("workload"), "form": "plain",
+                   "value_is": "whole-pipeline algorithmic bytes / wall time; the SpMM kernel "
+                               "rate is roofline.achieved"},
+    })
+    out.update(head)
+    if not args.no_secondary:
+        if args.workload != "sbm-1e5":
+            print("secondary sbm-1e5 ...", file=sys.stderr, flush=True)
+            out["sbm_1e5"] = bench_single(api, "sbm-1e5", sbm_gr, sbm_wl, args, dev, variants=True)
+        print("secondary batch64 ...", file=sys.stderr, flush=True)
+        out["batch64"] = bench_batch(api, WORKLOADS["batch64"], args, dev)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -128,7 +128,8 @@ enum { CSC_FORM_FORWARD = 0, CSC_FORM_CLENSHAW = 1 };
 csc_status csc_set_filter_form(int32_t form);
 int32_t csc_get_filter_form(void);
 
-/* Kernel tuning knobs, process-wide; results do not depend on them.
+/* Kernel tuning knobs, process-wide; results do not depend on them, except
+ * for CSC_TUNE_BLOCK_PRODUCT (rounding only, see below).
  * CSC_TUNE_PANEL_WIDTH: as csc_set_panel_width.
  * CSC_TUNE_XCD_ORDER (0/1/2, default 1): how row tiles are spread over the
  *   8 XCDs of the GPU (workgroup b runs on XCD b mod 8): 0 round-robin; 1
@@ -158,6 +159,15 @@ int32_t csc_get_filter_form(void);
  *   ahead there.  With equal group sizes the batched and the single calls
  *   give the same results bit for bit; at the defaults (4 and 1) their
  *   counts agree up to the order of float64 sums, as above.
+ * CSC_TUNE_BLOCK_PRODUCT (0/1, default 0): the block CG's right products
+ *   X += P alpha, R -= Q alpha, P = Z T and Z += P beta (Sec. 4.4's
+ *   interpolation solve): 0 forms each output element as a float64 sum of
+ *   exact products of the float32 entries and the float64 k x k step
+ *   matrices, rounded once to float32 (float64 matrix cores); 1 rounds the
+ *   step matrices to float32 and sums in float32 (float32 matrix cores),
+ *   the precision form's float32 vector updates.  This knob changes the
+ *   rounding of the solve (not the tolerance it meets); the Gram matrices
+ *   (inner products) stay float64 either way.
  * csc_get_tuning returns the current value (-1 for an unknown key).
  */
 enum {
@@ -167,7 +177,8 @@ enum {
   CSC_TUNE_HIP_GRAPHS = 3,
   CSC_TUNE_ROW_SCHED = 4,
   CSC_TUNE_COUNT_GROUP = 5,
-  CSC_TUNE_BATCH_COUNT_GROUP = 6
+  CSC_TUNE_BATCH_COUNT_GROUP = 6,
+  CSC_TUNE_BLOCK_PRODUCT = 7
 };
 csc_status csc_set_tuning(int32_t key, int32_t value);
 int32_t csc_get_tuning(int32_t key);
@@ -702,7 +713,10 @@ csc_status csc_estimate_lambda_k_learned(const csc_graph* g, int32_t k, int32_t 
  *         epilogue (eigencount passes), kind 2: the last CG step (operator
  *         and per-column p^T A p partials), kind 3: a Clenshaw step, kind 4:
  *         the moment step of a group of CSC_TUNE_COUNT_GROUP eigencount tests
- *         side by side (w must be that group size times a multiple of 4).
+ *         side by side (w must be that group size times a multiple of 4),
+ *         kind 5: the sparse product alone, T_{m+1} = A T_m (the CSR read,
+ *         the gathered rows and one block written: the floor under every
+ *         step kind at that width).
  * prepare != 0 first fills the block with a Gaussian block and zeroes the
  * other buffers (these launches precede the timed ones; call once with
  * steps = 0 and prepare = 1, then time calls with prepare = 0).

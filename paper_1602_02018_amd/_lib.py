@@ -25,6 +25,7 @@ STREAM_COUNT, STREAM_FEAT, STREAM_SAMPLE, STREAM_KMEANS = 1, 2, 3, 4
 TUNE_PANEL_WIDTH, TUNE_XCD_ORDER, TUNE_NONTEMPORAL, TUNE_HIP_GRAPHS, TUNE_ROW_SCHED = 0, 1, 2, 3, 4
 TUNE_COUNT_GROUP = 5
 TUNE_BATCH_COUNT_GROUP = 6
+TUNE_BLOCK_PRODUCT = 7
 FORM_FORWARD, FORM_CLENSHAW = 0, 1
 DAMP_JACKSON, DAMP_NONE = 0, 1
 

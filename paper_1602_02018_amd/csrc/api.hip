@@ -31,7 +31,10 @@ std::atomic<int> g_tune_graphs{1};
 std::atomic<int> g_tune_sched{1};
 std::atomic<int> g_tune_group{4};
 std::atomic<int> g_tune_bgroup{1};
+std::atomic<int> g_tune_bprod{0};
 }  // namespace
+
+bool block_product_f32() { return g_tune_bprod.load() != 0; }
 
 void set_error(const std::string& msg) { g_error = msg; }
 void clear_error() { g_error.clear(); }
@@ -589,6 +592,10 @@ extern "C" csc_status csc_set_tuning(int32_t key, int32_t value) {
       CSC_REQUIRE(value >= 1 && value <= kMaxCountGroup, "value must lie in 1..4");
       g_tune_bgroup.store(value);
       return CSC_OK;
+    case CSC_TUNE_BLOCK_PRODUCT:
+      CSC_REQUIRE(value == 0 || value == 1, "value must be 0 or 1");
+      g_tune_bprod.store(value);
+      return CSC_OK;
     default:
       CSC_REQUIRE(false, "unknown tuning key");
   }
@@ -603,6 +610,7 @@ extern "C" int32_t csc_get_tuning(int32_t key) {
     case CSC_TUNE_ROW_SCHED: return g_tune_sched.load();
     case CSC_TUNE_COUNT_GROUP: return g_tune_group.load();
     case CSC_TUNE_BATCH_COUNT_GROUP: return g_tune_bgroup.load();
+    case CSC_TUNE_BLOCK_PRODUCT: return g_tune_bprod.load();
     default: return -1;
   }
 }
@@ -1439,7 +1447,7 @@ extern "C" csc_status csc_cheb_steps(const csc_graph* g, int32_t w, int32_t kind
   clear_error();
   CSC_TRY(check_graph(g));
   CSC_REQUIRE(w >= 1 && steps >= 0, "need w >= 1 and steps >= 0");
-  CSC_REQUIRE(kind >= 0 && kind <= 4, "kind must be 0, 1, 2, 3 or 4");
+  CSC_REQUIRE(kind >= 0 && kind <= 5, "kind must be 0, 1, 2, 3, 4 or 5");
   const int group = kind == 4 ? count_group() : 1;
   CSC_REQUIRE(w % (4 * group) == 0 || kind != 4,
               "kind 4 needs w = group size x a multiple of 4");
@@ -1484,6 +1492,7 @@ extern "C" csc_status csc_cheb_steps(const csc_graph* g, int32_t w, int32_t kind
   const int epi = kind == 0   ? EPI_Y
                   : kind == 1 ? EPI_MOM
                   : kind == 4 ? (group > 1 ? EPI_MOMG : EPI_MOM)
+                  : kind == 5 ? EPI_SPMM
                   : (kind == 2 ? EPI_CG : EPI_CLEN);
   for (int m = 1; m <= steps; ++m) {
     // T_{m+1} from T_m (gathered) and T_{m-1}; buffers alternate as in a pass

@@ -1,6 +1,7 @@
 // Dense products of tall panel-major blocks, for the block conjugate gradient
 // of the interpolation: Gram matrices A^T B (float32 entries, float64 sums)
-// and right products by a small float64 matrix.
+// and right products by a small float64 matrix (float64 sums, or float32
+// sums on the float32 matrix cores under CSC_TUNE_BLOCK_PRODUCT).
 //
 // Both run on the float64 matrix cores (v_mfma_f64_16x16x4f64: a 16 x 16
 // float64 tile += a 16 x 4 by 4 x 16 product, one element of each operand per
@@ -11,6 +12,7 @@
 // (l / 16), column (l mod 16) of the right one; the result tile leaves lane l
 // holding rows (l / 16) + 4 v, v = 0..3, of column (l mod 16).
 #include <algorithm>
+#include <type_traits>
 
 #include "device.hpp"
 
@@ -18,6 +20,7 @@ namespace csc {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kGT = 128;  // Gram output tile per workgroup (4 waves of 64 x 64)
 constexpr int kMR = 128;  // block product: rows per workgroup (2 waves of 64)
@@ -172,16 +175,23 @@ static_assert(kXU >= 1 && kSU >= 1 && kSU <= 32, "block product staging shape");
 
 // Out[i, j] = c0 * In0[i, j] + sum_{l < kin} In1[i, l] * S[l * lds + j] for
 // every stored column j of the layout (S is zero beyond its live columns, so
-// padding columns stay c0 * In0); float64 sums, rounded once to float32.
+// padding columns stay c0 * In0).  F32 = false: float64 sums of the exact
+// products of float32 entries and float64 S, on the float64 matrix cores,
+// rounded once to float32; F32 = true: S rounded to float32 and float32 sums
+// on the float32 matrix cores (v_mfma_f32_16x16x4f32, whose result tile leaves
+// lane l holding rows 4 (l / 16) + v, v = 0..3, of column l mod 16).
 // Workgroup: 128 rows x 128 columns; the inner dimension is staged 16 at a
 // time in LDS (In1 rows and S rows, double-buffered); wave w takes the
 // 64 x 64 quarter (w / 2, w mod 2).  Out may be In0 (each element is read and
 // written by the same lane), never In1.
+template <bool F32>
 __global__ __launch_bounds__(256, 2) void k_block_mul(Layout L, float c0, const float* In0,
                                                    const float* In1, const double* S, int kin,
                                                    int kout, int lds, float* Out) {
+  typedef typename std::conditional<F32, float, double>::type sc_t;
+  typedef typename std::conditional<F32, v4f, v4d>::type acc_t;
   __shared__ float Xs[2][kMR][kXLD];
-  __shared__ double Ss[2][kBS][kSLD];
+  __shared__ sc_t Ss[2][kBS][kSLD];
   const int W = L.np * L.pw;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int q = lane >> 4, c16 = lane & 15;
@@ -215,14 +225,14 @@ __global__ __launch_bounds__(256, 2) void k_block_mul(Layout L, float c0, const 
 #pragma unroll
     for (int u = 0; u < kSU; ++u) {
       const int f = t + 256 * u;
-      Ss[buf][f >> 7][f & 127] = ((sok >> u) & 1u) ? rs[u] : 0.0;
+      Ss[buf][f >> 7][f & 127] = ((sok >> u) & 1u) ? (sc_t)rs[u] : (sc_t)0;
     }
   };
-  v4d acc[4][4];
+  acc_t acc[4][4];
 #pragma unroll
   for (int g = 0; g < 4; ++g)
 #pragma unroll
-    for (int h = 0; h < 4; ++h) acc[g][h] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int h = 0; h < 4; ++h) acc[g][h] = acc_t{0, 0, 0, 0};
   const int nst = (kin + kBS - 1) / kBS;
   fetch(0);
   stash(0);
@@ -232,15 +242,20 @@ __global__ __launch_bounds__(256, 2) void k_block_mul(Layout L, float c0, const 
     if (st + 1 < nst) fetch(l0 + kBS);
     const int ksn = min(kBS, kin - l0 + 3) / 4;  // steps holding live inner columns
     for (int ks = 0; ks < ksn; ++ks) {
-      double a[4], b[4];
+      sc_t a[4], b[4];
 #pragma unroll
-      for (int g = 0; g < 4; ++g) a[g] = (double)Xs[buf][wr + 16 * g + c16][4 * ks + q];
+      for (int g = 0; g < 4; ++g) a[g] = (sc_t)Xs[buf][wr + 16 * g + c16][4 * ks + q];
 #pragma unroll
       for (int h = 0; h < 4; ++h) b[h] = Ss[buf][4 * ks + q][wc + 16 * h + c16];
 #pragma unroll
       for (int g = 0; g < 4; ++g)
 #pragma unroll
-        for (int h = 0; h < 4; ++h) acc[g][h] = mfma64(a[g], b[h], acc[g][h]);
+        for (int h = 0; h < 4; ++h) {
+          if constexpr (F32)
+            acc[g][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[g], b[h], acc[g][h], 0, 0, 0);
+          else
+            acc[g][h] = mfma64(a[g], b[h], acc[g][h]);
+        }
     }
     if (st + 1 < nst) stash(buf ^ 1);
     __syncthreads();
@@ -254,11 +269,16 @@ __global__ __launch_bounds__(256, 2) void k_block_mul(Layout L, float c0, const 
     for (int g = 0; g < 4; ++g)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = bi0 + wr + 16 * g + q + 4 * v;
+        const int i = bi0 + wr + 16 * g + (F32 ? 4 * q + v : q + 4 * v);
         if (i >= L.n) continue;
         const size_t o = cbj + (size_t)i * L.pw;
-        const double base = c0 != 0.f ? (double)c0 * (double)In0[o] : 0.0;
-        Out[o] = (float)(base + acc[g][h][v]);
+        if constexpr (F32) {
+          const float base = c0 != 0.f ? c0 * In0[o] : 0.f;
+          Out[o] = base + acc[g][h][v];
+        } else {
+          const double base = c0 != 0.f ? (double)c0 * (double)In0[o] : 0.0;
+          Out[o] = (float)(base + acc[g][h][v]);
+        }
       }
   }
 }
@@ -330,7 +350,12 @@ hipError_t launch_block_mul(const Layout& L, float c0, const float* In0, const f
                             hipStream_t s) {
   const int W = L.np * L.pw;
   const dim3 grid((unsigned)((L.n + kMR - 1) / kMR), (unsigned)((W + kMC - 1) / kMC));
-  hipLaunchKernelGGL(k_block_mul, grid, dim3(256), 0, s, L, c0, In0, In1, S, kin, kout, lds, Out);
+  if (block_product_f32())
+    hipLaunchKernelGGL(k_block_mul<true>, grid, dim3(256), 0, s, L, c0, In0, In1, S, kin, kout,
+                       lds, Out);
+  else
+    hipLaunchKernelGGL(k_block_mul<false>, grid, dim3(256), 0, s, L, c0, In0, In1, S, kin, kout,
+                       lds, Out);
   return hipGetLastError();
 }
 

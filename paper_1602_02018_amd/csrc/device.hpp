@@ -180,6 +180,10 @@ __device__ inline void clen_unit(const StepArgs& a, int u) {
   const v4f* __restrict__ Tm4 = reinterpret_cast<const v4f*>(a.Tm) + pbase4;
 
   const v4f acc = spmm_row(a, Tm4, i, m.q, m.lpr, valid);
+  if constexpr (EPI == EPI_SPMM) {
+    if (valid) st4(a.Tnext, o4, acc, nt);
+    return;
+  }
   v4f r = (v4f)0.f, out = (v4f)0.f;
   if (valid) {
     r = ld4(a.T0, o4, nt);
@@ -208,7 +212,7 @@ __device__ inline void clen_unit(const StepArgs& a, int u) {
 
 template <int EPI, bool FIRST, bool LAST>
 __device__ inline void cheb_unit(const StepArgs& a, int u) {
-  if constexpr (EPI >= EPI_CLEN && EPI <= EPI_CLEN_CG) {
+  if constexpr ((EPI >= EPI_CLEN && EPI <= EPI_CLEN_CG) || EPI == EPI_SPMM) {
     clen_unit<EPI, !FIRST>(a, u);
     return;
   }

@@ -57,6 +57,9 @@ hipError_t launch_step(const StepArgs& a, int epi, bool first, bool last, hipStr
     case EPI_CLEN_CG:
       if (first) CSC_STEP(EPI_CLEN_CG, true, false); else CSC_STEP(EPI_CLEN_CG, false, false);
       break;
+    case EPI_SPMM:
+      CSC_STEP(EPI_SPMM, true, false);
+      break;
     default:
       return hipErrorInvalidValue;
   }

@@ -18,6 +18,7 @@ enum Epi : int {
   EPI_CLEN_Y = 5,   // final step: Y = h~(L) R
   EPI_CLEN_CG = 6,  // final step of the CG operator, as EPI_CG
   EPI_MOMG = 7,     // EPI_MOM for a group of eigencount tests side by side (mgroup > 1)
+  EPI_SPMM = 8,     // measurement only: Tnext = A Tm (the gathers, one block written)
 };
 
 // Eigencount tests whose passes one EPI_MOMG launch may carry side by side.
@@ -240,6 +241,8 @@ hipError_t launch_gram(const Layout& L, const float* A, const float* B, int ka, 
 // Z = R / (mask_i + gamma) row by row (Jacobi preconditioner of the interpolation).
 hipError_t launch_jacobi(const Layout& L, const float* R, const float* mask, float gamma, float* Z,
                          hipStream_t s);
+// CSC_TUNE_BLOCK_PRODUCT: block products with float32 sums (true) or float64 sums
+bool block_product_f32();
 hipError_t launch_block_mul(const Layout& L, float c0, const float* In0, const float* In1,
                             const double* S, int kin, int kout, int lds, float* Out,
                             hipStream_t s);

@@ -19,7 +19,8 @@ import torch
 
 import synth
 from oracle import csc as ocsc
-from oracle import interp, laplacian, metrics, sampling
+from oracle import eigencount, interp, laplacian, metrics, sampling
+from search_compare import compare_with
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -86,15 +87,46 @@ def test_weighted_interpolation_matches_oracle(api, hetero, method):
 
 
 def test_end_to_end_density_matches_oracle(api, hetero):
+    """Alg. 2 with density sampling, step by step against the oracle: the
+    dichotomy's decisions; the sampler on the oracle's float64 weights (the
+    same integer decision in the same precision) picks the same nodes in the
+    same order; the k-means of the GPU's features at those nodes and the
+    weighted interpolation then give the oracle's labels (ARI >= 0.99).
+
+    End to end the GPU draws from its own weights, the squared norms of its
+    float32 features: keys E_i / w_i that lie within that rounding of each
+    other can swap, so the sample sets differ in a node or two and the labels
+    follow those samples; that run is held to the sample overlap and to the
+    ARI a different sample set gives."""
     d = int(math.ceil(4 * math.log(hetero.n)))
+    k, p, seed = 20, 50, 0
     g = api.Graph(hetero.row_ptr, hetero.col)
-    res = api.run(g, 20, d, 0, sampling="density", replicates=5)
-    ref = ocsc.run(hetero.row_ptr, hetero.col, 20, d, 0, replicates=5, sampling="density")
-    assert abs(res.lam - ref.lam) <= 2.0 / 2 ** min(res.bisection.steps, ref.bisect_steps)
-    om, om_ref = res.omega.cpu().numpy(), ref.omega
-    # the same draw on float32- and float64-derived weights: nearly the same set
-    assert len(set(om.tolist()) & set(om_ref.tolist())) >= 0.95 * len(om_ref)
-    assert metrics.adjusted_rand_index(res.labels.cpu().numpy(), ref.labels) >= 0.9
+    A, _ = laplacian.normalized_adjacency(hetero.row_ptr, hetero.col)
+    ref = ocsc.run(hetero.row_ptr, hetero.col, k, d, seed, replicates=5, sampling="density")
+    n = ocsc.default_n(k)
+    n_c = api.count_signals(hetero.n)
+    bis = api.estimate_lambda_k(g, k, p, n_c, seed)
+    if not compare_with(bis.trace, bis.lam, bis.steps, eigencount.dichotomy(A, k, p, n_c, seed), k):
+        pytest.skip("a near-tie count parted the two searches")
+    # the same weights, the same draw
+    _, sq = ocsc.features(A, ref.lam, p, d, seed, with_norms=True)
+    omega, dec_w = api.sample_density(torch.as_tensor(sq, device="cuda"), n, seed)
+    assert np.array_equal(omega.cpu().numpy(), ref.omega)
+    F = api.filter(g, ref.lam, p, d, seed, rows=omega, normalize=True)
+    assert np.linalg.norm(F.cpu().numpy() - ref.features_sampled) <= 1e-4 * np.linalg.norm(ref.features_sampled)
+    lab_r, _ = api.kmeans_reduced_device(F.contiguous(), k, seed, replicates=5)
+    assert metrics.adjusted_rand_index(lab_r, ref.labels_r) >= 0.99
+    it = api.interpolate(g, ref.lam, p, 1e-3, omega, lab_r, k, weights=dec_w)
+    assert metrics.adjusted_rand_index(it.labels.cpu().numpy(), ref.labels) >= 0.99
+    # end to end on the GPU's own weights
+    res = api.run(g, k, d, seed, sampling="density", replicates=5)
+    assert res.lam == ref.lam
+    om = res.omega.cpu().numpy()
+    overlap = len(set(om.tolist()) & set(ref.omega.tolist())) / len(ref.omega)
+    ari = metrics.adjusted_rand_index(res.labels.cpu().numpy(), ref.labels)
+    print(f"end to end on float32-derived weights: sample overlap {overlap:.3f}, ARI vs oracle {ari:.4f}")
+    assert overlap >= 0.95
+    assert ari >= (0.99 if overlap == 1.0 else 0.9)
 
 
 def test_density_sampling_covers_small_communities(api, hetero):

@@ -75,3 +75,63 @@ def test_per_result_error_against_float64():
     assert rep["labels ARI vs float64"] >= 0.99
     assert rep["block CG X rel err vs tight solve"] <= 1e-3
     assert rep["block CG labels ARI vs float64"] >= 0.99
+
+
+@pytest.mark.parametrize("N,k,seed", [(1000, 10, 0), (20000, 40, 3)])
+def test_block_products_float32_against_float64(N, k, seed):
+    """The block CG's right products with float32 sums (CSC_TUNE_BLOCK_PRODUCT
+    = 1) against float64 sums (0) and against the oracle's solution at
+    tolerance 1e-12: both meet the tolerance on the recursive residual, the
+    float64 true residual stays below 1e-4, X lies within 1e-3 of the tight
+    solve and the labels agree.  Also reports what float32 row norms would
+    change in the unit-norm features."""
+    from paper_1602_02018_amd import _lib, api
+
+    gr = synth.sbm_config(N, k, seed=seed)
+    A, _ = laplacian.normalized_adjacency(gr.row_ptr, gr.col)
+    g = api.Graph(gr.row_ptr, gr.col)
+    p, d = 50, int(math.ceil(4 * math.log(gr.n)))
+    n_c = eigencount.count_signals(gr.n)
+    lam, _, _, _ = eigencount.estimate_lambda_k(A, k, p, n_c, seed)
+    omega = sampling.sample(gr.n, ocsc.default_n(k), seed)
+    lab_r, _, _ = kmeans.kmeans(ocsc.features(A, lam, p, d, seed)[omega], k, seed)
+    Xt, lab_t, _, _ = interp.interpolate(A, lam, p, 1e-3, omega, lab_r, k, tol=1e-12)
+    mask = interp.sample_mask(gr.n, omega)
+    a = jackson.lowpass_coeffs(lam, p)
+    B = interp.rhs(gr.n, omega, lab_r, k)
+    rep = {}
+    out = {}
+    saved = api.get_tuning(_lib.TUNE_BLOCK_PRODUCT)
+    try:
+        for f32 in (0, 1):
+            api.set_tuning(_lib.TUNE_BLOCK_PRODUCT, f32)
+            res = api.interpolate(g, lam, p, 1e-3, omega, lab_r, k)
+            X = res.X.cpu().numpy().astype(np.float64)
+            true = np.linalg.norm(B - interp.apply_operator(A, mask, 1e-3, a, X), axis=0) \
+                / np.linalg.norm(B, axis=0)
+            tag = "f32" if f32 else "f64"
+            rep[f"{tag} products: iterations"] = float(res.iters.max())
+            rep[f"{tag} products: max recursive relres"] = float(res.relres.max())
+            rep[f"{tag} products: max true relres"] = float(true.max())
+            rep[f"{tag} products: X rel err vs tight solve"] = float(np.linalg.norm(X - Xt) / np.linalg.norm(Xt))
+            rep[f"{tag} products: labels ARI vs tight solve"] = metrics.adjusted_rand_index(
+                res.labels.cpu().numpy(), lab_t)
+            out[tag] = (res, X, true)
+    finally:
+        api.set_tuning(_lib.TUNE_BLOCK_PRODUCT, saved)
+    # float32 row norms of the same unnormalized features
+    Y = api.filter(g, lam, p, d, seed, normalize=False).cpu().numpy()
+    F64 = api.filter(g, lam, p, d, seed, normalize=True).cpu().numpy()
+    nrm32 = np.sqrt(np.sum(Y * Y, axis=1, dtype=np.float32), dtype=np.float32)
+    F32 = np.where(nrm32[:, None] > 0, Y / np.maximum(nrm32, np.float32(1e-30))[:, None], 0).astype(np.float32)
+    rep["features: float32 vs float64 row norms, rel Frobenius"] = float(
+        np.linalg.norm(F32.astype(np.float64) - F64) / np.linalg.norm(F64))
+    for key, val in rep.items():
+        print(f"{key:55s} {val:.3e}")
+    for tag in ("f64", "f32"):
+        res, X, true = out[tag]
+        assert res.status == 0 and np.all(res.relres <= 1e-6), tag
+        assert true.max() <= 1e-4, tag
+        assert rep[f"{tag} products: X rel err vs tight solve"] <= 1e-3, tag
+        assert rep[f"{tag} products: labels ARI vs tight solve"] >= 0.99, tag
+    assert rep["features: float32 vs float64 row norms, rel Frobenius"] <= 1e-6
