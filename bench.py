@@ -53,6 +53,7 @@ PROF = os.path.join(ROOT, "profiles")
 COUNTERS = {
     ("sbm-1e5", "count"): os.path.join(PROF, "cheb_step_count_sbm_N1e5_4x24_counters.txt"),
     ("sbm-1e5", "cg"): os.path.join(PROF, "cheb_step_cg_sbm_N1e5_k100_counters.txt"),
+    ("sbm-1e5", "filter"): os.path.join(PROF, "cheb_step_filter_sbm_N1e5_w47_counters.txt"),
     ("chunglu-1e6", "count"): os.path.join(PROF, "cheb_step_count_chunglu_N1e6_4x28_counters.txt"),
     ("chunglu-1e6", "filter"): os.path.join(PROF, "cheb_step_filter_chunglu_N1e6_w56_counters.txt"),
     ("chunglu-1e6", "cg"): os.path.join(PROF, "cheb_step_cg_chunglu_N1e6_k250_counters.txt"),
@@ -582,6 +583,51 @@ def bench_batch(api, wl, args, dev):
     return out
 
 
+def gather_ceiling(dev, reps=20):
+    """The rate at which the GPU serves gathered rows: the sparse product alone
+    (csc_cheb_steps kind 5: CSR read, every neighbour row gathered, one block
+    written) on random graphs of mean degree 20 (uniform endpoints, random
+    node order), for gathered blocks from L2-sized to far beyond the
+    Infinity Cache.  Reported as 128-byte cache lines of gathered rows per
+    second: a row of w float32 values spans 4w/128 lines (w a multiple of
+    32), so this is the ceiling any step kernel of that width meets when its
+    gathers miss."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1602_02018_amd import api
+
+    rows = []
+    for logn in (16, 18, 20, 21):
+        N = 1 << logn
+        rng = np.random.default_rng(logn)
+        u = rng.integers(0, N, size=10 * N)
+        v = rng.integers(0, N, size=10 * N)
+        rp, cl = synth.csr_from_edges(N, u, v)
+        g = api.Graph(rp, cl, dev)
+        for w in (32, 64, 256):
+            st = api.StepTimer(g, w, 5)
+            st.launch(5)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            st.launch(reps)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / 1e3 / reps
+            lines = len(cl) * (4 * w // 128)
+            rows.append({"N": N, "nnz": int(len(cl)), "w": w, "gathered_block_MB": round(N * w * 4 / 2**20, 1),
+                         "us": round(t * 1e6, 2), "G_lines_per_s": round(lines / t / 1e9, 2),
+                         "gathered_GBs": round(lines * 128 / t / 1e9, 1)})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            del st
+        del g
+        torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -597,7 +643,14 @@ def main():
                     help="processes of the all-core CPU baseline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 256 MiB device copy (for scaling memory counters)")
+    ap.add_argument("--gather-ceiling", action="store_true",
+                    help="run only the gathered-row rate of the sparse product on random graphs")
     args = ap.parse_args()
+    if args.gather_ceiling:
+        import torch
+
+        print(json.dumps({"gather_ceiling": gather_ceiling(torch.device("cuda:0"))}), flush=True)
+        return
     if args.calibrate_copy:
         import torch
 
