@@ -99,12 +99,33 @@ def moment_steps(p):
     return (p + 1) // 2
 
 
+def live_widths(iters):
+    """Columns still iterating at each block-CG iteration t = 1, 2, ... (a
+    column leaves the block once it meets the tolerance; iters[j] is the
+    iteration at which it did, 0 for a zero right-hand side)."""
+    import numpy as np
+
+    it = np.asarray(iters)
+    return [int(np.sum(it >= t)) for t in range(1, int(it.max(initial=0)) + 1)]
+
+
 def job_bytes(N, nnz, k, d, n_c, p, bis_steps, cg_iters):
+    """Algorithmic bytes of one pipeline run; cg_iters: the per-column
+    iteration counts of the interpolation (each CG iteration counts its live
+    columns)."""
     gauss = 4 * N
     count = bis_steps * (gauss * n_c + moment_steps(p) * step_bytes(N, nnz, n_c, "mom"))
     feat = gauss * d + p * step_bytes(N, nnz, d, "clen") + 8 * N * d
-    cg = cg_iters * (p * step_bytes(N, nnz, k, "clen") + BLOCK_CG_BLOCKS * 4 * N * k)
+    cg = sum(p * step_bytes(N, nnz, w, "clen") + BLOCK_CG_BLOCKS * 4 * N * w
+             for w in live_widths(cg_iters))
     return count + feat + cg
+
+
+def full_width_iterations(iters, k):
+    """Block-CG iterations whose operator pass runs at the full width k: the
+    library runs the pass on a compact copy of the live columns once they fit
+    in half the block (counted here by live columns, an upper bound)."""
+    return sum(1 for w in live_widths(iters) if 2 * w > k)
 
 
 def kernel_hash():
@@ -384,7 +405,7 @@ def step_kernels(api, name, gr, wl, last, reps, dev):
              f"{n_c} signals side by side" if group > 1 else
              f"k_cheb_step<EPI_MOM> (moment step of the eigencount passes, {n_c} signals"),
             ("filter", d, None, 3, "clen", p, "k_cheb_step<EPI_CLEN> (Clenshaw step of the feature pass"),
-            ("cg", k, last.order, 3, "clen", int(last.interp.iters.max()) * p,
+            ("cg", k, last.order, 3, "clen", full_width_iterations(last.interp.iters, k) * p,
              "k_cheb_step<EPI_CLEN> (Clenshaw step of the CG operator pass")):
         avg_s = step_time(api, gr, order, w, p, reps, dev, kind=kind)
         # the sparse product alone at this width and order (CSR read, gathered
@@ -438,7 +459,7 @@ def bench_single(api, name, gr, wl, args, dev, variants):
     g = api.Graph(gr.row_ptr, gr.col, dev)
     torch.cuda.synchronize()
     results, elapsed = timed_runs(api, g, k, d, args.seed, p, args.steps, args.warmup)
-    total = sum(job_bytes(N, nnz, k, d, n_c, p, r.bisection.steps, int(r.interp.iters.max()))
+    total = sum(job_bytes(N, nnz, k, d, n_c, p, r.bisection.steps, r.interp.iters)
                 for r in results)
     last = results[-1]
     lab = last.labels.cpu().numpy()
@@ -452,6 +473,7 @@ def bench_single(api, name, gr, wl, args, dev, variants):
         "bisection_steps": last.bisection.steps,
         "lambda_k": last.lam,
         "cg_iters_max": int(last.interp.iters.max()),
+        "cg_live_columns_per_iteration": live_widths(last.interp.iters),
         "ari_vs_truth": round(float(adjusted_rand_index(lab, gr.truth)), 4),
     }
     if variants:
@@ -527,7 +549,7 @@ def bench_batch(api, wl, args, dev):
     a_other = ari_list(lab["other"], [g.truth for g in gs])
     same_lam = np.array([x.lam == y.lam for x, y in zip(both, plain)])
     total = sum(job_bytes(g.n, g.nnz, k, d, api.count_signals(g.n), p, r.bisection.steps,
-                          int(r.interp.iters.max())) for g, k, d, r in zip(gs, ks, ds, both))
+                          r.interp.iters) for g, k, d, r in zip(gs, ks, ds, both))
     out = {
         "workload": (f"batch64: {len(gs)} SBMs, sum N={sum(g.n for g in gs)}, "
                      f"sum nnz={sum(g.nnz for g in gs)}, k in [10,100], p={p}"),

@@ -1133,6 +1133,12 @@ csc_status pre_launch(BlockState& st, hipStream_t s) {
 }
 
 void pre_host(BlockState& st) {
+  // columns that met the tolerance leave the search space; their X and R
+  // stay as they were when they converged (post_host_a)
+  const int k = st.k;
+  for (int j = 0; j < k; ++j)
+    if (st.done[j])
+      for (int i = 0; i < k; ++i) st.G[(size_t)j * k + i] = st.G[(size_t)i * k + j] = 0.0;
   st.sr = dense::orth_transform(st.G, st.k, 1e-10, st.T);
   if (st.sr == 0) {  // Z = 0: every residual column vanished
     st.finished = true;
@@ -1171,6 +1177,9 @@ void post_host_a(BlockState& st) {
     return;
   }
   dense::chol_solve(st.W, sr, sr, st.C, k, 1.0);
+  for (int j = 0; j < k; ++j)
+    if (st.done[j])
+      for (int r = 0; r < sr; ++r) st.C[(size_t)r * k + j] = 0.0;
   st.N = st.C;
   for (auto& v : st.N) v = -v;
 }
@@ -1227,6 +1236,35 @@ csc_status post_finish(BlockState& st, hipStream_t s) {
   const int k = st.k, sr = st.sr;
   CSC_TRY(upload_d(b.S_b, st.C, s));
   CSC_HIP(launch_block_mul(st.L, 1.f, st.jacobi ? b.Z : b.R, b.P, b.S_b, sr, k, k, b.Z, s));
+  return CSC_OK;
+}
+
+// Q = M P for the block CG.  P's live columns are its first sr; when they
+// fit twice in one of the two recurrence buffers, the pass runs on a compact
+// copy of them (a layout of width sr with its own panel width) inside those
+// buffers, and only those columns of Q are written back (the block CG reads
+// no column of Q beyond sr).  Every element sums its row's neighbours in CSR
+// order whatever the layout, so Q is the same either way; a block whose
+// columns have mostly converged costs a pass of its live width.
+static csc_status block_pass(const csc_graph& g, const Layout& L, const double* a, int p, const Pass& pb,
+                      int sr, hipStream_t s) {
+  const Layout Lc = make_layout(L.n, std::max(sr, 1), choose_panel_width(L.n, std::max(sr, 1), g.nnz));
+  const size_t half = (Lc.elems() + 63) / 64 * 64;
+  // the compact pass writes its column partials into the wide pass's buffer
+  const bool part_fits =
+      (size_t)Lc.np * Lc.pw * tiles_for(Lc) <= (size_t)L.np * L.pw * tiles_for(L);
+  if (sr < 1 || sr >= L.w || 2 * half > L.elems() || !part_fits)
+    return chebyshev_pass(g, L, a, p, EPI_CG, pb, s);
+  Pass pc = pb;
+  float* Pc = pb.Ta;
+  float* Qc = pb.Ta + half;
+  pc.T0 = Pc;
+  pc.Ta = pb.Tb;
+  pc.Tb = pb.Tb + half;
+  pc.Y = Qc;
+  CSC_HIP(launch_to_compact(Lc, Pc, L, pb.T0, sr, s));
+  CSC_TRY(chebyshev_pass(g, Lc, a, p, EPI_CG, pc, s));
+  CSC_HIP(launch_from_compact(Lc, Qc, L, pb.Y, sr, s));
   return CSC_OK;
 }
 
@@ -1371,7 +1409,7 @@ extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* orde
     for (int it = 1; it <= max_iter && !bs.finished; ++it) {
       CSC_TRY(block_pre(bs, s));
       if (bs.finished) break;
-      CSC_TRY(chebyshev_pass(*g, L, a.data(), p, EPI_CG, pb, s));  // Q = M P
+      CSC_TRY(block_pass(*g, L, a.data(), p, pb, bs.sr, s));  // Q = M P
       CSC_TRY(block_post(bs, it, max_iter, s));
     }
     block_finish(bs, max_iter);

@@ -169,6 +169,30 @@ __global__ void k_gaussian_rows(int n_rows, int w, uint64_t seed, uint32_t t, ui
 }
 
 // -------------------------------------------------------------- layout ---
+// Columns [0, wc) of a block between a wide layout Lw and a compact layout
+// Lc (one thread per element of Lc; Lc's columns from wc on are zero).
+__global__ void k_to_compact(Layout Lc, float* dst, Layout Lw, const float* src, int wc) {
+  const size_t total = Lc.elems(), pe = Lc.panel_elems(), pw_pe = Lw.panel_elems();
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t q = idx / pe, rem = idx - q * pe;
+    const size_t i = rem / Lc.pw;
+    const int cg = (int)q * Lc.pw + (int)(rem - i * Lc.pw);
+    dst[idx] = cg < wc ? src[(size_t)(cg / Lw.pw) * pw_pe + i * Lw.pw + cg % Lw.pw] : 0.f;
+  }
+}
+
+__global__ void k_from_compact(Layout Lc, const float* src, Layout Lw, float* dst, int wc) {
+  const size_t total = Lc.elems(), pe = Lc.panel_elems(), pw_pe = Lw.panel_elems();
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t q = idx / pe, rem = idx - q * pe;
+    const size_t i = rem / Lc.pw;
+    const int cg = (int)q * Lc.pw + (int)(rem - i * Lc.pw);
+    if (cg < wc) dst[(size_t)(cg / Lw.pw) * pw_pe + i * Lw.pw + cg % Lw.pw] = src[idx];
+  }
+}
+
 __global__ void k_pack(Layout L, const float* X, int ld, float* out) {
   const size_t total = L.elems(), pe = L.panel_elems();
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -423,6 +447,22 @@ hipError_t launch_gaussian_rows(int n_rows, int w, uint64_t seed, uint32_t t, ui
 
 hipError_t launch_pack(const Layout& L, const float* X, int ld, float* out, hipStream_t s) {
   hipLaunchKernelGGL(k_pack, dim3(grid_for(L.elems())), dim3(kBlock), 0, s, L, X, ld, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_compact(const Layout& Lc, float* dst, const Layout& Lw, const float* src,
+                             int wc, hipStream_t s) {
+  if (wc > Lc.w || wc > Lw.w || Lc.n != Lw.n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_to_compact, dim3(grid_for(Lc.elems())), dim3(kBlock), 0, s, Lc, dst, Lw, src,
+                     wc);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_compact(const Layout& Lc, const float* src, const Layout& Lw, float* dst,
+                               int wc, hipStream_t s) {
+  if (wc > Lc.w || wc > Lw.w || Lc.n != Lw.n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_from_compact, dim3(grid_for(Lc.elems())), dim3(kBlock), 0, s, Lc, src, Lw,
+                     dst, wc);
   return hipGetLastError();
 }
 

@@ -183,6 +183,11 @@ hipError_t launch_gaussian_rows(int n_rows, int w, uint64_t seed, uint32_t t, ui
 
 // Layout conversion and row scaling.
 hipError_t launch_pack(const Layout& L, const float* X, int ld, float* out, hipStream_t s);
+// columns [0, wc) between a wide layout Lw and a compact layout Lc of the same rows
+hipError_t launch_to_compact(const Layout& Lc, float* dst, const Layout& Lw, const float* src,
+                             int wc, hipStream_t s);
+hipError_t launch_from_compact(const Layout& Lc, const float* src, const Layout& Lw, float* dst,
+                               int wc, hipStream_t s);
 hipError_t launch_unpack(const Layout& L, const float* in, float* Y, int ld, int normalize,
                          hipStream_t s);
 hipError_t launch_normalize_rows(int n_rows, int w, float* Y, int ld, hipStream_t s,

@@ -18,7 +18,9 @@ lies within twice that margin of k - 1/2, k + 1/2 or k (then the estimates
 stay within the interval of that test); sampled nodes bit-exact; features
 1e-4 relative Frobenius; interpolated columns within 1e-3 of the oracle's
 solution to 1e-10 (relative, on the stored rows); labels ARI >= 0.99 against
-the oracle's whenever the two estimates of lambda_k agree.
+the labels of the oracle's solve to 1e-10 whenever the two estimates of
+lambda_k agree (the side-by-side CGs, the oracle's own algorithm, against
+the oracle's CG at 1e-6).
 """
 import os
 import math
@@ -107,8 +109,12 @@ def test_sbm_1e5_interpolation_columns(api, sbm):
     X = it.X.cpu().numpy().astype(np.float64)[rows][:, cols]
     err = rel_cols(X, gold["X_exact_at_rows"])
     assert np.all(err <= 1e-3), err
-    # the labels of Eq. (5)'s solution against the oracle's, from the same inputs
-    assert adjusted_rand_index(it.labels.cpu().numpy(), gold["labels"]) >= 0.99
+    # the labels of Eq. (5)'s solution against the oracle's, from the same
+    # inputs: the block CG against the oracle's solve to 1e-10, the
+    # side-by-side CGs (the oracle's own algorithm) against its CG at 1e-6
+    assert adjusted_rand_index(it.labels.cpu().numpy(), gold["labels_tight"]) >= 0.99
+    itc = api.interpolate(g, lam, p, 1e-3, gold["omega"], gold["labels_r"], k, method=api.CG_COLUMNS)
+    assert adjusted_rand_index(itc.labels.cpu().numpy(), gold["labels"]) >= 0.99
 
 
 def test_sbm_1e5_end_to_end(api, sbm):
@@ -119,7 +125,7 @@ def test_sbm_1e5_end_to_end(api, sbm):
     same = compare_search(res.bisection.trace, res.lam, res.bisection.steps, gold, "", k)
     assert np.array_equal(res.omega.cpu().numpy(), gold["omega"])
     if same:
-        assert adjusted_rand_index(res.labels.cpu().numpy(), gold["labels"]) >= 0.99
+        assert adjusted_rand_index(res.labels.cpu().numpy(), gold["labels_tight"]) >= 0.99
 
 
 # ------------------------------------------------- Chung-Lu N = 1e6 -----
@@ -180,6 +186,8 @@ def test_chunglu_1e6_interpolation_columns(api, chunglu):
 def batch8():
     gold = _load("scale_batch8.npz")
     pos = [int(x) for x in gold["positions"]]
+    if f"g{pos[0]}_plain_labels_tight" not in gold.files:
+        pytest.skip("scale_batch8.npz predates the solves to 1e-10 (tests/golden/make_scale_goldens.py)")
     gs = synth.sbm_batch(only=pos)
     for gi, gr in zip(pos, gs):
         assert gr.n == int(gold[f"g{gi}_N"]) and gr.nnz == int(gold[f"g{gi}_nnz"])
@@ -194,23 +202,38 @@ def _batch_inputs(api, batch8):
     return pos, gs, gold, G, ks, ds, pos  # graph g of the batch is seeded g
 
 
-def _check_pipeline(res, gold, gi, prefix, k, mid_tol):
+def _check_pipeline(api, g, res, gold, gi, prefix, k, mid_tol):
+    """One graph's pipeline against the oracle's: the search; the samples;
+    and, when the two estimates agree, the k-means labels of the sampled
+    nodes, the interpolation from the oracle's own inputs and the final
+    labels, both against the labels of the oracle's solve to 1e-10 (the block
+    CG meets 1e-6 by another path than the oracle's CG, and on graphs with
+    many nearly tied nodes two 1e-6 solutions can label a few percent of the
+    nodes differently)."""
     same = compare_search(res.bisection.trace, res.lam, res.bisection.steps, gold, f"g{gi}_{prefix}",
                           k, mid_tol=mid_tol)
     assert np.array_equal(res.omega.cpu().numpy(), gold[f"g{gi}_plain_omega"])
-    ari = adjusted_rand_index(res.labels.cpu().numpy(), gold[f"g{gi}_{prefix}labels"])
-    if same:
-        assert ari >= 0.99, (gi, prefix, ari)
-    return same, ari
+    if not same:
+        return False
+    lab_r = gold[f"g{gi}_{prefix}labels_r"]
+    tight = gold[f"g{gi}_{prefix}labels_tight"]
+    assert adjusted_rand_index(res.labels_r, lab_r) >= 0.99, (gi, prefix)
+    it = api.interpolate(g, res.lam, 50, 1e-3, gold[f"g{gi}_plain_omega"], lab_r, k)
+    ari_i = adjusted_rand_index(it.labels.cpu().numpy(), tight)
+    ari = adjusted_rand_index(res.labels.cpu().numpy(), tight)
+    print(f"graph {gi} {prefix}: interpolation from the oracle's inputs ARI {ari_i:.4f}, end to end {ari:.4f}")
+    assert ari_i >= 0.99, (gi, prefix, ari_i)
+    assert ari >= 0.99, (gi, prefix, ari)
+    return True
 
 
 def test_batch8_plain_batched_and_single(api, batch8):
     pos, gs, gold, G, ks, ds, seeds = _batch_inputs(api, batch8)
     out = api.run_batched(G, ks, ds, seeds, p=50)
-    for gi, k, res in zip(pos, ks, out):
-        _check_pipeline(res, gold, gi, "plain_", k, 0.0)
+    for gi, g, k, res in zip(pos, G, ks, out):
+        _check_pipeline(api, g, res, gold, gi, "plain_", k, 0.0)
     for gi, g, k, d, s in zip(pos, G, ks, ds, seeds):
-        _check_pipeline(api.run(g, k, d, s, p=50), gold, gi, "plain_", k, 0.0)
+        _check_pipeline(api, g, api.run(g, k, d, s, p=50), gold, gi, "plain_", k, 0.0)
 
 
 def test_batch8_learned_batched_and_single(api, batch8):
@@ -220,9 +243,8 @@ def test_batch8_learned_batched_and_single(api, batch8):
     mlp = learned.load_params("cuda")
     out = api.run_batched(G, ks, ds, seeds, p=50, mlp_params=mlp)
     agree = 0
-    for gi, k, res in zip(pos, ks, out):
-        same, _ = _check_pipeline(res, gold, gi, "learned_", k, 2e-5)
-        agree += same
+    for gi, g, k, res in zip(pos, G, ks, out):
+        agree += _check_pipeline(api, g, res, gold, gi, "learned_", k, 2e-5)
     for gi, g, k, d, s in zip(pos, G, ks, ds, seeds):
-        _check_pipeline(api.run(g, k, d, s, p=50, mlp_params=mlp), gold, gi, "learned_", k, 2e-5)
+        _check_pipeline(api, g, api.run(g, k, d, s, p=50, mlp_params=mlp), gold, gi, "learned_", k, 2e-5)
     assert agree >= 6  # a near-tie may part at most a few searches
