@@ -211,6 +211,7 @@ struct Pass {
   float gamma = 0.f;
   int mgroup = 1;  // EPI_MOM: passes side by side, mnc4 columns each
   int mnc4 = 0;
+  int form = -1;   // EPI_Y / EPI_CG: filter form of this pass (-1: the process-wide setting)
 };
 
 }  // namespace
@@ -279,7 +280,8 @@ csc_status chebyshev_pass(const csc_graph& g, const Layout& L, const double* a, 
   apply_tuning(sa);
   const size_t nblocks = (size_t)L.np * sa.tiles;
   if (epi == EPI_Y || epi == EPI_CG) {
-    for (const PassStep& st : pass_plan(epi, a, p, b.T0, b.Ta, b.Tb, filter_form())) {
+    for (const PassStep& st : pass_plan(epi, a, p, b.T0, b.Ta, b.Tb,
+                                        b.form >= 0 ? b.form : filter_form())) {
       sa.Tm = st.Tm;
       sa.Tprev = st.Tprev;
       sa.Tnext = st.Tnext;
@@ -1239,29 +1241,47 @@ csc_status post_finish(BlockState& st, hipStream_t s) {
   return CSC_OK;
 }
 
-// Q = M P for the block CG.  P's live columns are its first sr; when they
-// fit twice in one of the two recurrence buffers, the pass runs on a compact
-// copy of them (a layout of width sr with its own panel width) inside those
-// buffers, and only those columns of Q are written back (the block CG reads
-// no column of Q beyond sr).  Every element sums its row's neighbours in CSR
-// order whatever the layout, so Q is the same either way; a block whose
-// columns have mostly converged costs a pass of its live width.
-static csc_status block_pass(const csc_graph& g, const Layout& L, const double* a, int p, const Pass& pb,
-                      int sr, hipStream_t s) {
-  const Layout Lc = make_layout(L.n, std::max(sr, 1), choose_panel_width(L.n, std::max(sr, 1), g.nnz));
-  const size_t half = (Lc.elems() + 63) / 64 * 64;
-  // the compact pass writes its column partials into the wide pass's buffer
-  const bool part_fits =
-      (size_t)Lc.np * Lc.pw * tiles_for(Lc) <= (size_t)L.np * L.pw * tiles_for(L);
-  if (sr < 1 || sr >= L.w || 2 * half > L.elems() || !part_fits)
+// Q = M P for the block CG.  P's live columns are its first sr; when they are
+// fewer than the block's width the pass runs on a compact copy of them (a
+// layout of width sr with its own panel width) and only those columns of Q
+// are written back (the block CG reads no column of Q beyond sr).  Every
+// element sums its row's neighbours in CSR order whatever the layout, so Q
+// is the same either way; a block whose columns have partly converged costs
+// a pass of its live width.
+// Buffers: in Clenshaw's form the compact P sits in Q's buffer (Q is written
+// only by the copy back), the recurrence in Ta / Tb, and the last step, which
+// reads b_2 and writes its output element by element in the same lane, writes
+// the compact Q over b_2; the forward form keeps two compact blocks in each of
+// Ta and Tb, so it compacts only blocks at most half as wide.
+static csc_status block_pass(const csc_graph& g, const Layout& L, const double* a, int p,
+                             const Pass& pb, int sr, hipStream_t s) {
+  if (sr < 1 || sr >= L.w) return chebyshev_pass(g, L, a, p, EPI_CG, pb, s);
+  const Layout Lc = make_layout(L.n, sr, choose_panel_width(L.n, sr, g.nnz));
+  // the compact blocks live in the wide blocks' buffers, and the compact pass
+  // writes its column partials into the wide pass's buffer
+  if (Lc.elems() > L.elems() ||
+      (size_t)Lc.np * Lc.pw * tiles_for(Lc) > (size_t)L.np * L.pw * tiles_for(L))
     return chebyshev_pass(g, L, a, p, EPI_CG, pb, s);
   Pass pc = pb;
-  float* Pc = pb.Ta;
-  float* Qc = pb.Ta + half;
+  float* Pc;
+  float* Qc;
+  const int form = filter_form();
+  const std::vector<PassStep> plan = pass_plan(EPI_CG, a, p, pb.T0, pb.Ta, pb.Tb, form);
+  if (form == FORM_CLENSHAW && !plan.empty() && plan.back().epi == EPI_CLEN_CG &&
+      (plan.back().Tprev == pb.Tb || plan.back().Tprev == nullptr) && plan.back().Tm != pb.Tb) {
+    Pc = pb.Y;
+    Qc = pb.Tb;  // b_2's buffer at the last step
+  } else {
+    const size_t half = (Lc.elems() + 63) / 64 * 64;
+    if (2 * half > L.elems()) return chebyshev_pass(g, L, a, p, EPI_CG, pb, s);
+    Pc = pb.Ta;
+    Qc = pb.Ta + half;
+    pc.Ta = pb.Tb;
+    pc.Tb = pb.Tb + half;
+  }
   pc.T0 = Pc;
-  pc.Ta = pb.Tb;
-  pc.Tb = pb.Tb + half;
   pc.Y = Qc;
+  pc.form = form;  // the buffer plan above holds for this form only
   CSC_HIP(launch_to_compact(Lc, Pc, L, pb.T0, sr, s));
   CSC_TRY(chebyshev_pass(g, Lc, a, p, EPI_CG, pc, s));
   CSC_HIP(launch_from_compact(Lc, Qc, L, pb.Y, sr, s));
