@@ -121,11 +121,11 @@ def job_bytes(N, nnz, k, d, n_c, p, bis_steps, cg_iters):
     return count + feat + cg
 
 
-def full_width_iterations(iters, k):
-    """Block-CG iterations whose operator pass runs at the full width k: the
-    library runs the pass on a compact copy of the live columns once they fit
-    in half the block (counted here by live columns, an upper bound)."""
-    return sum(1 for w in live_widths(iters) if 2 * w > k)
+def cg_pass_share(iters, k):
+    """The block CG's operator passes in units of one pass at the full width
+    k: the library runs each pass on a compact copy of the live columns, and
+    a step's time follows its gathered lines, ceil(w / 32) per row."""
+    return sum(math.ceil(w / 32) for w in live_widths(iters)) / math.ceil(k / 32)
 
 
 def kernel_hash():
@@ -405,7 +405,7 @@ def step_kernels(api, name, gr, wl, last, reps, dev):
              f"{n_c} signals side by side" if group > 1 else
              f"k_cheb_step<EPI_MOM> (moment step of the eigencount passes, {n_c} signals"),
             ("filter", d, None, 3, "clen", p, "k_cheb_step<EPI_CLEN> (Clenshaw step of the feature pass"),
-            ("cg", k, last.order, 3, "clen", full_width_iterations(last.interp.iters, k) * p,
+            ("cg", k, last.order, 3, "clen", len(live_widths(last.interp.iters)) * p,
              "k_cheb_step<EPI_CLEN> (Clenshaw step of the CG operator pass")):
         avg_s = step_time(api, gr, order, w, p, reps, dev, kind=kind)
         # the sparse product alone at this width and order (CSR read, gathered
@@ -431,6 +431,12 @@ def step_kernels(api, name, gr, wl, last, reps, dev):
             "launches_per_step": launches,
             "ms_per_step": round(launches * avg_s * 1e3, 3),
         }
+    # the CG passes run at their live widths: time in full-width passes
+    share = cg_pass_share(last.interp.iters, k)
+    out["cg"]["ms_per_step"] = round(share * p * out["cg"]["avg_launch_us"] / 1e3, 3)
+    out["cg"]["kernel"] += (f"; {len(live_widths(last.interp.iters))} iterations with "
+                            f"{live_widths(last.interp.iters)} live columns, passes on compact "
+                            f"copies of them: ms_per_step counts {share:.2f} full-width passes")
     return out
 
 
