@@ -184,7 +184,8 @@ csc_status csc_set_tuning(int32_t key, int32_t value);
 int32_t csc_get_tuning(int32_t key);
 
 /* Autotuner.  csc_autotune times one kind of Chebyshev step (as in
- * csc_cheb_steps: 0 accumulate, 1 moments, 2 CG operator) on graph g at block
+ * csc_cheb_steps: 0 accumulate, 1 moments, 2 CG operator, 3 Clenshaw step,
+ * 4 moments of a group of dichotomy tests side by side) on graph g at block
  * width w for candidate panel widths (the six best of the built-in cost
  * model and every multiple of 32 columns that pads w less than twofold) and
  * both XCD orders, `reps` launches each, timed with HIP events on `stream`.

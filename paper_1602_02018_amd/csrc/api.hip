@@ -1568,7 +1568,9 @@ extern "C" csc_status csc_autotune(const csc_graph* g, int32_t w, int32_t kind, 
                                    size_t ws_bytes, void* stream) {
   clear_error();
   CSC_TRY(check_graph(g));
-  CSC_REQUIRE(w >= 1 && kind >= 0 && kind <= 2 && reps >= 1, "need w >= 1, kind 0..2, reps >= 1");
+  CSC_REQUIRE(w >= 1 && kind >= 0 && kind <= 4 && reps >= 1, "need w >= 1, kind 0..4, reps >= 1");
+  CSC_REQUIRE(kind != 4 || w % (4 * count_group()) == 0,
+              "kind 4 needs w = group size x a multiple of 4");
   CSC_REQUIRE(g_panel_override.load() == 0, "a forced panel width is in effect");
   CSC_TRY(check_ws(ws, ws_bytes, csc_cheb_steps_workspace_bytes(g->n, w)));
   hipStream_t s = as_stream(stream);
