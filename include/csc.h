@@ -465,8 +465,12 @@ csc_status csc_kmeans_reduced_device(const float* F, int32_t n, int32_t d, int32
  *   one scale, which leaves only about k small eigenvalues for the block
  *   Krylov space to resolve.  All three stop when
  *   every column has ||r_j|| / ||b_j|| <= tol (recursive residuals); iters_out
- *   gives the iteration at which each column first met it.  All solve the
- *   same system; X agrees to the accuracy the tolerance implies.
+ *   gives the iteration at which each column first met it.  In the block
+ *   forms a column that has met it leaves the search block (its X and
+ *   residual keep the values it converged with), and a search block narrower
+ *   than k runs its Chebyshev pass on a compact copy of its live columns.
+ *   All solve the same system; X agrees to the accuracy the tolerance
+ *   implies.
  * ws: csc_interpolate_workspace_bytes(N, nnz, k, n) (covers every form).
  * Synchronises.  Returns CSC_W_NOT_CONVERGED if a column reached max_iter or
  * the block iteration broke down (outputs still hold the last iterate).

@@ -246,3 +246,18 @@ def test_argument_checks_from_two_threads_keep_their_own_errors():
             t.join()
     assert not errors, errors
     assert lib.csc_set_panel_width(0) == _lib.CSC_OK
+
+
+def test_bench_accounting_of_block_cg_live_columns():
+    """bench.py counts each block-CG iteration's live columns (a column leaves
+    the block once it meets the tolerance; zero right-hand sides never enter)."""
+    import bench
+
+    it = np.array([1] * 33 + [3] * 216 + [4])
+    assert bench.live_widths(it) == [250, 217, 217, 1]
+    assert bench.live_widths(np.array([0, 0, 2])) == [1, 1]
+    assert bench.live_widths(np.array([], dtype=int)) == []
+    assert abs(bench.cg_pass_share(it, 250) - (8 + 7 + 7 + 1) / 8) < 1e-12
+    full = bench.job_bytes(1000, 16000, 10, 28, 14, 50, 4, np.full(10, 3))
+    part = bench.job_bytes(1000, 16000, 10, 28, 14, 50, 4, np.array([3] * 5 + [1] * 5))
+    assert part < full
