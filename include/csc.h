@@ -142,8 +142,9 @@ int32_t csc_get_filter_form(void);
  *   and replay it; 0 launches every kernel directly.
  * CSC_TUNE_ROW_SCHED (0/1/2, default 1): when the step kernels follow the
  *   graph's row schedule (csc_graph.sched, when set): 0 never, 1 when a wave
- *   holds 8 rows or more (panel widths up to 32), 2 whenever a wave holds
- *   several rows.
+ *   holds exactly 8 rows (panel widths 29 to 32, the only shape where the
+ *   degree-sorted walk was measured to pay), 2 whenever a wave holds several
+ *   rows.
  * CSC_TUNE_COUNT_GROUP (1..4, default 4): the dichotomies
  *   (csc_estimate_lambda_k, csc_estimate_lambda_k_learned) run this many
  *   consecutive tests' eigencount passes as one wider pass (their signals do

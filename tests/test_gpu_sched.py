@@ -6,7 +6,7 @@ method): rows in chunks of 4096, each chunk by decreasing degree.
   attaches the schedule to skewed graphs only;
 * every step result is unchanged by the walk order: each row still sums its
   neighbours in CSR order, so filtered blocks and features are bit for bit
-  the same with the schedule off, on for panels of 8 rows per wave and on for every
+  the same with the schedule off, on for panels of exactly 8 rows per wave and on for every
   multi-row panel; eigencount moments differ only by the grouping of their
   float64 partial sums;
 * on a skewed-degree graph (Chung-Lu) the same holds, and the batched calls
