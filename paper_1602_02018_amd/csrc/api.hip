@@ -207,7 +207,7 @@ struct Pass {
   float* Ta = nullptr;
   float* Tb = nullptr;
   float* Y = nullptr;
-  double* part = nullptr;  // EPI_MOM: moment_raw(p) x nblocks; EPI_CG: columns x tiles
+  double* part = nullptr;  // EPI_MOM: moment_raw(p) x nblocks kMomSlots; EPI_CG: columns x tiles
   const int* slot = nullptr;
   float* Ys = nullptr;
   int lds = 0;
@@ -307,12 +307,13 @@ csc_status chebyshev_pass(const csc_graph& g, const Layout& L, const double* a, 
     sa.c1 = (float)a[m + 1];
     int e = epi;
     if (epi == EPI_MOM || epi == EPI_MOMG) {
-      sa.part = b.part + (size_t)(2 * m + 1) * nblocks;
-      sa.part2 = b.part + (size_t)(2 * m + 2) * nblocks;
+      const size_t nslots = nblocks * kMomSlots;
+      sa.part = b.part + (size_t)(2 * m + 1) * nslots;
+      sa.part2 = b.part + (size_t)(2 * m + 2) * nslots;
       sa.part0 = b.part;
       sa.mgroup = b.mgroup;
       sa.mnc4 = b.mnc4;
-      sa.mstride = (size_t)moment_raw(p) * nblocks;
+      sa.mstride = (size_t)moment_raw(p) * nslots;
     } else if (epi == EPI_CG) {
       e = last ? EPI_CG : EPI_Y;
       sa.part = b.part;
@@ -346,7 +347,7 @@ void moments_from_raw(const double* raw, int p, double* mom) {
 size_t count_bytes(const Layout& L, int p, int group) {
   const size_t nblocks = (size_t)L.np * tiles_for(L);
   size_t b = 4 * align_up(L.bytes());  // two signal blocks, two recurrence blocks
-  b += align_up((size_t)group * moment_raw(p) * nblocks * sizeof(double));
+  b += align_up((size_t)group * moment_raw(p) * nblocks * kMomSlots * sizeof(double));
   b += align_up((size_t)group * moment_raw(p) * sizeof(double));
   return b + 256;
 }
@@ -391,7 +392,7 @@ CountBuffers carve_count(Arena& ar, const Layout& L, int p, int group = 1) {
   c.T0n = ar.take<float>(L.elems());
   c.Ta = ar.take<float>(L.elems());
   c.Tb = ar.take<float>(L.elems());
-  c.part = ar.take<double>((size_t)group * moment_raw(p) * nblocks);
+  c.part = ar.take<double>((size_t)group * moment_raw(p) * nblocks * kMomSlots);
   c.mom = ar.take<double>((size_t)group * moment_raw(p));
   return c;
 }
@@ -476,7 +477,7 @@ csc_status moments_pass(const csc_graph& g, const Layout& L, int p, uint64_t see
   std::vector<double> zero(p + 1, 0.0);
   CSC_TRY(chebyshev_pass(g, L, zero.data(), p, EPI_MOM, b, s));
   const int nraw = moment_raw(p);
-  CSC_HIP(launch_reduce(c.part, (int)nblocks, cg.g * nraw, c.mom, s));
+  CSC_HIP(launch_reduce(c.part, (int)(nblocks * kMomSlots), cg.g * nraw, c.mom, s));
   std::vector<double> raw((size_t)cg.g * nraw);
   CSC_HIP(hipMemcpyAsync(raw.data(), c.mom, raw.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   if (between) CSC_TRY(between());
@@ -1494,7 +1495,10 @@ size_t steps_bytes(const Layout& L) {
   const size_t tiles = tiles_for(L), wp = (size_t)L.np * L.pw;
   size_t b = 4 * align_up(L.bytes());                       // T0, Ta, Tb, Y
   b += align_up((size_t)L.n * sizeof(float));               // mask
-  b += align_up(std::max(wp * tiles, (size_t)L.np * tiles) * sizeof(double));
+  // column partials (kinds 0, 2), or the moment partials of up to
+  // kMaxCountGroup tests (kinds 1, 4)
+  b += align_up(std::max(wp * tiles, (size_t)L.np * tiles * kMomSlots * kMaxCountGroup) *
+                sizeof(double));
   return b + 256;
 }
 }  // namespace
@@ -1523,7 +1527,8 @@ extern "C" csc_status csc_cheb_steps(const csc_graph* g, int32_t w, int32_t kind
   float* Tb = ar.take<float>(L.elems());
   float* Y = ar.take<float>(L.elems());
   float* mask = ar.take<float>(g->n);
-  double* part = ar.take<double>(std::max((size_t)L.np * L.pw * tiles, (size_t)L.np * tiles));
+  double* part = ar.take<double>(
+      std::max((size_t)L.np * L.pw * tiles, (size_t)L.np * tiles * kMomSlots * kMaxCountGroup));
   if (prepare) {
     CSC_HIP(launch_gaussian_panels(L, 1, 0, CSC_STREAM_FEAT, T0, s));
     CSC_HIP(launch_fill_f32(Ta, L.elems(), 0.f, s));
@@ -1547,9 +1552,11 @@ extern "C" csc_status csc_cheb_steps(const csc_graph* g, int32_t w, int32_t kind
   sa.part = part;
   sa.part2 = part;
   sa.part0 = part;
-  sa.mgroup = group;  // kind 4: pass j's partials at part + j * units (part holds pw >= 4 per unit)
+  // kinds 1 and 4: pass j's moment partials at part + j * units * kMomSlots
+  // (group <= kMaxCountGroup, within the partial buffer of steps_bytes)
+  sa.mgroup = group;
   sa.mnc4 = w / group;
-  sa.mstride = (size_t)L.np * tiles;
+  sa.mstride = (size_t)L.np * tiles * kMomSlots;
   apply_tuning(sa);
   const int epi = kind == 0   ? EPI_Y
                   : kind == 1 ? EPI_MOM

@@ -256,7 +256,7 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
     T0[g] = ar.take<float>(L[g].elems());
     Ta[g] = ar.take<float>(L[g].elems());
     Tb[g] = ar.take<float>(L[g].elems());
-    part[g] = ar.take<double>((size_t)gc * nraw * units[g]);
+    part[g] = ar.take<double>((size_t)gc * nraw * units[g] * kMomSlots);
   }
   double* mom = ar.take<double>((size_t)G * gc * nraw);
   StepArgs* d_steps = ar.take<StepArgs>((size_t)msteps * G);
@@ -296,15 +296,16 @@ extern "C" csc_status csc_estimate_lambda_k_batched(
       a.Tm = first ? T0[g] : ((m & 1) ? Ta[g] : Tb[g]);
       a.Tprev = first ? T0[g] : ((m - 1) == 0 ? T0[g] : (((m - 1) & 1) ? Ta[g] : Tb[g]));
       a.Tnext = ((m + 1) & 1) ? Ta[g] : Tb[g];
-      a.part = part[g] + (size_t)(2 * m + 1) * units[g];
-      a.part2 = part[g] + (size_t)(2 * m + 2) * units[g];
+      const size_t nslots = (size_t)units[g] * kMomSlots;
+      a.part = part[g] + (size_t)(2 * m + 1) * nslots;
+      a.part2 = part[g] + (size_t)(2 * m + 2) * nslots;
       a.part0 = part[g];
       a.mgroup = gc;
       a.mnc4 = gc > 1 ? round4(n_signals[g]) : n_signals[g];
-      a.mstride = (size_t)nraw * units[g];
+      a.mstride = (size_t)nraw * nslots;
     }
     h_red[g].part = part[g];
-    h_red[g].len = units[g];
+    h_red[g].len = units[g] * kMomSlots;
     h_red[g].out = mom + (size_t)g * gc * nraw;
     h_red[g].live = d_live + g;
     h_gauss[g].L = L[g];

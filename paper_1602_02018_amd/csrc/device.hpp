@@ -123,12 +123,43 @@ __device__ inline int step_row(const StepArgs& a, int r) {
 }
 
 // Row i of A times the gathered panel: sum_k val[k] T_m[col[k]], k in CSR order.
+// A row of 64 or more neighbours gathers 8 rows per round trip while the next
+// 8 column indices load, so a high-degree row's lane waits one round trip per
+// 8 neighbours instead of two per 4: on power-law graphs those lanes' chains
+// (~1000 round trips for a degree-2000 hub) otherwise set the step time at
+// narrow widths.  Shorter rows keep the 4-wide loop (measured no slower; the
+// threshold 16, 24, 32 or 64 changes little, 64 was best by 1-3%).  The sums
+// stay in CSR order either way.
 __device__ inline v4f spmm_row(const StepArgs& a, const v4f* __restrict__ Tm4, int i, int q,
                                int lpr, bool valid) {
   v4f acc = (v4f)0.f;
   if (valid) {
     int k = a.row_ptr[i];
     const int end = a.row_ptr[i + 1];
+    if (end - k >= 64) {
+      int j[8], jn[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) j[e] = a.col[k + e];
+      for (;;) {  // entries k .. k + 7 exist here
+        v4f t[8];
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] = Tm4[(unsigned)j[e] * lpr + q];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = a.val[k + e];
+        const bool more = k + 16 <= end;
+        if (more) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) jn[e] = a.col[k + 8 + e];
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc = fma4(v[e], t[e], acc);
+        k += 8;
+        if (!more) break;  // fewer than 8 entries left
+#pragma unroll
+        for (int e = 0; e < 8; ++e) j[e] = jn[e];
+      }
+    }
     for (; k + 4 <= end; k += 4) {
       const int j0 = a.col[k], j1 = a.col[k + 1], j2 = a.col[k + 2], j3 = a.col[k + 3];
       const float v0 = a.val[k], v1 = a.val[k + 1], v2 = a.val[k + 2], v3 = a.val[k + 3];
@@ -273,7 +304,7 @@ __device__ inline void cheb_unit(const StepArgs& a, int u) {
     // products for the Chebyshev doubling identities T_{2m} = 2 T_m^2 - 1 and
     // T_{2m+1} = 2 T_m T_{m+1} - T_1: <T_m, T_{m+1}> and <T_{m+1}, T_{m+1}>
     // (and <T_0, T_0> on the first step), so that p moments take p/2 steps
-    __shared__ double sh[8];
+    // each wave writes its own sums (slot u kMomSlots + wave): no barrier
     double sx = 0.0, sq = 0.0, s0 = 0.0;
     if (valid) {
       const v4f tm = FIRST ? x0 : ld4(a.Tm, o4, nt);
@@ -281,22 +312,20 @@ __device__ inline void cheb_unit(const StepArgs& a, int u) {
       sq = dot4v(tn, tn);
       if (FIRST) s0 = dot4v(tm, tm);
     }
-    const double bx = block_sum(sx, sh);
-    if (threadIdx.x == 0) a.part[u] = bx;
-    __syncthreads();
-    const double bq = block_sum(sq, sh);
-    if (threadIdx.x == 0) a.part2[u] = bq;
-    if (FIRST) {
-      __syncthreads();
-      const double b0 = block_sum(s0, sh);
-      if (threadIdx.x == 0) a.part0[u] = b0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const size_t slot = (size_t)u * kMomSlots + wave;
+    const double wx = wave_sum(sx), wq = wave_sum(sq);
+    const double w0 = FIRST ? wave_sum(s0) : 0.0;
+    if (lane == 0) {
+      a.part[slot] = wx;
+      a.part2[slot] = wq;
+      if (FIRST) a.part0[slot] = w0;
     }
-    __syncthreads();  // shared memory is reused by the next unit of a grid-stride loop
   } else if constexpr (EPI == EPI_MOMG) {
     // the same products for a group of eigencount tests side by side, one set
     // of sums per test: this lane's four columns lie in test
     // (panel pw + 4 q) / mnc4 (lanes past the group's columns hold zeros);
-    // wave sums per test, then the four waves in a fixed order
+    // wave sums per test, each wave writing its own slot as above
     double sx = 0.0, sq = 0.0, s0 = 0.0;
     if (valid) {
       const v4f tm = FIRST ? x0 : ld4(a.Tm, o4, nt);
@@ -304,30 +333,21 @@ __device__ inline void cheb_unit(const StepArgs& a, int u) {
       sq = dot4v(tn, tn);
       if (FIRST) s0 = dot4v(tm, tm);
     }
-    {
-      __shared__ double shg[4][3 * kMaxCountGroup];
-      const int jl = (panel * a.L.pw + m.q * 4) / a.mnc4;
-      const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-      for (int j = 0; j < a.mgroup; ++j) {
-        const bool mine = jl == j;
-        const double wx = wave_sum(mine ? sx : 0.0);
-        const double wq = wave_sum(mine ? sq : 0.0);
-        const double w0 = FIRST ? wave_sum(mine ? s0 : 0.0) : 0.0;
-        if (lane == 0) {
-          shg[wave][3 * j] = wx;
-          shg[wave][3 * j + 1] = wq;
-          shg[wave][3 * j + 2] = w0;
-        }
-      }
-      __syncthreads();
-      const int e = threadIdx.x;
-      if (e < 3 * a.mgroup && (e % 3 < 2 || FIRST)) {
-        const double v = (shg[0][e] + shg[1][e]) + (shg[2][e] + shg[3][e]);
-        double* dst = e % 3 == 0 ? a.part : (e % 3 == 1 ? a.part2 : a.part0);
-        dst[(size_t)(e / 3) * a.mstride + u] = v;
+    const int jl = (panel * a.L.pw + m.q * 4) / a.mnc4;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const size_t slot = (size_t)u * kMomSlots + wave;
+    for (int j = 0; j < a.mgroup; ++j) {
+      const bool mine = jl == j;
+      const double wx = wave_sum(mine ? sx : 0.0);
+      const double wq = wave_sum(mine ? sq : 0.0);
+      const double w0 = FIRST ? wave_sum(mine ? s0 : 0.0) : 0.0;
+      if (lane == 0) {
+        const size_t o = (size_t)j * a.mstride + slot;
+        a.part[o] = wx;
+        a.part2[o] = wq;
+        if (FIRST) a.part0[o] = w0;
       }
     }
-    __syncthreads();  // shared memory is reused by the next unit of a grid-stride loop
   } else if constexpr (EPI == EPI_CG) {
     __shared__ double sh[4 * 64 * 4];
     double cs[4] = {0.0, 0.0, 0.0, 0.0};

@@ -24,6 +24,12 @@ enum Epi : int {
 // Eigencount tests whose passes one EPI_MOMG launch may carry side by side.
 constexpr int kMaxCountGroup = 4;
 
+// Moment partial sums per work unit (EPI_MOM, EPI_MOMG): one per wave of the
+// 256-thread workgroup, so that no wave waits for the others of its
+// workgroup (on skewed degrees their rows end at very different times).  The
+// partial of wave v of unit u sits at index u * kMomSlots + v.
+constexpr int kMomSlots = 4;
+
 struct StepArgs {
   Layout L;
   int tiles = 0;  // row tiles per panel
@@ -37,7 +43,7 @@ struct StepArgs {
   const float* T0 = nullptr;     // T_0 (moments, CG)
   float* Y = nullptr;            // accumulator (EPI_Y, EPI_CG)
   float c0 = 0.f, c1 = 0.f;      // first step: Y = c0 T_0 + c1 T_1; later: Y += c1 T_{m+1}
-  double* part = nullptr;        // partial sums
+  double* part = nullptr;        // partial sums (EPI_MOM: of <T_m, T_{m+1}>, kMomSlots per unit)
   double* part2 = nullptr;       // EPI_MOM: partial of <T_{m+1}, T_{m+1}>
   double* part0 = nullptr;       // EPI_MOM, first step: partial of <T_0, T_0>
   const int* slot = nullptr;     // EPI_YS: output row of node i or -1
