@@ -396,12 +396,22 @@ __device__ inline void gaussian_group_elem(const Layout& L, uint64_t seed, uint3
 }
 
 // ---------------------------------------------------------- reductions ---
-// out[0] = sum_t part[t], t < len, by one workgroup in a fixed order.
+// out[0] = sum_t part[t], t < len, by one workgroup in a fixed order: thread
+// x keeps four running sums (of the elements x + 256 (4 r + c), c = 0..3),
+// so that four loads are in flight instead of one dependent chain, then the
+// four in order and the threads by block_sum.
 __device__ inline void reduce_vec(const double* part, int len, double* out) {
   __shared__ double sh[8];
-  double s = 0.0;
-  for (int t = threadIdx.x; t < len; t += kBlock) s += part[t];
-  const double b = block_sum(s, sh);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int t = threadIdx.x;
+  for (; t + 3 * kBlock < len; t += 4 * kBlock) {
+    s0 += part[t];
+    s1 += part[t + kBlock];
+    s2 += part[t + 2 * kBlock];
+    s3 += part[t + 3 * kBlock];
+  }
+  for (; t < len; t += kBlock) s0 += part[t];
+  const double b = block_sum((s0 + s1) + (s2 + s3), sh);
   if (threadIdx.x == 0) *out = b;
   __syncthreads();
 }
