@@ -10,6 +10,7 @@
 #include <cstring>
 #include <functional>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "dense.hpp"
@@ -1183,7 +1184,7 @@ void post_host_a(BlockState& st) {
     st.broke = true;
     return;
   }
-  dense::chol_solve(st.W, sr, sr, st.C, k, 1.0);
+  dense::chol_solve(st.W, sr, sr, st.C, k, 1.0, st.host_threads);
   for (int j = 0; j < k; ++j)
     if (st.done[j])
       for (int r = 0; r < sr; ++r) st.C[(size_t)r * k + j] = 0.0;
@@ -1234,7 +1235,7 @@ void post_host_b(BlockState& st, int it, int max_iter) {
     st.finished = true;
     return;
   }
-  dense::chol_solve(st.W, st.sr, st.sr, st.C, k, -1.0);
+  dense::chol_solve(st.W, st.sr, st.sr, st.C, k, -1.0, st.host_threads);
 }
 
 // Z = Z + P beta  (Z = R, or D^-1 R)
@@ -1423,6 +1424,7 @@ extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* orde
                        BlockBufs{P, AP, Ta, Tb, Xi, Rr, Zb, mask, part, gpart, Gd, S_t, S_a, S_na,
                                  S_b, rrn},
                        bnorm2, s));
+    bs.host_threads = (int)std::min(8u, std::max(1u, std::thread::hardware_concurrency()));
     Pass pb;
     pb.T0 = P;
     pb.Ta = Ta;

@@ -5,8 +5,10 @@
 // (no reductions), so the compiler vectorises them.
 #include "dense.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstddef>
+#include <thread>
 
 namespace csc {
 namespace dense {
@@ -96,24 +98,51 @@ CSC_DENSE_CLONES bool cholesky(std::vector<double>& W, int s, int ldw) {
   return true;
 }
 
-// C (s x k, leading dimension k) <- scale * (L L^T)^{-1} C.
-CSC_DENSE_CLONES void chol_solve(const std::vector<double>& Lw, int s, int ldw,
-                                  std::vector<double>& C, int k, double scale) {
-  double* c = C.data();
+// Columns [j0, j1) of C (s x k, leading dimension k) <- scale * (L L^T)^{-1} C.
+CSC_DENSE_CLONES void solve_cols(const double* Lw, int s, int ldw, double* c, int k, int j0,
+                                  int j1, double scale) {
+  const int w = j1 - j0;
   for (int i = 0; i < s; ++i) {  // L Y = C, row by row
-    double* ci = c + (size_t)i * k;
-    for (int t = 0; t < i; ++t) sub_scaled(ci, c + (size_t)t * k, Lw[(size_t)i * ldw + t], k);
+    double* ci = c + (size_t)i * k + j0;
+    for (int t = 0; t < i; ++t) sub_scaled(ci, c + (size_t)t * k + j0, Lw[(size_t)i * ldw + t], w);
     const double l = Lw[(size_t)i * ldw + i];
-    for (int j = 0; j < k; ++j) ci[j] /= l;
+    for (int j = 0; j < w; ++j) ci[j] /= l;
   }
   for (int i = s - 1; i >= 0; --i) {  // L^T X = Y
-    double* ci = c + (size_t)i * k;
-    for (int t = i + 1; t < s; ++t) sub_scaled(ci, c + (size_t)t * k, Lw[(size_t)t * ldw + i], k);
+    double* ci = c + (size_t)i * k + j0;
+    for (int t = i + 1; t < s; ++t) sub_scaled(ci, c + (size_t)t * k + j0, Lw[(size_t)t * ldw + i], w);
     const double l = Lw[(size_t)i * ldw + i];
-    for (int j = 0; j < k; ++j) ci[j] /= l;
+    for (int j = 0; j < w; ++j) ci[j] /= l;
   }
   if (scale != 1.0)
-    for (auto& v : C) v *= scale;
+    for (int i = 0; i < s; ++i)
+      for (int j = 0; j < w; ++j) c[(size_t)i * k + j0 + j] *= scale;
+}
+
+void chol_solve(const std::vector<double>& Lw, int s, int ldw, std::vector<double>& C, int k,
+                double scale, int threads) {
+  int nt = 1;
+  if (threads > 1 && (double)s * s * k >= (double)(1 << 22)) nt = std::min(threads, k / 32);
+  if (nt <= 1) {
+    solve_cols(Lw.data(), s, ldw, C.data(), k, 0, k, scale);
+    return;
+  }
+  const int chunk = ((k + nt - 1) / nt + 7) / 8 * 8;  // slices of whole 64-byte lines
+  std::vector<std::thread> pool;
+  for (int j0 = chunk; j0 < k; j0 += chunk) {
+    const int j1 = std::min(k, j0 + chunk);
+    // a direct call from the lambda: the address of a multi-versioned
+    // function is not a callable pointer in every compiler's shared objects
+    try {
+      pool.emplace_back([&Lw, &C, s, ldw, k, j0, j1, scale] {
+        solve_cols(Lw.data(), s, ldw, C.data(), k, j0, j1, scale);
+      });
+    } catch (...) {  // no thread to be had: solve the slice here
+      solve_cols(Lw.data(), s, ldw, C.data(), k, j0, j1, scale);
+    }
+  }
+  solve_cols(Lw.data(), s, ldw, C.data(), k, 0, std::min(k, chunk), scale);
+  for (auto& t : pool) t.join();
 }
 
 }  // namespace dense

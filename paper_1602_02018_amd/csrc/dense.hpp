@@ -21,9 +21,11 @@ int orth_transform(const std::vector<double>& G, int k, double rtol, std::vector
 bool cholesky(std::vector<double>& W, int s, int ldw);
 
 // C (s x k, leading dimension k) <- scale * (L L^T)^{-1} C, L the factor
-// cholesky() left in Lw.
+// cholesky() left in Lw.  threads > 1 splits the k right-hand sides into
+// column slices solved on that many host threads when the solve is large
+// (s^2 k >= 2^22); every element takes the same operations either way.
 void chol_solve(const std::vector<double>& Lw, int s, int ldw, std::vector<double>& C, int k,
-                double scale);
+                double scale, int threads = 1);
 
 }  // namespace dense
 }  // namespace csc

@@ -70,6 +70,7 @@ struct BlockState {
   int k = 0, sr = 0, ndone = 0, nlive = 0;
   double tol = 0.0;
   bool jacobi = false;  // preconditioned form: Z = D^-1 R, D = diag(mask) + gamma I
+  int host_threads = 1;  // host threads of the k x k solves (the batched form runs graphs in parallel)
   float gamma = 0.f;
   BlockBufs b{};
   bool finished = false, converged = false, broke = false;

@@ -12,10 +12,10 @@ extern "C" int dense_orth(const double* G, int k, double rtol, double* T) {
   return s;
 }
 
-extern "C" int dense_solve(const double* W, int s, double* C, int k, double scale) {
+extern "C" int dense_solve(const double* W, int s, double* C, int k, double scale, int threads) {
   std::vector<double> w(W, W + (size_t)s * s), c(C, C + (size_t)s * k);
   if (!csc::dense::cholesky(w, s, s)) return 0;
-  csc::dense::chol_solve(w, s, s, c, k, scale);
+  csc::dense::chol_solve(w, s, s, c, k, scale, threads);
   std::memcpy(C, c.data(), (size_t)s * k * sizeof(double));
   return 1;
 }

@@ -143,6 +143,22 @@ static void dense_case(int k, int rank, unsigned seed) {
   CHECK(!csc::dense::cholesky(bad, 2, 2));
 }
 
+// A solve large enough to split its right-hand sides over threads, against
+// the one-thread solve (same operations per element: equal bit for bit).
+static void threaded_solve_case(int s, int k, int threads, unsigned seed) {
+  std::mt19937_64 g(seed);
+  std::normal_distribution<double> N01;
+  std::vector<double> W((size_t)s * s, 0.0), R((size_t)s * k);
+  for (int a = 0; a < s; ++a) W[(size_t)a * s + a] = 2.0 + a;
+  for (int a = 0; a + 1 < s; ++a) W[(size_t)a * s + a + 1] = W[(size_t)(a + 1) * s + a] = 0.5;
+  for (auto& v : R) v = N01(g);
+  CHECK(csc::dense::cholesky(W, s, s));
+  std::vector<double> R1 = R;
+  csc::dense::chol_solve(W, s, s, R1, k, -1.0, 1);
+  csc::dense::chol_solve(W, s, s, R, k, -1.0, threads);
+  for (size_t i = 0; i < R.size(); ++i) CHECK(R[i] == R1[i]);
+}
+
 int main() {
   unsigned seed = 11;
   for (int mode = 0; mode < 3; ++mode) {
@@ -159,6 +175,8 @@ int main() {
   cores_case(200, 1, 300, 5);
   for (int k : {1, 2, 5, 16, 40})
     for (int rank : {1, k / 2 + 1, k}) dense_case(k, rank, (unsigned)(k * 31 + rank));
+  threaded_solve_case(128, 256, 4, 5);
+  threaded_solve_case(200, 257, 3, 6);
   if (failures) {
     std::fprintf(stderr, "%d checks failed\n", failures);
     return 1;

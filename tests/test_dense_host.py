@@ -11,13 +11,22 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-@pytest.fixture(scope="module")
-def dense(tmp_path_factory):
-    cxx = shutil.which("g++")
+CLANG = "/opt/rocm/llvm/bin/clang++"  # the compiler the library's host code is built with
+
+
+@pytest.fixture(scope="module", params=["g++", "clang++"])
+def dense(request, tmp_path_factory):
+    """The routines built with the system compiler and with the library's own
+    host compiler and flags (the latter is what libcsc.so runs)."""
+    if request.param == "g++":
+        cxx, flags = shutil.which("g++"), ["-O2", "-ffp-contract=off", "-pthread"]
+    else:
+        cxx = CLANG if os.path.exists(CLANG) else None
+        flags = ["-O3", "-std=c++17", "-Wall", "-ffp-contract=off"]
     if cxx is None:
-        pytest.skip("no C++ compiler")
+        pytest.skip(f"no {request.param}")
     out = tmp_path_factory.mktemp("dense") / "libdense.so"
-    subprocess.run([cxx, "-O2", "-ffp-contract=off", "-shared", "-fPIC", "-o", str(out),
+    subprocess.run([cxx, *flags, "-shared", "-fPIC", "-o", str(out),
                     os.path.join(HERE, "dense_host.cpp"),
                     os.path.join(HERE, "..", "paper_1602_02018_amd", "csrc", "dense.cpp")],
                    check=True)
@@ -25,7 +34,7 @@ def dense(tmp_path_factory):
     pd = C.POINTER(C.c_double)
     lib.dense_orth.argtypes = [pd, C.c_int, C.c_double, pd]
     lib.dense_orth.restype = C.c_int
-    lib.dense_solve.argtypes = [pd, C.c_int, pd, C.c_int, C.c_double]
+    lib.dense_solve.argtypes = [pd, C.c_int, pd, C.c_int, C.c_double, C.c_int]
     lib.dense_solve.restype = C.c_int
     return lib
 
@@ -81,11 +90,29 @@ def test_cholesky_solve(dense, s, k):
     W = M @ M.T + s * np.eye(s)
     Cm = rng.normal(size=(s, k))
     out = Cm.copy()
-    assert dense.dense_solve(_p(np.ascontiguousarray(W)), s, _p(out), k, -1.0) == 1
+    assert dense.dense_solve(_p(np.ascontiguousarray(W)), s, _p(out), k, -1.0, 1) == 1
     np.testing.assert_allclose(out, -np.linalg.solve(W, Cm), rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("s,k,threads", [(128, 256, 4), (250, 250, 8), (200, 257, 3), (64, 64, 8)])
+def test_cholesky_solve_threads_bit_identical(dense, s, k, threads):
+    """The column slices of a threaded solve take exactly the operations of
+    the one-thread solve (a large solve splits, a small one does not).  Also
+    the regression test of a crash: the library's compiler, given the address
+    of the multi-versioned slice solver as a thread function, produced a
+    pointer that faulted when called."""
+    rng = np.random.default_rng(s + k)
+    M = rng.normal(size=(s, s))
+    W = np.ascontiguousarray(M @ M.T + s * np.eye(s))
+    Cm = rng.normal(size=(s, k))
+    one, many = Cm.copy(), Cm.copy()
+    assert dense.dense_solve(_p(W), s, _p(one), k, -1.0, 1) == 1
+    assert dense.dense_solve(_p(W), s, _p(many), k, -1.0, threads) == 1
+    assert np.array_equal(one, many)
+    np.testing.assert_allclose(one, -np.linalg.solve(W, Cm), rtol=1e-8, atol=1e-10)
 
 
 def test_cholesky_rejects_indefinite(dense):
     W = np.array([[1.0, 2.0], [2.0, 1.0]])
     Cm = np.ones((2, 1))
-    assert dense.dense_solve(_p(W), 2, _p(Cm), 1, 1.0) == 0
+    assert dense.dense_solve(_p(W), 2, _p(Cm), 1, 1.0, 1) == 0
