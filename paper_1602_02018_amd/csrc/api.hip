@@ -88,7 +88,7 @@ void apply_tuning(StepArgs& sa) {
 }
 
 const int* step_sched(const csc_graph& g, const Layout& L) {
-  if (!g.sched) return nullptr;
+  if (!g.sched || L.pw < 4) return nullptr;
   const int mode = g_tune_sched.load();
   const int rows_per_wave = 64 / (L.pw / 4);
   if (mode == 2 && rows_per_wave >= 2) return g.sched;
@@ -1262,7 +1262,12 @@ csc_status post_finish(BlockState& st, hipStream_t s) {
 static csc_status block_pass(const csc_graph& g, const Layout& L, const double* a, int p,
                              const Pass& pb, int sr, hipStream_t s) {
   if (sr < 1 || sr >= L.w) return chebyshev_pass(g, L, a, p, EPI_CG, pb, s);
-  const Layout Lc = make_layout(L.n, sr, choose_panel_width(L.n, sr, g.nnz));
+  const int form = filter_form();
+  // a single live column in Clenshaw's form runs as an n-vector (the steps'
+  // single-column path); otherwise a panel layout of the live width
+  const Layout Lc = sr == 1 && form == FORM_CLENSHAW
+                        ? make_layout(L.n, 1, 1)
+                        : make_layout(L.n, sr, choose_panel_width(L.n, sr, g.nnz));
   // the compact blocks live in the wide blocks' buffers, and the compact pass
   // writes its column partials into the wide pass's buffer
   if (Lc.elems() > L.elems() ||
@@ -1271,7 +1276,6 @@ static csc_status block_pass(const csc_graph& g, const Layout& L, const double* 
   Pass pc = pb;
   float* Pc;
   float* Qc;
-  const int form = filter_form();
   const std::vector<PassStep> plan = pass_plan(EPI_CG, a, p, pb.T0, pb.Ta, pb.Tb, form);
   if (form == FORM_CLENSHAW && !plan.empty() && plan.back().epi == EPI_CLEN_CG &&
       (plan.back().Tprev == pb.Tb || plan.back().Tprev == nullptr) && plan.back().Tm != pb.Tb) {

@@ -9,6 +9,7 @@ namespace csc {
 namespace dev {
 
 constexpr int kBlock = 256;
+static_assert(kMomSlots * 64 == kBlock, "one moment partial per wave of a step workgroup");
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -130,9 +131,15 @@ __device__ inline int step_row(const StepArgs& a, int r) {
 // narrow widths.  Shorter rows keep the 4-wide loop (measured no slower; the
 // threshold 16, 24, 32 or 64 changes little, 64 was best by 1-3%).  The sums
 // stay in CSR order either way.
-__device__ inline v4f spmm_row(const StepArgs& a, const v4f* __restrict__ Tm4, int i, int q,
-                               int lpr, bool valid) {
-  v4f acc = (v4f)0.f;
+// T is v4f (lane q of the lpr lanes of a row, four columns) or float (a
+// single column, lpr = 1, q = 0).
+__device__ inline v4f fma_elt(float a, v4f x, v4f acc) { return fma4(a, x, acc); }
+__device__ inline float fma_elt(float a, float x, float acc) { return __builtin_fmaf(a, x, acc); }
+
+template <class T>
+__device__ inline T spmm_row_t(const StepArgs& a, const T* __restrict__ Tm4, int i, int q, int lpr,
+                               bool valid) {
+  T acc = (T)0.f;
   if (valid) {
     int k = a.row_ptr[i];
     const int end = a.row_ptr[i + 1];
@@ -141,7 +148,7 @@ __device__ inline v4f spmm_row(const StepArgs& a, const v4f* __restrict__ Tm4, i
 #pragma unroll
       for (int e = 0; e < 8; ++e) j[e] = a.col[k + e];
       for (;;) {  // entries k .. k + 7 exist here
-        v4f t[8];
+        T t[8];
         float v[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) t[e] = Tm4[(unsigned)j[e] * lpr + q];
@@ -153,7 +160,7 @@ __device__ inline v4f spmm_row(const StepArgs& a, const v4f* __restrict__ Tm4, i
           for (int e = 0; e < 8; ++e) jn[e] = a.col[k + 8 + e];
         }
 #pragma unroll
-        for (int e = 0; e < 8; ++e) acc = fma4(v[e], t[e], acc);
+        for (int e = 0; e < 8; ++e) acc = fma_elt(v[e], t[e], acc);
         k += 8;
         if (!more) break;  // fewer than 8 entries left
 #pragma unroll
@@ -163,18 +170,23 @@ __device__ inline v4f spmm_row(const StepArgs& a, const v4f* __restrict__ Tm4, i
     for (; k + 4 <= end; k += 4) {
       const int j0 = a.col[k], j1 = a.col[k + 1], j2 = a.col[k + 2], j3 = a.col[k + 3];
       const float v0 = a.val[k], v1 = a.val[k + 1], v2 = a.val[k + 2], v3 = a.val[k + 3];
-      const v4f t0 = Tm4[(unsigned)j0 * lpr + q];
-      const v4f t1 = Tm4[(unsigned)j1 * lpr + q];
-      const v4f t2 = Tm4[(unsigned)j2 * lpr + q];
-      const v4f t3 = Tm4[(unsigned)j3 * lpr + q];
-      acc = fma4(v0, t0, acc);
-      acc = fma4(v1, t1, acc);
-      acc = fma4(v2, t2, acc);
-      acc = fma4(v3, t3, acc);
+      const T t0 = Tm4[(unsigned)j0 * lpr + q];
+      const T t1 = Tm4[(unsigned)j1 * lpr + q];
+      const T t2 = Tm4[(unsigned)j2 * lpr + q];
+      const T t3 = Tm4[(unsigned)j3 * lpr + q];
+      acc = fma_elt(v0, t0, acc);
+      acc = fma_elt(v1, t1, acc);
+      acc = fma_elt(v2, t2, acc);
+      acc = fma_elt(v3, t3, acc);
     }
-    for (; k < end; ++k) acc = fma4(a.val[k], Tm4[(unsigned)a.col[k] * lpr + q], acc);
+    for (; k < end; ++k) acc = fma_elt(a.val[k], Tm4[(unsigned)a.col[k] * lpr + q], acc);
   }
   return acc;
+}
+
+__device__ inline v4f spmm_row(const StepArgs& a, const v4f* __restrict__ Tm4, int i, int q,
+                               int lpr, bool valid) {
+  return spmm_row_t<v4f>(a, Tm4, i, q, lpr, valid);
 }
 
 // Per-column sums over the rows of a workgroup in a fixed order, written to
@@ -238,6 +250,39 @@ __device__ inline void clen_unit(const StepArgs& a, int u) {
     column_partials(cs, m, a.L.pw, sh, a.part + (size_t)panel * a.L.pw * a.tiles + tile,
                     (size_t)a.tiles);
     __syncthreads();
+  }
+}
+
+// One Clenshaw step (EPI_CLEN or EPI_CLEN_CG) on a single column stored as
+// an n-vector (layout width and panel width 1): one row per thread, rows
+// u*256 .. u*256+255 of unit u in natural order.  Every element takes the
+// operations of clen_unit's lane for that column, so the results are the
+// same bit for bit; the gathered vector is a quarter of a 4-column panel's
+// bytes (4 MB at 1e6 nodes, about an XCD's L2).  EPI_CLEN_CG writes the
+// unit's partial of <r, ap> to part[u] (column 0 of the column partials).
+template <int EPI, bool PREV>
+__device__ inline void clen_scalar_unit(const StepArgs& a, int u) {
+  static_assert(EPI == EPI_CLEN || EPI == EPI_CLEN_CG, "single-column Clenshaw steps");
+  const int i = u * kBlock + (int)threadIdx.x;
+  const bool valid = i < a.L.n;
+  const float acc = spmm_row_t<float>(a, a.Tm, i, 0, 1, valid);
+  float r = 0.f, out = 0.f;
+  if (valid) {
+    r = a.T0[i];
+    out = __builtin_fmaf(a.c1, acc, a.c0 * r);
+    if (PREV) out = out - a.Tprev[i];
+    if constexpr (EPI == EPI_CLEN) a.Tnext[i] = out;
+  }
+  if constexpr (EPI == EPI_CLEN_CG) {
+    __shared__ double sh[8];
+    double cs = 0.0;
+    if (valid) {
+      const float ap = __builtin_fmaf(a.mask[i], r, a.gamma * (r - out));
+      a.Y[i] = ap;
+      cs = (double)r * (double)ap;
+    }
+    const double b = block_sum(cs, sh);
+    if (threadIdx.x == 0) a.part[u] = b;
   }
 }
 

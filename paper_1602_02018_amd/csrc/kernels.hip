@@ -23,6 +23,11 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(StepArgs a) {
   cheb_unit<EPI, FIRST, LAST>(a, work_unit(blockIdx.x, a.L.np * a.tiles, a.tiles, a.xcd));
 }
 
+template <int EPI, bool PREV>
+__global__ __launch_bounds__(kBlock) void k_clen_scalar(StepArgs a) {
+  clen_scalar_unit<EPI, PREV>(a, blockIdx.x);
+}
+
 hipError_t launch_step(const StepArgs& a, int epi, bool first, bool last, hipStream_t s) {
   const dim3 grid((unsigned)(a.L.np * a.tiles)), block(kBlock);
 #define CSC_STEP(E, F, L) hipLaunchKernelGGL((k_cheb_step<E, F, L>), grid, block, 0, s, a)
@@ -387,10 +392,25 @@ inline unsigned grid_for(size_t n, size_t per = kBlock, size_t cap = 65536) {
 }  // namespace
 
 // ============================================================ launchers ===
-int rows_per_tile(int pw) { return 4 * (64 / (pw / 4)); }
+// rows of a workgroup: PW/4 lanes per row, or one row per thread for the
+// single-column layout (PW = 1)
+int rows_per_tile(int pw) { return pw < 4 ? kBlock : 4 * (64 / (pw / 4)); }
 int tiles_for(const Layout& L) { return (L.n + rows_per_tile(L.pw) - 1) / rows_per_tile(L.pw); }
 
 hipError_t launch_cheb_step(const StepArgs& a, int epi, bool first, bool last, hipStream_t s) {
+  if (a.L.pw == 1 && a.L.w == 1 && a.L.np == 1) {  // a single column as an n-vector
+    const dim3 grid((unsigned)tiles_for(a.L)), block(kBlock);
+    if (epi == EPI_CLEN) {
+      if (first) hipLaunchKernelGGL((k_clen_scalar<EPI_CLEN, false>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_clen_scalar<EPI_CLEN, true>), grid, block, 0, s, a);
+    } else if (epi == EPI_CLEN_CG) {
+      if (first) hipLaunchKernelGGL((k_clen_scalar<EPI_CLEN_CG, false>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_clen_scalar<EPI_CLEN_CG, true>), grid, block, 0, s, a);
+    } else {
+      return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   if (a.L.pw < 4 || a.L.pw > 256 || (a.L.pw & 3)) return hipErrorInvalidValue;
   return launch_step(a, epi, first, last, s);
 }
