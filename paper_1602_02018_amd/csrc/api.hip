@@ -1434,7 +1434,7 @@ extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* orde
     pb.Ta = Ta;
     pb.Tb = Tb;
     pb.Y = AP;
-    pb.part = part;
+    pb.part = nullptr;  // the block CG takes P^T Q from a Gram, not the pass's column partials
     pb.mask = mask;
     pb.gamma = (float)gamma;
     for (int it = 1; it <= max_iter && !bs.finished; ++it) {

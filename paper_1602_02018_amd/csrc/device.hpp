@@ -247,9 +247,11 @@ __device__ inline void clen_unit(const StepArgs& a, int u) {
       cs[2] = (double)r.z * (double)ap.z;
       cs[3] = (double)r.w * (double)ap.w;
     }
-    column_partials(cs, m, a.L.pw, sh, a.part + (size_t)panel * a.L.pw * a.tiles + tile,
-                    (size_t)a.tiles);
-    __syncthreads();
+    if (a.part) {  // the per-column <p, Ap> partials (NULL: not wanted, no barrier)
+      column_partials(cs, m, a.L.pw, sh, a.part + (size_t)panel * a.L.pw * a.tiles + tile,
+                      (size_t)a.tiles);
+      __syncthreads();
+    }
   }
 }
 
@@ -259,7 +261,8 @@ __device__ inline void clen_unit(const StepArgs& a, int u) {
 // operations of clen_unit's lane for that column, so the results are the
 // same bit for bit; the gathered vector is a quarter of a 4-column panel's
 // bytes (4 MB at 1e6 nodes, about an XCD's L2).  EPI_CLEN_CG writes the
-// unit's partial of <r, ap> to part[u] (column 0 of the column partials).
+// unit's partial of <r, ap> to part[u] (column 0 of the column partials)
+// unless part is NULL.
 template <int EPI, bool PREV>
 __device__ inline void clen_scalar_unit(const StepArgs& a, int u) {
   static_assert(EPI == EPI_CLEN || EPI == EPI_CLEN_CG, "single-column Clenshaw steps");
@@ -281,8 +284,10 @@ __device__ inline void clen_scalar_unit(const StepArgs& a, int u) {
       a.Y[i] = ap;
       cs = (double)r * (double)ap;
     }
-    const double b = block_sum(cs, sh);
-    if (threadIdx.x == 0) a.part[u] = b;
+    if (a.part) {
+      const double b = block_sum(cs, sh);
+      if (threadIdx.x == 0) a.part[u] = b;
+    }
   }
 }
 
@@ -411,9 +416,11 @@ __device__ inline void cheb_unit(const StepArgs& a, int u) {
       cs[2] = (double)p0.z * (double)ap.z;
       cs[3] = (double)p0.w * (double)ap.w;
     }
-    column_partials(cs, m, a.L.pw, sh, a.part + (size_t)panel * a.L.pw * a.tiles + tile,
-                    (size_t)a.tiles);
-    __syncthreads();
+    if (a.part) {  // as in clen_unit
+      column_partials(cs, m, a.L.pw, sh, a.part + (size_t)panel * a.L.pw * a.tiles + tile,
+                      (size_t)a.tiles);
+      __syncthreads();
+    }
   }
 }
 
