@@ -39,7 +39,7 @@ __device__ inline float gauss_entry(uint64_t e, uint32_t t, uint32_t sid, uint64
 // ------------------------------------------------------- Chebyshev step ---
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-__device__ inline v4f fma4(float a, v4f x, v4f acc) {
+__host__ __device__ inline v4f fma4(float a, v4f x, v4f acc) {
   return __builtin_elementwise_fma((v4f)a, x, acc);
 }
 
@@ -72,7 +72,7 @@ __device__ inline double dot4v(v4f a, v4f b) {
 //      XCD keeps one row slab and all XCDs walk the panels in step, so only
 //      one panel's gathered rows are live at a time.
 // Each order is a bijection of [0, U).
-__device__ inline int work_unit(int b, int U, int T, int xcd) {
+__host__ __device__ inline int work_unit(int b, int U, int T, int xcd) {
   if (!xcd) return b;
   const int x = b & 7, j = b >> 3, q = U >> 3, r = U & 7;
   const int v = x * q + (x < r ? x : r) + j;
@@ -116,7 +116,7 @@ __device__ inline RowMap row_map(int pw) {
 // Row handled at walk position r of a step: r itself, or sched[r] when the
 // step follows a row schedule; -1 past the last row (or for a schedule entry
 // outside [0, n), which a valid schedule never holds).
-__device__ inline int step_row(const StepArgs& a, int r) {
+__host__ __device__ inline int step_row(const StepArgs& a, int r) {
   if (r >= a.L.n) return -1;
   if (!a.sched) return r;
   const int i = a.sched[r];
@@ -132,13 +132,16 @@ __device__ inline int step_row(const StepArgs& a, int r) {
 // threshold 16, 24, 32 or 64 changes little, 64 was best by 1-3%).  The sums
 // stay in CSR order either way.
 // T is v4f (lane q of the lpr lanes of a row, four columns) or float (a
-// single column, lpr = 1, q = 0).
-__device__ inline v4f fma_elt(float a, v4f x, v4f acc) { return fma4(a, x, acc); }
-__device__ inline float fma_elt(float a, float x, float acc) { return __builtin_fmaf(a, x, acc); }
+// single column, lpr = 1, q = 0).  Host-callable too, so that a CPU build
+// can check the loop's accesses and sums (tests/step_host.cpp).
+__host__ __device__ inline v4f fma_elt(float a, v4f x, v4f acc) { return fma4(a, x, acc); }
+__host__ __device__ inline float fma_elt(float a, float x, float acc) {
+  return __builtin_fmaf(a, x, acc);
+}
 
 template <class T>
-__device__ inline T spmm_row_t(const StepArgs& a, const T* __restrict__ Tm4, int i, int q, int lpr,
-                               bool valid) {
+__host__ __device__ inline T spmm_row_t(const StepArgs& a, const T* __restrict__ Tm4, int i, int q,
+                                        int lpr, bool valid) {
   T acc = (T)0.f;
   if (valid) {
     int k = a.row_ptr[i];
