@@ -1249,8 +1249,9 @@ csc_status post_finish(BlockState& st, hipStream_t s) {
 
 // Q = M P for the block CG.  P's live columns are its first sr; when they are
 // fewer than the block's width the pass runs on a compact copy of them (a
-// layout of width sr with its own panel width) and only those columns of Q
-// are written back (the block CG reads no column of Q beyond sr).  Every
+// layout of width sr with its own panel width, or an n-vector for a single
+// column in Clenshaw's form) and only those columns of Q are written back
+// (the block CG reads no column of Q beyond sr).  Every
 // element sums its row's neighbours in CSR order whatever the layout, so Q
 // is the same either way; a block whose columns have partly converged costs
 // a pass of its live width.
@@ -1268,10 +1269,10 @@ static csc_status block_pass(const csc_graph& g, const Layout& L, const double* 
   const Layout Lc = sr == 1 && form == FORM_CLENSHAW
                         ? make_layout(L.n, 1, 1)
                         : make_layout(L.n, sr, choose_panel_width(L.n, sr, g.nnz));
-  // the compact blocks live in the wide blocks' buffers, and the compact pass
-  // writes its column partials into the wide pass's buffer
+  // the compact blocks live in the wide blocks' buffers, and a compact pass
+  // given a partial buffer writes its column partials into the wide pass's
   if (Lc.elems() > L.elems() ||
-      (size_t)Lc.np * Lc.pw * tiles_for(Lc) > (size_t)L.np * L.pw * tiles_for(L))
+      (pb.part && (size_t)Lc.np * Lc.pw * tiles_for(Lc) > (size_t)L.np * L.pw * tiles_for(L)))
     return chebyshev_pass(g, L, a, p, EPI_CG, pb, s);
   Pass pc = pb;
   float* Pc;
