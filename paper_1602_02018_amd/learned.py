@@ -12,7 +12,7 @@ the rest of the search.  Everything runs through libcsc:
                 first pass's count curve (csc_count_root);
 * ``evaluate``  plain vs learned dichotomy on held-out graphs: passes used,
                 and |count(lambda) - k| from an independent eigencount pass
-                (fresh signals, sub-stream 1000) as the judge of each lambda;
+                (fresh signals, sub-stream 1000) as the referee of each lambda;
                 the one-pass KPM root of the first pass's count curve is
                 reported beside them.
 
@@ -168,15 +168,15 @@ def evaluate(specs, params, device="cuda", p: int = 50, pool=None, chunk: int = 
         learned = api.estimate_lambda_k_batched(gs, ks, p, ncs, seeds, mlp_params=params)
         for (s, _, _), g, a, b, nc in zip(buf, gs, plain, learned, ncs):
             lk, _ = api.count_root(a.moments, s["k"], nc)
-            judge = {}
+            referee = {}
             for name, lam in (("plain", a.lam), ("learned", b.lam), ("kpm", lk)):
                 cnt, _ = api.eigencount(g, lam, p, nc, s["seed"], 1000)
-                judge[name] = abs(cnt - s["k"])
+                referee[name] = abs(cnt - s["k"])
             rows.append(dict(N=g.n, k=s["k"], kind=s["kind"], plain_steps=a.steps,
                              learned_steps=b.steps, plain_lambda=a.lam, learned_lambda=b.lam,
                              kpm_lambda=lk, learned_status=b.status, plain_status=a.status,
-                             err_plain=judge["plain"], err_learned=judge["learned"],
-                             err_kpm=judge["kpm"]))
+                             err_plain=referee["plain"], err_learned=referee["learned"],
+                             err_kpm=referee["kpm"]))
         buf.clear()
         if log:
             log(f"evaluated {len(rows)} graphs")

@@ -21,7 +21,7 @@ def test_learned_bracket_saves_passes_at_equal_accuracy():
         plain_steps.append(a.steps)
         learned_steps.append(b.steps)
         for lam, errs in ((a.lam, err_plain), (b.lam, err_learned)):
-            cnt, _ = api.eigencount(g, lam, 50, nc, spec["seed"], 1000)  # independent judge
+            cnt, _ = api.eigencount(g, lam, 50, nc, spec["seed"], 1000)  # independent referee count
             errs.append(abs(cnt - spec["k"]))
     print(f"passes plain {np.mean(plain_steps):.2f} learned {np.mean(learned_steps):.2f}; "
           f"|count - k| plain {np.mean(err_plain):.2f} learned {np.mean(err_learned):.2f}")
