@@ -695,7 +695,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(the path shards by columns across GPUs, which this build does not run)",
+              f"(the path would shard by columns across GPUs; no multi-GPU form is implemented)",
               file=sys.stderr)
         sys.exit(2)
 
