@@ -103,16 +103,16 @@ __device__ inline void sqd_t3(const double* Xt, int n, int i, int s, const doubl
   const int i1 = i + s < n ? i + s : i, i2 = i + 2 * s < n ? i + 2 * s : i;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   int j = 0;
-  for (; j + 8 <= d; j += 8) {
-    double x0[8], x1[8], x2[8];
+  for (; j + 4 <= d; j += 4) {  // 12 loads in flight (the kernel keeps within 128 VGPRs)
+    double x0[4], x1[4], x2[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 4; ++q) {
       x0[q] = Xt[(size_t)(j + q) * n + i];
       x1[q] = Xt[(size_t)(j + q) * n + i1];
       x2[q] = Xt[(size_t)(j + q) * n + i2];
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 4; ++q) {
       const double cq = c[j + q];
       const double e0 = x0[q] - cq, e1 = x1[q] - cq, e2 = x2[q] - cq;
       a0 = a0 + e0 * e0;
