@@ -1204,7 +1204,7 @@ csc_status post_launch_b(BlockState& st, hipStream_t s) {
   CSC_HIP(launch_block_mul(L, 1.f, b.X, b.P, b.S_a, sr, k, k, b.X, s));
   CSC_HIP(launch_block_mul(L, 1.f, b.R, b.Q, b.S_na, sr, k, k, b.R, s));
   CSC_HIP(launch_col_dot(L, b.R, b.R, b.part, s));
-  CSC_HIP(launch_reduce(b.part, tiles_for(L), k, b.rn2, s));
+  CSC_HIP(launch_reduce(b.part, col_dot_chunks(L), k, b.rn2, s));
   if (st.jacobi) CSC_HIP(launch_jacobi(L, b.R, b.mask, st.gamma, b.Z, s));
   CSC_HIP(launch_gram(L, b.Q, st.jacobi ? b.Z : b.R, sr, k, b.gpart, b.G, k, s));
   st.rn2.resize(k);
@@ -1401,7 +1401,7 @@ extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* orde
   CSC_HIP(launch_fill_i32(flags, 4, 0, s));
   CSC_HIP(launch_cg_scatter(L, n, idx, labels_r, weights, Rr, P, mask, flags + 2, s));
   CSC_HIP(launch_col_dot(L, Rr, Rr, part, s));
-  CSC_HIP(launch_reduce(part, tiles, k, bnorm2, s));
+  CSC_HIP(launch_reduce(part, col_dot_chunks(L), k, bnorm2, s));
   // rr = bnorm2; active = bnorm2 > 0 (beta doubles as the activity probe)
   CSC_HIP(hipMemcpyAsync(rr, bnorm2, k * sizeof(double), hipMemcpyDeviceToDevice, s));
   {
@@ -1446,7 +1446,7 @@ extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* orde
     }
     block_finish(bs, max_iter);
     CSC_HIP(launch_col_dot(L, Xi, Xi, part, s));
-    CSC_HIP(launch_reduce(part, tiles, k, colnorm2, s));
+    CSC_HIP(launch_reduce(part, col_dot_chunks(L), k, colnorm2, s));
     CSC_HIP(launch_labels(L, Xi, colnorm2, labels, X, ldx, order, s));
     CSC_HIP(hipStreamSynchronize(s));
     if (iters_out) std::memcpy(iters_out, bs.iters.data(), k * sizeof(int));
@@ -1479,7 +1479,7 @@ extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* orde
     if (nactive == 0) break;
   }
   CSC_HIP(launch_col_dot(L, Xi, Xi, part, s));
-  CSC_HIP(launch_reduce(part, tiles, k, colnorm2, s));
+  CSC_HIP(launch_reduce(part, col_dot_chunks(L), k, colnorm2, s));
   CSC_HIP(launch_labels(L, Xi, colnorm2, labels, X, ldx, order, s));
   std::vector<int> hit(k);
   std::vector<double> hrel(k);

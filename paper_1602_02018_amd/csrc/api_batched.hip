@@ -757,7 +757,7 @@ extern "C" csc_status csc_interpolate_batched(
                               b.P, b.mask,
                               flags + 4 * g + 2, s));
     CSC_HIP(launch_col_dot(b.L, b.Rr, b.Rr, b.part, s));
-    CSC_HIP(launch_reduce(b.part, b.tiles, k[g], b.bnorm2, s));
+    CSC_HIP(launch_reduce(b.part, col_dot_chunks(b.L), k[g], b.bnorm2, s));
     CSC_HIP(hipMemcpyAsync(b.rr, b.bnorm2, k[g] * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
   std::vector<int> hflags((size_t)G * 4);
@@ -921,8 +921,9 @@ extern "C" csc_status csc_interpolate_batched(
     for (int g = 0; g < G; ++g) {
       block_finish(bs[g], max_iter);
       const Buf& b = B[g];
-      h_cd[g] = ColDotItem{b.L, b.tiles, b.Xi, b.Xi, b.part, nullptr};
-      h_cn[g] = ReduceItem{b.part, b.tiles, b.colnorm2, nullptr};
+      h_cd[g] = ColDotItem{b.L, col_dot_chunks(b.L), col_dot_rows(b.L), b.Xi, b.Xi, b.part,
+                           nullptr};
+      h_cn[g] = ReduceItem{b.part, col_dot_chunks(b.L), b.colnorm2, nullptr};
       h_lab[g] = LabelItem{b.L, b.Xi, b.colnorm2, labels[g], X ? X[g] : nullptr,
                            (X && X[g]) ? ldx[g] : 0, order ? order[g] : nullptr};
     }
@@ -976,8 +977,8 @@ extern "C" csc_status csc_interpolate_batched(
   std::vector<LabelItem> h_lab(G);
   for (int g = 0; g < G; ++g) {
     const Buf& b = B[g];
-    h_cd[g] = ColDotItem{b.L, b.tiles, b.Xi, b.Xi, b.part, nullptr};
-    h_cn[g] = ReduceItem{b.part, b.tiles, b.colnorm2, nullptr};
+    h_cd[g] = ColDotItem{b.L, col_dot_chunks(b.L), col_dot_rows(b.L), b.Xi, b.Xi, b.part, nullptr};
+    h_cn[g] = ReduceItem{b.part, col_dot_chunks(b.L), b.colnorm2, nullptr};
     h_lab[g] = LabelItem{b.L, b.Xi, b.colnorm2, labels[g], X ? X[g] : nullptr,
                          (X && X[g]) ? ldx[g] : 0, order ? order[g] : nullptr};
   }

@@ -51,7 +51,8 @@ __global__ __launch_bounds__(kBlock) void kb_col_dot(const ColDotItem* items, co
   const Work w = work[blockIdx.x];
   const ColDotItem it = items[w.item];
   if (it.live && *it.live == 0) return;
-  for (int u = w.u0; u < w.u0 + w.cnt; ++u) col_dot_unit(it.L, it.tiles, it.A, it.B, it.part, u);
+  for (int u = w.u0; u < w.u0 + w.cnt; ++u)
+    col_dot_unit(it.L, it.chunks, it.rows, it.A, it.B, it.part, u);
 }
 
 __global__ __launch_bounds__(kBlock) void kb_cg_alpha(const CgItem* items) {

@@ -471,24 +471,34 @@ __device__ inline void reduce_vec(const double* part, int len, double* out) {
   __syncthreads();
 }
 
-// Work unit u = (panel, tile): per-column sums of A(i, c) B(i, c) over the tile.
-__device__ inline void col_dot_unit(const Layout& L, int tiles, const float* A, const float* B,
-                                    double* part, int u) {
+// Work unit u = (panel, chunk) of np * chunks: per-column sums of A(i, c) B(i, c)
+// over rows [chunk * rows, (chunk + 1) * rows), to part[c * chunks + chunk].
+// Each lane sums its four columns over its rows of the chunk in order (the
+// products of float32 entries are exact in float64), then the workgroup's
+// row slots are added in a fixed order.  One partial per column and chunk
+// (a few thousand chunks in all), so the writes and the reduction after them
+// stay small; units past np * chunks (a work list sized for more) do nothing.
+__device__ inline void col_dot_unit(const Layout& L, int chunks, int rows, const float* A,
+                                    const float* B, double* part, int u) {
+  if (u >= L.np * chunks) return;  // uniform over the workgroup
   __shared__ double sh[4 * 64 * 4];
   const RowMap m = row_map(L.pw);
-  const int panel = u / tiles, tile = u - panel * tiles;
-  const int i = tile * m.rpb + m.r;
+  const int panel = u / chunks, chunk = u - panel * chunks;
+  const int r0 = chunk * rows, r1 = min(L.n, r0 + rows);
   double cs[4] = {0.0, 0.0, 0.0, 0.0};
-  if (m.lane_ok && i < L.n) {
-    const size_t o4 = (size_t)panel * L.panel_elems() / 4 + (size_t)i * m.lpr + m.q;
-    const v4f x = reinterpret_cast<const v4f*>(A)[o4];
-    const v4f y = reinterpret_cast<const v4f*>(B)[o4];
-    cs[0] = (double)x.x * y.x;
-    cs[1] = (double)x.y * y.y;
-    cs[2] = (double)x.z * y.z;
-    cs[3] = (double)x.w * y.w;
+  if (m.lane_ok) {
+    const size_t pb4 = (size_t)panel * L.panel_elems() / 4;
+    for (int i = r0 + m.r; i < r1; i += m.rpb) {
+      const size_t o4 = pb4 + (size_t)i * m.lpr + m.q;
+      const v4f x = reinterpret_cast<const v4f*>(A)[o4];
+      const v4f y = reinterpret_cast<const v4f*>(B)[o4];
+      cs[0] += (double)x.x * (double)y.x;
+      cs[1] += (double)x.y * (double)y.y;
+      cs[2] += (double)x.z * (double)y.z;
+      cs[3] += (double)x.w * (double)y.w;
+    }
   }
-  column_partials(cs, m, L.pw, sh, part + (size_t)panel * L.pw * tiles + tile, (size_t)tiles);
+  column_partials(cs, m, L.pw, sh, part + (size_t)panel * L.pw * chunks + chunk, (size_t)chunks);
   __syncthreads();
 }
 

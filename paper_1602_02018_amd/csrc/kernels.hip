@@ -8,6 +8,8 @@
 // lane owning four consecutive columns of the panel, so one gathered
 // neighbour row is a contiguous PW*4-byte segment read by consecutive lanes.  No MFMA: the step
 // moves ~16-20 bytes per 2 flops and is bound by memory bandwidth.
+#include <algorithm>
+
 #include <hipcub/hipcub.hpp>
 
 #include "device.hpp"
@@ -262,9 +264,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* part, int len, 
   reduce_vec(part + (size_t)blockIdx.x * len, len, out + blockIdx.x);
 }
 
-__global__ __launch_bounds__(kBlock) void k_col_dot(Layout L, int tiles, const float* A,
-                                                    const float* B, double* part) {
-  col_dot_unit(L, tiles, A, B, part, blockIdx.x);
+__global__ __launch_bounds__(kBlock) void k_col_dot(Layout L, int chunks, int rows,
+                                                    const float* A, const float* B, double* part) {
+  col_dot_unit(L, chunks, rows, A, B, part, blockIdx.x);
 }
 
 // ------------------------------------------------------------ sampling ---
@@ -525,11 +527,17 @@ hipError_t launch_reduce(const double* part, int len, int nvec, double* out, hip
   return hipGetLastError();
 }
 
+int col_dot_chunks(const Layout& L) { return std::max(1, std::min(tiles_for(L), 2048 / L.np)); }
+int col_dot_rows(const Layout& L) {
+  const int c = col_dot_chunks(L);
+  return (L.n + c - 1) / c;
+}
+
 hipError_t launch_col_dot(const Layout& L, const float* A, const float* B, double* part,
                           hipStream_t s) {
-  const int tiles = tiles_for(L);
-  hipLaunchKernelGGL(k_col_dot, dim3((unsigned)(L.np * tiles)), dim3(kBlock), 0, s, L, tiles, A,
-                     B, part);
+  const int chunks = col_dot_chunks(L);
+  hipLaunchKernelGGL(k_col_dot, dim3((unsigned)(L.np * chunks)), dim3(kBlock), 0, s, L, chunks,
+                     col_dot_rows(L), A, B, part);
   return hipGetLastError();
 }
 

@@ -95,7 +95,8 @@ struct ReduceItem {
 
 struct ColDotItem {
   Layout L;
-  int tiles = 0;
+  int chunks = 0;  // col_dot_chunks(L)
+  int rows = 0;    // col_dot_rows(L)
   const float* A = nullptr;
   const float* B = nullptr;
   double* part = nullptr;
@@ -206,7 +207,11 @@ hipError_t launch_slot_map(int n_rows, const int* rows, int n, int* slot, int* b
 
 // Deterministic reductions: out[v] = sum_t part[v * len + t], fixed order.
 hipError_t launch_reduce(const double* part, int len, int nvec, double* out, hipStream_t s);
-// part[c * tiles + tile] = sum over the tile's rows of A(i, c) * B(i, c).
+// part[c * chunks + chunk] = sum over the chunk's rows of A(i, c) * B(i, c),
+// chunks = col_dot_chunks(L) (at most tiles_for(L)) of col_dot_rows(L) rows;
+// launch_reduce(part, col_dot_chunks(L), w, out) then gives the column sums.
+int col_dot_chunks(const Layout& L);
+int col_dot_rows(const Layout& L);
 hipError_t launch_col_dot(const Layout& L, const float* A, const float* B, double* part,
                           hipStream_t s);
 
