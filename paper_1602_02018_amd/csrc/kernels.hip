@@ -378,10 +378,45 @@ __global__ __launch_bounds__(kBlock) void k_cg_update2(Layout L, const float* R,
     cg_update2_elem(L, R, P, beta, active, t);
 }
 
-__global__ void k_labels(Layout L, const float* X, const double* colnorm2, int* labels,
-                         float* Xout, int ldx, const int* out_map) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < L.n) labels_row(L, X, colnorm2, labels, Xout, ldx, out_map, i);
+// Hard labels with one wave per row (rows grid-strided over the waves): lane
+// l takes columns l, l + 64, ... under labels_row's rule (the first column of
+// the largest x_c / sqrt(n2_c) among columns with n2_c > 0), and the lanes'
+// picks merge to the larger value, the lower column on equal values: for
+// finite values the column labels_row picks.  The row's reads and the copy
+// out of X are coalesced over the lanes.
+__global__ __launch_bounds__(kBlock) void k_labels(Layout L, const float* X,
+                                                   const double* colnorm2, int* labels,
+                                                   float* Xout, int ldx, const int* out_map) {
+  const int lane = threadIdx.x & 63;
+  const int nw = (int)((gridDim.x * blockDim.x) >> 6);
+  const size_t pe = L.panel_elems();
+  for (int i = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); i < L.n; i += nw) {
+    const int o = out_map ? out_map[i] : i;
+    double best = 0.0;
+    int arg = -1;  // no column with n2 > 0 yet
+    for (int c = lane; c < L.w; c += 64) {
+      const float x = X[(size_t)(c / L.pw) * pe + (size_t)i * L.pw + c % L.pw];
+      if (Xout) Xout[(size_t)o * ldx + c] = x;
+      const double n2 = colnorm2[c];
+      if (n2 > 0.0) {
+        const double v = (double)x / sqrt(n2);
+        if (arg < 0 || v > best) {
+          best = v;
+          arg = c;
+        }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int oa = __shfl_xor(arg, off);
+      if (oa >= 0 && (arg < 0 || ob > best || (ob == best && oa < arg))) {
+        best = ob;
+        arg = oa;
+      }
+    }
+    if (lane == 0) labels[o] = arg < 0 ? 0 : arg;
+  }
 }
 
 inline unsigned grid_for(size_t n, size_t per = kBlock, size_t cap = 65536) {
@@ -615,8 +650,9 @@ hipError_t launch_cg_update2(const Layout& L, const float* R, float* P, const do
 
 hipError_t launch_labels(const Layout& L, const float* X, const double* colnorm2, int* labels,
                          float* Xout, int ldx, const int* out_map, hipStream_t s) {
-  hipLaunchKernelGGL(k_labels, dim3(grid_for(L.n, kBlock, 1u << 30)), dim3(kBlock), 0, s, L, X,
-                     colnorm2, labels, Xout, ldx, out_map);
+  // a wave per row: 4 rows per workgroup, at most 16384 workgroups (rows grid-strided)
+  hipLaunchKernelGGL(k_labels, dim3(grid_for((size_t)L.n, kBlock / 64, 16384)), dim3(kBlock), 0, s,
+                     L, X, colnorm2, labels, Xout, ldx, out_map);
   return hipGetLastError();
 }
 
