@@ -1194,14 +1194,17 @@ void post_host_a(BlockState& st) {
 
 // X += P alpha, R -= Q alpha; the column norms of R, and the next search
 // block's Gram Q^T Z formed before the convergence check so that both come
-// back in one round trip (after the last iteration it goes unused)
+// back in one round trip (after the last iteration it goes unused).  X feeds
+// nothing back into the iteration (R is updated by its own recurrence), so
+// its update takes float32 sums on the float32 matrix cores, the precision
+// form's float32 vector update, whatever CSC_TUNE_BLOCK_PRODUCT says.
 csc_status post_launch_b(BlockState& st, hipStream_t s) {
   const BlockBufs& b = st.b;
   const Layout& L = st.L;
   const int k = st.k, sr = st.sr;
   CSC_TRY(upload_d(b.S_a, st.C, s));
   CSC_TRY(upload_d(b.S_na, st.N, s));
-  CSC_HIP(launch_block_mul(L, 1.f, b.X, b.P, b.S_a, sr, k, k, b.X, s));
+  CSC_HIP(launch_block_mul(L, 1.f, b.X, b.P, b.S_a, sr, k, k, b.X, s, /*f32=*/true));
   CSC_HIP(launch_block_mul(L, 1.f, b.R, b.Q, b.S_na, sr, k, k, b.R, s));
   CSC_HIP(launch_col_dot(L, b.R, b.R, b.part, s));
   CSC_HIP(launch_reduce(b.part, col_dot_chunks(L), k, b.rn2, s));

@@ -347,10 +347,10 @@ hipError_t launch_gram(const Layout& L, const float* A, const float* B, int ka, 
 
 hipError_t launch_block_mul(const Layout& L, float c0, const float* In0, const float* In1,
                             const double* S, int kin, int kout, int lds, float* Out,
-                            hipStream_t s) {
+                            hipStream_t s, bool f32) {
   const int W = L.np * L.pw;
   const dim3 grid((unsigned)((L.n + kMR - 1) / kMR), (unsigned)((W + kMC - 1) / kMC));
-  if (block_product_f32())
+  if (f32 || block_product_f32())
     hipLaunchKernelGGL(k_block_mul<true>, grid, dim3(256), 0, s, L, c0, In0, In1, S, kin, kout,
                        lds, Out);
   else

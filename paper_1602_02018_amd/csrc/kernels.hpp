@@ -259,9 +259,10 @@ hipError_t launch_jacobi(const Layout& L, const float* R, const float* mask, flo
                          hipStream_t s);
 // CSC_TUNE_BLOCK_PRODUCT: block products with float32 sums (true) or float64 sums
 bool block_product_f32();
+// f32: float32 sums for this product whatever the knob says
 hipError_t launch_block_mul(const Layout& L, float c0, const float* In0, const float* In1,
                             const double* S, int kin, int kout, int lds, float* Out,
-                            hipStream_t s);
+                            hipStream_t s, bool f32 = false);
 
 // Row schedule of a CSR graph (order.hip): chunks of kSchedChunk rows, each
 // by decreasing degree, ties by index.
