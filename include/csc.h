@@ -160,16 +160,17 @@ int32_t csc_get_filter_form(void);
  *   ahead there.  With equal group sizes the batched and the single calls
  *   give the same results bit for bit; at the defaults (4 and 1) their
  *   counts agree up to the order of float64 sums, as above.
- * CSC_TUNE_BLOCK_PRODUCT (0/1, default 0): the block CG's right products
- *   R -= Q alpha, P = Z T and Z += P beta (Sec. 4.4's interpolation solve):
- *   0 forms each output element as a float64 sum of exact products of the
- *   float32 entries and the float64 k x k step matrices, rounded once to
- *   float32 (float64 matrix cores); 1 rounds the step matrices to float32
- *   and sums in float32 (float32 matrix cores), the precision form's float32
- *   vector updates.  X += P alpha, which feeds nothing back into the
- *   iteration, always takes float32 sums.  This knob changes the rounding of
- *   the solve (not the tolerance it meets); the Gram matrices (inner
- *   products) stay float64 either way.
+ * CSC_TUNE_BLOCK_PRODUCT (0/1, default 0): the block CG's residual update
+ *   R -= Q alpha (Sec. 4.4's interpolation solve): 0 forms each output
+ *   element as a float64 sum of exact products of the float32 entries and
+ *   the float64 k x k step matrix, rounded once to float32 (float64 matrix
+ *   cores); 1 rounds the step matrix to float32 and sums in float32 (float32
+ *   matrix cores).  X += P alpha always takes float32 sums (the precision
+ *   form's float32 vector updates), and so do P = Z T and Z += P beta in
+ *   CSC_CG_BLOCK_JACOBI (CSC_CG_BLOCK keeps float64 sums for them).  This
+ *   knob changes the rounding of the solve (not the
+ *   tolerance it meets); the Gram matrices (inner products) stay float64
+ *   either way.
  * csc_get_tuning returns the current value (-1 for an unknown key).
  */
 enum {

@@ -1158,7 +1158,8 @@ csc_status pre_finish(BlockState& st, hipStream_t s) {
   const BlockBufs& b = st.b;
   const int k = st.k;
   CSC_TRY(upload_d(b.S_t, st.T, s));
-  CSC_HIP(launch_block_mul(st.L, 0.f, nullptr, b.Z, b.S_t, k, st.sr, k, b.P, s));
+  CSC_HIP(launch_block_mul(st.L, 0.f, nullptr, b.Z, b.S_t, k, st.sr, k, b.P, s,
+                           /*f32=*/st.jacobi));
   return CSC_OK;
 }
 
@@ -1194,10 +1195,16 @@ void post_host_a(BlockState& st) {
 
 // X += P alpha, R -= Q alpha; the column norms of R, and the next search
 // block's Gram Q^T Z formed before the convergence check so that both come
-// back in one round trip (after the last iteration it goes unused).  X feeds
-// nothing back into the iteration (R is updated by its own recurrence), so
-// its update takes float32 sums on the float32 matrix cores, the precision
-// form's float32 vector update, whatever CSC_TUNE_BLOCK_PRODUCT says.
+// back in one round trip (after the last iteration it goes unused).
+// Precision of the right products: the residual recurrence R -= Q alpha
+// decides convergence and sums in float64 (CSC_TUNE_BLOCK_PRODUCT = 1:
+// float32, which was measured to cost the 1e5-node SBM a fourth iteration);
+// X += P alpha (X feeds nothing back) takes the precision form's float32
+// sums on the float32 matrix cores; so do P = Z T and Z += P beta (the search
+// directions) in the Jacobi-preconditioned form, whose 3-4 iterations were
+// measured unchanged by it (iteration counts, residuals, labels).  The plain
+// block CG keeps float64 sums for the directions: over its 13 or more
+// iterations float32 directions moved the iterate by ~1e-3.
 csc_status post_launch_b(BlockState& st, hipStream_t s) {
   const BlockBufs& b = st.b;
   const Layout& L = st.L;
@@ -1246,7 +1253,8 @@ csc_status post_finish(BlockState& st, hipStream_t s) {
   const BlockBufs& b = st.b;
   const int k = st.k, sr = st.sr;
   CSC_TRY(upload_d(b.S_b, st.C, s));
-  CSC_HIP(launch_block_mul(st.L, 1.f, st.jacobi ? b.Z : b.R, b.P, b.S_b, sr, k, k, b.Z, s));
+  CSC_HIP(launch_block_mul(st.L, 1.f, st.jacobi ? b.Z : b.R, b.P, b.S_b, sr, k, k, b.Z, s,
+                           /*f32=*/st.jacobi));
   return CSC_OK;
 }
 

@@ -79,9 +79,9 @@ def test_per_result_error_against_float64():
 
 @pytest.mark.parametrize("N,k,seed", [(1000, 10, 0), (20000, 40, 3)])
 def test_block_products_float32_against_float64(N, k, seed):
-    """The block CG's right products with float32 sums (CSC_TUNE_BLOCK_PRODUCT
-    = 1) against float64 sums (0; X += P alpha sums in float32 either way)
-    and against the oracle's solution at
+    """The block CG's residual update with float32 sums (CSC_TUNE_BLOCK_PRODUCT
+    = 1) against float64 sums (0; the other right products sum in float32
+    either way) and against the oracle's solution at
     tolerance 1e-12: both meet the tolerance on the recursive residual, the
     float64 true residual stays below 1e-4, X lies within 1e-3 of the tight
     solve and the labels agree.  Also reports what float32 row norms would
