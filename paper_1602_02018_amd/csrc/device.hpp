@@ -484,7 +484,8 @@ __device__ inline void col_dot_unit(const Layout& L, int chunks, int rows, const
   __shared__ double sh[4 * 64 * 4];
   const RowMap m = row_map(L.pw);
   const int panel = u / chunks, chunk = u - panel * chunks;
-  const int r0 = chunk * rows, r1 = min(L.n, r0 + rows);
+  const long long c0 = (long long)chunk * rows;  // chunks * rows < n + chunks
+  const int r0 = (int)min((long long)L.n, c0), r1 = (int)min((long long)L.n, c0 + rows);
   double cs[4] = {0.0, 0.0, 0.0, 0.0};
   if (m.lane_ok) {
     const size_t pb4 = (size_t)panel * L.panel_elems() / 4;
