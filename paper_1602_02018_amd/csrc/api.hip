@@ -1134,7 +1134,8 @@ csc_status block_init(BlockState& st, const Layout& L, int k, double tol, bool j
 csc_status pre_launch(BlockState& st, hipStream_t s) {
   const BlockBufs& b = st.b;
   const int k = st.k;
-  CSC_HIP(launch_gram(st.L, b.Z, b.Z, k, k, b.gpart, b.G, k, s));
+  // symmetric: the tiles on and below the diagonal, the rest mirrored
+  CSC_HIP(launch_gram(st.L, b.Z, b.Z, k, k, b.gpart, b.G, k, s, /*lower=*/true));
   st.G.resize((size_t)k * k);
   CSC_HIP(hipMemcpyAsync(st.G.data(), b.G, st.G.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   return CSC_OK;
@@ -1167,7 +1168,8 @@ csc_status pre_finish(BlockState& st, hipStream_t s) {
 csc_status post_launch_a(BlockState& st, hipStream_t s) {
   const BlockBufs& b = st.b;
   const int k = st.k, sr = st.sr;
-  CSC_HIP(launch_gram(st.L, b.P, b.Q, sr, sr, b.gpart, b.G, sr, s));
+  // the Cholesky factorisation reads W's lower triangle only
+  CSC_HIP(launch_gram(st.L, b.P, b.Q, sr, sr, b.gpart, b.G, sr, s, /*lower=*/true));
   CSC_HIP(launch_gram(st.L, b.P, b.R, sr, k, b.gpart, b.S_b, k, s));
   st.W.resize((size_t)sr * sr);
   st.C.resize((size_t)sr * k);
@@ -1193,6 +1195,49 @@ void post_host_a(BlockState& st) {
   for (auto& v : st.N) v = -v;
 }
 
+// X += P alpha feeds nothing back into the iteration: it runs on the side
+// stream, after the coefficient uploads, while the main stream goes on with
+// the residual and the host works out beta; the main stream waits for it
+// before P or S_a change again (post_finish) or X is read (block_join).
+// Without a side stream it runs in line.
+csc_status launch_x_update(BlockState& st, hipStream_t s) {
+  const BlockBufs& b = st.b;
+  BlockState::SideX& x = st.sx;
+  hipStream_t s2 = side_stream();
+  if (s2 && !x.go) {
+    if (hipEventCreateWithFlags(&x.go, hipEventDisableTiming) != hipSuccess) {
+      x.go = nullptr;
+    } else if (hipEventCreateWithFlags(&x.done, hipEventDisableTiming) != hipSuccess) {
+      (void)hipEventDestroy(x.go);
+      x.go = x.done = nullptr;
+    }
+  }
+  if (!s2 || !x.go) {
+    CSC_HIP(launch_block_mul(st.L, 1.f, b.X, b.P, b.S_a, st.sr, st.k, st.k, b.X, s, /*f32=*/true));
+    return CSC_OK;
+  }
+  CSC_HIP(hipEventRecord(x.go, s));
+  CSC_HIP(hipStreamWaitEvent(s2, x.go, 0));
+  x.main = s;
+  x.pending = true;
+  CSC_HIP(launch_block_mul(st.L, 1.f, b.X, b.P, b.S_a, st.sr, st.k, st.k, b.X, s2, /*f32=*/true));
+  CSC_HIP(hipEventRecord(x.done, s2));
+  return CSC_OK;
+}
+
+csc_status block_join(BlockState& st) {
+  if (!st.sx.pending) return CSC_OK;
+  st.sx.pending = false;
+  CSC_HIP(hipStreamWaitEvent(st.sx.main, st.sx.done, 0));
+  return CSC_OK;
+}
+
+BlockState::SideX::~SideX() {
+  if (pending && main && done) (void)hipStreamWaitEvent(main, done, 0);
+  if (go) (void)hipEventDestroy(go);
+  if (done) (void)hipEventDestroy(done);
+}
+
 // X += P alpha, R -= Q alpha; the column norms of R, and the next search
 // block's Gram Q^T Z formed before the convergence check so that both come
 // back in one round trip (after the last iteration it goes unused).
@@ -1211,7 +1256,7 @@ csc_status post_launch_b(BlockState& st, hipStream_t s) {
   const int k = st.k, sr = st.sr;
   CSC_TRY(upload_d(b.S_a, st.C, s));
   CSC_TRY(upload_d(b.S_na, st.N, s));
-  CSC_HIP(launch_block_mul(L, 1.f, b.X, b.P, b.S_a, sr, k, k, b.X, s, /*f32=*/true));
+  CSC_TRY(launch_x_update(st, s));
   CSC_HIP(launch_block_mul(L, 1.f, b.R, b.Q, b.S_na, sr, k, k, b.R, s));
   CSC_HIP(launch_col_dot(L, b.R, b.R, b.part, s));
   CSC_HIP(launch_reduce(b.part, col_dot_chunks(L), k, b.rn2, s));
@@ -1252,6 +1297,7 @@ void post_host_b(BlockState& st, int it, int max_iter) {
 csc_status post_finish(BlockState& st, hipStream_t s) {
   const BlockBufs& b = st.b;
   const int k = st.k, sr = st.sr;
+  CSC_TRY(block_join(st));
   CSC_TRY(upload_d(b.S_b, st.C, s));
   CSC_HIP(launch_block_mul(st.L, 1.f, st.jacobi ? b.Z : b.R, b.P, b.S_b, sr, k, k, b.Z, s,
                            /*f32=*/st.jacobi));
@@ -1455,6 +1501,7 @@ extern "C" csc_status csc_interpolate(const csc_graph* g_in, const int32_t* orde
       CSC_TRY(block_pass(*g, L, a.data(), p, pb, bs.sr, s));  // Q = M P
       CSC_TRY(block_post(bs, it, max_iter, s));
     }
+    CSC_TRY(block_join(bs));
     block_finish(bs, max_iter);
     CSC_HIP(launch_col_dot(L, Xi, Xi, part, s));
     CSC_HIP(launch_reduce(part, col_dot_chunks(L), k, colnorm2, s));

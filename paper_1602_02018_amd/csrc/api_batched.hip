@@ -919,6 +919,7 @@ extern "C" csc_status csc_interpolate_batched(
     std::vector<ReduceItem> h_cn(G);
     std::vector<LabelItem> h_lab(G);
     for (int g = 0; g < G; ++g) {
+      CSC_TRY(block_join(bs[g]));
       block_finish(bs[g], max_iter);
       const Buf& b = B[g];
       h_cd[g] = ColDotItem{b.L, col_dot_chunks(b.L), col_dot_rows(b.L), b.Xi, b.Xi, b.part,

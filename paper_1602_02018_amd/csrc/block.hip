@@ -63,16 +63,25 @@ constexpr int kGLD = kGT + 16;  // LDS row stride (floats): the 4 rows a wave re
                                 // fall on disjoint banks
 
 // part[chunk][r][c] = sum over the chunk's rows i of A[i, r] * B[i, c] for the
-// 128 x 128 output tile (ti, tj).  The workgroup stages 32 rows of both
+// 128 x 128 output tile (ti, tj); lower: only the tiles ti >= tj (a Gram whose
+// upper block triangle is taken from the lower one).  The workgroup stages 32 rows of both
 // column ranges in LDS (double-buffered, the next stage's global loads in
 // flight during the products); wave w takes the 64 x 64 quarter
 // (w / 2, w mod 2), four rows per matrix-core step.
 __global__ __launch_bounds__(256) void k_gram(Layout L, const float* A, const float* B, int ka,
                                               int kb, int rows_per_chunk, int tiles_b,
-                                              int rows_pad, double* part) {
+                                              int rows_pad, bool lower, double* part) {
   __shared__ float As[2][kGS][kGLD];
   __shared__ float Bs[2][kGS][kGLD];
-  const int ti = blockIdx.x / tiles_b, tj = blockIdx.x - ti * tiles_b;
+  int ti, tj;
+  if (lower) {  // the tiles on and below the diagonal only: (0,0), (1,0), (1,1), (2,0), ...
+    ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= (int)blockIdx.x) ++ti;
+    tj = (int)blockIdx.x - ti * (ti + 1) / 2;
+  } else {
+    ti = blockIdx.x / tiles_b;
+    tj = blockIdx.x - ti * tiles_b;
+  }
   const int chunk = blockIdx.y;
   const int r0 = chunk * rows_per_chunk;
   const int r1 = min(L.n, r0 + rows_per_chunk);
@@ -140,18 +149,21 @@ __global__ __launch_bounds__(256) void k_gram(Layout L, const float* A, const fl
 
 // G[i * ldg + j] = sum over chunks of the partial tiles: 16 entries per
 // workgroup, 16 threads per entry summing chunks s, s + 16, ... in order,
-// then the 16 slices in order.
+// then the 16 slices in order.  lower: an entry of a tile above the diagonal
+// is its mirror's sum (i and j swapped), bit for bit.
 __global__ __launch_bounds__(256) void k_gram_reduce(const double* part, int chunks, int rows_pad,
-                                                     int cols_pad, int ka, int kb, double* G,
-                                                     int ldg) {
+                                                     int cols_pad, int ka, int kb, bool lower,
+                                                     double* G, int ldg) {
   __shared__ double sh[16][17];
   const int slice = threadIdx.x >> 4, el = threadIdx.x & 15;
   const int e = blockIdx.x * 16 + el;
   const bool ok = e < ka * kb;
   const int i = ok ? e / kb : 0, j = ok ? e - i * kb : 0;
+  const bool mirror = lower && i / kGT < j / kGT;
+  const int pi = mirror ? j : i, pj = mirror ? i : j;
   double s = 0.0;
   if (ok)
-    for (int c = slice; c < chunks; c += 16) s += part[((size_t)c * rows_pad + i) * cols_pad + j];
+    for (int c = slice; c < chunks; c += 16) s += part[((size_t)c * rows_pad + pi) * cols_pad + pj];
   sh[slice][el] = s;
   __syncthreads();
   if (slice == 0 && ok) {
@@ -307,11 +319,13 @@ hipError_t launch_jacobi(const Layout& L, const float* R, const float* mask, flo
   return hipGetLastError();
 }
 
-GramPlan gram_plan(const Layout& L, int ka, int kb) {
+GramPlan gram_plan(const Layout& L, int ka, int kb, bool lower) {
   GramPlan g;
   g.tiles_a = (ka + kGT - 1) / kGT;
   g.tiles_b = (kb + kGT - 1) / kGT;
-  const int tiles = g.tiles_a * g.tiles_b;
+  g.lower = lower && ka == kb;
+  g.tiles = g.lower ? g.tiles_a * (g.tiles_a + 1) / 2 : g.tiles_a * g.tiles_b;
+  const int tiles = g.tiles;
   // about one workgroup per CU, chunks of at least 512 rows
   int chunks = std::max(1, 256 / tiles);
   chunks = std::min(chunks, std::max(1, L.n / 512));
@@ -325,23 +339,24 @@ GramPlan gram_plan(const Layout& L, int ka, int kb) {
 size_t gram_part_elems(const Layout& L, int kmax) {
   size_t m = 0;
   for (int ka = kGT; ka < kmax + kGT; ka += kGT)
-    for (int kb = kGT; kb < kmax + kGT; kb += kGT) {
-      const GramPlan g = gram_plan(L, std::min(ka, kmax), std::min(kb, kmax));
-      m = std::max(m, (size_t)g.chunks * g.tiles_a * kGT * g.tiles_b * kGT);
-    }
+    for (int kb = kGT; kb < kmax + kGT; kb += kGT)
+      for (const bool lower : {false, true}) {
+        const GramPlan g = gram_plan(L, std::min(ka, kmax), std::min(kb, kmax), lower);
+        m = std::max(m, (size_t)g.chunks * g.tiles_a * kGT * g.tiles_b * kGT);
+      }
   return m;
 }
 
 hipError_t launch_gram(const Layout& L, const float* A, const float* B, int ka, int kb,
-                       double* part, double* G, int ldg, hipStream_t s) {
-  const GramPlan g = gram_plan(L, ka, kb);
-  hipLaunchKernelGGL(k_gram, dim3((unsigned)(g.tiles_a * g.tiles_b), (unsigned)g.chunks), dim3(256),
-                     0, s, L, A, B, ka, kb, g.rows_per_chunk, g.tiles_b, g.tiles_a * kGT, part);
+                       double* part, double* G, int ldg, hipStream_t s, bool lower) {
+  const GramPlan g = gram_plan(L, ka, kb, lower);
+  hipLaunchKernelGGL(k_gram, dim3((unsigned)g.tiles, (unsigned)g.chunks), dim3(256), 0, s, L, A, B,
+                     ka, kb, g.rows_per_chunk, g.tiles_b, g.tiles_a * kGT, g.lower, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n = ka * kb;
   hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, s, part,
-                     g.chunks, g.tiles_a * kGT, g.tiles_b * kGT, ka, kb, G, ldg);
+                     g.chunks, g.tiles_a * kGT, g.tiles_b * kGT, ka, kb, g.lower, G, ldg);
   return hipGetLastError();
 }
 

@@ -26,57 +26,184 @@ __attribute__((always_inline)) inline void sub_scaled(double* __restrict__ y,
   for (int j = 0; j < n; ++j) y[j] -= a * x[j];
 }
 
+// Forward substitution, one register tile of RB rows x CB columns: rows
+// i0 .. i0+RB-1, columns c0 .. c0+CB-1 of C (leading dimension ldc) become
+//   (C[i] - sum_{t0 <= t < i} L[i][t] C[t]) / L[i][i],
+// the subtractions taken one at a time in increasing t.  Rows t < i0 are
+// final already; their products are shared by the tile's rows, which is what
+// the tile saves (one load of C[t] per RB rows).
+template <int RB, int CB>
+__attribute__((always_inline)) inline void forward_tile(const double* __restrict__ L, int ldl,
+                                                        double* __restrict__ c, int ldc, int i0,
+                                                        int c0, int t0) {
+  double acc[RB][CB];
+  for (int r = 0; r < RB; ++r)
+    for (int j = 0; j < CB; ++j) acc[r][j] = c[(size_t)(i0 + r) * ldc + c0 + j];
+  for (int t = t0; t < i0; ++t) {
+    const double* x = c + (size_t)t * ldc + c0;
+    for (int r = 0; r < RB; ++r) {
+      const double a = L[(size_t)(i0 + r) * ldl + t];
+      for (int j = 0; j < CB; ++j) acc[r][j] -= a * x[j];
+    }
+  }
+  for (int r = 0; r < RB; ++r) {
+    for (int t = 0; t < r; ++t) {
+      const double a = L[(size_t)(i0 + r) * ldl + i0 + t];
+      for (int j = 0; j < CB; ++j) acc[r][j] -= a * acc[t][j];
+    }
+    const double l = L[(size_t)(i0 + r) * ldl + i0 + r];
+    for (int j = 0; j < CB; ++j) acc[r][j] /= l;
+  }
+  for (int r = 0; r < RB; ++r)
+    for (int j = 0; j < CB; ++j) c[(size_t)(i0 + r) * ldc + c0 + j] = acc[r][j];
+}
+
+constexpr int kRB = 6, kCB = 16;  // forward tile: 12 of the 32 AVX-512 registers accumulate
+
+// C (s x w, leading dimension ldc) <- L^{-1} C for the lower-triangular L (s x s, leading
+// dimension ldl): every element (i, c) is C[i][c] minus L[i][t] C[t][c] for t = 0, 1, ..., i-1
+// in turn, then divided by L[i][i].  unit_lower: C starts as the identity (s = w), so column
+// block c0 is zero above row c0 and the rows t < c0 add nothing to it; the block then starts
+// at row c0 (the zero entries it does subtract leave every value as it was: C holds no
+// negative zeros).
+CSC_DENSE_CLONES void forward_cols(const double* L, int s, int ldl, double* c, int ldc, int w,
+                                   bool unit_lower) {
+  const int wb = w / kCB * kCB;
+  for (int c0 = 0; c0 < wb; c0 += kCB) {
+    const int i_begin = unit_lower ? std::min(c0, s) : 0;
+    int i0 = i_begin;
+    for (; i0 + kRB <= s; i0 += kRB) forward_tile<kRB, kCB>(L, ldl, c, ldc, i0, c0, i_begin);
+    for (; i0 < s; ++i0) forward_tile<1, kCB>(L, ldl, c, ldc, i0, c0, i_begin);
+  }
+  if (wb < w)
+    for (int i = 0; i < s; ++i) {
+      double* ci = c + (size_t)i * ldc + wb;
+      for (int t = 0; t < i; ++t)
+        sub_scaled(ci, c + (size_t)t * ldc + wb, L[(size_t)i * ldl + t], w - wb);
+      const double l = L[(size_t)i * ldl + i];
+      for (int j = 0; j < w - wb; ++j) ci[j] /= l;
+    }
+}
+
+constexpr int kGB = 32;  // orth_transform's column block (doubles)
+
+// out[0..kGB) = y0[0..kGB) - sum_t a[t] x[t * ldx + 0..kGB), subtracted in increasing t
+__attribute__((always_inline)) inline void block_gemv(double* out, const double* y0,
+                                                      const double* __restrict__ x, size_t ldx,
+                                                      const double* __restrict__ a, int nt) {
+  double acc[kGB];
+  for (int j = 0; j < kGB; ++j) acc[j] = y0[j];
+  for (int t = 0; t < nt; ++t) {
+    const double s = a[t];
+    const double* xt = x + (size_t)t * ldx;
+    for (int j = 0; j < kGB; ++j) acc[j] -= s * xt[j];
+  }
+  for (int j = 0; j < kGB; ++j) out[j] = acc[j];
+}
+
 // Rank-revealing orthonormalisation for the block CG: with G = Z^T Z (k x k,
 // row-major), returns s and T (k x s, row-major, leading dimension k) such
 // that P = Z T has orthonormal columns spanning the columns of Z.  Columns are
 // first scaled to unit norm (so a small residual column is not mistaken for
-// a dependent one); pivoted Cholesky of the scaled Gram (outer-product form:
-// the trailing matrix is updated after each pivot) stops when the largest
-// remaining pivot falls to rtol.
+// a dependent one); pivoted Cholesky of the scaled Gram A stops when the
+// largest remaining pivot falls to rtol.  Each step pivots on the largest
+// remaining diagonal entry (the lowest index among equals); a column whose
+// remaining diagonal entry is negative is dependent and leaves the search.
+// The factor is formed column by column (left-looking): step r needs only
+// the pivot's column of the updated A, i.e. A[i][j] minus l_t[i] l_t[j] for
+// the earlier factor columns t = 0 .. r-1 in turn, over the columns still in
+// the search, which sit compacted in positions 0 .. m-1 (dependent ones are
+// squeezed out once 16 have gathered).
 CSC_DENSE_CLONES int orth_transform(const std::vector<double>& G, int k, double rtol,
                                     std::vector<double>& T) {
-  std::vector<double> d(k), A((size_t)k * k), Lc((size_t)k * k, 0.0), diag(k);
-  for (int i = 0; i < k; ++i) d[i] = G[(size_t)i * k + i] > 0.0 ? std::sqrt(G[(size_t)i * k + i]) : 0.0;
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j)
-      A[(size_t)i * k + j] = (d[i] > 0.0 && d[j] > 0.0) ? G[(size_t)i * k + j] / (d[i] * d[j]) : 0.0;
-  for (int i = 0; i < k; ++i) diag[i] = d[i] > 0.0 ? A[(size_t)i * k + i] : -1.0;
+  const size_t ld = (size_t)(k + kGB - 1) / kGB * kGB;
+  std::vector<double> d(k), diag(k);
+  std::vector<int> perm, pos(k, -1);
+  for (int i = 0; i < k; ++i) {
+    const double g = G[(size_t)i * k + i];
+    d[i] = g > 0.0 ? std::sqrt(g) : 0.0;
+    diag[i] = d[i] > 0.0 ? g / (d[i] * d[i]) : -1.0;
+    if (diag[i] >= 0.0) {
+      pos[i] = (int)perm.size();
+      perm.push_back(i);
+    }
+  }
+  int m = (int)perm.size(), ndead = 0;
+  // Lp[t][p]: factor column t at position p; Ls: the factor's rows in pivot order
+  std::vector<double> Lp((size_t)k * ld, 0.0), Ls((size_t)k * k, 0.0), a(k), col0(ld, 0.0),
+      col(ld);
+  // At[j][i] = A[i][j] = G[i][j] / (d[i] d[j]) (read for columns i, j both in the search)
+  std::vector<double> At((size_t)k * k);
+  for (int i0 = 0; i0 < k; i0 += 16)
+    for (int j0 = 0; j0 < k; j0 += 16)
+      for (int i = i0; i < std::min(k, i0 + 16); ++i)
+        for (int j = j0; j < std::min(k, j0 + 16); ++j)
+          At[(size_t)j * k + i] = G[(size_t)i * k + j] / (d[i] * d[j]);
   std::vector<int> piv;
   for (int r = 0; r < k; ++r) {
+    // pivot: the lowest index holding the largest diagonal entry (NaN entries never win;
+    // nothing beats a NaN at index 0, which ends the factorisation)
     int j = 0;
-    for (int i = 1; i < k; ++i)
-      if (diag[i] > diag[j]) j = i;
+    if (!std::isnan(diag[0])) {
+      double mx[8];
+      for (int l = 0; l < 8; ++l) mx[l] = diag[0];
+      int i = 1;
+      for (; i + 8 <= k; i += 8)
+        for (int l = 0; l < 8; ++l) mx[l] = diag[i + l] > mx[l] ? diag[i + l] : mx[l];
+      for (; i < k; ++i) mx[0] = diag[i] > mx[0] ? diag[i] : mx[0];
+      double best = mx[0];
+      for (int l = 1; l < 8; ++l) best = mx[l] > best ? mx[l] : best;
+      while (!(diag[j] == best)) ++j;
+    }
     if (!(diag[j] > rtol)) break;
     const double ljj = std::sqrt(diag[j]);
-    // column r of the factor (row-indexed by the original column index), in Lc[r][.]
-    double* lr = Lc.data() + (size_t)r * k;
-    for (int i = 0; i < k; ++i) {
-      const bool live = diag[i] >= 0.0 && i != j;
-      lr[i] = i == j ? ljj : (live ? A[(size_t)i * k + j] / ljj : 0.0);
-    }
+    const int pj = pos[j];
+    for (int t = 0; t < r; ++t) a[t] = Lp[(size_t)t * ld + pj];
+    std::copy(a.begin(), a.begin() + r, Ls.begin() + (size_t)r * k);
+    Ls[(size_t)r * k + r] = ljj;
+    const double* atj = At.data() + (size_t)j * k;
+    for (int p = 0; p < m; ++p) col0[p] = atj[perm[p]];
+    for (int p0 = 0; p0 < m; p0 += kGB)
+      block_gemv(col.data() + p0, col0.data() + p0, Lp.data() + p0, ld, a.data(), r);
+    double* lr = Lp.data() + (size_t)r * ld;
     diag[j] = -1.0;
-    for (int i = 0; i < k; ++i) {
-      if (diag[i] < 0.0) continue;  // pivoted already, or a zero column
-      sub_scaled(A.data() + (size_t)i * k, lr, lr[i], k);
-      diag[i] -= lr[i] * lr[i];
+    for (int p = 0; p < m; ++p) {
+      const int i = perm[p];
+      if (!(diag[i] >= 0.0)) {  // the pivot, or out of the search already
+        lr[p] = p == pj ? ljj : 0.0;
+        continue;
+      }
+      lr[p] = col[p] / ljj;
+      diag[i] -= lr[p] * lr[p];
+      if (!(diag[i] >= 0.0)) ++ndead;
     }
     piv.push_back(j);
+    if (++ndead >= 16) {  // squeeze the columns out of the search out of the positions
+      int q = 0;
+      for (int p = 0; p < m; ++p) {
+        const int i = perm[p];
+        if (!(diag[i] >= 0.0)) {
+          pos[i] = -1;
+          continue;
+        }
+        if (q != p)
+          for (int t = 0; t <= r; ++t) Lp[(size_t)t * ld + q] = Lp[(size_t)t * ld + p];
+        perm[q] = i;
+        pos[i] = q++;
+      }
+      m = q;
+      ndead = 0;
+    }
   }
   const int s = (int)piv.size();
-  // Ls[r][c] = Lc[c][piv[r]] (lower triangular); X = inv(Ls) row by row;
-  // T[piv[r]][c] = X[c][r] / d[piv[r]]
-  std::vector<double> X((size_t)s * s, 0.0);
-  for (int r = 0; r < s; ++r) {
-    double* xr = X.data() + (size_t)r * s;
-    xr[r] = 1.0;
-    for (int t = 0; t < r; ++t)
-      sub_scaled(xr, X.data() + (size_t)t * s, Lc[(size_t)t * k + piv[r]], t + 1);
-    const double l = Lc[(size_t)r * k + piv[r]];
-    for (int c = 0; c <= r; ++c) xr[c] /= l;
-  }
+  // X = Ls^{-1} (row r of Ls: Ls[r][t] = l_t[piv[r]]); T[piv[r]][c] = X[c][r] / d[piv[r]]
+  const int lx = std::max(1, s);
+  std::vector<double> X((size_t)s * lx, 0.0);
+  for (int r = 0; r < s; ++r) X[(size_t)r * lx + r] = 1.0;
+  forward_cols(Ls.data(), s, k, X.data(), lx, s, /*unit_lower=*/true);
   T.assign((size_t)k * k, 0.0);
   for (int r = 0; r < s; ++r)
-    for (int c = r; c < s; ++c) T[(size_t)piv[r] * k + c] = X[(size_t)c * s + r] / d[piv[r]];
+    for (int c = r; c < s; ++c) T[(size_t)piv[r] * k + c] = X[(size_t)c * lx + r] / d[piv[r]];
   return s;
 }
 
@@ -102,13 +229,8 @@ CSC_DENSE_CLONES bool cholesky(std::vector<double>& W, int s, int ldw) {
 CSC_DENSE_CLONES void solve_cols(const double* Lw, int s, int ldw, double* c, int k, int j0,
                                   int j1, double scale) {
   const int w = j1 - j0;
-  for (int i = 0; i < s; ++i) {  // L Y = C, row by row
-    double* ci = c + (size_t)i * k + j0;
-    for (int t = 0; t < i; ++t) sub_scaled(ci, c + (size_t)t * k + j0, Lw[(size_t)i * ldw + t], w);
-    const double l = Lw[(size_t)i * ldw + i];
-    for (int j = 0; j < w; ++j) ci[j] /= l;
-  }
-  for (int i = s - 1; i >= 0; --i) {  // L^T X = Y
+  forward_cols(Lw, s, ldw, c + j0, k, w, false);  // L Y = C
+  for (int i = s - 1; i >= 0; --i) {              // L^T X = Y, row by row
     double* ci = c + (size_t)i * k + j0;
     for (int t = i + 1; t < s; ++t) sub_scaled(ci, c + (size_t)t * k + j0, Lw[(size_t)t * ldw + i], w);
     const double l = Lw[(size_t)i * ldw + i];

@@ -77,6 +77,18 @@ struct BlockState {
   std::vector<char> done;
   std::vector<int> iters;
   std::vector<double> bn2, relres, G, T, W, C, N, rn2;
+  // X += P alpha on the side stream (post_launch_b): `main` waits for `done`
+  // before P or S_a change again (post_finish), in block_join, and at the
+  // latest when the state goes away
+  struct SideX {
+    hipEvent_t go = nullptr, done = nullptr;
+    hipStream_t main = nullptr;
+    bool pending = false;
+    SideX() = default;
+    SideX(const SideX&) = delete;
+    SideX& operator=(const SideX&) = delete;
+    ~SideX();
+  } sx;
 };
 csc_status block_init(BlockState& st, const Layout& L, int k, double tol, bool jacobi, float gamma,
                       const BlockBufs& b, const double* bnorm2_dev, hipStream_t s);
@@ -94,6 +106,8 @@ csc_status post_launch_b(BlockState& st, hipStream_t s);
 void post_host_b(BlockState& st, int it, int max_iter);
 csc_status post_finish(BlockState& st, hipStream_t s);
 void block_finish(BlockState& st, int max_iter);
+// the stream waits for an X update still running on the side stream
+csc_status block_join(BlockState& st);
 
 // Workspace of permuted_graph, and the graph g permuted to `order` (row r =
 // node order[r], neighbours relabelled and kept in CSR order) with the sampled

@@ -245,15 +245,19 @@ hipError_t launch_labels(const Layout& L, const float* X, const double* colnorm2
 // Block products (block.hip).  Gram G = A^T B of the first ka and kb columns
 // of two N-row panel-major blocks (float64 sums in a fixed order, row-major
 // with leading dimension ldg); part holds gram_part_elems(L, max(ka, kb))
-// doubles.  Block product Out = c0 In0 + In1[:, :kin] S with S float64
-// kin x kout (leading dimension lds), every stored column written.
+// doubles.  lower (ka == kb): only the 128 x 128 tiles on and below the
+// diagonal are summed, and an entry above them is set to its mirror, which
+// a Gram that is symmetric (A = B) or whose upper triangle is never read
+// does not notice.  Block product Out = c0 In0 + In1[:, :kin] S with S
+// float64 kin x kout (leading dimension lds), every stored column written.
 struct GramPlan {
-  int tiles_a = 0, tiles_b = 0, chunks = 0, rows_per_chunk = 0;
+  int tiles_a = 0, tiles_b = 0, tiles = 0, chunks = 0, rows_per_chunk = 0;
+  bool lower = false;
 };
-GramPlan gram_plan(const Layout& L, int ka, int kb);
+GramPlan gram_plan(const Layout& L, int ka, int kb, bool lower = false);
 size_t gram_part_elems(const Layout& L, int kmax);
 hipError_t launch_gram(const Layout& L, const float* A, const float* B, int ka, int kb,
-                       double* part, double* G, int ldg, hipStream_t s);
+                       double* part, double* G, int ldg, hipStream_t s, bool lower = false);
 // Z = R / (mask_i + gamma) row by row (Jacobi preconditioner of the interpolation).
 hipError_t launch_jacobi(const Layout& L, const float* R, const float* mask, float gamma, float* Z,
                          hipStream_t s);

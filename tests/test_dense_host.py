@@ -116,3 +116,72 @@ def test_cholesky_rejects_indefinite(dense):
     W = np.array([[1.0, 2.0], [2.0, 1.0]])
     Cm = np.ones((2, 1))
     assert dense.dense_solve(_p(W), 2, _p(Cm), 1, 1.0, 1) == 0
+
+
+def _plain(lib):
+    pd = C.POINTER(C.c_double)
+    lib.dense_orth_plain.argtypes = [pd, C.c_int, C.c_double, pd]
+    lib.dense_orth_plain.restype = C.c_int
+    lib.dense_subst_plain.argtypes = [pd, C.c_int, pd, C.c_int, C.c_double]
+    lib.dense_subst_plain.restype = None
+    lib.dense_factor.argtypes = [pd, C.c_int]
+    lib.dense_factor.restype = C.c_int
+    return lib
+
+
+def _gram(rng, k, kind):
+    m = k + 40
+    if kind == "full":
+        Z = rng.normal(size=(m, k)) * rng.uniform(1e-3, 10, size=k)
+    elif kind == "low-rank":  # rank k/3: the remaining diagonal entries go to rounding noise
+        Z = rng.normal(size=(m, k // 3 + 1)) @ rng.normal(size=(k // 3 + 1, k))
+    elif kind == "zero-columns":
+        Z = rng.normal(size=(m, k))
+        Z[:, ::3] = 0.0
+    elif kind == "near-duplicates":
+        Z = rng.normal(size=(m, k))
+        Z[:, 1::2] = Z[:, 0:k - 1:2][:, : Z[:, 1::2].shape[1]] + 1e-9 * rng.normal(size=(m, k // 2))
+    else:  # exact combinations of earlier columns among independent ones: their remaining
+        # diagonal entries fall to rounding noise, some below zero, while others are still O(1)
+        Z = rng.normal(size=(m, k))
+        for c in range(2, k, 3):
+            Z[:, c] = Z[:, c - 2] - 0.5 * Z[:, c - 1]
+    return np.ascontiguousarray(Z.T @ Z)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 16, 17, 31, 33, 64, 100, 129, 250])
+@pytest.mark.parametrize("kind", ["full", "low-rank", "zero-columns", "near-duplicates",
+                                  "combinations"])
+def test_orth_equals_outer_product_form_bit_for_bit(dense, k, kind):
+    """The library factors column by column over the columns still in the
+    search (compacted positions, dependent columns squeezed out) and inverts
+    with register tiles; every entry must still take the textbook outer-
+    product form's operations in its order: T and s equal bit for bit."""
+    lib = _plain(dense)
+    G = _gram(np.random.default_rng(k * 7 + len(kind)), k, kind)
+    T1, T2 = np.zeros((k, k)), np.zeros((k, k))
+    s1 = lib.dense_orth(_p(G), k, 1e-10, _p(T1))
+    s2 = lib.dense_orth_plain(_p(G), k, 1e-10, _p(T2))
+    assert s1 == s2
+    assert np.array_equal(T1, T2)
+    if kind == "full":
+        assert s1 == k
+
+
+@pytest.mark.parametrize("s,k", [(1, 1), (5, 3), (6, 16), (7, 17), (13, 32), (100, 100),
+                                 (101, 250), (250, 7)])
+def test_solve_equals_plain_substitution_bit_for_bit(dense, s, k):
+    """Forward substitution runs in register tiles of several rows sharing
+    the loads of finished rows; each element's subtractions keep their
+    order, so the solve equals row-by-row substitution bit for bit."""
+    lib = _plain(dense)
+    rng = np.random.default_rng(s * 13 + k)
+    M = rng.normal(size=(s, s))
+    W = np.ascontiguousarray(M @ M.T + s * np.eye(s))
+    L = W.copy()
+    assert lib.dense_factor(_p(L), s) == 1
+    Cm = rng.normal(size=(s, k))
+    lib_out, plain_out = Cm.copy(), Cm.copy()
+    assert lib.dense_solve(_p(W), s, _p(lib_out), k, -1.0, 1) == 1
+    lib.dense_subst_plain(_p(L), s, _p(plain_out), k, -1.0)
+    assert np.array_equal(lib_out, plain_out)
