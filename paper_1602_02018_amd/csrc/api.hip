@@ -1196,10 +1196,11 @@ void post_host_a(BlockState& st) {
 }
 
 // X += P alpha feeds nothing back into the iteration: it runs on the side
-// stream, after the coefficient uploads, while the main stream goes on with
-// the residual and the host works out beta; the main stream waits for it
-// before P or S_a change again (post_finish) or X is read (block_join).
-// Without a side stream it runs in line.
+// stream once the main stream has brought back what the host needs (launched
+// last in post_launch_b), so that it fills the GPU while the host works out
+// beta; the main stream waits for it before P or S_a change again
+// (post_finish) or X is read (block_join).  Without a side stream it runs in
+// line.
 csc_status launch_x_update(BlockState& st, hipStream_t s) {
   const BlockBufs& b = st.b;
   BlockState::SideX& x = st.sx;
@@ -1256,7 +1257,6 @@ csc_status post_launch_b(BlockState& st, hipStream_t s) {
   const int k = st.k, sr = st.sr;
   CSC_TRY(upload_d(b.S_a, st.C, s));
   CSC_TRY(upload_d(b.S_na, st.N, s));
-  CSC_TRY(launch_x_update(st, s));
   CSC_HIP(launch_block_mul(L, 1.f, b.R, b.Q, b.S_na, sr, k, k, b.R, s));
   CSC_HIP(launch_col_dot(L, b.R, b.R, b.part, s));
   CSC_HIP(launch_reduce(b.part, col_dot_chunks(L), k, b.rn2, s));
@@ -1267,6 +1267,7 @@ csc_status post_launch_b(BlockState& st, hipStream_t s) {
   CSC_HIP(hipMemcpyAsync(st.rn2.data(), b.rn2, (size_t)k * sizeof(double), hipMemcpyDeviceToHost,
                          s));
   CSC_HIP(hipMemcpyAsync(st.C.data(), b.G, st.C.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  CSC_TRY(launch_x_update(st, s));  // after the copies: it runs while the host works
   return CSC_OK;
 }
 

@@ -58,31 +58,37 @@ __attribute__((always_inline)) inline void forward_tile(const double* __restrict
     for (int j = 0; j < CB; ++j) c[(size_t)(i0 + r) * ldc + c0 + j] = acc[r][j];
 }
 
-constexpr int kRB = 6, kCB = 16;  // forward tile: 12 of the 32 AVX-512 registers accumulate
+constexpr int kRB = 6;  // forward tile rows: 6 x 16 columns keep 12 of the 32 AVX-512 registers
+
+// Forward substitution of columns c0 .. c0+CB-1 over every row, in tiles of kRB rows.
+template <int CB>
+__attribute__((always_inline)) inline void forward_block(const double* L, int s, int ldl, double* c,
+                                                         int ldc, int c0, bool unit_lower) {
+  const int i_begin = unit_lower ? std::min(c0, s) : 0;
+  int i0 = i_begin;
+  for (; i0 + kRB <= s; i0 += kRB) forward_tile<kRB, CB>(L, ldl, c, ldc, i0, c0, i_begin);
+  for (; i0 < s; ++i0) forward_tile<1, CB>(L, ldl, c, ldc, i0, c0, i_begin);
+}
 
 // C (s x w, leading dimension ldc) <- L^{-1} C for the lower-triangular L (s x s, leading
 // dimension ldl): every element (i, c) is C[i][c] minus L[i][t] C[t][c] for t = 0, 1, ..., i-1
-// in turn, then divided by L[i][i].  unit_lower: C starts as the identity (s = w), so column
-// block c0 is zero above row c0 and the rows t < c0 add nothing to it; the block then starts
-// at row c0 (the zero entries it does subtract leave every value as it was: C holds no
-// negative zeros).
+// in turn, then divided by L[i][i].  Columns go in blocks of 16, then 8, 4 and 1.
+// unit_lower: C starts as the identity (s = w), so a column block starting at c0 is zero above
+// row c0 and the rows t < c0 add nothing to it; the block then starts at row c0 (the zero
+// entries it does subtract leave every value as it was: C holds no negative zeros).
 CSC_DENSE_CLONES void forward_cols(const double* L, int s, int ldl, double* c, int ldc, int w,
                                    bool unit_lower) {
-  const int wb = w / kCB * kCB;
-  for (int c0 = 0; c0 < wb; c0 += kCB) {
-    const int i_begin = unit_lower ? std::min(c0, s) : 0;
-    int i0 = i_begin;
-    for (; i0 + kRB <= s; i0 += kRB) forward_tile<kRB, kCB>(L, ldl, c, ldc, i0, c0, i_begin);
-    for (; i0 < s; ++i0) forward_tile<1, kCB>(L, ldl, c, ldc, i0, c0, i_begin);
+  int c0 = 0;
+  for (; c0 + 16 <= w; c0 += 16) forward_block<16>(L, s, ldl, c, ldc, c0, unit_lower);
+  if (c0 + 8 <= w) {
+    forward_block<8>(L, s, ldl, c, ldc, c0, unit_lower);
+    c0 += 8;
   }
-  if (wb < w)
-    for (int i = 0; i < s; ++i) {
-      double* ci = c + (size_t)i * ldc + wb;
-      for (int t = 0; t < i; ++t)
-        sub_scaled(ci, c + (size_t)t * ldc + wb, L[(size_t)i * ldl + t], w - wb);
-      const double l = L[(size_t)i * ldl + i];
-      for (int j = 0; j < w - wb; ++j) ci[j] /= l;
-    }
+  if (c0 + 4 <= w) {
+    forward_block<4>(L, s, ldl, c, ldc, c0, unit_lower);
+    c0 += 4;
+  }
+  for (; c0 < w; ++c0) forward_block<1>(L, s, ldl, c, ldc, c0, unit_lower);
 }
 
 constexpr int kGB = 32;  // orth_transform's column block (doubles)
@@ -118,7 +124,7 @@ CSC_DENSE_CLONES int orth_transform(const std::vector<double>& G, int k, double 
                                     std::vector<double>& T) {
   const size_t ld = (size_t)(k + kGB - 1) / kGB * kGB;
   std::vector<double> d(k), diag(k);
-  std::vector<int> perm, pos(k, -1);
+  std::vector<int> perm, pos(k, -1), keep(k);
   for (int i = 0; i < k; ++i) {
     const double g = G[(size_t)i * k + i];
     d[i] = g > 0.0 ? std::sqrt(g) : 0.0;
@@ -132,13 +138,19 @@ CSC_DENSE_CLONES int orth_transform(const std::vector<double>& G, int k, double 
   // Lp[t][p]: factor column t at position p; Ls: the factor's rows in pivot order
   std::vector<double> Lp((size_t)k * ld, 0.0), Ls((size_t)k * k, 0.0), a(k), col0(ld, 0.0),
       col(ld);
-  // At[j][i] = A[i][j] = G[i][j] / (d[i] d[j]) (read for columns i, j both in the search)
-  std::vector<double> At((size_t)k * k);
+  // At[j][i] = A[i][j] = G[i][j] / (d[i] d[j]) (read for columns i, j both in the search):
+  // the scaled rows, then their transpose in 16 x 16 blocks
+  std::vector<double> A((size_t)k * k), At((size_t)k * k);
+  for (int i = 0; i < k; ++i) {
+    const double* g = G.data() + (size_t)i * k;
+    double* a = A.data() + (size_t)i * k;
+    const double di = d[i];
+    for (int j = 0; j < k; ++j) a[j] = g[j] / (di * d[j]);
+  }
   for (int i0 = 0; i0 < k; i0 += 16)
     for (int j0 = 0; j0 < k; j0 += 16)
-      for (int i = i0; i < std::min(k, i0 + 16); ++i)
-        for (int j = j0; j < std::min(k, j0 + 16); ++j)
-          At[(size_t)j * k + i] = G[(size_t)i * k + j] / (d[i] * d[j]);
+      for (int j = j0; j < std::min(k, j0 + 16); ++j)
+        for (int i = i0; i < std::min(k, i0 + 16); ++i) At[(size_t)j * k + i] = A[(size_t)i * k + j];
   std::vector<int> piv;
   for (int r = 0; r < k; ++r) {
     // pivot: the lowest index holding the largest diagonal entry (NaN entries never win;
@@ -186,10 +198,13 @@ CSC_DENSE_CLONES int orth_transform(const std::vector<double>& G, int k, double 
           pos[i] = -1;
           continue;
         }
-        if (q != p)
-          for (int t = 0; t <= r; ++t) Lp[(size_t)t * ld + q] = Lp[(size_t)t * ld + p];
+        keep[q] = p;
         perm[q] = i;
         pos[i] = q++;
+      }
+      for (int t = 0; t <= r; ++t) {  // keep[q] >= q, increasing: in place, row by row
+        double* row = Lp.data() + (size_t)t * ld;
+        for (int u = 0; u < q; ++u) row[u] = row[keep[u]];
       }
       m = q;
       ndead = 0;
