@@ -113,44 +113,49 @@ __global__ void k_iota(int N, int* out) {
 
 // Nearest usable centroid of every row of F (squared Euclidean distance,
 // coordinates summed in order, ties to the lowest index).  A thread keeps its
-// row in registers; centroids are staged through LDS in chunks.
+// row in registers; centroids are staged through LDS in chunks, each row
+// padded with zeros to DMAX coordinates like the thread's own, so that the
+// distance loop runs the same DMAX steps for every d (a padded step adds
+// (0 - 0)^2 = 0 to a sum of squares, which leaves it unchanged) and its LDS
+// reads need no guard and can all be in flight at once.
 template <int DMAX>
 __global__ __launch_bounds__(kBlk) void k_nearest_centroid(int N, int d, const float* F,
                                                            size_t ldf, const float* C,
                                                            const int* usable, int k,
                                                            int* labels) {
-  // centroids and their usable flags staged in LDS, kc at a time; two
-  // centroids per pass over the node's coordinates (independent sums)
-  __shared__ float cs[kLdsFloats];
+  static_assert(DMAX % 4 == 0 && DMAX <= kLdsFloats, "padded centroid rows");
+  __shared__ __align__(16) float cs[kLdsFloats];
   __shared__ int use[kUseMax];
   const int i = blockIdx.x * kBlk + threadIdx.x;
   const bool row = i < N;
   float f[DMAX];
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) f[j] = (row && j < d) ? F[(size_t)i * ldf + j] : 0.f;
-  const int kc = min(kUseMax, kLdsFloats / d);
+  constexpr int kc = kUseMax < kLdsFloats / DMAX ? kUseMax : kLdsFloats / DMAX;
   float best = 0.f;
   int arg = 0;
   bool found = false;
   for (int c0 = 0; c0 < k; c0 += kc) {
     const int nc = min(kc, k - c0);
     __syncthreads();
-    for (int e = threadIdx.x; e < nc * d; e += kBlk) cs[e] = C[(size_t)c0 * d + e];
+    for (int e = threadIdx.x; e < nc * DMAX; e += kBlk) {
+      const int c = e / DMAX, j = e - c * DMAX;
+      cs[e] = j < d ? C[(size_t)(c0 + c) * d + j] : 0.f;
+    }
     for (int e = threadIdx.x; e < nc; e += kBlk) use[e] = usable[c0 + e];
     __syncthreads();
     if (row) {
       for (int c = 0; c < nc; c += 2) {
         const bool two = c + 1 < nc;
-        const float* ca = cs + c * d;
-        const float* cb = cs + (two ? c + 1 : c) * d;
+        const float* ca = cs + c * DMAX;
+        const float* cb = cs + (two ? c + 1 : c) * DMAX;
         float da = 0.f, db = 0.f;
 #pragma unroll
-        for (int j = 0; j < DMAX; ++j)
-          if (j < d) {
-            const float ta = f[j] - ca[j], tb = f[j] - cb[j];
-            da = fmaf(ta, ta, da);
-            db = fmaf(tb, tb, db);
-          }
+        for (int j = 0; j < DMAX; ++j) {
+          const float ta = f[j] - ca[j], tb = f[j] - cb[j];
+          da = fmaf(ta, ta, da);
+          db = fmaf(tb, tb, db);
+        }
         if (use[c] && (!found || da < best)) {
           best = da;
           arg = c0 + c;
@@ -365,11 +370,21 @@ hipError_t launch_gather_rows(int n, int d, const float* F, size_t ldf, const in
 hipError_t launch_nearest_centroid(int N, int d, const float* F, size_t ldf, const float* C,
                                    const int* usable, int k, int* labels, hipStream_t s) {
   const dim3 grid((unsigned)((N + kBlk - 1) / kBlk)), block(kBlk);
+  // the padded width: the smallest instance that holds d (the padding is work)
   if (d <= 32)
     hipLaunchKernelGGL(k_nearest_centroid<32>, grid, block, 0, s, N, d, F, ldf, C, usable, k,
                        labels);
+  else if (d <= 48)
+    hipLaunchKernelGGL(k_nearest_centroid<48>, grid, block, 0, s, N, d, F, ldf, C, usable, k,
+                       labels);
+  else if (d <= 56)
+    hipLaunchKernelGGL(k_nearest_centroid<56>, grid, block, 0, s, N, d, F, ldf, C, usable, k,
+                       labels);
   else if (d <= 64)
     hipLaunchKernelGGL(k_nearest_centroid<64>, grid, block, 0, s, N, d, F, ldf, C, usable, k,
+                       labels);
+  else if (d <= 96)
+    hipLaunchKernelGGL(k_nearest_centroid<96>, grid, block, 0, s, N, d, F, ldf, C, usable, k,
                        labels);
   else
     hipLaunchKernelGGL(k_nearest_centroid<128>, grid, block, 0, s, N, d, F, ldf, C, usable, k,
