@@ -211,34 +211,59 @@ __global__ void k_pack(Layout L, const float* X, int ld, float* out) {
   }
 }
 
-__global__ void k_unpack(Layout L, const float* in, float* Y, int ld, int normalize) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= L.n) return;
-  const size_t pe = L.panel_elems();
-  double inv = 1.0;
+// Rows of an n_rows x w block written row-major to Y (leading dimension ld),
+// from the panel-major layout L (PANEL) or from Y itself, optionally
+// normalised to unit length (sq: the squared norms, or NULL).  A workgroup
+// takes kTileRows rows and moves them with consecutive threads on
+// consecutive elements (a thread per row would touch a cache line per row
+// and per load); the norms go through LDS in chunks of kTileCols columns,
+// where thread r adds up row r's float64 squares in column order.  When the
+// row fits one chunk the staged tile also feeds the writes.
+constexpr int kTileRows = 64, kTileCols = 128;
+
+template <bool PANEL>
+__global__ __launch_bounds__(256) void k_rows_out(Layout L, const float* in, int n_rows, int w,
+                                                  float* Y, int ld, int normalize, double* sq) {
+  __shared__ float tile[kTileRows][kTileCols + 1];
+  __shared__ double inv[kTileRows];
+  const int i0 = blockIdx.x * kTileRows;
+  auto src = [&](int i, int c) -> float {
+    if (PANEL) return in[(size_t)(c / L.pw) * L.panel_elems() + (size_t)i * L.pw + c % L.pw];
+    return in[(size_t)i * ld + c];
+  };
+  const bool staged = normalize && w <= kTileCols;
   if (normalize) {
     double s = 0.0;
-    for (int c = 0; c < L.w; ++c) {
-      const double v = in[(size_t)(c / L.pw) * pe + (size_t)i * L.pw + c % L.pw];
-      s += v * v;
+    for (int c0 = 0; c0 < w; c0 += kTileCols) {
+      const int cw = min(kTileCols, w - c0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < kTileRows * cw; e += blockDim.x) {
+        const int r = e / cw, c = e - r * cw, i = i0 + r;
+        tile[r][c] = i < n_rows ? src(i, c0 + c) : 0.f;
+      }
+      __syncthreads();
+      if (threadIdx.x < kTileRows)
+        for (int c = 0; c < cw; ++c) {
+          const double v = tile[threadIdx.x][c];
+          s += v * v;
+        }
     }
-    inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    if (threadIdx.x < kTileRows) {
+      const int i = i0 + threadIdx.x;
+      if (sq && i < n_rows) sq[i] = s;
+      inv[threadIdx.x] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    }
+    __syncthreads();
   }
-  for (int c = 0; c < L.w; ++c) {
-    const float v = in[(size_t)(c / L.pw) * pe + (size_t)i * L.pw + c % L.pw];
-    Y[(size_t)i * ld + c] = normalize ? (float)((double)v * inv) : v;
+  for (int c0 = 0; c0 < w; c0 += kTileCols) {
+    const int cw = min(kTileCols, w - c0);
+    for (int e = threadIdx.x; e < kTileRows * cw; e += blockDim.x) {
+      const int r = e / cw, c = e - r * cw, i = i0 + r;
+      if (i >= n_rows) continue;
+      const float v = staged ? tile[r][c] : src(i, c0 + c);
+      Y[(size_t)i * ld + c0 + c] = normalize ? (float)((double)v * inv[r]) : v;
+    }
   }
-}
-
-__global__ void k_normalize_rows(int n_rows, int w, float* Y, int ld, double* sq) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_rows) return;
-  float* y = Y + (size_t)i * ld;
-  double s = 0.0;
-  for (int c = 0; c < w; ++c) s += (double)y[c] * (double)y[c];
-  if (sq) sq[i] = s;
-  const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-  for (int c = 0; c < w; ++c) y[c] = (float)((double)y[c] * inv);
 }
 
 template <class T>
@@ -525,15 +550,17 @@ hipError_t launch_from_compact(const Layout& Lc, const float* src, const Layout&
 
 hipError_t launch_unpack(const Layout& L, const float* in, float* Y, int ld, int normalize,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_unpack, dim3(grid_for(L.n, kBlock, 1u << 30)), dim3(kBlock), 0, s, L, in, Y,
-                     ld, normalize);
+  if (L.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows_out<true>, dim3((unsigned)((L.n + kTileRows - 1) / kTileRows)),
+                     dim3(256), 0, s, L, in, L.n, L.w, Y, ld, normalize, (double*)nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_normalize_rows(int n_rows, int w, float* Y, int ld, hipStream_t s,
                                 double* sq) {
-  hipLaunchKernelGGL(k_normalize_rows, dim3(grid_for(n_rows, kBlock, 1u << 30)), dim3(kBlock), 0, s,
-                     n_rows, w, Y, ld, sq);
+  if (n_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows_out<false>, dim3((unsigned)((n_rows + kTileRows - 1) / kTileRows)),
+                     dim3(256), 0, s, Layout{}, (const float*)Y, n_rows, w, Y, ld, 1, sq);
   return hipGetLastError();
 }
 

@@ -471,11 +471,14 @@ def test_end_to_end_tiny_graphs(api, N, kind, k):
         assert metrics.adjusted_rand_index(lab, ref.labels) >= 0.99
 
 
-@pytest.fixture(scope="module")
-def multi_panel():
-    """k = 300 columns on a 3000-node SBM and the oracle's tight solution."""
+@pytest.fixture(scope="module", params=[129, 300])
+def multi_panel(request):
+    """k = 129 or 300 columns on a 3000-node SBM and the oracle's tight
+    solution.  k = 129: the Gram matrices' second 128-column tile holds one
+    column (the symmetric ones sum the tiles on and below the diagonal and
+    mirror the rest); k = 300: three tiles, two panels."""
     gr = synth.sbm(3000, 30, 16.0, 0.25 * synth.eps_critical(16.0, 30), seed=4)
-    k, n = 300, 1200
+    k, n = request.param, 1200
     omega = sampling.sample(gr.n, n, 5)
     lab_r = np.arange(n) % k
     Xt, lab, _, _ = interp.interpolate(_A(gr), 0.6, 30, 1e-3, omega, lab_r, k, tol=1e-12)
@@ -484,11 +487,13 @@ def multi_panel():
 
 @pytest.mark.parametrize("method", [1, 2])
 def test_block_interpolation_with_several_panels(api, multi_panel, method):
-    """The k = 300 columns span two panels of the block layout (widths up to
-    256): the Gram matrices and block products cross panel boundaries."""
+    """k = 300 columns span two panels of the block layout (widths up to
+    256): the Gram matrices and block products cross panel boundaries; k = 129
+    puts one column in the Gram matrices' second tile."""
     gr, k, omega, lab_r, Xt, lab = multi_panel
     g = api.Graph(gr.row_ptr, gr.col)
-    assert api.panel_width(gr.n, k, gr.nnz) < k  # more than one panel
+    if k == 300:
+        assert api.panel_width(gr.n, k, gr.nnz) < k  # more than one panel
     res = api.interpolate(g, 0.6, 30, 1e-3, omega, lab_r, k, method=method)
     assert res.status == 0 and np.all(res.relres <= 1e-6)
     assert _relfro(res.X.cpu().numpy(), Xt) <= 1e-3
