@@ -41,8 +41,11 @@ constexpr int kUpdLds = 8192;    // update step: labels and members in LDS up to
 constexpr int kUpdK = 1024;      // update step: cluster sizes and offsets in LDS up to this k
 
 struct KmItem {
-  const double* X;   // n x d, row-major
-  const double* Xt;  // d x n (coordinate j of point i at Xt[j * n + i])
+  // the float32 points (k-means takes float32 features; every sum widens a
+  // coordinate to float64 exactly where it is used, so storing them as float
+  // changes no value and halves the bytes each pass reads)
+  const float* X;   // n x d, row-major
+  const float* Xt;  // d x n (coordinate j of point i at Xt[j * n + i])
   int n, d, k, r, max_iter;
   uint64_t seed;
   double* C;        // k x d
@@ -74,7 +77,7 @@ __device__ inline double sqd(const double* x, const double* c, int d) {
 // the same sum with the point read from the transposed block (coalesced
 // across the threads of a wave, one point per thread); the coordinate loads
 // of eight terms are issued before their additions, which stay in order
-__device__ inline double sqd_t(const double* Xt, int n, int i, const double* c, int d) {
+__device__ inline double sqd_t(const float* Xt, int n, int i, const double* c, int d) {
   double acc = 0.0;
   int j = 0;
   for (; j + 8 <= d; j += 8) {
@@ -98,13 +101,13 @@ __device__ inline double sqd_t(const double* Xt, int n, int i, const double* c, 
 // runs over the coordinates in order exactly as sqd_t's, the three points'
 // loads in flight together (a point past n reads point i's coordinates as a
 // stand-in and its result is not used).
-__device__ inline void sqd_t3(const double* Xt, int n, int i, int s, const double* c, int d,
+__device__ inline void sqd_t3(const float* Xt, int n, int i, int s, const double* c, int d,
                               double out[3]) {
   const int i1 = i + s < n ? i + s : i, i2 = i + 2 * s < n ? i + 2 * s : i;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   int j = 0;
   for (; j + 4 <= d; j += 4) {  // 12 loads in flight (the kernel keeps within 128 VGPRs)
-    double x0[4], x1[4], x2[4];
+    float x0[4], x1[4], x2[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       x0[q] = Xt[(size_t)(j + q) * n + i];
@@ -114,7 +117,7 @@ __device__ inline void sqd_t3(const double* Xt, int n, int i, int s, const doubl
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const double cq = c[j + q];
-      const double e0 = x0[q] - cq, e1 = x1[q] - cq, e2 = x2[q] - cq;
+      const double e0 = (double)x0[q] - cq, e1 = (double)x1[q] - cq, e2 = (double)x2[q] - cq;
       a0 = a0 + e0 * e0;
       a1 = a1 + e1 * e1;
       a2 = a2 + e2 * e2;
@@ -122,8 +125,8 @@ __device__ inline void sqd_t3(const double* Xt, int n, int i, int s, const doubl
   }
   for (; j < d; ++j) {
     const double cq = c[j];
-    const double e0 = Xt[(size_t)j * n + i] - cq, e1 = Xt[(size_t)j * n + i1] - cq,
-                 e2 = Xt[(size_t)j * n + i2] - cq;
+    const double e0 = (double)Xt[(size_t)j * n + i] - cq, e1 = (double)Xt[(size_t)j * n + i1] - cq,
+                 e2 = (double)Xt[(size_t)j * n + i2] - cq;
     a0 = a0 + e0 * e0;
     a1 = a1 + e1 * e1;
     a2 = a2 + e2 * e2;
@@ -218,7 +221,7 @@ __device__ inline int block_or(int v, int* sh) {
 __device__ void assign(const KmItem& t, const double* C, int* out) {
   const int n = t.n, d = t.d, k = t.k;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double* x = t.Xt + i;
+    const float* x = t.Xt + i;
     double best = 0.0;
     int arg = 0;
     int c = 0;
@@ -398,7 +401,7 @@ __global__ __launch_bounds__(kKmBlock) void k_km_seed(const KmItem* items) {
 // guards, which kept the compiler from scheduling the full stripe's products
 // freely (measured: the assignment 180 -> 112 us per launch).
 template <bool FULL>
-__device__ inline void stripe_sqd(const double* x, int n, const double* cb, int d, int nc,
+__device__ inline void stripe_sqd(const float* x, int n, const double* cb, int d, int nc,
                                   double (&a)[kStripe]) {
 #pragma unroll
   for (int u = 0; u < kStripe; ++u) a[u] = 0.0;
@@ -557,7 +560,7 @@ __global__ __launch_bounds__(kKmBlock) void k_km_update(const KmItem* items) {
     const int cnt = counts[c];
     if (cnt == 0) continue;
     double acc = 0.0;
-    const double* xj = t.X + j;
+    const float* xj = t.X + j;
     int m = mstart[c];
     const int m1 = mstart[c + 1];
     for (; m + 8 <= m1; m += 8) {
@@ -618,12 +621,12 @@ __global__ __launch_bounds__(kKmBlock) void k_km_finish(const KmItem* items) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) t.out_labels[i] = t.lab[i];
 }
 
-__global__ void k_to_f64(int n, int d, const float* F, int ld, double* X, double* Xt) {
+__global__ void k_stage_points(int n, int d, const float* F, int ld, float* X, float* Xt) {
   const size_t total = (size_t)n * d;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / d), j = (int)(e - (size_t)i * d);
-    const double v = (double)F[(size_t)i * ld + j];
+    const float v = F[(size_t)i * ld + j];
     X[e] = v;
     Xt[(size_t)j * n + i] = v;
   }
@@ -671,12 +674,12 @@ csc_status run_lloyd(const KmItem* items, int count, int max_stripes, int max_n,
   return CSC_OK;
 }
 
-// workspace of one input: X (n x d doubles) + per replicate C, mind, cum,
+// workspace of one input: X and its transpose (n x d floats) + per replicate C, mind, cum,
 // lab, fresh, counts, mstart, members, labels, stripe results, seeding block
 // offsets, Lloyd flags;
 // plus inertias
 size_t km_bytes(int n, int d, int k, int reps) {
-  size_t b = 2 * align_up((size_t)n * d * sizeof(double));
+  size_t b = 2 * align_up((size_t)n * d * sizeof(float));
   const size_t ns = (size_t)stripes(k);
   const size_t per = align_up((size_t)k * d * sizeof(double)) + 2 * align_up((size_t)n * sizeof(double)) +
                      4 * align_up((size_t)n * sizeof(int)) + 2 * align_up(((size_t)k + 1) * sizeof(int)) +
@@ -688,8 +691,8 @@ size_t km_bytes(int n, int d, int k, int reps) {
 }
 
 struct KmPlan {
-  double* X;
-  double* Xt;
+  float* X;
+  float* Xt;
   std::vector<KmItem> items;
   double* inertia;
   int* labels0;  // replicate r's labels at labels0 + r * n
@@ -697,8 +700,8 @@ struct KmPlan {
 
 csc_status plan_km(Arena& ar, const float* F, int n, int d, int ld, int k, int reps, int max_iter,
                    uint64_t seed, KmPlan& P, hipStream_t s) {
-  P.X = ar.take<double>((size_t)n * d);
-  P.Xt = ar.take<double>((size_t)n * d);
+  P.X = ar.take<float>((size_t)n * d);
+  P.Xt = ar.take<float>((size_t)n * d);
   P.inertia = ar.take<double>(reps);
   P.items.resize(reps);
   P.labels0 = nullptr;
@@ -731,7 +734,7 @@ csc_status plan_km(Arena& ar, const float* F, int n, int d, int ld, int k, int r
     set_error("internal: k-means workspace overflow");
     return CSC_E_INVALID_ARG;
   }
-  hipLaunchKernelGGL(k_to_f64, dim3((unsigned)std::min<size_t>(((size_t)n * d + 255) / 256, 4096)),
+  hipLaunchKernelGGL(k_stage_points, dim3((unsigned)std::min<size_t>(((size_t)n * d + 255) / 256, 4096)),
                      dim3(256), 0, s, n, d, F, ld, P.X, P.Xt);
   CSC_HIP(hipGetLastError());
   return CSC_OK;
