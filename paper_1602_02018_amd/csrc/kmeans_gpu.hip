@@ -39,6 +39,8 @@ constexpr int kStripeMaxD = 512;  // stripe centroids staged in LDS up to this d
 constexpr int kChecks = 4;       // Lloyd iterations launched between convergence checks
 constexpr int kUpdLds = 8192;    // update step: labels and members in LDS up to this n
 constexpr int kUpdK = 1024;      // update step: cluster sizes and offsets in LDS up to this k
+constexpr int kHistRows = 64;     // update step: points per block of the member-list counts
+constexpr int kHistInts = 12288;  // update step: those (blocks x k) counts in LDS up to this size
 
 struct KmItem {
   // the float32 points (k-means takes float32 features; every sum widens a
@@ -482,6 +484,7 @@ __global__ __launch_bounds__(kKmBlock) void k_km_update(const KmItem* items) {
   __shared__ __align__(16) int s_lab[kUpdLds];
   __shared__ int s_mem[kUpdLds];
   __shared__ int s_cnt[kUpdK], s_start[kUpdK + 1];
+  __shared__ int s_hist[kHistInts];
   const bool in_lds = n <= kUpdLds;  // labels and member lists in LDS for the scans
   const bool k_lds = k <= kUpdK;     // cluster sizes and list offsets likewise
   double* C = t.C;
@@ -521,11 +524,34 @@ __global__ __launch_bounds__(kKmBlock) void k_km_update(const KmItem* items) {
   }
   for (int i = threadIdx.x; i < n; i += blockDim.x) lab[i] = t.fresh[i];
   __syncthreads();
-  // cluster sizes (integer atomics, so their order does not matter), then the
-  // members of every cluster in index order
-  for (int c = threadIdx.x; c < k; c += blockDim.x) counts[c] = 0;
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&counts[lab[i]], 1);
+  // cluster sizes, then the members of every cluster in index order.  With
+  // the labels in LDS and (blocks of kHistRows points) x k counts fitting
+  // there too: per block and cluster the count, per cluster the running
+  // offsets over the blocks (so the sizes), and each block's points placed in
+  // order by one thread; else the sizes by integer atomics and each cluster's
+  // members by a scan of all labels.  Both give the same lists.
+  const int nbk = (n + kHistRows - 1) / kHistRows;
+  const bool hist = in_lds && (size_t)nbk * k <= (size_t)kHistInts;
+  if (hist) {
+    for (int e = threadIdx.x; e < nbk * k; e += blockDim.x) s_hist[e] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      atomicAdd(&s_hist[(i / kHistRows) * k + lab[i]], 1);
+    __syncthreads();
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+      int run = 0;
+      for (int b = 0; b < nbk; ++b) {
+        const int h = s_hist[b * k + c];
+        s_hist[b * k + c] = run;
+        run += h;
+      }
+      counts[c] = run;
+    }
+  } else {
+    for (int c = threadIdx.x; c < k; c += blockDim.x) counts[c] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&counts[lab[i]], 1);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     int sum = 0;
@@ -536,21 +562,32 @@ __global__ __launch_bounds__(kKmBlock) void k_km_update(const KmItem* items) {
     mstart[k] = sum;
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    int w = mstart[c];
-    int i = 0;
-    if (in_lds) {  // four labels per LDS read
-      const int4* l4 = reinterpret_cast<const int4*>(lab);
-      for (; i + 4 <= n; i += 4) {
-        const int4 q = l4[i >> 2];
-        if (q.x == c) members[w++] = i;
-        if (q.y == c) members[w++] = i + 1;
-        if (q.z == c) members[w++] = i + 2;
-        if (q.w == c) members[w++] = i + 3;
+  if (hist) {
+    for (int b = threadIdx.x; b < nbk; b += blockDim.x) {
+      int* off = s_hist + b * k;
+      const int i1 = min(n, (b + 1) * kHistRows);
+      for (int i = b * kHistRows; i < i1; ++i) {
+        const int c = lab[i];
+        members[mstart[c] + off[c]++] = i;
       }
     }
-    for (; i < n; ++i)
-      if (lab[i] == c) members[w++] = i;
+  } else {
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+      int w = mstart[c];
+      int i = 0;
+      if (in_lds) {  // four labels per LDS read
+        const int4* l4 = reinterpret_cast<const int4*>(lab);
+        for (; i + 4 <= n; i += 4) {
+          const int4 q = l4[i >> 2];
+          if (q.x == c) members[w++] = i;
+          if (q.y == c) members[w++] = i + 1;
+          if (q.z == c) members[w++] = i + 2;
+          if (q.w == c) members[w++] = i + 3;
+        }
+      }
+      for (; i < n; ++i)
+        if (lab[i] == c) members[w++] = i;
+    }
   }
   __syncthreads();
   // centroid sums over members in index order; the d threads of one cluster
