@@ -147,6 +147,78 @@ __global__ __launch_bounds__(256) void k_gram(Layout L, const float* A, const fl
             acc[g][h][v];
 }
 
+// k_gram for ka <= 16 (a search block of at most 16 live columns): only the
+// first 16 rows of each output tile hold anything, so each wave takes a
+// 16 x 32 strip of the tile's columns (wave w: columns 32 w .. 32 w + 31)
+// instead of a 64 x 64 quarter, an eighth of the matrix-core work.  Stages,
+// steps and lanes are k_gram's: every entry takes the same products in the
+// same order, so the partials (and the Gram) are k_gram's bit for bit.
+constexpr int kThinA = 16;
+__global__ __launch_bounds__(256) void k_gram_thin(Layout L, const float* A, const float* B,
+                                                   int ka, int kb, int rows_per_chunk,
+                                                   int rows_pad, double* part) {
+  __shared__ float As[2][kGS][kThinA + 4];
+  __shared__ float Bs[2][kGS][kGLD];
+  const int tj = blockIdx.x, chunk = blockIdx.y;
+  const int r0 = chunk * rows_per_chunk;
+  const int r1 = min(L.n, r0 + rows_per_chunk);
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int q = lane >> 4, c16 = lane & 15;
+  const int wb = wave * 32;
+  const int cb0 = tj * kGT;
+  float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb[4];
+  int la = 0, lb[4];
+  auto fetch = [&](int base) {
+    if (t < kGS * kThinA / 4) {  // 32 rows x 16 columns of A: one float4 per thread
+      const int row = t >> 2, c = (t & 3) * 4, i = base + row;
+      ra = cols4_load(L, A, i, c, ka, i < r1, la);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int f = t + 256 * u, row = f >> 5, c = (f & 31) * 4, i = base + row;
+      rb[u] = cols4_load(L, B, i, cb0 + c, kb, i < r1, lb[u]);
+    }
+  };
+  auto stash = [&](int buf) {
+    if (t < kGS * kThinA / 4)
+      *reinterpret_cast<float4*>(&As[buf][t >> 2][(t & 3) * 4]) = cols4_mask(ra, la);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int f = t + 256 * u, row = f >> 5, c = (f & 31) * 4;
+      *reinterpret_cast<float4*>(&Bs[buf][row][c]) = cols4_mask(rb[u], lb[u]);
+    }
+  };
+  v4d acc[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) acc[h] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int nst = (r1 - r0 + kGS - 1) / kGS;
+  fetch(r0);
+  stash(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst) fetch(r0 + (st + 1) * kGS);
+#pragma unroll 2
+    for (int ks = 0; ks < kGS / 4; ++ks) {
+      const double a = (double)As[buf][4 * ks + q][c16];
+      double b[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) b[h] = (double)Bs[buf][4 * ks + q][wb + 16 * h + c16];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) acc[h] = mfma64(a, b[h], acc[h]);
+    }
+    if (st + 1 < nst) stash(buf ^ 1);
+    __syncthreads();
+  }
+  const int ldp = gridDim.x * kGT;
+  double* out = part + (size_t)chunk * rows_pad * ldp;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      out[(size_t)(q + 4 * v) * ldp + cb0 + wb + 16 * h + c16] = acc[h][v];
+}
+
 // G[i * ldg + j] = sum over chunks of the partial tiles: 16 entries per
 // workgroup, 16 threads per entry summing chunks s, s + 16, ... in order,
 // then the 16 slices in order.  lower: an entry of a tile above the diagonal
@@ -350,8 +422,12 @@ size_t gram_part_elems(const Layout& L, int kmax) {
 hipError_t launch_gram(const Layout& L, const float* A, const float* B, int ka, int kb,
                        double* part, double* G, int ldg, hipStream_t s, bool lower) {
   const GramPlan g = gram_plan(L, ka, kb, lower);
-  hipLaunchKernelGGL(k_gram, dim3((unsigned)g.tiles, (unsigned)g.chunks), dim3(256), 0, s, L, A, B,
-                     ka, kb, g.rows_per_chunk, g.tiles_b, g.tiles_a * kGT, g.lower, part);
+  if (ka <= kThinA)  // one tile row: a 16-row strip of each tile (tiles = tiles_b)
+    hipLaunchKernelGGL(k_gram_thin, dim3((unsigned)g.tiles_b, (unsigned)g.chunks), dim3(256), 0, s,
+                       L, A, B, ka, kb, g.rows_per_chunk, g.tiles_a * kGT, part);
+  else
+    hipLaunchKernelGGL(k_gram, dim3((unsigned)g.tiles, (unsigned)g.chunks), dim3(256), 0, s, L, A,
+                       B, ka, kb, g.rows_per_chunk, g.tiles_b, g.tiles_a * kGT, g.lower, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n = ka * kb;
