@@ -41,6 +41,8 @@ def _blobs(seed, n, d, k, spread=0.3):
     (12, 1, 3, 1, 2),         # one point, one cluster
     (6, 1025, 49, 40, 4),     # just past it in both n and d
     (8, 700, 49, 30, 4),      # past it in d only
+    (13, 3000, 8, 300, 2),    # member lists by a scan of the labels: (blocks x k) counts past LDS
+    (14, 9000, 6, 12, 2),     # labels past the update's LDS copy: the scan over global memory
 ])
 def test_device_kmeans_is_bit_identical_to_host(api, seed, n, d, k, reps):
     X = _blobs(seed, n, d, k)
