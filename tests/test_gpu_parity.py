@@ -166,8 +166,9 @@ def test_filter_block_on_graph_without_edges(api):
 
 
 @pytest.mark.parametrize("normalize", [True, False])
-def test_feature_pass_all_rows(api, cfg1, normalize):
-    d, p, seed, lam = 28, 50, 0, 0.46875
+@pytest.mark.parametrize("d", [28, 130])  # rows written in one LDS chunk, or two (d > 128)
+def test_feature_pass_all_rows(api, cfg1, normalize, d):
+    p, seed, lam = 50, 0, 0.46875
     g = api.Graph(cfg1.row_ptr, cfg1.col)
     F = api.filter(g, lam, p, d, seed, normalize=normalize).cpu().numpy()
     R = philox.gaussian_block(seed, cfg1.n, d, 0, philox.FEAT)
