@@ -208,3 +208,28 @@ def test_run_with_and_without_order(api, cfg1, seed):
     assert np.array_equal(a.labels_r, b.labels_r)
     assert metrics.adjusted_rand_index(a.labels.cpu().numpy(), b.labels.cpu().numpy()) >= 0.99
     assert metrics.adjusted_rand_index(b.labels.cpu().numpy(), cfg1.truth) > 0.9
+
+
+@pytest.mark.parametrize("d", [5, 28, 47, 56, 64, 90, 128])
+def test_nearest_centroid_at_every_padded_width(api, cfg1, d):
+    """Each instance of the nearest-centroid kernel (rows padded with zeros to
+    32, 48, 56, 64, 96 or 128 coordinates): labels agree with a float64 host
+    argmin wherever the two nearest centroids are not tied within float32
+    rounding, ties to the lowest index."""
+    rng = np.random.default_rng(d)
+    k = 20
+    N = cfg1.n
+    F_all = torch.as_tensor(rng.normal(size=(N, d)).astype(np.float32), device="cuda")
+    g = api.Graph(cfg1.row_ptr, cfg1.col)
+    omega = api.sample(N, 200, 3)
+    lab_r = (np.arange(200) % k).astype(np.int32)
+    _, nl = api.community_order(g, F_all, omega, lab_r, k, want_labels=True)
+    nl = nl.cpu().numpy()
+    Fs = F_all.cpu().numpy().astype(np.float64)[omega.cpu().numpy()]
+    C = np.stack([Fs[lab_r == c].mean(axis=0) for c in range(k)]).astype(np.float32).astype(np.float64)
+    Fa = F_all.cpu().numpy().astype(np.float64)
+    D = ((Fa[:, None, :] - C[None, :, :]) ** 2).sum(axis=2)
+    srt = np.sort(D, axis=1)
+    clear = srt[:, 1] - srt[:, 0] > 1e-5 * (1 + srt[:, 0])
+    assert clear.mean() > 0.9
+    assert np.array_equal(nl[clear], np.argmin(D, axis=1)[clear])
