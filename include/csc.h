@@ -473,7 +473,11 @@ csc_status csc_kmeans_reduced_device(const float* F, int32_t n, int32_t d, int32
  *   residual keep the values it converged with), and a search block narrower
  *   than k runs its Chebyshev pass on a compact copy of its live columns.
  *   All solve the same system; X agrees to the accuracy the tolerance
- *   implies.
+ *   implies.  In the block forms the update X += P alpha runs on a
+ *   library-owned second stream while the host works out the next step
+ *   matrix; events order it after the work it reads and make `stream` wait
+ *   for it before X or P is touched again, so the caller sees the usual
+ *   stream order.
  * ws: csc_interpolate_workspace_bytes(N, nnz, k, n) (covers every form).
  * Synchronises.  Returns CSC_W_NOT_CONVERGED if a column reached max_iter or
  * the block iteration broke down (outputs still hold the last iterate).
