@@ -459,8 +459,10 @@ class SignalAhead {
 // One eigencount pass on the signals of pass t: drawn into c.T0 first, or
 // already in T0 (drawn ahead by the caller) when T0 is given.
 // With a group, the passes of tests t .. t + g - 1 at once, moments of test
-// t + j in mom_host[j (p + 1) ..].  `between` runs on the host after the pass
-// is enqueued, before the wait.
+// t + j in mom_host[j (p + 1) ..].  `between` runs on the host as soon as the
+// pass's steps are enqueued: before the copy of the moments, which, into
+// pageable host memory, returns only once the pass has run (work that
+// `between` enqueues on another stream then overlaps the pass).
 csc_status moments_pass(const csc_graph& g, const Layout& L, int p, uint64_t seed, uint32_t t,
                         const CountBuffers& c, double* mom_host, hipStream_t s,
                         const float* T0 = nullptr,
@@ -477,11 +479,11 @@ csc_status moments_pass(const csc_graph& g, const Layout& L, int p, uint64_t see
   b.mnc4 = cg.nc4;
   std::vector<double> zero(p + 1, 0.0);
   CSC_TRY(chebyshev_pass(g, L, zero.data(), p, EPI_MOM, b, s));
+  if (between) CSC_TRY(between());
   const int nraw = moment_raw(p);
   CSC_HIP(launch_reduce(c.part, (int)(nblocks * kMomSlots), cg.g * nraw, c.mom, s));
   std::vector<double> raw((size_t)cg.g * nraw);
   CSC_HIP(hipMemcpyAsync(raw.data(), c.mom, raw.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  if (between) CSC_TRY(between());
   CSC_HIP(hipStreamSynchronize(s));
   for (int j = 0; j < cg.g; ++j)
     moments_from_raw(raw.data() + (size_t)j * nraw, p, mom_host + (size_t)j * (p + 1));
