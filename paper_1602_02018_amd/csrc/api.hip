@@ -1133,11 +1133,29 @@ csc_status block_init(BlockState& st, const Layout& L, int k, double tol, bool j
 // stream in between).  block_pre and block_post chain the stages of one
 // graph; the batched form runs each stage for all graphs, one
 // synchronisation per stage and the host stages in parallel.
+// Bit t set when 128-column tile t of the k columns holds a column still in
+// the search: the Gram entries and block-product columns of the other tiles
+// are never read (done columns are zeroed out of G and have zero step
+// coefficients), so their kernels skip them.
+uint64_t live_tiles(const BlockState& st) {
+  uint64_t m = 0;
+  for (int j = 0; j < st.k; ++j)
+    if (!st.done[j]) m |= 1ull << std::min(j / kBlockTile, 63);
+  return m;
+}
+
+// Tiles covering columns [0, w).
+uint64_t prefix_tiles(int w) {
+  const int t = (w + kBlockTile - 1) / kBlockTile;
+  return t >= 64 ? ~0ull : (1ull << t) - 1;
+}
+
 csc_status pre_launch(BlockState& st, hipStream_t s) {
   const BlockBufs& b = st.b;
   const int k = st.k;
   // symmetric: the tiles on and below the diagonal, the rest mirrored
-  CSC_HIP(launch_gram(st.L, b.Z, b.Z, k, k, b.gpart, b.G, k, s, /*lower=*/true));
+  const uint64_t live = live_tiles(st);
+  CSC_HIP(launch_gram(st.L, b.Z, b.Z, k, k, b.gpart, b.G, k, s, /*lower=*/true, live, live));
   st.G.resize((size_t)k * k);
   CSC_HIP(hipMemcpyAsync(st.G.data(), b.G, st.G.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   return CSC_OK;
@@ -1161,8 +1179,10 @@ csc_status pre_finish(BlockState& st, hipStream_t s) {
   const BlockBufs& b = st.b;
   const int k = st.k;
   CSC_TRY(upload_d(b.S_t, st.T, s));
+  // P's columns past sr are read by nothing (passes, Grams and products all
+  // stop at sr; a full-width pass leaves them in columns nobody reads)
   CSC_HIP(launch_block_mul(st.L, 0.f, nullptr, b.Z, b.S_t, k, st.sr, k, b.P, s,
-                           /*f32=*/st.jacobi));
+                           /*f32=*/st.jacobi, prefix_tiles(st.sr)));
   return CSC_OK;
 }
 
@@ -1172,7 +1192,7 @@ csc_status post_launch_a(BlockState& st, hipStream_t s) {
   const int k = st.k, sr = st.sr;
   // the Cholesky factorisation reads W's lower triangle only
   CSC_HIP(launch_gram(st.L, b.P, b.Q, sr, sr, b.gpart, b.G, sr, s, /*lower=*/true));
-  CSC_HIP(launch_gram(st.L, b.P, b.R, sr, k, b.gpart, b.S_b, k, s));
+  CSC_HIP(launch_gram(st.L, b.P, b.R, sr, k, b.gpart, b.S_b, k, s, false, ~0ull, live_tiles(st)));
   st.W.resize((size_t)sr * sr);
   st.C.resize((size_t)sr * k);
   CSC_HIP(hipMemcpyAsync(st.W.data(), b.G, st.W.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1216,14 +1236,16 @@ csc_status launch_x_update(BlockState& st, hipStream_t s) {
     }
   }
   if (!s2 || !x.go) {
-    CSC_HIP(launch_block_mul(st.L, 1.f, b.X, b.P, b.S_a, st.sr, st.k, st.k, b.X, s, /*f32=*/true));
+    CSC_HIP(launch_block_mul(st.L, 1.f, b.X, b.P, b.S_a, st.sr, st.k, st.k, b.X, s, /*f32=*/true,
+                             live_tiles(st)));
     return CSC_OK;
   }
   CSC_HIP(hipEventRecord(x.go, s));
   CSC_HIP(hipStreamWaitEvent(s2, x.go, 0));
   x.main = s;
   x.pending = true;
-  CSC_HIP(launch_block_mul(st.L, 1.f, b.X, b.P, b.S_a, st.sr, st.k, st.k, b.X, s2, /*f32=*/true));
+  CSC_HIP(launch_block_mul(st.L, 1.f, b.X, b.P, b.S_a, st.sr, st.k, st.k, b.X, s2, /*f32=*/true,
+                           live_tiles(st)));
   CSC_HIP(hipEventRecord(x.done, s2));
   return CSC_OK;
 }
@@ -1259,11 +1281,13 @@ csc_status post_launch_b(BlockState& st, hipStream_t s) {
   const int k = st.k, sr = st.sr;
   CSC_TRY(upload_d(b.S_a, st.C, s));
   CSC_TRY(upload_d(b.S_na, st.N, s));
-  CSC_HIP(launch_block_mul(L, 1.f, b.R, b.Q, b.S_na, sr, k, k, b.R, s));
+  const uint64_t live = live_tiles(st);
+  CSC_HIP(launch_block_mul(L, 1.f, b.R, b.Q, b.S_na, sr, k, k, b.R, s, false, live));
   CSC_HIP(launch_col_dot(L, b.R, b.R, b.part, s));
   CSC_HIP(launch_reduce(b.part, col_dot_chunks(L), k, b.rn2, s));
   if (st.jacobi) CSC_HIP(launch_jacobi(L, b.R, b.mask, st.gamma, b.Z, s));
-  CSC_HIP(launch_gram(L, b.Q, st.jacobi ? b.Z : b.R, sr, k, b.gpart, b.G, k, s));
+  CSC_HIP(launch_gram(L, b.Q, st.jacobi ? b.Z : b.R, sr, k, b.gpart, b.G, k, s, false, ~0ull,
+                      live));
   st.rn2.resize(k);
   st.C.resize((size_t)sr * k);
   CSC_HIP(hipMemcpyAsync(st.rn2.data(), b.rn2, (size_t)k * sizeof(double), hipMemcpyDeviceToHost,
@@ -1303,7 +1327,7 @@ csc_status post_finish(BlockState& st, hipStream_t s) {
   CSC_TRY(block_join(st));
   CSC_TRY(upload_d(b.S_b, st.C, s));
   CSC_HIP(launch_block_mul(st.L, 1.f, st.jacobi ? b.Z : b.R, b.P, b.S_b, sr, k, k, b.Z, s,
-                           /*f32=*/st.jacobi));
+                           /*f32=*/st.jacobi, live_tiles(st)));
   return CSC_OK;
 }
 

@@ -25,6 +25,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kGT = 128;  // Gram output tile per workgroup (4 waves of 64 x 64)
 constexpr int kMR = 128;  // block product: rows per workgroup (2 waves of 64)
 constexpr int kMC = 128;  // block product: columns per workgroup (2 waves of 64)
+static_assert(kGT == kBlockTile && kMC == kBlockTile, "column tiles of the tile masks");
 
 // Offset of column c within row 0 of a panel-major block: element (i, c) is at
 // col_base(L, c) + i * pw.
@@ -70,7 +71,8 @@ constexpr int kGLD = kGT + 16;  // LDS row stride (floats): the 4 rows a wave re
 // (w / 2, w mod 2), four rows per matrix-core step.
 __global__ __launch_bounds__(256) void k_gram(Layout L, const float* A, const float* B, int ka,
                                               int kb, int rows_per_chunk, int tiles_b,
-                                              int rows_pad, bool lower, double* part) {
+                                              int rows_pad, bool lower, uint64_t amask,
+                                              uint64_t bmask, double* part) {
   __shared__ float As[2][kGS][kGLD];
   __shared__ float Bs[2][kGS][kGLD];
   int ti, tj;
@@ -82,6 +84,7 @@ __global__ __launch_bounds__(256) void k_gram(Layout L, const float* A, const fl
     ti = blockIdx.x / tiles_b;
     tj = blockIdx.x - ti * tiles_b;
   }
+  if (!((amask >> ti) & 1) || !((bmask >> tj) & 1)) return;  // a tile nobody reads
   const int chunk = blockIdx.y;
   const int r0 = chunk * rows_per_chunk;
   const int r1 = min(L.n, r0 + rows_per_chunk);
@@ -156,10 +159,11 @@ __global__ __launch_bounds__(256) void k_gram(Layout L, const float* A, const fl
 constexpr int kThinA = 16;
 __global__ __launch_bounds__(256) void k_gram_thin(Layout L, const float* A, const float* B,
                                                    int ka, int kb, int rows_per_chunk,
-                                                   int rows_pad, double* part) {
+                                                   int rows_pad, uint64_t bmask, double* part) {
   __shared__ float As[2][kGS][kThinA + 4];
   __shared__ float Bs[2][kGS][kGLD];
   const int tj = blockIdx.x, chunk = blockIdx.y;
+  if (!((bmask >> tj) & 1)) return;  // a tile nobody reads
   const int r0 = chunk * rows_per_chunk;
   const int r1 = min(L.n, r0 + rows_per_chunk);
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
@@ -271,7 +275,8 @@ static_assert(kXU >= 1 && kSU >= 1 && kSU <= 32, "block product staging shape");
 template <bool F32>
 __global__ __launch_bounds__(256, 2) void k_block_mul(Layout L, float c0, const float* In0,
                                                    const float* In1, const double* S, int kin,
-                                                   int kout, int lds, float* Out) {
+                                                   int kout, int lds, uint64_t cmask, float* Out) {
+  if (!((cmask >> blockIdx.y) & 1)) return;  // columns nobody reads
   typedef typename std::conditional<F32, float, double>::type sc_t;
   typedef typename std::conditional<F32, v4f, v4d>::type acc_t;
   __shared__ float Xs[2][kMR][kXLD];
@@ -420,14 +425,19 @@ size_t gram_part_elems(const Layout& L, int kmax) {
 }
 
 hipError_t launch_gram(const Layout& L, const float* A, const float* B, int ka, int kb,
-                       double* part, double* G, int ldg, hipStream_t s, bool lower) {
+                       double* part, double* G, int ldg, hipStream_t s, bool lower,
+                       uint64_t amask, uint64_t bmask) {
   const GramPlan g = gram_plan(L, ka, kb, lower);
+  if (g.tiles_a > 64) amask = ~0ull;
+  if (g.tiles_b > 64) bmask = ~0ull;
   if (ka <= kThinA)  // one tile row: a 16-row strip of each tile (tiles = tiles_b)
     hipLaunchKernelGGL(k_gram_thin, dim3((unsigned)g.tiles_b, (unsigned)g.chunks), dim3(256), 0, s,
-                       L, A, B, ka, kb, g.rows_per_chunk, g.tiles_a * kGT, part);
+                       L, A, B, ka, kb, g.rows_per_chunk, g.tiles_a * kGT,
+                       (amask & 1) ? bmask : 0ull, part);
   else
     hipLaunchKernelGGL(k_gram, dim3((unsigned)g.tiles, (unsigned)g.chunks), dim3(256), 0, s, L, A,
-                       B, ka, kb, g.rows_per_chunk, g.tiles_b, g.tiles_a * kGT, g.lower, part);
+                       B, ka, kb, g.rows_per_chunk, g.tiles_b, g.tiles_a * kGT, g.lower, amask,
+                       bmask, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n = ka * kb;
@@ -438,15 +448,16 @@ hipError_t launch_gram(const Layout& L, const float* A, const float* B, int ka, 
 
 hipError_t launch_block_mul(const Layout& L, float c0, const float* In0, const float* In1,
                             const double* S, int kin, int kout, int lds, float* Out,
-                            hipStream_t s, bool f32) {
+                            hipStream_t s, bool f32, uint64_t cmask) {
   const int W = L.np * L.pw;
   const dim3 grid((unsigned)((L.n + kMR - 1) / kMR), (unsigned)((W + kMC - 1) / kMC));
+  if (grid.y > 64) cmask = ~0ull;
   if (f32 || block_product_f32())
     hipLaunchKernelGGL(k_block_mul<true>, grid, dim3(256), 0, s, L, c0, In0, In1, S, kin, kout,
-                       lds, Out);
+                       lds, cmask, Out);
   else
     hipLaunchKernelGGL(k_block_mul<false>, grid, dim3(256), 0, s, L, c0, In0, In1, S, kin, kout,
-                       lds, Out);
+                       lds, cmask, Out);
   return hipGetLastError();
 }
 

@@ -248,8 +248,13 @@ hipError_t launch_labels(const Layout& L, const float* X, const double* colnorm2
 // doubles.  lower (ka == kb): only the 128 x 128 tiles on and below the
 // diagonal are summed, and an entry above them is set to its mirror, which
 // a Gram that is symmetric (A = B) or whose upper triangle is never read
-// does not notice.  Block product Out = c0 In0 + In1[:, :kin] S with S
-// float64 kin x kout (leading dimension lds), every stored column written.
+// does not notice.  amask, bmask: bit t set when 128-column tile t of A (B)
+// is read afterwards; the other tiles' entries are left unspecified (all
+// bits are taken as set past 64 tiles).  Block product Out = c0 In0 +
+// In1[:, :kin] S with S float64 kin x kout (leading dimension lds), every
+// stored column written, except the 128-column tiles whose bit in cmask is
+// clear, which keep their contents.
+constexpr int kBlockTile = 128;  // column tile of the Gram and block-product kernels
 struct GramPlan {
   int tiles_a = 0, tiles_b = 0, tiles = 0, chunks = 0, rows_per_chunk = 0;
   bool lower = false;
@@ -257,7 +262,8 @@ struct GramPlan {
 GramPlan gram_plan(const Layout& L, int ka, int kb, bool lower = false);
 size_t gram_part_elems(const Layout& L, int kmax);
 hipError_t launch_gram(const Layout& L, const float* A, const float* B, int ka, int kb,
-                       double* part, double* G, int ldg, hipStream_t s, bool lower = false);
+                       double* part, double* G, int ldg, hipStream_t s, bool lower = false,
+                       uint64_t amask = ~0ull, uint64_t bmask = ~0ull);
 // Z = R / (mask_i + gamma) row by row (Jacobi preconditioner of the interpolation).
 hipError_t launch_jacobi(const Layout& L, const float* R, const float* mask, float gamma, float* Z,
                          hipStream_t s);
@@ -266,7 +272,7 @@ bool block_product_f32();
 // f32: float32 sums for this product whatever the knob says
 hipError_t launch_block_mul(const Layout& L, float c0, const float* In0, const float* In1,
                             const double* S, int kin, int kout, int lds, float* Out,
-                            hipStream_t s, bool f32 = false);
+                            hipStream_t s, bool f32 = false, uint64_t cmask = ~0ull);
 
 // Row schedule of a CSR graph (order.hip): chunks of kSchedChunk rows, each
 // by decreasing degree, ties by index.
