@@ -67,15 +67,6 @@ struct KmItem {
   int* picks;       // k seeding picks, or NULL
 };
 
-__device__ inline double sqd(const double* x, const double* c, int d) {
-  double acc = 0.0;
-  for (int j = 0; j < d; ++j) {
-    const double diff = x[j] - c[j];
-    acc = acc + diff * diff;
-  }
-  return acc;
-}
-
 // the same sum with the point read from the transposed block (coalesced
 // across the threads of a wave, one point per thread); the coordinate loads
 // of eight terms are issued before their additions, which stay in order
@@ -216,59 +207,6 @@ __device__ inline int block_or(int v, int* sh) {
   const int out = *sh;
   __syncthreads();
   return out;
-}
-
-// nearest centroid of every point, ties to the lowest index; four centroids
-// at a time (independent sums, each in coordinate order)
-__device__ void assign(const KmItem& t, const double* C, int* out) {
-  const int n = t.n, d = t.d, k = t.k;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const float* x = t.Xt + i;
-    double best = 0.0;
-    int arg = 0;
-    int c = 0;
-    for (; c + 8 <= k; c += 8) {
-      const double* cb = C + (size_t)c * d;
-      double a[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = 0.0;
-      int j = 0;
-      for (; j + 4 <= d; j += 4) {
-        double xv[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) xv[q] = x[(size_t)(j + q) * n];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const double e = xv[q] - cb[(size_t)u * d + j + q];
-            a[u] = a[u] + e * e;
-          }
-      }
-      for (; j < d; ++j) {
-        const double xj = x[(size_t)j * n];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const double e = xj - cb[(size_t)u * d + j];
-          a[u] = a[u] + e * e;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (c + u == 0 || a[u] < best) {
-          best = a[u];
-          arg = c + u;
-        }
-    }
-    for (; c < k; ++c) {
-      const double v = sqd_t(t.Xt, n, i, C + (size_t)c * d, d);
-      if (c == 0 || v < best) {
-        best = v;
-        arg = c;
-      }
-    }
-    out[i] = arg;
-  }
 }
 
 // Lloyd state of one replicate between launches (flags[]): whether the last

@@ -334,8 +334,8 @@ hipError_t launch_perm_check(int N, const int* inv, int* bad, hipStream_t s) {
 }
 
 size_t perm_graph_temp_bytes(int N) {
-  size_t bytes = 0;
-  hipcub::DeviceScan::InclusiveSum(nullptr, bytes, (const int*)nullptr, (int*)nullptr, N);
+  size_t bytes = 0;  // a failed query leaves 0, and the scan then reports the error
+  (void)hipcub::DeviceScan::InclusiveSum(nullptr, bytes, (const int*)nullptr, (int*)nullptr, N);
   return bytes;
 }
 
@@ -393,9 +393,10 @@ hipError_t launch_nearest_centroid(int N, int d, const float* F, size_t ldf, con
 }
 
 size_t sort_labels_temp_bytes(int N) {
-  size_t bytes = 0;
-  hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const unsigned*)nullptr, (unsigned*)nullptr,
-                                     (const int*)nullptr, (int*)nullptr, N);
+  size_t bytes = 0;  // a failed query leaves 0, and the sort then reports the error
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const unsigned*)nullptr,
+                                           (unsigned*)nullptr, (const int*)nullptr, (int*)nullptr,
+                                           N);
   return bytes;
 }
 
